@@ -1,0 +1,481 @@
+/*
+ * kappa_oracle.c -- sequential CPU oracle for the coarsening hierarchy of the
+ * multilevel partitioner in "Engineering a Scalable High Quality Graph
+ * Partitioner" (Holtgrewe, Sanders, Schulz).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library includes, links or
+ * calls this file; only the test suite, the smoke check and the CPU baseline of
+ * the benchmark load it.  It is plain, single-threaded C99 (plus the compiler's
+ * unsigned __int128), written for a reader who checks it against the paper by
+ * eye, not for speed.
+ *
+ * Conventions (readings of the paper, shared with the GPU library only through
+ * the paper and the design notes, never through code):
+ *   - G = (V, E, c, w) as in Section 2 ("Preliminaries"), stored as a symmetric
+ *     CSR: xadj[n+1] (int64), adj[nnz] (int32), ew[nnz] (uint32 = w),
+ *     vw[n] (uint32 = c).  nnz = 2|E|.
+ *   - weights are integers: w >= 1, c >= 0, sum w(E) <= 2^32-1 and
+ *     sum c(V) <= 2^32-1 (Section 2 allows reals; integers make every
+ *     comparison exact).
+ *   - a rating is an exact rational num/den with num, den < 2^64; ratings are
+ *     compared by 128-bit cross products (Section 3.1 defines the ratings).
+ *   - the strict order on edges: e > f iff num_e*den_f > num_f*den_e, else
+ *     h(e) > h(f), else eid(e) < eid(f), with eid = (min << 32) | max and
+ *     h(e) = mix64(seed ^ eid).  The paper leaves ties open; this order makes
+ *     the matching unique.
+ *   - mix64 is the output function ("finaliser") of SplitMix64 (Steele, Lea,
+ *     Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef unsigned __int128 u128;
+
+/* Status codes.  Same numbers as the library's, fixed by the design notes. */
+#define ORC_OK 0
+#define ORC_E_ARG (-1)
+#define ORC_E_GRAPH (-2)
+#define ORC_E_RANGE (-3)
+
+/* Rating selector (Section 3.1). */
+#define ORC_EXPANSION_STAR2 0
+#define ORC_INNER_OUTER 1
+#define ORC_WEIGHT 2
+#define ORC_EXPANSION 3
+#define ORC_EXPANSION_STAR 4
+
+/* ------------------------------------------------------------------------ */
+/* SplitMix64 output function, from its published definition.              */
+/* ------------------------------------------------------------------------ */
+uint64_t orc_mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+/* SplitMix64 stream: state += golden gamma, then the output function. */
+uint64_t orc_splitmix64_next(uint64_t *state)
+{
+    *state += 0x9e3779b97f4a7c15ULL;
+    return orc_mix64(*state);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Validation: the input must be the graph of Section 2 in CSR form.        */
+/* Checks are grouped in three classes with a fixed priority:               */
+/*   ARG   (sizes / pointers) > GRAPH (structure) > RANGE (weights).        */
+/* ------------------------------------------------------------------------ */
+static int row_contains(const int64_t *xadj, const int32_t *adj, const uint32_t *ew,
+                        int32_t row, int32_t target, uint32_t *w_out)
+{
+    for (int64_t j = xadj[row]; j < xadj[row + 1]; ++j)
+        if (adj[j] == target) { *w_out = ew[j]; return 1; }
+    return 0;
+}
+
+int orc_validate(int32_t n, int64_t nnz, const int64_t *xadj, const int32_t *adj,
+                 const uint32_t *ew, const uint32_t *vw)
+{
+    if (n < 0 || nnz < 0) return ORC_E_ARG;
+    if (xadj == NULL) return ORC_E_ARG;
+    if (n > 0 && vw == NULL) return ORC_E_ARG;
+    if (nnz > 0 && (adj == NULL || ew == NULL)) return ORC_E_ARG;
+
+    /* structure: offsets */
+    if (xadj[0] != 0 || xadj[n] != nnz) return ORC_E_GRAPH;
+    for (int32_t v = 0; v < n; ++v)
+        if (xadj[v + 1] < xadj[v]) return ORC_E_GRAPH;
+    /* structure: targets in range, no self loop, rows strictly ascending
+       (no parallel edges: the graph is simple), and symmetric with equal
+       weights (the graph is undirected). */
+    for (int32_t v = 0; v < n; ++v) {
+        for (int64_t j = xadj[v]; j < xadj[v + 1]; ++j) {
+            int32_t u = adj[j];
+            if (u < 0 || u >= n || u == v) return ORC_E_GRAPH;
+            if (j > xadj[v] && adj[j - 1] >= u) return ORC_E_GRAPH;
+        }
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        for (int64_t j = xadj[v]; j < xadj[v + 1]; ++j) {
+            uint32_t back;
+            if (!row_contains(xadj, adj, ew, adj[j], v, &back)) return ORC_E_GRAPH;
+            if (back != ew[j]) return ORC_E_GRAPH;
+        }
+    }
+    /* range: w >= 1 (Section 2 asks w > 0), sums below 2^32 */
+    uint64_t sw = 0, sc = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        sc += vw[v];
+        for (int64_t j = xadj[v]; j < xadj[v + 1]; ++j) {
+            if (ew[j] == 0) return ORC_E_RANGE;
+            if (adj[j] > v) sw += ew[j];
+        }
+    }
+    if (sw > 0xffffffffULL || sc > 0xffffffffULL) return ORC_E_RANGE;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Out(v) = sum of w over the edges at v (Section 3.1, definition under the  */
+/* innerOuter rating).                                                      */
+/* ------------------------------------------------------------------------ */
+void orc_out(int32_t n, const int64_t *xadj, const uint32_t *ew, uint64_t *out)
+{
+    for (int32_t v = 0; v < n; ++v) {
+        uint64_t s = 0;
+        for (int64_t j = xadj[v]; j < xadj[v + 1]; ++j) s += ew[j];
+        out[v] = s;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ratings of Section 3.1 as exact rationals num/den for the edge {u,v}.     */
+/* ------------------------------------------------------------------------ */
+static void rating(int kind, uint64_t w, uint64_t cu, uint64_t cv,
+                   uint64_t out_u, uint64_t out_v, uint64_t *num, uint64_t *den)
+{
+    switch (kind) {
+    case ORC_WEIGHT:          /* w(e) */
+        *num = w; *den = 1; break;
+    case ORC_EXPANSION:       /* w / (c(u) + c(v)) */
+        *num = w; *den = cu + cv; break;
+    case ORC_EXPANSION_STAR:  /* w / (c(u) c(v)) */
+        *num = w; *den = cu * cv; break;
+    case ORC_INNER_OUTER:     /* w / (Out(v) + Out(u) - 2 w) */
+        *num = w; *den = out_u + out_v - 2 * w; break;
+    case ORC_EXPANSION_STAR2: /* w^2 / (c(u) c(v)) */
+    default:
+        *num = w * w; *den = cu * cv; break;
+    }
+}
+
+/* Rating of every CSR entry (both directions of each edge get the same value). */
+int orc_rate(int32_t n, const int64_t *xadj, const int32_t *adj, const uint32_t *ew,
+             const uint32_t *vw, int kind, uint64_t *num, uint64_t *den)
+{
+    if (kind < 0 || kind > 4) return ORC_E_ARG;
+    uint64_t *out = (uint64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(uint64_t));
+    orc_out(n, xadj, ew, out);
+    for (int32_t v = 0; v < n; ++v)
+        for (int64_t j = xadj[v]; j < xadj[v + 1]; ++j) {
+            int32_t u = adj[j];
+            rating(kind, ew[j], vw[u], vw[v], out[u], out[v], &num[j], &den[j]);
+        }
+    free(out);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The strict order on edges.                                              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t a, b;        /* endpoints, a < b */
+    uint64_t num, den;   /* rating */
+    uint64_t h;          /* tie-break hash */
+} orc_edge;
+
+static uint64_t edge_id(int32_t x, int32_t y)
+{
+    uint64_t lo = (uint64_t)(x < y ? x : y), hi = (uint64_t)(x < y ? y : x);
+    return (lo << 32) | hi;
+}
+
+/* +1 if e is above f in the order, -1 if below, 0 only if e and f are the
+   same edge. */
+static int edge_cmp(const orc_edge *e, const orc_edge *f)
+{
+    u128 l = (u128)e->num * f->den;
+    u128 r = (u128)f->num * e->den;
+    if (l != r) return l > r ? 1 : -1;
+    if (e->h != f->h) return e->h > f->h ? 1 : -1;
+    uint64_t ie = edge_id(e->a, e->b), jf = edge_id(f->a, f->b);
+    if (ie != jf) return ie < jf ? 1 : -1;
+    return 0;
+}
+
+static int edge_cmp_desc(const void *p, const void *q)
+{
+    return -edge_cmp((const orc_edge *)p, (const orc_edge *)q);
+}
+
+/* Fill the list of undirected edges {a,b}, a < b, with their ratings. */
+static int64_t collect_edges(int32_t n, const int64_t *xadj, const int32_t *adj,
+                             const uint32_t *ew, const uint32_t *vw, int kind,
+                             uint64_t seed, orc_edge *edges)
+{
+    uint64_t *out = (uint64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(uint64_t));
+    orc_out(n, xadj, ew, out);
+    int64_t m = 0;
+    for (int32_t v = 0; v < n; ++v)
+        for (int64_t j = xadj[v]; j < xadj[v + 1]; ++j) {
+            int32_t u = adj[j];
+            if (u <= v) continue;
+            orc_edge *e = &edges[m++];
+            e->a = v; e->b = u;
+            rating(kind, ew[j], vw[v], vw[u], out[v], out[u], &e->num, &e->den);
+            e->h = orc_mix64(seed ^ edge_id(v, u));
+        }
+    free(out);
+    return m;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Matching, formulation A: Greedy (Section 3.2).  Edges are scanned in     */
+/* descending order; an edge enters the matching if both ends are free.     */
+/* Returns |M|; mate[v] = partner or -1.                                    */
+/* ------------------------------------------------------------------------ */
+int64_t orc_match_greedy(int32_t n, int64_t nnz, const int64_t *xadj, const int32_t *adj,
+                         const uint32_t *ew, const uint32_t *vw, int kind, uint64_t seed,
+                         int32_t *mate)
+{
+    orc_edge *edges = (orc_edge *)malloc((size_t)(nnz / 2 + 1) * sizeof(orc_edge));
+    int64_t m = collect_edges(n, xadj, adj, ew, vw, kind, seed, edges);
+    qsort(edges, (size_t)m, sizeof(orc_edge), edge_cmp_desc);
+    for (int32_t v = 0; v < n; ++v) mate[v] = -1;
+    int64_t matched = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        int32_t a = edges[i].a, b = edges[i].b;
+        if (mate[a] < 0 && mate[b] < 0) { mate[a] = b; mate[b] = a; ++matched; }
+    }
+    free(edges);
+    return matched;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Matching, formulation B: the parallel scheme of Section 3.3 run in       */
+/* synchronous rounds.  In each round every free node that still has a free */
+/* neighbour points at its best incident edge to a free neighbour; edges    */
+/* that are best at both ends are matched; repeat until no free node has a  */
+/* free neighbour.  round_active[r] / round_degree[r] (optional, capacity   */
+/* max_rounds) receive the number of pointing nodes in round r and the sum  */
+/* of their degrees.  Returns the number of rounds; *matched_out = |M|.     */
+/* ------------------------------------------------------------------------ */
+int32_t orc_match_rounds(int32_t n, int64_t nnz, const int64_t *xadj, const int32_t *adj,
+                         const uint32_t *ew, const uint32_t *vw, int kind, uint64_t seed,
+                         int32_t *mate, int64_t *matched_out,
+                         int64_t *round_active, int64_t *round_degree, int32_t max_rounds)
+{
+    (void)nnz;
+    uint64_t *out = (uint64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(uint64_t));
+    orc_out(n, xadj, ew, out);
+    int32_t *best = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    for (int32_t v = 0; v < n; ++v) mate[v] = -1;
+    int32_t rounds = 0;
+    int64_t matched = 0;
+    for (;;) {
+        int64_t active = 0, degsum = 0;
+        for (int32_t v = 0; v < n; ++v) {
+            best[v] = -1;
+            if (mate[v] >= 0) continue;
+            orc_edge cur, cand;
+            int have = 0;
+            for (int64_t j = xadj[v]; j < xadj[v + 1]; ++j) {
+                int32_t u = adj[j];
+                if (mate[u] >= 0) continue;
+                cand.a = v < u ? v : u; cand.b = v < u ? u : v;
+                rating(kind, ew[j], vw[v], vw[u], out[v], out[u], &cand.num, &cand.den);
+                cand.h = orc_mix64(seed ^ edge_id(v, u));
+                if (!have || edge_cmp(&cand, &cur) > 0) { cur = cand; best[v] = u; have = 1; }
+            }
+            if (have) { ++active; degsum += xadj[v + 1] - xadj[v]; }
+        }
+        if (active == 0) break;
+        if (round_active && rounds < max_rounds) {
+            round_active[rounds] = active;
+            round_degree[rounds] = degsum;
+        }
+        ++rounds;
+        for (int32_t v = 0; v < n; ++v) {
+            int32_t u = best[v];
+            if (u >= 0 && best[u] == v && v < u) { mate[v] = u; mate[u] = v; ++matched; }
+        }
+    }
+    free(best);
+    free(out);
+    *matched_out = matched;
+    return rounds;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Contraction (Section 2): each matched pair {u,v} becomes one node x with */
+/* c(x) = c(u) + c(v); the edges of u and v move to x; parallel edges are   */
+/* merged with summed weight; the contracted edge itself disappears.        */
+/* Coarse numbering (the paper leaves it open): a node is a representative  */
+/* if it is unmatched or the smaller end of its matched edge; coarse ids    */
+/* are the representatives' ranks in ascending fine id; rows ascend.        */
+/* Outputs: cmap[n], cvw[n'], cxadj[n'+1], cadj/cew[nnz'].  Capacities are  */
+/* those of the fine graph.  Returns n'; *cnnz_out = nnz'.                  */
+/* ------------------------------------------------------------------------ */
+typedef struct { uint64_t key; uint32_t w; } orc_entry;
+
+static int entry_cmp(const void *p, const void *q)
+{
+    uint64_t a = ((const orc_entry *)p)->key, b = ((const orc_entry *)q)->key;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+int32_t orc_contract(int32_t n, int64_t nnz, const int64_t *xadj, const int32_t *adj,
+                     const uint32_t *ew, const uint32_t *vw, const int32_t *mate,
+                     int32_t *cmap, uint32_t *cvw, int64_t *cxadj, int32_t *cadj,
+                     uint32_t *cew, int64_t *cnnz_out)
+{
+    /* coarse ids */
+    int32_t nc = 0;
+    for (int32_t v = 0; v < n; ++v)
+        if (mate[v] < 0 || v < mate[v]) cmap[v] = nc++;
+    for (int32_t v = 0; v < n; ++v)
+        if (mate[v] >= 0 && v > mate[v]) cmap[v] = cmap[mate[v]];
+    /* coarse node weights */
+    for (int32_t x = 0; x < nc; ++x) cvw[x] = 0;
+    for (int32_t v = 0; v < n; ++v) cvw[cmap[v]] += vw[v];
+    /* every fine entry (v,u) that is not the contracted edge becomes a
+       coarse entry (cmap v, cmap u); sort and merge equal pairs */
+    orc_entry *ent = (orc_entry *)malloc((size_t)(nnz + 1) * sizeof(orc_entry));
+    int64_t k = 0;
+    for (int32_t v = 0; v < n; ++v)
+        for (int64_t j = xadj[v]; j < xadj[v + 1]; ++j) {
+            int32_t a = cmap[v], b = cmap[adj[j]];
+            if (a == b) continue;
+            ent[k].key = ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
+            ent[k].w = ew[j];
+            ++k;
+        }
+    qsort(ent, (size_t)k, sizeof(orc_entry), entry_cmp);
+    for (int32_t x = 0; x <= nc; ++x) cxadj[x] = 0;
+    int64_t out = 0;
+    for (int64_t i = 0; i < k; ) {
+        uint64_t key = ent[i].key;
+        uint64_t s = 0;
+        while (i < k && ent[i].key == key) s += ent[i++].w;
+        int32_t a = (int32_t)(key >> 32), b = (int32_t)(key & 0xffffffffu);
+        cadj[out] = b;
+        cew[out] = (uint32_t)s;
+        ++out;
+        cxadj[a + 1] += 1;
+    }
+    for (int32_t x = 0; x < nc; ++x) cxadj[x + 1] += cxadj[x];
+    free(ent);
+    *cnnz_out = out;
+    return nc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Stand-in for initial partitioning of the coarsest graph: block of x is    */
+/* mix64(seed + x) mod k.  (The paper runs Scotch or pMetis here, Section 4; */
+/* those systems are not part of this hierarchy.)                           */
+/* ------------------------------------------------------------------------ */
+void orc_initial_partition(int32_t n, int32_t k, uint64_t seed, int32_t *part)
+{
+    for (int32_t x = 0; x < n; ++x)
+        part[x] = (int32_t)(orc_mix64(seed + (uint64_t)x) % (uint64_t)k);
+}
+
+/* Uncontraction seen as projection: a fine node takes the block of the
+   coarse node it was contracted into (Section 2, "uncontracting"). */
+void orc_project(int32_t n_fine, const int32_t *cmap, const int32_t *part_coarse,
+                 int32_t *part_fine)
+{
+    for (int32_t v = 0; v < n_fine; ++v) part_fine[v] = part_coarse[cmap[v]];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cut and balance (Section 2, and the imbalance of Section 5.2).           */
+/*   cut      = sum over edges {u,v} with different blocks of w({u,v})      */
+/*   W_i      = c(V_i)                                                      */
+/*   L_max    = (1+eps) c(V)/k + max_v c(v), eps = eps_num/eps_den, kept as */
+/*              the exact rational lmax_num / lmax_den                      */
+/*   imbalance= max(0, max_i W_i - L_max)  (numerator over lmax_den)        */
+/*   balance  = k max_i W_i / c(V)          (bal_num / bal_den)             */
+/* res[] layout: cut, total, max_block, max_node, lmax_num, lmax_den,        */
+/*               imb_num, bal_num, bal_den, feasible                         */
+/* ------------------------------------------------------------------------ */
+int orc_cut_balance(int32_t n, const int64_t *xadj, const int32_t *adj, const uint32_t *ew,
+                    const uint32_t *vw, const int32_t *part, int32_t k,
+                    uint32_t eps_num, uint32_t eps_den, uint64_t *block_w, uint64_t *res)
+{
+    /* k in [1, 4096], eps = eps_num/eps_den with eps_den in [1, 10^6] and
+       eps_num <= 16 eps_den: every result below then fits 64 bits. */
+    if (k < 1 || k > 4096 || eps_den == 0 || eps_den > 1000000u ||
+        eps_num > 16000000u)
+        return ORC_E_ARG;
+    for (int32_t v = 0; v < n; ++v)
+        if (part[v] < 0 || part[v] >= k) return ORC_E_RANGE;
+    uint64_t cut = 0, total = 0, maxc = 0, maxw = 0;
+    for (int32_t i = 0; i < k; ++i) block_w[i] = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        block_w[part[v]] += vw[v];
+        total += vw[v];
+        if (vw[v] > maxc) maxc = vw[v];
+        for (int64_t j = xadj[v]; j < xadj[v + 1]; ++j)
+            if (adj[j] > v && part[adj[j]] != part[v]) cut += ew[j];
+    }
+    for (int32_t i = 0; i < k; ++i) if (block_w[i] > maxw) maxw = block_w[i];
+    u128 lnum = (u128)((uint64_t)eps_den + eps_num) * total + (u128)k * eps_den * maxc;
+    u128 lden = (u128)k * eps_den;
+    u128 lhs = lden * maxw;
+    res[0] = cut;
+    res[1] = total;
+    res[2] = maxw;
+    res[3] = maxc;
+    res[4] = (uint64_t)lnum;
+    res[5] = (uint64_t)lden;
+    res[6] = lhs > lnum ? (uint64_t)(lhs - lnum) : 0;
+    res[7] = (uint64_t)k * maxw;
+    res[8] = total;
+    res[9] = lhs <= lnum ? 1 : 0;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Greedy certificate, used to check a matching at sizes where re-running    */
+/* Greedy is too slow.  A matching M equals the Greedy matching of the      */
+/* strict order iff every edge outside M touches an edge of M that is above */
+/* it (by induction over the descending scan).  Returns the number of edges */
+/* that break this, plus the number of broken mate entries; 0 means M is    */
+/* exactly the Greedy matching.                                             */
+/* ------------------------------------------------------------------------ */
+int64_t orc_greedy_certificate(int32_t n, const int64_t *xadj, const int32_t *adj,
+                               const uint32_t *ew, const uint32_t *vw, int kind,
+                               uint64_t seed, const int32_t *mate)
+{
+    uint64_t *out = (uint64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(uint64_t));
+    orc_out(n, xadj, ew, out);
+    int64_t bad = 0;
+    /* M must be a matching made of graph edges */
+    uint32_t *mw = (uint32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(uint32_t));
+    for (int32_t v = 0; v < n; ++v) {
+        int32_t u = mate[v];
+        if (u < 0) continue;
+        if (u >= n || u == v || mate[u] != v) { ++bad; continue; }
+        uint32_t w;
+        if (!row_contains(xadj, adj, ew, v, u, &w)) { ++bad; continue; }
+        mw[v] = w;
+    }
+    if (bad) { free(mw); free(out); return bad; }
+    for (int32_t v = 0; v < n; ++v)
+        for (int64_t j = xadj[v]; j < xadj[v + 1]; ++j) {
+            int32_t u = adj[j];
+            if (u <= v || mate[v] == u) continue;
+            orc_edge f;
+            f.a = v; f.b = u;
+            rating(kind, ew[j], vw[v], vw[u], out[v], out[u], &f.num, &f.den);
+            f.h = orc_mix64(seed ^ edge_id(v, u));
+            int blocked = 0;
+            int32_t ends[2] = {v, u};
+            for (int t = 0; t < 2 && !blocked; ++t) {
+                int32_t x = ends[t], y = mate[x];
+                if (y < 0) continue;
+                orc_edge g;
+                g.a = x < y ? x : y; g.b = x < y ? y : x;
+                rating(kind, mw[x], vw[x], vw[y], out[x], out[y], &g.num, &g.den);
+                g.h = orc_mix64(seed ^ edge_id(x, y));
+                if (edge_cmp(&g, &f) > 0) blocked = 1;
+            }
+            if (!blocked) ++bad;
+        }
+    free(mw);
+    free(out);
+    return bad;
+}

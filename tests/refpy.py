@@ -1,0 +1,125 @@
+"""Pure-Python brute-force checks for tiny graphs, written independently of the
+C oracle: ratings as ``fractions.Fraction``, matchings by exhaustive search,
+contraction with dictionaries.  Used only to pin the oracle."""
+from __future__ import annotations
+
+import itertools
+from fractions import Fraction
+
+M64 = (1 << 64) - 1
+
+
+def mix64(z: int) -> int:
+    """SplitMix64 output function (pinned by the published stream values)."""
+    z &= M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+    return z ^ (z >> 31)
+
+
+def edges_of(g):
+    """Undirected edges (a, b, w) with a < b, from a CSR."""
+    out = []
+    for v in range(g.n):
+        for j in range(int(g.xadj[v]), int(g.xadj[v + 1])):
+            u = int(g.adj[j])
+            if u > v:
+                out.append((v, u, int(g.ew[j])))
+    return out
+
+
+def out_of(g):
+    return [sum(int(g.ew[j]) for j in range(int(g.xadj[v]), int(g.xadj[v + 1]))) for v in range(g.n)]
+
+
+INF = None  # marker for a zero denominator
+
+
+def rating_value(kind: str, w: int, cu: int, cv: int, ou: int, ov: int):
+    """Section 3.1 ratings as Fractions; a zero denominator gives +infinity
+    (returned as (1, 0) so that it sorts above every finite value)."""
+    if kind == "weight":
+        num, den = w, 1
+    elif kind == "expansion":
+        num, den = w, cu + cv
+    elif kind == "expansion*":
+        num, den = w, cu * cv
+    elif kind == "expansion*2":
+        num, den = w * w, cu * cv
+    elif kind == "innerOuter":
+        num, den = w, ou + ov - 2 * w
+    else:
+        raise ValueError(kind)
+    if den == 0:
+        return (1, Fraction(0))
+    return (0, Fraction(num, den))
+
+
+def order_key(kind, g, seed, a, b, w, outs):
+    """Sort key: larger key = higher in the strict edge order."""
+    cu, cv = int(g.vw[a]), int(g.vw[b])
+    r = rating_value(kind, w, cu, cv, outs[a], outs[b])
+    eid = (min(a, b) << 32) | max(a, b)
+    return (r, mix64(seed ^ eid), -eid)
+
+
+def greedy(g, kind, seed):
+    """Greedy of Section 3.2 under the strict order."""
+    outs = out_of(g)
+    es = edges_of(g)
+    es.sort(key=lambda e: order_key(kind, g, seed, e[0], e[1], e[2], outs), reverse=True)
+    mate = [-1] * g.n
+    for a, b, _ in es:
+        if mate[a] < 0 and mate[b] < 0:
+            mate[a], mate[b] = b, a
+    return mate
+
+
+def all_matchings(n, es):
+    """Every matching of the edge list (exponential; tiny graphs only)."""
+    res = []
+
+    def rec(i, used, cur):
+        if i == len(es):
+            res.append(list(cur))
+            return
+        rec(i + 1, used, cur)
+        a, b = es[i][0], es[i][1]
+        if a not in used and b not in used:
+            used.add(a); used.add(b); cur.append(es[i])
+            rec(i + 1, used, cur)
+            cur.pop(); used.discard(a); used.discard(b)
+
+    rec(0, set(), [])
+    return res
+
+
+def finite_value(kind, g, e, outs):
+    inf, val = rating_value(kind, e[2], int(g.vw[e[0]]), int(g.vw[e[1]]), outs[e[0]], outs[e[1]])
+    return val if not inf else None
+
+
+def contract_dict(g, mate):
+    """Contraction of Section 2 with dictionaries and min-representative ids."""
+    reps = [v for v in range(g.n) if mate[v] < 0 or v < mate[v]]
+    cid = {v: i for i, v in enumerate(reps)}
+    cmap = [cid[v] if (mate[v] < 0 or v < mate[v]) else cid[mate[v]] for v in range(g.n)]
+    nc = len(reps)
+    cvw = [0] * nc
+    for v in range(g.n):
+        cvw[cmap[v]] += int(g.vw[v])
+    rows = [dict() for _ in range(nc)]
+    for a, b, w in edges_of(g):
+        x, y = cmap[a], cmap[b]
+        if x == y:
+            continue
+        rows[x][y] = rows[x].get(y, 0) + w
+        rows[y][x] = rows[y].get(x, 0) + w
+    xadj = [0]
+    adj, ew = [], []
+    for x in range(nc):
+        for y in sorted(rows[x]):
+            adj.append(y)
+            ew.append(rows[x][y])
+        xadj.append(len(adj))
+    return cmap, nc, xadj, adj, ew, cvw
