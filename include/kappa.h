@@ -1,0 +1,244 @@
+/*
+ * kappa.h -- C ABI of the MI355X (gfx950) coarsening-hierarchy library.
+ *
+ * Implements the contraction phase of the multilevel graph partitioner of
+ * "Engineering a Scalable High Quality Graph Partitioner" (Holtgrewe, Sanders,
+ * Schulz), together with the projection and cut/balance evaluation used on the
+ * way back up:
+ *   edge rating (Section 3.1) -> locally-heaviest-edge matching (Section 3.3)
+ *   -> contraction into a weighted coarse graph (Section 2) -> repeat until
+ *   small (Section 2, stop rule of Section 4) -> projection of a partition
+ *   (uncontraction, Section 2) -> cut and balance (Section 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Graph.  G = (V, E, c, w) of Section 2 as a symmetric CSR in device memory:
+ *   xadj[n+1] int64   row offsets, xadj[0] = 0, non-decreasing, xadj[n] = nnz
+ *   adj[nnz]  int32   neighbour ids, each row strictly ascending, no self loop
+ *   ew[nnz]   uint32  edge weight w({v,u}), equal in both directions, w >= 1
+ *   vw[n]     uint32  node weight c(v) >= 0
+ *   nnz = 2|E|.  Sum of w over E and sum of c over V must stay <= 2^32 - 1;
+ *   contraction never increases either sum, so every level keeps the bound and
+ *   every weight of every level fits uint32.  (The paper allows real weights;
+ *   integers make every comparison exact.)  Callers holding int32 tensors pass
+ *   their bits: they are read as uint32.
+ * Pointers.  Every array argument is a DEVICE pointer unless its comment says
+ *   host.  The caller owns every array it passes; the library never frees
+ *   them.  Arrays of length 0 may be NULL.
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *   enqueued on it.  Calls that return a result on the host (status of a
+ *   validation, round counts, cut values) synchronise that stream before they
+ *   return.
+ * Errors.  Every entry point returns a kappa_status; no exception crosses the
+ *   ABI.  On an error nothing is guaranteed about the output arrays.
+ * Ratings.  Ratings are exact rationals num/den with num, den < 2^64; edge e
+ *   ranks above edge f iff num_e*den_f > num_f*den_e (128-bit), else
+ *   h(e) > h(f), else eid(e) < eid(f), where eid = (min(u,v) << 32) | max(u,v)
+ *   and h(e) = mix64(seed ^ eid), mix64 being the SplitMix64 output function.
+ *   A zero denominator is +infinity.  This strict order makes the matching
+ *   unique: it equals the Greedy matching of Section 3.2 under the same order.
+ */
+#ifndef KAPPA_H
+#define KAPPA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *kappa_stream_t; /* a hipStream_t */
+
+typedef enum {
+    KAPPA_OK = 0,
+    KAPPA_E_ARG = -1,      /* bad size, NULL pointer, unknown enum, k or eps out of range */
+    KAPPA_E_GRAPH = -2,    /* CSR not symmetric / not simple / rows not ascending / bad offsets */
+    KAPPA_E_RANGE = -3,    /* w = 0, sum of w or c above 2^32-1, block id or map entry out of range */
+    KAPPA_E_NOMEM = -4,    /* device allocation failed */
+    KAPPA_E_CAPACITY = -5, /* an output buffer is smaller than the result */
+    KAPPA_E_HIP = -6       /* a HIP runtime call failed */
+} kappa_status;
+
+/* Section 3.1 ratings of an edge {u,v} with weight w. */
+typedef enum {
+    KAPPA_EXPANSION_STAR2 = 0, /* w^2 / (c(u) c(v))                 (paper's default) */
+    KAPPA_INNER_OUTER = 1,     /* w / (Out(u) + Out(v) - 2w), Out(v) = sum of w at v */
+    KAPPA_WEIGHT = 2,          /* w                                                   */
+    KAPPA_EXPANSION = 3,       /* w / (c(u) + c(v))                                   */
+    KAPPA_EXPANSION_STAR = 4   /* w / (c(u) c(v))                                     */
+} kappa_rating;
+
+/* Why the level loop ended (recorded on the coarsest level). */
+typedef enum {
+    KAPPA_STOP_NONE = 0,
+    KAPPA_STOP_SIZE = 1,     /* n <= stop_n before matching                     */
+    KAPPA_STOP_EMPTY = 2,    /* the matching of the last level was empty        */
+    KAPPA_STOP_STALL = 3,    /* the last contraction removed < stall of nodes   */
+    KAPPA_STOP_MAXLEVEL = 4  /* max_levels contractions done                    */
+} kappa_stop;
+
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    const int64_t *xadj;
+    const int32_t *adj;
+    const uint32_t *ew;
+    const uint32_t *vw;
+} kappa_graph;
+
+/* Caller-allocated output graph.  cap_n / cap_nnz are the capacities of the
+   arrays (vw and xadj need cap_n and cap_n + 1 entries); n / nnz receive the
+   sizes.  Capacities equal to the fine graph's n and nnz always suffice. */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    int32_t cap_n;
+    int64_t cap_nnz;
+    int64_t *xadj;
+    int32_t *adj;
+    uint32_t *ew;
+    uint32_t *vw;
+} kappa_graph_out;
+
+typedef struct {
+    int32_t rating;       /* kappa_rating */
+    uint64_t seed;        /* level l matches with seed_l = mix64(seed + l) */
+    int32_t stop_n;       /* stop once n <= stop_n */
+    uint32_t stall_num;   /* stop after a level with (n_l - n_{l+1}) * stall_den */
+    uint32_t stall_den;   /*   < stall_num * n_l; stall_num = 0 disables the rule */
+    int32_t max_levels;   /* at most this many contractions (<= 256) */
+} kappa_coarsen_params;
+
+/* Exact cut/balance of a k-way partition (Section 2; imbalance as in
+   Section 5.2).  L_max = (1 + eps) c(V)/k + max_v c(v) = lmax_num / lmax_den
+   with lmax_den = k * eps_den. */
+typedef struct {
+    uint64_t cut;        /* sum of w over edges whose ends lie in different blocks */
+    uint64_t total;      /* c(V) */
+    uint64_t max_block;  /* max_i c(V_i) */
+    uint64_t max_node;   /* max_v c(v) on this graph */
+    uint64_t lmax_num;
+    uint64_t lmax_den;
+    uint64_t imb_num;    /* max(0, max_block - L_max) * lmax_den */
+    uint64_t bal_num;    /* balance = k * max_block / c(V) = bal_num / bal_den */
+    uint64_t bal_den;
+    int64_t feasible;    /* 1 iff max_block <= L_max */
+} kappa_cut_result;
+
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    int32_t rounds;      /* matching rounds spent on this level (0 on the coarsest) */
+    int64_t matched;     /* |M| of this level's matching */
+    int32_t stop_reason; /* kappa_stop; nonzero only on the coarsest level */
+} kappa_level_info;
+
+typedef struct kappa_hierarchy kappa_hierarchy; /* opaque, library-owned */
+
+/* Checks that g is a graph in the form above (Section 2: simple, undirected,
+   w > 0, c >= 0) and that the weight sums fit.  Returns KAPPA_OK,
+   KAPPA_E_ARG (sizes/NULL), KAPPA_E_GRAPH (structure) or KAPPA_E_RANGE
+   (weights), checked in that priority.  Synchronous. */
+kappa_status kappa_validate(const kappa_graph *g, kappa_stream_t stream);
+
+/* Section 3.1: writes the rating of every CSR entry j (edge {v, adj[j]})
+   as num[j] / den[j] (both uint64, nnz entries each).  g must be valid. */
+kappa_status kappa_rate(const kappa_graph *g, int32_t rating, uint64_t *num, uint64_t *den,
+                        kappa_stream_t stream);
+
+/* Section 3.3: parallel locally-heaviest-edge matching.  In every round each
+   free node with a free neighbour points at its best edge to a free
+   neighbour; edges that are best at both ends are matched; rounds repeat
+   until no edge can be added.  mate[n] (device, out): partner or -1.
+   rounds_out, matched_out (host, may be NULL): round count and |M|.
+   level_seed is the tie-break seed used in h(e) directly.  Synchronous. */
+kappa_status kappa_match(const kappa_graph *g, int32_t rating, uint64_t level_seed,
+                         int32_t *mate, int32_t *rounds_out, int64_t *matched_out,
+                         kappa_stream_t stream);
+
+/* Section 2: contracts the matching `mate` (as written by kappa_match, or any
+   valid matching of g).  Coarse ids: a node is a representative if it is
+   unmatched or the smaller end of its matched edge; representatives are
+   numbered in ascending fine id.  cmap[n] (device, out): coarse id of each
+   fine node.  coarse (host struct, device arrays): the coarse graph, rows
+   ascending, parallel edges merged with summed weight.  Returns
+   KAPPA_E_CAPACITY if coarse's capacities are too small.  Synchronous. */
+kappa_status kappa_contract(const kappa_graph *g, const int32_t *mate, int32_t *cmap,
+                            kappa_graph_out *coarse, kappa_stream_t stream);
+
+/* The whole contraction phase: validate g, then match and contract level
+   after level (level l uses seed_l = mix64(seed + l)) until a stop rule
+   fires.  *out receives a library-owned hierarchy; level 0 refers to the
+   caller's arrays of g, which must stay alive and unchanged while the
+   hierarchy is used.  Synchronous. */
+kappa_status kappa_coarsen(const kappa_graph *g, const kappa_coarsen_params *params,
+                           kappa_hierarchy **out, kappa_stream_t stream);
+
+int32_t kappa_hierarchy_levels(const kappa_hierarchy *h);
+
+/* Level l of h (0 = input): its graph (device arrays owned by h), its fine ->
+   coarse map (NULL on the coarsest level) and its statistics.  Any output
+   pointer may be NULL. */
+kappa_status kappa_hierarchy_level(const kappa_hierarchy *h, int32_t l, kappa_graph *g,
+                                   const int32_t **cmap, kappa_level_info *info);
+
+/* Round statistics of level l's matching (Section 3.3 rounds): for round r
+   (0-based), pointing[r] = number of free nodes that had a free neighbour and
+   degsum[r] = the sum of their degrees.  Copies min(rounds, cap) entries to
+   the host arrays and returns the level's round count (at most 64 rounds are
+   kept per level; a negative kappa_status on a bad argument). */
+int32_t kappa_hierarchy_round_stats(const kappa_hierarchy *h, int32_t l, int64_t *pointing,
+                                    int64_t *degsum, int32_t cap);
+
+/* Frees h (stream-ordered on the stream it was built on). NULL is a no-op. */
+void kappa_hierarchy_free(kappa_hierarchy *h);
+
+/* Stand-in for the initial partitioning of Section 4 (which runs external
+   partitioners): part[x] = mix64(seed + x) mod k for x < n.  k in [1, 4096]. */
+kappa_status kappa_initial_partition(int32_t n, int32_t k, uint64_t seed, int32_t *part,
+                                     kappa_stream_t stream);
+
+/* Uncontraction as projection (Section 2): part_fine[v] =
+   part_coarse[cmap[v]] for v < n_fine.  Every cmap entry must lie in
+   [0, n_coarse), else KAPPA_E_RANGE.  Synchronous. */
+kappa_status kappa_project(const int32_t *cmap, int32_t n_fine, int32_t n_coarse,
+                           const int32_t *part_coarse, int32_t *part_fine,
+                           kappa_stream_t stream);
+
+/* Cut and balance of the k-way partition part[n] of g (Section 2).
+   k in [1, 4096]; eps = eps_num / eps_den with eps_den in [1, 10^6] and
+   eps_num <= 16 * 10^6.  block_w (device, k entries, out, may be NULL):
+   c(V_i).  out (host): the exact results.  KAPPA_E_RANGE if a block id is
+   outside [0, k).  Synchronous. */
+kappa_status kappa_cut_balance(const kappa_graph *g, const int32_t *part, int32_t k,
+                               uint32_t eps_num, uint32_t eps_den, uint64_t *block_w,
+                               kappa_cut_result *out, kappa_stream_t stream);
+
+/* The way back up in one call: partitions the coarsest level of h with
+   kappa_initial_partition(part_seed), projects level by level down to
+   level 0 and evaluates cut/balance on every level.  part0 (device, n_0
+   entries, out): the level-0 partition.  results (host, one entry per level,
+   may be NULL): results[l] for level l.  Synchronous. */
+kappa_status kappa_uncoarsen(const kappa_hierarchy *h, int32_t k, uint64_t part_seed,
+                             uint32_t eps_num, uint32_t eps_den, int32_t *part0,
+                             kappa_cut_result *results, kappa_stream_t stream);
+
+/* Per-kernel timing with HIP events on the launch stream.  While enabled,
+   every kernel launch of the library is bracketed by two events; read the
+   totals with kappa_profile_read.  Not thread-safe. */
+void kappa_profile_enable(int32_t on);
+void kappa_profile_reset(void);
+/* Copies up to `cap` entries: name (host, static strings), launches and
+   summed milliseconds per kernel.  Returns the number of kernels recorded.
+   Synchronises the device. */
+int32_t kappa_profile_read(const char **names, int64_t *launches, double *ms, int32_t cap);
+
+const char *kappa_status_str(kappa_status st);
+const char *kappa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KAPPA_H */

@@ -1,0 +1,369 @@
+"""ctypes binding of libkappa.so (include/kappa.h).  Argument marshalling only:
+every step of the method runs in the library's HIP kernels.
+
+Tensors are torch CUDA (HIP) tensors; weights travel as int32 tensors whose
+bits the library reads as uint32.  Work is enqueued on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+from typing import List, Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkappa.so")
+HEADER = os.path.join(HERE, "..", "include", "kappa.h")
+
+OK, E_ARG, E_GRAPH, E_RANGE, E_NOMEM, E_CAPACITY, E_HIP = 0, -1, -2, -3, -4, -5, -6
+EXPANSION_STAR2, INNER_OUTER, WEIGHT, EXPANSION, EXPANSION_STAR = 0, 1, 2, 3, 4
+RATINGS = {"expansion*2": 0, "innerOuter": 1, "weight": 2, "expansion": 3, "expansion*": 4}
+STOP_NONE, STOP_SIZE, STOP_EMPTY, STOP_STALL, STOP_MAXLEVEL = 0, 1, 2, 3, 4
+
+
+class KappaError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        self.status = status
+        super().__init__(f"{fn} failed: {status} ({status_str(status)})")
+
+
+class c_graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("xadj", ctypes.c_void_p),
+                ("adj", ctypes.c_void_p), ("ew", ctypes.c_void_p), ("vw", ctypes.c_void_p)]
+
+
+class c_graph_out(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("cap_n", ctypes.c_int32),
+                ("cap_nnz", ctypes.c_int64), ("xadj", ctypes.c_void_p), ("adj", ctypes.c_void_p),
+                ("ew", ctypes.c_void_p), ("vw", ctypes.c_void_p)]
+
+
+class c_params(ctypes.Structure):
+    _fields_ = [("rating", ctypes.c_int32), ("seed", ctypes.c_uint64), ("stop_n", ctypes.c_int32),
+                ("stall_num", ctypes.c_uint32), ("stall_den", ctypes.c_uint32),
+                ("max_levels", ctypes.c_int32)]
+
+
+class c_cut(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in ("cut", "total", "max_block", "max_node", "lmax_num",
+                                                 "lmax_den", "imb_num", "bal_num", "bal_den")] + \
+               [("feasible", ctypes.c_int64)]
+
+    def as_tuple(self):
+        return (self.cut, self.total, self.max_block, self.max_node, self.lmax_num, self.lmax_den,
+                self.imb_num, self.bal_num, self.bal_den, int(self.feasible))
+
+
+class c_level_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("rounds", ctypes.c_int32),
+                ("matched", ctypes.c_int64), ("stop_reason", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def declared_functions() -> List[str]:
+    """Names of the functions declared in include/kappa.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kappa_[a-z_0-9]+)\s*\(", text)))
+
+
+def lib():
+    """Loads libkappa.so.  Raises if it is missing: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_0910_2004_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+    st = ctypes.c_int
+    sig = {
+        "kappa_validate": (st, [ctypes.POINTER(c_graph), P]),
+        "kappa_rate": (st, [ctypes.POINTER(c_graph), i32, P, P, P]),
+        "kappa_match": (st, [ctypes.POINTER(c_graph), i32, u64, P, ctypes.POINTER(i32),
+                             ctypes.POINTER(i64), P]),
+        "kappa_contract": (st, [ctypes.POINTER(c_graph), P, P, ctypes.POINTER(c_graph_out), P]),
+        "kappa_coarsen": (st, [ctypes.POINTER(c_graph), ctypes.POINTER(c_params),
+                               ctypes.POINTER(P), P]),
+        "kappa_hierarchy_levels": (i32, [P]),
+        "kappa_hierarchy_level": (st, [P, i32, ctypes.POINTER(c_graph), ctypes.POINTER(P),
+                                       ctypes.POINTER(c_level_info)]),
+        "kappa_hierarchy_round_stats": (i32, [P, i32, P, P, i32]),
+        "kappa_hierarchy_free": (None, [P]),
+        "kappa_initial_partition": (st, [i32, i32, u64, P, P]),
+        "kappa_project": (st, [P, i32, i32, P, P, P]),
+        "kappa_cut_balance": (st, [ctypes.POINTER(c_graph), P, i32, u32, u32, P,
+                                   ctypes.POINTER(c_cut), P]),
+        "kappa_uncoarsen": (st, [P, i32, u64, u32, u32, P, P, P]),
+        "kappa_profile_enable": (None, [i32]),
+        "kappa_profile_reset": (None, []),
+        "kappa_profile_read": (i32, [P, P, P, i32]),
+        "kappa_status_str": (ctypes.c_char_p, [st]),
+        "kappa_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def status_str(st: int) -> str:
+    try:
+        return lib().kappa_status_str(st).decode()
+    except Exception:
+        return "?"
+
+
+def _check(fn: str, st: int):
+    if st != OK:
+        raise KappaError(fn, st)
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# HIP runtime copy (used to read library-owned hierarchy arrays into tensors)
+# ---------------------------------------------------------------------------
+_hip = None
+
+
+def _hip_rt():
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpyAsync.restype = ctypes.c_int
+        _hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_int, ctypes.c_void_p]
+    return _hip
+
+
+def _copy_from_ptr(ptr: int, count: int, dtype, device):
+    import torch
+    out = torch.empty(max(count, 0), dtype=dtype, device=device)
+    if count > 0 and ptr:
+        nbytes = count * out.element_size()
+        r = _hip_rt().hipMemcpyAsync(ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ptr), nbytes,
+                                     3, _stream())
+        if r != 0:
+            raise RuntimeError(f"hipMemcpyAsync failed: {r}")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Graphs on the device
+# ---------------------------------------------------------------------------
+@dataclass
+class DeviceGraph:
+    n: int
+    nnz: int
+    xadj: object   # torch.int64 [n+1]
+    adj: object    # torch.int32 [nnz]
+    ew: object     # torch.int32 [nnz] (uint32 bits)
+    vw: object     # torch.int32 [n]   (uint32 bits)
+
+    def c(self) -> c_graph:
+        return c_graph(self.n, self.nnz, self.xadj.data_ptr(),
+                       self.adj.data_ptr() if self.nnz else None,
+                       self.ew.data_ptr() if self.nnz else None,
+                       self.vw.data_ptr() if self.n else None)
+
+    @staticmethod
+    def from_csr(g, device="cuda") -> "DeviceGraph":
+        import numpy as np
+        import torch
+        xadj = torch.from_numpy(np.ascontiguousarray(g.xadj, dtype=np.int64)).to(device)
+        adj = torch.from_numpy(np.ascontiguousarray(g.adj, dtype=np.int32)).to(device)
+        ew = torch.from_numpy(np.ascontiguousarray(g.ew).astype(np.uint32).view(np.int32)).to(device)
+        vw = torch.from_numpy(np.ascontiguousarray(g.vw).astype(np.uint32).view(np.int32)).to(device)
+        return DeviceGraph(int(g.n), int(g.xadj[-1]), xadj, adj, ew, vw)
+
+    def numpy(self):
+        """(xadj, adj, ew, vw) as numpy arrays (ew, vw as uint32)."""
+        import numpy as np
+        return (self.xadj.cpu().numpy(), self.adj.cpu().numpy(),
+                self.ew.cpu().numpy().view(np.uint32), self.vw.cpu().numpy().view(np.uint32))
+
+
+def kappa_validate(g: DeviceGraph) -> int:
+    return int(lib().kappa_validate(ctypes.byref(g.c()), _stream()))
+
+
+def kappa_rate(g: DeviceGraph, rating: int):
+    """Returns (num, den) as int64 tensors holding uint64 bits."""
+    import torch
+    num = torch.empty(max(g.nnz, 1), dtype=torch.int64, device=g.xadj.device)
+    den = torch.empty(max(g.nnz, 1), dtype=torch.int64, device=g.xadj.device)
+    _check("kappa_rate", lib().kappa_rate(ctypes.byref(g.c()), rating, _ptr(num), _ptr(den), _stream()))
+    return num[:g.nnz], den[:g.nnz]
+
+
+def kappa_match(g: DeviceGraph, rating: int, level_seed: int):
+    import torch
+    mate = torch.empty(max(g.n, 1), dtype=torch.int32, device=g.xadj.device)
+    rounds = ctypes.c_int32(0)
+    matched = ctypes.c_int64(0)
+    _check("kappa_match", lib().kappa_match(ctypes.byref(g.c()), rating,
+                                            ctypes.c_uint64(level_seed & (2**64 - 1)), _ptr(mate),
+                                            ctypes.byref(rounds), ctypes.byref(matched), _stream()))
+    return mate[:g.n], int(rounds.value), int(matched.value)
+
+
+def kappa_contract(g: DeviceGraph, mate, cap_n: Optional[int] = None, cap_nnz: Optional[int] = None):
+    """Returns (cmap, coarse DeviceGraph)."""
+    import torch
+    dev = g.xadj.device
+    cap_n = g.n if cap_n is None else cap_n
+    cap_nnz = g.nnz if cap_nnz is None else cap_nnz
+    cmap = torch.empty(max(g.n, 1), dtype=torch.int32, device=dev)
+    cx = torch.empty(cap_n + 1, dtype=torch.int64, device=dev)
+    ca = torch.empty(max(cap_nnz, 1), dtype=torch.int32, device=dev)
+    ce = torch.empty(max(cap_nnz, 1), dtype=torch.int32, device=dev)
+    cv = torch.empty(max(cap_n, 1), dtype=torch.int32, device=dev)
+    out = c_graph_out(0, 0, cap_n, cap_nnz, cx.data_ptr(), ca.data_ptr(), ce.data_ptr(), cv.data_ptr())
+    _check("kappa_contract", lib().kappa_contract(ctypes.byref(g.c()), _ptr(mate), _ptr(cmap),
+                                                  ctypes.byref(out), _stream()))
+    n, m = int(out.n), int(out.nnz)
+    return cmap[:g.n], DeviceGraph(n, m, cx[:n + 1], ca[:m], ce[:m], cv[:n])
+
+
+@dataclass
+class LevelView:
+    graph: DeviceGraph
+    cmap: object          # torch.int32 [n] or None on the coarsest level
+    rounds: int
+    matched: int
+    stop_reason: int
+
+
+class Hierarchy:
+    """Owns a kappa_hierarchy handle (freed with the object).  Keeps the input
+    graph alive: level 0 of the hierarchy refers to its arrays."""
+
+    def __init__(self, handle, device, graph=None):
+        self.handle = handle
+        self.device = device
+        self.graph = graph
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().kappa_hierarchy_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    def __len__(self):
+        return int(lib().kappa_hierarchy_levels(self.handle))
+
+    def info(self, l: int) -> c_level_info:
+        inf = c_level_info()
+        _check("kappa_hierarchy_level", lib().kappa_hierarchy_level(self.handle, l, None, None,
+                                                                    ctypes.byref(inf)))
+        return inf
+
+    def round_stats(self, l: int):
+        import numpy as np
+        p = np.zeros(64, dtype=np.int64)
+        d = np.zeros(64, dtype=np.int64)
+        r = lib().kappa_hierarchy_round_stats(self.handle, l, p.ctypes.data_as(ctypes.c_void_p),
+                                              d.ctypes.data_as(ctypes.c_void_p), 64)
+        k = min(r, 64)
+        return int(r), p[:k].copy(), d[:k].copy()
+
+    def level(self, l: int) -> LevelView:
+        """Copies level l into torch tensors."""
+        import torch
+        g = c_graph()
+        cm = ctypes.c_void_p()
+        inf = c_level_info()
+        _check("kappa_hierarchy_level", lib().kappa_hierarchy_level(self.handle, l, ctypes.byref(g),
+                                                                    ctypes.byref(cm), ctypes.byref(inf)))
+        n, m = int(g.n), int(g.nnz)
+        dg = DeviceGraph(n, m, _copy_from_ptr(g.xadj, n + 1, torch.int64, self.device),
+                         _copy_from_ptr(g.adj, m, torch.int32, self.device),
+                         _copy_from_ptr(g.ew, m, torch.int32, self.device),
+                         _copy_from_ptr(g.vw, n, torch.int32, self.device))
+        cmap = _copy_from_ptr(cm.value, n, torch.int32, self.device) if cm.value else None
+        return LevelView(dg, cmap, int(inf.rounds), int(inf.matched), int(inf.stop_reason))
+
+
+def kappa_coarsen(g: DeviceGraph, rating: int = EXPANSION_STAR2, seed: int = 42, stop_n: int = 256,
+                  stall_num: int = 1, stall_den: int = 20, max_levels: int = 64) -> Hierarchy:
+    p = c_params(rating, seed & (2**64 - 1), stop_n, stall_num, stall_den, max_levels)
+    h = ctypes.c_void_p()
+    _check("kappa_coarsen", lib().kappa_coarsen(ctypes.byref(g.c()), ctypes.byref(p), ctypes.byref(h),
+                                                _stream()))
+    return Hierarchy(h, g.xadj.device, g)
+
+
+def kappa_initial_partition(n: int, k: int, seed: int, device="cuda"):
+    import torch
+    part = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+    _check("kappa_initial_partition", lib().kappa_initial_partition(n, k, ctypes.c_uint64(seed),
+                                                                    _ptr(part), _stream()))
+    return part[:n]
+
+
+def kappa_project(cmap, n_coarse: int, part_coarse):
+    import torch
+    n = int(cmap.numel())
+    out = torch.empty(max(n, 1), dtype=torch.int32, device=cmap.device)
+    _check("kappa_project", lib().kappa_project(_ptr(cmap), n, n_coarse, _ptr(part_coarse),
+                                                _ptr(out), _stream()))
+    return out[:n]
+
+
+def kappa_cut_balance(g: DeviceGraph, part, k: int, eps_num: int = 3, eps_den: int = 100):
+    """Returns (c_cut result, block weights as an int64 tensor)."""
+    import torch
+    bw = torch.empty(max(k, 1), dtype=torch.int64, device=g.xadj.device)
+    res = c_cut()
+    _check("kappa_cut_balance", lib().kappa_cut_balance(ctypes.byref(g.c()), _ptr(part), k, eps_num,
+                                                        eps_den, _ptr(bw), ctypes.byref(res),
+                                                        _stream()))
+    return res, bw[:k]
+
+
+def kappa_uncoarsen(h: Hierarchy, k: int, part_seed: int = 1, eps_num: int = 3, eps_den: int = 100,
+                    part0=None):
+    """Returns (level-0 partition tensor, [c_cut per level])."""
+    import torch
+    n0 = int(h.info(0).n)
+    if part0 is None:
+        part0 = torch.empty(max(n0, 1), dtype=torch.int32, device=h.device)
+    L = len(h)
+    res = (c_cut * L)()
+    _check("kappa_uncoarsen", lib().kappa_uncoarsen(h.handle, k, ctypes.c_uint64(part_seed), eps_num,
+                                                    eps_den, _ptr(part0), res, _stream()))
+    return part0[:n0], list(res)
+
+
+def profile_enable(on: bool = True):
+    lib().kappa_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    lib().kappa_profile_reset()
+
+
+def profile_read():
+    """{kernel name: (launches, milliseconds)} since the last reset."""
+    cap = 128
+    names = (ctypes.c_char_p * cap)()
+    launches = (ctypes.c_int64 * cap)()
+    ms = (ctypes.c_double * cap)()
+    n = lib().kappa_profile_read(names, launches, ms, cap)
+    return {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(min(n, cap))}

@@ -1,0 +1,447 @@
+// k_graph.hip -- CSR sweeps: validation, Out(v), ratings, initial partition,
+// projection, cut/balance, plus the scan helper kernel.
+//
+// The per-entry sweeps (validation, Out, ratings, cut) are load balanced by
+// entries, not rows: block t owns entries [t*ETILE, (t+1)*ETILE).  A small
+// pre-pass records the row holding each tile's first entry; a block stages the
+// row offsets of its tile in LDS and finds each entry's row by binary search
+// there.  Reads of adj/ew are fully coalesced and a node of any degree costs
+// the same per entry (power-law hubs spread over many blocks).
+#include "kappa_internal.h"
+
+namespace kappa {
+
+constexpr int ETILE_ITEMS = 8;
+constexpr int ETILE = BLOCK * ETILE_ITEMS;   // 2048 entries per block
+constexpr int ETILE_ROWS = 2048;             // row offsets staged in LDS
+
+// ---------------------------------------------------------------------------
+__global__ void fill_u32_k(uint32_t *p, int64_t n, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void fill_u64_k(uint64_t *p, int64_t n, uint64_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n <= 0) return;
+    KAPPA_PROF("fill", s);
+    hipLaunchKernelGGL(fill_u32_k, dim3(grid_for(n, BLOCK, 4096)), dim3(BLOCK), 0, s, p, n, v);
+}
+void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s) {
+    if (n <= 0) return;
+    KAPPA_PROF("fill", s);
+    hipLaunchKernelGGL(fill_u64_k, dim3(grid_for(n, BLOCK, 4096)), dim3(BLOCK), 0, s, p, n, v);
+}
+
+// ---------------------------------------------------------------------------
+// One-block exclusive scan of the tile sums of launch_scan.
+// ---------------------------------------------------------------------------
+__global__ void scan_partials_k(int64_t *partials, int64_t nparts, int64_t *total) {
+    __shared__ int64_t sh[1024 / WAVE + 1];
+    int64_t per = (nparts + blockDim.x - 1) / blockDim.x;
+    int64_t b = (int64_t)threadIdx.x * per, e = b + per < nparts ? b + per : nparts;
+    int64_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += partials[i];
+    int64_t tot;
+    int64_t pre = block_excl_scan(s, sh, &tot);
+    for (int64_t i = b; i < e; ++i) {
+        int64_t t = partials[i];
+        partials[i] = pre;
+        pre += t;
+    }
+    if (threadIdx.x == 0 && total) *total = tot;
+}
+
+// ---------------------------------------------------------------------------
+// Entry tiles
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int64_t etiles(int64_t nnz) { return (nnz + ETILE - 1) / ETILE; }
+int64_t tile_rows_needed(int64_t nnz) { return etiles(nnz) + 1; }
+
+// tile_row[t] = row holding entry t*ETILE (largest v with xadj[v] <= t*ETILE).
+__global__ void tile_rows_k(DevGraph g, int32_t *tile_row, int64_t ntiles) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        int64_t b = g.xadj[v], e = g.xadj[v + 1];
+        if (b < 0 || e > g.nnz || e <= b) continue;   // also safe on broken offsets
+        for (int64_t t = (b + ETILE - 1) / ETILE; t * ETILE < e && t < ntiles; ++t)
+            tile_row[t] = (int32_t)v;
+    }
+}
+
+void launch_tile_rows(const DevGraph &g, int32_t *tile_row, hipStream_t s) {
+    int64_t nt = etiles(g.nnz);
+    if (nt == 0) return;
+    KAPPA_PROF("tile_rows", s);
+    hipLaunchKernelGGL(tile_rows_k, dim3(grid_for(g.n, BLOCK, 8192)), dim3(BLOCK), 0, s, g,
+                       tile_row, nt);
+}
+
+struct TileCtx {
+    int64_t j0, j1;
+    int32_t r0, r1;
+    bool lds;
+};
+
+// Sets up the block's tile: LDS offsets of rows r0..r1 (+1) when they fit.
+__device__ __forceinline__ TileCtx tile_begin(const DevGraph &g, const int32_t *tile_row,
+                                              int64_t *s_off) {
+    TileCtx t;
+    t.j0 = (int64_t)blockIdx.x * ETILE;
+    t.j1 = t.j0 + ETILE < g.nnz ? t.j0 + ETILE : g.nnz;
+    t.r0 = tile_row[blockIdx.x];
+    int64_t last_tile = etiles(g.nnz) - 1;
+    t.r1 = (int64_t)blockIdx.x < last_tile ? tile_row[blockIdx.x + 1] : g.n - 1;
+    int32_t nr = t.r1 - t.r0 + 1;
+    t.lds = nr <= ETILE_ROWS;
+    if (t.lds)
+        for (int i = threadIdx.x; i <= nr; i += blockDim.x) s_off[i] = g.xadj[t.r0 + i];
+    __syncthreads();
+    return t;
+}
+
+// Row of entry j inside the tile.
+__device__ __forceinline__ int32_t tile_row_of(const DevGraph &g, const TileCtx &t,
+                                               const int64_t *s_off, int64_t j) {
+    int32_t lo, hi;
+    if (t.lds) {
+        lo = 0; hi = t.r1 - t.r0;
+        while (lo < hi) {
+            int32_t mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= j) lo = mid; else hi = mid - 1;
+        }
+        return t.r0 + lo;
+    }
+    lo = t.r0; hi = t.r1;
+    while (lo < hi) {
+        int32_t mid = lo + ((hi - lo + 1) >> 1);
+        if (g.xadj[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t tile_row_start(const DevGraph &g, const TileCtx &t,
+                                                  const int64_t *s_off, int32_t v) {
+    return t.lds ? s_off[v - t.r0] : g.xadj[v];
+}
+
+// ---------------------------------------------------------------------------
+// Validation (Section 2 graph model).  flags: 1 = offsets, 2 = structure,
+// 4 = weight range.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(BLOCK) validate_offsets_k(DevGraph g, uint32_t *flags,
+                                                            uint64_t *sums) {
+    __shared__ uint64_t sh[BLOCK / WAVE + 1];
+    uint32_t bad = 0;
+    uint64_t csum = 0;
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v == 0 && (g.xadj[0] != 0 || g.xadj[g.n] != g.nnz)) bad |= 1;
+    if (v < g.n) {
+        if (g.xadj[v + 1] < g.xadj[v]) bad |= 1;
+        csum = g.vw[v];
+    }
+    csum = block_sum(csum, sh);
+    if (threadIdx.x == 0 && csum) atomicAdd((unsigned long long *)&sums[1], (unsigned long long)csum);
+    if (bad) atomicOr(flags, bad);
+}
+
+__global__ void __launch_bounds__(BLOCK) validate_entries_k(DevGraph g, const int32_t *tile_row,
+                                                            uint32_t *flags, uint64_t *sums) {
+    __shared__ int64_t s_off[ETILE_ROWS + 1];
+    __shared__ uint64_t sh[BLOCK / WAVE + 1];
+    if (flags[0] & 1u) return;   // offsets broken: rows cannot be read safely
+    TileCtx t = tile_begin(g, tile_row, s_off);
+    uint32_t bad = 0;
+    uint64_t wsum = 0;
+    for (int i = 0; i < ETILE_ITEMS; ++i) {
+        int64_t j = t.j0 + (int64_t)i * BLOCK + threadIdx.x;
+        if (j >= t.j1) break;
+        int32_t v = tile_row_of(g, t, s_off, j);
+        int32_t u = g.adj[j];
+        uint32_t w = g.ew[j];
+        if (u < 0 || u >= g.n || u == v) { bad |= 2; continue; }
+        if (j > tile_row_start(g, t, s_off, v) && g.adj[j - 1] >= u) bad |= 2;
+        // the reverse entry (v in row u) must exist with the same weight
+        int64_t lo = g.xadj[u], hi = g.xadj[u + 1] - 1;
+        bool found = false;
+        while (lo <= hi) {
+            int64_t mid = (lo + hi) >> 1;
+            int32_t x = g.adj[mid];
+            if (x == v) { found = g.ew[mid] == w; break; }
+            if (x < v) lo = mid + 1; else hi = mid - 1;
+        }
+        if (!found) bad |= 2;
+        if (w == 0) bad |= 4;
+        if (u > v) wsum += w;
+    }
+    wsum = block_sum(wsum, sh);
+    if (threadIdx.x == 0 && wsum) atomicAdd((unsigned long long *)&sums[0], (unsigned long long)wsum);
+    if (bad) atomicOr(flags, bad);
+}
+
+void launch_validate(const DevGraph &g, int32_t *tile_row, uint32_t *flags, uint64_t *sums,
+                     hipStream_t s) {
+    // tile rows are written after the offsets check only when offsets are
+    // sane; tile_rows_k itself only reads xadj[v], xadj[v+1] pairs and stops
+    // at ntiles, so it is safe on any offsets.
+    int64_t nt = etiles(g.nnz);
+    {
+        KAPPA_PROF("validate_offsets", s);
+        hipLaunchKernelGGL(validate_offsets_k, dim3(grid_for((int64_t)g.n + 1, BLOCK, 1u << 30)),
+                           dim3(BLOCK), 0, s, g, flags, sums);
+    }
+    if (nt == 0) return;
+    launch_tile_rows(g, tile_row, s);
+    KAPPA_PROF("validate_entries", s);
+    hipLaunchKernelGGL(validate_entries_k, dim3((unsigned)nt), dim3(BLOCK), 0, s, g, tile_row,
+                       flags, sums);
+}
+
+// ---------------------------------------------------------------------------
+// Out(v) = sum of w over the edges at v (Section 3.1, innerOuter).  Row sums
+// are gathered in LDS per tile, then added to out[] (zeroed first).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(BLOCK) out_k(DevGraph g, const int32_t *tile_row,
+                                               uint32_t *out) {
+    __shared__ int64_t s_off[ETILE_ROWS + 1];
+    __shared__ uint32_t s_sum[ETILE_ROWS];
+    TileCtx t = tile_begin(g, tile_row, s_off);
+    int32_t nr = t.r1 - t.r0 + 1;
+    if (t.lds)
+        for (int i = threadIdx.x; i < nr; i += blockDim.x) s_sum[i] = 0;
+    __syncthreads();
+    for (int i = 0; i < ETILE_ITEMS; ++i) {
+        int64_t j = t.j0 + (int64_t)i * BLOCK + threadIdx.x;
+        if (j >= t.j1) break;
+        int32_t v = tile_row_of(g, t, s_off, j);
+        if (t.lds) atomicAdd(&s_sum[v - t.r0], g.ew[j]);
+        else atomicAdd(&out[v], g.ew[j]);
+    }
+    __syncthreads();
+    if (t.lds)
+        for (int i = threadIdx.x; i < nr; i += blockDim.x)
+            if (s_sum[i]) atomicAdd(&out[t.r0 + i], s_sum[i]);
+}
+
+void launch_out(const DevGraph &g, const int32_t *tr, uint32_t *out, hipStream_t s) {
+    launch_fill_u32(out, g.n, 0, s);
+    int64_t nt = etiles(g.nnz);
+    if (nt == 0) return;
+    KAPPA_PROF("out", s);
+    hipLaunchKernelGGL(out_k, dim3((unsigned)nt), dim3(BLOCK), 0, s, g, tr, out);
+}
+
+// ---------------------------------------------------------------------------
+// Ratings of every entry (Section 3.1).
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ void __launch_bounds__(BLOCK) rate_k(DevGraph g, const int32_t *tile_row,
+                                                const uint32_t *out, uint64_t *num,
+                                                uint64_t *den) {
+    __shared__ int64_t s_off[ETILE_ROWS + 1];
+    TileCtx t = tile_begin(g, tile_row, s_off);
+    for (int i = 0; i < ETILE_ITEMS; ++i) {
+        int64_t j = t.j0 + (int64_t)i * BLOCK + threadIdx.x;
+        if (j >= t.j1) break;
+        int32_t v = tile_row_of(g, t, s_off, j);
+        int32_t u = g.adj[j];
+        uint32_t ou = 0, ov = 0;
+        if (R == KAPPA_INNER_OUTER) { ou = out[u]; ov = out[v]; }
+        uint64_t a, b;
+        rate<R>(g.ew[j], g.vw[u], g.vw[v], ou, ov, a, b);
+        num[j] = a;
+        den[j] = b;
+    }
+}
+
+void launch_rate(const DevGraph &g, const int32_t *tr, int rating, const uint32_t *out,
+                 uint64_t *num, uint64_t *den, hipStream_t s) {
+    int64_t nt = etiles(g.nnz);
+    if (nt == 0) return;
+    KAPPA_PROF("rate", s);
+    dim3 gr((unsigned)nt), bl(BLOCK);
+    switch (rating) {
+    case KAPPA_INNER_OUTER: hipLaunchKernelGGL(rate_k<KAPPA_INNER_OUTER>, gr, bl, 0, s, g, tr, out, num, den); break;
+    case KAPPA_WEIGHT: hipLaunchKernelGGL(rate_k<KAPPA_WEIGHT>, gr, bl, 0, s, g, tr, out, num, den); break;
+    case KAPPA_EXPANSION: hipLaunchKernelGGL(rate_k<KAPPA_EXPANSION>, gr, bl, 0, s, g, tr, out, num, den); break;
+    case KAPPA_EXPANSION_STAR: hipLaunchKernelGGL(rate_k<KAPPA_EXPANSION_STAR>, gr, bl, 0, s, g, tr, out, num, den); break;
+    default: hipLaunchKernelGGL(rate_k<KAPPA_EXPANSION_STAR2>, gr, bl, 0, s, g, tr, out, num, den); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Matching check for externally supplied mate arrays.
+// ---------------------------------------------------------------------------
+__global__ void check_matching_k(DevGraph g, const int32_t *mate, uint32_t *flags) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        int32_t m = mate[v];
+        if (m == -1) continue;
+        if (m < 0 || m >= g.n || m == v || mate[m] != v) { atomicOr(flags, 1u); continue; }
+        int64_t lo = g.xadj[v], hi = g.xadj[v + 1] - 1;
+        bool found = false;
+        while (lo <= hi) {
+            int64_t mid = (lo + hi) >> 1;
+            int32_t x = g.adj[mid];
+            if (x == m) { found = true; break; }
+            if (x < m) lo = mid + 1; else hi = mid - 1;
+        }
+        if (!found) atomicOr(flags, 1u);
+    }
+}
+
+void launch_check_matching(const DevGraph &g, const int32_t *mate, uint32_t *flags,
+                           hipStream_t s) {
+    if (g.n <= 0) return;
+    KAPPA_PROF("check_matching", s);
+    hipLaunchKernelGGL(check_matching_k, dim3(grid_for(g.n, BLOCK, 4096)), dim3(BLOCK), 0, s, g,
+                       mate, flags);
+}
+
+// ---------------------------------------------------------------------------
+// Initial partition stand-in and projection (Section 2, uncontraction).
+// ---------------------------------------------------------------------------
+__global__ void initial_partition_k(int32_t n, int32_t k, uint64_t seed, int32_t *part) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * blockDim.x)
+        part[x] = (int32_t)(mix64(seed + (uint64_t)x) % (uint64_t)k);
+}
+
+void launch_initial_partition(int32_t n, int32_t k, uint64_t seed, int32_t *part,
+                              hipStream_t s) {
+    if (n <= 0) return;
+    KAPPA_PROF("initial_partition", s);
+    hipLaunchKernelGGL(initial_partition_k, dim3(grid_for(n, BLOCK, 4096)), dim3(BLOCK), 0, s, n,
+                       k, seed, part);
+}
+
+__global__ void project_k(const int32_t *cmap, int32_t n_fine, int32_t n_coarse,
+                          const int32_t *part_coarse, int32_t *part_fine, uint32_t *flag) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n_fine;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        int32_t c = cmap[v];
+        if (c < 0 || c >= n_coarse) {
+            part_fine[v] = -1;
+            if (flag) atomicOr(flag, 1u);
+        } else {
+            part_fine[v] = part_coarse[c];
+        }
+    }
+}
+
+void launch_project(const int32_t *cmap, int32_t n_fine, int32_t n_coarse,
+                    const int32_t *part_coarse, int32_t *part_fine, uint32_t *flag,
+                    hipStream_t s) {
+    if (n_fine <= 0) return;
+    KAPPA_PROF("project", s);
+    hipLaunchKernelGGL(project_k, dim3(grid_for(n_fine, BLOCK, 8192)), dim3(BLOCK), 0, s, cmap,
+                       n_fine, n_coarse, part_coarse, part_fine, flag);
+}
+
+// ---------------------------------------------------------------------------
+// Cut and balance (Section 2; imbalance of Section 5.2).
+// acc[0] = cut, acc[1] = c(V), acc[2] = max_v c(v).
+// ---------------------------------------------------------------------------
+constexpr int CUT_NODE_BLOCKS = 256;
+
+__global__ void __launch_bounds__(BLOCK) cut_nodes_k(DevGraph g, const int32_t *part, int32_t k,
+                                                     uint64_t *block_w, uint64_t *acc,
+                                                     uint32_t *flag) {
+    extern __shared__ uint64_t s_hist[];   // k entries
+    __shared__ uint64_t sh[BLOCK / WAVE + 1];
+    for (int i = threadIdx.x; i < k; i += blockDim.x) s_hist[i] = 0;
+    __syncthreads();
+    uint64_t tot = 0;
+    uint32_t mx = 0, bad = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        int32_t p = part[v];
+        uint32_t c = g.vw[v];
+        if (p < 0 || p >= k) { bad = 1; continue; }
+        if (c) atomicAdd((unsigned long long *)&s_hist[p], (unsigned long long)c);
+        tot += c;
+        mx = c > mx ? c : mx;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += blockDim.x)
+        if (s_hist[i]) atomicAdd((unsigned long long *)&block_w[i], (unsigned long long)s_hist[i]);
+    tot = block_sum(tot, sh);
+    mx = wave_max(mx);
+    if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&acc[1], (unsigned long long)tot);
+    if (lane_id() == 0 && mx) atomicMax((unsigned long long *)&acc[2], (unsigned long long)mx);
+    if (bad) atomicOr(flag, 2u);
+}
+
+__global__ void __launch_bounds__(BLOCK) cut_entries_k(DevGraph g, const int32_t *tile_row,
+                                                       const int32_t *part, uint64_t *acc) {
+    __shared__ int64_t s_off[ETILE_ROWS + 1];
+    __shared__ uint64_t sh[BLOCK / WAVE + 1];
+    TileCtx t = tile_begin(g, tile_row, s_off);
+    uint64_t cut = 0;
+    for (int i = 0; i < ETILE_ITEMS; ++i) {
+        int64_t j = t.j0 + (int64_t)i * BLOCK + threadIdx.x;
+        if (j >= t.j1) break;
+        int32_t v = tile_row_of(g, t, s_off, j);
+        int32_t u = g.adj[j];
+        if (u > v && part[u] != part[v]) cut += g.ew[j];
+    }
+    cut = block_sum(cut, sh);
+    if (threadIdx.x == 0 && cut) atomicAdd((unsigned long long *)&acc[0], (unsigned long long)cut);
+}
+
+typedef unsigned __int128 u128;
+
+__global__ void __launch_bounds__(BLOCK) cut_finalize_k(const uint64_t *block_w, int32_t k,
+                                                        uint32_t eps_num, uint32_t eps_den,
+                                                        const uint64_t *acc,
+                                                        kappa_cut_result *res) {
+    __shared__ uint64_t sh[BLOCK / WAVE];
+    uint64_t mx = 0;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) mx = block_w[i] > mx ? block_w[i] : mx;
+    mx = wave_max(mx);
+    if (lane_id() == 0) sh[threadIdx.x / WAVE] = mx;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int i = 1; i < BLOCK / WAVE; ++i) mx = sh[i] > mx ? sh[i] : mx;
+    uint64_t total = acc[1], maxc = acc[2];
+    // L_max = (1 + eps) c(V) / k + max c(v) = lnum / lden, lden = k * eps_den
+    u128 lnum = (u128)((uint64_t)eps_den + eps_num) * total + (u128)((uint64_t)k * eps_den) * maxc;
+    u128 lden = (u128)k * eps_den;
+    u128 lhs = lden * mx;
+    res->cut = acc[0];
+    res->total = total;
+    res->max_block = mx;
+    res->max_node = maxc;
+    res->lmax_num = (uint64_t)lnum;
+    res->lmax_den = (uint64_t)lden;
+    res->imb_num = lhs > lnum ? (uint64_t)(lhs - lnum) : 0;
+    res->bal_num = (uint64_t)k * mx;
+    res->bal_den = total;
+    res->feasible = lhs <= lnum ? 1 : 0;
+}
+
+void launch_cut_balance(const DevGraph &g, const int32_t *tr, const int32_t *part, int32_t k,
+                        uint32_t eps_num, uint32_t eps_den, uint64_t *block_w, uint64_t *acc,
+                        uint32_t *flag, kappa_cut_result *res_dev, hipStream_t s) {
+    launch_fill_u64(block_w, k, 0, s);
+    launch_fill_u64(acc, 3, 0, s);
+    if (g.n > 0) {
+        KAPPA_PROF("cut_nodes", s);
+        hipLaunchKernelGGL(cut_nodes_k, dim3(grid_for(g.n, BLOCK, CUT_NODE_BLOCKS)), dim3(BLOCK),
+                           (size_t)k * sizeof(uint64_t), s, g, part, k, block_w, acc, flag);
+    }
+    int64_t nt = etiles(g.nnz);
+    if (nt > 0) {
+        KAPPA_PROF("cut_entries", s);
+        hipLaunchKernelGGL(cut_entries_k, dim3((unsigned)nt), dim3(BLOCK), 0, s, g, tr, part, acc);
+    }
+    KAPPA_PROF("cut_finalize", s);
+    hipLaunchKernelGGL(cut_finalize_k, dim3(1), dim3(BLOCK), 0, s, block_w, k, eps_num, eps_den,
+                       acc, res_dev);
+}
+
+}  // namespace kappa

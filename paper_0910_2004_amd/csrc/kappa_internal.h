@@ -1,0 +1,357 @@
+// kappa_internal.h -- device helpers and launch-wrapper declarations shared by
+// the library's translation units.  gfx950 only (64-lane wavefronts).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/kappa.h"
+
+namespace kappa {
+
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;          // threads per block of the sweep kernels
+constexpr int SCAN_ITEMS = 8;       // items per thread in the scan tiles
+constexpr int SCAN_TILE = BLOCK * SCAN_ITEMS;
+
+// Degree classes of the node-centric kernels.
+constexpr int BIN_SMALL_MAX = 16;   // deg <= 16: 8 lanes per node
+constexpr int BIN_MID_MAX = 1024;   // deg <= 1024: one wave per node; above: one block
+constexpr int SMALL_G = 8;
+
+// Matching rounds: a single workgroup finishes once at most TAIL_MAX nodes
+// still point somewhere.
+constexpr int TAIL_MAX = 2048;
+constexpr int FINISH_THREADS = 1024;
+constexpr int MAX_ROUND_STATS = 4096;
+
+// Row classes of the contraction (bound = deg(u) + deg(v) - 2 for a pair).
+constexpr int ROW_SMALL_MAX = 64;   // 16 lanes per row, rank sort in LDS
+constexpr int ROW_SMALL_G = 16;
+constexpr int ROW_MID_MAX = 4094;   // one block per row, bitonic sort of <= 4096 in LDS
+constexpr int HUB_SLOTS = 32;       // rows above ROW_MID_MAX: dense accumulators
+
+struct DevGraph {
+    int32_t n;
+    int64_t nnz;
+    const int64_t *xadj;
+    const int32_t *adj;
+    const uint32_t *ew;
+    const uint32_t *vw;
+};
+
+// ---------------------------------------------------------------------------
+// SplitMix64 output function (Steele, Lea, Flood 2014), the tie-break hash.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+__host__ __device__ inline uint64_t edge_id(int32_t a, int32_t b) {
+    uint32_t lo = (uint32_t)(a < b ? a : b), hi = (uint32_t)(a < b ? b : a);
+    return ((uint64_t)lo << 32) | hi;
+}
+
+// ---------------------------------------------------------------------------
+// Ratings (Section 3.1) as exact rationals.  Out() is only read by innerOuter.
+// ---------------------------------------------------------------------------
+template <int R>
+__device__ __forceinline__ void rate(uint32_t w, uint32_t cu, uint32_t cv, uint32_t ou,
+                                     uint32_t ov, uint64_t &num, uint64_t &den) {
+    if (R == KAPPA_WEIGHT) { num = w; den = 1; }
+    else if (R == KAPPA_EXPANSION) { num = w; den = (uint64_t)cu + cv; }
+    else if (R == KAPPA_EXPANSION_STAR) { num = w; den = (uint64_t)cu * cv; }
+    else if (R == KAPPA_INNER_OUTER) { num = w; den = (uint64_t)ou + ov - 2ull * w; }
+    else { num = (uint64_t)w * w; den = (uint64_t)cu * cv; }
+}
+
+// A candidate edge {v, u} seen from v.  u < 0 means "none".
+struct Cand {
+    uint64_t num, den, h;
+    int32_t u;
+};
+
+__device__ __forceinline__ Cand cand_none() {
+    Cand c;
+    c.num = 0; c.den = 1; c.h = 0; c.u = -1;
+    return c;
+}
+
+// a above b in the strict order (both incident to v).  Rational part by
+// 128-bit cross products num_a*den_b vs num_b*den_a, then hash, then the
+// smaller edge id.
+__device__ __forceinline__ bool cand_better(const Cand &a, const Cand &b, int32_t v) {
+    if (a.u < 0) return false;
+    if (b.u < 0) return true;
+    uint64_t l_lo = a.num * b.den, l_hi = __umul64hi(a.num, b.den);
+    uint64_t r_lo = b.num * a.den, r_hi = __umul64hi(b.num, a.den);
+    if (l_hi != r_hi) return l_hi > r_hi;
+    if (l_lo != r_lo) return l_lo > r_lo;
+    if (a.h != b.h) return a.h > b.h;
+    return edge_id(v, a.u) < edge_id(v, b.u);
+}
+
+__device__ __forceinline__ Cand cand_shfl_xor(const Cand &c, int mask, int width) {
+    Cand o;
+    o.num = __shfl_xor(c.num, mask, width);
+    o.den = __shfl_xor(c.den, mask, width);
+    o.h = __shfl_xor(c.h, mask, width);
+    o.u = __shfl_xor(c.u, mask, width);
+    return o;
+}
+
+// ---------------------------------------------------------------------------
+// Wave / block primitives
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    int l = lane_id();
+    return l == 0 ? 0ull : ((~0ull) >> (64 - l));
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+    for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_max(T v) {
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        T o = __shfl_xor(v, off, WAVE);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Inclusive scan over the wave.
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    int l = lane_id();
+    for (int off = 1; off < WAVE; off <<= 1) {
+        T o = __shfl_up(v, off, WAVE);
+        if (l >= off) v += o;
+    }
+    return v;
+}
+
+// Block-wide exclusive scan of one value per thread (blockDim.x <= 1024).
+// `sh` must hold blockDim.x / WAVE + 1 entries.  Returns the exclusive prefix;
+// *total receives the block sum.  Contains __syncthreads.
+template <class T>
+__device__ T block_excl_scan(T v, T *sh, T *total) {
+    int w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    T inc = wave_incl_scan(v);
+    if (lane_id() == WAVE - 1) sh[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T run = 0;
+        for (int i = 0; i < nw; ++i) { T t = sh[i]; sh[i] = run; run += t; }
+        sh[nw] = run;
+    }
+    __syncthreads();
+    T res = sh[w] + inc - v;
+    *total = sh[nw];
+    __syncthreads();
+    return res;
+}
+
+// Appends val to list where pred holds, one atomic per wave.  All 64 lanes
+// must call it (wave-uniform control flow).  Order inside the list is not
+// deterministic; no consumer depends on it.
+__device__ __forceinline__ void wave_append(bool pred, int32_t val, int32_t *list,
+                                            int32_t *counter) {
+    uint64_t mask = __ballot(pred);
+    if (mask == 0) return;
+    int leader = __ffsll((unsigned long long)mask) - 1;
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(counter, (int)__popcll(mask));
+    base = __shfl(base, leader, WAVE);
+    if (pred) list[base + __popcll(mask & lanemask_lt())] = val;
+}
+
+template <class T>
+__device__ T block_sum(T v, T *sh) {
+    T t;
+    block_excl_scan(v, sh, &t);
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Generic exclusive scan over up to n_max items (three kernels: tile sums,
+// one-block scan of the tile sums, rescan with offsets).  F(i) -> int64 value
+// (0 past the live size), W(i, prefix, value) stores.
+// ---------------------------------------------------------------------------
+template <class F>
+__global__ void __launch_bounds__(BLOCK) scan_reduce_k(int64_t n_max, F f, int64_t *partials) {
+    __shared__ int64_t sh[BLOCK / WAVE + 1];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int64_t s = 0;
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        int64_t idx = base + (int64_t)i * BLOCK + threadIdx.x;
+        if (idx < n_max) s += f(idx);
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void scan_partials_k(int64_t *partials, int64_t nparts, int64_t *total);
+
+template <class F, class W>
+__global__ void __launch_bounds__(BLOCK) scan_apply_k(int64_t n_max, F f, W w,
+                                                       const int64_t *partials) {
+    __shared__ int64_t sh[BLOCK / WAVE + 1];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    // each thread owns SCAN_ITEMS consecutive items
+    int64_t first = base + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int64_t vals[SCAN_ITEMS];
+    int64_t s = 0;
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        int64_t idx = first + i;
+        vals[i] = idx < n_max ? f(idx) : 0;
+        s += vals[i];
+    }
+    int64_t tot;
+    int64_t pre = block_excl_scan(s, sh, &tot) + partials[blockIdx.x];
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        int64_t idx = first + i;
+        if (idx < n_max) w(idx, pre, vals[i]);
+        pre += vals[i];
+    }
+}
+
+inline int64_t scan_tiles(int64_t n_max) { return (n_max + SCAN_TILE - 1) / SCAN_TILE; }
+
+// Scratch for a scan: scan_tiles(n_max) + 1 int64 partials.
+template <class F, class W>
+inline void launch_scan(int64_t n_max, F f, W w, int64_t *partials, int64_t *total,
+                        hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Profiling (events around launches), implemented in api.hip
+// ---------------------------------------------------------------------------
+struct ProfScope {
+    int id;
+    hipStream_t s;
+    ProfScope(const char *name, hipStream_t s);
+    ~ProfScope();
+};
+#define KAPPA_PROF(name, stream) ::kappa::ProfScope _kappa_prof_scope(name, stream)
+
+template <class F, class W>
+inline void launch_scan(int64_t n_max, F f, W w, int64_t *partials, int64_t *total,
+                        hipStream_t s) {
+    int64_t tiles = scan_tiles(n_max);
+    if (tiles == 0) tiles = 1;
+    {
+        KAPPA_PROF("scan_reduce", s);
+        hipLaunchKernelGGL(scan_reduce_k<F>, dim3((unsigned)tiles), dim3(BLOCK), 0, s, n_max, f,
+                           partials);
+    }
+    {
+        KAPPA_PROF("scan_partials", s);
+        hipLaunchKernelGGL(scan_partials_k, dim3(1), dim3(1024), 0, s, partials, tiles, total);
+    }
+    {
+        KAPPA_PROF("scan_apply", s);
+        hipLaunchKernelGGL((scan_apply_k<F, W>), dim3((unsigned)tiles), dim3(BLOCK), 0, s, n_max,
+                           f, w, partials);
+    }
+}
+
+inline unsigned grid_for(int64_t items, int per_block, unsigned cap = 65535u * 4) {
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > (int64_t)cap) g = cap;
+    return (unsigned)g;
+}
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (host functions) per translation unit
+// ---------------------------------------------------------------------------
+// k_graph.hip
+void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
+// Entry tiles: tile_row[t] = row holding CSR entry t * 2048.  Needs
+// tile_rows_needed(nnz) int32 entries.  Valid until the graph changes.
+int64_t tile_rows_needed(int64_t nnz);
+void launch_tile_rows(const DevGraph &g, int32_t *tile_row, hipStream_t s);
+// flags: bit0 offsets, bit1 structure, bit2 range; sums[0] = sum w(E), sums[1] = sum c(V).
+// Computes its own tile rows into tile_row.
+void launch_validate(const DevGraph &g, int32_t *tile_row, uint32_t *flags, uint64_t *sums,
+                     hipStream_t s);
+void launch_out(const DevGraph &g, const int32_t *tile_row, uint32_t *out, hipStream_t s);
+void launch_rate(const DevGraph &g, const int32_t *tile_row, int rating, const uint32_t *out,
+                 uint64_t *num, uint64_t *den, hipStream_t s);
+// flags |= 1 if mate is not a matching of g (entry out of range, not
+// symmetric, or a matched pair that is not an edge).
+void launch_check_matching(const DevGraph &g, const int32_t *mate, uint32_t *flags,
+                           hipStream_t s);
+void launch_initial_partition(int32_t n, int32_t k, uint64_t seed, int32_t *part,
+                              hipStream_t s);
+void launch_project(const int32_t *cmap, int32_t n_fine, int32_t n_coarse,
+                    const int32_t *part_coarse, int32_t *part_fine, uint32_t *flag,
+                    hipStream_t s);
+// acc: [0]=cut [1]=total [2]=max_node; block_w[k] zeroed inside
+void launch_cut_balance(const DevGraph &g, const int32_t *tile_row, const int32_t *part,
+                        int32_t k, uint32_t eps_num, uint32_t eps_den, uint64_t *block_w,
+                        uint64_t *acc, uint32_t *flag, kappa_cut_result *res_dev, hipStream_t s);
+
+// k_match.hip
+// Device-resident state of the matching rounds of one level.
+struct MatchState {
+    int32_t cnt[4][4];      // [round & 3][bin]: sizes of the pending lists written by a round
+    int32_t handoff;        // -1: rounds continue; r >= 0: the finisher resumes after round r; -2: done
+    int32_t rounds;         // last round in which some node pointed at a neighbour
+    int32_t pad[2];
+    int64_t matched;        // |M|
+    // per round r (index r-1; the last slot aggregates later rounds):
+    // [0] nodes that had a free neighbour, [1] their summed degree
+    int64_t stat[MAX_ROUND_STATS][2];
+};
+struct MatchScratch {
+    int32_t *best;          // n
+    int32_t *lists;         // 6n: pending lists [parity][bin]
+    uint32_t *out;          // n (innerOuter)
+    int32_t *tile_row;      // tile rows of the graph (innerOuter)
+    MatchState *state;
+};
+// Out(v) if needed, mate = best = -1, degree bins for round 1, state reset.
+void launch_match_begin(const DevGraph &g, int rating, int32_t *mate, MatchScratch &ms,
+                        hipStream_t s);
+// Rounds r_first .. r_first + count - 1 (pick + mate kernels each), then the
+// one-workgroup finisher.  maxdeg bounds the degrees of g (selects bins).
+void launch_match_rounds(const DevGraph &g, int rating, uint64_t seed, int32_t maxdeg,
+                         int32_t *mate, MatchScratch &ms, int r_first, int count, hipStream_t s);
+// Max degree of g into *out (device int32, must be zero on entry).
+void launch_max_degree(const DevGraph &g, int32_t *out, hipStream_t s);
+
+// k_contract.hip
+struct ContractScratch {
+    int32_t *rep_of;      // n   coarse -> representative fine node
+    int64_t *tmp_off;     // n+1 padded row offsets
+    int32_t *cdeg;        // n   coarse degrees
+    int32_t *rows;        // 3*n row-class lists
+    int32_t *row_cnt;     // 4   row-class counts
+    int32_t *tmp_adj;     // nnz
+    uint32_t *tmp_ew;     // nnz
+    int64_t *partials;    // scan partials
+    int64_t *totals;      // [0] = n', [1] = padded total, [2] = nnz', [3] = max coarse degree
+    uint32_t *hub_acc;    // HUB_SLOTS * n, all zero between uses (only if hub rows can occur)
+    uint32_t *hub_bits;   // HUB_SLOTS * hub_words, all zero between uses
+    int64_t hub_words;    // n/32 + 1
+};
+// Phase 1: coarse ids, cmap, coarse node weights, padded offsets, merged rows
+// into the padded buffer, coarse degrees and final offsets (cxadj, n'+1).
+// max_bound bounds deg(u) + deg(v) - 2 over the pairs (selects the row classes).
+void launch_contract_build(const DevGraph &g, const int32_t *mate, int64_t max_bound,
+                           int32_t *cmap, uint32_t *cvw, int64_t *cxadj, ContractScratch &cs,
+                           hipStream_t s);
+// Phase 2: copy merged rows into the exact-size coarse arrays.
+void launch_contract_compact(const ContractScratch &cs, int32_t n_fine, int64_t max_bound,
+                             const int64_t *cxadj, int32_t *cadj, uint32_t *cew, hipStream_t s);
+
+}  // namespace kappa

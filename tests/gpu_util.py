@@ -1,0 +1,55 @@
+"""Helpers for the GPU parity tests: run the HIP path through the C ABI and
+compare with the oracle element by element."""
+import numpy as np
+
+import oracle as O
+import paper_0910_2004_amd as K
+
+
+def dev(g):
+    return K.DeviceGraph.from_csr(g, "cuda")
+
+
+def graph_np(dg):
+    x, a, e, v = dg.numpy()
+    return O.Graph(int(dg.n), x.astype(np.int64), a.astype(np.int32), e, v)
+
+
+def assert_graph_equal(got: O.Graph, want: O.Graph, what=""):
+    assert got.n == want.n, f"{what}: n {got.n} != {want.n}"
+    assert np.array_equal(got.xadj, want.xadj), f"{what}: xadj differs"
+    assert np.array_equal(got.adj, want.adj), f"{what}: adj differs"
+    assert np.array_equal(got.ew, want.ew), f"{what}: ew differs"
+    assert np.array_equal(got.vw, want.vw), f"{what}: vw differs"
+
+
+def check_hierarchy(g, rating, seed, stop_n, stall=(1, 20), max_levels=64, k=2,
+                    part_seed=1, eps=(3, 100), check_rounds=True, check_uncoarsen=True,
+                    oracle_h=None):
+    """Coarsen on the GPU and with the oracle; compare every level, map,
+    round count, round statistics and the way back up.  Returns the
+    hierarchy (GPU) and the oracle hierarchy."""
+    H = K.kappa_coarsen(dev(g), rating, seed, stop_n, stall[0], stall[1], max_levels)
+    OH = oracle_h or O.coarsen(g, rating, seed, stop_n, stall[0], stall[1], max_levels,
+                               round_stats=check_rounds)
+    assert len(H) == len(OH.levels), f"levels {len(H)} != {len(OH.levels)}"
+    for l, ol in enumerate(OH.levels):
+        lv = H.level(l)
+        assert_graph_equal(graph_np(lv.graph), ol.graph, f"level {l}")
+        assert lv.stop_reason == ol.stop_reason, f"level {l} stop {lv.stop_reason} != {ol.stop_reason}"
+        if ol.cmap is not None:
+            assert np.array_equal(lv.cmap.cpu().numpy(), ol.cmap), f"level {l}: cmap differs"
+            assert lv.matched == ol.matched
+        if check_rounds and ol.mate is not None:
+            assert lv.rounds == ol.rounds, f"level {l}: rounds {lv.rounds} != {ol.rounds}"
+            r, p, d = H.round_stats(l)
+            kk = min(r, 64)
+            assert np.array_equal(p, ol.round_active[:kk]), f"level {l}: round activity differs"
+            assert np.array_equal(d, ol.round_degree[:kk]), f"level {l}: round degrees differ"
+    if check_uncoarsen:
+        part0, res = K.kappa_uncoarsen(H, k, part_seed, eps[0], eps[1])
+        oparts, ores = O.uncoarsen(OH, k, part_seed, eps[0], eps[1])
+        assert np.array_equal(part0.cpu().numpy(), oparts[0])
+        for l in range(len(OH.levels)):
+            assert res[l].as_tuple() == ores[l].as_tuple(), f"level {l}: cut/balance differs"
+    return H, OH

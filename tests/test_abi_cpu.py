@@ -1,0 +1,53 @@
+"""The C-ABI library loads and exports every function include/kappa.h
+declares (no compute calls: this runs without a GPU)."""
+import ctypes
+import os
+
+import pytest
+
+import paper_0910_2004_amd as K
+
+
+def test_header_declares_the_boundary():
+    names = K.declared_functions()
+    for required in ["kappa_validate", "kappa_rate", "kappa_match", "kappa_contract",
+                     "kappa_coarsen", "kappa_project", "kappa_cut_balance", "kappa_uncoarsen",
+                     "kappa_hierarchy_levels", "kappa_hierarchy_level", "kappa_hierarchy_free",
+                     "kappa_initial_partition", "kappa_status_str"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(os.path.join(os.path.dirname(K.__file__), "libkappa.so")):
+        pytest.fail("libkappa.so is not built (run __graft_entry__.build())")
+    L = K.lib()
+    missing = [n for n in K.declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_version():
+    L = K.lib()
+    for st in range(0, -7, -1):
+        s = L.kappa_status_str(st).decode()
+        assert s and s != "unknown status"
+    assert L.kappa_status_str(5).decode() == "unknown status"
+    assert b"gfx950" in L.kappa_version()
+
+
+def test_null_arguments_rejected_without_gpu_work():
+    L = K.lib()
+    # every entry point checks its arguments before touching the device
+    assert L.kappa_validate(None, None) == K.E_ARG
+    assert L.kappa_coarsen(None, None, None, None) == K.E_ARG
+    assert L.kappa_hierarchy_levels(None) == 0
+    assert L.kappa_hierarchy_level(None, 0, None, None, None) == K.E_ARG
+    assert L.kappa_initial_partition(10, 0, 1, None, None) == K.E_ARG
+    assert L.kappa_initial_partition(10, 5000, 1, None, None) == K.E_ARG
+    g = K._lib.c_graph(-1, 0, None, None, None, None)
+    assert L.kappa_validate(ctypes.byref(g), None) == K.E_ARG
+    assert L.kappa_rate(ctypes.byref(g), 0, None, None, None) == K.E_ARG
+    g = K._lib.c_graph(4, 6, None, None, None, None)
+    assert L.kappa_match(ctypes.byref(g), 0, 1, None, None, None, None) == K.E_ARG
+    g = K._lib.c_graph(0, 0, ctypes.c_void_p(8), None, None, None)
+    assert L.kappa_rate(ctypes.byref(g), 7, None, None, None) == K.E_ARG
+    L.kappa_hierarchy_free(None)
