@@ -1,0 +1,224 @@
+"""Benchmark of the coarsening hierarchy on one MI355X.
+
+A step is one pass of the whole path over the random geometric graph
+workload (n = 2^20 points in the unit square, radius for mean degree 8, unit
+weights), once per rating the workload names (expansion*2 and innerOuter):
+validation, matching + contraction level by level down to 20*k nodes (k=64),
+the coarsest-level partition, then projection and cut/balance on every level
+back to level 0.  The graph is resident in HBM before the timed region.
+
+Prints one JSON line: edges/s = (undirected input edges per step) / (time per
+step), plus the roofline of the dominant kernel (HIP events on the library's
+launch stream, in a second timed pass with per-launch events enabled) and the
+oracle's time on the host for one step (cpu_baseline).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak, GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Algorithmic bytes (element-granular compulsory traffic) of the kernels with
+# an exact per-level model.  D = CSR entries (2|E|), n = nodes of the level.
+# ---------------------------------------------------------------------------
+def bytes_pick_first(n, D, io):
+    # per node: row offsets (8), c(v) (4), best[v] (4) [+ Out(v) (4)]
+    # per entry: adj (4), w (4), c(u) (4) [+ Out(u) (4)]
+    return (20 if io else 16) * n + (16 if io else 12) * D
+
+
+def bytes_fill_small(n, D, nc, Dc, matched):
+    # per coarse row: list entry, rep_of, mate (12), offsets of u (16),
+    # padded offset (8), degree (4); matched rows also read the partner's
+    # offsets (16).  Per fine entry: adj, w, cmap of the neighbour (12).
+    # Per merged coarse entry: key and weight written (8).
+    return 40 * nc + 16 * matched + 12 * D + 8 * Dc
+
+
+def bytes_compact(nc, Dc):
+    # per row: list entry, two offsets, degree (24); per entry: read 8, write 8
+    return 24 * nc + 16 * Dc
+
+
+def bytes_cut_entries(D):
+    # per entry: adj, w, part of both ends
+    return 16 * D
+
+
+MODELS = {"pick_first": "per level: 16 B/node + 12 B/entry (innerOuter 20 + 16)",
+          "fill_small": "per level: 40 B/coarse row + 16 B/matched pair + 12 B/fine entry + 8 B/coarse entry",
+          "compact_small": "per level: 24 B/coarse row + 16 B/coarse entry",
+          "cut_entries": "per level: 16 B/entry"}
+
+
+def level_stats(H):
+    out = []
+    for l in range(len(H)):
+        inf = H.info(l)
+        out.append((int(inf.n), int(inf.nnz), int(inf.matched), int(inf.rounds)))
+    return out
+
+
+def model_bytes(stats_by_rating, maxbound_ok):
+    """Total model bytes per kernel class over one step."""
+    tot = {k: 0 for k in MODELS}
+    for rating, lv in stats_by_rating.items():
+        io = rating == 1
+        for l, (n, D, matched, rounds) in enumerate(lv):
+            tot["cut_entries"] += bytes_cut_entries(D)
+            if l + 1 < len(lv):
+                nc, Dc = lv[l + 1][0], lv[l + 1][1]
+                tot["pick_first"] += bytes_pick_first(n, D, io)
+                tot["fill_small"] += bytes_fill_small(n, D, nc, Dc, matched)
+                tot["compact_small"] += bytes_compact(nc, Dc)
+    return tot
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--scale", type=int, default=20, help="log2 of the node count")
+    ap.add_argument("--k", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-out", default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_0910_2004_amd as K
+    from workloads import rgg
+
+    n = 1 << args.scale
+    k = args.k
+    stop_n = 20 * k
+    eps = (3, 100)
+    seed, part_seed = 42, 1
+    ratings = [K.EXPANSION_STAR2, K.INNER_OUTER]
+
+    t0 = time.time()
+    g = rgg(n, seed=2)
+    log(f"generated rgg n={g.n} |E|={g.m} in {time.time() - t0:.1f}s")
+    torch.cuda.set_device(0)
+    dg = K.DeviceGraph.from_csr(g, "cuda:0")
+    part0 = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
+    torch.cuda.synchronize()
+
+    def step():
+        stats = {}
+        for r in ratings:
+            H = K.kappa_coarsen(dg, r, seed, stop_n, 1, 20, 64)
+            _, res = K.kappa_uncoarsen(H, k, part_seed, eps[0], eps[1], part0=part0)
+            stats[r] = (level_stats(H), res[0].as_tuple())
+            del H
+        return stats
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        stats = step()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ms_step = (t2 - t1) * 1e3 / args.steps
+    edges_step = g.m * len(ratings)
+    value = edges_step / (ms_step / 1e3)
+
+    # second timed pass with per-launch HIP events
+    K.profile_reset()
+    K.profile_enable(True)
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    K.profile_enable(False)
+    prof = K.profile_read()
+    K.profile_reset()
+
+    lv = {r: stats[r][0] for r in ratings}
+    mb = model_bytes(lv, True)
+    total_ms = sum(ms for _, ms in prof.values()) / args.steps
+    kern = sorted(prof.items(), key=lambda kv: -kv[1][1])
+    log("kernel time per step (ms), launches per step:")
+    for name, (cnt, ms) in kern:
+        log(f"  {name:20s} {ms / args.steps:8.3f} ms  {cnt / args.steps:7.1f}")
+    dom = kern[0][0]
+    # the dominant kernel with a byte model (the roofline object reports it)
+    cand = [name for name, _ in kern if name in mb]
+    rk = cand[0] if cand else None
+    roof = None
+    if rk:
+        cnt, ms = prof[rk]
+        per_launch_bytes = mb[rk] / (cnt / args.steps)
+        avg_s = ms / cnt / 1e3
+        achieved = per_launch_bytes / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": rk, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": round(avg_s * 1e6, 2), "bytes_per_launch": int(per_launch_bytes),
+                "model": MODELS[rk], "time_share": round(ms / args.steps / total_ms, 3),
+                "dominant_kernel": dom}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        t3 = time.perf_counter()
+        for r in ratings:
+            OH = O.coarsen(g, r, seed, stop_n, 1, 20, 64)
+            O.uncoarsen(OH, k, part_seed, eps[0], eps[1])
+        t4 = time.perf_counter()
+        cpu = {"value": round(edges_step / (t4 - t3), 1), "unit": "edges/s", "cores": 1,
+               "kind": "oracle",
+               "sample": "one full step (both ratings) of the same workload on one host thread; "
+                         f"{t4 - t3:.2f} s"}
+
+    levels = {("expansion*2" if r == 0 else "innerOuter"): [x[0] for x in lv[r]] for r in ratings}
+    out = {
+        "metric": "coarsening edges/s per GPU (full hierarchy)",
+        "value": round(value, 1),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32/u64 (exact integer; 128-bit rating compares)",
+        "data": "synthetic",
+        "config": {"workload": f"rgg n=2^{args.scale} mean degree 8, unit weights, both ratings "
+                               f"(expansion*2, innerOuter), k={k}, stop n<={stop_n}, eps=3/100",
+                   "n": g.n, "m": g.m, "edges_per_step": edges_step, "k": k, "stop_n": stop_n,
+                   "seed": seed, "graph_seed": 2, "levels_n": levels},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernel_ms_per_step": {name: round(ms / args.steps, 4) for name, (cnt, ms) in kern},
+        "path_model_gbs": round(sum(mb.values()) / (ms_step / 1e3) / 1e9, 1),
+    }
+    if args.profile_out:
+        with open(args.profile_out, "w") as f:
+            json.dump({"prof": prof, "model_bytes": mb, "levels": {str(r): lv[r] for r in ratings}},
+                      f, indent=1)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

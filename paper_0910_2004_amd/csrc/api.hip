@@ -1,12 +1,19 @@
 // api.hip -- the C ABI (include/kappa.h): argument checks, stream-ordered
-// device memory, the multilevel loop and the way back up.
+// device memory, the multilevel driver and the way back up.
+//
+// The multilevel loop runs on device state (k_level.hip): the host enqueues a
+// batch of levels, then reads the control block once; levels whose stop rule
+// has fired turn into no-ops on the device.  All levels live in one arena
+// owned by the hierarchy.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
-#include <string>
 #include <vector>
 
 #include "kappa_internal.h"
@@ -142,8 +149,8 @@ struct Arena {
 
 // Pinned host memory for read-backs, per thread, kept for the process.
 // Fixed regions so that read-backs of different kinds never alias.
-enum PinnedRegion { PIN_SMALL = 0, PIN_MATCH = 1, PIN_RESULTS = 2 };
-constexpr size_t PIN_REGION_BYTES = 96 * 1024;
+enum PinnedRegion { PIN_SMALL = 0, PIN_LEVELS = 1, PIN_RESULTS = 2 };
+constexpr size_t PIN_REGION_BYTES = 320 * 1024;
 void *pinned(size_t bytes, PinnedRegion region = PIN_SMALL) {
     thread_local char *buf = nullptr;
     if (bytes > PIN_REGION_BYTES) return nullptr;
@@ -175,23 +182,38 @@ DevGraph dev(const kappa_graph *g) {
     return d;
 }
 
-#define HIPCHK(expr)                                  \
-    do {                                              \
-        if ((expr) != hipSuccess) return KAPPA_E_HIP; \
+// KAPPA_DEBUG=1 in the environment prints the HIP call or device flag behind
+// an error status to stderr.
+bool debug_on() {
+    static int on = -1;
+    if (on < 0) {
+        const char *e = getenv("KAPPA_DEBUG");
+        on = (e && e[0] && e[0] != '0') ? 1 : 0;
+    }
+    return on == 1;
+}
+
+#define HIPCHK(expr)                                                                  \
+    do {                                                                              \
+        hipError_t _e = (expr);                                                       \
+        if (_e != hipSuccess) {                                                       \
+            if (debug_on())                                                           \
+                fprintf(stderr, "kappa: %s failed: %s (%s:%d)\n", #expr,              \
+                        hipGetErrorString(_e), __FILE__, __LINE__);                   \
+            return KAPPA_E_HIP;                                                       \
+        }                                                                             \
     } while (0)
 
 // Validation + max degree, one read-back.
 kappa_status validate_impl(const DevGraph &g, hipStream_t s, int32_t *maxdeg_out) {
     Arena ar(s);
-    // [0] flags (u32) [1] maxdeg (i32) | sums (2 x u64)
-    uint32_t *small = ar.get<uint32_t>(2);
+    uint32_t *small = ar.get<uint32_t>(2);   // [0] flags, [1] max degree
     uint64_t *sums = ar.get<uint64_t>(2);
     int32_t *tr = ar.get<int32_t>(tile_rows_needed(g.nnz));
     if (ar.failed) return KAPPA_E_NOMEM;
     launch_fill_u32(small, 2, 0, s);
     launch_fill_u64(sums, 2, 0, s);
-    launch_validate(g, tr, small, sums, s);
-    launch_max_degree(g, (int32_t *)(small + 1), s);
+    launch_validate(g, tr, small, sums, (int32_t *)(small + 1), s);
     struct RB {
         uint32_t small[2];
         uint64_t sums[2];
@@ -209,80 +231,19 @@ kappa_status validate_impl(const DevGraph &g, hipStream_t s, int32_t *maxdeg_out
     return KAPPA_OK;
 }
 
-int32_t max_degree_sync(const DevGraph &g, hipStream_t s, kappa_status *st) {
-    Arena ar(s);
-    int32_t *d = ar.get<int32_t>(1);
-    if (ar.failed) { *st = KAPPA_E_NOMEM; return 0; }
-    launch_fill_u32((uint32_t *)d, 1, 0, s);
-    launch_max_degree(g, d, s);
-    int32_t *h = (int32_t *)pinned(sizeof(int32_t));
-    if (hipMemcpyAsync(h, d, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
-        *st = KAPPA_E_HIP;
-        return 0;
-    }
-    *st = KAPPA_OK;
-    return *h;
-}
-
 // ---------------------------------------------------------------------------
-// Matching driver: batches of rounds, one read-back per batch.
+// Scratch shared by every level (sized for level 0).
 // ---------------------------------------------------------------------------
-constexpr int STAT_KEEP = 64;   // rounds of statistics kept per level
-
-struct MatchResult {
-    int32_t rounds = 0;
-    int64_t matched = 0;
-    std::vector<int64_t> pointing, degsum;
-};
-
-kappa_status run_matching(const DevGraph &g, int rating, uint64_t seed, int32_t maxdeg,
-                          int32_t *mate, MatchScratch &ms, hipStream_t s, MatchResult &res) {
-    static_assert(sizeof(MatchState) <= PIN_REGION_BYTES, "read-back region too small");
-    launch_match_begin(g, rating, mate, ms, s);
-    MatchState *rb = (MatchState *)pinned(sizeof(MatchState), PIN_MATCH);
-    if (!rb) return KAPPA_E_NOMEM;
-    const size_t head = offsetof(MatchState, stat);
-    int r = 1, chunk = 8;
-    for (;;) {
-        launch_match_rounds(g, rating, seed, maxdeg, mate, ms, r, chunk, s);
-        r += chunk;
-        HIPCHK(hipMemcpyAsync(rb, ms.state, head, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (rb->handoff == -2 || g.n == 0) break;
-        // -3: the finisher hit its round cap; more than n/2 + 1 rounds cannot
-        // happen (each round with a pointing node matches a pair)
-        if (rb->handoff == -3 || (int64_t)r > (int64_t)g.n + 256) return KAPPA_E_HIP;
-        chunk = std::min(chunk * 2, 64);
-    }
-    res.rounds = rb->rounds;
-    res.matched = rb->matched;
-    int keep = std::min(res.rounds, STAT_KEEP);
-    res.pointing.assign(keep, 0);
-    res.degsum.assign(keep, 0);
-    if (keep > 0) {
-        HIPCHK(hipMemcpyAsync(&rb->stat[0][0], &ms.state->stat[0][0], sizeof(int64_t) * 2 * keep,
-                              hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        for (int i = 0; i < keep; ++i) {
-            res.pointing[i] = rb->stat[i][0];
-            res.degsum[i] = rb->stat[i][1];
-        }
-    }
-    return KAPPA_OK;
-}
-
-bool alloc_match_scratch(Arena &ar, const DevGraph &g, int rating, MatchScratch &ms) {
+bool alloc_scratch(Arena &ar, const DevGraph &g, int rating, bool hubs, Ctx &c) {
+    MatchScratch &ms = c.ms;
+    ContractScratch &cs = c.cs;
     ms.best = ar.get<int32_t>(g.n);
     ms.lists = ar.get<int32_t>(6 * (int64_t)g.n);
     ms.out = rating == KAPPA_INNER_OUTER ? ar.get<uint32_t>(g.n) : nullptr;
     ms.tile_row = rating == KAPPA_INNER_OUTER ? ar.get<int32_t>(tile_rows_needed(g.nnz)) : nullptr;
     ms.state = ar.get<MatchState>(1);
-    return !ar.failed;
-}
-
-bool alloc_contract_scratch(Arena &ar, const DevGraph &g, ContractScratch &cs) {
     cs.rep_of = ar.get<int32_t>(g.n);
+    cs.partner = ar.get<int32_t>(g.n);
     cs.tmp_off = ar.get<int64_t>((int64_t)g.n + 1);
     cs.cdeg = ar.get<int32_t>(g.n);
     cs.rows = ar.get<int32_t>(3 * (int64_t)g.n);
@@ -291,23 +252,36 @@ bool alloc_contract_scratch(Arena &ar, const DevGraph &g, ContractScratch &cs) {
     cs.tmp_ew = ar.get<uint32_t>(g.nnz);
     cs.partials = ar.get<int64_t>(scan_tiles((int64_t)g.n + 1) + 2);
     cs.totals = ar.get<int64_t>(4);
+    cs.hub_words = (int64_t)g.n / 32 + 1;
     cs.hub_acc = nullptr;
     cs.hub_bits = nullptr;
-    cs.hub_words = (int64_t)g.n / 32 + 1;
+    if (hubs) {
+        cs.hub_acc = ar.get<uint32_t>((int64_t)HUB_SLOTS * g.n);
+        cs.hub_bits = ar.get<uint32_t>((int64_t)HUB_SLOTS * cs.hub_words);
+        if (!ar.failed) {
+            launch_fill_u32(cs.hub_acc, (int64_t)HUB_SLOTS * g.n, 0, ar.s);
+            launch_fill_u32(cs.hub_bits, (int64_t)HUB_SLOTS * cs.hub_words, 0, ar.s);
+        }
+    }
     return !ar.failed;
 }
 
-bool alloc_hubs(Arena &ar, int32_t n, ContractScratch &cs, hipStream_t s) {
-    cs.hub_words = (int64_t)n / 32 + 1;
-    cs.hub_acc = ar.get<uint32_t>((int64_t)HUB_SLOTS * n);
-    cs.hub_bits = ar.get<uint32_t>((int64_t)HUB_SLOTS * cs.hub_words);
-    if (ar.failed) return false;
-    launch_fill_u32(cs.hub_acc, (int64_t)HUB_SLOTS * n, 0, s);
-    launch_fill_u32(cs.hub_bits, (int64_t)HUB_SLOTS * cs.hub_words, 0, s);
-    return true;
+// Host-side level size estimate (grid sizing only; any value is correct).
+inline int32_t n_hint_of(int32_t n0, int l) {
+    double v = (double)n0 * std::pow(0.6, l);
+    return (int32_t)std::max(1.0, std::min((double)n0, v));
 }
 
-inline int64_t bound_of(int32_t maxdeg) { return maxdeg > 0 ? 2 * (int64_t)maxdeg - 2 : 0; }
+// Multi-block matching rounds before the one-workgroup finisher.
+inline int rounds_for(int32_t n_hint) {
+    if (n_hint <= TAIL_MAX) return 1;
+    int r = (int)std::ceil(std::log((double)n_hint / TAIL_MAX) / std::log(3.5));
+    return std::min(std::max(r, 1), 8);
+}
+
+struct HostControl {
+    Control c;
+};
 
 }  // namespace
 
@@ -333,30 +307,137 @@ struct kappa_level {
 struct kappa_hierarchy {
     hipStream_t s = nullptr;
     std::vector<kappa_level> levels;
-    std::vector<void *> owned;
+    void *arena = nullptr;
     ~kappa_hierarchy() {
-        for (void *p : owned) (void)hipFreeAsync(p, s);
-    }
-    template <class T>
-    T *alloc(int64_t count) {
-        if (count <= 0) count = 1;
-        void *p = nullptr;
-        if (hipMallocAsync(&p, (size_t)count * sizeof(T), s) != hipSuccess || !p) return nullptr;
-        owned.push_back(p);
-        return (T *)p;
+        if (arena) (void)hipFreeAsync(arena, s);
     }
 };
 
-static DevGraph dev_level(const kappa_level &L) {
-    DevGraph d;
-    d.n = L.n;
-    d.nnz = L.nnz;
-    d.xadj = L.xadj;
-    d.adj = L.adj;
-    d.ew = L.ew;
-    d.vw = L.vw;
-    return d;
+namespace {
+
+// One attempt at the whole contraction phase with a given arena size.
+// Returns KAPPA_OK and fills H, or a status; *retry_flags gets the control
+// flags asking for another attempt (arena too small, hub accumulators).
+kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_coarsen_params *p,
+                             hipStream_t s, uint64_t arena_bytes, bool hubs, kappa_hierarchy *H,
+                             uint32_t *retry_flags) {
+    *retry_flags = 0;
+    Arena ar(s);
+    Ctx c;
+    c.rating = p->rating;
+    c.seed = p->seed;
+    c.seed_direct = 0;
+    const int maxl = p->max_levels;
+    c.ctrl = ar.get<Control>(1);
+    c.lv = ar.get<LevelDesc>(maxl + 2);
+    if (ar.failed || !alloc_scratch(ar, d0, p->rating, hubs, c)) return KAPPA_E_NOMEM;
+    void *arena = nullptr;
+    if (hipMallocAsync(&arena, arena_bytes, s) != hipSuccess || !arena) return KAPPA_E_NOMEM;
+
+    // control block and level 0
+    struct Init {
+        Control ctrl;
+        LevelDesc l0;
+    };
+    Init *in = (Init *)pinned(sizeof(Init));
+    std::memset(in, 0, sizeof(Init));
+    in->ctrl.done = 0;
+    in->ctrl.nlevels = 1;
+    in->ctrl.flags = 0;
+    in->ctrl.cursor = 0;
+    in->ctrl.cap = arena_bytes;
+    in->ctrl.base = (char *)arena;
+    in->ctrl.stop_n = p->stop_n;
+    in->ctrl.max_levels = maxl;
+    in->ctrl.stall_num = p->stall_num;
+    in->ctrl.stall_den = p->stall_den;
+    in->l0.n = d0.n;
+    in->l0.maxdeg = maxdeg0;
+    in->l0.nnz = d0.nnz;
+    in->l0.xadj = const_cast<int64_t *>(d0.xadj);
+    in->l0.adj = const_cast<int32_t *>(d0.adj);
+    in->l0.ew = const_cast<uint32_t *>(d0.ew);
+    in->l0.vw = const_cast<uint32_t *>(d0.vw);
+    in->l0.phase = PH_IDLE;
+    // every descriptor starts idle (zero): kernels of levels not built yet are no-ops
+    HIPCHK(hipMemsetAsync(c.lv, 0, (size_t)(maxl + 2) * sizeof(LevelDesc), s));
+    HIPCHK(hipMemcpyAsync(c.ctrl, &in->ctrl, sizeof(Control), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c.lv, &in->l0, sizeof(LevelDesc), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));   // `in` is reused below
+
+    // levels in batches; one read-back per batch
+    const int32_t n0 = d0.n;
+    int first = (int)std::ceil(std::log(std::max(2.0, (double)n0 / std::max(1, p->stop_n))) /
+                               std::log(1.0 / 0.6)) + 2;
+    int launched = 0, batch = std::max(1, std::min(first, maxl + 1));
+    Control *hc = (Control *)pinned(sizeof(Control));
+    for (;;) {
+        for (int l = launched; l < launched + batch && l <= maxl; ++l) {
+            int32_t nh = n_hint_of(n0, l);
+            // unit input weights can make level 0 need many rounds (innerOuter:
+            // ratings follow degree sums); coarser levels settle in a few
+            launch_level(c, l, nh, d0.nnz, n0, l == 0 ? 24 : rounds_for(nh) + 2, s);
+        }
+        launched += batch;
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(hc, c.ctrl, sizeof(Control), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (hc->done || launched > maxl) break;
+        batch = 4;
+    }
+    if (hc->flags && debug_on())
+        fprintf(stderr, "kappa: coarsen control flags 0x%x (levels %d)\n", hc->flags, hc->nlevels);
+    if (hc->flags & (CF_ARENA | CF_HUBS)) {
+        *retry_flags = hc->flags;
+        (void)hipFreeAsync(arena, s);
+        return KAPPA_E_NOMEM;
+    }
+    if (hc->flags & (CF_ROUNDS | CF_STATE)) {
+        (void)hipFreeAsync(arena, s);
+        return KAPPA_E_HIP;
+    }
+    // read the level descriptors back
+    const int nl = hc->nlevels;
+    if ((size_t)nl * sizeof(LevelDesc) > PIN_REGION_BYTES) {
+        (void)hipFreeAsync(arena, s);
+        return KAPPA_E_NOMEM;
+    }
+    LevelDesc *hl = (LevelDesc *)pinned((size_t)nl * sizeof(LevelDesc), PIN_LEVELS);
+    HIPCHK(hipMemcpyAsync(hl, c.lv, (size_t)nl * sizeof(LevelDesc), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    H->levels.clear();
+    for (int l = 0; l < nl; ++l) {
+        kappa_level L;
+        L.n = hl[l].n;
+        L.nnz = hl[l].nnz;
+        L.maxdeg = hl[l].maxdeg;
+        L.xadj = hl[l].xadj;
+        L.adj = hl[l].adj;
+        L.ew = hl[l].ew;
+        L.vw = hl[l].vw;
+        L.cmap = l + 1 < nl ? hl[l].cmap : nullptr;
+        L.mate = hl[l].mate;
+        L.rounds = hl[l].rounds;
+        L.matched = hl[l].matched;
+        L.stop = hl[l].stop;
+        if (l + 1 < nl || L.stop == KAPPA_STOP_EMPTY) {
+            int keep = std::min(L.rounds, STAT_ROUNDS);
+            for (int i = 0; i < keep; ++i) {
+                L.pointing.push_back(hl[l].stat[i][0]);
+                L.degsum.push_back(hl[l].stat[i][1]);
+            }
+        } else {
+            L.rounds = 0;
+            L.matched = 0;
+        }
+        if (l + 1 < nl) L.stop = KAPPA_STOP_NONE;
+        H->levels.push_back(L);
+    }
+    H->arena = arena;
+    return KAPPA_OK;
 }
+
+}  // namespace
 
 // ===========================================================================
 // Entry points
@@ -383,80 +464,12 @@ extern "C" kappa_status kappa_rate(const kappa_graph *g, int32_t rating, uint64_
     return KAPPA_OK;
 }
 
-extern "C" kappa_status kappa_match(const kappa_graph *g, int32_t rating, uint64_t level_seed,
-                                    int32_t *mate, int32_t *rounds_out, int64_t *matched_out,
-                                    kappa_stream_t stream) {
-    if (!graph_args_ok(g) || rating < 0 || rating > 4) return KAPPA_E_ARG;
-    if (g->n > 0 && !mate) return KAPPA_E_ARG;
-    hipStream_t s = S(stream);
-    DevGraph d = dev(g);
-    kappa_status st;
-    int32_t maxdeg = max_degree_sync(d, s, &st);
-    if (st != KAPPA_OK) return st;
-    Arena ar(s);
-    MatchScratch ms;
-    if (!alloc_match_scratch(ar, d, rating, ms)) return KAPPA_E_NOMEM;
-    if (ms.tile_row) launch_tile_rows(d, ms.tile_row, s);
-    MatchResult res;
-    st = run_matching(d, rating, level_seed, maxdeg, mate, ms, s, res);
-    if (st != KAPPA_OK) return st;
-    if (rounds_out) *rounds_out = res.rounds;
-    if (matched_out) *matched_out = res.matched;
-    return KAPPA_OK;
-}
-
-extern "C" kappa_status kappa_contract(const kappa_graph *g, const int32_t *mate, int32_t *cmap,
-                                       kappa_graph_out *coarse, kappa_stream_t stream) {
-    if (!graph_args_ok(g) || !coarse) return KAPPA_E_ARG;
-    if (g->n > 0 && (!mate || !cmap || !coarse->vw)) return KAPPA_E_ARG;
-    if (!coarse->xadj || coarse->cap_n < 0 || coarse->cap_nnz < 0) return KAPPA_E_ARG;
-    hipStream_t s = S(stream);
-    DevGraph d = dev(g);
-    kappa_status st;
-    int32_t maxdeg = max_degree_sync(d, s, &st);
-    if (st != KAPPA_OK) return st;
-    Arena ar(s);
-    uint32_t *flag = ar.get<uint32_t>(1);
-    ContractScratch cs;
-    if (!alloc_contract_scratch(ar, d, cs)) return KAPPA_E_NOMEM;
-    int64_t mb = bound_of(maxdeg);
-    if (mb > ROW_MID_MAX && !alloc_hubs(ar, d.n, cs, s)) return KAPPA_E_NOMEM;
-    // the coarse row offsets and weights need n' (+1) entries; n' <= n
-    int64_t *cx = ar.get<int64_t>((int64_t)d.n + 1);
-    uint32_t *cv = ar.get<uint32_t>(d.n);
-    if (ar.failed) return KAPPA_E_NOMEM;
-    launch_fill_u32(flag, 1, 0, s);
-    launch_check_matching(d, mate, flag, s);
-    uint32_t *hf = (uint32_t *)pinned(sizeof(uint32_t));
-    HIPCHK(hipMemcpyAsync(hf, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (*hf) return KAPPA_E_ARG;
-    launch_contract_build(d, mate, mb, cmap, cv, cx, cs, s);
-    int64_t *tot = (int64_t *)pinned(4 * sizeof(int64_t));
-    HIPCHK(hipMemcpyAsync(tot, cs.totals, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    int32_t nc = (int32_t)tot[0];
-    int64_t nnzc = tot[2];
-    coarse->n = nc;
-    coarse->nnz = nnzc;
-    if (nc > coarse->cap_n || nnzc > coarse->cap_nnz) return KAPPA_E_CAPACITY;
-    if (nnzc > 0 && (!coarse->adj || !coarse->ew)) return KAPPA_E_ARG;
-    launch_contract_compact(cs, d.n, mb, cx, coarse->adj, coarse->ew, s);
-    HIPCHK(hipMemcpyAsync(coarse->xadj, cx, ((size_t)nc + 1) * sizeof(int64_t),
-                          hipMemcpyDeviceToDevice, s));
-    if (nc > 0)
-        HIPCHK(hipMemcpyAsync(coarse->vw, cv, (size_t)nc * sizeof(uint32_t),
-                              hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
-    return KAPPA_OK;
-}
-
 extern "C" kappa_status kappa_coarsen(const kappa_graph *g, const kappa_coarsen_params *p,
                                       kappa_hierarchy **out, kappa_stream_t stream) {
     if (!out) return KAPPA_E_ARG;
     *out = nullptr;
     if (!graph_args_ok(g) || !p) return KAPPA_E_ARG;
-    if (p->rating < 0 || p->rating > 4 || p->max_levels < 0 || p->max_levels > 256 ||
+    if (p->rating < 0 || p->rating > 4 || p->max_levels < 0 || p->max_levels > MAX_LEVELS ||
         (p->stall_num > 0 && p->stall_den == 0))
         return KAPPA_E_ARG;
     hipStream_t s = S(stream);
@@ -468,72 +481,175 @@ extern "C" kappa_status kappa_coarsen(const kappa_graph *g, const kappa_coarsen_
     kappa_hierarchy *H = new (std::nothrow) kappa_hierarchy();
     if (!H) return KAPPA_E_NOMEM;
     H->s = s;
-    kappa_level L0;
-    L0.n = d0.n; L0.nnz = d0.nnz; L0.maxdeg = maxdeg;
-    L0.xadj = d0.xadj; L0.adj = d0.adj; L0.ew = d0.ew; L0.vw = d0.vw;
-    H->levels.push_back(L0);
-
-    Arena ar(s);
-    MatchScratch ms;
-    ContractScratch cs;
-    if (!alloc_match_scratch(ar, d0, p->rating, ms) || !alloc_contract_scratch(ar, d0, cs)) {
+    // arena: every level's nodes (vw, xadj, mate, cmap: 24 B) and entries
+    // (adj, ew: 8 B), three times level 0 to start with
+    uint64_t lvl0 = (uint64_t)d0.n * 24 + (uint64_t)d0.nnz * 8 + 4096;
+    uint64_t arena = 3 * lvl0 + (1u << 20);
+    bool hubs = 2 * (int64_t)maxdeg - 2 > ROW_MID_MAX / 8;
+    for (int attempt = 0; attempt < 6; ++attempt) {
+        uint32_t retry = 0;
+        st = coarsen_attempt(d0, maxdeg, p, s, arena, hubs, H, &retry);
+        if (st == KAPPA_OK) break;
+        if (!retry) break;
+        if (retry & CF_ARENA) arena *= 4;
+        if (retry & CF_HUBS) hubs = true;
+    }
+    if (st != KAPPA_OK) {
         delete H;
-        return KAPPA_E_NOMEM;
+        return st;
     }
-    bool hubs = false;
-    int64_t *tot = (int64_t *)pinned(4 * sizeof(int64_t));
-
-    for (int32_t l = 0;; ++l) {
-        kappa_level &cur = H->levels.back();
-        if (cur.n <= p->stop_n) { cur.stop = KAPPA_STOP_SIZE; break; }
-        if (l == p->max_levels) { cur.stop = KAPPA_STOP_MAXLEVEL; break; }
-        DevGraph d = dev_level(cur);
-        uint64_t seed_l = mix64(p->seed + (uint64_t)l);
-        cur.mate = H->alloc<int32_t>(d.n);
-        if (!cur.mate) { delete H; return KAPPA_E_NOMEM; }
-        if (ms.tile_row) launch_tile_rows(d, ms.tile_row, s);
-        MatchResult mr;
-        st = run_matching(d, p->rating, seed_l, cur.maxdeg, cur.mate, ms, s, mr);
-        if (st != KAPPA_OK) { delete H; return st; }
-        cur.rounds = mr.rounds;
-        cur.matched = mr.matched;
-        cur.pointing = mr.pointing;
-        cur.degsum = mr.degsum;
-        if (mr.matched == 0) { cur.stop = KAPPA_STOP_EMPTY; break; }
-
-        int64_t mb = bound_of(cur.maxdeg);
-        if (mb > ROW_MID_MAX && !hubs) {
-            if (!alloc_hubs(ar, d0.n, cs, s)) { delete H; return KAPPA_E_NOMEM; }
-            hubs = true;
-        }
-        cur.cmap = H->alloc<int32_t>(d.n);
-        int64_t *cx = H->alloc<int64_t>((int64_t)d.n + 1);
-        uint32_t *cv = H->alloc<uint32_t>(d.n);
-        if (!cur.cmap || !cx || !cv) { delete H; return KAPPA_E_NOMEM; }
-        launch_contract_build(d, cur.mate, mb, cur.cmap, cv, cx, cs, s);
-        HIPCHK(hipMemcpyAsync(tot, cs.totals, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        kappa_level nxt;
-        nxt.n = (int32_t)tot[0];
-        nxt.nnz = tot[2];
-        nxt.maxdeg = (int32_t)tot[3];
-        int32_t *ca = H->alloc<int32_t>(nxt.nnz);
-        uint32_t *ce = H->alloc<uint32_t>(nxt.nnz);
-        if (!ca || !ce) { delete H; return KAPPA_E_NOMEM; }
-        launch_contract_compact(cs, d.n, mb, cx, ca, ce, s);
-        nxt.xadj = cx; nxt.adj = ca; nxt.ew = ce; nxt.vw = cv;
-        int32_t n_prev = cur.n;
-        H->levels.push_back(nxt);
-        if (p->stall_num > 0 &&
-            (uint64_t)(n_prev - nxt.n) * p->stall_den < (uint64_t)p->stall_num * (uint64_t)n_prev) {
-            H->levels.back().stop = KAPPA_STOP_STALL;
-            break;
-        }
-    }
-    if (hipGetLastError() != hipSuccess) { delete H; return KAPPA_E_HIP; }
-    HIPCHK(hipStreamSynchronize(s));
     *out = H;
     return KAPPA_OK;
+}
+
+extern "C" kappa_status kappa_match(const kappa_graph *g, int32_t rating, uint64_t level_seed,
+                                    int32_t *mate, int32_t *rounds_out, int64_t *matched_out,
+                                    kappa_stream_t stream) {
+    if (!graph_args_ok(g) || rating < 0 || rating > 4) return KAPPA_E_ARG;
+    if (g->n > 0 && !mate) return KAPPA_E_ARG;
+    hipStream_t s = S(stream);
+    DevGraph d = dev(g);
+    Arena ar(s);
+    Ctx c;
+    c.rating = rating;
+    c.seed = level_seed;   // used as is: h(e) = mix64(level_seed ^ eid)
+    c.seed_direct = 1;
+    c.ctrl = ar.get<Control>(1);
+    c.lv = ar.get<LevelDesc>(2);
+    int32_t *cm = ar.get<int32_t>(d.n);
+    if (ar.failed || !alloc_scratch(ar, d, rating, false, c)) return KAPPA_E_NOMEM;
+    struct Init {
+        Control ctrl;
+        LevelDesc l0;
+    };
+    Init *in = (Init *)pinned(sizeof(Init));
+    std::memset(in, 0, sizeof(Init));
+    in->ctrl.nlevels = 1;
+    in->ctrl.stop_n = -1;
+    in->ctrl.max_levels = MAX_LEVELS;
+    in->l0.n = d.n;
+    in->l0.nnz = d.nnz;
+    in->l0.xadj = const_cast<int64_t *>(d.xadj);
+    in->l0.adj = const_cast<int32_t *>(d.adj);
+    in->l0.ew = const_cast<uint32_t *>(d.ew);
+    in->l0.vw = const_cast<uint32_t *>(d.vw);
+    in->l0.mate = mate;
+    in->l0.cmap = cm;
+    in->l0.phase = PH_IDLE;
+    HIPCHK(hipMemsetAsync(c.lv, 0, 2 * sizeof(LevelDesc), s));
+    HIPCHK(hipMemcpyAsync(c.ctrl, &in->ctrl, sizeof(Control), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c.lv, &in->l0, sizeof(LevelDesc), hipMemcpyHostToDevice, s));
+    launch_level_begin(c, 0, false, s);
+    launch_level_match(c, 0, d.n, d.nnz, 24, s);
+    LevelDesc *hl = (LevelDesc *)pinned(sizeof(LevelDesc), PIN_LEVELS);
+    Control *hc = (Control *)pinned(sizeof(Control));
+    HIPCHK(hipMemcpyAsync(hl, c.lv, sizeof(LevelDesc), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hc, c.ctrl, sizeof(Control), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hc->flags & (CF_ROUNDS | CF_STATE)) {
+        if (debug_on()) fprintf(stderr, "kappa: match control flags 0x%x\n", hc->flags);
+        return KAPPA_E_HIP;
+    }
+    if (rounds_out) *rounds_out = hl->rounds;
+    if (matched_out) *matched_out = hl->matched;
+    return KAPPA_OK;
+}
+
+extern "C" kappa_status kappa_contract(const kappa_graph *g, const int32_t *mate, int32_t *cmap,
+                                       kappa_graph_out *coarse, kappa_stream_t stream) {
+    if (!graph_args_ok(g) || !coarse) return KAPPA_E_ARG;
+    if (g->n > 0 && (!mate || !cmap || !coarse->vw)) return KAPPA_E_ARG;
+    if (!coarse->xadj || coarse->cap_n < 0 || coarse->cap_nnz < 0) return KAPPA_E_ARG;
+    hipStream_t s = S(stream);
+    DevGraph d = dev(g);
+    Arena ar(s);
+    uint32_t *flag = ar.get<uint32_t>(2);   // [0] matching check, [1] max degree
+    Ctx c;
+    c.rating = 0;
+    c.seed = 0;
+    c.seed_direct = 0;
+    c.ctrl = ar.get<Control>(1);
+    c.lv = ar.get<LevelDesc>(2);
+    if (ar.failed) return KAPPA_E_NOMEM;
+    launch_fill_u32(flag, 2, 0, s);
+    launch_check_matching(d, mate, flag, s);
+    {
+        // max degree via the validation's offsets kernel is not needed here:
+        // row classes are chosen on the device; hub accumulators are
+        // allocated when some row could exceed the mid class
+    }
+    uint32_t *hf = (uint32_t *)pinned(sizeof(uint32_t));
+    HIPCHK(hipMemcpyAsync(hf, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (*hf) return KAPPA_E_ARG;
+    uint64_t arena_bytes = (uint64_t)d.n * 12 + (uint64_t)d.nnz * 8 + 4096;
+    bool hubs = false;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        Arena ar2(s);
+        Ctx cc = c;
+        if (!alloc_scratch(ar2, d, 0, hubs, cc)) return KAPPA_E_NOMEM;
+        void *arena = ar2.get<char>((int64_t)arena_bytes);
+        if (!arena) return KAPPA_E_NOMEM;
+        struct Init {
+            Control ctrl;
+            LevelDesc l0;
+        };
+        Init *in = (Init *)pinned(sizeof(Init));
+        std::memset(in, 0, sizeof(Init));
+        in->ctrl.nlevels = 1;
+        in->ctrl.stop_n = -1;
+        in->ctrl.max_levels = MAX_LEVELS;
+        in->ctrl.cap = arena_bytes;
+        in->ctrl.base = (char *)arena;
+        in->l0.n = d.n;
+        in->l0.nnz = d.nnz;
+        in->l0.xadj = const_cast<int64_t *>(d.xadj);
+        in->l0.adj = const_cast<int32_t *>(d.adj);
+        in->l0.ew = const_cast<uint32_t *>(d.ew);
+        in->l0.vw = const_cast<uint32_t *>(d.vw);
+        in->l0.mate = const_cast<int32_t *>(mate);
+        in->l0.cmap = cmap;
+        in->l0.phase = PH_CONTRACT;
+        HIPCHK(hipMemsetAsync(cc.lv, 0, 2 * sizeof(LevelDesc), s));
+        HIPCHK(hipMemcpyAsync(cc.ctrl, &in->ctrl, sizeof(Control), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(cc.lv, &in->l0, sizeof(LevelDesc), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemsetAsync(cc.cs.row_cnt, 0, 4 * sizeof(int32_t), s));
+        HIPCHK(hipMemsetAsync(cc.cs.totals, 0, 4 * sizeof(int64_t), s));
+        launch_level_contract(cc, 0, d.n, d.n, s);
+        struct RB {
+            Control ctrl;
+            LevelDesc l1;
+        };
+        RB *rb = (RB *)pinned(sizeof(RB), PIN_LEVELS);
+        HIPCHK(hipMemcpyAsync(&rb->ctrl, cc.ctrl, sizeof(Control), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&rb->l1, cc.lv + 1, sizeof(LevelDesc), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (rb->ctrl.flags & CF_HUBS) {
+            hubs = true;
+            continue;
+        }
+        if (rb->ctrl.flags & CF_ARENA || rb->ctrl.nlevels != 2) return KAPPA_E_NOMEM;
+        int32_t nc = rb->l1.n;
+        int64_t nnzc = rb->l1.nnz;
+        coarse->n = nc;
+        coarse->nnz = nnzc;
+        if (nc > coarse->cap_n || nnzc > coarse->cap_nnz) return KAPPA_E_CAPACITY;
+        if (nnzc > 0 && (!coarse->adj || !coarse->ew)) return KAPPA_E_ARG;
+        HIPCHK(hipMemcpyAsync(coarse->xadj, rb->l1.xadj, ((size_t)nc + 1) * sizeof(int64_t),
+                              hipMemcpyDeviceToDevice, s));
+        if (nc > 0)
+            HIPCHK(hipMemcpyAsync(coarse->vw, rb->l1.vw, (size_t)nc * sizeof(uint32_t),
+                                  hipMemcpyDeviceToDevice, s));
+        if (nnzc > 0) {
+            HIPCHK(hipMemcpyAsync(coarse->adj, rb->l1.adj, (size_t)nnzc * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemcpyAsync(coarse->ew, rb->l1.ew, (size_t)nnzc * sizeof(uint32_t),
+                                  hipMemcpyDeviceToDevice, s));
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        return KAPPA_OK;
+    }
+    return KAPPA_E_NOMEM;
 }
 
 extern "C" int32_t kappa_hierarchy_levels(const kappa_hierarchy *h) {
@@ -655,7 +771,8 @@ extern "C" kappa_status kappa_uncoarsen(const kappa_hierarchy *h, int32_t k, uin
         const kappa_level &lv = h->levels[l];
         if (l < L)
             launch_project(lv.cmap, lv.n, h->levels[l + 1].n, part[l + 1], part[l], flag, s);
-        DevGraph d = dev_level(lv);
+        DevGraph d;
+        d.n = lv.n; d.nnz = lv.nnz; d.xadj = lv.xadj; d.adj = lv.adj; d.ew = lv.ew; d.vw = lv.vw;
         launch_tile_rows(d, tr, s);
         launch_cut_balance(d, tr, part[l], k, eps_num, eps_den, bw, acc, flag, rd + l, s);
     }
@@ -683,4 +800,4 @@ extern "C" const char *kappa_status_str(kappa_status st) {
     }
 }
 
-extern "C" const char *kappa_version(void) { return "kappa-mi355x 0.1 (gfx950)"; }
+extern "C" const char *kappa_version(void) { return "kappa-mi355x 0.2 (gfx950)"; }

@@ -1,18 +1,18 @@
 // k_graph.hip -- CSR sweeps: validation, Out(v), ratings, initial partition,
-// projection, cut/balance, plus the scan helper kernel.
+// projection, cut/balance.
 //
 // The per-entry sweeps (validation, Out, ratings, cut) are load balanced by
-// entries, not rows: block t owns entries [t*ETILE, (t+1)*ETILE).  A small
+// entries, not rows: tile t owns entries [t*ETILE, (t+1)*ETILE).  A small
 // pre-pass records the row holding each tile's first entry; a block stages the
 // row offsets of its tile in LDS and finds each entry's row by binary search
 // there.  Reads of adj/ew are fully coalesced and a node of any degree costs
-// the same per entry (power-law hubs spread over many blocks).
+// the same per entry (power-law hubs spread over many tiles).
 #include "kappa_internal.h"
 
 namespace kappa {
 
 constexpr int ETILE_ITEMS = 8;
-constexpr int ETILE = BLOCK * ETILE_ITEMS;   // 2048 entries per block
+constexpr int ETILE = BLOCK * ETILE_ITEMS;   // 2048 entries per tile
 constexpr int ETILE_ROWS = 2048;             // row offsets staged in LDS
 
 // ---------------------------------------------------------------------------
@@ -38,32 +38,14 @@ void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// One-block exclusive scan of the tile sums of launch_scan.
-// ---------------------------------------------------------------------------
-__global__ void scan_partials_k(int64_t *partials, int64_t nparts, int64_t *total) {
-    __shared__ int64_t sh[1024 / WAVE + 1];
-    int64_t per = (nparts + blockDim.x - 1) / blockDim.x;
-    int64_t b = (int64_t)threadIdx.x * per, e = b + per < nparts ? b + per : nparts;
-    int64_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += partials[i];
-    int64_t tot;
-    int64_t pre = block_excl_scan(s, sh, &tot);
-    for (int64_t i = b; i < e; ++i) {
-        int64_t t = partials[i];
-        partials[i] = pre;
-        pre += t;
-    }
-    if (threadIdx.x == 0 && total) *total = tot;
-}
-
-// ---------------------------------------------------------------------------
 // Entry tiles
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int64_t etiles(int64_t nnz) { return (nnz + ETILE - 1) / ETILE; }
 int64_t tile_rows_needed(int64_t nnz) { return etiles(nnz) + 1; }
 
 // tile_row[t] = row holding entry t*ETILE (largest v with xadj[v] <= t*ETILE).
-__global__ void tile_rows_k(DevGraph g, int32_t *tile_row, int64_t ntiles) {
+__device__ __forceinline__ void tile_rows_body(const DevGraph &g, int32_t *tile_row) {
+    const int64_t ntiles = etiles(g.nnz);
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n;
          v += (int64_t)gridDim.x * blockDim.x) {
         int64_t b = g.xadj[v], e = g.xadj[v + 1];
@@ -73,12 +55,13 @@ __global__ void tile_rows_k(DevGraph g, int32_t *tile_row, int64_t ntiles) {
     }
 }
 
+__global__ void tile_rows_k(DevGraph g, int32_t *tile_row) { tile_rows_body(g, tile_row); }
+
 void launch_tile_rows(const DevGraph &g, int32_t *tile_row, hipStream_t s) {
-    int64_t nt = etiles(g.nnz);
-    if (nt == 0) return;
+    if (etiles(g.nnz) == 0) return;
     KAPPA_PROF("tile_rows", s);
-    hipLaunchKernelGGL(tile_rows_k, dim3(grid_for(g.n, BLOCK, 8192)), dim3(BLOCK), 0, s, g,
-                       tile_row, nt);
+    hipLaunchKernelGGL(tile_rows_k, dim3(grid_for(g.n, BLOCK, 4096)), dim3(BLOCK), 0, s, g,
+                       tile_row);
 }
 
 struct TileCtx {
@@ -87,17 +70,17 @@ struct TileCtx {
     bool lds;
 };
 
-// Sets up the block's tile: LDS offsets of rows r0..r1 (+1) when they fit.
+// Sets up tile t: LDS offsets of rows r0..r1 (+1) when they fit.  Block-wide.
 __device__ __forceinline__ TileCtx tile_begin(const DevGraph &g, const int32_t *tile_row,
-                                              int64_t *s_off) {
+                                              int64_t t_idx, int64_t *s_off) {
     TileCtx t;
-    t.j0 = (int64_t)blockIdx.x * ETILE;
+    t.j0 = t_idx * ETILE;
     t.j1 = t.j0 + ETILE < g.nnz ? t.j0 + ETILE : g.nnz;
-    t.r0 = tile_row[blockIdx.x];
-    int64_t last_tile = etiles(g.nnz) - 1;
-    t.r1 = (int64_t)blockIdx.x < last_tile ? tile_row[blockIdx.x + 1] : g.n - 1;
+    t.r0 = tile_row[t_idx];
+    t.r1 = t_idx + 1 < etiles(g.nnz) ? tile_row[t_idx + 1] : g.n - 1;
     int32_t nr = t.r1 - t.r0 + 1;
     t.lds = nr <= ETILE_ROWS;
+    __syncthreads();   // s_off may still be read for the previous tile
     if (t.lds)
         for (int i = threadIdx.x; i <= nr; i += blockDim.x) s_off[i] = g.xadj[t.r0 + i];
     __syncthreads();
@@ -131,108 +114,197 @@ __device__ __forceinline__ int64_t tile_row_start(const DevGraph &g, const TileC
 
 // ---------------------------------------------------------------------------
 // Validation (Section 2 graph model).  flags: 1 = offsets, 2 = structure,
-// 4 = weight range.
+// 4 = weight range.  Also the maximum degree.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(BLOCK) validate_offsets_k(DevGraph g, uint32_t *flags,
-                                                            uint64_t *sums) {
+                                                            uint64_t *sums, int32_t *maxdeg) {
     __shared__ uint64_t sh[BLOCK / WAVE + 1];
-    uint32_t bad = 0;
+    __shared__ int32_t shm[BLOCK / WAVE];
+    bool bad = false;
     uint64_t csum = 0;
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v == 0 && (g.xadj[0] != 0 || g.xadj[g.n] != g.nnz)) bad |= 1;
-    if (v < g.n) {
-        if (g.xadj[v + 1] < g.xadj[v]) bad |= 1;
-        csum = g.vw[v];
+    int32_t md = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && (g.xadj[0] != 0 || g.xadj[g.n] != g.nnz)) bad = true;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        int64_t d = g.xadj[v + 1] - g.xadj[v];
+        if (d < 0) bad = true;
+        else if (d > md) md = d > 0x7fffffff ? 0x7fffffff : (int32_t)d;
+        csum += g.vw[v];
     }
     csum = block_sum(csum, sh);
-    if (threadIdx.x == 0 && csum) atomicAdd((unsigned long long *)&sums[1], (unsigned long long)csum);
-    if (bad) atomicOr(flags, bad);
+    md = wave_max(md);
+    if (lane_id() == 0) shm[threadIdx.x / WAVE] = md;
+    bool wbad = __ballot(bad) != 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < BLOCK / WAVE; ++i) md = shm[i] > md ? shm[i] : md;
+        if (csum) atomicAdd((unsigned long long *)&sums[1], (unsigned long long)csum);
+        if (md) atomicMax(maxdeg, md);
+    }
+    if (wbad && lane_id() == 0) atomicOr(flags, 1u);
 }
 
+// The reverse-entry check runs the binary searches of a thread's entries in
+// lockstep, so their loads overlap.
 __global__ void __launch_bounds__(BLOCK) validate_entries_k(DevGraph g, const int32_t *tile_row,
                                                             uint32_t *flags, uint64_t *sums) {
     __shared__ int64_t s_off[ETILE_ROWS + 1];
     __shared__ uint64_t sh[BLOCK / WAVE + 1];
     if (flags[0] & 1u) return;   // offsets broken: rows cannot be read safely
-    TileCtx t = tile_begin(g, tile_row, s_off);
+    const int64_t ntiles = etiles(g.nnz);
     uint32_t bad = 0;
     uint64_t wsum = 0;
-    for (int i = 0; i < ETILE_ITEMS; ++i) {
-        int64_t j = t.j0 + (int64_t)i * BLOCK + threadIdx.x;
-        if (j >= t.j1) break;
-        int32_t v = tile_row_of(g, t, s_off, j);
-        int32_t u = g.adj[j];
-        uint32_t w = g.ew[j];
-        if (u < 0 || u >= g.n || u == v) { bad |= 2; continue; }
-        if (j > tile_row_start(g, t, s_off, v) && g.adj[j - 1] >= u) bad |= 2;
-        // the reverse entry (v in row u) must exist with the same weight
-        int64_t lo = g.xadj[u], hi = g.xadj[u + 1] - 1;
-        bool found = false;
-        while (lo <= hi) {
-            int64_t mid = (lo + hi) >> 1;
-            int32_t x = g.adj[mid];
-            if (x == v) { found = g.ew[mid] == w; break; }
-            if (x < v) lo = mid + 1; else hi = mid - 1;
+    for (int64_t tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
+        TileCtx t = tile_begin(g, tile_row, tt, s_off);
+        int32_t vv[ETILE_ITEMS], uu[ETILE_ITEMS];
+        uint32_t ww[ETILE_ITEMS];
+        int64_t lo[ETILE_ITEMS], len[ETILE_ITEMS];
+        for (int i = 0; i < ETILE_ITEMS; ++i) {
+            int64_t j = t.j0 + (int64_t)i * BLOCK + threadIdx.x;
+            uu[i] = -1;
+            vv[i] = 0;
+            ww[i] = 0;
+            len[i] = 0;
+            lo[i] = 0;
+            if (j >= t.j1) continue;
+            int32_t v = tile_row_of(g, t, s_off, j);
+            int32_t u = g.adj[j];
+            uint32_t w = g.ew[j];
+            vv[i] = v;
+            ww[i] = w;
+            if (u < 0 || u >= g.n || u == v) { bad |= 2; continue; }
+            if (j > tile_row_start(g, t, s_off, v) && g.adj[j - 1] >= u) bad |= 2;
+            if (w == 0) bad |= 4;
+            if (u > v) wsum += w;
+            uu[i] = u;
         }
-        if (!found) bad |= 2;
-        if (w == 0) bad |= 4;
-        if (u > v) wsum += w;
+        for (int i = 0; i < ETILE_ITEMS; ++i)
+            if (uu[i] >= 0) { lo[i] = g.xadj[uu[i]]; len[i] = g.xadj[uu[i] + 1] - lo[i]; }
+        // lower_bound of v in row u, all searches advanced together
+        bool any = true;
+        while (any) {
+            any = false;
+            for (int i = 0; i < ETILE_ITEMS; ++i) {
+                if (len[i] <= 0) continue;
+                int64_t half = len[i] >> 1;
+                if (g.adj[lo[i] + half] < vv[i]) { lo[i] += half + 1; len[i] -= half + 1; }
+                else len[i] = half;
+                any = any || len[i] > 0;
+            }
+        }
+        for (int i = 0; i < ETILE_ITEMS; ++i) {
+            if (uu[i] < 0) continue;
+            int64_t end = g.xadj[uu[i] + 1];
+            if (lo[i] >= end || g.adj[lo[i]] != vv[i] || g.ew[lo[i]] != ww[i]) bad |= 2;
+        }
     }
     wsum = block_sum(wsum, sh);
     if (threadIdx.x == 0 && wsum) atomicAdd((unsigned long long *)&sums[0], (unsigned long long)wsum);
-    if (bad) atomicOr(flags, bad);
+    for (int off = WAVE / 2; off > 0; off >>= 1) bad |= __shfl_xor(bad, off, WAVE);
+    if (bad && lane_id() == 0) atomicOr(flags, bad);
 }
 
 void launch_validate(const DevGraph &g, int32_t *tile_row, uint32_t *flags, uint64_t *sums,
-                     hipStream_t s) {
-    // tile rows are written after the offsets check only when offsets are
-    // sane; tile_rows_k itself only reads xadj[v], xadj[v+1] pairs and stops
-    // at ntiles, so it is safe on any offsets.
+                     int32_t *maxdeg, hipStream_t s) {
     int64_t nt = etiles(g.nnz);
     {
         KAPPA_PROF("validate_offsets", s);
-        hipLaunchKernelGGL(validate_offsets_k, dim3(grid_for((int64_t)g.n + 1, BLOCK, 1u << 30)),
-                           dim3(BLOCK), 0, s, g, flags, sums);
+        hipLaunchKernelGGL(validate_offsets_k, dim3(grid_for((int64_t)g.n + 1, BLOCK * 4, 1024)),
+                           dim3(BLOCK), 0, s, g, flags, sums, maxdeg);
     }
     if (nt == 0) return;
     launch_tile_rows(g, tile_row, s);
     KAPPA_PROF("validate_entries", s);
-    hipLaunchKernelGGL(validate_entries_k, dim3((unsigned)nt), dim3(BLOCK), 0, s, g, tile_row,
-                       flags, sums);
+    hipLaunchKernelGGL(validate_entries_k, dim3(grid_for(nt, 1, 8192)), dim3(BLOCK), 0, s, g,
+                       tile_row, flags, sums);
 }
 
 // ---------------------------------------------------------------------------
 // Out(v) = sum of w over the edges at v (Section 3.1, innerOuter).  Row sums
 // are gathered in LDS per tile, then added to out[] (zeroed first).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(BLOCK) out_k(DevGraph g, const int32_t *tile_row,
-                                               uint32_t *out) {
-    __shared__ int64_t s_off[ETILE_ROWS + 1];
-    __shared__ uint32_t s_sum[ETILE_ROWS];
-    TileCtx t = tile_begin(g, tile_row, s_off);
-    int32_t nr = t.r1 - t.r0 + 1;
-    if (t.lds)
-        for (int i = threadIdx.x; i < nr; i += blockDim.x) s_sum[i] = 0;
-    __syncthreads();
-    for (int i = 0; i < ETILE_ITEMS; ++i) {
-        int64_t j = t.j0 + (int64_t)i * BLOCK + threadIdx.x;
-        if (j >= t.j1) break;
-        int32_t v = tile_row_of(g, t, s_off, j);
-        if (t.lds) atomicAdd(&s_sum[v - t.r0], g.ew[j]);
-        else atomicAdd(&out[v], g.ew[j]);
+__device__ __forceinline__ void out_body(const DevGraph &g, const int32_t *tile_row,
+                                         uint32_t *out, int64_t *s_off, uint32_t *s_sum) {
+    const int64_t ntiles = etiles(g.nnz);
+    for (int64_t tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
+        TileCtx t = tile_begin(g, tile_row, tt, s_off);
+        int32_t nr = t.r1 - t.r0 + 1;
+        if (t.lds)
+            for (int i = threadIdx.x; i < nr; i += blockDim.x) s_sum[i] = 0;
+        __syncthreads();
+        for (int i = 0; i < ETILE_ITEMS; ++i) {
+            int64_t j = t.j0 + (int64_t)i * BLOCK + threadIdx.x;
+            if (j >= t.j1) break;
+            int32_t v = tile_row_of(g, t, s_off, j);
+            if (t.lds) atomicAdd(&s_sum[v - t.r0], g.ew[j]);
+            else atomicAdd(&out[v], g.ew[j]);
+        }
+        __syncthreads();
+        if (t.lds)
+            for (int i = threadIdx.x; i < nr; i += blockDim.x)
+                if (s_sum[i]) atomicAdd(&out[t.r0 + i], s_sum[i]);
     }
-    __syncthreads();
-    if (t.lds)
-        for (int i = threadIdx.x; i < nr; i += blockDim.x)
-            if (s_sum[i]) atomicAdd(&out[t.r0 + i], s_sum[i]);
 }
 
-void launch_out(const DevGraph &g, const int32_t *tr, uint32_t *out, hipStream_t s) {
+__global__ void __launch_bounds__(BLOCK) out_k(DevGraph g, const int32_t *tile_row, uint32_t *out) {
+    __shared__ int64_t s_off[ETILE_ROWS + 1];
+    __shared__ uint32_t s_sum[ETILE_ROWS];
+    out_body(g, tile_row, out, s_off, s_sum);
+}
+
+void launch_out(const DevGraph &g, const int32_t *tile_row, uint32_t *out, hipStream_t s) {
     launch_fill_u32(out, g.n, 0, s);
     int64_t nt = etiles(g.nnz);
     if (nt == 0) return;
     KAPPA_PROF("out", s);
-    hipLaunchKernelGGL(out_k, dim3((unsigned)nt), dim3(BLOCK), 0, s, g, tr, out);
+    hipLaunchKernelGGL(out_k, dim3(grid_for(nt, 1, 8192)), dim3(BLOCK), 0, s, g, tile_row, out);
+}
+
+// Level-resident Out(v): level l's graph from its descriptor, only while it
+// is matching.
+__device__ __forceinline__ bool level_graph(const LevelDesc *L, int32_t want, DevGraph &g) {
+    if (L->phase != want) return false;
+    g.n = L->n; g.nnz = L->nnz; g.xadj = L->xadj; g.adj = L->adj; g.ew = L->ew; g.vw = L->vw;
+    return true;
+}
+
+__global__ void lv_out_zero_k(const LevelDesc *L, uint32_t *out) {
+    DevGraph g;
+    if (!level_graph(L, PH_MATCH, g)) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = 0;
+}
+__global__ void lv_tile_rows_k(const LevelDesc *L, int32_t *tile_row) {
+    DevGraph g;
+    if (!level_graph(L, PH_MATCH, g)) return;
+    tile_rows_body(g, tile_row);
+}
+__global__ void __launch_bounds__(BLOCK) lv_out_k(const LevelDesc *L, const int32_t *tile_row,
+                                                  uint32_t *out) {
+    __shared__ int64_t s_off[ETILE_ROWS + 1];
+    __shared__ uint32_t s_sum[ETILE_ROWS];
+    DevGraph g;
+    if (!level_graph(L, PH_MATCH, g)) return;
+    out_body(g, tile_row, out, s_off, s_sum);
+}
+
+void launch_level_out(const Ctx &c, int l, int64_t nnz_cap, int32_t n_hint, hipStream_t s) {
+    const LevelDesc *L = c.lv + l;
+    {
+        KAPPA_PROF("out_zero", s);
+        hipLaunchKernelGGL(lv_out_zero_k, dim3(grid_for(n_hint, BLOCK * 4, 1024)), dim3(BLOCK), 0, s,
+                           L, c.ms.out);
+    }
+    {
+        KAPPA_PROF("tile_rows", s);
+        hipLaunchKernelGGL(lv_tile_rows_k, dim3(grid_for(n_hint, BLOCK, 4096)), dim3(BLOCK), 0, s,
+                           L, c.ms.tile_row);
+    }
+    KAPPA_PROF("out", s);
+    int64_t nt_hint = etiles(nnz_cap);
+    hipLaunchKernelGGL(lv_out_k, dim3(grid_for(nt_hint, 1, 8192)), dim3(BLOCK), 0, s, L,
+                       c.ms.tile_row, c.ms.out);
 }
 
 // ---------------------------------------------------------------------------
@@ -243,18 +315,21 @@ __global__ void __launch_bounds__(BLOCK) rate_k(DevGraph g, const int32_t *tile_
                                                 const uint32_t *out, uint64_t *num,
                                                 uint64_t *den) {
     __shared__ int64_t s_off[ETILE_ROWS + 1];
-    TileCtx t = tile_begin(g, tile_row, s_off);
-    for (int i = 0; i < ETILE_ITEMS; ++i) {
-        int64_t j = t.j0 + (int64_t)i * BLOCK + threadIdx.x;
-        if (j >= t.j1) break;
-        int32_t v = tile_row_of(g, t, s_off, j);
-        int32_t u = g.adj[j];
-        uint32_t ou = 0, ov = 0;
-        if (R == KAPPA_INNER_OUTER) { ou = out[u]; ov = out[v]; }
-        uint64_t a, b;
-        rate<R>(g.ew[j], g.vw[u], g.vw[v], ou, ov, a, b);
-        num[j] = a;
-        den[j] = b;
+    const int64_t ntiles = etiles(g.nnz);
+    for (int64_t tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
+        TileCtx t = tile_begin(g, tile_row, tt, s_off);
+        for (int i = 0; i < ETILE_ITEMS; ++i) {
+            int64_t j = t.j0 + (int64_t)i * BLOCK + threadIdx.x;
+            if (j >= t.j1) break;
+            int32_t v = tile_row_of(g, t, s_off, j);
+            int32_t u = g.adj[j];
+            uint32_t ou = 0, ov = 0;
+            if (R == KAPPA_INNER_OUTER) { ou = out[u]; ov = out[v]; }
+            uint64_t a, b;
+            rate<R>(g.ew[j], g.vw[u], g.vw[v], ou, ov, a, b);
+            num[j] = a;
+            den[j] = b;
+        }
     }
 }
 
@@ -263,7 +338,7 @@ void launch_rate(const DevGraph &g, const int32_t *tr, int rating, const uint32_
     int64_t nt = etiles(g.nnz);
     if (nt == 0) return;
     KAPPA_PROF("rate", s);
-    dim3 gr((unsigned)nt), bl(BLOCK);
+    dim3 gr(grid_for(nt, 1, 8192)), bl(BLOCK);
     switch (rating) {
     case KAPPA_INNER_OUTER: hipLaunchKernelGGL(rate_k<KAPPA_INNER_OUTER>, gr, bl, 0, s, g, tr, out, num, den); break;
     case KAPPA_WEIGHT: hipLaunchKernelGGL(rate_k<KAPPA_WEIGHT>, gr, bl, 0, s, g, tr, out, num, den); break;
@@ -277,11 +352,12 @@ void launch_rate(const DevGraph &g, const int32_t *tr, int rating, const uint32_
 // Matching check for externally supplied mate arrays.
 // ---------------------------------------------------------------------------
 __global__ void check_matching_k(DevGraph g, const int32_t *mate, uint32_t *flags) {
+    bool bad = false;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n;
          v += (int64_t)gridDim.x * blockDim.x) {
         int32_t m = mate[v];
         if (m == -1) continue;
-        if (m < 0 || m >= g.n || m == v || mate[m] != v) { atomicOr(flags, 1u); continue; }
+        if (m < 0 || m >= g.n || m == v || mate[m] != v) { bad = true; continue; }
         int64_t lo = g.xadj[v], hi = g.xadj[v + 1] - 1;
         bool found = false;
         while (lo <= hi) {
@@ -290,8 +366,9 @@ __global__ void check_matching_k(DevGraph g, const int32_t *mate, uint32_t *flag
             if (x == m) { found = true; break; }
             if (x < m) lo = mid + 1; else hi = mid - 1;
         }
-        if (!found) atomicOr(flags, 1u);
+        if (!found) bad = true;
     }
+    if (__ballot(bad) && lane_id() == 0) atomicOr(flags, 1u);
 }
 
 void launch_check_matching(const DevGraph &g, const int32_t *mate, uint32_t *flags,
@@ -321,16 +398,18 @@ void launch_initial_partition(int32_t n, int32_t k, uint64_t seed, int32_t *part
 
 __global__ void project_k(const int32_t *cmap, int32_t n_fine, int32_t n_coarse,
                           const int32_t *part_coarse, int32_t *part_fine, uint32_t *flag) {
+    bool bad = false;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n_fine;
          v += (int64_t)gridDim.x * blockDim.x) {
         int32_t c = cmap[v];
         if (c < 0 || c >= n_coarse) {
             part_fine[v] = -1;
-            if (flag) atomicOr(flag, 1u);
+            bad = true;
         } else {
             part_fine[v] = part_coarse[c];
         }
     }
+    if (__ballot(bad) && lane_id() == 0 && flag) atomicOr(flag, 1u);
 }
 
 void launch_project(const int32_t *cmap, int32_t n_fine, int32_t n_coarse,
@@ -338,7 +417,7 @@ void launch_project(const int32_t *cmap, int32_t n_fine, int32_t n_coarse,
                     hipStream_t s) {
     if (n_fine <= 0) return;
     KAPPA_PROF("project", s);
-    hipLaunchKernelGGL(project_k, dim3(grid_for(n_fine, BLOCK, 8192)), dim3(BLOCK), 0, s, cmap,
+    hipLaunchKernelGGL(project_k, dim3(grid_for(n_fine, BLOCK * 4, 2048)), dim3(BLOCK), 0, s, cmap,
                        n_fine, n_coarse, part_coarse, part_fine, flag);
 }
 
@@ -353,15 +432,17 @@ __global__ void __launch_bounds__(BLOCK) cut_nodes_k(DevGraph g, const int32_t *
                                                      uint32_t *flag) {
     extern __shared__ uint64_t s_hist[];   // k entries
     __shared__ uint64_t sh[BLOCK / WAVE + 1];
+    __shared__ uint32_t shm[BLOCK / WAVE];
     for (int i = threadIdx.x; i < k; i += blockDim.x) s_hist[i] = 0;
     __syncthreads();
     uint64_t tot = 0;
-    uint32_t mx = 0, bad = 0;
+    uint32_t mx = 0;
+    bool bad = false;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n;
          v += (int64_t)gridDim.x * blockDim.x) {
         int32_t p = part[v];
         uint32_t c = g.vw[v];
-        if (p < 0 || p >= k) { bad = 1; continue; }
+        if (p < 0 || p >= k) { bad = true; continue; }
         if (c) atomicAdd((unsigned long long *)&s_hist[p], (unsigned long long)c);
         tot += c;
         mx = c > mx ? c : mx;
@@ -371,23 +452,32 @@ __global__ void __launch_bounds__(BLOCK) cut_nodes_k(DevGraph g, const int32_t *
         if (s_hist[i]) atomicAdd((unsigned long long *)&block_w[i], (unsigned long long)s_hist[i]);
     tot = block_sum(tot, sh);
     mx = wave_max(mx);
-    if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&acc[1], (unsigned long long)tot);
-    if (lane_id() == 0 && mx) atomicMax((unsigned long long *)&acc[2], (unsigned long long)mx);
-    if (bad) atomicOr(flag, 2u);
+    if (lane_id() == 0) shm[threadIdx.x / WAVE] = mx;
+    bool wbad = __ballot(bad) != 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < BLOCK / WAVE; ++i) mx = shm[i] > mx ? shm[i] : mx;
+        if (tot) atomicAdd((unsigned long long *)&acc[1], (unsigned long long)tot);
+        if (mx) atomicMax((unsigned long long *)&acc[2], (unsigned long long)mx);
+    }
+    if (wbad && lane_id() == 0) atomicOr(flag, 2u);
 }
 
 __global__ void __launch_bounds__(BLOCK) cut_entries_k(DevGraph g, const int32_t *tile_row,
                                                        const int32_t *part, uint64_t *acc) {
     __shared__ int64_t s_off[ETILE_ROWS + 1];
     __shared__ uint64_t sh[BLOCK / WAVE + 1];
-    TileCtx t = tile_begin(g, tile_row, s_off);
+    const int64_t ntiles = etiles(g.nnz);
     uint64_t cut = 0;
-    for (int i = 0; i < ETILE_ITEMS; ++i) {
-        int64_t j = t.j0 + (int64_t)i * BLOCK + threadIdx.x;
-        if (j >= t.j1) break;
-        int32_t v = tile_row_of(g, t, s_off, j);
-        int32_t u = g.adj[j];
-        if (u > v && part[u] != part[v]) cut += g.ew[j];
+    for (int64_t tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
+        TileCtx t = tile_begin(g, tile_row, tt, s_off);
+        for (int i = 0; i < ETILE_ITEMS; ++i) {
+            int64_t j = t.j0 + (int64_t)i * BLOCK + threadIdx.x;
+            if (j >= t.j1) break;
+            int32_t v = tile_row_of(g, t, s_off, j);
+            int32_t u = g.adj[j];
+            if (u > v && part[u] != part[v]) cut += g.ew[j];
+        }
     }
     cut = block_sum(cut, sh);
     if (threadIdx.x == 0 && cut) atomicAdd((unsigned long long *)&acc[0], (unsigned long long)cut);
@@ -431,13 +521,14 @@ void launch_cut_balance(const DevGraph &g, const int32_t *tr, const int32_t *par
     launch_fill_u64(acc, 3, 0, s);
     if (g.n > 0) {
         KAPPA_PROF("cut_nodes", s);
-        hipLaunchKernelGGL(cut_nodes_k, dim3(grid_for(g.n, BLOCK, CUT_NODE_BLOCKS)), dim3(BLOCK),
+        hipLaunchKernelGGL(cut_nodes_k, dim3(grid_for(g.n, BLOCK * 4, CUT_NODE_BLOCKS)), dim3(BLOCK),
                            (size_t)k * sizeof(uint64_t), s, g, part, k, block_w, acc, flag);
     }
     int64_t nt = etiles(g.nnz);
     if (nt > 0) {
         KAPPA_PROF("cut_entries", s);
-        hipLaunchKernelGGL(cut_entries_k, dim3((unsigned)nt), dim3(BLOCK), 0, s, g, tr, part, acc);
+        hipLaunchKernelGGL(cut_entries_k, dim3(grid_for(nt, 1, 4096)), dim3(BLOCK), 0, s, g, tr,
+                           part, acc);
     }
     KAPPA_PROF("cut_finalize", s);
     hipLaunchKernelGGL(cut_finalize_k, dim3(1), dim3(BLOCK), 0, s, block_w, k, eps_num, eps_den,

@@ -1,0 +1,1201 @@
+// k_level.hip -- one level of the multilevel loop (Section 2): matching
+// (Section 3.3) and contraction, driven entirely by device-resident state.
+//
+// Every kernel reads its level's graph from the level descriptor and checks
+// the level's phase, so the host enqueues whole levels without reading
+// anything back: a level whose stop rule fired (or that does not exist yet)
+// turns every later kernel into a no-op.  Allocation of the next level's
+// arrays is a device-side bump in one arena.
+//
+// Matching: rounds as in the paper's parallel scheme.  Every free node that
+// still has a free neighbour points at its best edge to a free neighbour
+// (the strict order of kappa.h); edges that are best at both ends are
+// matched; repeat until no free node has a free neighbour.  Under a strict
+// total order this is exactly the Greedy matching of Section 3.2.
+//   pick kernel  -- node-centric argmax over the row, nodes binned by degree:
+//                   bin 0 (deg <= 16) 8 lanes per node, bin 1 (deg <= 1024)
+//                   one wave per node, bin 2 one block per node.  A pending
+//                   node whose previous choice is still free keeps it (free
+//                   sets only shrink, so it is still the maximum).
+//   mate kernel  -- mutual check best[best[v]] == v, matched pairs written,
+//                   survivors appended (block-aggregated) to the next lists.
+//   finisher     -- one 1024-thread workgroup runs the remaining rounds with
+//                   workgroup barriers once few nodes remain.
+//
+// Contraction: each matched pair {u, v} becomes one coarse node x with
+// c(x) = c(u) + c(v); the rows of u and v are merged (neighbours renamed to
+// coarse ids, the contracted edge dropped, parallel edges summed).  Coarse
+// ids: representatives (unmatched nodes and the smaller end of each matched
+// edge) numbered in ascending fine id by a device scan.
+//   1. scan of representative flags -> cmap of representatives, rep_of;
+//      then (one thread) arrays of the next level's nodes are allocated
+//   2. coarse_nodes: c(x), cmap of partners, bound(x) = deg(u) + deg(v) - 2,
+//      row class by bound
+//   3. scan of the bounds -> padded row offsets
+//   4. merge of each coarse row into the padded buffer, by class:
+//        small (<= 64 entries): 16 lanes per row, rank sort in LDS
+//        mid (<= 4094):         one block per row, bitonic sort in LDS
+//        large:                 dense per-slot accumulator + bitmap, read
+//                               back in ascending id order
+//      Equal coarse neighbours form runs of at most 4 entries (a coarse node
+//      has at most two fine nodes on each side).
+//   5. scan of the merged degrees -> coarse row offsets; then (one thread)
+//      the next level's edge arrays are allocated and the stall rule checked
+//   6. compact: copy merged rows into the exact-size coarse arrays
+#include <cstdio>
+#include <cstdlib>
+
+#include "kappa_internal.h"
+
+namespace kappa {
+
+// ===========================================================================
+// Common
+// ===========================================================================
+__device__ __forceinline__ bool load_level(const LevelDesc *L, int32_t want, DevGraph &g) {
+    if (L->phase != want) return false;
+    g.n = L->n; g.nnz = L->nnz; g.xadj = L->xadj; g.adj = L->adj; g.ew = L->ew; g.vw = L->vw;
+    return true;
+}
+
+__device__ __forceinline__ int bin_of(int64_t deg) {
+    return deg <= BIN_SMALL_MAX ? 0 : (deg <= BIN_MID_MAX ? 1 : 2);
+}
+
+__device__ __forceinline__ int32_t *list_ptr(int32_t *lists, int32_t n, int par, int bin) {
+    return lists + ((int64_t)(par * 3 + bin)) * n;
+}
+
+// Node id read from a pending list: -1 (and a control flag) if out of range.
+// Valid state never trips this; it keeps a broken state from indexing memory.
+__device__ __forceinline__ int32_t checked_node(int32_t v, int32_t n, Control *ctrl) {
+    if ((uint32_t)v < (uint32_t)n) return v;
+    atomicOr(&ctrl->flags, (uint32_t)CF_STATE);
+    return -1;
+}
+
+// ===========================================================================
+// Level start: stop rules (Section 2 threshold, Section 4), allocations,
+// state resets.
+// ===========================================================================
+__global__ void level_begin_k(Ctx c, int l, int stop_rules) {
+    __shared__ int go;
+    Control *ctrl = c.ctrl;
+    LevelDesc *L = c.lv + l;
+    if (threadIdx.x == 0) {
+        go = 0;
+        if (!ctrl->done && ctrl->nlevels == l + 1 && L->phase == PH_IDLE) {
+            if (stop_rules && L->n <= ctrl->stop_n) {
+                L->stop = KAPPA_STOP_SIZE;
+                L->phase = PH_STOPPED;
+                ctrl->done = 1;
+            } else if (stop_rules && l >= ctrl->max_levels) {
+                L->stop = KAPPA_STOP_MAXLEVEL;
+                L->phase = PH_STOPPED;
+                ctrl->done = 1;
+            } else {
+                if (!L->mate) L->mate = (int32_t *)arena_alloc(ctrl, (uint64_t)L->n * 4);
+                if (!L->cmap) L->cmap = (int32_t *)arena_alloc(ctrl, (uint64_t)L->n * 4);
+                if (!L->mate || !L->cmap) {
+                    L->phase = PH_STOPPED;
+                    ctrl->done = 1;
+                } else {
+                    L->phase = PH_MATCH;
+                    go = 1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (!go) return;
+    MatchState *st = c.ms.state;
+    int t = threadIdx.x;
+    if (t < 16) st->cnt[t >> 2][t & 3] = 0;
+    if (t == 0) {
+        st->handoff = -1;
+        st->rounds = 0;
+        st->matched = 0;
+        st->pad[0] = 0;   // grid-barrier counter
+        st->pad[1] = 0;   // grid-barrier generation
+        L->matched = 0;
+        L->rounds = 0;
+    }
+    for (int i = t; i < STAT_ROUNDS; i += blockDim.x) {
+        st->stat[i][0] = 0;
+        st->stat[i][1] = 0;
+    }
+}
+
+// ===========================================================================
+// Matching
+// ===========================================================================
+template <int R, int G>
+__device__ __forceinline__ Cand scan_row(const DevGraph &g, int32_t v, int sub,
+                                         const int32_t *mate, const uint32_t *out,
+                                         uint64_t seed, bool first) {
+    Cand best = cand_none();
+    int64_t b = g.xadj[v], e = g.xadj[v + 1];
+    uint32_t cv = g.vw[v];
+    uint32_t ov = (R == KAPPA_INNER_OUTER) ? out[v] : 0u;
+    for (int64_t j = b + sub; j < e; j += G) {
+        int32_t u = g.adj[j];
+        if (!first && mate[u] >= 0) continue;
+        Cand cd;
+        rate<R>(g.ew[j], g.vw[u], cv, (R == KAPPA_INNER_OUTER) ? out[u] : 0u, ov, cd.num, cd.den);
+        cd.h = mix64(seed ^ edge_id(v, u));
+        cd.u = u;
+        if (cand_better(cd, best, v)) best = cd;
+    }
+    return best;
+}
+
+template <int G>
+__device__ __forceinline__ Cand group_reduce(Cand cd, int32_t v) {
+    for (int off = G / 2; off > 0; off >>= 1) {
+        Cand o = cand_shfl_xor(cd, off, G);
+        if (cand_better(o, cd, v)) cd = o;
+    }
+    return cd;
+}
+
+// Whole-block argmax (all threads call; contains barriers).
+__device__ __forceinline__ Cand block_reduce_cand(Cand cd, int32_t v, Cand *sh) {
+    cd = group_reduce<WAVE>(cd, v);
+    int w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    if (lane_id() == 0) sh[w] = cd;
+    __syncthreads();
+    Cand r = sh[0];
+    for (int i = 1; i < nw; ++i)
+        if (cand_better(sh[i], r, v)) r = sh[i];
+    __syncthreads();
+    return r;
+}
+
+// A pending node keeps its choice while that neighbour is still free.
+__device__ __forceinline__ bool needs_rescan(int32_t v, const int32_t *best, const int32_t *mate) {
+    int32_t b = best[v];
+    return !(b >= 0 && mate[b] < 0);
+}
+
+__device__ __forceinline__ uint64_t level_seed(const Ctx &c, int l) {
+    return c.seed_direct ? c.seed : mix64(c.seed + (uint64_t)l);
+}
+
+// --- phases shared by the per-round kernels and the cooperative kernel -----
+// Blocks [bid] of [nb] cooperate on each phase (grid-stride loops).
+
+// mate = best = -1; nodes of bins 1 and 2 go to the round-1 lists (parity 0).
+__device__ __forceinline__ void init_phase(const Ctx &c, const DevGraph &g, LevelDesc *L,
+                                           unsigned bid, unsigned nb, int32_t *sha) {
+    int32_t *mate = L->mate, *best = c.ms.best;
+    MatchState *st = c.ms.state;
+    int32_t *lists[3] = {list_ptr(c.ms.lists, g.n, 0, 0), list_ptr(c.ms.lists, g.n, 0, 1),
+                         list_ptr(c.ms.lists, g.n, 0, 2)};
+    int32_t *cnts[3] = {&st->cnt[0][0], &st->cnt[0][1], &st->cnt[0][2]};
+    const int64_t stride = (int64_t)nb * blockDim.x;
+    const int64_t lim = ((int64_t)g.n + stride - 1) / stride * stride;   // block-uniform trips
+    for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < lim; i += stride) {
+        int bn = -1;
+        if (i < g.n) {
+            mate[i] = -1;
+            best[i] = -1;
+            int64_t d = g.xadj[i + 1] - g.xadj[i];
+            bn = bin_of(d);
+            if (bn == 0) bn = -1;
+        }
+        block_append3(bn, (int32_t)i, lists, cnts, sha);
+    }
+}
+
+// Inputs of round r: counts and lists (round 1: bin 0 is every node).
+template <bool FIRST>
+__device__ __forceinline__ int64_t round_inputs(const Ctx &c, const DevGraph &g, int r,
+                                                int32_t cn[3], const int32_t *Ls[3]) {
+    MatchState *st = c.ms.state;
+    if (FIRST) {
+        cn[0] = g.n; cn[1] = st->cnt[0][1]; cn[2] = st->cnt[0][2];
+        Ls[0] = nullptr;
+        Ls[1] = list_ptr(c.ms.lists, g.n, 0, 1);
+        Ls[2] = list_ptr(c.ms.lists, g.n, 0, 2);
+        return (int64_t)g.n;
+    }
+    int slot = (r - 1) & 3, par = (r - 1) & 1;
+    cn[0] = st->cnt[slot][0]; cn[1] = st->cnt[slot][1]; cn[2] = st->cnt[slot][2];
+    Ls[0] = list_ptr(c.ms.lists, g.n, par, 0);
+    Ls[1] = list_ptr(c.ms.lists, g.n, par, 1);
+    Ls[2] = list_ptr(c.ms.lists, g.n, par, 2);
+    return (int64_t)cn[0] + cn[1] + cn[2];
+}
+
+// bin 0: 8 lanes per node
+template <int R, bool FIRST>
+__device__ __forceinline__ void pick_bin0(const Ctx &c, const DevGraph &g, const LevelDesc *L,
+                                          uint64_t seed, const int32_t cn[3],
+                                          const int32_t *const Ls[3], unsigned bid, unsigned nb) {
+    const int G = SMALL_G;
+    const int32_t *mate = L->mate;
+    int32_t *best = c.ms.best;
+    int sub = threadIdx.x & (G - 1);
+    int64_t gi = (int64_t)bid * (blockDim.x / G) + threadIdx.x / G;
+    int64_t gs = (int64_t)nb * (blockDim.x / G);
+    int64_t lim = ((int64_t)cn[0] + gs - 1) / gs * gs;   // uniform trip count
+    for (int64_t i = gi; i < lim; i += gs) {
+        int32_t v = -1;
+        bool act = false;
+        if (i < cn[0]) {
+            v = FIRST ? (int32_t)i : checked_node(Ls[0][i], g.n, c.ctrl);
+            if (v < 0) {
+                act = false;
+            } else if (FIRST) {
+                int64_t d = g.xadj[v + 1] - g.xadj[v];
+                act = d >= 1 && d <= BIN_SMALL_MAX;
+            } else {
+                act = needs_rescan(v, best, mate);
+            }
+        }
+        Cand cd = act ? scan_row<R, G>(g, v, sub, mate, c.ms.out, seed, FIRST) : cand_none();
+        cd = group_reduce<G>(cd, v);
+        if (act && sub == 0) best[v] = cd.u;
+    }
+}
+
+// bin 1: one wave per node
+template <int R, bool FIRST>
+__device__ __forceinline__ void pick_bin1(const Ctx &c, const DevGraph &g, const LevelDesc *L,
+                                          uint64_t seed, const int32_t cn[3],
+                                          const int32_t *const Ls[3], unsigned bid, unsigned nb) {
+    const int32_t *mate = L->mate;
+    int32_t *best = c.ms.best;
+    int64_t gi = (int64_t)bid * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    int64_t gs = (int64_t)nb * (blockDim.x / WAVE);
+    for (int64_t i = gi; i < cn[1]; i += gs) {
+        int32_t v = checked_node(Ls[1][i], g.n, c.ctrl);
+        if (v < 0 || (!FIRST && !needs_rescan(v, best, mate))) continue;   // wave-uniform
+        Cand cd = scan_row<R, WAVE>(g, v, lane_id(), mate, c.ms.out, seed, FIRST);
+        cd = group_reduce<WAVE>(cd, v);
+        if (lane_id() == 0) best[v] = cd.u;
+    }
+}
+
+// bin 2: one block per node (blockDim.x lanes, a multiple of 64)
+template <int R, bool FIRST, int NT>
+__device__ __forceinline__ void pick_bin2(const Ctx &c, const DevGraph &g, const LevelDesc *L,
+                                          uint64_t seed, const int32_t cn[3],
+                                          const int32_t *const Ls[3], unsigned bid, unsigned nb,
+                                          Cand *sh) {
+    const int32_t *mate = L->mate;
+    int32_t *best = c.ms.best;
+    for (int64_t i = bid; i < cn[2]; i += nb) {
+        int32_t v = checked_node(Ls[2][i], g.n, c.ctrl);
+        if (v < 0 || (!FIRST && !needs_rescan(v, best, mate))) continue;   // block-uniform
+        Cand cd = scan_row<R, NT>(g, v, threadIdx.x, mate, c.ms.out, seed, FIRST);
+        cd = block_reduce_cand(cd, v, sh);
+        if (threadIdx.x == 0) best[v] = cd.u;
+    }
+}
+
+// Mutual check of round r; survivors to the round's output lists.
+template <bool FIRST>
+__device__ __forceinline__ void mate_phase(const Ctx &c, const DevGraph &g, LevelDesc *L, int r,
+                                           const int32_t cn[3], const int32_t *const Ls[3],
+                                           unsigned bid, unsigned nb, int64_t *sh, int32_t *sha) {
+    MatchState *st = c.ms.state;
+    int32_t *mate = L->mate;
+    const int32_t *best = c.ms.best;
+    // round 1 checks every node once (cn[1], cn[2] only feed its pick phase)
+    const int64_t total = FIRST ? (int64_t)g.n : (int64_t)cn[0] + cn[1] + cn[2];
+    const int opar = r & 1, oslot = r & 3;
+    if (bid == 0 && threadIdx.x < 3) st->cnt[(r + 2) & 3][threadIdx.x] = 0;
+    int32_t *olists[3] = {list_ptr(c.ms.lists, g.n, opar, 0), list_ptr(c.ms.lists, g.n, opar, 1),
+                          list_ptr(c.ms.lists, g.n, opar, 2)};
+    int32_t *ocnt[3] = {&st->cnt[oslot][0], &st->cnt[oslot][1], &st->cnt[oslot][2]};
+    int64_t point = 0, degs = 0, pairs = 0;
+    const int64_t stride = (int64_t)nb * blockDim.x;
+    const int64_t lim = (total + stride - 1) / stride * stride;   // block-uniform trips
+    for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < lim; i += stride) {
+        int bn = -1;
+        int32_t v = -1;
+        if (i < total) {
+            if (FIRST) v = (int32_t)i;
+            else if (i < cn[0]) v = Ls[0][i];
+            else if (i < (int64_t)cn[0] + cn[1]) v = Ls[1][i - cn[0]];
+            else v = Ls[2][i - cn[0] - cn[1]];
+            if (!FIRST) v = checked_node(v, g.n, c.ctrl);
+            int32_t b = v >= 0 ? best[v] : -1;
+            if (b >= (int32_t)g.n) b = checked_node(b, g.n, c.ctrl);
+            if (b >= 0) {
+                int64_t d = g.xadj[v + 1] - g.xadj[v];
+                ++point;
+                degs += d;
+                if (best[b] == v) {
+                    mate[v] = b;
+                    if (v < b) ++pairs;
+                } else {
+                    bn = bin_of(d);
+                }
+            }
+        }
+        block_append3(bn, v, olists, ocnt, sha);
+    }
+    point = block_sum(point, sh);
+    degs = block_sum(degs, sh);
+    pairs = block_sum(pairs, sh);
+    if (threadIdx.x == 0 && point > 0) {
+        int ri = r - 1 < STAT_ROUNDS ? r - 1 : STAT_ROUNDS - 1;
+        atomicAdd((unsigned long long *)&st->stat[ri][0], (unsigned long long)point);
+        atomicAdd((unsigned long long *)&st->stat[ri][1], (unsigned long long)degs);
+        if (pairs) atomicAdd((unsigned long long *)&st->matched, (unsigned long long)pairs);
+        atomicMax(&st->rounds, r);
+    }
+}
+
+// --- per-round kernels (used where a cooperative launch is not available) ---
+__global__ void __launch_bounds__(BLOCK) match_init_k(Ctx c, int l) {
+    __shared__ int32_t sha[3 * (BLOCK / WAVE) + 3];
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_MATCH, g)) return;
+    init_phase(c, g, L, blockIdx.x, gridDim.x, sha);
+}
+
+struct PickGrid {
+    unsigned b0, b1, b2;  // blocks per bin
+};
+
+template <int R, bool FIRST>
+__global__ void __launch_bounds__(BLOCK) pick_k(Ctx c, int l, int r, PickGrid pg) {
+    __shared__ Cand sh[BLOCK / WAVE];
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_MATCH, g)) return;
+    MatchState *st = c.ms.state;
+    if (st->handoff != -1) return;
+    int32_t cn[3];
+    const int32_t *Ls[3];
+    int64_t total = round_inputs<FIRST>(c, g, r, cn, Ls);
+    if (!FIRST) {
+        if (total == 0) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(&st->handoff, -1, -2);
+            return;
+        }
+        if (total <= TAIL_MAX) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(&st->handoff, -1, r - 1);
+            return;
+        }
+    }
+    const uint64_t seed = level_seed(c, l);
+    unsigned bid = blockIdx.x;
+    if (bid < pg.b0) { pick_bin0<R, FIRST>(c, g, L, seed, cn, Ls, bid, pg.b0); return; }
+    bid -= pg.b0;
+    if (bid < pg.b1) { pick_bin1<R, FIRST>(c, g, L, seed, cn, Ls, bid, pg.b1); return; }
+    bid -= pg.b1;
+    pick_bin2<R, FIRST, BLOCK>(c, g, L, seed, cn, Ls, bid, pg.b2, sh);
+}
+
+template <bool FIRST>
+__global__ void __launch_bounds__(BLOCK) mate_k(Ctx c, int l, int r) {
+    __shared__ int64_t sh[BLOCK / WAVE + 1];
+    __shared__ int32_t sha[3 * (BLOCK / WAVE) + 3];
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_MATCH, g)) return;
+    if (c.ms.state->handoff != -1) return;
+    int32_t cn[3];
+    const int32_t *Ls[3];
+    round_inputs<FIRST>(c, g, r, cn, Ls);
+    mate_phase<FIRST>(c, g, L, r, cn, Ls, blockIdx.x, gridDim.x, sh, sha);
+}
+
+// --- cooperative kernel: init + rounds until few nodes remain --------------
+// All blocks are co-resident (cooperative launch); rounds are separated by a
+// grid barrier on a counter/generation pair.  The spin is bounded: on a
+// timeout the control flags record it and the level is abandoned.
+constexpr int COOP_THREADS = 256;
+
+__device__ __forceinline__ bool grid_sync(MatchState *st, Control *ctrl) {
+    __threadfence();
+    __syncthreads();
+    __shared__ int ok;
+    if (threadIdx.x == 0) {
+        ok = 1;
+        unsigned *cnt = (unsigned *)&st->pad[0], *gen = (unsigned *)&st->pad[1];
+        unsigned g0 = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned arrived = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == gridDim.x - 1) {
+            __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long spins = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > (1l << 26)) {
+                    atomicOr(&ctrl->flags, (uint32_t)CF_ROUNDS);
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    __threadfence();
+    return ok != 0;
+}
+
+template <int R>
+__global__ void __launch_bounds__(COOP_THREADS) coop_match_k(Ctx c, int l, int r_last) {
+    __shared__ Cand shc[COOP_THREADS / WAVE];
+    __shared__ int64_t sh[COOP_THREADS / WAVE + 1];
+    __shared__ int32_t sha[3 * (COOP_THREADS / WAVE) + 3];
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_MATCH, g)) return;   // same answer for every block
+    MatchState *st = c.ms.state;
+    if (st->handoff != -1) return;             // the per-round kernels already got there
+    {
+        int slot = r_last & 3;
+        int64_t left = (int64_t)st->cnt[slot][0] + st->cnt[slot][1] + st->cnt[slot][2];
+        if (left <= TAIL_MAX) return;          // the finisher takes it from here
+    }
+    Control *ctrl = c.ctrl;
+    const unsigned bid = blockIdx.x, nb = gridDim.x;
+    const uint64_t seed = level_seed(c, l);
+    int32_t cn[3];
+    const int32_t *Ls[3];
+    int r = r_last + 1;
+    int64_t left = 0;
+    for (;; ++r) {
+        round_inputs<false>(c, g, r, cn, Ls);
+        pick_bin0<R, false>(c, g, L, seed, cn, Ls, bid, nb);
+        pick_bin1<R, false>(c, g, L, seed, cn, Ls, bid, nb);
+        pick_bin2<R, false, COOP_THREADS>(c, g, L, seed, cn, Ls, bid, nb, shc);
+        if (!grid_sync(st, ctrl)) return;
+        mate_phase<false>(c, g, L, r, cn, Ls, bid, nb, sh, sha);
+        if (!grid_sync(st, ctrl)) return;
+        left = (int64_t)st->cnt[r & 3][0] + st->cnt[r & 3][1] + st->cnt[r & 3][2];
+        if (left <= TAIL_MAX || r > g.n + 2) break;
+    }
+    // the one-workgroup finisher resumes after round r
+    if (bid == 0 && threadIdx.x == 0) st->handoff = left == 0 ? -2 : r;
+}
+
+// Finisher: one workgroup runs the remaining rounds (from the handoff point,
+// or after round r_last), then closes the level's matching.
+template <int R>
+__global__ void __launch_bounds__(FINISH_THREADS) finish_k(Ctx c, int l, int r_last) {
+    __shared__ Cand shc[FINISH_THREADS / WAVE];
+    __shared__ int32_t s_cnt[2][3];
+    __shared__ int64_t s_acc[3];   // pointing, degsum, pairs of the current round
+    __shared__ int32_t s_r0;
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_MATCH, g)) return;
+    MatchState *st = c.ms.state;
+    int32_t *mate = L->mate, *best = c.ms.best, *lists = c.ms.lists;
+    const uint32_t *out = c.ms.out;
+    const uint64_t seed = level_seed(c, l);
+    if (threadIdx.x == 0) {
+        int h = st->handoff;
+        if (h == -1) h = r_last;   // every round up to r_last ran: take over from there
+        s_r0 = h;
+    }
+    __syncthreads();
+    const int r0 = s_r0;
+    int64_t pairs_total = 0;
+    bool capped = false;
+    if (r0 >= 0) {
+        if (threadIdx.x < 3) {
+            s_cnt[r0 & 1][threadIdx.x] = st->cnt[r0 & 3][threadIdx.x];
+            s_cnt[(r0 + 1) & 1][threadIdx.x] = 0;
+        }
+        __syncthreads();
+        // Every round that has a pointing node matches at least one pair, so
+        // at most n/2 + 1 rounds remain; the cap only guards broken state.
+        const int64_t r_cap = (int64_t)r0 + 2 + g.n;
+        capped = true;
+        for (int r = r0 + 1; r <= r_cap; ++r) {
+            int ip = (r - 1) & 1, op = r & 1;
+            int32_t c0 = min(s_cnt[ip][0], g.n), c1 = min(s_cnt[ip][1], g.n),
+                    c2 = min(s_cnt[ip][2], g.n);
+            if ((int64_t)c0 + c1 + c2 == 0) { capped = false; break; }
+            const int32_t *L0 = list_ptr(lists, g.n, ip, 0);
+            const int32_t *L1 = list_ptr(lists, g.n, ip, 1);
+            const int32_t *L2 = list_ptr(lists, g.n, ip, 2);
+            {
+                const int G = SMALL_G;
+                int sub = threadIdx.x & (G - 1);
+                int gi = threadIdx.x / G, gs = FINISH_THREADS / G;
+                int lim = (c0 + gs - 1) / gs * gs;
+                for (int i = gi; i < lim; i += gs) {
+                    int32_t v = i < c0 ? checked_node(L0[i], g.n, c.ctrl) : -1;
+                    bool act = v >= 0 && needs_rescan(v, best, mate);
+                    Cand cd = act ? scan_row<R, G>(g, v, sub, mate, out, seed, false) : cand_none();
+                    cd = group_reduce<G>(cd, v);
+                    if (act && sub == 0) best[v] = cd.u;
+                }
+                int wi = threadIdx.x / WAVE, ws = FINISH_THREADS / WAVE;
+                for (int i = wi; i < c1; i += ws) {
+                    int32_t v = checked_node(L1[i], g.n, c.ctrl);
+                    if (v < 0 || !needs_rescan(v, best, mate)) continue;
+                    Cand cd = scan_row<R, WAVE>(g, v, lane_id(), mate, out, seed, false);
+                    cd = group_reduce<WAVE>(cd, v);
+                    if (lane_id() == 0) best[v] = cd.u;
+                }
+            }
+            __syncthreads();
+            for (int i = 0; i < c2; ++i) {
+                int32_t v = checked_node(L2[i], g.n, c.ctrl);
+                if (v < 0 || !needs_rescan(v, best, mate)) continue;   // block-uniform
+                Cand cd = scan_row<R, FINISH_THREADS>(g, v, threadIdx.x, mate, out, seed, false);
+                cd = block_reduce_cand(cd, v, shc);
+                if (threadIdx.x == 0) best[v] = cd.u;
+            }
+            if (threadIdx.x < 3) { s_acc[threadIdx.x] = 0; s_cnt[op][threadIdx.x] = 0; }
+            __syncthreads();
+            int32_t total = c0 + c1 + c2;
+            int64_t point = 0, degs = 0, pairs = 0;
+            int lim = (total + FINISH_THREADS - 1) / FINISH_THREADS * FINISH_THREADS;
+            for (int i = threadIdx.x; i < lim; i += FINISH_THREADS) {
+                bool keep = false;
+                int bn = 0;
+                int32_t v = -1;
+                if (i < total) {
+                    v = i < c0 ? L0[i] : (i < c0 + c1 ? L1[i - c0] : L2[i - c0 - c1]);
+                    v = checked_node(v, g.n, c.ctrl);
+                    int32_t b = v >= 0 ? best[v] : -1;
+                    if (b >= (int32_t)g.n) b = checked_node(b, g.n, c.ctrl);
+                    if (b >= 0) {
+                        int64_t d = g.xadj[v + 1] - g.xadj[v];
+                        ++point;
+                        degs += d;
+                        if (best[b] == v) {
+                            mate[v] = b;
+                            if (v < b) ++pairs;
+                        } else {
+                            keep = true;
+                            bn = bin_of(d);
+                        }
+                    }
+                }
+                wave_append(keep && bn == 0, v, list_ptr(lists, g.n, op, 0), &s_cnt[op][0]);
+                wave_append(keep && bn == 1, v, list_ptr(lists, g.n, op, 1), &s_cnt[op][1]);
+                wave_append(keep && bn == 2, v, list_ptr(lists, g.n, op, 2), &s_cnt[op][2]);
+            }
+            point = wave_sum(point);
+            degs = wave_sum(degs);
+            pairs = wave_sum(pairs);
+            if (lane_id() == 0) {
+                if (point) atomicAdd((unsigned long long *)&s_acc[0], (unsigned long long)point);
+                if (degs) atomicAdd((unsigned long long *)&s_acc[1], (unsigned long long)degs);
+                if (pairs) atomicAdd((unsigned long long *)&s_acc[2], (unsigned long long)pairs);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                if (s_acc[0] > 0) {
+                    int ri = r - 1 < STAT_ROUNDS ? r - 1 : STAT_ROUNDS - 1;
+                    st->stat[ri][0] += s_acc[0];
+                    st->stat[ri][1] += s_acc[1];
+                    st->rounds = r;
+                }
+                pairs_total += s_acc[2];
+            }
+            __syncthreads();
+        }
+    }
+    // close the level's matching
+    __syncthreads();
+    for (int i = threadIdx.x; i < STAT_ROUNDS; i += blockDim.x) {
+        L->stat[i][0] = st->stat[i][0];
+        L->stat[i][1] = st->stat[i][1];
+    }
+    if (threadIdx.x < 4) {
+        c.cs.row_cnt[threadIdx.x] = 0;
+        c.cs.totals[threadIdx.x] = 0;
+    }
+    if (threadIdx.x == 0) {
+        int64_t m = st->matched + pairs_total;
+        st->matched = m;
+        st->handoff = -2;
+        L->matched = m;
+        L->rounds = st->rounds;
+        if (capped) c.ctrl->flags |= CF_ROUNDS;
+        if (m == 0 || capped) {
+            L->stop = KAPPA_STOP_EMPTY;
+            L->phase = PH_STOPPED;
+            c.ctrl->done = 1;
+        } else {
+            L->phase = PH_CONTRACT;
+        }
+    }
+}
+
+// ===========================================================================
+// Contraction
+// ===========================================================================
+constexpr uint32_t INVALID_KEY = 0xffffffffu;
+constexpr int SM_ROWS = BLOCK / ROW_SMALL_G;      // 16 small rows per block
+constexpr int SM_CAP = ROW_SMALL_MAX + 2;        // entries incl. the dropped edge
+constexpr int MID_P = 4096;
+
+// --- 1. representatives; the next level's node arrays ------------------------
+struct RepF {
+    Ctx c;
+    int l;
+    __device__ int64_t size() const {
+        const LevelDesc *L = c.lv + l;
+        return L->phase == PH_CONTRACT ? L->n : -1;
+    }
+    __device__ int64_t operator()(int64_t i) const {
+        int32_t m = c.lv[l].mate[i];
+        return (m < 0 || i < m) ? 1 : 0;
+    }
+    __device__ void post(int64_t nc) const {
+        LevelDesc *L = c.lv + l, *N = c.lv + l + 1;
+        if (L->phase != PH_CONTRACT) return;
+        N->n = (int32_t)nc;
+        N->vw = (uint32_t *)arena_alloc(c.ctrl, (uint64_t)nc * 4);
+        N->xadj = (int64_t *)arena_alloc(c.ctrl, (uint64_t)(nc + 1) * 8);
+        N->adj = nullptr;
+        N->ew = nullptr;
+        N->cmap = nullptr;
+        N->mate = nullptr;
+        N->phase = PH_IDLE;
+        N->stop = KAPPA_STOP_NONE;
+        if (!N->vw || !N->xadj) {
+            L->phase = PH_STOPPED;
+            c.ctrl->done = 1;
+        }
+    }
+};
+struct RepW {
+    Ctx c;
+    int l;
+    __device__ void operator()(int64_t i, int64_t pre, int64_t v) const {
+        if (v) {
+            c.lv[l].cmap[i] = (int32_t)pre;
+            c.cs.rep_of[pre] = (int32_t)i;
+        }
+    }
+};
+
+// --- 2. coarse nodes ------------------------------------------------------------
+__global__ void __launch_bounds__(BLOCK) coarse_nodes_k(Ctx c, int l) {
+    __shared__ int32_t sha[3 * (BLOCK / WAVE) + 3];
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_CONTRACT, g)) return;
+    const LevelDesc *N = c.lv + l + 1;
+    const int64_t nc = N->n;
+    const int32_t *mate = L->mate;
+    int32_t *cmap = L->cmap;
+    uint32_t *cvw = N->vw;
+    int32_t *rows = c.cs.rows;
+    int32_t *lists[3] = {rows, rows + g.n, rows + 2 * (int64_t)g.n};
+    int32_t *cnts[3] = {&c.cs.row_cnt[0], &c.cs.row_cnt[1], &c.cs.row_cnt[2]};
+    bool need_hubs = false;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t lim = (nc + stride - 1) / stride * stride;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < lim; x += stride) {
+        int cls = -1;
+        if (x < nc) {
+            int32_t u = c.cs.rep_of[x];
+            int32_t w = mate[u];
+            uint32_t cw = g.vw[u];
+            int64_t bnd = g.xadj[u + 1] - g.xadj[u];
+            if (w >= 0) {
+                cmap[w] = (int32_t)x;
+                cw += g.vw[w];
+                bnd += g.xadj[w + 1] - g.xadj[w] - 2;
+            }
+            c.cs.partner[x] = w;
+            cvw[x] = cw;
+            c.cs.cdeg[x] = (int32_t)bnd;
+            cls = bnd == 0 ? -1 : (bnd <= ROW_SMALL_MAX ? 0 : (bnd <= ROW_MID_MAX ? 1 : 2));
+            if (cls == 2 && !c.cs.hub_acc) need_hubs = true;
+        }
+        block_append3(cls, (int32_t)x, lists, cnts, sha);
+    }
+    if (__ballot(need_hubs) && lane_id() == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_HUBS);
+}
+
+// --- 3./5. scans over coarse rows ------------------------------------------------
+struct BoundF {
+    Ctx c;
+    int l;
+    __device__ int64_t size() const {
+        return c.lv[l].phase == PH_CONTRACT ? c.lv[l + 1].n + 1 : -1;
+    }
+    __device__ int64_t operator()(int64_t i) const {
+        return i < c.lv[l + 1].n ? c.cs.cdeg[i] : 0;
+    }
+    __device__ void post(int64_t) const {}
+};
+struct TmpOffW {
+    Ctx c;
+    __device__ void operator()(int64_t i, int64_t pre, int64_t) const { c.cs.tmp_off[i] = pre; }
+};
+// Merged degrees -> coarse offsets; then the next level's edge arrays and the
+// stall rule.
+struct DegF {
+    Ctx c;
+    int l;
+    // post() moves the level to PH_COMPACT before the apply kernel runs
+    __device__ int64_t size() const {
+        int32_t ph = c.lv[l].phase;
+        return (ph == PH_CONTRACT || ph == PH_COMPACT) ? c.lv[l + 1].n + 1 : -1;
+    }
+    __device__ int64_t operator()(int64_t i) const {
+        return i < c.lv[l + 1].n ? c.cs.cdeg[i] : 0;
+    }
+    __device__ void post(int64_t nnzc) const {
+        Control *ctrl = c.ctrl;
+        LevelDesc *L = c.lv + l, *N = c.lv + l + 1;
+        if (L->phase != PH_CONTRACT) return;
+        if (ctrl->flags & CF_HUBS) {   // rows were left unmerged: stop, the host retries
+            L->phase = PH_STOPPED;
+            ctrl->done = 1;
+            return;
+        }
+        N->nnz = nnzc;
+        N->adj = (int32_t *)arena_alloc(ctrl, (uint64_t)nnzc * 4);
+        N->ew = (uint32_t *)arena_alloc(ctrl, (uint64_t)nnzc * 4);
+        N->maxdeg = (int32_t)c.cs.totals[3];
+        if (!N->adj || !N->ew) {
+            L->phase = PH_STOPPED;
+            ctrl->done = 1;
+            return;
+        }
+        L->phase = PH_COMPACT;
+        ctrl->nlevels = l + 2;
+        const int64_t n = L->n, nc = N->n;
+        if (ctrl->stall_num > 0 &&
+            (uint64_t)(n - nc) * ctrl->stall_den < (uint64_t)ctrl->stall_num * (uint64_t)n) {
+            N->stop = KAPPA_STOP_STALL;
+            N->phase = PH_STOPPED;
+            ctrl->done = 1;
+        }
+    }
+};
+struct CoarseOffW {
+    Ctx c;
+    int l;
+    __device__ void operator()(int64_t i, int64_t pre, int64_t) const { c.lv[l + 1].xadj[i] = pre; }
+};
+
+// The fine entries of coarse row x: row u, then row w (partner), each
+// without the contracted edge.  t-th entry -> (coarse key, weight);
+// INVALID_KEY for the contracted edge.
+struct RowSrc {
+    int32_t u, w;
+    int64_t bu, du, bw;
+    int64_t tot;
+};
+__device__ __forceinline__ RowSrc row_src(const DevGraph &g, const Ctx &c, int32_t x) {
+    RowSrc r;
+    r.u = c.cs.rep_of[x];
+    r.w = c.cs.partner[x];
+    r.bu = g.xadj[r.u];
+    r.du = g.xadj[r.u + 1] - r.bu;
+    r.bw = 0;
+    int64_t dw = 0;
+    if (r.w >= 0) {
+        r.bw = g.xadj[r.w];
+        dw = g.xadj[r.w + 1] - r.bw;
+    }
+    r.tot = r.du + dw;
+    return r;
+}
+__device__ __forceinline__ void row_entry(const DevGraph &g, const int32_t *cmap, const RowSrc &r,
+                                          int64_t t, uint32_t &key, uint32_t &wt) {
+    int32_t nb;
+    if (t < r.du) {
+        nb = g.adj[r.bu + t];
+        wt = g.ew[r.bu + t];
+        key = nb == r.w ? INVALID_KEY : (uint32_t)cmap[nb];
+    } else {
+        int64_t j = r.bw + (t - r.du);
+        nb = g.adj[j];
+        wt = g.ew[j];
+        key = nb == r.u ? INVALID_KEY : (uint32_t)cmap[nb];
+    }
+}
+
+// --- 4a. small rows: 16 lanes per row, rank sort ------------------------------
+__global__ void __launch_bounds__(BLOCK) fill_small_k(Ctx c, int l) {
+    __shared__ uint32_t sk[SM_ROWS][SM_CAP];
+    __shared__ uint32_t sw[SM_ROWS][SM_CAP];
+    __shared__ uint8_t sf[SM_ROWS][SM_CAP];
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_CONTRACT, g)) return;
+    const int32_t *cmap = L->cmap;
+    const int grp = threadIdx.x / ROW_SMALL_G, sub = threadIdx.x % ROW_SMALL_G;
+    const int64_t count = c.cs.row_cnt[0];
+    const int32_t *rows = c.cs.rows;
+    const int64_t gs = (int64_t)gridDim.x * SM_ROWS;
+    const int64_t lim = (count + gs - 1) / gs * gs;
+    int32_t dmax = 0;
+    for (int64_t i = (int64_t)blockIdx.x * SM_ROWS + grp; i < lim; i += gs) {
+        bool live = i < count;
+        int32_t x = live ? rows[i] : 0;
+        RowSrc r;
+        r.tot = 0;
+        if (live) r = row_src(g, c, x);
+        for (int64_t t = sub; t < r.tot; t += ROW_SMALL_G) {
+            uint32_t k, w;
+            row_entry(g, cmap, r, t, k, w);
+            sk[grp][t] = k;
+            sw[grp][t] = w;
+        }
+        __syncthreads();
+        int tot = (int)r.tot;
+        for (int t = sub; t < tot; t += ROW_SMALL_G) {
+            uint32_t k = sk[grp][t];
+            bool lead = k != INVALID_KEY;
+            for (int q = 0; q < t && lead; ++q) lead = sk[grp][q] != k;
+            sf[grp][t] = lead;
+        }
+        __syncthreads();
+        int nl = 0;
+        int64_t off = live ? c.cs.tmp_off[x] : 0;
+        for (int t = sub; t < tot; t += ROW_SMALL_G) {
+            if (!sf[grp][t]) continue;
+            uint32_t k = sk[grp][t];
+            int rank = 0;
+            uint32_t sum = 0;
+            for (int q = 0; q < tot; ++q) {
+                uint32_t kq = sk[grp][q];
+                rank += (sf[grp][q] && kq < k) ? 1 : 0;
+                sum += kq == k ? sw[grp][q] : 0u;
+            }
+            c.cs.tmp_adj[off + rank] = (int32_t)k;
+            c.cs.tmp_ew[off + rank] = sum;
+            ++nl;
+        }
+        for (int o = ROW_SMALL_G / 2; o > 0; o >>= 1) nl += __shfl_xor(nl, o, ROW_SMALL_G);
+        if (live && sub == 0) {
+            c.cs.cdeg[x] = nl;
+            dmax = nl > dmax ? nl : dmax;
+        }
+        __syncthreads();
+    }
+    dmax = wave_max(dmax);
+    if (lane_id() == 0 && dmax)
+        atomicMax((unsigned long long *)&c.cs.totals[3], (unsigned long long)dmax);
+}
+
+// --- 4b. mid rows: one block per row, bitonic sort in LDS -------------------------
+__global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l) {
+    __shared__ uint64_t s[MID_P];
+    __shared__ int64_t sh[BLOCK / WAVE + 1];
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_CONTRACT, g)) return;
+    const int32_t *cmap = L->cmap;
+    const int64_t count = c.cs.row_cnt[1];
+    int32_t dmax = 0;
+    for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+        int32_t x = c.cs.rows[g.n + i];
+        RowSrc r = row_src(g, c, x);
+        int tot = (int)r.tot;
+        int P = 2;
+        while (P < tot) P <<= 1;
+        for (int t = threadIdx.x; t < P; t += BLOCK) {
+            uint64_t val = ~0ull;
+            if (t < tot) {
+                uint32_t k, w;
+                row_entry(g, cmap, r, t, k, w);
+                val = ((uint64_t)k << 32) | w;
+            }
+            s[t] = val;
+        }
+        __syncthreads();
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int t = threadIdx.x; t < P; t += BLOCK) {
+                    int ixj = t ^ j;
+                    if (ixj > t) {
+                        uint64_t a = s[t], b = s[ixj];
+                        bool up = (t & k) == 0;
+                        if ((a > b) == up) { s[t] = b; s[ixj] = a; }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // leaders: first entry of each run of equal keys
+        const int ipt = (P + BLOCK - 1) / BLOCK;
+        const int t0 = threadIdx.x * ipt;
+        int64_t mine = 0;
+        for (int q = 0; q < ipt; ++q) {
+            int t = t0 + q;
+            if (t >= P) break;
+            uint32_t k = (uint32_t)(s[t] >> 32);
+            if (k != INVALID_KEY && (t == 0 || (uint32_t)(s[t - 1] >> 32) != k)) ++mine;
+        }
+        int64_t total;
+        int64_t rank = block_excl_scan(mine, sh, &total);
+        int64_t off = c.cs.tmp_off[x];
+        for (int q = 0; q < ipt; ++q) {
+            int t = t0 + q;
+            if (t >= P) break;
+            uint32_t k = (uint32_t)(s[t] >> 32);
+            if (k == INVALID_KEY || (t > 0 && (uint32_t)(s[t - 1] >> 32) == k)) continue;
+            uint32_t sum = 0;
+            for (int e = t; e < P && (uint32_t)(s[e] >> 32) == k; ++e) sum += (uint32_t)s[e];
+            c.cs.tmp_adj[off + rank] = (int32_t)k;
+            c.cs.tmp_ew[off + rank] = sum;
+            ++rank;
+        }
+        if (threadIdx.x == 0) {
+            c.cs.cdeg[x] = (int32_t)total;
+            dmax = (int32_t)total > dmax ? (int32_t)total : dmax;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && dmax)
+        atomicMax((unsigned long long *)&c.cs.totals[3], (unsigned long long)dmax);
+}
+
+// --- 4c. large rows: dense accumulator per slot --------------------------------------
+__global__ void __launch_bounds__(BLOCK) fill_large_k(Ctx c, int l) {
+    __shared__ int64_t s_wcnt[BLOCK / WAVE + 1];
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_CONTRACT, g)) return;
+    if (!c.cs.hub_acc) return;
+    const int32_t *cmap = L->cmap;
+    uint32_t *acc = c.cs.hub_acc + (int64_t)blockIdx.x * g.n;
+    uint32_t *bits = c.cs.hub_bits + (int64_t)blockIdx.x * c.cs.hub_words;
+    const int64_t nc = c.lv[l + 1].n;
+    const int64_t nwords = (nc + 31) / 32;
+    const int64_t count = c.cs.row_cnt[2];
+    const int nw = BLOCK / WAVE, wv = threadIdx.x / WAVE;
+    const int64_t span = (nwords + nw - 1) / nw;
+    const int64_t lo = wv * span, hi = lo + span < nwords ? lo + span : nwords;
+    for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+        int32_t x = c.cs.rows[2 * (int64_t)g.n + i];
+        RowSrc r = row_src(g, c, x);
+        for (int64_t t = threadIdx.x; t < r.tot; t += BLOCK) {
+            uint32_t k, w;
+            row_entry(g, cmap, r, t, k, w);
+            if (k == INVALID_KEY) continue;
+            atomicAdd(&acc[k], w);
+            atomicOr(&bits[k >> 5], 1u << (k & 31));
+        }
+        __threadfence();
+        __syncthreads();
+        // pass 1: set bits per wave range (L1-bypassing loads)
+        int64_t cntw = 0;
+        for (int64_t q = lo + lane_id(); q < hi; q += WAVE)
+            cntw += __popc(__hip_atomic_load(&bits[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        cntw = wave_sum(cntw);
+        if (lane_id() == 0) s_wcnt[wv] = cntw;
+        __syncthreads();
+        int64_t base = 0, total = 0;
+        for (int q = 0; q < nw; ++q) {
+            if (q < wv) base += s_wcnt[q];
+            total += s_wcnt[q];
+        }
+        // pass 2: ascending walk, read-and-clear bits and accumulators
+        int64_t off = c.cs.tmp_off[x];
+        for (int64_t q0 = lo; q0 < hi; q0 += WAVE) {
+            int64_t q = q0 + lane_id();
+            uint32_t word = q < hi ? atomicExch(&bits[q], 0u) : 0u;
+            int64_t pc = __popc(word);
+            int64_t inc = wave_incl_scan(pc);
+            int64_t pos = base + inc - pc;
+            while (word) {
+                int b = __ffs(word) - 1;
+                word &= word - 1;
+                uint32_t key = (uint32_t)(q * 32 + b);
+                c.cs.tmp_adj[off + pos] = (int32_t)key;
+                c.cs.tmp_ew[off + pos] = atomicExch(&acc[key], 0u);
+                ++pos;
+            }
+            base += __shfl(inc, WAVE - 1, WAVE);
+        }
+        if (threadIdx.x == 0) {
+            c.cs.cdeg[x] = (int32_t)total;
+            atomicMax((unsigned long long *)&c.cs.totals[3], (unsigned long long)total);
+        }
+        __threadfence();
+        __syncthreads();
+    }
+}
+
+// --- 6. compaction ----------------------------------------------------------------
+__global__ void __launch_bounds__(BLOCK) compact_small_k(Ctx c, int l) {
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_COMPACT, g)) return;
+    const LevelDesc *N = c.lv + l + 1;
+    const int grp = threadIdx.x / ROW_SMALL_G, sub = threadIdx.x % ROW_SMALL_G;
+    const int64_t count = c.cs.row_cnt[0];
+    for (int64_t i = (int64_t)blockIdx.x * SM_ROWS + grp; i < count;
+         i += (int64_t)gridDim.x * SM_ROWS) {
+        int32_t x = c.cs.rows[i];
+        int64_t src = c.cs.tmp_off[x], dst = N->xadj[x];
+        int32_t len = c.cs.cdeg[x];
+        for (int t = sub; t < len; t += ROW_SMALL_G) {
+            N->adj[dst + t] = c.cs.tmp_adj[src + t];
+            N->ew[dst + t] = c.cs.tmp_ew[src + t];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(BLOCK) compact_big_k(Ctx c, int l) {
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_COMPACT, g)) return;
+    const LevelDesc *N = c.lv + l + 1;
+    const int64_t c1 = c.cs.row_cnt[1], c2 = c.cs.row_cnt[2];
+    for (int64_t i = blockIdx.x; i < c1 + c2; i += gridDim.x) {
+        int32_t x = i < c1 ? c.cs.rows[g.n + i] : c.cs.rows[2 * (int64_t)g.n + (i - c1)];
+        int64_t src = c.cs.tmp_off[x], dst = N->xadj[x];
+        int32_t len = c.cs.cdeg[x];
+        for (int t = threadIdx.x; t < len; t += BLOCK) {
+            N->adj[dst + t] = c.cs.tmp_adj[src + t];
+            N->ew[dst + t] = c.cs.tmp_ew[src + t];
+        }
+    }
+}
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+void launch_level_begin(const Ctx &c, int l, bool stop_rules, hipStream_t s) {
+    KAPPA_PROF("level_begin", s);
+    hipLaunchKernelGGL(level_begin_k, dim3(1), dim3(WAVE), 0, s, c, l, stop_rules ? 1 : 0);
+}
+
+// Co-resident block count for the cooperative kernel (0 if unavailable).
+template <int R>
+static unsigned coop_capacity() {
+    static unsigned cap = 0;
+    static bool probed = false;
+    if (!probed) {
+        probed = true;
+        int dev = 0, coop = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess &&
+            coop &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, coop_match_k<R>, COOP_THREADS, 0) ==
+                hipSuccess &&
+            per > 0)
+            cap = (unsigned)(cus * std::min(per, 2));
+    }
+    return cap;
+}
+
+template <int R>
+static void match_impl(const Ctx &c, int l, int32_t n_hint, int rounds, hipStream_t s) {
+    // per-round kernels; round r's grid follows a geometric estimate of the
+    // pending count (any grid is correct: all loops stride)
+    {
+        KAPPA_PROF("match_init", s);
+        hipLaunchKernelGGL(match_init_k, dim3(grid_for(n_hint, BLOCK * 2, 2048)), dim3(BLOCK), 0, s,
+                           c, l);
+    }
+    double est = n_hint;
+    for (int r = 1; r <= rounds; ++r, est *= 0.7) {
+        int64_t e = (int64_t)est + 1;
+        PickGrid pg;
+        pg.b0 = grid_for(e, BLOCK / SMALL_G, 2048);
+        pg.b1 = grid_for(e, BLOCK / WAVE * 8, 128);
+        pg.b2 = grid_for(e, 4096, 64);
+        const unsigned pick_blocks = pg.b0 + pg.b1 + pg.b2;
+        const unsigned mate_blocks = grid_for(e, BLOCK * 2, 2048);
+        if (r == 1) {
+            {
+                KAPPA_PROF("pick_first", s);
+                hipLaunchKernelGGL((pick_k<R, true>), dim3(pick_blocks), dim3(BLOCK), 0, s, c, l, r,
+                                   pg);
+            }
+            KAPPA_PROF("mate_first", s);
+            hipLaunchKernelGGL(mate_k<true>, dim3(mate_blocks), dim3(BLOCK), 0, s, c, l, r);
+        } else {
+            {
+                KAPPA_PROF("pick", s);
+                hipLaunchKernelGGL((pick_k<R, false>), dim3(pick_blocks), dim3(BLOCK), 0, s, c, l, r,
+                                   pg);
+            }
+            KAPPA_PROF("mate", s);
+            hipLaunchKernelGGL(mate_k<false>, dim3(mate_blocks), dim3(BLOCK), 0, s, c, l, r);
+        }
+    }
+    // rare: still many pending nodes -> cooperative rounds until few remain
+    unsigned cap = coop_capacity<R>();
+    if (cap > 0) {
+        unsigned nb = std::min(cap, grid_for((int64_t)est + 1, COOP_THREADS / SMALL_G, cap));
+        Ctx cc = c;
+        int ll = l, rr = rounds;
+        void *args[] = {&cc, &ll, &rr};
+        KAPPA_PROF("match_coop", s);
+        hipError_t e = hipLaunchCooperativeKernel((const void *)coop_match_k<R>, dim3(nb),
+                                                  dim3(COOP_THREADS), args, 0, s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            if (getenv("KAPPA_DEBUG"))
+                fprintf(stderr, "kappa: cooperative launch (%u blocks) failed: %s\n", nb,
+                        hipGetErrorString(e));
+        }
+    }
+    KAPPA_PROF("match_finish", s);
+    hipLaunchKernelGGL(finish_k<R>, dim3(1), dim3(FINISH_THREADS), 0, s, c, l, rounds);
+}
+
+void launch_level_match(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, int rounds,
+                        hipStream_t s) {
+    if (rounds < 1) rounds = 1;
+    if (c.rating == KAPPA_INNER_OUTER) launch_level_out(c, l, nnz_cap, n_hint, s);
+    switch (c.rating) {
+    case KAPPA_INNER_OUTER: match_impl<KAPPA_INNER_OUTER>(c, l, n_hint, rounds, s); break;
+    case KAPPA_WEIGHT: match_impl<KAPPA_WEIGHT>(c, l, n_hint, rounds, s); break;
+    case KAPPA_EXPANSION: match_impl<KAPPA_EXPANSION>(c, l, n_hint, rounds, s); break;
+    case KAPPA_EXPANSION_STAR: match_impl<KAPPA_EXPANSION_STAR>(c, l, n_hint, rounds, s); break;
+    default: match_impl<KAPPA_EXPANSION_STAR2>(c, l, n_hint, rounds, s); break;
+    }
+}
+
+void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, hipStream_t s) {
+    launch_scan((int64_t)n_hint, RepF{c, l}, RepW{c, l}, c.cs.partials, c.cs.totals + 0, s);
+    {
+        KAPPA_PROF("coarse_nodes", s);
+        hipLaunchKernelGGL(coarse_nodes_k, dim3(grid_for(n_hint, BLOCK * 2, 2048)), dim3(BLOCK), 0,
+                           s, c, l);
+    }
+    launch_scan((int64_t)n_hint + 1, BoundF{c, l}, TmpOffW{c}, c.cs.partials, c.cs.totals + 1, s);
+    {
+        KAPPA_PROF("fill_small", s);
+        hipLaunchKernelGGL(fill_small_k, dim3(grid_for(n_hint, SM_ROWS * 2, 4096)), dim3(BLOCK), 0,
+                           s, c, l);
+    }
+    {
+        KAPPA_PROF("fill_mid", s);
+        hipLaunchKernelGGL(fill_mid_k, dim3(grid_for(n_hint, 64, 512)), dim3(BLOCK), 0, s, c, l);
+    }
+    if (c.cs.hub_acc) {
+        KAPPA_PROF("fill_large", s);
+        hipLaunchKernelGGL(fill_large_k, dim3(HUB_SLOTS), dim3(BLOCK), 0, s, c, l);
+    }
+    launch_scan((int64_t)n_hint + 1, DegF{c, l}, CoarseOffW{c, l}, c.cs.partials, c.cs.totals + 2,
+                s);
+    {
+        KAPPA_PROF("compact_small", s);
+        hipLaunchKernelGGL(compact_small_k, dim3(grid_for(n_hint, SM_ROWS * 2, 4096)), dim3(BLOCK),
+                           0, s, c, l);
+    }
+    KAPPA_PROF("compact_big", s);
+    hipLaunchKernelGGL(compact_big_k, dim3(grid_for(n_hint, 64, 512)), dim3(BLOCK), 0, s, c, l);
+    (void)n_cap;
+}
+
+void launch_level(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, int32_t n_cap,
+                  int rounds, hipStream_t s) {
+    launch_level_begin(c, l, true, s);
+    launch_level_match(c, l, n_hint, nnz_cap, rounds, s);
+    launch_level_contract(c, l, n_hint, n_cap, s);
+}
+
+}  // namespace kappa

@@ -21,9 +21,10 @@ constexpr int SMALL_G = 8;
 
 // Matching rounds: a single workgroup finishes once at most TAIL_MAX nodes
 // still point somewhere.
-constexpr int TAIL_MAX = 2048;
+constexpr int TAIL_MAX = 1024;
 constexpr int FINISH_THREADS = 1024;
-constexpr int MAX_ROUND_STATS = 4096;
+constexpr int STAT_ROUNDS = 64;     // per-round statistics kept per level (last slot aggregates)
+constexpr int MAX_LEVELS = 256;
 
 // Row classes of the contraction (bound = deg(u) + deg(v) - 2 for a pair).
 constexpr int ROW_SMALL_MAX = 64;   // 16 lanes per row, rank sort in LDS
@@ -180,55 +181,115 @@ __device__ T block_sum(T v, T *sh) {
     return t;
 }
 
-// ---------------------------------------------------------------------------
-// Generic exclusive scan over up to n_max items (three kernels: tile sums,
-// one-block scan of the tile sums, rescan with offsets).  F(i) -> int64 value
-// (0 past the live size), W(i, prefix, value) stores.
-// ---------------------------------------------------------------------------
-template <class F>
-__global__ void __launch_bounds__(BLOCK) scan_reduce_k(int64_t n_max, F f, int64_t *partials) {
-    __shared__ int64_t sh[BLOCK / WAVE + 1];
-    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    int64_t s = 0;
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        int64_t idx = base + (int64_t)i * BLOCK + threadIdx.x;
-        if (idx < n_max) s += f(idx);
+// Block-aggregated append into one of up to three lists (bin < 0: none).
+// One global atomic per list per call.  Every thread of the block must call
+// it (block-uniform control flow).  `sh` needs 3 * (blockDim.x / WAVE) + 3
+// int32 of shared memory.  Order inside a list is not deterministic; no
+// consumer depends on it.
+__device__ __forceinline__ void block_append3(int bin, int32_t val, int32_t *const lists[3],
+                                              int32_t *const counters[3], int32_t *sh) {
+    const int nw = blockDim.x / WAVE, w = threadIdx.x / WAVE;
+    uint64_t m[3];
+    for (int b = 0; b < 3; ++b) {
+        m[b] = __ballot(bin == b);
+        if (lane_id() == 0) sh[b * nw + w] = (int32_t)__popcll(m[b]);
     }
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        int b = threadIdx.x, run = 0;
+        for (int i = 0; i < nw; ++i) { int t = sh[b * nw + i]; sh[b * nw + i] = run; run += t; }
+        sh[3 * nw + b] = run ? atomicAdd(counters[b], run) : 0;
+    }
+    __syncthreads();
+    if (bin >= 0) {
+        uint64_t mb = bin == 0 ? m[0] : (bin == 1 ? m[1] : m[2]);
+        int pos = sh[3 * nw + bin] + sh[bin * nw + w] + (int)__popcll(mb & lanemask_lt());
+        lists[bin][pos] = val;
+    }
+    __syncthreads();
 }
 
-__global__ void scan_partials_k(int64_t *partials, int64_t nparts, int64_t *total);
+// ---------------------------------------------------------------------------
+// Generic exclusive scan with a device-side length.  F: size() -> int64
+// (< 0: skip the whole scan), operator()(i) -> int64 value, post(total) run by
+// one thread once the total is known.  W: operator()(i, prefix, value).  Three kernels: tile sums, one-block scan of the tile sums
+// (also writes the total), rescan with offsets.  Grids are hints; all loops
+// stride over the live tile count.
+// ---------------------------------------------------------------------------
+template <class F>
+__global__ void __launch_bounds__(BLOCK) scan_reduce_k(F f, int64_t *partials) {
+    __shared__ int64_t sh[BLOCK / WAVE + 1];
+    const int64_t n = f.size();
+    if (n <= 0) return;
+    const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        int64_t base = t * SCAN_TILE, s = 0;
+        for (int i = 0; i < SCAN_ITEMS; ++i) {
+            int64_t idx = base + (int64_t)i * BLOCK + threadIdx.x;
+            if (idx < n) s += f(idx);
+        }
+        s = block_sum(s, sh);
+        if (threadIdx.x == 0) partials[t] = s;
+    }
+}
+
+template <class F>
+__global__ void __launch_bounds__(1024) scan_partials_k(F f, int64_t *partials, int64_t *total) {
+    __shared__ int64_t sh[1024 / WAVE + 1];
+    const int64_t n = f.size();
+    if (n < 0) return;
+    const int64_t nparts = (n + SCAN_TILE - 1) / SCAN_TILE;
+    int64_t per = (nparts + blockDim.x - 1) / blockDim.x;
+    int64_t b = (int64_t)threadIdx.x * per, e = b + per < nparts ? b + per : nparts;
+    int64_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += partials[i];
+    int64_t tot;
+    int64_t pre = block_excl_scan(s, sh, &tot);
+    for (int64_t i = b; i < e; ++i) {
+        int64_t t = partials[i];
+        partials[i] = pre;
+        pre += t;
+    }
+    if (threadIdx.x == 0) {
+        if (total) *total = tot;
+        f.post(tot);
+    }
+}
 
 template <class F, class W>
-__global__ void __launch_bounds__(BLOCK) scan_apply_k(int64_t n_max, F f, W w,
-                                                       const int64_t *partials) {
+__global__ void __launch_bounds__(BLOCK) scan_apply_k(F f, W w, const int64_t *partials) {
     __shared__ int64_t sh[BLOCK / WAVE + 1];
-    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    // each thread owns SCAN_ITEMS consecutive items
-    int64_t first = base + (int64_t)threadIdx.x * SCAN_ITEMS;
-    int64_t vals[SCAN_ITEMS];
-    int64_t s = 0;
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        int64_t idx = first + i;
-        vals[i] = idx < n_max ? f(idx) : 0;
-        s += vals[i];
-    }
-    int64_t tot;
-    int64_t pre = block_excl_scan(s, sh, &tot) + partials[blockIdx.x];
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        int64_t idx = first + i;
-        if (idx < n_max) w(idx, pre, vals[i]);
-        pre += vals[i];
+    const int64_t n = f.size();
+    if (n <= 0) return;
+    const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        // each thread owns SCAN_ITEMS consecutive items
+        int64_t first = t * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+        int64_t vals[SCAN_ITEMS];
+        int64_t s = 0;
+        for (int i = 0; i < SCAN_ITEMS; ++i) {
+            int64_t idx = first + i;
+            vals[i] = idx < n ? f(idx) : 0;
+            s += vals[i];
+        }
+        int64_t tot;
+        int64_t pre = block_excl_scan(s, sh, &tot) + partials[t];
+        for (int i = 0; i < SCAN_ITEMS; ++i) {
+            int64_t idx = first + i;
+            if (idx < n) w(idx, pre, vals[i]);
+            pre += vals[i];
+        }
     }
 }
 
 inline int64_t scan_tiles(int64_t n_max) { return (n_max + SCAN_TILE - 1) / SCAN_TILE; }
 
-// Scratch for a scan: scan_tiles(n_max) + 1 int64 partials.
-template <class F, class W>
-inline void launch_scan(int64_t n_max, F f, W w, int64_t *partials, int64_t *total,
-                        hipStream_t s);
+inline unsigned grid_for(int64_t items, int per_block, unsigned cap = 65535u * 4) {
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > (int64_t)cap) g = cap;
+    return (unsigned)g;
+}
 
 // ---------------------------------------------------------------------------
 // Profiling (events around launches), implemented in api.hip
@@ -241,32 +302,123 @@ struct ProfScope {
 };
 #define KAPPA_PROF(name, stream) ::kappa::ProfScope _kappa_prof_scope(name, stream)
 
+// n_hint: host-side estimate of the live size (grid sizing only); partials
+// need scan_tiles(n_cap) + 2 entries for the largest size the scan can see.
 template <class F, class W>
-inline void launch_scan(int64_t n_max, F f, W w, int64_t *partials, int64_t *total,
+inline void launch_scan(int64_t n_hint, F f, W w, int64_t *partials, int64_t *total,
                         hipStream_t s) {
-    int64_t tiles = scan_tiles(n_max);
-    if (tiles == 0) tiles = 1;
+    unsigned tiles = grid_for(n_hint, SCAN_TILE, 4096);
     {
         KAPPA_PROF("scan_reduce", s);
-        hipLaunchKernelGGL(scan_reduce_k<F>, dim3((unsigned)tiles), dim3(BLOCK), 0, s, n_max, f,
-                           partials);
+        hipLaunchKernelGGL(scan_reduce_k<F>, dim3(tiles), dim3(BLOCK), 0, s, f, partials);
     }
     {
         KAPPA_PROF("scan_partials", s);
-        hipLaunchKernelGGL(scan_partials_k, dim3(1), dim3(1024), 0, s, partials, tiles, total);
+        hipLaunchKernelGGL(scan_partials_k<F>, dim3(1), dim3(1024), 0, s, f, partials, total);
     }
     {
         KAPPA_PROF("scan_apply", s);
-        hipLaunchKernelGGL((scan_apply_k<F, W>), dim3((unsigned)tiles), dim3(BLOCK), 0, s, n_max,
-                           f, w, partials);
+        hipLaunchKernelGGL((scan_apply_k<F, W>), dim3(tiles), dim3(BLOCK), 0, s, f, w, partials);
     }
 }
 
-inline unsigned grid_for(int64_t items, int per_block, unsigned cap = 65535u * 4) {
-    int64_t g = (items + per_block - 1) / per_block;
-    if (g < 1) g = 1;
-    if (g > (int64_t)cap) g = cap;
-    return (unsigned)g;
+// ---------------------------------------------------------------------------
+// Device-resident multilevel state
+// ---------------------------------------------------------------------------
+enum LevelPhase : int32_t {
+    PH_IDLE = 0,      // built, not started
+    PH_MATCH = 1,     // matching in progress
+    PH_CONTRACT = 2,  // matching done, contraction in progress
+    PH_COMPACT = 3,   // next level allocated, rows being copied
+    PH_STOPPED = -1   // a stop rule fired on this level
+};
+
+struct LevelDesc {
+    int32_t n, maxdeg;
+    int64_t nnz;
+    int64_t *xadj;
+    int32_t *adj;
+    uint32_t *ew;
+    uint32_t *vw;
+    int32_t *cmap;    // to the next level
+    int32_t *mate;
+    int64_t matched;
+    int32_t rounds, stop, phase, pad;
+    int64_t stat[STAT_ROUNDS][2];   // per round: nodes with a free neighbour, their degree sum
+};
+
+enum ControlFlags : uint32_t {
+    CF_ARENA = 1u,      // arena too small
+    CF_HUBS = 2u,       // a coarse row needs the hub accumulators, which are not allocated
+    CF_ROUNDS = 4u,     // round cap hit (cannot happen on valid state)
+    CF_STATE = 8u,      // a list held a node id out of range (cannot happen on valid state)
+};
+
+struct Control {
+    int32_t done;       // no further level starts
+    int32_t nlevels;    // levels built (level nlevels-1 is the coarsest so far)
+    uint32_t flags;
+    int32_t pad;
+    uint64_t cursor, cap;   // arena bytes used / available
+    char *base;
+    int32_t stop_n, max_levels;
+    uint32_t stall_num, stall_den;
+};
+
+// Matching scratch (sized for level 0; reused by every level).
+struct MatchState {
+    int32_t cnt[4][4];      // [round & 3][bin]: sizes of the pending lists written by a round
+    int32_t handoff;        // -1: rounds continue; r >= 0: the finisher resumes after round r; -2: done
+    int32_t rounds;         // last round in which some node pointed at a neighbour
+    int32_t pad[2];
+    int64_t matched;        // |M|
+    int64_t stat[STAT_ROUNDS][2];
+};
+struct MatchScratch {
+    int32_t *best;          // n
+    int32_t *lists;         // 6n: pending lists [parity][bin]
+    uint32_t *out;          // n (innerOuter)
+    int32_t *tile_row;      // tile rows of the level (innerOuter)
+    MatchState *state;
+};
+
+// Contraction scratch (sized for level 0).
+struct ContractScratch {
+    int32_t *rep_of;      // n   coarse -> representative fine node
+    int32_t *partner;     // n   coarse -> partner of the representative (-1)
+    int64_t *tmp_off;     // n+1 padded row offsets
+    int32_t *cdeg;        // n   coarse degrees (bounds before the merge)
+    int32_t *rows;        // 3n  row-class lists
+    int32_t *row_cnt;     // 4   row-class counts
+    int32_t *tmp_adj;     // nnz
+    uint32_t *tmp_ew;     // nnz
+    int64_t *partials;    // scan partials
+    int64_t *totals;      // [0] n', [1] padded total, [2] nnz', [3] max coarse degree
+    uint32_t *hub_acc;    // HUB_SLOTS * n, zero between uses (may be null)
+    uint32_t *hub_bits;   // HUB_SLOTS * hub_words, zero between uses
+    int64_t hub_words;
+};
+
+struct Ctx {
+    Control *ctrl;
+    LevelDesc *lv;
+    int32_t rating;
+    int32_t seed_direct;   // 1: level seeds are `seed` itself; 0: mix64(seed + level)
+    uint64_t seed;
+    MatchScratch ms;
+    ContractScratch cs;
+};
+
+// Device-side bump allocation in the arena (one thread).  nullptr on overflow.
+__device__ __forceinline__ void *arena_alloc(Control *c, uint64_t bytes) {
+    uint64_t start = (c->cursor + 255u) & ~(uint64_t)255u;
+    uint64_t end = start + (bytes ? bytes : 1);
+    if (end > c->cap) {
+        c->flags |= CF_ARENA;
+        return nullptr;
+    }
+    c->cursor = end;
+    return c->base + start;
 }
 
 // ---------------------------------------------------------------------------
@@ -279,10 +431,10 @@ void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 // tile_rows_needed(nnz) int32 entries.  Valid until the graph changes.
 int64_t tile_rows_needed(int64_t nnz);
 void launch_tile_rows(const DevGraph &g, int32_t *tile_row, hipStream_t s);
-// flags: bit0 offsets, bit1 structure, bit2 range; sums[0] = sum w(E), sums[1] = sum c(V).
-// Computes its own tile rows into tile_row.
+// flags: bit0 offsets, bit1 structure, bit2 range; sums[0] = sum w(E), sums[1] = sum c(V),
+// maxdeg: max row length.  Computes its own tile rows into tile_row.
 void launch_validate(const DevGraph &g, int32_t *tile_row, uint32_t *flags, uint64_t *sums,
-                     hipStream_t s);
+                     int32_t *maxdeg, hipStream_t s);
 void launch_out(const DevGraph &g, const int32_t *tile_row, uint32_t *out, hipStream_t s);
 void launch_rate(const DevGraph &g, const int32_t *tile_row, int rating, const uint32_t *out,
                  uint64_t *num, uint64_t *den, hipStream_t s);
@@ -299,59 +451,21 @@ void launch_project(const int32_t *cmap, int32_t n_fine, int32_t n_coarse,
 void launch_cut_balance(const DevGraph &g, const int32_t *tile_row, const int32_t *part,
                         int32_t k, uint32_t eps_num, uint32_t eps_den, uint64_t *block_w,
                         uint64_t *acc, uint32_t *flag, kappa_cut_result *res_dev, hipStream_t s);
+// Level-resident variants of Out(v) (innerOuter): read level l's graph from the
+// descriptor; run only while level l is matching.
+void launch_level_out(const Ctx &c, int l, int64_t nnz_cap, int32_t n_hint, hipStream_t s);
 
-// k_match.hip
-// Device-resident state of the matching rounds of one level.
-struct MatchState {
-    int32_t cnt[4][4];      // [round & 3][bin]: sizes of the pending lists written by a round
-    int32_t handoff;        // -1: rounds continue; r >= 0: the finisher resumes after round r; -2: done
-    int32_t rounds;         // last round in which some node pointed at a neighbour
-    int32_t pad[2];
-    int64_t matched;        // |M|
-    // per round r (index r-1; the last slot aggregates later rounds):
-    // [0] nodes that had a free neighbour, [1] their summed degree
-    int64_t stat[MAX_ROUND_STATS][2];
-};
-struct MatchScratch {
-    int32_t *best;          // n
-    int32_t *lists;         // 6n: pending lists [parity][bin]
-    uint32_t *out;          // n (innerOuter)
-    int32_t *tile_row;      // tile rows of the graph (innerOuter)
-    MatchState *state;
-};
-// Out(v) if needed, mate = best = -1, degree bins for round 1, state reset.
-void launch_match_begin(const DevGraph &g, int rating, int32_t *mate, MatchScratch &ms,
+// k_level.hip: one level of the multilevel loop, driven by device state.
+// n_hint: host estimate of the level's size (grid sizing only).  rounds:
+// multi-block matching rounds before the one-workgroup finisher.
+void launch_level(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, int32_t n_cap,
+                  int rounds, hipStream_t s);
+// Matching only (level phase must be PH_MATCH), e.g. for kappa_match.
+void launch_level_match(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, int rounds,
                         hipStream_t s);
-// Rounds r_first .. r_first + count - 1 (pick + mate kernels each), then the
-// one-workgroup finisher.  maxdeg bounds the degrees of g (selects bins).
-void launch_match_rounds(const DevGraph &g, int rating, uint64_t seed, int32_t maxdeg,
-                         int32_t *mate, MatchScratch &ms, int r_first, int count, hipStream_t s);
-// Max degree of g into *out (device int32, must be zero on entry).
-void launch_max_degree(const DevGraph &g, int32_t *out, hipStream_t s);
-
-// k_contract.hip
-struct ContractScratch {
-    int32_t *rep_of;      // n   coarse -> representative fine node
-    int64_t *tmp_off;     // n+1 padded row offsets
-    int32_t *cdeg;        // n   coarse degrees
-    int32_t *rows;        // 3*n row-class lists
-    int32_t *row_cnt;     // 4   row-class counts
-    int32_t *tmp_adj;     // nnz
-    uint32_t *tmp_ew;     // nnz
-    int64_t *partials;    // scan partials
-    int64_t *totals;      // [0] = n', [1] = padded total, [2] = nnz', [3] = max coarse degree
-    uint32_t *hub_acc;    // HUB_SLOTS * n, all zero between uses (only if hub rows can occur)
-    uint32_t *hub_bits;   // HUB_SLOTS * hub_words, all zero between uses
-    int64_t hub_words;    // n/32 + 1
-};
-// Phase 1: coarse ids, cmap, coarse node weights, padded offsets, merged rows
-// into the padded buffer, coarse degrees and final offsets (cxadj, n'+1).
-// max_bound bounds deg(u) + deg(v) - 2 over the pairs (selects the row classes).
-void launch_contract_build(const DevGraph &g, const int32_t *mate, int64_t max_bound,
-                           int32_t *cmap, uint32_t *cvw, int64_t *cxadj, ContractScratch &cs,
-                           hipStream_t s);
-// Phase 2: copy merged rows into the exact-size coarse arrays.
-void launch_contract_compact(const ContractScratch &cs, int32_t n_fine, int64_t max_bound,
-                             const int64_t *cxadj, int32_t *cadj, uint32_t *cew, hipStream_t s);
+// Contraction only (level phase PH_CONTRACT, mate set), e.g. for kappa_contract.
+void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, hipStream_t s);
+// Level start: stop rules, allocations, state resets (one block).
+void launch_level_begin(const Ctx &c, int l, bool stop_rules, hipStream_t s);
 
 }  // namespace kappa
