@@ -95,6 +95,9 @@ def main():
     ap.add_argument("--k", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-out", default=None)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (3x) so that HBM byte counters "
+                         "can be scaled against a kernel of known traffic")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -213,6 +216,13 @@ def main():
         "kernel_ms_per_step": {name: round(ms / args.steps, 4) for name, (cnt, ms) in kern},
         "path_model_gbs": round(sum(mb.values()) / (ms_step / 1e3) / 1e9, 1),
     }
+    if args.copy_calibration:
+        a = torch.ones(64 << 20, dtype=torch.int32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {a.numel() * 4} bytes read and written")
     if args.profile_out:
         with open(args.profile_out, "w") as f:
             json.dump({"prof": prof, "model_bytes": mb, "levels": {str(r): lv[r] for r in ratings}},

@@ -208,15 +208,15 @@ bool debug_on() {
 kappa_status validate_impl(const DevGraph &g, hipStream_t s, int32_t *maxdeg_out) {
     Arena ar(s);
     uint32_t *small = ar.get<uint32_t>(2);   // [0] flags, [1] max degree
-    uint64_t *sums = ar.get<uint64_t>(2);
+    uint64_t *sums = ar.get<uint64_t>(4);
     int32_t *tr = ar.get<int32_t>(tile_rows_needed(g.nnz));
     if (ar.failed) return KAPPA_E_NOMEM;
     launch_fill_u32(small, 2, 0, s);
-    launch_fill_u64(sums, 2, 0, s);
+    launch_fill_u64(sums, 4, 0, s);
     launch_validate(g, tr, small, sums, (int32_t *)(small + 1), s);
     struct RB {
         uint32_t small[2];
-        uint64_t sums[2];
+        uint64_t sums[4];
     };
     RB *rb = (RB *)pinned(sizeof(RB));
     if (!rb) return KAPPA_E_NOMEM;
@@ -225,7 +225,7 @@ kappa_status validate_impl(const DevGraph &g, hipStream_t s, int32_t *maxdeg_out
     HIPCHK(hipStreamSynchronize(s));
     uint32_t f = rb->small[0];
     if (maxdeg_out) *maxdeg_out = (int32_t)rb->small[1];
-    if (f & 3u) return KAPPA_E_GRAPH;
+    if ((f & 3u) || rb->sums[2] != rb->sums[3]) return KAPPA_E_GRAPH;
     if ((f & 4u) || rb->sums[0] > 0xffffffffull || rb->sums[1] > 0xffffffffull)
         return KAPPA_E_RANGE;
     return KAPPA_OK;
@@ -244,7 +244,6 @@ bool alloc_scratch(Arena &ar, const DevGraph &g, int rating, bool hubs, Ctx &c) 
     ms.state = ar.get<MatchState>(1);
     cs.rep_of = ar.get<int32_t>(g.n);
     cs.partner = ar.get<int32_t>(g.n);
-    cs.tmp_off = ar.get<int64_t>((int64_t)g.n + 1);
     cs.cdeg = ar.get<int32_t>(g.n);
     cs.rows = ar.get<int32_t>(3 * (int64_t)g.n);
     cs.row_cnt = ar.get<int32_t>(4);
@@ -252,6 +251,7 @@ bool alloc_scratch(Arena &ar, const DevGraph &g, int rating, bool hubs, Ctx &c) 
     cs.tmp_ew = ar.get<uint32_t>(g.nnz);
     cs.partials = ar.get<int64_t>(scan_tiles((int64_t)g.n + 1) + 2);
     cs.totals = ar.get<int64_t>(4);
+    if (cs.partials) (void)hipMemsetAsync(cs.partials, 0, sizeof(int64_t), ar.s);   // block counter
     cs.hub_words = (int64_t)g.n / 32 + 1;
     cs.hub_acc = nullptr;
     cs.hub_bits = nullptr;
@@ -374,9 +374,13 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     for (;;) {
         for (int l = launched; l < launched + batch && l <= maxl; ++l) {
             int32_t nh = n_hint_of(n0, l);
-            // unit input weights can make level 0 need many rounds (innerOuter:
-            // ratings follow degree sums); coarser levels settle in a few
-            launch_level(c, l, nh, d0.nnz, n0, l == 0 ? 24 : rounds_for(nh) + 2, s);
+            // innerOuter on unit input weights ranks edges by degree sums,
+            // which chains level 0 over many rounds; otherwise rounds shrink
+            // the pending set about threefold each (the cooperative kernel
+            // and the finisher complete any remainder)
+            int rounds = rounds_for(nh) + 2;
+            if (l == 0 && p->rating == KAPPA_INNER_OUTER) rounds = 24;
+            launch_level(c, l, nh, d0.nnz, n0, rounds, s);
         }
         launched += batch;
         HIPCHK(hipGetLastError());

@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(BLOCK) validate_entries_k(DevGraph g, const in
     if (flags[0] & 1u) return;   // offsets broken: rows cannot be read safely
     const int64_t ntiles = etiles(g.nnz);
     uint32_t bad = 0;
-    uint64_t wsum = 0;
+    uint64_t wsum = 0, above = 0, below = 0;
     for (int64_t tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
         TileCtx t = tile_begin(g, tile_row, tt, s_off);
         int32_t vv[ETILE_ITEMS], uu[ETILE_ITEMS];
@@ -175,8 +175,12 @@ __global__ void __launch_bounds__(BLOCK) validate_entries_k(DevGraph g, const in
             if (u < 0 || u >= g.n || u == v) { bad |= 2; continue; }
             if (j > tile_row_start(g, t, s_off, v) && g.adj[j - 1] >= u) bad |= 2;
             if (w == 0) bad |= 4;
-            if (u > v) wsum += w;
-            uu[i] = u;
+            // Only entries above the diagonal look up their reverse: with no
+            // duplicates in a row, that map is injective into the entries
+            // below the diagonal, so equal counts above and below (checked on
+            // the host) make it a bijection.
+            if (u > v) { wsum += w; uu[i] = u; ++above; }
+            else ++below;
         }
         for (int i = 0; i < ETILE_ITEMS; ++i)
             if (uu[i] >= 0) { lo[i] = g.xadj[uu[i]]; len[i] = g.xadj[uu[i] + 1] - lo[i]; }
@@ -199,7 +203,13 @@ __global__ void __launch_bounds__(BLOCK) validate_entries_k(DevGraph g, const in
         }
     }
     wsum = block_sum(wsum, sh);
-    if (threadIdx.x == 0 && wsum) atomicAdd((unsigned long long *)&sums[0], (unsigned long long)wsum);
+    above = block_sum(above, sh);
+    below = block_sum(below, sh);
+    if (threadIdx.x == 0) {
+        if (wsum) atomicAdd((unsigned long long *)&sums[0], (unsigned long long)wsum);
+        if (above) atomicAdd((unsigned long long *)&sums[2], (unsigned long long)above);
+        if (below) atomicAdd((unsigned long long *)&sums[3], (unsigned long long)below);
+    }
     for (int off = WAVE / 2; off > 0; off >>= 1) bad |= __shfl_xor(bad, off, WAVE);
     if (bad && lane_id() == 0) atomicOr(flags, bad);
 }

@@ -636,7 +636,8 @@ constexpr int SM_ROWS = BLOCK / ROW_SMALL_G;      // 16 small rows per block
 constexpr int SM_CAP = ROW_SMALL_MAX + 2;        // entries incl. the dropped edge
 constexpr int MID_P = 4096;
 
-// --- 1. representatives; the next level's node arrays ------------------------
+// --- 1. coarse ids: scan of representative flags; the apply writes the whole
+//        coarse node (cmap of both ends, rep_of, partner, c(x)) ----------------
 struct RepF {
     Ctx c;
     int l;
@@ -670,71 +671,23 @@ struct RepW {
     Ctx c;
     int l;
     __device__ void operator()(int64_t i, int64_t pre, int64_t v) const {
-        if (v) {
-            c.lv[l].cmap[i] = (int32_t)pre;
-            c.cs.rep_of[pre] = (int32_t)i;
+        if (!v) return;
+        const LevelDesc *L = c.lv + l;
+        const int32_t x = (int32_t)pre, w = L->mate[i];
+        uint32_t cw = L->vw[i];
+        L->cmap[i] = x;
+        if (w >= 0) {
+            L->cmap[w] = x;
+            cw += L->vw[w];
         }
+        c.cs.rep_of[x] = (int32_t)i;
+        c.cs.partner[x] = w;
+        c.lv[l + 1].vw[x] = cw;
     }
 };
 
-// --- 2. coarse nodes ------------------------------------------------------------
-__global__ void __launch_bounds__(BLOCK) coarse_nodes_k(Ctx c, int l) {
-    __shared__ int32_t sha[3 * (BLOCK / WAVE) + 3];
-    DevGraph g;
-    LevelDesc *L = c.lv + l;
-    if (!load_level(L, PH_CONTRACT, g)) return;
-    const LevelDesc *N = c.lv + l + 1;
-    const int64_t nc = N->n;
-    const int32_t *mate = L->mate;
-    int32_t *cmap = L->cmap;
-    uint32_t *cvw = N->vw;
-    int32_t *rows = c.cs.rows;
-    int32_t *lists[3] = {rows, rows + g.n, rows + 2 * (int64_t)g.n};
-    int32_t *cnts[3] = {&c.cs.row_cnt[0], &c.cs.row_cnt[1], &c.cs.row_cnt[2]};
-    bool need_hubs = false;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t lim = (nc + stride - 1) / stride * stride;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < lim; x += stride) {
-        int cls = -1;
-        if (x < nc) {
-            int32_t u = c.cs.rep_of[x];
-            int32_t w = mate[u];
-            uint32_t cw = g.vw[u];
-            int64_t bnd = g.xadj[u + 1] - g.xadj[u];
-            if (w >= 0) {
-                cmap[w] = (int32_t)x;
-                cw += g.vw[w];
-                bnd += g.xadj[w + 1] - g.xadj[w] - 2;
-            }
-            c.cs.partner[x] = w;
-            cvw[x] = cw;
-            c.cs.cdeg[x] = (int32_t)bnd;
-            cls = bnd == 0 ? -1 : (bnd <= ROW_SMALL_MAX ? 0 : (bnd <= ROW_MID_MAX ? 1 : 2));
-            if (cls == 2 && !c.cs.hub_acc) need_hubs = true;
-        }
-        block_append3(cls, (int32_t)x, lists, cnts, sha);
-    }
-    if (__ballot(need_hubs) && lane_id() == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_HUBS);
-}
-
-// --- 3./5. scans over coarse rows ------------------------------------------------
-struct BoundF {
-    Ctx c;
-    int l;
-    __device__ int64_t size() const {
-        return c.lv[l].phase == PH_CONTRACT ? c.lv[l + 1].n + 1 : -1;
-    }
-    __device__ int64_t operator()(int64_t i) const {
-        return i < c.lv[l + 1].n ? c.cs.cdeg[i] : 0;
-    }
-    __device__ void post(int64_t) const {}
-};
-struct TmpOffW {
-    Ctx c;
-    __device__ void operator()(int64_t i, int64_t pre, int64_t) const { c.cs.tmp_off[i] = pre; }
-};
-// Merged degrees -> coarse offsets; then the next level's edge arrays and the
-// stall rule.
+// --- 3. scan of the merged degrees -> coarse row offsets; then the next
+//        level's edge arrays and the stall rule ---------------------------------
 struct DegF {
     Ctx c;
     int l;
@@ -783,7 +736,9 @@ struct CoarseOffW {
 
 // The fine entries of coarse row x: row u, then row w (partner), each
 // without the contracted edge.  t-th entry -> (coarse key, weight);
-// INVALID_KEY for the contracted edge.
+// INVALID_KEY for the contracted edge.  The merged row is staged in the same
+// two fine rows' slots (it has at most deg(u) + deg(w) - 2 entries): merged
+// position p lives at xadj[u] + p while p < deg(u), then at xadj[w] + p - deg(u).
 struct RowSrc {
     int32_t u, w;
     int64_t bu, du, bw;
@@ -804,6 +759,12 @@ __device__ __forceinline__ RowSrc row_src(const DevGraph &g, const Ctx &c, int32
     r.tot = r.du + dw;
     return r;
 }
+__device__ __forceinline__ int64_t row_bound(const RowSrc &r) {
+    return r.w >= 0 ? r.tot - 2 : r.tot;
+}
+__device__ __forceinline__ int64_t staged_at(const RowSrc &r, int64_t p) {
+    return p < r.du ? r.bu + p : r.bw + (p - r.du);
+}
 __device__ __forceinline__ void row_entry(const DevGraph &g, const int32_t *cmap, const RowSrc &r,
                                           int64_t t, uint32_t &key, uint32_t &wt) {
     int32_t nb;
@@ -819,7 +780,19 @@ __device__ __forceinline__ void row_entry(const DevGraph &g, const int32_t *cmap
     }
 }
 
-// --- 4a. small rows: 16 lanes per row, rank sort ------------------------------
+__device__ __forceinline__ int row_class(int64_t bound) {
+    return bound == 0 ? -1 : (bound <= ROW_SMALL_MAX ? 0 : (bound <= ROW_MID_MAX ? 1 : 2));
+}
+
+// Orders the LDS traffic of one wave (all lanes of the wave call it).
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// --- 2a. small rows: 16 lanes per row, rank sort; every coarse row passes
+//         here (empty rows get degree 0, bigger rows go to the class lists) --
 __global__ void __launch_bounds__(BLOCK) fill_small_k(Ctx c, int l) {
     __shared__ uint32_t sk[SM_ROWS][SM_CAP];
     __shared__ uint32_t sw[SM_ROWS][SM_CAP];
@@ -829,34 +802,42 @@ __global__ void __launch_bounds__(BLOCK) fill_small_k(Ctx c, int l) {
     if (!load_level(L, PH_CONTRACT, g)) return;
     const int32_t *cmap = L->cmap;
     const int grp = threadIdx.x / ROW_SMALL_G, sub = threadIdx.x % ROW_SMALL_G;
-    const int64_t count = c.cs.row_cnt[0];
-    const int32_t *rows = c.cs.rows;
+    const int64_t count = c.lv[l + 1].n;
+    int32_t *lists1 = c.cs.rows + g.n, *lists2 = c.cs.rows + 2 * (int64_t)g.n;
     const int64_t gs = (int64_t)gridDim.x * SM_ROWS;
-    const int64_t lim = (count + gs - 1) / gs * gs;
+    const int64_t lim = (count + gs - 1) / gs * gs;   // uniform trip count
     int32_t dmax = 0;
+    bool need_hubs = false;
     for (int64_t i = (int64_t)blockIdx.x * SM_ROWS + grp; i < lim; i += gs) {
-        bool live = i < count;
-        int32_t x = live ? rows[i] : 0;
+        const bool live = i < count;
+        const int32_t x = live ? (int32_t)i : 0;
         RowSrc r;
         r.tot = 0;
-        if (live) r = row_src(g, c, x);
-        for (int64_t t = sub; t < r.tot; t += ROW_SMALL_G) {
+        r.w = -1;
+        int cls = -1;
+        if (live) {
+            r = row_src(g, c, x);
+            cls = row_class(row_bound(r));
+            if (cls == 2 && !c.cs.hub_acc) need_hubs = true;
+        }
+        wave_append(sub == 0 && cls == 1, x, lists1, &c.cs.row_cnt[1]);
+        wave_append(sub == 0 && cls == 2, x, lists2, &c.cs.row_cnt[2]);
+        const int tot = cls == 0 ? (int)r.tot : 0;
+        for (int t = sub; t < tot; t += ROW_SMALL_G) {
             uint32_t k, w;
             row_entry(g, cmap, r, t, k, w);
             sk[grp][t] = k;
             sw[grp][t] = w;
         }
-        __syncthreads();
-        int tot = (int)r.tot;
+        wave_sync_lds();
         for (int t = sub; t < tot; t += ROW_SMALL_G) {
             uint32_t k = sk[grp][t];
             bool lead = k != INVALID_KEY;
             for (int q = 0; q < t && lead; ++q) lead = sk[grp][q] != k;
             sf[grp][t] = lead;
         }
-        __syncthreads();
+        wave_sync_lds();
         int nl = 0;
-        int64_t off = live ? c.cs.tmp_off[x] : 0;
         for (int t = sub; t < tot; t += ROW_SMALL_G) {
             if (!sf[grp][t]) continue;
             uint32_t k = sk[grp][t];
@@ -867,23 +848,25 @@ __global__ void __launch_bounds__(BLOCK) fill_small_k(Ctx c, int l) {
                 rank += (sf[grp][q] && kq < k) ? 1 : 0;
                 sum += kq == k ? sw[grp][q] : 0u;
             }
-            c.cs.tmp_adj[off + rank] = (int32_t)k;
-            c.cs.tmp_ew[off + rank] = sum;
+            int64_t at = staged_at(r, rank);
+            c.cs.tmp_adj[at] = (int32_t)k;
+            c.cs.tmp_ew[at] = sum;
             ++nl;
         }
         for (int o = ROW_SMALL_G / 2; o > 0; o >>= 1) nl += __shfl_xor(nl, o, ROW_SMALL_G);
-        if (live && sub == 0) {
+        if (live && sub == 0 && cls <= 0) {
             c.cs.cdeg[x] = nl;
             dmax = nl > dmax ? nl : dmax;
         }
-        __syncthreads();
+        wave_sync_lds();
     }
     dmax = wave_max(dmax);
     if (lane_id() == 0 && dmax)
         atomicMax((unsigned long long *)&c.cs.totals[3], (unsigned long long)dmax);
+    if (__ballot(need_hubs) && lane_id() == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_HUBS);
 }
 
-// --- 4b. mid rows: one block per row, bitonic sort in LDS -------------------------
+// --- 2b. mid rows: one block per row, bitonic sort in LDS -------------------------
 __global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l) {
     __shared__ uint64_t s[MID_P];
     __shared__ int64_t sh[BLOCK / WAVE + 1];
@@ -934,7 +917,6 @@ __global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l) {
         }
         int64_t total;
         int64_t rank = block_excl_scan(mine, sh, &total);
-        int64_t off = c.cs.tmp_off[x];
         for (int q = 0; q < ipt; ++q) {
             int t = t0 + q;
             if (t >= P) break;
@@ -942,8 +924,9 @@ __global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l) {
             if (k == INVALID_KEY || (t > 0 && (uint32_t)(s[t - 1] >> 32) == k)) continue;
             uint32_t sum = 0;
             for (int e = t; e < P && (uint32_t)(s[e] >> 32) == k; ++e) sum += (uint32_t)s[e];
-            c.cs.tmp_adj[off + rank] = (int32_t)k;
-            c.cs.tmp_ew[off + rank] = sum;
+            int64_t at = staged_at(r, rank);
+            c.cs.tmp_adj[at] = (int32_t)k;
+            c.cs.tmp_ew[at] = sum;
             ++rank;
         }
         if (threadIdx.x == 0) {
@@ -956,7 +939,7 @@ __global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l) {
         atomicMax((unsigned long long *)&c.cs.totals[3], (unsigned long long)dmax);
 }
 
-// --- 4c. large rows: dense accumulator per slot --------------------------------------
+// --- 2c. large rows: dense accumulator per slot --------------------------------------
 __global__ void __launch_bounds__(BLOCK) fill_large_k(Ctx c, int l) {
     __shared__ int64_t s_wcnt[BLOCK / WAVE + 1];
     DevGraph g;
@@ -997,7 +980,6 @@ __global__ void __launch_bounds__(BLOCK) fill_large_k(Ctx c, int l) {
             total += s_wcnt[q];
         }
         // pass 2: ascending walk, read-and-clear bits and accumulators
-        int64_t off = c.cs.tmp_off[x];
         for (int64_t q0 = lo; q0 < hi; q0 += WAVE) {
             int64_t q = q0 + lane_id();
             uint32_t word = q < hi ? atomicExch(&bits[q], 0u) : 0u;
@@ -1008,8 +990,9 @@ __global__ void __launch_bounds__(BLOCK) fill_large_k(Ctx c, int l) {
                 int b = __ffs(word) - 1;
                 word &= word - 1;
                 uint32_t key = (uint32_t)(q * 32 + b);
-                c.cs.tmp_adj[off + pos] = (int32_t)key;
-                c.cs.tmp_ew[off + pos] = atomicExch(&acc[key], 0u);
+                int64_t at = staged_at(r, pos);
+                c.cs.tmp_adj[at] = (int32_t)key;
+                c.cs.tmp_ew[at] = atomicExch(&acc[key], 0u);
                 ++pos;
             }
             base += __shfl(inc, WAVE - 1, WAVE);
@@ -1023,22 +1006,25 @@ __global__ void __launch_bounds__(BLOCK) fill_large_k(Ctx c, int l) {
     }
 }
 
-// --- 6. compaction ----------------------------------------------------------------
+// --- 4. compaction ----------------------------------------------------------------
 __global__ void __launch_bounds__(BLOCK) compact_small_k(Ctx c, int l) {
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_COMPACT, g)) return;
     const LevelDesc *N = c.lv + l + 1;
     const int grp = threadIdx.x / ROW_SMALL_G, sub = threadIdx.x % ROW_SMALL_G;
-    const int64_t count = c.cs.row_cnt[0];
-    for (int64_t i = (int64_t)blockIdx.x * SM_ROWS + grp; i < count;
-         i += (int64_t)gridDim.x * SM_ROWS) {
-        int32_t x = c.cs.rows[i];
-        int64_t src = c.cs.tmp_off[x], dst = N->xadj[x];
+    const int64_t count = N->n;
+    for (int64_t x = (int64_t)blockIdx.x * SM_ROWS + grp; x < count;
+         x += (int64_t)gridDim.x * SM_ROWS) {
         int32_t len = c.cs.cdeg[x];
+        if (len == 0) continue;
+        RowSrc r = row_src(g, c, (int32_t)x);
+        if (row_bound(r) > ROW_SMALL_MAX) continue;   // compact_big copies it
+        int64_t dst = N->xadj[x];
         for (int t = sub; t < len; t += ROW_SMALL_G) {
-            N->adj[dst + t] = c.cs.tmp_adj[src + t];
-            N->ew[dst + t] = c.cs.tmp_ew[src + t];
+            int64_t at = staged_at(r, t);
+            N->adj[dst + t] = c.cs.tmp_adj[at];
+            N->ew[dst + t] = c.cs.tmp_ew[at];
         }
     }
 }
@@ -1051,11 +1037,13 @@ __global__ void __launch_bounds__(BLOCK) compact_big_k(Ctx c, int l) {
     const int64_t c1 = c.cs.row_cnt[1], c2 = c.cs.row_cnt[2];
     for (int64_t i = blockIdx.x; i < c1 + c2; i += gridDim.x) {
         int32_t x = i < c1 ? c.cs.rows[g.n + i] : c.cs.rows[2 * (int64_t)g.n + (i - c1)];
-        int64_t src = c.cs.tmp_off[x], dst = N->xadj[x];
+        RowSrc r = row_src(g, c, x);
+        int64_t dst = N->xadj[x];
         int32_t len = c.cs.cdeg[x];
         for (int t = threadIdx.x; t < len; t += BLOCK) {
-            N->adj[dst + t] = c.cs.tmp_adj[src + t];
-            N->ew[dst + t] = c.cs.tmp_ew[src + t];
+            int64_t at = staged_at(r, t);
+            N->adj[dst + t] = c.cs.tmp_adj[at];
+            N->ew[dst + t] = c.cs.tmp_ew[at];
         }
     }
 }
@@ -1124,8 +1112,9 @@ static void match_impl(const Ctx &c, int l, int32_t n_hint, int rounds, hipStrea
             hipLaunchKernelGGL(mate_k<false>, dim3(mate_blocks), dim3(BLOCK), 0, s, c, l, r);
         }
     }
-    // rare: still many pending nodes -> cooperative rounds until few remain
-    unsigned cap = coop_capacity<R>();
+    // level 0 only (unit input weights can chain long): if many nodes are
+    // still pending, cooperative rounds continue until few remain
+    unsigned cap = l == 0 ? coop_capacity<R>() : 0;
     if (cap > 0) {
         unsigned nb = std::min(cap, grid_for((int64_t)est + 1, COOP_THREADS / SMALL_G, cap));
         Ctx cc = c;
@@ -1160,12 +1149,6 @@ void launch_level_match(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, in
 
 void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, hipStream_t s) {
     launch_scan((int64_t)n_hint, RepF{c, l}, RepW{c, l}, c.cs.partials, c.cs.totals + 0, s);
-    {
-        KAPPA_PROF("coarse_nodes", s);
-        hipLaunchKernelGGL(coarse_nodes_k, dim3(grid_for(n_hint, BLOCK * 2, 2048)), dim3(BLOCK), 0,
-                           s, c, l);
-    }
-    launch_scan((int64_t)n_hint + 1, BoundF{c, l}, TmpOffW{c}, c.cs.partials, c.cs.totals + 1, s);
     {
         KAPPA_PROF("fill_small", s);
         hipLaunchKernelGGL(fill_small_k, dim3(grid_for(n_hint, SM_ROWS * 2, 4096)), dim3(BLOCK), 0,

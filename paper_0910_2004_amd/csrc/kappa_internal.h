@@ -210,17 +210,24 @@ __device__ __forceinline__ void block_append3(int bin, int32_t val, int32_t *con
 }
 
 // ---------------------------------------------------------------------------
-// Generic exclusive scan with a device-side length.  F: size() -> int64
-// (< 0: skip the whole scan), operator()(i) -> int64 value, post(total) run by
-// one thread once the total is known.  W: operator()(i, prefix, value).  Three kernels: tile sums, one-block scan of the tile sums
-// (also writes the total), rescan with offsets.  Grids are hints; all loops
-// stride over the live tile count.
+// Generic exclusive scan with a device-side length, two kernels.
+// F: size() -> int64 (< 0: skip the whole scan), operator()(i) -> int64
+// value, post(total) run by one thread once the total is known (before the
+// apply kernel starts).  W: operator()(i, prefix, value).
+//   reduce: tile sums; the last block to finish scans the tile sums in place,
+//           writes the total and runs post()
+//   apply:  rescan of each tile from its tile prefix
+// Grids are hints; loops stride over the live tile count.  `ws` holds the
+// tile sums (scan_tiles(cap) + 2 int64) and a block counter at ws[0] that
+// must be zero before the first use (the last block resets it).
 // ---------------------------------------------------------------------------
 template <class F>
-__global__ void __launch_bounds__(BLOCK) scan_reduce_k(F f, int64_t *partials) {
+__global__ void __launch_bounds__(BLOCK) scan_reduce_k(F f, int64_t *ws, int64_t *total) {
     __shared__ int64_t sh[BLOCK / WAVE + 1];
+    __shared__ int last;
     const int64_t n = f.size();
-    if (n <= 0) return;
+    if (n < 0) return;
+    int64_t *partials = ws + 1;
     const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         int64_t base = t * SCAN_TILE, s = 0;
@@ -231,36 +238,39 @@ __global__ void __launch_bounds__(BLOCK) scan_reduce_k(F f, int64_t *partials) {
         s = block_sum(s, sh);
         if (threadIdx.x == 0) partials[t] = s;
     }
-}
-
-template <class F>
-__global__ void __launch_bounds__(1024) scan_partials_k(F f, int64_t *partials, int64_t *total) {
-    __shared__ int64_t sh[1024 / WAVE + 1];
-    const int64_t n = f.size();
-    if (n < 0) return;
-    const int64_t nparts = (n + SCAN_TILE - 1) / SCAN_TILE;
-    int64_t per = (nparts + blockDim.x - 1) / blockDim.x;
-    int64_t b = (int64_t)threadIdx.x * per, e = b + per < nparts ? b + per : nparts;
-    int64_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += partials[i];
-    int64_t tot;
-    int64_t pre = block_excl_scan(s, sh, &tot);
-    for (int64_t i = b; i < e; ++i) {
-        int64_t t = partials[i];
-        partials[i] = pre;
-        pre += t;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long done = atomicAdd((unsigned long long *)&ws[0], 1ull);
+        last = done == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // exclusive scan of the tile sums, in chunks of blockDim.x
+    int64_t run = 0;
+    for (int64_t b0 = 0; b0 < tiles; b0 += blockDim.x) {
+        int64_t i = b0 + threadIdx.x;
+        int64_t v = i < tiles ? __hip_atomic_load(&partials[i], __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT) : 0;
+        int64_t tot;
+        int64_t pre = block_excl_scan(v, sh, &tot);
+        if (i < tiles) partials[i] = run + pre;
+        run += tot;
     }
     if (threadIdx.x == 0) {
-        if (total) *total = tot;
-        f.post(tot);
+        ws[0] = 0;
+        if (total) *total = run;
+        f.post(run);
     }
 }
 
 template <class F, class W>
-__global__ void __launch_bounds__(BLOCK) scan_apply_k(F f, W w, const int64_t *partials) {
+__global__ void __launch_bounds__(BLOCK) scan_apply_k(F f, W w, const int64_t *ws) {
     __shared__ int64_t sh[BLOCK / WAVE + 1];
     const int64_t n = f.size();
     if (n <= 0) return;
+    const int64_t *partials = ws + 1;
     const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         // each thread owns SCAN_ITEMS consecutive items
@@ -302,24 +312,17 @@ struct ProfScope {
 };
 #define KAPPA_PROF(name, stream) ::kappa::ProfScope _kappa_prof_scope(name, stream)
 
-// n_hint: host-side estimate of the live size (grid sizing only); partials
-// need scan_tiles(n_cap) + 2 entries for the largest size the scan can see.
+// n_hint: host-side estimate of the live size (grid sizing only); ws: the
+// scan workspace described above.
 template <class F, class W>
-inline void launch_scan(int64_t n_hint, F f, W w, int64_t *partials, int64_t *total,
-                        hipStream_t s) {
-    unsigned tiles = grid_for(n_hint, SCAN_TILE, 4096);
+inline void launch_scan(int64_t n_hint, F f, W w, int64_t *ws, int64_t *total, hipStream_t s) {
+    unsigned tiles = grid_for(n_hint, SCAN_TILE, 2048);
     {
         KAPPA_PROF("scan_reduce", s);
-        hipLaunchKernelGGL(scan_reduce_k<F>, dim3(tiles), dim3(BLOCK), 0, s, f, partials);
+        hipLaunchKernelGGL(scan_reduce_k<F>, dim3(tiles), dim3(BLOCK), 0, s, f, ws, total);
     }
-    {
-        KAPPA_PROF("scan_partials", s);
-        hipLaunchKernelGGL(scan_partials_k<F>, dim3(1), dim3(1024), 0, s, f, partials, total);
-    }
-    {
-        KAPPA_PROF("scan_apply", s);
-        hipLaunchKernelGGL((scan_apply_k<F, W>), dim3(tiles), dim3(BLOCK), 0, s, f, w, partials);
-    }
+    KAPPA_PROF("scan_apply", s);
+    hipLaunchKernelGGL((scan_apply_k<F, W>), dim3(tiles), dim3(BLOCK), 0, s, f, w, ws);
 }
 
 // ---------------------------------------------------------------------------
@@ -386,14 +389,13 @@ struct MatchScratch {
 struct ContractScratch {
     int32_t *rep_of;      // n   coarse -> representative fine node
     int32_t *partner;     // n   coarse -> partner of the representative (-1)
-    int64_t *tmp_off;     // n+1 padded row offsets
-    int32_t *cdeg;        // n   coarse degrees (bounds before the merge)
-    int32_t *rows;        // 3n  row-class lists
+    int32_t *cdeg;        // n   coarse degrees
+    int32_t *rows;        // 3n  row-class lists (classes 1 and 2 are used)
     int32_t *row_cnt;     // 4   row-class counts
     int32_t *tmp_adj;     // nnz
     uint32_t *tmp_ew;     // nnz
-    int64_t *partials;    // scan partials
-    int64_t *totals;      // [0] n', [1] padded total, [2] nnz', [3] max coarse degree
+    int64_t *partials;    // scan workspace: [0] block counter (zero), then tile sums
+    int64_t *totals;      // [0] n', [1] unused, [2] nnz', [3] max coarse degree
     uint32_t *hub_acc;    // HUB_SLOTS * n, zero between uses (may be null)
     uint32_t *hub_bits;   // HUB_SLOTS * hub_words, zero between uses
     int64_t hub_words;
@@ -432,6 +434,7 @@ void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 int64_t tile_rows_needed(int64_t nnz);
 void launch_tile_rows(const DevGraph &g, int32_t *tile_row, hipStream_t s);
 // flags: bit0 offsets, bit1 structure, bit2 range; sums[0] = sum w(E), sums[1] = sum c(V),
+// sums[2] / sums[3] = entries above / below the diagonal (must be equal);
 // maxdeg: max row length.  Computes its own tile rows into tile_row.
 void launch_validate(const DevGraph &g, int32_t *tile_row, uint32_t *flags, uint64_t *sums,
                      int32_t *maxdeg, hipStream_t s);
