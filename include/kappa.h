@@ -234,6 +234,13 @@ void kappa_profile_reset(void);
    Synchronises the device. */
 int32_t kappa_profile_read(const char **names, int64_t *launches, double *ms, int32_t cap);
 
+/* Device memory kept between calls: per stream, one workspace for call-local
+   buffers (grown on demand, reused by the next call on that stream) and up
+   to four arenas of freed hierarchies (reused by kappa_coarsen on that
+   stream).  kappa_cache_release synchronises the device and frees all of it;
+   no call may be running on any stream.  Later calls allocate again. */
+kappa_status kappa_cache_release(void);
+
 const char *kappa_status_str(kappa_status st);
 const char *kappa_version(void);
 

@@ -102,6 +102,7 @@ def lib():
         "kappa_profile_enable": (None, [i32]),
         "kappa_profile_reset": (None, []),
         "kappa_profile_read": (i32, [P, P, P, i32]),
+        "kappa_cache_release": (st, []),
         "kappa_status_str": (ctypes.c_char_p, [st]),
         "kappa_version": (ctypes.c_char_p, []),
     }
@@ -349,6 +350,11 @@ def kappa_uncoarsen(h: Hierarchy, k: int, part_seed: int = 1, eps_num: int = 3, 
     _check("kappa_uncoarsen", lib().kappa_uncoarsen(h.handle, k, ctypes.c_uint64(part_seed), eps_num,
                                                     eps_den, _ptr(part0), res, _stream()))
     return part0[:n0], list(res)
+
+
+def kappa_cache_release():
+    """Frees the device memory the library keeps between calls."""
+    _check("kappa_cache_release", lib().kappa_cache_release())
 
 
 def profile_enable(on: bool = True):

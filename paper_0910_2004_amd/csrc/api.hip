@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -105,7 +106,11 @@ extern "C" int32_t kappa_profile_read(const char **names, int64_t *launches, dou
 }
 
 // ===========================================================================
-// Device memory: stream-ordered pool allocations.
+// Device memory.  Per stream, the library keeps one grow-only workspace for
+// call-local buffers (held under a host lock while a call uses it) and a few
+// released hierarchy arenas for reuse, so that a call on a warm stream
+// allocates nothing.  All are stream-ordered allocations from the device's
+// default pool.
 // ===========================================================================
 namespace {
 
@@ -123,28 +128,126 @@ void pool_init() {
     });
 }
 
-// A list of stream-ordered allocations released together.
-struct Arena {
+constexpr size_t KEEP_ARENAS = 4;
+
+struct StreamCache {
     hipStream_t s = nullptr;
-    std::vector<void *> ptrs;
-    bool failed = false;
-    explicit Arena(hipStream_t st) : s(st) { pool_init(); }
+    std::mutex mu;            // held by the call using `ws`
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    std::mutex amu;           // guards `arenas`
+    std::vector<std::pair<void *, size_t>> arenas;
+};
+
+std::mutex g_cache_mu;
+std::vector<StreamCache *> g_caches;
+
+StreamCache *cache_of(hipStream_t s) {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    for (StreamCache *c : g_caches)
+        if (c->s == s) return c;
+    StreamCache *c = new StreamCache();
+    c->s = s;
+    g_caches.push_back(c);
+    return c;
+}
+
+// 256-byte aligned sub-buffers of one block; with base == nullptr it only
+// measures the layout.
+struct Carve {
+    char *base = nullptr;
+    size_t off = 0;
     template <class T>
     T *get(int64_t count) {
         if (count <= 0) count = 1;
-        void *p = nullptr;
-        if (hipMallocAsync(&p, (size_t)count * sizeof(T), s) != hipSuccess || !p) {
-            failed = true;
-            return nullptr;
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += (size_t)count * sizeof(T);
+        return p;
+    }
+};
+
+// The stream's workspace, locked, at least `bytes` large (base == nullptr if
+// it could not be allocated).  Calls on one stream are stream-ordered, so
+// the next holder may reuse the memory while earlier kernels still run.
+struct Workspace {
+    StreamCache *c;
+    std::unique_lock<std::mutex> lk;
+    char *base = nullptr;
+    Workspace(hipStream_t s, size_t bytes) : c(cache_of(s)), lk(c->mu) {
+        pool_init();
+        if (c->ws_bytes < bytes) {
+            if (c->ws) (void)hipFreeAsync(c->ws, s);
+            c->ws = nullptr;
+            c->ws_bytes = 0;
+            size_t want = bytes + bytes / 4 + 4096;
+            void *p = nullptr;
+            if (hipMallocAsync(&p, want, s) != hipSuccess || !p) return;
+            c->ws = (char *)p;
+            c->ws_bytes = want;
         }
-        ptrs.push_back(p);
-        return (T *)p;
+        base = c->ws;
     }
-    void release() {
-        for (void *p : ptrs) (void)hipFreeAsync(p, s);
-        ptrs.clear();
+};
+
+// Runs `layout(Carve&)` once to measure and once on the locked workspace.
+template <class L>
+bool carve_workspace(hipStream_t s, std::unique_ptr<Workspace> &w, L &&layout) {
+    Carve m;
+    layout(m);
+    w.reset(new (std::nothrow) Workspace(s, m.off));
+    if (!w || !w->base) return false;
+    Carve r;
+    r.base = w->base;
+    layout(r);
+    return true;
+}
+
+void *take_arena(hipStream_t s, size_t bytes, size_t *got) {
+    StreamCache *c = cache_of(s);
+    {
+        std::lock_guard<std::mutex> g(c->amu);
+        int best = -1;
+        for (size_t i = 0; i < c->arenas.size(); ++i)
+            if (c->arenas[i].second >= bytes &&
+                (best < 0 || c->arenas[i].second < c->arenas[best].second))
+                best = (int)i;
+        if (best >= 0) {
+            void *p = c->arenas[best].first;
+            *got = c->arenas[best].second;
+            c->arenas.erase(c->arenas.begin() + best);
+            return p;
+        }
     }
-    ~Arena() { release(); }
+    pool_init();
+    void *p = nullptr;
+    if (hipMallocAsync(&p, bytes, s) != hipSuccess || !p) return nullptr;
+    *got = bytes;
+    return p;
+}
+
+void give_arena(hipStream_t s, void *p, size_t bytes) {
+    if (!p) return;
+    StreamCache *c = cache_of(s);
+    std::lock_guard<std::mutex> g(c->amu);
+    if (c->arenas.size() < KEEP_ARENAS) {
+        c->arenas.emplace_back(p, bytes);
+        return;
+    }
+    (void)hipFreeAsync(p, s);
+}
+
+// Returns an arena to the stream's cache unless released to a hierarchy.
+struct ArenaHold {
+    hipStream_t s;
+    void *p;
+    size_t bytes;
+    ~ArenaHold() { give_arena(s, p, bytes); }
+    void *release() {
+        void *q = p;
+        p = nullptr;
+        return q;
+    }
 };
 
 // Pinned host memory for read-backs, per thread, kept for the process.
@@ -206,64 +309,80 @@ bool debug_on() {
 
 // Validation + max degree, one read-back.
 kappa_status validate_impl(const DevGraph &g, hipStream_t s, int32_t *maxdeg_out) {
-    Arena ar(s);
-    uint32_t *small = ar.get<uint32_t>(2);   // [0] flags, [1] max degree
-    uint64_t *sums = ar.get<uint64_t>(4);
-    int32_t *tr = ar.get<int32_t>(tile_rows_needed(g.nnz));
-    if (ar.failed) return KAPPA_E_NOMEM;
-    launch_fill_u32(small, 2, 0, s);
-    launch_fill_u64(sums, 4, 0, s);
-    launch_validate(g, tr, small, sums, (int32_t *)(small + 1), s);
+    uint32_t *flags = nullptr;
+    int32_t *mdeg = nullptr;
+    uint64_t *sums = nullptr;
+    int32_t *tr = nullptr;
+    std::unique_ptr<Workspace> w;
+    bool ok = carve_workspace(s, w, [&](Carve &cv) {
+        flags = cv.get<uint32_t>(1);
+        mdeg = cv.get<int32_t>(NSHARD);
+        sums = cv.get<uint64_t>(4 * NSHARD);
+        tr = cv.get<int32_t>(tile_rows_needed(g.nnz));
+    });
+    if (!ok) return KAPPA_E_NOMEM;
+    launch_fill_u32(flags, 1, 0, s);
+    launch_fill_u32((uint32_t *)mdeg, NSHARD, 0, s);
+    launch_fill_u64(sums, 4 * NSHARD, 0, s);
+    launch_validate(g, tr, flags, sums, mdeg, s);
     struct RB {
-        uint32_t small[2];
-        uint64_t sums[4];
+        uint32_t flags;
+        int32_t mdeg[NSHARD];
+        uint64_t sums[4 * NSHARD];
     };
     RB *rb = (RB *)pinned(sizeof(RB));
     if (!rb) return KAPPA_E_NOMEM;
-    HIPCHK(hipMemcpyAsync(rb->small, small, sizeof(rb->small), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&rb->flags, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(rb->mdeg, mdeg, sizeof(rb->mdeg), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(rb->sums, sums, sizeof(rb->sums), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    uint32_t f = rb->small[0];
-    if (maxdeg_out) *maxdeg_out = (int32_t)rb->small[1];
-    if ((f & 3u) || rb->sums[2] != rb->sums[3]) return KAPPA_E_GRAPH;
-    if ((f & 4u) || rb->sums[0] > 0xffffffffull || rb->sums[1] > 0xffffffffull)
-        return KAPPA_E_RANGE;
+    uint64_t tot[4] = {0, 0, 0, 0};
+    int32_t md = 0;
+    for (int i = 0; i < NSHARD; ++i) {
+        for (int q = 0; q < 4; ++q) tot[q] += rb->sums[q * NSHARD + i];
+        md = std::max(md, rb->mdeg[i]);
+    }
+    if (maxdeg_out) *maxdeg_out = md;
+    uint32_t f = rb->flags;
+    if ((f & 3u) || tot[2] != tot[3]) return KAPPA_E_GRAPH;
+    if ((f & 4u) || tot[0] > 0xffffffffull || tot[1] > 0xffffffffull) return KAPPA_E_RANGE;
     return KAPPA_OK;
 }
 
 // ---------------------------------------------------------------------------
-// Scratch shared by every level (sized for level 0).
+// Scratch shared by every level (sized for level 0), carved from the
+// workspace.  After the real pass the caller zeroes `arrive` (and the hub
+// arrays) with fill_scratch.
 // ---------------------------------------------------------------------------
-bool alloc_scratch(Arena &ar, const DevGraph &g, int rating, bool hubs, Ctx &c) {
+void carve_scratch(Carve &cv, const DevGraph &g, int rating, bool hubs, Ctx &c) {
     MatchScratch &ms = c.ms;
     ContractScratch &cs = c.cs;
-    ms.best = ar.get<int32_t>(g.n);
-    ms.lists = ar.get<int32_t>(6 * (int64_t)g.n);
-    ms.out = rating == KAPPA_INNER_OUTER ? ar.get<uint32_t>(g.n) : nullptr;
-    ms.tile_row = rating == KAPPA_INNER_OUTER ? ar.get<int32_t>(tile_rows_needed(g.nnz)) : nullptr;
-    ms.state = ar.get<MatchState>(1);
-    cs.rep_of = ar.get<int32_t>(g.n);
-    cs.partner = ar.get<int32_t>(g.n);
-    cs.cdeg = ar.get<int32_t>(g.n);
-    cs.rows = ar.get<int32_t>(3 * (int64_t)g.n);
-    cs.row_cnt = ar.get<int32_t>(4);
-    cs.tmp_adj = ar.get<int32_t>(g.nnz);
-    cs.tmp_ew = ar.get<uint32_t>(g.nnz);
-    cs.partials = ar.get<int64_t>(scan_tiles((int64_t)g.n + 1) + 2);
-    cs.totals = ar.get<int64_t>(4);
-    if (cs.partials) (void)hipMemsetAsync(cs.partials, 0, sizeof(int64_t), ar.s);   // block counter
+    ms.best = cv.get<int32_t>(g.n);
+    ms.lists = cv.get<int32_t>(6 * (int64_t)g.n);
+    ms.out = rating == KAPPA_INNER_OUTER ? cv.get<uint32_t>(g.n) : nullptr;
+    ms.tile_row = rating == KAPPA_INNER_OUTER ? cv.get<int32_t>(tile_rows_needed(g.nnz)) : nullptr;
+    ms.state = cv.get<MatchState>(1);
+    cs.rep_of = cv.get<int32_t>(g.n);
+    cs.partner = cv.get<int32_t>(g.n);
+    cs.cdeg = cv.get<int32_t>(g.n);
+    cs.rows = cv.get<int32_t>(3 * (int64_t)g.n);
+    cs.row_cnt = cv.get<int32_t>(4);
+    cs.tmp_adj = cv.get<int32_t>(g.nnz);
+    cs.tmp_ew = cv.get<uint32_t>(g.nnz);
+    cs.partials = cv.get<int64_t>(scan_tiles((int64_t)g.n + 1) + 1);
+    cs.arrive = cv.get<unsigned>(ARRIVE_WORDS);
+    cs.totals = cv.get<int64_t>(4);
     cs.hub_words = (int64_t)g.n / 32 + 1;
-    cs.hub_acc = nullptr;
-    cs.hub_bits = nullptr;
-    if (hubs) {
-        cs.hub_acc = ar.get<uint32_t>((int64_t)HUB_SLOTS * g.n);
-        cs.hub_bits = ar.get<uint32_t>((int64_t)HUB_SLOTS * cs.hub_words);
-        if (!ar.failed) {
-            launch_fill_u32(cs.hub_acc, (int64_t)HUB_SLOTS * g.n, 0, ar.s);
-            launch_fill_u32(cs.hub_bits, (int64_t)HUB_SLOTS * cs.hub_words, 0, ar.s);
-        }
+    cs.hub_acc = hubs ? cv.get<uint32_t>((int64_t)HUB_SLOTS * g.n) : nullptr;
+    cs.hub_bits = hubs ? cv.get<uint32_t>((int64_t)HUB_SLOTS * cs.hub_words) : nullptr;
+}
+
+void fill_scratch(const DevGraph &g, const Ctx &c, hipStream_t s) {
+    launch_fill_u32(c.cs.arrive, ARRIVE_WORDS, 0, s);
+    if (c.cs.hub_acc) {
+        launch_fill_u32(c.cs.hub_acc, (int64_t)HUB_SLOTS * g.n, 0, s);
+        launch_fill_u32(c.cs.hub_bits, (int64_t)HUB_SLOTS * c.cs.hub_words, 0, s);
     }
-    return !ar.failed;
 }
 
 // Host-side level size estimate (grid sizing only; any value is correct).
@@ -308,9 +427,8 @@ struct kappa_hierarchy {
     hipStream_t s = nullptr;
     std::vector<kappa_level> levels;
     void *arena = nullptr;
-    ~kappa_hierarchy() {
-        if (arena) (void)hipFreeAsync(arena, s);
-    }
+    size_t arena_bytes = 0;
+    ~kappa_hierarchy() { give_arena(s, arena, arena_bytes); }
 };
 
 namespace {
@@ -322,17 +440,24 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
                              hipStream_t s, uint64_t arena_bytes, bool hubs, kappa_hierarchy *H,
                              uint32_t *retry_flags) {
     *retry_flags = 0;
-    Arena ar(s);
     Ctx c;
     c.rating = p->rating;
     c.seed = p->seed;
     c.seed_direct = 0;
     const int maxl = p->max_levels;
-    c.ctrl = ar.get<Control>(1);
-    c.lv = ar.get<LevelDesc>(maxl + 2);
-    if (ar.failed || !alloc_scratch(ar, d0, p->rating, hubs, c)) return KAPPA_E_NOMEM;
-    void *arena = nullptr;
-    if (hipMallocAsync(&arena, arena_bytes, s) != hipSuccess || !arena) return KAPPA_E_NOMEM;
+    std::unique_ptr<Workspace> w;
+    if (!carve_workspace(s, w, [&](Carve &cv) {
+            c.ctrl = cv.get<Control>(1);
+            c.lv = cv.get<LevelDesc>(maxl + 2);
+            carve_scratch(cv, d0, p->rating, hubs, c);
+        }))
+        return KAPPA_E_NOMEM;
+    size_t arena_got = 0;
+    void *arena = take_arena(s, arena_bytes, &arena_got);
+    if (!arena) return KAPPA_E_NOMEM;
+    arena_bytes = arena_got;
+    ArenaHold hold{s, arena, arena_bytes};
+    fill_scratch(d0, c, s);
 
     // control block and level 0
     struct Init {
@@ -393,17 +518,14 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
         fprintf(stderr, "kappa: coarsen control flags 0x%x (levels %d)\n", hc->flags, hc->nlevels);
     if (hc->flags & (CF_ARENA | CF_HUBS)) {
         *retry_flags = hc->flags;
-        (void)hipFreeAsync(arena, s);
         return KAPPA_E_NOMEM;
     }
     if (hc->flags & (CF_ROUNDS | CF_STATE)) {
-        (void)hipFreeAsync(arena, s);
         return KAPPA_E_HIP;
     }
     // read the level descriptors back
     const int nl = hc->nlevels;
     if ((size_t)nl * sizeof(LevelDesc) > PIN_REGION_BYTES) {
-        (void)hipFreeAsync(arena, s);
         return KAPPA_E_NOMEM;
     }
     LevelDesc *hl = (LevelDesc *)pinned((size_t)nl * sizeof(LevelDesc), PIN_LEVELS);
@@ -437,7 +559,8 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
         if (l + 1 < nl) L.stop = KAPPA_STOP_NONE;
         H->levels.push_back(L);
     }
-    H->arena = arena;
+    H->arena = hold.release();
+    H->arena_bytes = arena_bytes;
     return KAPPA_OK;
 }
 
@@ -457,10 +580,14 @@ extern "C" kappa_status kappa_rate(const kappa_graph *g, int32_t rating, uint64_
     if (g->nnz > 0 && (!num || !den)) return KAPPA_E_ARG;
     hipStream_t s = S(stream);
     DevGraph d = dev(g);
-    Arena ar(s);
-    int32_t *tr = ar.get<int32_t>(tile_rows_needed(d.nnz));
-    uint32_t *out = rating == KAPPA_INNER_OUTER ? ar.get<uint32_t>(d.n) : nullptr;
-    if (ar.failed) return KAPPA_E_NOMEM;
+    int32_t *tr = nullptr;
+    uint32_t *out = nullptr;
+    std::unique_ptr<Workspace> w;
+    if (!carve_workspace(s, w, [&](Carve &cv) {
+            tr = cv.get<int32_t>(tile_rows_needed(d.nnz));
+            out = rating == KAPPA_INNER_OUTER ? cv.get<uint32_t>(d.n) : nullptr;
+        }))
+        return KAPPA_E_NOMEM;
     launch_tile_rows(d, tr, s);
     if (out) launch_out(d, tr, out, s);
     launch_rate(d, tr, rating, out, num, den, s);
@@ -513,15 +640,20 @@ extern "C" kappa_status kappa_match(const kappa_graph *g, int32_t rating, uint64
     if (g->n > 0 && !mate) return KAPPA_E_ARG;
     hipStream_t s = S(stream);
     DevGraph d = dev(g);
-    Arena ar(s);
     Ctx c;
     c.rating = rating;
     c.seed = level_seed;   // used as is: h(e) = mix64(level_seed ^ eid)
     c.seed_direct = 1;
-    c.ctrl = ar.get<Control>(1);
-    c.lv = ar.get<LevelDesc>(2);
-    int32_t *cm = ar.get<int32_t>(d.n);
-    if (ar.failed || !alloc_scratch(ar, d, rating, false, c)) return KAPPA_E_NOMEM;
+    int32_t *cm = nullptr;
+    std::unique_ptr<Workspace> w;
+    if (!carve_workspace(s, w, [&](Carve &cv) {
+            c.ctrl = cv.get<Control>(1);
+            c.lv = cv.get<LevelDesc>(2);
+            cm = cv.get<int32_t>(d.n);
+            carve_scratch(cv, d, rating, false, c);
+        }))
+        return KAPPA_E_NOMEM;
+    fill_scratch(d, c, s);
     struct Init {
         Control ctrl;
         LevelDesc l0;
@@ -566,34 +698,33 @@ extern "C" kappa_status kappa_contract(const kappa_graph *g, const int32_t *mate
     if (!coarse->xadj || coarse->cap_n < 0 || coarse->cap_nnz < 0) return KAPPA_E_ARG;
     hipStream_t s = S(stream);
     DevGraph d = dev(g);
-    Arena ar(s);
-    uint32_t *flag = ar.get<uint32_t>(2);   // [0] matching check, [1] max degree
-    Ctx c;
-    c.rating = 0;
-    c.seed = 0;
-    c.seed_direct = 0;
-    c.ctrl = ar.get<Control>(1);
-    c.lv = ar.get<LevelDesc>(2);
-    if (ar.failed) return KAPPA_E_NOMEM;
-    launch_fill_u32(flag, 2, 0, s);
-    launch_check_matching(d, mate, flag, s);
-    {
-        // max degree via the validation's offsets kernel is not needed here:
-        // row classes are chosen on the device; hub accumulators are
-        // allocated when some row could exceed the mid class
-    }
-    uint32_t *hf = (uint32_t *)pinned(sizeof(uint32_t));
-    HIPCHK(hipMemcpyAsync(hf, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (*hf) return KAPPA_E_ARG;
-    uint64_t arena_bytes = (uint64_t)d.n * 12 + (uint64_t)d.nnz * 8 + 4096;
-    bool hubs = false;
+    const uint64_t arena_bytes = (uint64_t)d.n * 12 + (uint64_t)d.nnz * 8 + 4096;
     for (int attempt = 0; attempt < 2; ++attempt) {
-        Arena ar2(s);
-        Ctx cc = c;
-        if (!alloc_scratch(ar2, d, 0, hubs, cc)) return KAPPA_E_NOMEM;
-        void *arena = ar2.get<char>((int64_t)arena_bytes);
-        if (!arena) return KAPPA_E_NOMEM;
+        const bool hubs = attempt > 0;
+        uint32_t *flag = nullptr;
+        char *arena = nullptr;
+        Ctx c;
+        c.rating = 0;
+        c.seed = 0;
+        c.seed_direct = 0;
+        std::unique_ptr<Workspace> w;
+        if (!carve_workspace(s, w, [&](Carve &cv) {
+                flag = cv.get<uint32_t>(1);
+                c.ctrl = cv.get<Control>(1);
+                c.lv = cv.get<LevelDesc>(2);
+                carve_scratch(cv, d, 0, hubs, c);
+                arena = cv.get<char>((int64_t)arena_bytes);
+            }))
+            return KAPPA_E_NOMEM;
+        if (attempt == 0) {
+            launch_fill_u32(flag, 1, 0, s);
+            launch_check_matching(d, mate, flag, s);
+            uint32_t *hf = (uint32_t *)pinned(sizeof(uint32_t));
+            HIPCHK(hipMemcpyAsync(hf, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (*hf) return KAPPA_E_ARG;
+        }
+        fill_scratch(d, c, s);
         struct Init {
             Control ctrl;
             LevelDesc l0;
@@ -604,7 +735,7 @@ extern "C" kappa_status kappa_contract(const kappa_graph *g, const int32_t *mate
         in->ctrl.stop_n = -1;
         in->ctrl.max_levels = MAX_LEVELS;
         in->ctrl.cap = arena_bytes;
-        in->ctrl.base = (char *)arena;
+        in->ctrl.base = arena;
         in->l0.n = d.n;
         in->l0.nnz = d.nnz;
         in->l0.xadj = const_cast<int64_t *>(d.xadj);
@@ -614,24 +745,21 @@ extern "C" kappa_status kappa_contract(const kappa_graph *g, const int32_t *mate
         in->l0.mate = const_cast<int32_t *>(mate);
         in->l0.cmap = cmap;
         in->l0.phase = PH_CONTRACT;
-        HIPCHK(hipMemsetAsync(cc.lv, 0, 2 * sizeof(LevelDesc), s));
-        HIPCHK(hipMemcpyAsync(cc.ctrl, &in->ctrl, sizeof(Control), hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(cc.lv, &in->l0, sizeof(LevelDesc), hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemsetAsync(cc.cs.row_cnt, 0, 4 * sizeof(int32_t), s));
-        HIPCHK(hipMemsetAsync(cc.cs.totals, 0, 4 * sizeof(int64_t), s));
-        launch_level_contract(cc, 0, d.n, d.n, s);
+        HIPCHK(hipMemsetAsync(c.lv, 0, 2 * sizeof(LevelDesc), s));
+        HIPCHK(hipMemcpyAsync(c.ctrl, &in->ctrl, sizeof(Control), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(c.lv, &in->l0, sizeof(LevelDesc), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemsetAsync(c.cs.row_cnt, 0, 4 * sizeof(int32_t), s));
+        HIPCHK(hipMemsetAsync(c.cs.totals, 0, 4 * sizeof(int64_t), s));
+        launch_level_contract(c, 0, d.n, d.n, s);
         struct RB {
             Control ctrl;
             LevelDesc l1;
         };
         RB *rb = (RB *)pinned(sizeof(RB), PIN_LEVELS);
-        HIPCHK(hipMemcpyAsync(&rb->ctrl, cc.ctrl, sizeof(Control), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(&rb->l1, cc.lv + 1, sizeof(LevelDesc), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&rb->ctrl, c.ctrl, sizeof(Control), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&rb->l1, c.lv + 1, sizeof(LevelDesc), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        if (rb->ctrl.flags & CF_HUBS) {
-            hubs = true;
-            continue;
-        }
+        if (rb->ctrl.flags & CF_HUBS) continue;
         if (rb->ctrl.flags & CF_ARENA || rb->ctrl.nlevels != 2) return KAPPA_E_NOMEM;
         int32_t nc = rb->l1.n;
         int64_t nnzc = rb->l1.nnz;
@@ -706,9 +834,10 @@ extern "C" kappa_status kappa_project(const int32_t *cmap, int32_t n_fine, int32
     if (n_fine < 0 || n_coarse < 0) return KAPPA_E_ARG;
     if (n_fine > 0 && (!cmap || !part_fine || (n_coarse > 0 && !part_coarse))) return KAPPA_E_ARG;
     hipStream_t s = S(stream);
-    Arena ar(s);
-    uint32_t *flag = ar.get<uint32_t>(1);
-    if (ar.failed) return KAPPA_E_NOMEM;
+    uint32_t *flag = nullptr;
+    std::unique_ptr<Workspace> w;
+    if (!carve_workspace(s, w, [&](Carve &cv) { flag = cv.get<uint32_t>(1); }))
+        return KAPPA_E_NOMEM;
     launch_fill_u32(flag, 1, 0, s);
     launch_project(cmap, n_fine, n_coarse, part_coarse, part_fine, flag, s);
     uint32_t *hf = (uint32_t *)pinned(sizeof(uint32_t));
@@ -728,13 +857,19 @@ extern "C" kappa_status kappa_cut_balance(const kappa_graph *g, const int32_t *p
     if (g->n > 0 && !part) return KAPPA_E_ARG;
     hipStream_t s = S(stream);
     DevGraph d = dev(g);
-    Arena ar(s);
-    uint64_t *bw = block_w ? block_w : ar.get<uint64_t>(k);
-    uint64_t *acc = ar.get<uint64_t>(3);
-    uint32_t *flag = ar.get<uint32_t>(1);
-    kappa_cut_result *rd = ar.get<kappa_cut_result>(1);
-    int32_t *tr = ar.get<int32_t>(tile_rows_needed(d.nnz));
-    if (ar.failed) return KAPPA_E_NOMEM;
+    uint64_t *bw = nullptr, *acc = nullptr;
+    uint32_t *flag = nullptr;
+    kappa_cut_result *rd = nullptr;
+    int32_t *tr = nullptr;
+    std::unique_ptr<Workspace> w;
+    if (!carve_workspace(s, w, [&](Carve &cv) {
+            bw = block_w ? block_w : cv.get<uint64_t>(k);
+            acc = cv.get<uint64_t>(3 * NSHARD);
+            flag = cv.get<uint32_t>(1);
+            rd = cv.get<kappa_cut_result>(1);
+            tr = cv.get<int32_t>(tile_rows_needed(d.nnz));
+        }))
+        return KAPPA_E_NOMEM;
     launch_fill_u32(flag, 1, 0, s);
     launch_tile_rows(d, tr, s);
     launch_cut_balance(d, tr, part, k, eps_num, eps_den, bw, acc, flag, rd, s);
@@ -758,16 +893,22 @@ extern "C" kappa_status kappa_uncoarsen(const kappa_hierarchy *h, int32_t k, uin
     if (h->levels[0].n > 0 && !part0) return KAPPA_E_ARG;
     hipStream_t s = S(stream);
     const int32_t nl = (int32_t)h->levels.size();
-    Arena ar(s);
     std::vector<int32_t *> part(nl, nullptr);
+    kappa_cut_result *rd = nullptr;
+    uint64_t *bw = nullptr, *acc = nullptr;
+    uint32_t *flag = nullptr;
+    int32_t *tr = nullptr;
+    std::unique_ptr<Workspace> w;
+    if (!carve_workspace(s, w, [&](Carve &cv) {
+            for (int32_t l = 1; l < nl; ++l) part[l] = cv.get<int32_t>(h->levels[l].n);
+            rd = cv.get<kappa_cut_result>(nl);
+            bw = cv.get<uint64_t>(k);
+            acc = cv.get<uint64_t>(3 * NSHARD);
+            flag = cv.get<uint32_t>(1);
+            tr = cv.get<int32_t>(tile_rows_needed(h->levels[0].nnz));
+        }))
+        return KAPPA_E_NOMEM;
     part[0] = part0;
-    for (int32_t l = 1; l < nl; ++l) part[l] = ar.get<int32_t>(h->levels[l].n);
-    kappa_cut_result *rd = ar.get<kappa_cut_result>(nl);
-    uint64_t *bw = ar.get<uint64_t>(k);
-    uint64_t *acc = ar.get<uint64_t>(3);
-    uint32_t *flag = ar.get<uint32_t>(1);
-    int32_t *tr = ar.get<int32_t>(tile_rows_needed(h->levels[0].nnz));
-    if (ar.failed) return KAPPA_E_NOMEM;
     launch_fill_u32(flag, 1, 0, s);
     const int32_t L = nl - 1;
     launch_initial_partition(h->levels[L].n, k, part_seed, part[L], s);
@@ -788,6 +929,20 @@ extern "C" kappa_status kappa_uncoarsen(const kappa_hierarchy *h, int32_t k, uin
     HIPCHK(hipStreamSynchronize(s));
     if (*hf) return KAPPA_E_RANGE;
     if (results) std::memcpy(results, hr, sizeof(kappa_cut_result) * nl);
+    return KAPPA_OK;
+}
+
+extern "C" kappa_status kappa_cache_release(void) {
+    HIPCHK(hipDeviceSynchronize());
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    for (StreamCache *c : g_caches) {
+        std::lock_guard<std::mutex> a(c->mu), b(c->amu);
+        if (c->ws) (void)hipFree(c->ws);
+        c->ws = nullptr;
+        c->ws_bytes = 0;
+        for (auto &pr : c->arenas) (void)hipFree(pr.first);
+        c->arenas.clear();
+    }
     return KAPPA_OK;
 }
 

@@ -137,9 +137,10 @@ __global__ void __launch_bounds__(BLOCK) validate_offsets_k(DevGraph g, uint32_t
     bool wbad = __ballot(bad) != 0;
     __syncthreads();
     if (threadIdx.x == 0) {
+        const int sd = shard_of_block();
         for (int i = 1; i < BLOCK / WAVE; ++i) md = shm[i] > md ? shm[i] : md;
-        if (csum) atomicAdd((unsigned long long *)&sums[1], (unsigned long long)csum);
-        if (md) atomicMax(maxdeg, md);
+        if (csum) atomicAdd((unsigned long long *)&sums[1 * NSHARD + sd], (unsigned long long)csum);
+        if (md) atomicMax(&maxdeg[sd], md);
     }
     if (wbad && lane_id() == 0) atomicOr(flags, 1u);
 }
@@ -206,9 +207,10 @@ __global__ void __launch_bounds__(BLOCK) validate_entries_k(DevGraph g, const in
     above = block_sum(above, sh);
     below = block_sum(below, sh);
     if (threadIdx.x == 0) {
-        if (wsum) atomicAdd((unsigned long long *)&sums[0], (unsigned long long)wsum);
-        if (above) atomicAdd((unsigned long long *)&sums[2], (unsigned long long)above);
-        if (below) atomicAdd((unsigned long long *)&sums[3], (unsigned long long)below);
+        const int sd = shard_of_block();
+        if (wsum) atomicAdd((unsigned long long *)&sums[0 * NSHARD + sd], (unsigned long long)wsum);
+        if (above) atomicAdd((unsigned long long *)&sums[2 * NSHARD + sd], (unsigned long long)above);
+        if (below) atomicAdd((unsigned long long *)&sums[3 * NSHARD + sd], (unsigned long long)below);
     }
     for (int off = WAVE / 2; off > 0; off >>= 1) bad |= __shfl_xor(bad, off, WAVE);
     if (bad && lane_id() == 0) atomicOr(flags, bad);
@@ -433,7 +435,8 @@ void launch_project(const int32_t *cmap, int32_t n_fine, int32_t n_coarse,
 
 // ---------------------------------------------------------------------------
 // Cut and balance (Section 2; imbalance of Section 5.2).
-// acc[0] = cut, acc[1] = c(V), acc[2] = max_v c(v).
+// acc[3][NSHARD], summed over shards: [0] = cut, [1] = c(V), [2] = max_v c(v)
+// (maximum over shards).
 // ---------------------------------------------------------------------------
 constexpr int CUT_NODE_BLOCKS = 256;
 
@@ -466,9 +469,10 @@ __global__ void __launch_bounds__(BLOCK) cut_nodes_k(DevGraph g, const int32_t *
     bool wbad = __ballot(bad) != 0;
     __syncthreads();
     if (threadIdx.x == 0) {
+        const int sd = shard_of_block();
         for (int i = 1; i < BLOCK / WAVE; ++i) mx = shm[i] > mx ? shm[i] : mx;
-        if (tot) atomicAdd((unsigned long long *)&acc[1], (unsigned long long)tot);
-        if (mx) atomicMax((unsigned long long *)&acc[2], (unsigned long long)mx);
+        if (tot) atomicAdd((unsigned long long *)&acc[1 * NSHARD + sd], (unsigned long long)tot);
+        if (mx) atomicMax((unsigned long long *)&acc[2 * NSHARD + sd], (unsigned long long)mx);
     }
     if (wbad && lane_id() == 0) atomicOr(flag, 2u);
 }
@@ -490,7 +494,8 @@ __global__ void __launch_bounds__(BLOCK) cut_entries_k(DevGraph g, const int32_t
         }
     }
     cut = block_sum(cut, sh);
-    if (threadIdx.x == 0 && cut) atomicAdd((unsigned long long *)&acc[0], (unsigned long long)cut);
+    if (threadIdx.x == 0 && cut)
+        atomicAdd((unsigned long long *)&acc[shard_of_block()], (unsigned long long)cut);
 }
 
 typedef unsigned __int128 u128;
@@ -500,19 +505,29 @@ __global__ void __launch_bounds__(BLOCK) cut_finalize_k(const uint64_t *block_w,
                                                         const uint64_t *acc,
                                                         kappa_cut_result *res) {
     __shared__ uint64_t sh[BLOCK / WAVE];
+    __shared__ uint64_t s_acc[3];
+    static_assert(BLOCK / WAVE >= 3 && NSHARD == WAVE, "one wave per sharded accumulator");
     uint64_t mx = 0;
     for (int i = threadIdx.x; i < k; i += blockDim.x) mx = block_w[i] > mx ? block_w[i] : mx;
     mx = wave_max(mx);
     if (lane_id() == 0) sh[threadIdx.x / WAVE] = mx;
+    {
+        const int w = threadIdx.x / WAVE;
+        if (w < 3) {
+            uint64_t v = acc[w * NSHARD + lane_id()];
+            v = w == 2 ? wave_max(v) : wave_sum(v);
+            if (lane_id() == 0) s_acc[w] = v;
+        }
+    }
     __syncthreads();
     if (threadIdx.x != 0) return;
     for (int i = 1; i < BLOCK / WAVE; ++i) mx = sh[i] > mx ? sh[i] : mx;
-    uint64_t total = acc[1], maxc = acc[2];
+    uint64_t total = s_acc[1], maxc = s_acc[2];
     // L_max = (1 + eps) c(V) / k + max c(v) = lnum / lden, lden = k * eps_den
     u128 lnum = (u128)((uint64_t)eps_den + eps_num) * total + (u128)((uint64_t)k * eps_den) * maxc;
     u128 lden = (u128)k * eps_den;
     u128 lhs = lden * mx;
-    res->cut = acc[0];
+    res->cut = s_acc[0];
     res->total = total;
     res->max_block = mx;
     res->max_node = maxc;
@@ -528,7 +543,7 @@ void launch_cut_balance(const DevGraph &g, const int32_t *tr, const int32_t *par
                         uint32_t eps_num, uint32_t eps_den, uint64_t *block_w, uint64_t *acc,
                         uint32_t *flag, kappa_cut_result *res_dev, hipStream_t s) {
     launch_fill_u64(block_w, k, 0, s);
-    launch_fill_u64(acc, 3, 0, s);
+    launch_fill_u64(acc, 3 * NSHARD, 0, s);
     if (g.n > 0) {
         KAPPA_PROF("cut_nodes", s);
         hipLaunchKernelGGL(cut_nodes_k, dim3(grid_for(g.n, BLOCK * 4, CUT_NODE_BLOCKS)), dim3(BLOCK),

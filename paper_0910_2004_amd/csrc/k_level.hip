@@ -113,17 +113,13 @@ __global__ void level_begin_k(Ctx c, int l, int stop_rules) {
     if (t < 16) st->cnt[t >> 2][t & 3] = 0;
     if (t == 0) {
         st->handoff = -1;
-        st->rounds = 0;
-        st->matched = 0;
-        st->pad[0] = 0;   // grid-barrier counter
-        st->pad[1] = 0;   // grid-barrier generation
         L->matched = 0;
         L->rounds = 0;
     }
-    for (int i = t; i < STAT_ROUNDS; i += blockDim.x) {
-        st->stat[i][0] = 0;
-        st->stat[i][1] = 0;
-    }
+    for (int i = t; i < ARRIVE_WORDS + 1; i += blockDim.x) st->barrier[i] = 0;
+    for (int i = t; i < NSHARD; i += blockDim.x) st->sround[i] = 0;
+    int64_t *ss = &st->sstat[0][0][0];
+    for (int i = t; i < STAT_ROUNDS * 3 * NSHARD; i += blockDim.x) ss[i] = 0;
 }
 
 // ===========================================================================
@@ -341,11 +337,11 @@ __device__ __forceinline__ void mate_phase(const Ctx &c, const DevGraph &g, Leve
     degs = block_sum(degs, sh);
     pairs = block_sum(pairs, sh);
     if (threadIdx.x == 0 && point > 0) {
-        int ri = r - 1 < STAT_ROUNDS ? r - 1 : STAT_ROUNDS - 1;
-        atomicAdd((unsigned long long *)&st->stat[ri][0], (unsigned long long)point);
-        atomicAdd((unsigned long long *)&st->stat[ri][1], (unsigned long long)degs);
-        if (pairs) atomicAdd((unsigned long long *)&st->matched, (unsigned long long)pairs);
-        atomicMax(&st->rounds, r);
+        const int ri = r - 1 < STAT_ROUNDS ? r - 1 : STAT_ROUNDS - 1, sd = shard_of_block();
+        atomicAdd((unsigned long long *)&st->sstat[ri][0][sd], (unsigned long long)point);
+        atomicAdd((unsigned long long *)&st->sstat[ri][1][sd], (unsigned long long)degs);
+        if (pairs) atomicAdd((unsigned long long *)&st->sstat[ri][2][sd], (unsigned long long)pairs);
+        atomicMax(&st->sround[sd], r);
     }
 }
 
@@ -413,16 +409,13 @@ __global__ void __launch_bounds__(BLOCK) mate_k(Ctx c, int l, int r) {
 constexpr int COOP_THREADS = 256;
 
 __device__ __forceinline__ bool grid_sync(MatchState *st, Control *ctrl) {
-    __threadfence();
     __syncthreads();
     __shared__ int ok;
     if (threadIdx.x == 0) {
         ok = 1;
-        unsigned *cnt = (unsigned *)&st->pad[0], *gen = (unsigned *)&st->pad[1];
+        unsigned *gen = &st->barrier[ARRIVE_WORDS];
         unsigned g0 = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned arrived = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == gridDim.x - 1) {
-            __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrive_last(st->barrier)) {
             __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             long spins = 0;
@@ -500,7 +493,6 @@ __global__ void __launch_bounds__(FINISH_THREADS) finish_k(Ctx c, int l, int r_l
     }
     __syncthreads();
     const int r0 = s_r0;
-    int64_t pairs_total = 0;
     bool capped = false;
     if (r0 >= 0) {
         if (threadIdx.x < 3) {
@@ -589,34 +581,46 @@ __global__ void __launch_bounds__(FINISH_THREADS) finish_k(Ctx c, int l, int r_l
                 if (pairs) atomicAdd((unsigned long long *)&s_acc[2], (unsigned long long)pairs);
             }
             __syncthreads();
-            if (threadIdx.x == 0) {
-                if (s_acc[0] > 0) {
-                    int ri = r - 1 < STAT_ROUNDS ? r - 1 : STAT_ROUNDS - 1;
-                    st->stat[ri][0] += s_acc[0];
-                    st->stat[ri][1] += s_acc[1];
-                    st->rounds = r;
-                }
-                pairs_total += s_acc[2];
+            if (threadIdx.x == 0 && s_acc[0] > 0) {
+                // this block is alone now: shard 0 takes the round's statistics
+                const int ri = r - 1 < STAT_ROUNDS ? r - 1 : STAT_ROUNDS - 1;
+                st->sstat[ri][0][0] += s_acc[0];
+                st->sstat[ri][1][0] += s_acc[1];
+                st->sstat[ri][2][0] += s_acc[2];
+                st->sround[0] = r > st->sround[0] ? r : st->sround[0];
             }
             __syncthreads();
         }
     }
-    // close the level's matching
+    // close the level's matching: sum the shards (one wave per statistic)
     __syncthreads();
-    for (int i = threadIdx.x; i < STAT_ROUNDS; i += blockDim.x) {
-        L->stat[i][0] = st->stat[i][0];
-        L->stat[i][1] = st->stat[i][1];
+    if (threadIdx.x < 2) s_acc[threadIdx.x] = 0;
+    __syncthreads();
+    {
+        const int w = threadIdx.x / WAVE, nw = FINISH_THREADS / WAVE;
+        for (int q = w; q < STAT_ROUNDS * 3; q += nw) {
+            const int i = q / 3, f = q % 3;
+            int64_t v = wave_sum(st->sstat[i][f][lane_id()]);
+            if (lane_id() == 0) {
+                if (f < 2) L->stat[i][f] = v;
+                else if (v) atomicAdd((unsigned long long *)&s_acc[0], (unsigned long long)v);
+            }
+        }
+        if (w == nw - 1) {
+            int32_t rr = wave_max(st->sround[lane_id()]);
+            if (lane_id() == 0) s_acc[1] = rr;
+        }
     }
     if (threadIdx.x < 4) {
         c.cs.row_cnt[threadIdx.x] = 0;
         c.cs.totals[threadIdx.x] = 0;
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        int64_t m = st->matched + pairs_total;
-        st->matched = m;
+        int64_t m = s_acc[0];
         st->handoff = -2;
         L->matched = m;
-        L->rounds = st->rounds;
+        L->rounds = (int32_t)s_acc[1];
         if (capped) c.ctrl->flags |= CF_ROUNDS;
         if (m == 0 || capped) {
             L->stop = KAPPA_STOP_EMPTY;
@@ -711,7 +715,7 @@ struct DegF {
         N->nnz = nnzc;
         N->adj = (int32_t *)arena_alloc(ctrl, (uint64_t)nnzc * 4);
         N->ew = (uint32_t *)arena_alloc(ctrl, (uint64_t)nnzc * 4);
-        N->maxdeg = (int32_t)c.cs.totals[3];
+        N->maxdeg = 0;   // not tracked below level 0
         if (!N->adj || !N->ew) {
             L->phase = PH_STOPPED;
             ctrl->done = 1;
@@ -806,7 +810,6 @@ __global__ void __launch_bounds__(BLOCK) fill_small_k(Ctx c, int l) {
     int32_t *lists1 = c.cs.rows + g.n, *lists2 = c.cs.rows + 2 * (int64_t)g.n;
     const int64_t gs = (int64_t)gridDim.x * SM_ROWS;
     const int64_t lim = (count + gs - 1) / gs * gs;   // uniform trip count
-    int32_t dmax = 0;
     bool need_hubs = false;
     for (int64_t i = (int64_t)blockIdx.x * SM_ROWS + grp; i < lim; i += gs) {
         const bool live = i < count;
@@ -854,15 +857,9 @@ __global__ void __launch_bounds__(BLOCK) fill_small_k(Ctx c, int l) {
             ++nl;
         }
         for (int o = ROW_SMALL_G / 2; o > 0; o >>= 1) nl += __shfl_xor(nl, o, ROW_SMALL_G);
-        if (live && sub == 0 && cls <= 0) {
-            c.cs.cdeg[x] = nl;
-            dmax = nl > dmax ? nl : dmax;
-        }
+        if (live && sub == 0 && cls <= 0) c.cs.cdeg[x] = nl;
         wave_sync_lds();
     }
-    dmax = wave_max(dmax);
-    if (lane_id() == 0 && dmax)
-        atomicMax((unsigned long long *)&c.cs.totals[3], (unsigned long long)dmax);
     if (__ballot(need_hubs) && lane_id() == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_HUBS);
 }
 
@@ -875,7 +872,6 @@ __global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l) {
     if (!load_level(L, PH_CONTRACT, g)) return;
     const int32_t *cmap = L->cmap;
     const int64_t count = c.cs.row_cnt[1];
-    int32_t dmax = 0;
     for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
         int32_t x = c.cs.rows[g.n + i];
         RowSrc r = row_src(g, c, x);
@@ -929,14 +925,9 @@ __global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l) {
             c.cs.tmp_ew[at] = sum;
             ++rank;
         }
-        if (threadIdx.x == 0) {
-            c.cs.cdeg[x] = (int32_t)total;
-            dmax = (int32_t)total > dmax ? (int32_t)total : dmax;
-        }
+        if (threadIdx.x == 0) c.cs.cdeg[x] = (int32_t)total;
         __syncthreads();
     }
-    if (threadIdx.x == 0 && dmax)
-        atomicMax((unsigned long long *)&c.cs.totals[3], (unsigned long long)dmax);
 }
 
 // --- 2c. large rows: dense accumulator per slot --------------------------------------
@@ -997,10 +988,7 @@ __global__ void __launch_bounds__(BLOCK) fill_large_k(Ctx c, int l) {
             }
             base += __shfl(inc, WAVE - 1, WAVE);
         }
-        if (threadIdx.x == 0) {
-            c.cs.cdeg[x] = (int32_t)total;
-            atomicMax((unsigned long long *)&c.cs.totals[3], (unsigned long long)total);
-        }
+        if (threadIdx.x == 0) c.cs.cdeg[x] = (int32_t)total;
         __threadfence();
         __syncthreads();
     }
@@ -1053,7 +1041,7 @@ __global__ void __launch_bounds__(BLOCK) compact_big_k(Ctx c, int l) {
 // ===========================================================================
 void launch_level_begin(const Ctx &c, int l, bool stop_rules, hipStream_t s) {
     KAPPA_PROF("level_begin", s);
-    hipLaunchKernelGGL(level_begin_k, dim3(1), dim3(WAVE), 0, s, c, l, stop_rules ? 1 : 0);
+    hipLaunchKernelGGL(level_begin_k, dim3(1), dim3(BLOCK), 0, s, c, l, stop_rules ? 1 : 0);
 }
 
 // Co-resident block count for the cooperative kernel (0 if unavailable).
@@ -1148,7 +1136,8 @@ void launch_level_match(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, in
 }
 
 void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, hipStream_t s) {
-    launch_scan((int64_t)n_hint, RepF{c, l}, RepW{c, l}, c.cs.partials, c.cs.totals + 0, s);
+    launch_scan((int64_t)n_hint, RepF{c, l}, RepW{c, l}, c.cs.partials, c.cs.arrive,
+                c.cs.totals + 0, s);
     {
         KAPPA_PROF("fill_small", s);
         hipLaunchKernelGGL(fill_small_k, dim3(grid_for(n_hint, SM_ROWS * 2, 4096)), dim3(BLOCK), 0,
@@ -1162,8 +1151,8 @@ void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, h
         KAPPA_PROF("fill_large", s);
         hipLaunchKernelGGL(fill_large_k, dim3(HUB_SLOTS), dim3(BLOCK), 0, s, c, l);
     }
-    launch_scan((int64_t)n_hint + 1, DegF{c, l}, CoarseOffW{c, l}, c.cs.partials, c.cs.totals + 2,
-                s);
+    launch_scan((int64_t)n_hint + 1, DegF{c, l}, CoarseOffW{c, l}, c.cs.partials, c.cs.arrive,
+                c.cs.totals + 2, s);
     {
         KAPPA_PROF("compact_small", s);
         hipLaunchKernelGGL(compact_small_k, dim3(grid_for(n_hint, SM_ROWS * 2, 4096)), dim3(BLOCK),

@@ -32,6 +32,15 @@ constexpr int ROW_SMALL_G = 16;
 constexpr int ROW_MID_MAX = 4094;   // one block per row, bitonic sort of <= 4096 in LDS
 constexpr int HUB_SLOTS = 32;       // rows above ROW_MID_MAX: dense accumulators
 
+// Device-scope atomics on one address from many blocks serialise where the
+// XCDs meet (about 10 ns each), so kernel-wide accumulators are split over
+// NSHARD slots picked by block index and summed by their consumer, and
+// "last block" detection counts arrivals in groups of ARRIVE_GROUP blocks.
+constexpr int NSHARD = 64;
+constexpr int ARRIVE_GROUP = 32;
+constexpr int ARRIVE_MAX_BLOCKS = 4096;   // grids that use arrival counters stay below
+constexpr int ARRIVE_WORDS = 1 + ARRIVE_MAX_BLOCKS / ARRIVE_GROUP;
+
 struct DevGraph {
     int32_t n;
     int64_t nnz;
@@ -174,6 +183,28 @@ __device__ __forceinline__ void wave_append(bool pred, int32_t val, int32_t *lis
     if (pred) list[base + __popcll(mask & lanemask_lt())] = val;
 }
 
+__device__ __forceinline__ int shard_of_block() { return (int)(blockIdx.x & (NSHARD - 1)); }
+
+// Called by thread 0 of every block of a grid (<= ARRIVE_MAX_BLOCKS blocks)
+// after its global writes; returns true in exactly one block, the last to
+// arrive, which then sees every other block's writes.  `cnt` holds
+// ARRIVE_WORDS zeroed words and is zero again when the grid ends.
+__device__ __forceinline__ bool arrive_last(unsigned *cnt) {
+    const unsigned nb = gridDim.x, g = blockIdx.x / ARRIVE_GROUP;
+    const unsigned ng = (nb + ARRIVE_GROUP - 1) / ARRIVE_GROUP;
+    const unsigned gsize = g + 1 < ng ? ARRIVE_GROUP : nb - g * ARRIVE_GROUP;
+    // release: this block's writes (ordered before by a block barrier) are
+    // published; acquire: the last arrival sees everyone's
+    unsigned old = __hip_atomic_fetch_add(&cnt[1 + g], 1u, __ATOMIC_ACQ_REL,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+    if (old != gsize - 1) return false;
+    __hip_atomic_store(&cnt[1 + g], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    old = __hip_atomic_fetch_add(&cnt[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (old != ng - 1) return false;
+    __hip_atomic_store(&cnt[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
 template <class T>
 __device__ T block_sum(T v, T *sh) {
     T t;
@@ -217,17 +248,18 @@ __device__ __forceinline__ void block_append3(int bin, int32_t val, int32_t *con
 //   reduce: tile sums; the last block to finish scans the tile sums in place,
 //           writes the total and runs post()
 //   apply:  rescan of each tile from its tile prefix
-// Grids are hints; loops stride over the live tile count.  `ws` holds the
-// tile sums (scan_tiles(cap) + 2 int64) and a block counter at ws[0] that
-// must be zero before the first use (the last block resets it).
+// Grids are hints (at most ARRIVE_MAX_BLOCKS); loops stride over the live
+// tile count.  `ws` holds the tile sums (scan_tiles(cap) + 1 int64); `arr`
+// the arrival counters (ARRIVE_WORDS, zero between uses).
 // ---------------------------------------------------------------------------
 template <class F>
-__global__ void __launch_bounds__(BLOCK) scan_reduce_k(F f, int64_t *ws, int64_t *total) {
+__global__ void __launch_bounds__(BLOCK) scan_reduce_k(F f, int64_t *ws, unsigned *arr,
+                                                       int64_t *total) {
     __shared__ int64_t sh[BLOCK / WAVE + 1];
     __shared__ int last;
     const int64_t n = f.size();
     if (n < 0) return;
-    int64_t *partials = ws + 1;
+    int64_t *partials = ws;
     const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         int64_t base = t * SCAN_TILE, s = 0;
@@ -238,15 +270,10 @@ __global__ void __launch_bounds__(BLOCK) scan_reduce_k(F f, int64_t *ws, int64_t
         s = block_sum(s, sh);
         if (threadIdx.x == 0) partials[t] = s;
     }
-    __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long done = atomicAdd((unsigned long long *)&ws[0], 1ull);
-        last = done == gridDim.x - 1;
-    }
+    if (threadIdx.x == 0) last = arrive_last(arr);
     __syncthreads();
     if (!last) return;
-    __threadfence();
     // exclusive scan of the tile sums, in chunks of blockDim.x
     int64_t run = 0;
     for (int64_t b0 = 0; b0 < tiles; b0 += blockDim.x) {
@@ -259,7 +286,6 @@ __global__ void __launch_bounds__(BLOCK) scan_reduce_k(F f, int64_t *ws, int64_t
         run += tot;
     }
     if (threadIdx.x == 0) {
-        ws[0] = 0;
         if (total) *total = run;
         f.post(run);
     }
@@ -270,7 +296,7 @@ __global__ void __launch_bounds__(BLOCK) scan_apply_k(F f, W w, const int64_t *w
     __shared__ int64_t sh[BLOCK / WAVE + 1];
     const int64_t n = f.size();
     if (n <= 0) return;
-    const int64_t *partials = ws + 1;
+    const int64_t *partials = ws;
     const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         // each thread owns SCAN_ITEMS consecutive items
@@ -315,11 +341,12 @@ struct ProfScope {
 // n_hint: host-side estimate of the live size (grid sizing only); ws: the
 // scan workspace described above.
 template <class F, class W>
-inline void launch_scan(int64_t n_hint, F f, W w, int64_t *ws, int64_t *total, hipStream_t s) {
+inline void launch_scan(int64_t n_hint, F f, W w, int64_t *ws, unsigned *arr, int64_t *total,
+                        hipStream_t s) {
     unsigned tiles = grid_for(n_hint, SCAN_TILE, 2048);
     {
         KAPPA_PROF("scan_reduce", s);
-        hipLaunchKernelGGL(scan_reduce_k<F>, dim3(tiles), dim3(BLOCK), 0, s, f, ws, total);
+        hipLaunchKernelGGL(scan_reduce_k<F>, dim3(tiles), dim3(BLOCK), 0, s, f, ws, arr, total);
     }
     KAPPA_PROF("scan_apply", s);
     hipLaunchKernelGGL((scan_apply_k<F, W>), dim3(tiles), dim3(BLOCK), 0, s, f, w, ws);
@@ -372,10 +399,10 @@ struct Control {
 struct MatchState {
     int32_t cnt[4][4];      // [round & 3][bin]: sizes of the pending lists written by a round
     int32_t handoff;        // -1: rounds continue; r >= 0: the finisher resumes after round r; -2: done
-    int32_t rounds;         // last round in which some node pointed at a neighbour
-    int32_t pad[2];
-    int64_t matched;        // |M|
-    int64_t stat[STAT_ROUNDS][2];
+    int32_t pad[3];
+    unsigned barrier[ARRIVE_WORDS + 1];   // grid barrier of the cooperative kernel: counters, generation
+    int32_t sround[NSHARD];               // per shard: last round in which some node pointed
+    int64_t sstat[STAT_ROUNDS][3][NSHARD];  // per round and shard: pointing nodes, their degree sum, pairs
 };
 struct MatchScratch {
     int32_t *best;          // n
@@ -394,8 +421,9 @@ struct ContractScratch {
     int32_t *row_cnt;     // 4   row-class counts
     int32_t *tmp_adj;     // nnz
     uint32_t *tmp_ew;     // nnz
-    int64_t *partials;    // scan workspace: [0] block counter (zero), then tile sums
-    int64_t *totals;      // [0] n', [1] unused, [2] nnz', [3] max coarse degree
+    int64_t *partials;    // scan workspace: tile sums
+    unsigned *arrive;     // ARRIVE_WORDS arrival counters of the scans (zero between uses)
+    int64_t *totals;      // [0] n', [1] unused, [2] nnz', [3] unused
     uint32_t *hub_acc;    // HUB_SLOTS * n, zero between uses (may be null)
     uint32_t *hub_bits;   // HUB_SLOTS * hub_words, zero between uses
     int64_t hub_words;
@@ -433,9 +461,11 @@ void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 // tile_rows_needed(nnz) int32 entries.  Valid until the graph changes.
 int64_t tile_rows_needed(int64_t nnz);
 void launch_tile_rows(const DevGraph &g, int32_t *tile_row, hipStream_t s);
-// flags: bit0 offsets, bit1 structure, bit2 range; sums[0] = sum w(E), sums[1] = sum c(V),
-// sums[2] / sums[3] = entries above / below the diagonal (must be equal);
-// maxdeg: max row length.  Computes its own tile rows into tile_row.
+// flags: bit0 offsets, bit1 structure, bit2 range.  sums[4][NSHARD] (zeroed
+// by the caller), summed over shards: [0] = sum w(E), [1] = sum c(V),
+// [2] / [3] = entries above / below the diagonal (must be equal);
+// maxdeg[NSHARD] (zeroed): max row length per shard.  Computes its own tile
+// rows into tile_row.
 void launch_validate(const DevGraph &g, int32_t *tile_row, uint32_t *flags, uint64_t *sums,
                      int32_t *maxdeg, hipStream_t s);
 void launch_out(const DevGraph &g, const int32_t *tile_row, uint32_t *out, hipStream_t s);
@@ -450,7 +480,8 @@ void launch_initial_partition(int32_t n, int32_t k, uint64_t seed, int32_t *part
 void launch_project(const int32_t *cmap, int32_t n_fine, int32_t n_coarse,
                     const int32_t *part_coarse, int32_t *part_fine, uint32_t *flag,
                     hipStream_t s);
-// acc: [0]=cut [1]=total [2]=max_node; block_w[k] zeroed inside
+// acc: [3][NSHARD] (cut, c(V), max c(v) per shard); acc and block_w[k] are
+// zeroed inside
 void launch_cut_balance(const DevGraph &g, const int32_t *tile_row, const int32_t *part,
                         int32_t k, uint32_t eps_num, uint32_t eps_den, uint64_t *block_w,
                         uint64_t *acc, uint32_t *flag, kappa_cut_result *res_dev, hipStream_t s);
