@@ -241,6 +241,14 @@ int32_t kappa_profile_read(const char **names, int64_t *launches, double *ms, in
    no call may be running on any stream.  Later calls allocate again. */
 kappa_status kappa_cache_release(void);
 
+/* on = 1: launch sequences that repeat with the same sizes and buffers (a
+   batch of levels of kappa_coarsen, the whole of kappa_uncoarsen) are
+   captured as HIP graphs on their second occurrence and replayed from then
+   on, on a side stream of the caller's stream ordered by events both ways.
+   on = 0 (the default, measured faster on gfx950) launches every kernel
+   directly.  Results do not depend on it. */
+void kappa_graphs_enable(int32_t on);
+
 const char *kappa_status_str(kappa_status st);
 const char *kappa_version(void);
 

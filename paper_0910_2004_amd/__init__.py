@@ -12,5 +12,5 @@ from ._lib import (  # noqa: F401
     declared_functions, lib, status_str,
     kappa_validate, kappa_rate, kappa_match, kappa_contract, kappa_coarsen,
     kappa_initial_partition, kappa_project, kappa_cut_balance, kappa_uncoarsen, kappa_cache_release,
-    profile_enable, profile_reset, profile_read,
+    graphs_enable, profile_enable, profile_reset, profile_read,
 )

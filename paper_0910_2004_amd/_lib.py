@@ -103,6 +103,7 @@ def lib():
         "kappa_profile_reset": (None, []),
         "kappa_profile_read": (i32, [P, P, P, i32]),
         "kappa_cache_release": (st, []),
+        "kappa_graphs_enable": (None, [i32]),
         "kappa_status_str": (ctypes.c_char_p, [st]),
         "kappa_version": (ctypes.c_char_p, []),
     }
@@ -355,6 +356,11 @@ def kappa_uncoarsen(h: Hierarchy, k: int, part_seed: int = 1, eps_num: int = 3, 
 def kappa_cache_release():
     """Frees the device memory the library keeps between calls."""
     _check("kappa_cache_release", lib().kappa_cache_release())
+
+
+def graphs_enable(on: bool = True):
+    """Replay repeated launch sequences as HIP graphs (default) or launch directly."""
+    lib().kappa_graphs_enable(1 if on else 0)
 
 
 def profile_enable(on: bool = True):

@@ -130,13 +130,25 @@ void pool_init() {
 
 constexpr size_t KEEP_ARENAS = 4;
 
+struct GraphEntry {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec;      // nullptr: capture failed, run directly
+    uint64_t last_use;
+};
+
 struct StreamCache {
     hipStream_t s = nullptr;
-    std::mutex mu;            // held by the call using `ws`
+    std::mutex mu;            // held by the call using `ws` (and the graph cache)
     char *ws = nullptr;
     size_t ws_bytes = 0;
     std::mutex amu;           // guards `arenas`
     std::vector<std::pair<void *, size_t>> arenas;
+    // launch sequences replayed as graphs (see run_seq)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<GraphEntry> graphs;
+    std::vector<std::vector<uint64_t>> seen;
+    uint64_t clock = 0;
 };
 
 std::mutex g_cache_mu;
@@ -236,6 +248,87 @@ void give_arena(hipStream_t s, void *p, size_t bytes) {
     }
     (void)hipFreeAsync(p, s);
 }
+
+// ---------------------------------------------------------------------------
+// Launch sequences (a batch of levels, the way back up) as HIP graphs.  A
+// sequence is keyed by everything its kernel arguments and grids depend on
+// (the workspace address included).  The first call with a key launches
+// directly; the second captures the sequence on the stream's side stream and
+// instantiates it; later calls replay it.  Replays run on the side stream,
+// ordered against the caller's stream by an event each way.  The sequences
+// hold kernel launches only.
+// ---------------------------------------------------------------------------
+bool debug_on();
+bool g_graphs_on = false;   // measured slower than direct launches on gfx950 (ROCm 7)
+constexpr size_t KEEP_GRAPHS = 24, KEEP_SEEN = 48;
+
+template <class E>
+hipError_t run_seq(StreamCache *c, hipStream_t s, const std::vector<uint64_t> &key, E &&enqueue) {
+    if (!g_graphs_on || g_prof.on) {
+        enqueue(s);
+        return hipGetLastError();
+    }
+    ++c->clock;
+    GraphEntry *hit = nullptr;
+    for (GraphEntry &e : c->graphs)
+        if (e.key == key) hit = &e;
+    if (!hit) {
+        bool again = false;
+        for (auto &k : c->seen) again = again || k == key;
+        if (!again) {
+            if (c->seen.size() >= KEEP_SEEN) c->seen.erase(c->seen.begin());
+            c->seen.push_back(key);
+            enqueue(s);
+            return hipGetLastError();
+        }
+        if (!c->side) {
+            if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) {
+                enqueue(s);
+                return hipGetLastError();
+            }
+        }
+        if (c->graphs.size() >= KEEP_GRAPHS) {
+            size_t old = 0;
+            for (size_t i = 1; i < c->graphs.size(); ++i)
+                if (c->graphs[i].last_use < c->graphs[old].last_use) old = i;
+            (void)hipStreamSynchronize(c->side);
+            if (c->graphs[old].exec) (void)hipGraphExecDestroy(c->graphs[old].exec);
+            c->graphs.erase(c->graphs.begin() + old);
+        }
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ex = nullptr;
+        bool ok = hipStreamBeginCapture(c->side, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            enqueue(c->side);
+            ok = hipStreamEndCapture(c->side, &g) == hipSuccess && g;
+            ok = ok && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess && ex;
+            if (g) (void)hipGraphDestroy(g);
+        }
+        (void)hipGetLastError();
+        if (!ok && ex) {
+            (void)hipGraphExecDestroy(ex);
+            ex = nullptr;
+        }
+        c->graphs.push_back(GraphEntry{key, ex, c->clock});
+        hit = &c->graphs.back();
+        if (debug_on() && !ex) fprintf(stderr, "kappa: graph capture failed; launching directly\n");
+    }
+    hit->last_use = c->clock;
+    if (!hit->exec) {
+        enqueue(s);
+        return hipGetLastError();
+    }
+    hipError_t e = hipEventRecord(c->ev_in, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->ev_in, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(hit->exec, c->side);
+    if (e == hipSuccess) e = hipEventRecord(c->ev_out, c->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->ev_out, 0);
+    return e;
+}
+
+inline uint64_t pkey(const void *p) { return (uint64_t)(uintptr_t)p; }
 
 // Returns an arena to the stream's cache unless released to a hierarchy.
 struct ArenaHold {
@@ -379,6 +472,7 @@ void carve_scratch(Carve &cv, const DevGraph &g, int rating, bool hubs, Ctx &c) 
 
 void fill_scratch(const DevGraph &g, const Ctx &c, hipStream_t s) {
     launch_fill_u32(c.cs.arrive, ARRIVE_WORDS, 0, s);
+    launch_fill_u32((uint32_t *)&c.ms.state->cnt[0][0], 16, 0, s);   // round-1 list counters
     if (c.cs.hub_acc) {
         launch_fill_u32(c.cs.hub_acc, (int64_t)HUB_SLOTS * g.n, 0, s);
         launch_fill_u32(c.cs.hub_bits, (int64_t)HUB_SLOTS * c.cs.hub_words, 0, s);
@@ -469,7 +563,9 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     in->ctrl.done = 0;
     in->ctrl.nlevels = 1;
     in->ctrl.flags = 0;
-    in->ctrl.cursor = 0;
+    // level 0's mate and cmap open the arena
+    const uint64_t n_al = ((uint64_t)d0.n * 4 + 255) & ~(uint64_t)255;
+    in->ctrl.cursor = 2 * n_al;
     in->ctrl.cap = arena_bytes;
     in->ctrl.base = (char *)arena;
     in->ctrl.stop_n = p->stop_n;
@@ -483,6 +579,8 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     in->l0.adj = const_cast<int32_t *>(d0.adj);
     in->l0.ew = const_cast<uint32_t *>(d0.ew);
     in->l0.vw = const_cast<uint32_t *>(d0.vw);
+    in->l0.mate = (int32_t *)arena;
+    in->l0.cmap = (int32_t *)((char *)arena + n_al);
     in->l0.phase = PH_IDLE;
     // every descriptor starts idle (zero): kernels of levels not built yet are no-ops
     HIPCHK(hipMemsetAsync(c.lv, 0, (size_t)(maxl + 2) * sizeof(LevelDesc), s));
@@ -497,18 +595,23 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     int launched = 0, batch = std::max(1, std::min(first, maxl + 1));
     Control *hc = (Control *)pinned(sizeof(Control));
     for (;;) {
-        for (int l = launched; l < launched + batch && l <= maxl; ++l) {
-            int32_t nh = n_hint_of(n0, l);
-            // innerOuter on unit input weights ranks edges by degree sums,
-            // which chains level 0 over many rounds; otherwise rounds shrink
-            // the pending set about threefold each (the cooperative kernel
-            // and the finisher complete any remainder)
-            int rounds = rounds_for(nh) + 2;
-            if (l == 0 && p->rating == KAPPA_INNER_OUTER) rounds = 24;
-            launch_level(c, l, nh, d0.nnz, n0, rounds, s);
-        }
+        const int l_end = std::min(launched + batch, maxl + 1);
+        const std::vector<uint64_t> key = {1, pkey(w->base), (uint64_t)n0, (uint64_t)d0.nnz,
+                                           (uint64_t)p->rating, p->seed, (uint64_t)maxl,
+                                           (uint64_t)hubs, (uint64_t)launched, (uint64_t)l_end};
+        HIPCHK(run_seq(w->c, s, key, [&](hipStream_t q) {
+            for (int l = launched; l < l_end; ++l) {
+                int32_t nh = n_hint_of(n0, l);
+                // innerOuter on unit input weights ranks edges by degree
+                // sums, which chains level 0 over many rounds; otherwise
+                // rounds shrink the pending set about threefold each (the
+                // finisher completes any remainder)
+                int rounds = rounds_for(nh) + 2;
+                if (l == 0 && p->rating == KAPPA_INNER_OUTER) rounds = 24;
+                launch_level(c, l, nh, d0.nnz, n0, rounds, q);
+            }
+        }));
         launched += batch;
-        HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(hc, c.ctrl, sizeof(Control), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (hc->done || launched > maxl) break;
@@ -675,8 +778,7 @@ extern "C" kappa_status kappa_match(const kappa_graph *g, int32_t rating, uint64
     HIPCHK(hipMemsetAsync(c.lv, 0, 2 * sizeof(LevelDesc), s));
     HIPCHK(hipMemcpyAsync(c.ctrl, &in->ctrl, sizeof(Control), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(c.lv, &in->l0, sizeof(LevelDesc), hipMemcpyHostToDevice, s));
-    launch_level_begin(c, 0, false, s);
-    launch_level_match(c, 0, d.n, d.nnz, 24, s);
+    launch_level_match(c, 0, d.n, d.nnz, 24, false, true, s);
     LevelDesc *hl = (LevelDesc *)pinned(sizeof(LevelDesc), PIN_LEVELS);
     Control *hc = (Control *)pinned(sizeof(Control));
     HIPCHK(hipMemcpyAsync(hl, c.lv, sizeof(LevelDesc), hipMemcpyDeviceToHost, s));
@@ -698,7 +800,8 @@ extern "C" kappa_status kappa_contract(const kappa_graph *g, const int32_t *mate
     if (!coarse->xadj || coarse->cap_n < 0 || coarse->cap_nnz < 0) return KAPPA_E_ARG;
     hipStream_t s = S(stream);
     DevGraph d = dev(g);
-    const uint64_t arena_bytes = (uint64_t)d.n * 12 + (uint64_t)d.nnz * 8 + 4096;
+    // the coarse level: vw, xadj, mate, cmap (20 B per node), adj, ew
+    const uint64_t arena_bytes = (uint64_t)d.n * 20 + (uint64_t)d.nnz * 8 + 8192;
     for (int attempt = 0; attempt < 2; ++attempt) {
         const bool hubs = attempt > 0;
         uint32_t *flag = nullptr;
@@ -909,18 +1012,31 @@ extern "C" kappa_status kappa_uncoarsen(const kappa_hierarchy *h, int32_t k, uin
         }))
         return KAPPA_E_NOMEM;
     part[0] = part0;
-    launch_fill_u32(flag, 1, 0, s);
     const int32_t L = nl - 1;
-    launch_initial_partition(h->levels[L].n, k, part_seed, part[L], s);
-    for (int32_t l = L; l >= 0; --l) {
-        const kappa_level &lv = h->levels[l];
-        if (l < L)
-            launch_project(lv.cmap, lv.n, h->levels[l + 1].n, part[l + 1], part[l], flag, s);
-        DevGraph d;
-        d.n = lv.n; d.nnz = lv.nnz; d.xadj = lv.xadj; d.adj = lv.adj; d.ew = lv.ew; d.vw = lv.vw;
-        launch_tile_rows(d, tr, s);
-        launch_cut_balance(d, tr, part[l], k, eps_num, eps_den, bw, acc, flag, rd + l, s);
+    std::vector<uint64_t> key = {2, pkey(w->base), (uint64_t)nl, (uint64_t)k, part_seed,
+                                 (uint64_t)eps_num, (uint64_t)eps_den, pkey(part0)};
+    for (const kappa_level &lv : h->levels) {
+        key.push_back((uint64_t)lv.n);
+        key.push_back((uint64_t)lv.nnz);
+        key.push_back(pkey(lv.xadj));
+        key.push_back(pkey(lv.adj));
+        key.push_back(pkey(lv.ew));
+        key.push_back(pkey(lv.vw));
+        key.push_back(pkey(lv.cmap));
     }
+    HIPCHK(run_seq(w->c, s, key, [&](hipStream_t q) {
+        launch_fill_u32(flag, 1, 0, q);
+        launch_initial_partition(h->levels[L].n, k, part_seed, part[L], q);
+        for (int32_t l = L; l >= 0; --l) {
+            const kappa_level &lv = h->levels[l];
+            if (l < L)
+                launch_project(lv.cmap, lv.n, h->levels[l + 1].n, part[l + 1], part[l], flag, q);
+            DevGraph d;
+            d.n = lv.n; d.nnz = lv.nnz; d.xadj = lv.xadj; d.adj = lv.adj; d.ew = lv.ew; d.vw = lv.vw;
+            launch_tile_rows(d, tr, q);
+            launch_cut_balance(d, tr, part[l], k, eps_num, eps_den, bw, acc, flag, rd + l, q);
+        }
+    }));
     uint32_t *hf = (uint32_t *)pinned(sizeof(kappa_cut_result) * nl + 8, PIN_RESULTS);
     if (!hf) return KAPPA_E_ARG;
     kappa_cut_result *hr = (kappa_cut_result *)((char *)hf + 8);
@@ -937,6 +1053,10 @@ extern "C" kappa_status kappa_cache_release(void) {
     std::lock_guard<std::mutex> g(g_cache_mu);
     for (StreamCache *c : g_caches) {
         std::lock_guard<std::mutex> a(c->mu), b(c->amu);
+        for (GraphEntry &e : c->graphs)
+            if (e.exec) (void)hipGraphExecDestroy(e.exec);
+        c->graphs.clear();
+        c->seen.clear();
         if (c->ws) (void)hipFree(c->ws);
         c->ws = nullptr;
         c->ws_bytes = 0;
@@ -945,6 +1065,8 @@ extern "C" kappa_status kappa_cache_release(void) {
     }
     return KAPPA_OK;
 }
+
+extern "C" void kappa_graphs_enable(int32_t on) { g_graphs_on = on != 0; }
 
 extern "C" const char *kappa_status_str(kappa_status st) {
     switch (st) {

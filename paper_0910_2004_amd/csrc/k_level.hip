@@ -27,21 +27,18 @@
 // coarse ids, the contracted edge dropped, parallel edges summed).  Coarse
 // ids: representatives (unmatched nodes and the smaller end of each matched
 // edge) numbered in ascending fine id by a device scan.
-//   1. scan of representative flags -> cmap of representatives, rep_of;
-//      then (one thread) arrays of the next level's nodes are allocated
-//   2. coarse_nodes: c(x), cmap of partners, bound(x) = deg(u) + deg(v) - 2,
-//      row class by bound
-//   3. scan of the bounds -> padded row offsets
-//   4. merge of each coarse row into the padded buffer, by class:
+//   1. scan of representative flags; its apply writes the whole coarse node
+//      (cmap of both ends, rep_of, partner, c(x)); the epilogue allocates the
+//      next level's node arrays
+//   2. merge of each coarse row, staged in the slots of its two fine rows
+//      (deg(u) + deg(v) - 2 entries at most), by class of that bound:
 //        small (<= 64 entries): 16 lanes per row, rank sort in LDS
 //        mid (<= 4094):         one block per row, bitonic sort in LDS
 //        large:                 dense per-slot accumulator + bitmap, read
 //                               back in ascending id order
-//      Equal coarse neighbours form runs of at most 4 entries (a coarse node
-//      has at most two fine nodes on each side).
-//   5. scan of the merged degrees -> coarse row offsets; then (one thread)
-//      the next level's edge arrays are allocated and the stall rule checked
-//   6. compact: copy merged rows into the exact-size coarse arrays
+//   3. scan of the merged degrees -> coarse row offsets; the epilogue
+//      allocates the next level's edge arrays and checks the stall rule
+//   4. compact: copy merged rows into the exact-size coarse arrays
 #include <cstdio>
 #include <cstdlib>
 
@@ -75,51 +72,30 @@ __device__ __forceinline__ int32_t checked_node(int32_t v, int32_t n, Control *c
 }
 
 // ===========================================================================
-// Level start: stop rules (Section 2 threshold, Section 4), allocations,
-// state resets.
+// Level start (first kernel of a level): stop rules (Section 2 threshold,
+// Section 4), state resets.  Every block takes the same decision from the
+// same inputs; block 0 writes it (the only fields it changes are read as
+// "this level goes on" either way, or end the level for every block).
 // ===========================================================================
-__global__ void level_begin_k(Ctx c, int l, int stop_rules) {
-    __shared__ int go;
+__device__ __forceinline__ bool level_gate(const Ctx &c, int l, bool stop_rules, bool writer) {
     Control *ctrl = c.ctrl;
     LevelDesc *L = c.lv + l;
-    if (threadIdx.x == 0) {
-        go = 0;
-        if (!ctrl->done && ctrl->nlevels == l + 1 && L->phase == PH_IDLE) {
-            if (stop_rules && L->n <= ctrl->stop_n) {
-                L->stop = KAPPA_STOP_SIZE;
-                L->phase = PH_STOPPED;
-                ctrl->done = 1;
-            } else if (stop_rules && l >= ctrl->max_levels) {
-                L->stop = KAPPA_STOP_MAXLEVEL;
-                L->phase = PH_STOPPED;
-                ctrl->done = 1;
-            } else {
-                if (!L->mate) L->mate = (int32_t *)arena_alloc(ctrl, (uint64_t)L->n * 4);
-                if (!L->cmap) L->cmap = (int32_t *)arena_alloc(ctrl, (uint64_t)L->n * 4);
-                if (!L->mate || !L->cmap) {
-                    L->phase = PH_STOPPED;
-                    ctrl->done = 1;
-                } else {
-                    L->phase = PH_MATCH;
-                    go = 1;
-                }
-            }
+    if (ctrl->done || ctrl->nlevels != l + 1) return false;
+    const int32_t ph = L->phase;
+    if (ph != PH_IDLE && ph != PH_MATCH) return false;
+    int32_t stop = KAPPA_STOP_NONE;
+    if (stop_rules && L->n <= ctrl->stop_n) stop = KAPPA_STOP_SIZE;
+    else if (stop_rules && l >= ctrl->max_levels) stop = KAPPA_STOP_MAXLEVEL;
+    if (stop != KAPPA_STOP_NONE || !L->mate || !L->cmap) {
+        if (writer) {
+            L->stop = stop;
+            L->phase = PH_STOPPED;
+            ctrl->done = 1;
         }
+        return false;
     }
-    __syncthreads();
-    if (!go) return;
-    MatchState *st = c.ms.state;
-    int t = threadIdx.x;
-    if (t < 16) st->cnt[t >> 2][t & 3] = 0;
-    if (t == 0) {
-        st->handoff = -1;
-        L->matched = 0;
-        L->rounds = 0;
-    }
-    for (int i = t; i < ARRIVE_WORDS + 1; i += blockDim.x) st->barrier[i] = 0;
-    for (int i = t; i < NSHARD; i += blockDim.x) st->sround[i] = 0;
-    int64_t *ss = &st->sstat[0][0][0];
-    for (int i = t; i < STAT_ROUNDS * 3 * NSHARD; i += blockDim.x) ss[i] = 0;
+    if (writer) L->phase = PH_MATCH;
+    return true;
 }
 
 // ===========================================================================
@@ -177,7 +153,7 @@ __device__ __forceinline__ uint64_t level_seed(const Ctx &c, int l) {
     return c.seed_direct ? c.seed : mix64(c.seed + (uint64_t)l);
 }
 
-// --- phases shared by the per-round kernels and the cooperative kernel -----
+// --- phases of the per-round kernels --------------------------------------
 // Blocks [bid] of [nb] cooperate on each phase (grid-stride loops).
 
 // mate = best = -1; nodes of bins 1 and 2 go to the round-1 lists (parity 0).
@@ -345,12 +321,32 @@ __device__ __forceinline__ void mate_phase(const Ctx &c, const DevGraph &g, Leve
     }
 }
 
-// --- per-round kernels (used where a cooperative launch is not available) ---
-__global__ void __launch_bounds__(BLOCK) match_init_k(Ctx c, int l) {
+// --- per-round kernels -----------------------------------------------------
+// The level's first kernel: gate, then mate = best = -1 and the round-1
+// lists.  Block 0 also resets the matching state (read by later kernels).
+// The list counters of round 1 are zero on entry (reset by the previous
+// level's finisher, or by the host before level 0).
+__global__ void __launch_bounds__(BLOCK) match_init_k(Ctx c, int l, int stop_rules) {
     __shared__ int32_t sha[3 * (BLOCK / WAVE) + 3];
-    DevGraph g;
+    __shared__ int go;
+    if (threadIdx.x == 0) go = level_gate(c, l, stop_rules != 0, blockIdx.x == 0);
+    __syncthreads();
+    if (!go) return;
     LevelDesc *L = c.lv + l;
-    if (!load_level(L, PH_MATCH, g)) return;
+    DevGraph g;
+    g.n = L->n; g.nnz = L->nnz; g.xadj = L->xadj; g.adj = L->adj; g.ew = L->ew; g.vw = L->vw;
+    if (blockIdx.x == 0) {
+        MatchState *st = c.ms.state;
+        const int t = threadIdx.x;
+        if (t == 0) {
+            st->handoff = -1;
+            L->matched = 0;
+            L->rounds = 0;
+        }
+        for (int i = t; i < NSHARD; i += blockDim.x) st->sround[i] = 0;
+        int64_t *ss = &st->sstat[0][0][0];
+        for (int i = t; i < STAT_ROUNDS * 3 * NSHARD; i += blockDim.x) ss[i] = 0;
+    }
     init_phase(c, g, L, blockIdx.x, gridDim.x, sha);
 }
 
@@ -400,75 +396,6 @@ __global__ void __launch_bounds__(BLOCK) mate_k(Ctx c, int l, int r) {
     const int32_t *Ls[3];
     round_inputs<FIRST>(c, g, r, cn, Ls);
     mate_phase<FIRST>(c, g, L, r, cn, Ls, blockIdx.x, gridDim.x, sh, sha);
-}
-
-// --- cooperative kernel: init + rounds until few nodes remain --------------
-// All blocks are co-resident (cooperative launch); rounds are separated by a
-// grid barrier on a counter/generation pair.  The spin is bounded: on a
-// timeout the control flags record it and the level is abandoned.
-constexpr int COOP_THREADS = 256;
-
-__device__ __forceinline__ bool grid_sync(MatchState *st, Control *ctrl) {
-    __syncthreads();
-    __shared__ int ok;
-    if (threadIdx.x == 0) {
-        ok = 1;
-        unsigned *gen = &st->barrier[ARRIVE_WORDS];
-        unsigned g0 = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrive_last(st->barrier)) {
-            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            long spins = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > (1l << 26)) {
-                    atomicOr(&ctrl->flags, (uint32_t)CF_ROUNDS);
-                    ok = 0;
-                    break;
-                }
-            }
-        }
-    }
-    __syncthreads();
-    __threadfence();
-    return ok != 0;
-}
-
-template <int R>
-__global__ void __launch_bounds__(COOP_THREADS) coop_match_k(Ctx c, int l, int r_last) {
-    __shared__ Cand shc[COOP_THREADS / WAVE];
-    __shared__ int64_t sh[COOP_THREADS / WAVE + 1];
-    __shared__ int32_t sha[3 * (COOP_THREADS / WAVE) + 3];
-    DevGraph g;
-    LevelDesc *L = c.lv + l;
-    if (!load_level(L, PH_MATCH, g)) return;   // same answer for every block
-    MatchState *st = c.ms.state;
-    if (st->handoff != -1) return;             // the per-round kernels already got there
-    {
-        int slot = r_last & 3;
-        int64_t left = (int64_t)st->cnt[slot][0] + st->cnt[slot][1] + st->cnt[slot][2];
-        if (left <= TAIL_MAX) return;          // the finisher takes it from here
-    }
-    Control *ctrl = c.ctrl;
-    const unsigned bid = blockIdx.x, nb = gridDim.x;
-    const uint64_t seed = level_seed(c, l);
-    int32_t cn[3];
-    const int32_t *Ls[3];
-    int r = r_last + 1;
-    int64_t left = 0;
-    for (;; ++r) {
-        round_inputs<false>(c, g, r, cn, Ls);
-        pick_bin0<R, false>(c, g, L, seed, cn, Ls, bid, nb);
-        pick_bin1<R, false>(c, g, L, seed, cn, Ls, bid, nb);
-        pick_bin2<R, false, COOP_THREADS>(c, g, L, seed, cn, Ls, bid, nb, shc);
-        if (!grid_sync(st, ctrl)) return;
-        mate_phase<false>(c, g, L, r, cn, Ls, bid, nb, sh, sha);
-        if (!grid_sync(st, ctrl)) return;
-        left = (int64_t)st->cnt[r & 3][0] + st->cnt[r & 3][1] + st->cnt[r & 3][2];
-        if (left <= TAIL_MAX || r > g.n + 2) break;
-    }
-    // the one-workgroup finisher resumes after round r
-    if (bid == 0 && threadIdx.x == 0) st->handoff = left == 0 ? -2 : r;
 }
 
 // Finisher: one workgroup runs the remaining rounds (from the handoff point,
@@ -615,7 +542,8 @@ __global__ void __launch_bounds__(FINISH_THREADS) finish_k(Ctx c, int l, int r_l
         c.cs.row_cnt[threadIdx.x] = 0;
         c.cs.totals[threadIdx.x] = 0;
     }
-    __syncthreads();
+    __syncthreads();   // every read of st->cnt above is done
+    if (threadIdx.x < 16) st->cnt[threadIdx.x >> 2][threadIdx.x & 3] = 0;   // next level's lists
     if (threadIdx.x == 0) {
         int64_t m = s_acc[0];
         st->handoff = -2;
@@ -659,13 +587,13 @@ struct RepF {
         N->n = (int32_t)nc;
         N->vw = (uint32_t *)arena_alloc(c.ctrl, (uint64_t)nc * 4);
         N->xadj = (int64_t *)arena_alloc(c.ctrl, (uint64_t)(nc + 1) * 8);
+        N->mate = (int32_t *)arena_alloc(c.ctrl, (uint64_t)nc * 4);
+        N->cmap = (int32_t *)arena_alloc(c.ctrl, (uint64_t)nc * 4);
         N->adj = nullptr;
         N->ew = nullptr;
-        N->cmap = nullptr;
-        N->mate = nullptr;
         N->phase = PH_IDLE;
         N->stop = KAPPA_STOP_NONE;
-        if (!N->vw || !N->xadj) {
+        if (!N->vw || !N->xadj || !N->mate || !N->cmap) {
             L->phase = PH_STOPPED;
             c.ctrl->done = 1;
         }
@@ -995,43 +923,68 @@ __global__ void __launch_bounds__(BLOCK) fill_large_k(Ctx c, int l) {
 }
 
 // --- 4. compaction ----------------------------------------------------------------
+// Also writes Out(x) = sum of the coarse row's weights when the rating needs
+// it (innerOuter): the next level's matching reads it.
 __global__ void __launch_bounds__(BLOCK) compact_small_k(Ctx c, int l) {
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_COMPACT, g)) return;
     const LevelDesc *N = c.lv + l + 1;
+    uint32_t *out = c.rating == KAPPA_INNER_OUTER ? c.ms.out : nullptr;
     const int grp = threadIdx.x / ROW_SMALL_G, sub = threadIdx.x % ROW_SMALL_G;
     const int64_t count = N->n;
-    for (int64_t x = (int64_t)blockIdx.x * SM_ROWS + grp; x < count;
-         x += (int64_t)gridDim.x * SM_ROWS) {
-        int32_t len = c.cs.cdeg[x];
-        if (len == 0) continue;
-        RowSrc r = row_src(g, c, (int32_t)x);
-        if (row_bound(r) > ROW_SMALL_MAX) continue;   // compact_big copies it
-        int64_t dst = N->xadj[x];
-        for (int t = sub; t < len; t += ROW_SMALL_G) {
-            int64_t at = staged_at(r, t);
-            N->adj[dst + t] = c.cs.tmp_adj[at];
-            N->ew[dst + t] = c.cs.tmp_ew[at];
+    const int64_t gs = (int64_t)gridDim.x * SM_ROWS;
+    const int64_t lim = (count + gs - 1) / gs * gs;   // uniform trip count (group shuffles)
+    for (int64_t x = (int64_t)blockIdx.x * SM_ROWS + grp; x < lim; x += gs) {
+        int32_t len = x < count ? c.cs.cdeg[x] : 0;
+        bool mine = len > 0;
+        RowSrc r;
+        if (mine) {
+            r = row_src(g, c, (int32_t)x);
+            mine = row_bound(r) <= ROW_SMALL_MAX;   // else compact_big copies it
+        }
+        uint32_t sum = 0;
+        if (mine) {
+            int64_t dst = N->xadj[x];
+            for (int t = sub; t < len; t += ROW_SMALL_G) {
+                int64_t at = staged_at(r, t);
+                uint32_t w = c.cs.tmp_ew[at];
+                N->adj[dst + t] = c.cs.tmp_adj[at];
+                N->ew[dst + t] = w;
+                sum += w;
+            }
+        }
+        if (out) {
+            for (int o = ROW_SMALL_G / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, ROW_SMALL_G);
+            if (sub == 0 && x < count && (mine || len == 0)) out[x] = sum;
         }
     }
 }
 
 __global__ void __launch_bounds__(BLOCK) compact_big_k(Ctx c, int l) {
+    __shared__ uint32_t sh[BLOCK / WAVE + 1];
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_COMPACT, g)) return;
     const LevelDesc *N = c.lv + l + 1;
+    uint32_t *out = c.rating == KAPPA_INNER_OUTER ? c.ms.out : nullptr;
     const int64_t c1 = c.cs.row_cnt[1], c2 = c.cs.row_cnt[2];
     for (int64_t i = blockIdx.x; i < c1 + c2; i += gridDim.x) {
         int32_t x = i < c1 ? c.cs.rows[g.n + i] : c.cs.rows[2 * (int64_t)g.n + (i - c1)];
         RowSrc r = row_src(g, c, x);
         int64_t dst = N->xadj[x];
         int32_t len = c.cs.cdeg[x];
+        uint32_t sum = 0;
         for (int t = threadIdx.x; t < len; t += BLOCK) {
             int64_t at = staged_at(r, t);
+            uint32_t w = c.cs.tmp_ew[at];
             N->adj[dst + t] = c.cs.tmp_adj[at];
-            N->ew[dst + t] = c.cs.tmp_ew[at];
+            N->ew[dst + t] = w;
+            sum += w;
+        }
+        if (out) {
+            sum = block_sum(sum, sh);
+            if (threadIdx.x == 0) out[x] = sum;
         }
     }
 }
@@ -1039,40 +992,11 @@ __global__ void __launch_bounds__(BLOCK) compact_big_k(Ctx c, int l) {
 // ===========================================================================
 // Host side
 // ===========================================================================
-void launch_level_begin(const Ctx &c, int l, bool stop_rules, hipStream_t s) {
-    KAPPA_PROF("level_begin", s);
-    hipLaunchKernelGGL(level_begin_k, dim3(1), dim3(BLOCK), 0, s, c, l, stop_rules ? 1 : 0);
-}
-
-// Co-resident block count for the cooperative kernel (0 if unavailable).
-template <int R>
-static unsigned coop_capacity() {
-    static unsigned cap = 0;
-    static bool probed = false;
-    if (!probed) {
-        probed = true;
-        int dev = 0, coop = 0, cus = 0, per = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess &&
-            coop &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, coop_match_k<R>, COOP_THREADS, 0) ==
-                hipSuccess &&
-            per > 0)
-            cap = (unsigned)(cus * std::min(per, 2));
-    }
-    return cap;
-}
 
 template <int R>
 static void match_impl(const Ctx &c, int l, int32_t n_hint, int rounds, hipStream_t s) {
     // per-round kernels; round r's grid follows a geometric estimate of the
     // pending count (any grid is correct: all loops stride)
-    {
-        KAPPA_PROF("match_init", s);
-        hipLaunchKernelGGL(match_init_k, dim3(grid_for(n_hint, BLOCK * 2, 2048)), dim3(BLOCK), 0, s,
-                           c, l);
-    }
     double est = n_hint;
     for (int r = 1; r <= rounds; ++r, est *= 0.7) {
         int64_t e = (int64_t)est + 1;
@@ -1100,32 +1024,19 @@ static void match_impl(const Ctx &c, int l, int32_t n_hint, int rounds, hipStrea
             hipLaunchKernelGGL(mate_k<false>, dim3(mate_blocks), dim3(BLOCK), 0, s, c, l, r);
         }
     }
-    // level 0 only (unit input weights can chain long): if many nodes are
-    // still pending, cooperative rounds continue until few remain
-    unsigned cap = l == 0 ? coop_capacity<R>() : 0;
-    if (cap > 0) {
-        unsigned nb = std::min(cap, grid_for((int64_t)est + 1, COOP_THREADS / SMALL_G, cap));
-        Ctx cc = c;
-        int ll = l, rr = rounds;
-        void *args[] = {&cc, &ll, &rr};
-        KAPPA_PROF("match_coop", s);
-        hipError_t e = hipLaunchCooperativeKernel((const void *)coop_match_k<R>, dim3(nb),
-                                                  dim3(COOP_THREADS), args, 0, s);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            if (getenv("KAPPA_DEBUG"))
-                fprintf(stderr, "kappa: cooperative launch (%u blocks) failed: %s\n", nb,
-                        hipGetErrorString(e));
-        }
-    }
     KAPPA_PROF("match_finish", s);
     hipLaunchKernelGGL(finish_k<R>, dim3(1), dim3(FINISH_THREADS), 0, s, c, l, rounds);
 }
 
 void launch_level_match(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, int rounds,
-                        hipStream_t s) {
+                        bool stop_rules, bool out_kernels, hipStream_t s) {
     if (rounds < 1) rounds = 1;
-    if (c.rating == KAPPA_INNER_OUTER) launch_level_out(c, l, nnz_cap, n_hint, s);
+    {
+        KAPPA_PROF("match_init", s);
+        hipLaunchKernelGGL(match_init_k, dim3(grid_for(n_hint, BLOCK * 2, 2048)), dim3(BLOCK), 0, s,
+                           c, l, stop_rules ? 1 : 0);
+    }
+    if (c.rating == KAPPA_INNER_OUTER && out_kernels) launch_level_out(c, l, nnz_cap, n_hint, s);
     switch (c.rating) {
     case KAPPA_INNER_OUTER: match_impl<KAPPA_INNER_OUTER>(c, l, n_hint, rounds, s); break;
     case KAPPA_WEIGHT: match_impl<KAPPA_WEIGHT>(c, l, n_hint, rounds, s); break;
@@ -1165,8 +1076,8 @@ void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, h
 
 void launch_level(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, int32_t n_cap,
                   int rounds, hipStream_t s) {
-    launch_level_begin(c, l, true, s);
-    launch_level_match(c, l, n_hint, nnz_cap, rounds, s);
+    // Out(v) of levels above 0 is written by the previous level's compaction
+    launch_level_match(c, l, n_hint, nnz_cap, rounds, true, l == 0, s);
     launch_level_contract(c, l, n_hint, n_cap, s);
 }
 

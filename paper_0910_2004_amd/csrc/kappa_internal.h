@@ -400,7 +400,6 @@ struct MatchState {
     int32_t cnt[4][4];      // [round & 3][bin]: sizes of the pending lists written by a round
     int32_t handoff;        // -1: rounds continue; r >= 0: the finisher resumes after round r; -2: done
     int32_t pad[3];
-    unsigned barrier[ARRIVE_WORDS + 1];   // grid barrier of the cooperative kernel: counters, generation
     int32_t sround[NSHARD];               // per shard: last round in which some node pointed
     int64_t sstat[STAT_ROUNDS][3][NSHARD];  // per round and shard: pointing nodes, their degree sum, pairs
 };
@@ -494,12 +493,14 @@ void launch_level_out(const Ctx &c, int l, int64_t nnz_cap, int32_t n_hint, hipS
 // multi-block matching rounds before the one-workgroup finisher.
 void launch_level(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, int32_t n_cap,
                   int rounds, hipStream_t s);
-// Matching only (level phase must be PH_MATCH), e.g. for kappa_match.
+// Matching only (first kernel: the level gate, which moves an idle level to
+// PH_MATCH unless a stop rule fires; stop_rules = false checks none), e.g.
+// for kappa_match.  out_kernels: compute Out(v) (innerOuter) from the graph;
+// otherwise it must already be in the scratch (written by the previous
+// level's compaction).  Needs st->cnt zero on entry.
 void launch_level_match(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, int rounds,
-                        hipStream_t s);
+                        bool stop_rules, bool out_kernels, hipStream_t s);
 // Contraction only (level phase PH_CONTRACT, mate set), e.g. for kappa_contract.
 void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, hipStream_t s);
-// Level start: stop rules, allocations, state resets (one block).
-void launch_level_begin(const Ctx &c, int l, bool stop_rules, hipStream_t s);
 
 }  // namespace kappa

@@ -25,11 +25,13 @@ def assert_graph_equal(got: O.Graph, want: O.Graph, what=""):
 
 def check_hierarchy(g, rating, seed, stop_n, stall=(1, 20), max_levels=64, k=2,
                     part_seed=1, eps=(3, 100), check_rounds=True, check_uncoarsen=True,
-                    oracle_h=None):
+                    oracle_h=None, dg=None, part0=None):
     """Coarsen on the GPU and with the oracle; compare every level, map,
     round count, round statistics and the way back up.  Returns the
-    hierarchy (GPU) and the oracle hierarchy."""
-    H = K.kappa_coarsen(dev(g), rating, seed, stop_n, stall[0], stall[1], max_levels)
+    hierarchy (GPU) and the oracle hierarchy.  dg / part0: device input
+    graph and level-0 partition buffer to use (fresh ones by default)."""
+    H = K.kappa_coarsen(dg if dg is not None else dev(g), rating, seed, stop_n, stall[0], stall[1],
+                        max_levels)
     OH = oracle_h or O.coarsen(g, rating, seed, stop_n, stall[0], stall[1], max_levels,
                                round_stats=check_rounds)
     assert len(H) == len(OH.levels), f"levels {len(H)} != {len(OH.levels)}"
@@ -47,7 +49,7 @@ def check_hierarchy(g, rating, seed, stop_n, stall=(1, 20), max_levels=64, k=2,
             assert np.array_equal(p, ol.round_active[:kk]), f"level {l}: round activity differs"
             assert np.array_equal(d, ol.round_degree[:kk]), f"level {l}: round degrees differ"
     if check_uncoarsen:
-        part0, res = K.kappa_uncoarsen(H, k, part_seed, eps[0], eps[1])
+        part0, res = K.kappa_uncoarsen(H, k, part_seed, eps[0], eps[1], part0=part0)
         oparts, ores = O.uncoarsen(OH, k, part_seed, eps[0], eps[1])
         assert np.array_equal(part0.cpu().numpy(), oparts[0])
         for l in range(len(OH.levels)):

@@ -245,3 +245,27 @@ def test_deterministic_repeat():
     for l in range(len(H1)):
         a, b = H1.level(l), H2.level(l)
         assert_graph_equal(graph_np(a.graph), graph_np(b.graph), f"level {l}")
+
+
+def test_graph_replays_equal_oracle_and_direct_launches():
+    """A launch sequence seen twice is captured as a HIP graph and replayed
+    from then on.  Every call (direct, capture, replays with eager torch work
+    and host synchronisation in between, and direct launches again with
+    graphs switched off) must equal the oracle."""
+    import torch
+    g = rgg(1 << 14, seed=9)
+    for rating in (O.EXPANSION_STAR2, O.INNER_OUTER):
+        OH = O.coarsen(g, rating, 5, 64, 1, 20, 64, round_stats=True)
+        dg = dev(g)
+        part0 = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        for rep in range(5):
+            say(f"rating {rating} call {rep}")
+            K.graphs_enable(rep < 4)
+            try:
+                H, _ = check_hierarchy(g, rating, 5, 64, k=8, oracle_h=OH, dg=dg, part0=part0)
+                del H
+            finally:
+                K.graphs_enable(False)
+            x = torch.arange(1 << 16, device="cuda", dtype=torch.int64)
+            assert int((x * 2).sum().item()) == (1 << 16) * ((1 << 16) - 1)
+            torch.cuda.synchronize()
