@@ -40,11 +40,11 @@ def bytes_pick_first(n, D, io):
 
 
 def bytes_fill_small(n, D, nc, Dc, matched):
-    # per coarse row: list entry, rep_of, mate (12), offsets of u (16),
-    # padded offset (8), degree (4); matched rows also read the partner's
-    # offsets (16).  Per fine entry: adj, w, cmap of the neighbour (12).
-    # Per merged coarse entry: key and weight written (8).
-    return 40 * nc + 16 * matched + 12 * D + 8 * Dc
+    # per coarse row: rep_of, partner (8), offsets of the representative (16),
+    # merged degree written (4); matched rows also read the partner's offsets
+    # (16).  Per fine entry: adj, w, cmap of the neighbour (12).  Per merged
+    # coarse entry: key and weight written (8).
+    return 28 * nc + 16 * matched + 12 * D + 8 * Dc
 
 
 def bytes_compact(nc, Dc):
@@ -58,9 +58,29 @@ def bytes_cut_entries(D):
 
 
 MODELS = {"pick_first": "per level: 16 B/node + 12 B/entry (innerOuter 20 + 16)",
-          "fill_small": "per level: 40 B/coarse row + 16 B/matched pair + 12 B/fine entry + 8 B/coarse entry",
+          "fill_small": "per level: 28 B/coarse row + 16 B/matched pair + 12 B/fine entry + 8 B/coarse entry",
           "compact_small": "per level: 24 B/coarse row + 16 B/coarse entry",
           "cut_entries": "per level: 16 B/entry"}
+
+
+def counter_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/<kernel>_counters.json: FETCH_SIZE and WRITE_SIZE per step,
+    scaled by a plain copy), or None when the kernel's source changed since
+    the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def level_stats(H):
@@ -174,8 +194,10 @@ def main():
         per_launch_bytes = mb[rk] / (cnt / args.steps)
         avg_s = ms / cnt / 1e3
         achieved = per_launch_bytes / avg_s / 1e9
+        traffic = counter_traffic(rk)
         roof = {"bound": "hbm", "kernel": rk, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else int(traffic),
                 "avg_launch_us": round(avg_s * 1e6, 2), "bytes_per_launch": int(per_launch_bytes),
                 "model": MODELS[rk], "time_share": round(ms / args.steps / total_ms, 3),
                 "dominant_kernel": dom}
