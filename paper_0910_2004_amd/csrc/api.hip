@@ -451,7 +451,10 @@ void carve_scratch(Carve &cv, const DevGraph &g, int rating, bool hubs, Ctx &c) 
     MatchScratch &ms = c.ms;
     ContractScratch &cs = c.cs;
     ms.best = cv.get<int32_t>(g.n);
-    ms.lists = cv.get<int32_t>(6 * (int64_t)g.n);
+    ms.lv = cv.get<int32_t>(6 * (int64_t)g.n);
+    ms.lb = cv.get<int32_t>(6 * (int64_t)g.n);
+    ms.ld = cv.get<int32_t>(6 * (int64_t)g.n);
+    ms.nrec = cv.get<int2>(g.n);
     ms.out = rating == KAPPA_INNER_OUTER ? cv.get<uint32_t>(g.n) : nullptr;
     ms.tile_row = rating == KAPPA_INNER_OUTER ? cv.get<int32_t>(tile_rows_needed(g.nnz)) : nullptr;
     ms.state = cv.get<MatchState>(1);

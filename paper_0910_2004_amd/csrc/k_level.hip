@@ -13,7 +13,7 @@
 // matched; repeat until no free node has a free neighbour.  Under a strict
 // total order this is exactly the Greedy matching of Section 3.2.
 //   pick kernel  -- node-centric argmax over the row, nodes binned by degree:
-//                   bin 0 (deg <= 16) 8 lanes per node, bin 1 (deg <= 1024)
+//                   bin 0 (deg <= 16) 4 lanes per node, bin 1 (deg <= 1024)
 //                   one wave per node, bin 2 one block per node.  A pending
 //                   node whose previous choice is still free keeps it (free
 //                   sets only shrink, so it is still the maximum).
@@ -59,9 +59,6 @@ __device__ __forceinline__ int bin_of(int64_t deg) {
     return deg <= BIN_SMALL_MAX ? 0 : (deg <= BIN_MID_MAX ? 1 : 2);
 }
 
-__device__ __forceinline__ int32_t *list_ptr(int32_t *lists, int32_t n, int par, int bin) {
-    return lists + ((int64_t)(par * 3 + bin)) * n;
-}
 
 // Node id read from a pending list: -1 (and a control flag) if out of range.
 // Valid state never trips this; it keeps a broken state from indexing memory.
@@ -101,21 +98,86 @@ __device__ __forceinline__ bool level_gate(const Ctx &c, int l, bool stop_rules,
 // ===========================================================================
 // Matching
 // ===========================================================================
-template <int R, int G>
-__device__ __forceinline__ Cand scan_row(const DevGraph &g, int32_t v, int sub,
-                                         const int32_t *mate, const uint32_t *out,
-                                         uint64_t seed, bool first) {
+// Pending nodes of a round live in lists per degree bin, stored as three
+// arrays: the node, its current choice (-1: none yet) and its degree.  Round
+// r reads parity (r-1)&1 (round 1: every node for bin 0, the init lists for
+// bins 1 and 2) and writes parity r&1.
+struct PList {
+    int32_t *v, *b, *d;
+};
+__device__ __forceinline__ PList plist(const MatchScratch &ms, int32_t n, int par, int bin) {
+    const int64_t off = (int64_t)(par * 3 + bin) * n;
+    return PList{ms.lv + off, ms.lb + off, ms.ld + off};
+}
+
+// The rating's node attribute: c(v), or Out(v) for innerOuter (weight uses
+// neither).  Round 1 reads it from the graph; later rounds from the packed
+// node record {attribute, mate}, one 8-byte gather per neighbour.
+template <int R>
+__device__ __forceinline__ uint32_t attr_src(const DevGraph &g, const uint32_t *out, int32_t v) {
+    return R == KAPPA_INNER_OUTER ? out[v] : (R == KAPPA_WEIGHT ? 0u : g.vw[v]);
+}
+
+// Best edge from v to a free neighbour over the entries sub, sub+G, ...
+template <int R, int G, bool FIRST>
+__device__ __forceinline__ Cand scan_row(const DevGraph &g, int32_t v, uint32_t av, int sub,
+                                         const int2 *nrec, const uint32_t *out, uint64_t seed) {
     Cand best = cand_none();
-    int64_t b = g.xadj[v], e = g.xadj[v + 1];
-    uint32_t cv = g.vw[v];
-    uint32_t ov = (R == KAPPA_INNER_OUTER) ? out[v] : 0u;
+    const int64_t b = g.xadj[v], e = g.xadj[v + 1];
     for (int64_t j = b + sub; j < e; j += G) {
-        int32_t u = g.adj[j];
-        if (!first && mate[u] >= 0) continue;
+        const int32_t u = g.adj[j];
+        uint32_t au;
+        if (FIRST) {
+            au = attr_src<R>(g, out, u);   // round 1: every node is free
+        } else {
+            const int2 rec = nrec[u];
+            if (rec.y >= 0) continue;
+            au = (uint32_t)rec.x;
+        }
         Cand cd;
-        rate<R>(g.ew[j], g.vw[u], cv, (R == KAPPA_INNER_OUTER) ? out[u] : 0u, ov, cd.num, cd.den);
+        rate<R>(g.ew[j], au, av, au, av, cd.num, cd.den);
         cd.h = mix64(seed ^ edge_id(v, u));
         cd.u = u;
+        if (cand_better(cd, best, v)) best = cd;
+    }
+    return best;
+}
+
+// The same over a row of at most BIN_SMALL_MAX entries [b, e): every load of
+// a lane's entries is issued before the first comparison.
+template <int R, int G, bool FIRST>
+__device__ __forceinline__ Cand scan_row_small(const DevGraph &g, int32_t v, uint32_t av, int sub,
+                                               int64_t b, int64_t e, const int2 *nrec,
+                                               const uint32_t *out, uint64_t seed) {
+    constexpr int T = BIN_SMALL_MAX / G;
+    int32_t u[T];
+    uint32_t w[T], au[T];
+    bool ok[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int64_t j = b + sub + (int64_t)t * G;
+        ok[t] = j < e;
+        u[t] = ok[t] ? g.adj[j] : 0;
+        w[t] = ok[t] ? g.ew[j] : 0u;
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        if (FIRST) {
+            au[t] = ok[t] ? attr_src<R>(g, out, u[t]) : 0u;
+        } else {
+            const int2 rec = ok[t] ? nrec[u[t]] : make_int2(0, 0);
+            ok[t] = ok[t] && rec.y < 0;
+            au[t] = (uint32_t)rec.x;
+        }
+    }
+    Cand best = cand_none();
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        if (!ok[t]) continue;
+        Cand cd;
+        rate<R>(w[t], au[t], av, au[t], av, cd.num, cd.den);
+        cd.h = mix64(seed ^ edge_id(v, u[t]));
+        cd.u = u[t];
         if (cand_better(cd, best, v)) best = cd;
     }
     return best;
@@ -143,180 +205,298 @@ __device__ __forceinline__ Cand block_reduce_cand(Cand cd, int32_t v, Cand *sh) 
     return r;
 }
 
-// A pending node keeps its choice while that neighbour is still free.
-__device__ __forceinline__ bool needs_rescan(int32_t v, const int32_t *best, const int32_t *mate) {
-    int32_t b = best[v];
-    return !(b >= 0 && mate[b] < 0);
+// A pending node keeps its choice while that neighbour is still free (free
+// sets only shrink, so it is still the maximum).
+__device__ __forceinline__ bool keeps_choice(int32_t bp, int32_t n, const int2 *nrec) {
+    return bp >= 0 && bp < n && nrec[bp].y < 0;
 }
 
 __device__ __forceinline__ uint64_t level_seed(const Ctx &c, int l) {
     return c.seed_direct ? c.seed : mix64(c.seed + (uint64_t)l);
 }
 
+// Block-aggregated append of up to MK entries per thread into the three bin
+// lists `ol` (bin < 0: none); counters cnt[3] may be global or LDS.  Every
+// thread of the block calls it; sh: BLOCK/WAVE + 1 (blockDim.x/WAVE + 1)
+// int64, sbase: 3 int32 of LDS.  Order inside a list is not deterministic;
+// no consumer depends on it.
+constexpr int MK = 8;
+__device__ __forceinline__ void block_append_mk(const int bin[MK], const int32_t v[MK],
+                                                const int32_t b[MK], const int32_t d[MK],
+                                                const PList ol[3], int32_t *cnt, int64_t *sh,
+                                                int32_t *sbase) {
+    constexpr int64_t M = 0x1fffff;   // 21 bits per bin: at most 1024 * MK entries per block
+    int64_t packed = 0;
+#pragma unroll
+    for (int k = 0; k < MK; ++k)
+        if (bin[k] >= 0) packed += (int64_t)1 << (21 * bin[k]);
+    int64_t tot;
+    const int64_t pre = block_excl_scan(packed, sh, &tot);
+    if (threadIdx.x < 3) {
+        const int32_t t = (int32_t)((tot >> (21 * threadIdx.x)) & M);
+        sbase[threadIdx.x] = t ? atomicAdd(&cnt[threadIdx.x], t) : 0;
+    }
+    __syncthreads();
+    int32_t p0 = sbase[0] + (int32_t)(pre & M), p1 = sbase[1] + (int32_t)((pre >> 21) & M),
+            p2 = sbase[2] + (int32_t)((pre >> 42) & M);
+#pragma unroll
+    for (int k = 0; k < MK; ++k) {
+        if (bin[k] < 0) continue;
+        int32_t p;
+        PList o;
+        if (bin[k] == 0) { p = p0++; o = ol[0]; }
+        else if (bin[k] == 1) { p = p1++; o = ol[1]; }
+        else { p = p2++; o = ol[2]; }
+        o.v[p] = v[k];
+        o.b[p] = b[k];
+        o.d[p] = d[k];
+    }
+    __syncthreads();   // sbase is reused by the next call
+}
+
 // --- phases of the per-round kernels --------------------------------------
-// Blocks [bid] of [nb] cooperate on each phase (grid-stride loops).
 
 // mate = best = -1; nodes of bins 1 and 2 go to the round-1 lists (parity 0).
+// Loads of a thread's MK entries are issued before its stores.
 __device__ __forceinline__ void init_phase(const Ctx &c, const DevGraph &g, LevelDesc *L,
-                                           unsigned bid, unsigned nb, int32_t *sha) {
+                                           int64_t *sh, int32_t *sbase) {
     int32_t *mate = L->mate, *best = c.ms.best;
     MatchState *st = c.ms.state;
-    int32_t *lists[3] = {list_ptr(c.ms.lists, g.n, 0, 0), list_ptr(c.ms.lists, g.n, 0, 1),
-                         list_ptr(c.ms.lists, g.n, 0, 2)};
-    int32_t *cnts[3] = {&st->cnt[0][0], &st->cnt[0][1], &st->cnt[0][2]};
-    const int64_t stride = (int64_t)nb * blockDim.x;
-    const int64_t lim = ((int64_t)g.n + stride - 1) / stride * stride;   // block-uniform trips
-    for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < lim; i += stride) {
-        int bn = -1;
-        if (i < g.n) {
-            mate[i] = -1;
-            best[i] = -1;
-            int64_t d = g.xadj[i + 1] - g.xadj[i];
-            bn = bin_of(d);
-            if (bn == 0) bn = -1;
+    const PList ol[3] = {plist(c.ms, g.n, 0, 0), plist(c.ms, g.n, 0, 1), plist(c.ms, g.n, 0, 2)};
+    // pass p, slot k of block b covers entries ((p * MK + k) * nb + b) * blockDim.x + t:
+    // small inputs spread over every block first
+    const int64_t row = (int64_t)gridDim.x * blockDim.x, per_pass = row * MK;
+    for (int64_t base = 0; base < g.n; base += per_pass) {   // block-uniform
+        const int64_t first = base + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        int bin[MK];
+        int32_t vv[MK], bb[MK], dd[MK];
+        int64_t deg[MK];
+#pragma unroll
+        for (int k = 0; k < MK; ++k) {
+            const int64_t i = first + (int64_t)k * row;
+            deg[k] = i < g.n ? g.xadj[i + 1] - g.xadj[i] : 0;
         }
-        block_append3(bn, (int32_t)i, lists, cnts, sha);
+#pragma unroll
+        for (int k = 0; k < MK; ++k) {
+            const int64_t i = first + (int64_t)k * row;
+            vv[k] = (int32_t)i;
+            bb[k] = -1;
+            dd[k] = (int32_t)deg[k];
+            const int bn = bin_of(deg[k]);
+            bin[k] = i < g.n && bn > 0 ? bn : -1;
+            if (i < g.n) {
+                mate[i] = -1;
+                best[i] = -1;
+            }
+        }
+        block_append_mk(bin, vv, bb, dd, ol, &st->cnt[0][0], sh, sbase);
     }
 }
 
-// Inputs of round r: counts and lists (round 1: bin 0 is every node).
+// Inputs of round r: lists and their sizes (round 1: bin 0 is every node).
+struct RoundIn {
+    PList in[3];
+    int32_t cn[3];
+};
 template <bool FIRST>
-__device__ __forceinline__ int64_t round_inputs(const Ctx &c, const DevGraph &g, int r,
-                                                int32_t cn[3], const int32_t *Ls[3]) {
-    MatchState *st = c.ms.state;
-    if (FIRST) {
-        cn[0] = g.n; cn[1] = st->cnt[0][1]; cn[2] = st->cnt[0][2];
-        Ls[0] = nullptr;
-        Ls[1] = list_ptr(c.ms.lists, g.n, 0, 1);
-        Ls[2] = list_ptr(c.ms.lists, g.n, 0, 2);
-        return (int64_t)g.n;
+__device__ __forceinline__ RoundIn round_inputs(const Ctx &c, const DevGraph &g, int r,
+                                                const int32_t *cnt3) {
+    RoundIn ri;
+    const int par = FIRST ? 0 : ((r - 1) & 1);
+    for (int b = 0; b < 3; ++b) {
+        ri.in[b] = plist(c.ms, g.n, par, b);
+        ri.cn[b] = min(cnt3[b], g.n);
     }
-    int slot = (r - 1) & 3, par = (r - 1) & 1;
-    cn[0] = st->cnt[slot][0]; cn[1] = st->cnt[slot][1]; cn[2] = st->cnt[slot][2];
-    Ls[0] = list_ptr(c.ms.lists, g.n, par, 0);
-    Ls[1] = list_ptr(c.ms.lists, g.n, par, 1);
-    Ls[2] = list_ptr(c.ms.lists, g.n, par, 2);
-    return (int64_t)cn[0] + cn[1] + cn[2];
+    if (FIRST) ri.cn[0] = g.n;
+    return ri;
 }
 
-// bin 0: 8 lanes per node
+// bin 0: SMALL_G lanes per node
 template <int R, bool FIRST>
-__device__ __forceinline__ void pick_bin0(const Ctx &c, const DevGraph &g, const LevelDesc *L,
-                                          uint64_t seed, const int32_t cn[3],
-                                          const int32_t *const Ls[3], unsigned bid, unsigned nb) {
+__device__ __forceinline__ void pick_bin0(const Ctx &c, const DevGraph &g, uint64_t seed,
+                                          const RoundIn &ri, unsigned bid, unsigned nb) {
     const int G = SMALL_G;
-    const int32_t *mate = L->mate;
     int32_t *best = c.ms.best;
-    int sub = threadIdx.x & (G - 1);
-    int64_t gi = (int64_t)bid * (blockDim.x / G) + threadIdx.x / G;
-    int64_t gs = (int64_t)nb * (blockDim.x / G);
-    int64_t lim = ((int64_t)cn[0] + gs - 1) / gs * gs;   // uniform trip count
+    const int2 *nrec = c.ms.nrec;
+    const uint32_t *out = c.ms.out;
+    const int sub = threadIdx.x & (G - 1);
+    const int64_t gi = (int64_t)bid * (blockDim.x / G) + threadIdx.x / G;
+    const int64_t gs = (int64_t)nb * (blockDim.x / G);
+    const int64_t cnt = ri.cn[0];
+    const int64_t lim = (cnt + gs - 1) / gs * gs;   // uniform trip count (group shuffles)
     for (int64_t i = gi; i < lim; i += gs) {
         int32_t v = -1;
         bool act = false;
-        if (i < cn[0]) {
-            v = FIRST ? (int32_t)i : checked_node(Ls[0][i], g.n, c.ctrl);
-            if (v < 0) {
-                act = false;
-            } else if (FIRST) {
-                int64_t d = g.xadj[v + 1] - g.xadj[v];
-                act = d >= 1 && d <= BIN_SMALL_MAX;
+        uint32_t av = 0;
+        int64_t rb = 0, re = 0;
+        if (i < cnt) {
+            if (FIRST) {
+                v = (int32_t)i;
+                rb = g.xadj[v];
+                re = g.xadj[v + 1];
+                act = re - rb >= 1 && re - rb <= BIN_SMALL_MAX;
+                if (act) av = attr_src<R>(g, out, v);
             } else {
-                act = needs_rescan(v, best, mate);
+                v = checked_node(ri.in[0].v[i], g.n, c.ctrl);
+                if (v >= 0 && !keeps_choice(ri.in[0].b[i], g.n, nrec)) {
+                    act = true;
+                    av = (uint32_t)nrec[v].x;
+                    rb = g.xadj[v];
+                    re = g.xadj[v + 1];
+                    if (re - rb > BIN_SMALL_MAX) re = rb + BIN_SMALL_MAX;   // valid lists never
+                }
             }
         }
-        Cand cd = act ? scan_row<R, G>(g, v, sub, mate, c.ms.out, seed, FIRST) : cand_none();
+        Cand cd = act ? scan_row_small<R, G, FIRST>(g, v, av, sub, rb, re, nrec, out, seed)
+                      : cand_none();
         cd = group_reduce<G>(cd, v);
-        if (act && sub == 0) best[v] = cd.u;
+        if (act && sub == 0) {
+            best[v] = cd.u;
+            if (!FIRST) ri.in[0].b[i] = cd.u;
+        }
     }
 }
 
 // bin 1: one wave per node
 template <int R, bool FIRST>
-__device__ __forceinline__ void pick_bin1(const Ctx &c, const DevGraph &g, const LevelDesc *L,
-                                          uint64_t seed, const int32_t cn[3],
-                                          const int32_t *const Ls[3], unsigned bid, unsigned nb) {
-    const int32_t *mate = L->mate;
+__device__ __forceinline__ void pick_bin1(const Ctx &c, const DevGraph &g, uint64_t seed,
+                                          const RoundIn &ri, unsigned bid, unsigned nb) {
     int32_t *best = c.ms.best;
-    int64_t gi = (int64_t)bid * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-    int64_t gs = (int64_t)nb * (blockDim.x / WAVE);
-    for (int64_t i = gi; i < cn[1]; i += gs) {
-        int32_t v = checked_node(Ls[1][i], g.n, c.ctrl);
-        if (v < 0 || (!FIRST && !needs_rescan(v, best, mate))) continue;   // wave-uniform
-        Cand cd = scan_row<R, WAVE>(g, v, lane_id(), mate, c.ms.out, seed, FIRST);
+    const int2 *nrec = c.ms.nrec;
+    const uint32_t *out = c.ms.out;
+    const int64_t gi = (int64_t)bid * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int64_t gs = (int64_t)nb * (blockDim.x / WAVE);
+    for (int64_t i = gi; i < ri.cn[1]; i += gs) {
+        const int32_t v = checked_node(ri.in[1].v[i], g.n, c.ctrl);
+        if (v < 0 || (!FIRST && keeps_choice(ri.in[1].b[i], g.n, nrec))) continue;   // wave-uniform
+        const uint32_t av = FIRST ? attr_src<R>(g, out, v) : (uint32_t)nrec[v].x;
+        Cand cd = scan_row<R, WAVE, FIRST>(g, v, av, lane_id(), nrec, out, seed);
         cd = group_reduce<WAVE>(cd, v);
-        if (lane_id() == 0) best[v] = cd.u;
+        if (lane_id() == 0) {
+            best[v] = cd.u;
+            ri.in[1].b[i] = cd.u;
+        }
     }
 }
 
 // bin 2: one block per node (blockDim.x lanes, a multiple of 64)
 template <int R, bool FIRST, int NT>
-__device__ __forceinline__ void pick_bin2(const Ctx &c, const DevGraph &g, const LevelDesc *L,
-                                          uint64_t seed, const int32_t cn[3],
-                                          const int32_t *const Ls[3], unsigned bid, unsigned nb,
-                                          Cand *sh) {
-    const int32_t *mate = L->mate;
+__device__ __forceinline__ void pick_bin2(const Ctx &c, const DevGraph &g, uint64_t seed,
+                                          const RoundIn &ri, unsigned bid, unsigned nb, Cand *sh) {
     int32_t *best = c.ms.best;
-    for (int64_t i = bid; i < cn[2]; i += nb) {
-        int32_t v = checked_node(Ls[2][i], g.n, c.ctrl);
-        if (v < 0 || (!FIRST && !needs_rescan(v, best, mate))) continue;   // block-uniform
-        Cand cd = scan_row<R, NT>(g, v, threadIdx.x, mate, c.ms.out, seed, FIRST);
+    const int2 *nrec = c.ms.nrec;
+    const uint32_t *out = c.ms.out;
+    for (int64_t i = bid; i < ri.cn[2]; i += nb) {
+        const int32_t v = checked_node(ri.in[2].v[i], g.n, c.ctrl);
+        if (v < 0 || (!FIRST && keeps_choice(ri.in[2].b[i], g.n, nrec))) continue;   // block-uniform
+        const uint32_t av = FIRST ? attr_src<R>(g, out, v) : (uint32_t)nrec[v].x;
+        Cand cd = scan_row<R, NT, FIRST>(g, v, av, threadIdx.x, nrec, out, seed);
         cd = block_reduce_cand(cd, v, sh);
-        if (threadIdx.x == 0) best[v] = cd.u;
+        if (threadIdx.x == 0) {
+            best[v] = cd.u;
+            ri.in[2].b[i] = cd.u;
+        }
     }
 }
 
-// Mutual check of round r; survivors to the round's output lists.
-template <bool FIRST>
+// Mutual check of round r; matched pairs written (mate and the node
+// record), survivors appended to the output lists (counters ocnt[3]).
+// Round 1 also writes every node's record {attribute, mate}.  A thread's MK
+// entries are loaded first, then their partners' choices, then stored.
+template <int R, bool FIRST>
 __device__ __forceinline__ void mate_phase(const Ctx &c, const DevGraph &g, LevelDesc *L, int r,
-                                           const int32_t cn[3], const int32_t *const Ls[3],
-                                           unsigned bid, unsigned nb, int64_t *sh, int32_t *sha) {
+                                           const RoundIn &ri, int32_t *ocnt, unsigned bid,
+                                           unsigned nb, int64_t *sh, int32_t *sbase) {
     MatchState *st = c.ms.state;
     int32_t *mate = L->mate;
     const int32_t *best = c.ms.best;
-    // round 1 checks every node once (cn[1], cn[2] only feed its pick phase)
-    const int64_t total = FIRST ? (int64_t)g.n : (int64_t)cn[0] + cn[1] + cn[2];
-    const int opar = r & 1, oslot = r & 3;
-    if (bid == 0 && threadIdx.x < 3) st->cnt[(r + 2) & 3][threadIdx.x] = 0;
-    int32_t *olists[3] = {list_ptr(c.ms.lists, g.n, opar, 0), list_ptr(c.ms.lists, g.n, opar, 1),
-                          list_ptr(c.ms.lists, g.n, opar, 2)};
-    int32_t *ocnt[3] = {&st->cnt[oslot][0], &st->cnt[oslot][1], &st->cnt[oslot][2]};
+    int2 *nrec = c.ms.nrec;
+    const uint32_t *out = c.ms.out;
+    const int32_t n = g.n, c0 = ri.cn[0], c1 = ri.cn[1];
+    const int64_t total = FIRST ? (int64_t)n : (int64_t)c0 + c1 + ri.cn[2];
+    const int opar = r & 1;
+    const PList ol[3] = {plist(c.ms, n, opar, 0), plist(c.ms, n, opar, 1), plist(c.ms, n, opar, 2)};
     int64_t point = 0, degs = 0, pairs = 0;
-    const int64_t stride = (int64_t)nb * blockDim.x;
-    const int64_t lim = (total + stride - 1) / stride * stride;   // block-uniform trips
-    for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < lim; i += stride) {
-        int bn = -1;
-        int32_t v = -1;
-        if (i < total) {
-            if (FIRST) v = (int32_t)i;
-            else if (i < cn[0]) v = Ls[0][i];
-            else if (i < (int64_t)cn[0] + cn[1]) v = Ls[1][i - cn[0]];
-            else v = Ls[2][i - cn[0] - cn[1]];
-            if (!FIRST) v = checked_node(v, g.n, c.ctrl);
-            int32_t b = v >= 0 ? best[v] : -1;
-            if (b >= (int32_t)g.n) b = checked_node(b, g.n, c.ctrl);
-            if (b >= 0) {
-                int64_t d = g.xadj[v + 1] - g.xadj[v];
-                ++point;
-                degs += d;
-                if (best[b] == v) {
-                    mate[v] = b;
-                    if (v < b) ++pairs;
-                } else {
-                    bn = bin_of(d);
-                }
+    bool bad = false;
+    // pass p, slot k of block b covers entries ((p * MK + k) * nb + b) * blockDim.x + t
+    const int64_t row = (int64_t)nb * blockDim.x, per_pass = row * MK;
+    for (int64_t base = 0; base < total; base += per_pass) {   // block-uniform
+        const int64_t first = base + (int64_t)bid * blockDim.x + threadIdx.x;
+        int bin[MK];
+        int32_t vv[MK], bb[MK], dd[MK], bq[MK];
+        uint32_t av[MK];
+        // 1. the entries: node, choice, degree (and the attribute in round 1)
+#pragma unroll
+        for (int k = 0; k < MK; ++k) {
+            const int64_t i = first + (int64_t)k * row;
+            vv[k] = -1;
+            bb[k] = -1;
+            dd[k] = 0;
+            av[k] = 0;
+            if (i >= total) continue;
+            if (FIRST) {
+                vv[k] = (int32_t)i;
+                bb[k] = best[i];
+                dd[k] = (int32_t)(g.xadj[i + 1] - g.xadj[i]);
+                av[k] = attr_src<R>(g, out, (int32_t)i);
+            } else {
+                PList src;
+                int64_t j;
+                if (i < c0) { src = ri.in[0]; j = i; }
+                else if (i < (int64_t)c0 + c1) { src = ri.in[1]; j = i - c0; }
+                else { src = ri.in[2]; j = i - c0 - c1; }
+                vv[k] = src.v[j];
+                bb[k] = src.b[j];
+                dd[k] = src.d[j];
             }
         }
-        block_append3(bn, v, olists, ocnt, sha);
+        // 2. range checks (valid state never fails them), partners' choices
+#pragma unroll
+        for (int k = 0; k < MK; ++k) {
+            if ((uint32_t)vv[k] >= (uint32_t)n) {
+                bad = bad || vv[k] != -1;
+                vv[k] = -1;
+            }
+            if (vv[k] < 0 || (uint32_t)bb[k] >= (uint32_t)n) {
+                bad = bad || (vv[k] >= 0 && bb[k] >= n);
+                bb[k] = -1;
+            }
+            bq[k] = bb[k] >= 0 ? best[bb[k]] : -2;
+        }
+        // 3. decide and store
+#pragma unroll
+        for (int k = 0; k < MK; ++k) {
+            bin[k] = -1;
+            const int32_t v = vv[k], b = bb[k];
+            if (v < 0) continue;
+            int32_t m = -1;
+            if (b >= 0) {
+                ++point;
+                degs += dd[k];
+                if (bq[k] == v) {
+                    m = b;
+                    if (v < b) ++pairs;
+                } else {
+                    bin[k] = bin_of(dd[k]);
+                }
+            }
+            if (FIRST) {
+                nrec[v] = make_int2((int32_t)av[k], m);
+                if (m >= 0) mate[v] = m;
+            } else if (m >= 0) {
+                mate[v] = m;
+                nrec[v].y = m;
+            }
+        }
+        block_append_mk(bin, vv, bb, dd, ol, ocnt, sh, sbase);
     }
-    point = block_sum(point, sh);
-    degs = block_sum(degs, sh);
-    pairs = block_sum(pairs, sh);
+    if (__ballot(bad) && lane_id() == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_STATE);
+    block_sum3(point, degs, pairs, sh);
     if (threadIdx.x == 0 && point > 0) {
-        const int ri = r - 1 < STAT_ROUNDS ? r - 1 : STAT_ROUNDS - 1, sd = shard_of_block();
-        atomicAdd((unsigned long long *)&st->sstat[ri][0][sd], (unsigned long long)point);
-        atomicAdd((unsigned long long *)&st->sstat[ri][1][sd], (unsigned long long)degs);
-        if (pairs) atomicAdd((unsigned long long *)&st->sstat[ri][2][sd], (unsigned long long)pairs);
+        const int ri_ = r - 1 < STAT_ROUNDS ? r - 1 : STAT_ROUNDS - 1, sd = shard_of_block();
+        atomicAdd((unsigned long long *)&st->sstat[ri_][0][sd], (unsigned long long)point);
+        atomicAdd((unsigned long long *)&st->sstat[ri_][1][sd], (unsigned long long)degs);
+        if (pairs) atomicAdd((unsigned long long *)&st->sstat[ri_][2][sd], (unsigned long long)pairs);
         atomicMax(&st->sround[sd], r);
     }
 }
@@ -327,7 +507,8 @@ __device__ __forceinline__ void mate_phase(const Ctx &c, const DevGraph &g, Leve
 // The list counters of round 1 are zero on entry (reset by the previous
 // level's finisher, or by the host before level 0).
 __global__ void __launch_bounds__(BLOCK) match_init_k(Ctx c, int l, int stop_rules) {
-    __shared__ int32_t sha[3 * (BLOCK / WAVE) + 3];
+    __shared__ int64_t sh[BLOCK / WAVE + 1];
+    __shared__ int32_t sbase[3];
     __shared__ int go;
     if (threadIdx.x == 0) go = level_gate(c, l, stop_rules != 0, blockIdx.x == 0);
     __syncthreads();
@@ -347,7 +528,7 @@ __global__ void __launch_bounds__(BLOCK) match_init_k(Ctx c, int l, int stop_rul
         int64_t *ss = &st->sstat[0][0][0];
         for (int i = t; i < STAT_ROUNDS * 3 * NSHARD; i += blockDim.x) ss[i] = 0;
     }
-    init_phase(c, g, L, blockIdx.x, gridDim.x, sha);
+    init_phase(c, g, L, sh, sbase);
 }
 
 struct PickGrid {
@@ -362,10 +543,9 @@ __global__ void __launch_bounds__(BLOCK) pick_k(Ctx c, int l, int r, PickGrid pg
     if (!load_level(L, PH_MATCH, g)) return;
     MatchState *st = c.ms.state;
     if (st->handoff != -1) return;
-    int32_t cn[3];
-    const int32_t *Ls[3];
-    int64_t total = round_inputs<FIRST>(c, g, r, cn, Ls);
+    const RoundIn ri = round_inputs<FIRST>(c, g, r, st->cnt[FIRST ? 0 : (r - 1) & 3]);
     if (!FIRST) {
+        const int64_t total = (int64_t)ri.cn[0] + ri.cn[1] + ri.cn[2];
         if (total == 0) {
             if (blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(&st->handoff, -1, -2);
             return;
@@ -377,41 +557,43 @@ __global__ void __launch_bounds__(BLOCK) pick_k(Ctx c, int l, int r, PickGrid pg
     }
     const uint64_t seed = level_seed(c, l);
     unsigned bid = blockIdx.x;
-    if (bid < pg.b0) { pick_bin0<R, FIRST>(c, g, L, seed, cn, Ls, bid, pg.b0); return; }
+    if (bid < pg.b0) { pick_bin0<R, FIRST>(c, g, seed, ri, bid, pg.b0); return; }
     bid -= pg.b0;
-    if (bid < pg.b1) { pick_bin1<R, FIRST>(c, g, L, seed, cn, Ls, bid, pg.b1); return; }
+    if (bid < pg.b1) { pick_bin1<R, FIRST>(c, g, seed, ri, bid, pg.b1); return; }
     bid -= pg.b1;
-    pick_bin2<R, FIRST, BLOCK>(c, g, L, seed, cn, Ls, bid, pg.b2, sh);
+    pick_bin2<R, FIRST, BLOCK>(c, g, seed, ri, bid, pg.b2, sh);
 }
 
-template <bool FIRST>
+template <int R, bool FIRST>
 __global__ void __launch_bounds__(BLOCK) mate_k(Ctx c, int l, int r) {
-    __shared__ int64_t sh[BLOCK / WAVE + 1];
-    __shared__ int32_t sha[3 * (BLOCK / WAVE) + 3];
+    __shared__ int64_t sh[3 * (BLOCK / WAVE) + 1];
+    __shared__ int32_t sbase[3];
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_MATCH, g)) return;
-    if (c.ms.state->handoff != -1) return;
-    int32_t cn[3];
-    const int32_t *Ls[3];
-    round_inputs<FIRST>(c, g, r, cn, Ls);
-    mate_phase<FIRST>(c, g, L, r, cn, Ls, blockIdx.x, gridDim.x, sh, sha);
+    MatchState *st = c.ms.state;
+    if (st->handoff != -1) return;
+    const RoundIn ri = round_inputs<FIRST>(c, g, r, st->cnt[FIRST ? 0 : (r - 1) & 3]);
+    // the counters of round r + 2 were last read by round r - 1
+    if (blockIdx.x == 0 && threadIdx.x < 3) st->cnt[(r + 2) & 3][threadIdx.x] = 0;
+    mate_phase<R, FIRST>(c, g, L, r, ri, st->cnt[r & 3], blockIdx.x, gridDim.x, sh, sbase);
 }
 
 // Finisher: one workgroup runs the remaining rounds (from the handoff point,
-// or after round r_last), then closes the level's matching.
+// or after round r_last) with workgroup barriers, then closes the level's
+// matching.
 template <int R>
 __global__ void __launch_bounds__(FINISH_THREADS) finish_k(Ctx c, int l, int r_last) {
     __shared__ Cand shc[FINISH_THREADS / WAVE];
+    __shared__ int64_t sh[3 * (FINISH_THREADS / WAVE) + 1];
     __shared__ int32_t s_cnt[2][3];
-    __shared__ int64_t s_acc[3];   // pointing, degsum, pairs of the current round
+    __shared__ int32_t sbase[3];
+    __shared__ int64_t s_acc[2];
     __shared__ int32_t s_r0;
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_MATCH, g)) return;
     MatchState *st = c.ms.state;
-    int32_t *mate = L->mate, *best = c.ms.best, *lists = c.ms.lists;
-    const uint32_t *out = c.ms.out;
     const uint64_t seed = level_seed(c, l);
     if (threadIdx.x == 0) {
         int h = st->handoff;
@@ -432,90 +614,18 @@ __global__ void __launch_bounds__(FINISH_THREADS) finish_k(Ctx c, int l, int r_l
         const int64_t r_cap = (int64_t)r0 + 2 + g.n;
         capped = true;
         for (int r = r0 + 1; r <= r_cap; ++r) {
-            int ip = (r - 1) & 1, op = r & 1;
-            int32_t c0 = min(s_cnt[ip][0], g.n), c1 = min(s_cnt[ip][1], g.n),
-                    c2 = min(s_cnt[ip][2], g.n);
-            if ((int64_t)c0 + c1 + c2 == 0) { capped = false; break; }
-            const int32_t *L0 = list_ptr(lists, g.n, ip, 0);
-            const int32_t *L1 = list_ptr(lists, g.n, ip, 1);
-            const int32_t *L2 = list_ptr(lists, g.n, ip, 2);
-            {
-                const int G = SMALL_G;
-                int sub = threadIdx.x & (G - 1);
-                int gi = threadIdx.x / G, gs = FINISH_THREADS / G;
-                int lim = (c0 + gs - 1) / gs * gs;
-                for (int i = gi; i < lim; i += gs) {
-                    int32_t v = i < c0 ? checked_node(L0[i], g.n, c.ctrl) : -1;
-                    bool act = v >= 0 && needs_rescan(v, best, mate);
-                    Cand cd = act ? scan_row<R, G>(g, v, sub, mate, out, seed, false) : cand_none();
-                    cd = group_reduce<G>(cd, v);
-                    if (act && sub == 0) best[v] = cd.u;
-                }
-                int wi = threadIdx.x / WAVE, ws = FINISH_THREADS / WAVE;
-                for (int i = wi; i < c1; i += ws) {
-                    int32_t v = checked_node(L1[i], g.n, c.ctrl);
-                    if (v < 0 || !needs_rescan(v, best, mate)) continue;
-                    Cand cd = scan_row<R, WAVE>(g, v, lane_id(), mate, out, seed, false);
-                    cd = group_reduce<WAVE>(cd, v);
-                    if (lane_id() == 0) best[v] = cd.u;
-                }
+            const RoundIn ri = round_inputs<false>(c, g, r, s_cnt[(r - 1) & 1]);
+            if ((int64_t)ri.cn[0] + ri.cn[1] + ri.cn[2] == 0) {
+                capped = false;
+                break;
             }
+            pick_bin0<R, false>(c, g, seed, ri, 0, 1);
+            pick_bin1<R, false>(c, g, seed, ri, 0, 1);
             __syncthreads();
-            for (int i = 0; i < c2; ++i) {
-                int32_t v = checked_node(L2[i], g.n, c.ctrl);
-                if (v < 0 || !needs_rescan(v, best, mate)) continue;   // block-uniform
-                Cand cd = scan_row<R, FINISH_THREADS>(g, v, threadIdx.x, mate, out, seed, false);
-                cd = block_reduce_cand(cd, v, shc);
-                if (threadIdx.x == 0) best[v] = cd.u;
-            }
-            if (threadIdx.x < 3) { s_acc[threadIdx.x] = 0; s_cnt[op][threadIdx.x] = 0; }
+            pick_bin2<R, false, FINISH_THREADS>(c, g, seed, ri, 0, 1, shc);
+            if (threadIdx.x < 3) s_cnt[r & 1][threadIdx.x] = 0;
             __syncthreads();
-            int32_t total = c0 + c1 + c2;
-            int64_t point = 0, degs = 0, pairs = 0;
-            int lim = (total + FINISH_THREADS - 1) / FINISH_THREADS * FINISH_THREADS;
-            for (int i = threadIdx.x; i < lim; i += FINISH_THREADS) {
-                bool keep = false;
-                int bn = 0;
-                int32_t v = -1;
-                if (i < total) {
-                    v = i < c0 ? L0[i] : (i < c0 + c1 ? L1[i - c0] : L2[i - c0 - c1]);
-                    v = checked_node(v, g.n, c.ctrl);
-                    int32_t b = v >= 0 ? best[v] : -1;
-                    if (b >= (int32_t)g.n) b = checked_node(b, g.n, c.ctrl);
-                    if (b >= 0) {
-                        int64_t d = g.xadj[v + 1] - g.xadj[v];
-                        ++point;
-                        degs += d;
-                        if (best[b] == v) {
-                            mate[v] = b;
-                            if (v < b) ++pairs;
-                        } else {
-                            keep = true;
-                            bn = bin_of(d);
-                        }
-                    }
-                }
-                wave_append(keep && bn == 0, v, list_ptr(lists, g.n, op, 0), &s_cnt[op][0]);
-                wave_append(keep && bn == 1, v, list_ptr(lists, g.n, op, 1), &s_cnt[op][1]);
-                wave_append(keep && bn == 2, v, list_ptr(lists, g.n, op, 2), &s_cnt[op][2]);
-            }
-            point = wave_sum(point);
-            degs = wave_sum(degs);
-            pairs = wave_sum(pairs);
-            if (lane_id() == 0) {
-                if (point) atomicAdd((unsigned long long *)&s_acc[0], (unsigned long long)point);
-                if (degs) atomicAdd((unsigned long long *)&s_acc[1], (unsigned long long)degs);
-                if (pairs) atomicAdd((unsigned long long *)&s_acc[2], (unsigned long long)pairs);
-            }
-            __syncthreads();
-            if (threadIdx.x == 0 && s_acc[0] > 0) {
-                // this block is alone now: shard 0 takes the round's statistics
-                const int ri = r - 1 < STAT_ROUNDS ? r - 1 : STAT_ROUNDS - 1;
-                st->sstat[ri][0][0] += s_acc[0];
-                st->sstat[ri][1][0] += s_acc[1];
-                st->sstat[ri][2][0] += s_acc[2];
-                st->sround[0] = r > st->sround[0] ? r : st->sround[0];
-            }
+            mate_phase<R, false>(c, g, L, r, ri, s_cnt[r & 1], 0, 1, sh, sbase);
             __syncthreads();
         }
     }
@@ -1005,7 +1115,7 @@ static void match_impl(const Ctx &c, int l, int32_t n_hint, int rounds, hipStrea
         pg.b1 = grid_for(e, BLOCK / WAVE * 8, 128);
         pg.b2 = grid_for(e, 4096, 64);
         const unsigned pick_blocks = pg.b0 + pg.b1 + pg.b2;
-        const unsigned mate_blocks = grid_for(e, BLOCK * 2, 2048);
+        const unsigned mate_blocks = grid_for(e, BLOCK, 2048);
         if (r == 1) {
             {
                 KAPPA_PROF("pick_first", s);
@@ -1013,7 +1123,7 @@ static void match_impl(const Ctx &c, int l, int32_t n_hint, int rounds, hipStrea
                                    pg);
             }
             KAPPA_PROF("mate_first", s);
-            hipLaunchKernelGGL(mate_k<true>, dim3(mate_blocks), dim3(BLOCK), 0, s, c, l, r);
+            hipLaunchKernelGGL((mate_k<R, true>), dim3(mate_blocks), dim3(BLOCK), 0, s, c, l, r);
         } else {
             {
                 KAPPA_PROF("pick", s);
@@ -1021,7 +1131,7 @@ static void match_impl(const Ctx &c, int l, int32_t n_hint, int rounds, hipStrea
                                    pg);
             }
             KAPPA_PROF("mate", s);
-            hipLaunchKernelGGL(mate_k<false>, dim3(mate_blocks), dim3(BLOCK), 0, s, c, l, r);
+            hipLaunchKernelGGL((mate_k<R, false>), dim3(mate_blocks), dim3(BLOCK), 0, s, c, l, r);
         }
     }
     KAPPA_PROF("match_finish", s);
@@ -1033,7 +1143,7 @@ void launch_level_match(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, in
     if (rounds < 1) rounds = 1;
     {
         KAPPA_PROF("match_init", s);
-        hipLaunchKernelGGL(match_init_k, dim3(grid_for(n_hint, BLOCK * 2, 2048)), dim3(BLOCK), 0, s,
+        hipLaunchKernelGGL(match_init_k, dim3(grid_for(n_hint, BLOCK, 2048)), dim3(BLOCK), 0, s,
                            c, l, stop_rules ? 1 : 0);
     }
     if (c.rating == KAPPA_INNER_OUTER && out_kernels) launch_level_out(c, l, nnz_cap, n_hint, s);

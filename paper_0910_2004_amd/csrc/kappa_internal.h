@@ -15,9 +15,9 @@ constexpr int SCAN_ITEMS = 8;       // items per thread in the scan tiles
 constexpr int SCAN_TILE = BLOCK * SCAN_ITEMS;
 
 // Degree classes of the node-centric kernels.
-constexpr int BIN_SMALL_MAX = 16;   // deg <= 16: 8 lanes per node
+constexpr int BIN_SMALL_MAX = 16;   // deg <= 16: SMALL_G lanes per node
 constexpr int BIN_MID_MAX = 1024;   // deg <= 1024: one wave per node; above: one block
-constexpr int SMALL_G = 8;
+constexpr int SMALL_G = 4;
 
 // Matching rounds: a single workgroup finishes once at most TAIL_MAX nodes
 // still point somewhere.
@@ -203,6 +203,30 @@ __device__ __forceinline__ bool arrive_last(unsigned *cnt) {
     if (old != ng - 1) return false;
     __hip_atomic_store(&cnt[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return true;
+}
+
+// Block sums of three per-thread values, valid in thread 0 (two barriers).
+// sh: 3 * (blockDim.x / WAVE) entries.
+__device__ __forceinline__ void block_sum3(int64_t &a, int64_t &b, int64_t &c, int64_t *sh) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    const int w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    __syncthreads();   // sh may still be read by a previous use
+    if (lane_id() == 0) {
+        sh[w] = a;
+        sh[nw + w] = b;
+        sh[2 * nw + w] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = b = c = 0;
+        for (int i = 0; i < nw; ++i) {
+            a += sh[i];
+            b += sh[nw + i];
+            c += sh[2 * nw + i];
+        }
+    }
 }
 
 template <class T>
@@ -404,8 +428,9 @@ struct MatchState {
     int64_t sstat[STAT_ROUNDS][3][NSHARD];  // per round and shard: pointing nodes, their degree sum, pairs
 };
 struct MatchScratch {
-    int32_t *best;          // n
-    int32_t *lists;         // 6n: pending lists [parity][bin]
+    int32_t *best;          // n: current choice of every node (-1: none)
+    int32_t *lv, *lb, *ld;  // 6n each: pending lists [parity][bin] (node, choice, degree)
+    int2 *nrec;             // n: {rating attribute c(v) or Out(v), mate} per node
     uint32_t *out;          // n (innerOuter)
     int32_t *tile_row;      // tile rows of the level (innerOuter)
     MatchState *state;
