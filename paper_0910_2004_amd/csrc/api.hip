@@ -476,6 +476,8 @@ void carve_scratch(Carve &cv, const DevGraph &g, int rating, bool hubs, Ctx &c) 
 void fill_scratch(const DevGraph &g, const Ctx &c, hipStream_t s) {
     launch_fill_u32(c.cs.arrive, ARRIVE_WORDS, 0, s);
     launch_fill_u32((uint32_t *)&c.ms.state->cnt[0][0], 16, 0, s);   // round-1 list counters
+    launch_fill_u32((uint32_t *)&c.ms.state->sround[0], NSHARD, 0, s);
+    launch_fill_u64((uint64_t *)&c.ms.state->sstat[0][0][0], (int64_t)STAT_ROUNDS * 3 * NSHARD, 0, s);
     if (c.cs.hub_acc) {
         launch_fill_u32(c.cs.hub_acc, (int64_t)HUB_SLOTS * g.n, 0, s);
         launch_fill_u32(c.cs.hub_bits, (int64_t)HUB_SLOTS * c.cs.hub_words, 0, s);

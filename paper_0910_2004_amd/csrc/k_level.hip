@@ -504,8 +504,8 @@ __device__ __forceinline__ void mate_phase(const Ctx &c, const DevGraph &g, Leve
 // --- per-round kernels -----------------------------------------------------
 // The level's first kernel: gate, then mate = best = -1 and the round-1
 // lists.  Block 0 also resets the matching state (read by later kernels).
-// The list counters of round 1 are zero on entry (reset by the previous
-// level's finisher, or by the host before level 0).
+// The list counters and round statistics are zero on entry (reset by the
+// previous level's finisher, or by the host before level 0).
 __global__ void __launch_bounds__(BLOCK) match_init_k(Ctx c, int l, int stop_rules) {
     __shared__ int64_t sh[BLOCK / WAVE + 1];
     __shared__ int32_t sbase[3];
@@ -516,17 +516,12 @@ __global__ void __launch_bounds__(BLOCK) match_init_k(Ctx c, int l, int stop_rul
     LevelDesc *L = c.lv + l;
     DevGraph g;
     g.n = L->n; g.nnz = L->nnz; g.xadj = L->xadj; g.adj = L->adj; g.ew = L->ew; g.vw = L->vw;
-    if (blockIdx.x == 0) {
-        MatchState *st = c.ms.state;
-        const int t = threadIdx.x;
-        if (t == 0) {
-            st->handoff = -1;
-            L->matched = 0;
-            L->rounds = 0;
-        }
-        for (int i = t; i < NSHARD; i += blockDim.x) st->sround[i] = 0;
-        int64_t *ss = &st->sstat[0][0][0];
-        for (int i = t; i < STAT_ROUNDS * 3 * NSHARD; i += blockDim.x) ss[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // the round statistics are zero on entry (the previous level's
+        // finisher, or the host before level 0, cleared them)
+        c.ms.state->handoff = -1;
+        L->matched = 0;
+        L->rounds = 0;
     }
     init_phase(c, g, L, sh, sbase);
 }
@@ -629,23 +624,30 @@ __global__ void __launch_bounds__(FINISH_THREADS) finish_k(Ctx c, int l, int r_l
             __syncthreads();
         }
     }
-    // close the level's matching: sum the shards (one wave per statistic)
+    // close the level's matching: sum the shards of the rounds used (one wave
+    // per statistic) and leave them zero for the next level
     __syncthreads();
-    if (threadIdx.x < 2) s_acc[threadIdx.x] = 0;
+    if (threadIdx.x < WAVE) {
+        const int32_t rr = wave_max(st->sround[lane_id()]);
+        st->sround[lane_id()] = 0;
+        if (lane_id() == 0) {
+            s_acc[0] = 0;
+            s_acc[1] = rr;
+        }
+    }
     __syncthreads();
     {
         const int w = threadIdx.x / WAVE, nw = FINISH_THREADS / WAVE;
-        for (int q = w; q < STAT_ROUNDS * 3; q += nw) {
+        const int slots = (int)min<int64_t>(s_acc[1], STAT_ROUNDS);
+        for (int q = w; q < slots * 3; q += nw) {
             const int i = q / 3, f = q % 3;
-            int64_t v = wave_sum(st->sstat[i][f][lane_id()]);
+            int64_t *p = &st->sstat[i][f][lane_id()];
+            const int64_t v = wave_sum(*p);
+            *p = 0;
             if (lane_id() == 0) {
                 if (f < 2) L->stat[i][f] = v;
                 else if (v) atomicAdd((unsigned long long *)&s_acc[0], (unsigned long long)v);
             }
-        }
-        if (w == nw - 1) {
-            int32_t rr = wave_max(st->sround[lane_id()]);
-            if (lane_id() == 0) s_acc[1] = rr;
         }
     }
     if (threadIdx.x < 4) {
@@ -712,19 +714,35 @@ struct RepF {
 struct RepW {
     Ctx c;
     int l;
-    __device__ void operator()(int64_t i, int64_t pre, int64_t v) const {
-        if (!v) return;
-        const LevelDesc *L = c.lv + l;
-        const int32_t x = (int32_t)pre, w = L->mate[i];
-        uint32_t cw = L->vw[i];
-        L->cmap[i] = x;
-        if (w >= 0) {
-            L->cmap[w] = x;
-            cw += L->vw[w];
+    struct Pre {
+        int32_t w;
+        uint32_t cw;
+    };
+    struct Bound {
+        const int32_t *mate;
+        const uint32_t *vw;
+        int32_t *cmap, *rep_of, *partner;
+        uint32_t *cvw;
+        __device__ Pre prefetch(int64_t i, int64_t v) const {
+            Pre p{-1, 0u};
+            if (!v) return p;
+            p.w = mate[i];
+            p.cw = vw[i] + (p.w >= 0 ? vw[p.w] : 0u);
+            return p;
         }
-        c.cs.rep_of[x] = (int32_t)i;
-        c.cs.partner[x] = w;
-        c.lv[l + 1].vw[x] = cw;
+        __device__ void operator()(int64_t i, int64_t pre, int64_t v, const Pre &p) const {
+            if (!v) return;
+            const int32_t x = (int32_t)pre;
+            cmap[i] = x;
+            if (p.w >= 0) cmap[p.w] = x;
+            rep_of[x] = (int32_t)i;
+            partner[x] = p.w;
+            cvw[x] = p.cw;
+        }
+    };
+    __device__ Bound bind() const {
+        const LevelDesc *L = c.lv + l;
+        return Bound{L->mate, L->vw, L->cmap, c.cs.rep_of, c.cs.partner, c.lv[l + 1].vw};
     }
 };
 
@@ -773,7 +791,13 @@ struct DegF {
 struct CoarseOffW {
     Ctx c;
     int l;
-    __device__ void operator()(int64_t i, int64_t pre, int64_t) const { c.lv[l + 1].xadj[i] = pre; }
+    struct Pre {};
+    struct Bound {
+        int64_t *xadj;
+        __device__ Pre prefetch(int64_t, int64_t) const { return Pre{}; }
+        __device__ void operator()(int64_t i, int64_t pre, int64_t, const Pre &) const { xadj[i] = pre; }
+    };
+    __device__ Bound bind() const { return Bound{c.lv[l + 1].xadj}; }
 };
 
 // The fine entries of coarse row x: row u, then row w (partner), each

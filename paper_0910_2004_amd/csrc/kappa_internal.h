@@ -268,7 +268,10 @@ __device__ __forceinline__ void block_append3(int bin, int32_t val, int32_t *con
 // Generic exclusive scan with a device-side length, two kernels.
 // F: size() -> int64 (< 0: skip the whole scan), operator()(i) -> int64
 // value, post(total) run by one thread once the total is known (before the
-// apply kernel starts).  W: operator()(i, prefix, value).
+// apply kernel starts).  W: bind() -> B, called after post(), holding the
+// output pointers; B::prefetch(i, value) -> B::Pre loads what the store
+// needs; B::operator()(i, prefix, value, pre) stores.  A thread prefetches
+// all of its items before it stores any, so their loads overlap.
 //   reduce: tile sums; the last block to finish scans the tile sums in place,
 //           writes the total and runs post()
 //   apply:  rescan of each tile from its tile prefix
@@ -322,23 +325,106 @@ __global__ void __launch_bounds__(BLOCK) scan_apply_k(F f, W w, const int64_t *w
     if (n <= 0) return;
     const int64_t *partials = ws;
     const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    const auto wb = w.bind();
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         // each thread owns SCAN_ITEMS consecutive items
         int64_t first = t * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
         int64_t vals[SCAN_ITEMS];
         int64_t s = 0;
+#pragma unroll
         for (int i = 0; i < SCAN_ITEMS; ++i) {
             int64_t idx = first + i;
             vals[i] = idx < n ? f(idx) : 0;
             s += vals[i];
         }
+        typename W::Pre pf[SCAN_ITEMS];
+#pragma unroll
+        for (int i = 0; i < SCAN_ITEMS; ++i)
+            if (first + i < n) pf[i] = wb.prefetch(first + i, vals[i]);
         int64_t tot;
         int64_t pre = block_excl_scan(s, sh, &tot) + partials[t];
+#pragma unroll
         for (int i = 0; i < SCAN_ITEMS; ++i) {
             int64_t idx = first + i;
-            if (idx < n) w(idx, pre, vals[i]);
+            if (idx < n) wb(idx, pre, vals[i], pf[i]);
             pre += vals[i];
         }
+    }
+}
+
+// The same scan in one workgroup, for short inputs (no second launch, no
+// arrival counter): items held in registers when n <= ONE_SCAN_CHUNK, else
+// a reduction pass, post(), then chunked scan-and-apply passes.  post()
+// runs (thread 0) before any apply, as in the two-kernel form.
+constexpr int ONE_SCAN_THREADS = 1024, ONE_SCAN_ITEMS = 16;
+constexpr int64_t ONE_SCAN_CHUNK = (int64_t)ONE_SCAN_THREADS * ONE_SCAN_ITEMS;
+
+template <class F, class W>
+__global__ void __launch_bounds__(ONE_SCAN_THREADS) scan_one_block_k(F f, W w, int64_t *total) {
+    __shared__ int64_t sh[ONE_SCAN_THREADS / WAVE + 1];
+    const int64_t n = f.size();
+    if (n < 0) return;
+    const int64_t first = (int64_t)threadIdx.x * ONE_SCAN_ITEMS;
+    if (n <= ONE_SCAN_CHUNK) {
+        int64_t vals[ONE_SCAN_ITEMS];
+        int64_t s = 0;
+#pragma unroll
+        for (int i = 0; i < ONE_SCAN_ITEMS; ++i) {
+            vals[i] = first + i < n ? f(first + i) : 0;
+            s += vals[i];
+        }
+        int64_t tot;
+        int64_t pre = block_excl_scan(s, sh, &tot);
+        if (threadIdx.x == 0) {
+            if (total) *total = tot;
+            f.post(tot);
+        }
+        __syncthreads();
+        const auto wb = w.bind();
+        typename W::Pre pf[ONE_SCAN_ITEMS];
+#pragma unroll
+        for (int i = 0; i < ONE_SCAN_ITEMS; ++i)
+            if (first + i < n) pf[i] = wb.prefetch(first + i, vals[i]);
+#pragma unroll
+        for (int i = 0; i < ONE_SCAN_ITEMS; ++i) {
+            if (first + i < n) wb(first + i, pre, vals[i], pf[i]);
+            pre += vals[i];
+        }
+        return;
+    }
+    int64_t s = 0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += f(i);
+    int64_t tot;
+    block_excl_scan(s, sh, &tot);
+    if (threadIdx.x == 0) {
+        if (total) *total = tot;
+        f.post(tot);
+    }
+    __syncthreads();
+    const auto wb = w.bind();
+    int64_t run = 0;
+    for (int64_t base = 0; base < n; base += ONE_SCAN_CHUNK) {
+        int64_t vals[ONE_SCAN_ITEMS];
+        typename W::Pre pf[ONE_SCAN_ITEMS];
+        int64_t t = 0;
+#pragma unroll
+        for (int i = 0; i < ONE_SCAN_ITEMS; ++i) {
+            const int64_t idx = base + first + i;
+            vals[i] = idx < n ? f(idx) : 0;
+            t += vals[i];
+        }
+#pragma unroll
+        for (int i = 0; i < ONE_SCAN_ITEMS; ++i)
+            if (base + first + i < n) pf[i] = wb.prefetch(base + first + i, vals[i]);
+        int64_t ctot;
+        int64_t pre = block_excl_scan(t, sh, &ctot) + run;
+#pragma unroll
+        for (int i = 0; i < ONE_SCAN_ITEMS; ++i) {
+            const int64_t idx = base + first + i;
+            if (idx < n) wb(idx, pre, vals[i], pf[i]);
+            pre += vals[i];
+        }
+        run += ctot;
     }
 }
 
@@ -367,6 +453,12 @@ struct ProfScope {
 template <class F, class W>
 inline void launch_scan(int64_t n_hint, F f, W w, int64_t *ws, unsigned *arr, int64_t *total,
                         hipStream_t s) {
+    if (n_hint <= 2 * ONE_SCAN_CHUNK) {   // any n is correct; short ones are fast
+        KAPPA_PROF("scan_one_block", s);
+        hipLaunchKernelGGL((scan_one_block_k<F, W>), dim3(1), dim3(ONE_SCAN_THREADS), 0, s, f, w,
+                           total);
+        return;
+    }
     unsigned tiles = grid_for(n_hint, SCAN_TILE, 2048);
     {
         KAPPA_PROF("scan_reduce", s);
