@@ -965,29 +965,29 @@ extern "C" kappa_status kappa_cut_balance(const kappa_graph *g, const int32_t *p
     if (g->n > 0 && !part) return KAPPA_E_ARG;
     hipStream_t s = S(stream);
     DevGraph d = dev(g);
-    uint64_t *bw = nullptr, *acc = nullptr;
-    uint32_t *flag = nullptr;
+    UpAcc a;
     kappa_cut_result *rd = nullptr;
     int32_t *tr = nullptr;
     std::unique_ptr<Workspace> w;
     if (!carve_workspace(s, w, [&](Carve &cv) {
-            bw = block_w ? block_w : cv.get<uint64_t>(k);
-            acc = cv.get<uint64_t>(3 * NSHARD);
-            flag = cv.get<uint32_t>(1);
+            a.bw = cv.get<uint64_t>((int64_t)BW_SHARDS * k);
+            a.acc = cv.get<uint64_t>(3 * NSHARD);
+            a.arrive = cv.get<unsigned>(ARRIVE_WORDS);
+            a.flag = cv.get<uint32_t>(1);
             rd = cv.get<kappa_cut_result>(1);
             tr = cv.get<int32_t>(tile_rows_needed(d.nnz));
         }))
         return KAPPA_E_NOMEM;
-    launch_fill_u32(flag, 1, 0, s);
-    launch_tile_rows(d, tr, s);
-    launch_cut_balance(d, tr, part, k, eps_num, eps_den, bw, acc, flag, rd, s);
+    launch_up_clear(a, k, s);
+    launch_up_level(d, UP_GIVEN, nullptr, 0, nullptr, 0, const_cast<int32_t *>(part), k, eps_num,
+                    eps_den, tr, a, block_w, rd, s);
     struct RB {
         kappa_cut_result r;
         uint32_t f;
     };
     RB *rb = (RB *)pinned(sizeof(RB));
     HIPCHK(hipMemcpyAsync(&rb->r, rd, sizeof(kappa_cut_result), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&rb->f, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&rb->f, a.flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (rb->f) return KAPPA_E_RANGE;
     *out = rb->r;
@@ -1003,16 +1003,16 @@ extern "C" kappa_status kappa_uncoarsen(const kappa_hierarchy *h, int32_t k, uin
     const int32_t nl = (int32_t)h->levels.size();
     std::vector<int32_t *> part(nl, nullptr);
     kappa_cut_result *rd = nullptr;
-    uint64_t *bw = nullptr, *acc = nullptr;
-    uint32_t *flag = nullptr;
+    UpAcc a;
     int32_t *tr = nullptr;
     std::unique_ptr<Workspace> w;
     if (!carve_workspace(s, w, [&](Carve &cv) {
             for (int32_t l = 1; l < nl; ++l) part[l] = cv.get<int32_t>(h->levels[l].n);
             rd = cv.get<kappa_cut_result>(nl);
-            bw = cv.get<uint64_t>(k);
-            acc = cv.get<uint64_t>(3 * NSHARD);
-            flag = cv.get<uint32_t>(1);
+            a.bw = cv.get<uint64_t>((int64_t)BW_SHARDS * k);
+            a.acc = cv.get<uint64_t>(3 * NSHARD);
+            a.arrive = cv.get<unsigned>(ARRIVE_WORDS);
+            a.flag = cv.get<uint32_t>(1);
             tr = cv.get<int32_t>(tile_rows_needed(h->levels[0].nnz));
         }))
         return KAPPA_E_NOMEM;
@@ -1030,22 +1030,23 @@ extern "C" kappa_status kappa_uncoarsen(const kappa_hierarchy *h, int32_t k, uin
         key.push_back(pkey(lv.cmap));
     }
     HIPCHK(run_seq(w->c, s, key, [&](hipStream_t q) {
-        launch_fill_u32(flag, 1, 0, q);
-        launch_initial_partition(h->levels[L].n, k, part_seed, part[L], q);
+        launch_up_clear(a, k, q);
         for (int32_t l = L; l >= 0; --l) {
             const kappa_level &lv = h->levels[l];
-            if (l < L)
-                launch_project(lv.cmap, lv.n, h->levels[l + 1].n, part[l + 1], part[l], flag, q);
             DevGraph d;
             d.n = lv.n; d.nnz = lv.nnz; d.xadj = lv.xadj; d.adj = lv.adj; d.ew = lv.ew; d.vw = lv.vw;
-            launch_tile_rows(d, tr, q);
-            launch_cut_balance(d, tr, part[l], k, eps_num, eps_den, bw, acc, flag, rd + l, q);
+            if (l == L)
+                launch_up_level(d, UP_INITIAL, nullptr, 0, nullptr, part_seed, part[l], k, eps_num,
+                                eps_den, tr, a, nullptr, rd + l, q);
+            else
+                launch_up_level(d, UP_PROJECT, lv.cmap, h->levels[l + 1].n, part[l + 1], 0, part[l],
+                                k, eps_num, eps_den, tr, a, nullptr, rd + l, q);
         }
     }));
     uint32_t *hf = (uint32_t *)pinned(sizeof(kappa_cut_result) * nl + 8, PIN_RESULTS);
     if (!hf) return KAPPA_E_ARG;
     kappa_cut_result *hr = (kappa_cut_result *)((char *)hf + 8);
-    HIPCHK(hipMemcpyAsync(hf, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hf, a.flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(hr, rd, sizeof(kappa_cut_result) * nl, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (*hf) return KAPPA_E_RANGE;

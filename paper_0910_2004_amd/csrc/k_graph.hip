@@ -434,39 +434,72 @@ void launch_project(const int32_t *cmap, int32_t n_fine, int32_t n_coarse,
 }
 
 // ---------------------------------------------------------------------------
-// Cut and balance (Section 2; imbalance of Section 5.2).
-// acc[3][NSHARD], summed over shards: [0] = cut, [1] = c(V), [2] = max_v c(v)
-// (maximum over shards).
+// One level of the way back up (Section 2: uncontraction, then cut and
+// balance; imbalance of Section 5.2), two kernels.
+//   up_nodes:   the level's partition (projected through cmap, or the
+//               stand-in initial partition, or given), block weights in an
+//               LDS histogram, c(V) and max c(v), the entry tiles' rows
+//   up_entries: the cut over entry tiles; the last block to finish sums the
+//               shards, writes the result and clears the accumulators for
+//               the next level
+// Accumulators (zero on entry, zero again on exit): bw[BW_SHARDS][k],
+// acc[3][NSHARD] (cut, c(V), max c(v)), arrive[ARRIVE_WORDS].
+// flag bit 0: a map entry out of range; bit 1: a block id out of range.
 // ---------------------------------------------------------------------------
-constexpr int CUT_NODE_BLOCKS = 256;
+constexpr int UP_NODE_BLOCKS = 512;
 
-__global__ void __launch_bounds__(BLOCK) cut_nodes_k(DevGraph g, const int32_t *part, int32_t k,
-                                                     uint64_t *block_w, uint64_t *acc,
-                                                     uint32_t *flag) {
+__global__ void __launch_bounds__(BLOCK) up_nodes_k(DevGraph g, int mode, const int32_t *cmap,
+                                                    int32_t n_coarse, const int32_t *part_c,
+                                                    uint64_t part_seed, int32_t *part, int32_t k,
+                                                    int32_t *tile_row, uint64_t *bw, uint64_t *acc,
+                                                    uint32_t *flag) {
     extern __shared__ uint64_t s_hist[];   // k entries
     __shared__ uint64_t sh[BLOCK / WAVE + 1];
     __shared__ uint32_t shm[BLOCK / WAVE];
     for (int i = threadIdx.x; i < k; i += blockDim.x) s_hist[i] = 0;
     __syncthreads();
+    const int64_t ntiles = etiles(g.nnz);
     uint64_t tot = 0;
-    uint32_t mx = 0;
-    bool bad = false;
+    uint32_t mx = 0, bad = 0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n;
          v += (int64_t)gridDim.x * blockDim.x) {
-        int32_t p = part[v];
-        uint32_t c = g.vw[v];
-        if (p < 0 || p >= k) { bad = true; continue; }
-        if (c) atomicAdd((unsigned long long *)&s_hist[p], (unsigned long long)c);
+        int32_t p;
+        if (mode == UP_PROJECT) {
+            const int32_t cx = cmap[v];
+            if (cx < 0 || cx >= n_coarse) {
+                p = -1;
+                bad |= 1u;
+            } else {
+                p = part_c[cx];
+            }
+            part[v] = p;
+        } else if (mode == UP_INITIAL) {
+            p = (int32_t)(mix64(part_seed + (uint64_t)v) % (uint64_t)k);
+            part[v] = p;
+        } else {
+            p = part[v];
+        }
+        const uint32_t c = g.vw[v];
+        if (p < 0 || p >= k) {
+            bad |= 2u;
+        } else if (c) {
+            atomicAdd((unsigned long long *)&s_hist[p], (unsigned long long)c);
+        }
         tot += c;
         mx = c > mx ? c : mx;
+        const int64_t b = g.xadj[v], e = g.xadj[v + 1];
+        for (int64_t t = (b + ETILE - 1) / ETILE; t * ETILE < e && t < ntiles; ++t)
+            tile_row[t] = (int32_t)v;
     }
     __syncthreads();
+    uint64_t *bws = bw + (int64_t)(blockIdx.x % BW_SHARDS) * k;
     for (int i = threadIdx.x; i < k; i += blockDim.x)
-        if (s_hist[i]) atomicAdd((unsigned long long *)&block_w[i], (unsigned long long)s_hist[i]);
+        if (s_hist[i]) atomicAdd((unsigned long long *)&bws[i], (unsigned long long)s_hist[i]);
     tot = block_sum(tot, sh);
     mx = wave_max(mx);
     if (lane_id() == 0) shm[threadIdx.x / WAVE] = mx;
-    bool wbad = __ballot(bad) != 0;
+    for (int o = WAVE / 2; o > 0; o >>= 1) bad |= __shfl_xor(bad, o, WAVE);
+    if (bad && lane_id() == 0) atomicOr(flag, bad);
     __syncthreads();
     if (threadIdx.x == 0) {
         const int sd = shard_of_block();
@@ -474,90 +507,121 @@ __global__ void __launch_bounds__(BLOCK) cut_nodes_k(DevGraph g, const int32_t *
         if (tot) atomicAdd((unsigned long long *)&acc[1 * NSHARD + sd], (unsigned long long)tot);
         if (mx) atomicMax((unsigned long long *)&acc[2 * NSHARD + sd], (unsigned long long)mx);
     }
-    if (wbad && lane_id() == 0) atomicOr(flag, 2u);
-}
-
-__global__ void __launch_bounds__(BLOCK) cut_entries_k(DevGraph g, const int32_t *tile_row,
-                                                       const int32_t *part, uint64_t *acc) {
-    __shared__ int64_t s_off[ETILE_ROWS + 1];
-    __shared__ uint64_t sh[BLOCK / WAVE + 1];
-    const int64_t ntiles = etiles(g.nnz);
-    uint64_t cut = 0;
-    for (int64_t tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
-        TileCtx t = tile_begin(g, tile_row, tt, s_off);
-        for (int i = 0; i < ETILE_ITEMS; ++i) {
-            int64_t j = t.j0 + (int64_t)i * BLOCK + threadIdx.x;
-            if (j >= t.j1) break;
-            int32_t v = tile_row_of(g, t, s_off, j);
-            int32_t u = g.adj[j];
-            if (u > v && part[u] != part[v]) cut += g.ew[j];
-        }
-    }
-    cut = block_sum(cut, sh);
-    if (threadIdx.x == 0 && cut)
-        atomicAdd((unsigned long long *)&acc[shard_of_block()], (unsigned long long)cut);
 }
 
 typedef unsigned __int128 u128;
 
-__global__ void __launch_bounds__(BLOCK) cut_finalize_k(const uint64_t *block_w, int32_t k,
-                                                        uint32_t eps_num, uint32_t eps_den,
-                                                        const uint64_t *acc,
-                                                        kappa_cut_result *res) {
-    __shared__ uint64_t sh[BLOCK / WAVE];
+__global__ void __launch_bounds__(BLOCK) up_entries_k(DevGraph g, const int32_t *tile_row,
+                                                      const int32_t *part, int32_t k,
+                                                      uint32_t eps_num, uint32_t eps_den,
+                                                      uint64_t *bw, uint64_t *acc, unsigned *arrive,
+                                                      uint64_t *block_w_out,
+                                                      kappa_cut_result *res) {
+    __shared__ int64_t s_off[ETILE_ROWS + 1];
+    __shared__ uint64_t sh[BLOCK / WAVE + 1];
     __shared__ uint64_t s_acc[3];
+    __shared__ int last;
     static_assert(BLOCK / WAVE >= 3 && NSHARD == WAVE, "one wave per sharded accumulator");
-    uint64_t mx = 0;
-    for (int i = threadIdx.x; i < k; i += blockDim.x) mx = block_w[i] > mx ? block_w[i] : mx;
-    mx = wave_max(mx);
-    if (lane_id() == 0) sh[threadIdx.x / WAVE] = mx;
+    const int64_t ntiles = etiles(g.nnz);
+    uint64_t cut = 0;
+    for (int64_t tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
+        TileCtx t = tile_begin(g, tile_row, tt, s_off);
+        int32_t vv[ETILE_ITEMS], uu[ETILE_ITEMS];
+        uint32_t ww[ETILE_ITEMS];
+#pragma unroll
+        for (int i = 0; i < ETILE_ITEMS; ++i) {
+            const int64_t j = t.j0 + (int64_t)i * BLOCK + threadIdx.x;
+            uu[i] = -1;
+            vv[i] = 0;
+            ww[i] = 0;
+            if (j < t.j1) {
+                vv[i] = tile_row_of(g, t, s_off, j);
+                uu[i] = g.adj[j];
+                ww[i] = g.ew[j];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < ETILE_ITEMS; ++i)
+            if (uu[i] > vv[i] && part[uu[i]] != part[vv[i]]) cut += ww[i];
+    }
+    cut = block_sum(cut, sh);
+    if (threadIdx.x == 0 && cut)
+        atomicAdd((unsigned long long *)&acc[shard_of_block()], (unsigned long long)cut);
+    __syncthreads();
+    if (threadIdx.x == 0) last = arrive_last(arrive);
+    __syncthreads();
+    if (!last) return;
+    // the last block: sums, the exact L_max test, and cleared accumulators
+    uint64_t mxb = 0;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+        uint64_t part_w[BW_SHARDS];
+#pragma unroll
+        for (int q = 0; q < BW_SHARDS; ++q)
+            part_w[q] = __hip_atomic_load(&bw[(int64_t)q * k + i], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t w = 0;
+#pragma unroll
+        for (int q = 0; q < BW_SHARDS; ++q) {
+            w += part_w[q];
+            bw[(int64_t)q * k + i] = 0;
+        }
+        if (block_w_out) block_w_out[i] = w;
+        mxb = w > mxb ? w : mxb;
+    }
+    mxb = wave_max(mxb);
     {
         const int w = threadIdx.x / WAVE;
         if (w < 3) {
-            uint64_t v = acc[w * NSHARD + lane_id()];
+            uint64_t *p = &acc[w * NSHARD + lane_id()];
+            uint64_t v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            *p = 0;
             v = w == 2 ? wave_max(v) : wave_sum(v);
             if (lane_id() == 0) s_acc[w] = v;
         }
     }
+    if (lane_id() == 0) sh[threadIdx.x / WAVE] = mxb;
     __syncthreads();
     if (threadIdx.x != 0) return;
-    for (int i = 1; i < BLOCK / WAVE; ++i) mx = sh[i] > mx ? sh[i] : mx;
-    uint64_t total = s_acc[1], maxc = s_acc[2];
+    for (int i = 1; i < BLOCK / WAVE; ++i) mxb = sh[i] > mxb ? sh[i] : mxb;
+    const uint64_t total = s_acc[1], maxc = s_acc[2];
     // L_max = (1 + eps) c(V) / k + max c(v) = lnum / lden, lden = k * eps_den
-    u128 lnum = (u128)((uint64_t)eps_den + eps_num) * total + (u128)((uint64_t)k * eps_den) * maxc;
-    u128 lden = (u128)k * eps_den;
-    u128 lhs = lden * mx;
+    const u128 lnum =
+        (u128)((uint64_t)eps_den + eps_num) * total + (u128)((uint64_t)k * eps_den) * maxc;
+    const u128 lden = (u128)k * eps_den;
+    const u128 lhs = lden * mxb;
     res->cut = s_acc[0];
     res->total = total;
-    res->max_block = mx;
+    res->max_block = mxb;
     res->max_node = maxc;
     res->lmax_num = (uint64_t)lnum;
     res->lmax_den = (uint64_t)lden;
     res->imb_num = lhs > lnum ? (uint64_t)(lhs - lnum) : 0;
-    res->bal_num = (uint64_t)k * mx;
+    res->bal_num = (uint64_t)k * mxb;
     res->bal_den = total;
     res->feasible = lhs <= lnum ? 1 : 0;
 }
 
-void launch_cut_balance(const DevGraph &g, const int32_t *tr, const int32_t *part, int32_t k,
-                        uint32_t eps_num, uint32_t eps_den, uint64_t *block_w, uint64_t *acc,
-                        uint32_t *flag, kappa_cut_result *res_dev, hipStream_t s) {
-    launch_fill_u64(block_w, k, 0, s);
-    launch_fill_u64(acc, 3 * NSHARD, 0, s);
-    if (g.n > 0) {
-        KAPPA_PROF("cut_nodes", s);
-        hipLaunchKernelGGL(cut_nodes_k, dim3(grid_for(g.n, BLOCK * 4, CUT_NODE_BLOCKS)), dim3(BLOCK),
-                           (size_t)k * sizeof(uint64_t), s, g, part, k, block_w, acc, flag);
+void launch_up_level(const DevGraph &g, int mode, const int32_t *cmap, int32_t n_coarse,
+                     const int32_t *part_c, uint64_t part_seed, int32_t *part, int32_t k,
+                     uint32_t eps_num, uint32_t eps_den, int32_t *tile_row, const UpAcc &a,
+                     uint64_t *block_w_out, kappa_cut_result *res, hipStream_t s) {
+    {
+        KAPPA_PROF("up_nodes", s);
+        hipLaunchKernelGGL(up_nodes_k, dim3(grid_for(g.n, BLOCK * 4, UP_NODE_BLOCKS)), dim3(BLOCK),
+                           (size_t)k * sizeof(uint64_t), s, g, mode, cmap, n_coarse, part_c,
+                           part_seed, part, k, tile_row, a.bw, a.acc, a.flag);
     }
-    int64_t nt = etiles(g.nnz);
-    if (nt > 0) {
-        KAPPA_PROF("cut_entries", s);
-        hipLaunchKernelGGL(cut_entries_k, dim3(grid_for(nt, 1, 4096)), dim3(BLOCK), 0, s, g, tr,
-                           part, acc);
-    }
-    KAPPA_PROF("cut_finalize", s);
-    hipLaunchKernelGGL(cut_finalize_k, dim3(1), dim3(BLOCK), 0, s, block_w, k, eps_num, eps_den,
-                       acc, res_dev);
+    KAPPA_PROF("up_entries", s);
+    hipLaunchKernelGGL(up_entries_k, dim3(grid_for(etiles(g.nnz), 1, ARRIVE_MAX_BLOCKS)),
+                       dim3(BLOCK), 0, s, g, tile_row, part, k, eps_num, eps_den, a.bw, a.acc,
+                       a.arrive, block_w_out, res);
+}
+
+void launch_up_clear(const UpAcc &a, int32_t k, hipStream_t s) {
+    launch_fill_u64(a.bw, (int64_t)BW_SHARDS * k, 0, s);
+    launch_fill_u64(a.acc, 3 * NSHARD, 0, s);
+    launch_fill_u32(a.arrive, ARRIVE_WORDS, 0, s);
+    launch_fill_u32(a.flag, 1, 0, s);
 }
 
 }  // namespace kappa

@@ -696,16 +696,20 @@ struct RepF {
     __device__ void post(int64_t nc) const {
         LevelDesc *L = c.lv + l, *N = c.lv + l + 1;
         if (L->phase != PH_CONTRACT) return;
+        const uint64_t b4 = (uint64_t)nc * 4;
+        const uint64_t bytes[4] = {b4, (uint64_t)(nc + 1) * 8, b4, b4};
+        void *p[4];
+        const bool ok = arena_alloc_k<4>(c.ctrl, bytes, p);
         N->n = (int32_t)nc;
-        N->vw = (uint32_t *)arena_alloc(c.ctrl, (uint64_t)nc * 4);
-        N->xadj = (int64_t *)arena_alloc(c.ctrl, (uint64_t)(nc + 1) * 8);
-        N->mate = (int32_t *)arena_alloc(c.ctrl, (uint64_t)nc * 4);
-        N->cmap = (int32_t *)arena_alloc(c.ctrl, (uint64_t)nc * 4);
+        N->vw = (uint32_t *)p[0];
+        N->xadj = (int64_t *)p[1];
+        N->mate = (int32_t *)p[2];
+        N->cmap = (int32_t *)p[3];
         N->adj = nullptr;
         N->ew = nullptr;
         N->phase = PH_IDLE;
         N->stop = KAPPA_STOP_NONE;
-        if (!N->vw || !N->xadj || !N->mate || !N->cmap) {
+        if (!ok) {
             L->phase = PH_STOPPED;
             c.ctrl->done = 1;
         }
@@ -762,26 +766,32 @@ struct DegF {
     __device__ void post(int64_t nnzc) const {
         Control *ctrl = c.ctrl;
         LevelDesc *L = c.lv + l, *N = c.lv + l + 1;
-        if (L->phase != PH_CONTRACT) return;
-        if (ctrl->flags & CF_HUBS) {   // rows were left unmerged: stop, the host retries
+        // everything read here is loaded before the first decision
+        const int32_t phase = L->phase;
+        const uint32_t flags = ctrl->flags, stall_num = ctrl->stall_num,
+                       stall_den = ctrl->stall_den;
+        const int64_t n = L->n, nc = N->n;
+        if (phase != PH_CONTRACT) return;
+        if (flags & CF_HUBS) {   // rows were left unmerged: stop, the host retries
             L->phase = PH_STOPPED;
             ctrl->done = 1;
             return;
         }
+        const uint64_t bytes[2] = {(uint64_t)nnzc * 4, (uint64_t)nnzc * 4};
+        void *p[2];
+        const bool ok = arena_alloc_k<2>(ctrl, bytes, p);
         N->nnz = nnzc;
-        N->adj = (int32_t *)arena_alloc(ctrl, (uint64_t)nnzc * 4);
-        N->ew = (uint32_t *)arena_alloc(ctrl, (uint64_t)nnzc * 4);
+        N->adj = (int32_t *)p[0];
+        N->ew = (uint32_t *)p[1];
         N->maxdeg = 0;   // not tracked below level 0
-        if (!N->adj || !N->ew) {
+        if (!ok) {
             L->phase = PH_STOPPED;
             ctrl->done = 1;
             return;
         }
         L->phase = PH_COMPACT;
         ctrl->nlevels = l + 2;
-        const int64_t n = L->n, nc = N->n;
-        if (ctrl->stall_num > 0 &&
-            (uint64_t)(n - nc) * ctrl->stall_den < (uint64_t)ctrl->stall_num * (uint64_t)n) {
+        if (stall_num > 0 && (uint64_t)(n - nc) * stall_den < (uint64_t)stall_num * (uint64_t)n) {
             N->stop = KAPPA_STOP_STALL;
             N->phase = PH_STOPPED;
             ctrl->done = 1;

@@ -453,7 +453,7 @@ struct ProfScope {
 template <class F, class W>
 inline void launch_scan(int64_t n_hint, F f, W w, int64_t *ws, unsigned *arr, int64_t *total,
                         hipStream_t s) {
-    if (n_hint <= 2 * ONE_SCAN_CHUNK) {   // any n is correct; short ones are fast
+    if (n_hint <= ONE_SCAN_CHUNK) {   // any n is correct; short ones are fast
         KAPPA_PROF("scan_one_block", s);
         hipLaunchKernelGGL((scan_one_block_k<F, W>), dim3(1), dim3(ONE_SCAN_THREADS), 0, s, f, w,
                            total);
@@ -555,16 +555,31 @@ struct Ctx {
     ContractScratch cs;
 };
 
-// Device-side bump allocation in the arena (one thread).  nullptr on overflow.
-__device__ __forceinline__ void *arena_alloc(Control *c, uint64_t bytes) {
-    uint64_t start = (c->cursor + 255u) & ~(uint64_t)255u;
-    uint64_t end = start + (bytes ? bytes : 1);
-    if (end > c->cap) {
-        c->flags |= CF_ARENA;
-        return nullptr;
+// K bump allocations in the arena with one read and one write of the cursor
+// (one thread).  false (and every pointer null) on overflow.
+template <int K>
+__device__ __forceinline__ bool arena_alloc_k(Control *c, const uint64_t (&bytes)[K],
+                                              void *(&out)[K]) {
+    uint64_t cur = c->cursor;
+    const uint64_t cap = c->cap;
+    char *const base = c->base;
+    uint64_t off[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        cur = (cur + 255u) & ~(uint64_t)255u;
+        off[i] = cur;
+        cur += bytes[i] ? bytes[i] : 1;
     }
-    c->cursor = end;
-    return c->base + start;
+    if (cur > cap) {
+        c->flags |= CF_ARENA;
+#pragma unroll
+        for (int i = 0; i < K; ++i) out[i] = nullptr;
+        return false;
+    }
+    c->cursor = cur;
+#pragma unroll
+    for (int i = 0; i < K; ++i) out[i] = base + off[i];
+    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -596,11 +611,25 @@ void launch_initial_partition(int32_t n, int32_t k, uint64_t seed, int32_t *part
 void launch_project(const int32_t *cmap, int32_t n_fine, int32_t n_coarse,
                     const int32_t *part_coarse, int32_t *part_fine, uint32_t *flag,
                     hipStream_t s);
-// acc: [3][NSHARD] (cut, c(V), max c(v) per shard); acc and block_w[k] are
-// zeroed inside
-void launch_cut_balance(const DevGraph &g, const int32_t *tile_row, const int32_t *part,
-                        int32_t k, uint32_t eps_num, uint32_t eps_den, uint64_t *block_w,
-                        uint64_t *acc, uint32_t *flag, kappa_cut_result *res_dev, hipStream_t s);
+// One level of the way back up: the level's partition (mode: UP_GIVEN reads
+// part, UP_PROJECT writes part[v] = part_c[cmap[v]], UP_INITIAL writes the
+// stand-in part[v] = mix64(part_seed + v) mod k), then cut and balance into
+// res (device).  block_w_out (device [k], may be null) receives the block
+// weights.  The accumulators in `a` are zero on entry and left zero
+// (launch_up_clear zeroes them once).  tile_row: tile_rows_needed(g.nnz).
+enum UpMode { UP_GIVEN = 0, UP_PROJECT = 1, UP_INITIAL = 2 };
+constexpr int BW_SHARDS = 8;
+struct UpAcc {
+    uint64_t *bw;      // BW_SHARDS * k
+    uint64_t *acc;     // 3 * NSHARD
+    unsigned *arrive;  // ARRIVE_WORDS
+    uint32_t *flag;    // 1: bit 0 map entry, bit 1 block id out of range
+};
+void launch_up_level(const DevGraph &g, int mode, const int32_t *cmap, int32_t n_coarse,
+                     const int32_t *part_c, uint64_t part_seed, int32_t *part, int32_t k,
+                     uint32_t eps_num, uint32_t eps_den, int32_t *tile_row, const UpAcc &a,
+                     uint64_t *block_w_out, kappa_cut_result *res, hipStream_t s);
+void launch_up_clear(const UpAcc &a, int32_t k, hipStream_t s);
 // Level-resident variants of Out(v) (innerOuter): read level l's graph from the
 // descriptor; run only while level l is matching.
 void launch_level_out(const Ctx &c, int l, int64_t nnz_cap, int32_t n_hint, hipStream_t s);
