@@ -189,19 +189,24 @@ __device__ __forceinline__ int shard_of_block() { return (int)(blockIdx.x & (NSH
 // after its global writes; returns true in exactly one block, the last to
 // arrive, which then sees every other block's writes.  `cnt` holds
 // ARRIVE_WORDS zeroed words and is zero again when the grid ends.
+// Arrivals only release: an agent-scope release waits for the block's
+// writes (ordered before by a block barrier) and writes the XCD's L2 back to
+// memory before the counter moves, so once every arrival has counted, every
+// block's data is in memory.  The one acquire (it invalidates the XCD's L2,
+// which would evict every other block's gathered lines) is taken by the last
+// block alone, before it reads the others' data.
 __device__ __forceinline__ bool arrive_last(unsigned *cnt) {
     const unsigned nb = gridDim.x, g = blockIdx.x / ARRIVE_GROUP;
     const unsigned ng = (nb + ARRIVE_GROUP - 1) / ARRIVE_GROUP;
     const unsigned gsize = g + 1 < ng ? ARRIVE_GROUP : nb - g * ARRIVE_GROUP;
-    // release: this block's writes (ordered before by a block barrier) are
-    // published; acquire: the last arrival sees everyone's
-    unsigned old = __hip_atomic_fetch_add(&cnt[1 + g], 1u, __ATOMIC_ACQ_REL,
+    unsigned old = __hip_atomic_fetch_add(&cnt[1 + g], 1u, __ATOMIC_RELEASE,
                                           __HIP_MEMORY_SCOPE_AGENT);
     if (old != gsize - 1) return false;
     __hip_atomic_store(&cnt[1 + g], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    old = __hip_atomic_fetch_add(&cnt[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    old = __hip_atomic_fetch_add(&cnt[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     if (old != ng - 1) return false;
     __hip_atomic_store(&cnt[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return true;
 }
 
