@@ -511,47 +511,12 @@ __global__ void __launch_bounds__(BLOCK) up_nodes_k(DevGraph g, int mode, const 
 
 typedef unsigned __int128 u128;
 
-__global__ void __launch_bounds__(BLOCK) up_entries_k(DevGraph g, const int32_t *tile_row,
-                                                      const int32_t *part, int32_t k,
-                                                      uint32_t eps_num, uint32_t eps_den,
-                                                      uint64_t *bw, uint64_t *acc, unsigned *arrive,
-                                                      uint64_t *block_w_out,
-                                                      kappa_cut_result *res) {
-    __shared__ int64_t s_off[ETILE_ROWS + 1];
-    __shared__ uint64_t sh[BLOCK / WAVE + 1];
-    __shared__ uint64_t s_acc[3];
-    __shared__ int last;
+// The sums, the exact L_max test, and cleared accumulators (one block, all
+// threads call; the accumulators' writers have finished).
+__device__ __forceinline__ void up_finalize(int32_t k, uint32_t eps_num, uint32_t eps_den,
+                                            uint64_t *bw, uint64_t *acc, uint64_t *block_w_out,
+                                            kappa_cut_result *res, uint64_t *sh, uint64_t *s_acc) {
     static_assert(BLOCK / WAVE >= 3 && NSHARD == WAVE, "one wave per sharded accumulator");
-    const int64_t ntiles = etiles(g.nnz);
-    uint64_t cut = 0;
-    for (int64_t tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
-        TileCtx t = tile_begin(g, tile_row, tt, s_off);
-        int32_t vv[ETILE_ITEMS], uu[ETILE_ITEMS];
-        uint32_t ww[ETILE_ITEMS];
-#pragma unroll
-        for (int i = 0; i < ETILE_ITEMS; ++i) {
-            const int64_t j = t.j0 + (int64_t)i * BLOCK + threadIdx.x;
-            uu[i] = -1;
-            vv[i] = 0;
-            ww[i] = 0;
-            if (j < t.j1) {
-                vv[i] = tile_row_of(g, t, s_off, j);
-                uu[i] = g.adj[j];
-                ww[i] = g.ew[j];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < ETILE_ITEMS; ++i)
-            if (uu[i] > vv[i] && part[uu[i]] != part[vv[i]]) cut += ww[i];
-    }
-    cut = block_sum(cut, sh);
-    if (threadIdx.x == 0 && cut)
-        atomicAdd((unsigned long long *)&acc[shard_of_block()], (unsigned long long)cut);
-    __syncthreads();
-    if (threadIdx.x == 0) last = arrive_last(arrive);
-    __syncthreads();
-    if (!last) return;
-    // the last block: sums, the exact L_max test, and cleared accumulators
     uint64_t mxb = 0;
     for (int i = threadIdx.x; i < k; i += blockDim.x) {
         uint64_t part_w[BW_SHARDS];
@@ -601,6 +566,63 @@ __global__ void __launch_bounds__(BLOCK) up_entries_k(DevGraph g, const int32_t 
     res->feasible = lhs <= lnum ? 1 : 0;
 }
 
+// LAST: the block that finishes last finalizes (small grids); otherwise
+// up_finalize_k runs next (a release per block costs more on large grids).
+template <bool LAST>
+__global__ void __launch_bounds__(BLOCK) up_entries_k(DevGraph g, const int32_t *tile_row,
+                                                      const int32_t *part, int32_t k,
+                                                      uint32_t eps_num, uint32_t eps_den,
+                                                      uint64_t *bw, uint64_t *acc, unsigned *arrive,
+                                                      uint64_t *block_w_out,
+                                                      kappa_cut_result *res) {
+    __shared__ int64_t s_off[ETILE_ROWS + 1];
+    __shared__ uint64_t sh[BLOCK / WAVE + 1];
+    __shared__ uint64_t s_acc[3];
+    __shared__ int last;
+    const int64_t ntiles = etiles(g.nnz);
+    uint64_t cut = 0;
+    for (int64_t tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
+        TileCtx t = tile_begin(g, tile_row, tt, s_off);
+        int32_t vv[ETILE_ITEMS], uu[ETILE_ITEMS];
+        uint32_t ww[ETILE_ITEMS];
+#pragma unroll
+        for (int i = 0; i < ETILE_ITEMS; ++i) {
+            const int64_t j = t.j0 + (int64_t)i * BLOCK + threadIdx.x;
+            uu[i] = -1;
+            vv[i] = 0;
+            ww[i] = 0;
+            if (j < t.j1) {
+                vv[i] = tile_row_of(g, t, s_off, j);
+                uu[i] = g.adj[j];
+                ww[i] = g.ew[j];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < ETILE_ITEMS; ++i)
+            if (uu[i] > vv[i] && part[uu[i]] != part[vv[i]]) cut += ww[i];
+    }
+    cut = block_sum(cut, sh);
+    if (threadIdx.x == 0 && cut)
+        atomicAdd((unsigned long long *)&acc[shard_of_block()], (unsigned long long)cut);
+    if (!LAST) return;
+    __syncthreads();
+    if (threadIdx.x == 0) last = arrive_last(arrive);
+    __syncthreads();
+    if (!last) return;
+    up_finalize(k, eps_num, eps_den, bw, acc, block_w_out, res, sh, s_acc);
+}
+
+__global__ void __launch_bounds__(BLOCK) up_finalize_k(int32_t k, uint32_t eps_num,
+                                                       uint32_t eps_den, uint64_t *bw,
+                                                       uint64_t *acc, uint64_t *block_w_out,
+                                                       kappa_cut_result *res) {
+    __shared__ uint64_t sh[BLOCK / WAVE + 1];
+    __shared__ uint64_t s_acc[3];
+    up_finalize(k, eps_num, eps_den, bw, acc, block_w_out, res, sh, s_acc);
+}
+
+constexpr unsigned UP_LAST_BLOCKS = 64;   // grids up to this size finalize in their last block
+
 void launch_up_level(const DevGraph &g, int mode, const int32_t *cmap, int32_t n_coarse,
                      const int32_t *part_c, uint64_t part_seed, int32_t *part, int32_t k,
                      uint32_t eps_num, uint32_t eps_den, int32_t *tile_row, const UpAcc &a,
@@ -611,10 +633,21 @@ void launch_up_level(const DevGraph &g, int mode, const int32_t *cmap, int32_t n
                            (size_t)k * sizeof(uint64_t), s, g, mode, cmap, n_coarse, part_c,
                            part_seed, part, k, tile_row, a.bw, a.acc, a.flag);
     }
-    KAPPA_PROF("up_entries", s);
-    hipLaunchKernelGGL(up_entries_k, dim3(grid_for(etiles(g.nnz), 1, ARRIVE_MAX_BLOCKS)),
-                       dim3(BLOCK), 0, s, g, tile_row, part, k, eps_num, eps_den, a.bw, a.acc,
-                       a.arrive, block_w_out, res);
+    const unsigned grid = grid_for(etiles(g.nnz), 1, ARRIVE_MAX_BLOCKS);
+    if (grid <= UP_LAST_BLOCKS) {
+        KAPPA_PROF("up_entries", s);
+        hipLaunchKernelGGL(up_entries_k<true>, dim3(grid), dim3(BLOCK), 0, s, g, tile_row, part, k,
+                           eps_num, eps_den, a.bw, a.acc, a.arrive, block_w_out, res);
+        return;
+    }
+    {
+        KAPPA_PROF("up_entries", s);
+        hipLaunchKernelGGL(up_entries_k<false>, dim3(grid), dim3(BLOCK), 0, s, g, tile_row, part,
+                           k, eps_num, eps_den, a.bw, a.acc, a.arrive, block_w_out, res);
+    }
+    KAPPA_PROF("up_finalize", s);
+    hipLaunchKernelGGL(up_finalize_k, dim3(1), dim3(BLOCK), 0, s, k, eps_num, eps_den, a.bw, a.acc,
+                       block_w_out, res);
 }
 
 void launch_up_clear(const UpAcc &a, int32_t k, hipStream_t s) {

@@ -21,7 +21,7 @@ constexpr int SMALL_G = 4;
 
 // Matching rounds: a single workgroup finishes once at most TAIL_MAX nodes
 // still point somewhere.
-constexpr int TAIL_MAX = 1024;
+constexpr int TAIL_MAX = 128;
 constexpr int FINISH_THREADS = 1024;
 constexpr int STAT_ROUNDS = 64;     // per-round statistics kept per level (last slot aggregates)
 constexpr int MAX_LEVELS = 256;
