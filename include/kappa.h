@@ -194,6 +194,34 @@ int32_t kappa_hierarchy_round_stats(const kappa_hierarchy *h, int32_t l, int64_t
 /* Frees h (stream-ordered on the stream it was built on). NULL is a no-op. */
 void kappa_hierarchy_free(kappa_hierarchy *h);
 
+/* Batched form.  `count` independent graphs laid out as ONE block-diagonal
+   CSR `u` (device arrays, global ids): graph g owns nodes
+   [node_off[g], node_off[g+1]) and only edges among them.  node_off (host,
+   count + 1 entries, node_off[0] = 0, non-decreasing, node_off[count] =
+   u->n) and stop_n (host, count entries, or NULL for p->stop_n everywhere)
+   stay with the caller.  All graphs are coarsened together, level by level,
+   every kernel launch covering every graph still coarsening; each graph's
+   hierarchy equals what kappa_coarsen gives for that graph alone with the
+   same parameters (tie hashes use graph-local ids; the size, empty-matching
+   and stall rules and max_levels apply per graph).  Returns KAPPA_E_GRAPH if
+   an edge joins two graphs, else as kappa_coarsen.  Synchronous; the batch is
+   library-owned (kappa_batch_free). */
+typedef struct kappa_batch kappa_batch;
+kappa_status kappa_coarsen_batch(const kappa_graph *u, int32_t count, const int32_t *node_off,
+                                 const int32_t *stop_n, const kappa_coarsen_params *p,
+                                 kappa_batch **out, kappa_stream_t stream);
+int32_t kappa_batch_count(const kappa_batch *b);
+/* levels (host, may be NULL): graph g's level count; stop_reason: its kappa_stop. */
+kappa_status kappa_batch_graph_info(const kappa_batch *b, int32_t g, int32_t *levels,
+                                    int32_t *stop_reason);
+/* Graph g's hierarchy as a standalone, library-owned kappa_hierarchy (ids
+   local to g; level info has rounds = 0, since rounds are shared by the
+   batch), for every hierarchy call (kappa_hierarchy_level,
+   kappa_uncoarsen, ...).  Free it with kappa_hierarchy_free.  Synchronous. */
+kappa_status kappa_batch_hierarchy(const kappa_batch *b, int32_t g, kappa_hierarchy **out,
+                                   kappa_stream_t stream);
+void kappa_batch_free(kappa_batch *b);
+
 /* Stand-in for the initial partitioning of Section 4 (which runs external
    partitioners): part[x] = mix64(seed + x) mod k for x < n.  k in [1, 4096]. */
 kappa_status kappa_initial_partition(int32_t n, int32_t k, uint64_t seed, int32_t *part,

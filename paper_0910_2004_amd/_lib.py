@@ -102,6 +102,12 @@ def lib():
         "kappa_profile_enable": (None, [i32]),
         "kappa_profile_reset": (None, []),
         "kappa_profile_read": (i32, [P, P, P, i32]),
+        "kappa_coarsen_batch": (st, [ctypes.POINTER(c_graph), i32, P, P, ctypes.POINTER(c_params),
+                                     ctypes.POINTER(P), P]),
+        "kappa_batch_count": (i32, [P]),
+        "kappa_batch_graph_info": (st, [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "kappa_batch_hierarchy": (st, [P, i32, ctypes.POINTER(P), P]),
+        "kappa_batch_free": (None, [P]),
         "kappa_cache_release": (st, []),
         "kappa_graphs_enable": (None, [i32]),
         "kappa_status_str": (ctypes.c_char_p, [st]),
@@ -309,6 +315,64 @@ def kappa_coarsen(g: DeviceGraph, rating: int = EXPANSION_STAR2, seed: int = 42,
     _check("kappa_coarsen", lib().kappa_coarsen(ctypes.byref(g.c()), ctypes.byref(p), ctypes.byref(h),
                                                 _stream()))
     return Hierarchy(h, g.xadj.device, g)
+
+
+class Batch:
+    """Owns a kappa_batch handle (freed with the object); keeps the union
+    graph alive (level 0 of the batch refers to its arrays)."""
+
+    def __init__(self, handle, device, graph, count):
+        self.handle = handle
+        self.device = device
+        self.graph = graph
+        self.count = count
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().kappa_batch_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    def __len__(self):
+        return self.count
+
+    def info(self, g: int):
+        """(levels, stop reason) of graph g."""
+        lv, st = ctypes.c_int32(), ctypes.c_int32()
+        _check("kappa_batch_graph_info", lib().kappa_batch_graph_info(self.handle, g, ctypes.byref(lv),
+                                                                      ctypes.byref(st)))
+        return int(lv.value), int(st.value)
+
+    def hierarchy(self, g: int) -> Hierarchy:
+        """Graph g's hierarchy (local ids) as a standalone Hierarchy."""
+        h = ctypes.c_void_p()
+        _check("kappa_batch_hierarchy", lib().kappa_batch_hierarchy(self.handle, g, ctypes.byref(h),
+                                                                    _stream()))
+        return Hierarchy(h, self.device, self)
+
+
+def kappa_coarsen_batch(u: DeviceGraph, node_off, rating: int = EXPANSION_STAR2, seed: int = 42,
+                        stop_n=256, stall_num: int = 1, stall_den: int = 20,
+                        max_levels: int = 64) -> Batch:
+    """Coarsens the graphs of the block-diagonal union `u` (graph g owns nodes
+    node_off[g] .. node_off[g+1]-1) together.  stop_n: one int for all graphs
+    or a sequence with one per graph."""
+    import numpy as np
+    off = np.ascontiguousarray(np.asarray(node_off, dtype=np.int32))
+    count = len(off) - 1
+    sn = None
+    if not np.isscalar(stop_n):
+        sn = np.ascontiguousarray(np.asarray(stop_n, dtype=np.int32))
+        stop_n = 0
+    p = c_params(rating, seed & (2**64 - 1), int(stop_n), stall_num, stall_den, max_levels)
+    h = ctypes.c_void_p()
+    _check("kappa_coarsen_batch", lib().kappa_coarsen_batch(
+        ctypes.byref(u.c()), count, off.ctypes.data_as(ctypes.c_void_p),
+        sn.ctypes.data_as(ctypes.c_void_p) if sn is not None else None, ctypes.byref(p),
+        ctypes.byref(h), _stream()))
+    return Batch(h, u.xadj.device, u, count)
 
 
 def kappa_initial_partition(n: int, k: int, seed: int, device="cuda"):

@@ -535,20 +535,45 @@ namespace {
 // One attempt at the whole contraction phase with a given arena size.
 // Returns KAPPA_OK and fills H, or a status; *retry_flags gets the control
 // flags asking for another attempt (arena too small, hub accumulators).
+// Inputs of the batched form (a disjoint union of `count` graphs).
+struct BatchIn {
+    int32_t count;
+    const int32_t *node_off;   // host, count + 1
+    const int32_t *stop_n;     // host, count
+};
+// Per-graph results of the batched form.
+struct BatchOut {
+    std::vector<std::vector<int32_t>> noff;   // per union level: first node of each graph
+    std::vector<int32_t> coarsest, reason;    // per graph
+};
+
 kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_coarsen_params *p,
-                             hipStream_t s, uint64_t arena_bytes, bool hubs, kappa_hierarchy *H,
-                             uint32_t *retry_flags) {
+                             hipStream_t s, uint64_t arena_bytes, bool hubs, const BatchIn *bi,
+                             kappa_hierarchy *H, BatchOut *bo, uint32_t *retry_flags) {
     *retry_flags = 0;
     Ctx c;
     c.rating = p->rating;
     c.seed = p->seed;
     c.seed_direct = 0;
     const int maxl = p->max_levels;
+    const int32_t count = bi ? bi->count : 0;
+    uint32_t *bflag = nullptr;
     std::unique_ptr<Workspace> w;
     if (!carve_workspace(s, w, [&](Carve &cv) {
             c.ctrl = cv.get<Control>(1);
             c.lv = cv.get<LevelDesc>(maxl + 2);
             carve_scratch(cv, d0, p->rating, hubs, c);
+            if (bi) {
+                c.b.count = count;
+                c.b.stall_num = p->stall_num;
+                c.b.stall_den = p->stall_den;
+                c.b.stop_n = cv.get<int32_t>(count);
+                c.b.active = cv.get<uint8_t>(count);
+                c.b.coarsest = cv.get<int32_t>(count);
+                c.b.reason = cv.get<int32_t>(count);
+                c.b.excl = cv.get<int32_t>(d0.n);
+                bflag = cv.get<uint32_t>(1);
+            }
         }))
         return KAPPA_E_NOMEM;
     size_t arena_got = 0;
@@ -568,14 +593,19 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     in->ctrl.done = 0;
     in->ctrl.nlevels = 1;
     in->ctrl.flags = 0;
-    // level 0's mate and cmap open the arena
+    // level 0's mate and cmap (and, batched, its graph ids and offsets)
+    // open the arena
     const uint64_t n_al = ((uint64_t)d0.n * 4 + 255) & ~(uint64_t)255;
-    in->ctrl.cursor = 2 * n_al;
+    const uint64_t g_al = ((uint64_t)(count + 1) * 4 + 255) & ~(uint64_t)255;
+    int32_t *gid0 = bi ? (int32_t *)((char *)arena + 2 * n_al) : nullptr;
+    int32_t *noff0 = bi ? (int32_t *)((char *)arena + 3 * n_al) : nullptr;
+    in->ctrl.cursor = bi ? 3 * n_al + g_al : 2 * n_al;
     in->ctrl.cap = arena_bytes;
     in->ctrl.base = (char *)arena;
-    in->ctrl.stop_n = p->stop_n;
+    // batched: size and stall rules apply per graph (batch_begin / batch_end)
+    in->ctrl.stop_n = bi ? -1 : p->stop_n;
     in->ctrl.max_levels = maxl;
-    in->ctrl.stall_num = p->stall_num;
+    in->ctrl.stall_num = bi ? 0 : p->stall_num;
     in->ctrl.stall_den = p->stall_den;
     in->l0.n = d0.n;
     in->l0.maxdeg = maxdeg0;
@@ -586,7 +616,27 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     in->l0.vw = const_cast<uint32_t *>(d0.vw);
     in->l0.mate = (int32_t *)arena;
     in->l0.cmap = (int32_t *)((char *)arena + n_al);
+    in->l0.gid = gid0;
+    in->l0.noff = noff0;
     in->l0.phase = PH_IDLE;
+    if (bi) {
+        HIPCHK(hipMemcpyAsync(noff0, bi->node_off, (size_t)(count + 1) * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync((void *)c.b.stop_n, bi->stop_n, (size_t)count * 4,
+                              hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemsetAsync(c.b.active, 1, (size_t)count, s));
+        HIPCHK(hipMemsetAsync(c.b.coarsest, 0xff, (size_t)count * 4, s));
+        HIPCHK(hipMemsetAsync(c.b.reason, 0, (size_t)count * 4, s));
+        HIPCHK(hipMemsetAsync(bflag, 0, sizeof(uint32_t), s));
+        launch_batch_gid(noff0, count, gid0, s);
+        DevGraph db = d0;
+        db.gid = gid0;
+        db.noff = noff0;
+        launch_batch_check(db, bflag, s);
+        uint32_t *hf = (uint32_t *)pinned(sizeof(uint32_t));
+        HIPCHK(hipMemcpyAsync(hf, bflag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (*hf) return KAPPA_E_GRAPH;   // an edge joins two graphs of the batch
+    }
     // every descriptor starts idle (zero): kernels of levels not built yet are no-ops
     HIPCHK(hipMemsetAsync(c.lv, 0, (size_t)(maxl + 2) * sizeof(LevelDesc), s));
     HIPCHK(hipMemcpyAsync(c.ctrl, &in->ctrl, sizeof(Control), hipMemcpyHostToDevice, s));
@@ -603,7 +653,8 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
         const int l_end = std::min(launched + batch, maxl + 1);
         const std::vector<uint64_t> key = {1, pkey(w->base), (uint64_t)n0, (uint64_t)d0.nnz,
                                            (uint64_t)p->rating, p->seed, (uint64_t)maxl,
-                                           (uint64_t)hubs, (uint64_t)launched, (uint64_t)l_end};
+                                           (uint64_t)hubs, (uint64_t)launched, (uint64_t)l_end,
+                                           (uint64_t)count};
         HIPCHK(run_seq(w->c, s, key, [&](hipStream_t q) {
             for (int l = launched; l < l_end; ++l) {
                 int32_t nh = n_hint_of(n0, l);
@@ -667,6 +718,25 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
         if (l + 1 < nl) L.stop = KAPPA_STOP_NONE;
         H->levels.push_back(L);
     }
+    if (bi) {
+        bo->noff.assign(nl, std::vector<int32_t>(count + 1));
+        for (int l = 0; l < nl; ++l)
+            HIPCHK(hipMemcpyAsync(bo->noff[l].data(), hl[l].noff, (size_t)(count + 1) * 4,
+                                  hipMemcpyDeviceToHost, s));
+        bo->coarsest.assign(count, 0);
+        bo->reason.assign(count, 0);
+        HIPCHK(hipMemcpyAsync(bo->coarsest.data(), c.b.coarsest, (size_t)count * 4,
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(bo->reason.data(), c.b.reason, (size_t)count * 4,
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const int32_t last_stop = hl[nl - 1].stop;
+        for (int32_t g = 0; g < count; ++g)
+            if (bo->coarsest[g] < 0) {   // still coarsening when the union stopped
+                bo->coarsest[g] = nl - 1;
+                bo->reason[g] = last_stop;
+            }
+    }
     H->arena = hold.release();
     H->arena_bytes = arena_bytes;
     return KAPPA_OK;
@@ -727,7 +797,7 @@ extern "C" kappa_status kappa_coarsen(const kappa_graph *g, const kappa_coarsen_
     bool hubs = 2 * (int64_t)maxdeg - 2 > ROW_MID_MAX / 8;
     for (int attempt = 0; attempt < 6; ++attempt) {
         uint32_t retry = 0;
-        st = coarsen_attempt(d0, maxdeg, p, s, arena, hubs, H, &retry);
+        st = coarsen_attempt(d0, maxdeg, p, s, arena, hubs, nullptr, H, nullptr, &retry);
         if (st == KAPPA_OK) break;
         if (!retry) break;
         if (retry & CF_ARENA) arena *= 4;
@@ -740,6 +810,154 @@ extern "C" kappa_status kappa_coarsen(const kappa_graph *g, const kappa_coarsen_
     *out = H;
     return KAPPA_OK;
 }
+
+// ===========================================================================
+// Batched form
+// ===========================================================================
+struct kappa_batch {
+    kappa_hierarchy union_h;   // the union's levels (owns the arena)
+    int32_t count = 0;
+    BatchOut out;
+};
+
+extern "C" kappa_status kappa_coarsen_batch(const kappa_graph *u, int32_t count,
+                                            const int32_t *node_off, const int32_t *stop_n,
+                                            const kappa_coarsen_params *p, kappa_batch **out,
+                                            kappa_stream_t stream) {
+    if (!out) return KAPPA_E_ARG;
+    *out = nullptr;
+    if (!graph_args_ok(u) || !p || count < 1 || !node_off) return KAPPA_E_ARG;
+    if (p->rating < 0 || p->rating > 4 || p->max_levels < 0 || p->max_levels > MAX_LEVELS ||
+        (p->stall_num > 0 && p->stall_den == 0))
+        return KAPPA_E_ARG;
+    if (node_off[0] != 0 || node_off[count] != u->n) return KAPPA_E_ARG;
+    for (int32_t g = 0; g < count; ++g)
+        if (node_off[g + 1] < node_off[g]) return KAPPA_E_ARG;
+    hipStream_t s = S(stream);
+    DevGraph d0 = dev(u);
+    int32_t maxdeg = 0;
+    kappa_status st = validate_impl(d0, s, &maxdeg);
+    if (st != KAPPA_OK) return st;
+    std::vector<int32_t> sn(count, p->stop_n);
+    if (stop_n) sn.assign(stop_n, stop_n + count);
+    BatchIn bi{count, node_off, sn.data()};
+    kappa_batch *B = new (std::nothrow) kappa_batch();
+    if (!B) return KAPPA_E_NOMEM;
+    B->union_h.s = s;
+    B->count = count;
+    // arena: every level's nodes (vw, xadj, mate, cmap, graph id: 28 B),
+    // entries (8 B) and graph offsets, three times level 0 to start with
+    uint64_t lvl0 = (uint64_t)d0.n * 28 + (uint64_t)d0.nnz * 8 + (uint64_t)(count + 1) * 4 + 8192;
+    uint64_t arena = 3 * lvl0 + (uint64_t)(count + 1) * 4 * 64 + (1u << 20);
+    bool hubs = 2 * (int64_t)maxdeg - 2 > ROW_MID_MAX / 8;
+    for (int attempt = 0; attempt < 6; ++attempt) {
+        uint32_t retry = 0;
+        st = coarsen_attempt(d0, maxdeg, p, s, arena, hubs, &bi, &B->union_h, &B->out, &retry);
+        if (st == KAPPA_OK) break;
+        if (!retry) break;
+        if (retry & CF_ARENA) arena *= 4;
+        if (retry & CF_HUBS) hubs = true;
+    }
+    if (st != KAPPA_OK) {
+        delete B;
+        return st;
+    }
+    *out = B;
+    return KAPPA_OK;
+}
+
+extern "C" int32_t kappa_batch_count(const kappa_batch *b) { return b ? b->count : 0; }
+
+extern "C" kappa_status kappa_batch_graph_info(const kappa_batch *b, int32_t g, int32_t *levels,
+                                               int32_t *stop_reason) {
+    if (!b || g < 0 || g >= b->count) return KAPPA_E_ARG;
+    if (levels) *levels = b->out.coarsest[g] + 1;
+    if (stop_reason) *stop_reason = b->out.reason[g];
+    return KAPPA_OK;
+}
+
+extern "C" kappa_status kappa_batch_hierarchy(const kappa_batch *b, int32_t g,
+                                              kappa_hierarchy **out, kappa_stream_t stream) {
+    if (!out) return KAPPA_E_ARG;
+    *out = nullptr;
+    if (!b || g < 0 || g >= b->count) return KAPPA_E_ARG;
+    hipStream_t s = S(stream);
+    const int32_t L = b->out.coarsest[g];
+    const auto &U = b->union_h.levels;
+    // node and entry ranges of the graph on every level
+    std::vector<int32_t> na(L + 1), nb(L + 1);
+    std::vector<int64_t> ea(L + 1), eb(L + 1);
+    for (int32_t l = 0; l <= L; ++l) {
+        na[l] = b->out.noff[l][g];
+        nb[l] = b->out.noff[l][g + 1];
+        int64_t e2[2] = {0, 0};
+        HIPCHK(hipMemcpyAsync(&e2[0], U[l].xadj + na[l], sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&e2[1], U[l].xadj + nb[l], sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        ea[l] = e2[0];
+        eb[l] = e2[1];
+    }
+    Carve lay;
+    struct Arr {
+        int64_t *xadj;
+        int32_t *adj, *cmap, *mate;
+        uint32_t *ew, *vw;
+    };
+    std::vector<Arr> arr(L + 1);
+    auto layout = [&](Carve &cv) {
+        for (int32_t l = 0; l <= L; ++l) {
+            const int64_t n = nb[l] - na[l], nnz = eb[l] - ea[l];
+            arr[l].xadj = cv.get<int64_t>(n + 1);
+            arr[l].adj = cv.get<int32_t>(nnz);
+            arr[l].ew = cv.get<uint32_t>(nnz);
+            arr[l].vw = cv.get<uint32_t>(n);
+            arr[l].cmap = cv.get<int32_t>(n);
+            arr[l].mate = cv.get<int32_t>(n);
+        }
+    };
+    layout(lay);
+    std::unique_ptr<kappa_hierarchy> H(new (std::nothrow) kappa_hierarchy());
+    if (!H) return KAPPA_E_NOMEM;
+    H->s = s;
+    size_t got = 0;
+    void *arena = take_arena(s, lay.off, &got);
+    if (!arena) return KAPPA_E_NOMEM;
+    H->arena = arena;
+    H->arena_bytes = got;
+    Carve real;
+    real.base = (char *)arena;
+    layout(real);
+    for (int32_t l = 0; l <= L; ++l) {
+        const kappa_level &src = U[l];
+        DevGraph du;
+        du.n = src.n; du.nnz = src.nnz; du.xadj = src.xadj; du.adj = src.adj; du.ew = src.ew;
+        du.vw = src.vw;
+        const bool has_next = l < L;
+        launch_batch_extract(du, has_next ? src.cmap : nullptr, has_next ? src.mate : nullptr,
+                             na[l], nb[l], ea[l], eb[l] - ea[l], has_next ? b->out.noff[l + 1][g] : 0,
+                             arr[l].xadj, arr[l].adj, arr[l].ew, arr[l].vw, arr[l].cmap,
+                             arr[l].mate, s);
+        kappa_level lv;
+        lv.n = nb[l] - na[l];
+        lv.nnz = eb[l] - ea[l];
+        lv.xadj = arr[l].xadj;
+        lv.adj = arr[l].adj;
+        lv.ew = arr[l].ew;
+        lv.vw = arr[l].vw;
+        lv.cmap = has_next ? arr[l].cmap : nullptr;
+        lv.mate = has_next ? arr[l].mate : nullptr;
+        lv.matched = has_next ? (int64_t)lv.n - (b->out.noff[l + 1][g + 1] - b->out.noff[l + 1][g]) : 0;
+        lv.rounds = 0;   // rounds are counted for the union, not per graph
+        lv.stop = has_next ? KAPPA_STOP_NONE : b->out.reason[g];
+        H->levels.push_back(lv);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    *out = H.release();
+    return KAPPA_OK;
+}
+
+extern "C" void kappa_batch_free(kappa_batch *b) { delete b; }
 
 extern "C" kappa_status kappa_match(const kappa_graph *g, int32_t rating, uint64_t level_seed,
                                     int32_t *mate, int32_t *rounds_out, int64_t *matched_out,

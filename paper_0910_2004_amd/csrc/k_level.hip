@@ -39,6 +39,7 @@
 //   3. scan of the merged degrees -> coarse row offsets; the epilogue
 //      allocates the next level's edge arrays and checks the stall rule
 //   4. compact: copy merged rows into the exact-size coarse arrays
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 
@@ -52,7 +53,13 @@ namespace kappa {
 __device__ __forceinline__ bool load_level(const LevelDesc *L, int32_t want, DevGraph &g) {
     if (L->phase != want) return false;
     g.n = L->n; g.nnz = L->nnz; g.xadj = L->xadj; g.adj = L->adj; g.ew = L->ew; g.vw = L->vw;
+    g.gid = L->gid; g.noff = L->noff;
     return true;
+}
+
+// Batched form: is v's graph still coarsening?
+__device__ __forceinline__ bool graph_active(const Ctx &c, const DevGraph &g, int64_t v) {
+    return !g.gid || c.b.active[g.gid[v]];
 }
 
 __device__ __forceinline__ int bin_of(int64_t deg) {
@@ -121,7 +128,8 @@ __device__ __forceinline__ uint32_t attr_src(const DevGraph &g, const uint32_t *
 // Best edge from v to a free neighbour over the entries sub, sub+G, ...
 template <int R, int G, bool FIRST>
 __device__ __forceinline__ Cand scan_row(const DevGraph &g, int32_t v, uint32_t av, int sub,
-                                         const int2 *nrec, const uint32_t *out, uint64_t seed) {
+                                         const int2 *nrec, const uint32_t *out, uint64_t seed,
+                                         int32_t base) {
     Cand best = cand_none();
     const int64_t b = g.xadj[v], e = g.xadj[v + 1];
     for (int64_t j = b + sub; j < e; j += G) {
@@ -136,7 +144,7 @@ __device__ __forceinline__ Cand scan_row(const DevGraph &g, int32_t v, uint32_t 
         }
         Cand cd;
         rate<R>(g.ew[j], au, av, au, av, cd.num, cd.den);
-        cd.h = mix64(seed ^ edge_id(v, u));
+        cd.h = mix64(seed ^ edge_id_local(v, u, base));
         cd.u = u;
         if (cand_better(cd, best, v)) best = cd;
     }
@@ -148,7 +156,7 @@ __device__ __forceinline__ Cand scan_row(const DevGraph &g, int32_t v, uint32_t 
 template <int R, int G, bool FIRST>
 __device__ __forceinline__ Cand scan_row_small(const DevGraph &g, int32_t v, uint32_t av, int sub,
                                                int64_t b, int64_t e, const int2 *nrec,
-                                               const uint32_t *out, uint64_t seed) {
+                                               const uint32_t *out, uint64_t seed, int32_t base) {
     constexpr int T = BIN_SMALL_MAX / G;
     int32_t u[T];
     uint32_t w[T], au[T];
@@ -176,7 +184,7 @@ __device__ __forceinline__ Cand scan_row_small(const DevGraph &g, int32_t v, uin
         if (!ok[t]) continue;
         Cand cd;
         rate<R>(w[t], au[t], av, au[t], av, cd.num, cd.den);
-        cd.h = mix64(seed ^ edge_id(v, u[t]));
+        cd.h = mix64(seed ^ edge_id_local(v, u[t], base));
         cd.u = u[t];
         if (cand_better(cd, best, v)) best = cd;
     }
@@ -283,7 +291,7 @@ __device__ __forceinline__ void init_phase(const Ctx &c, const DevGraph &g, Leve
             bb[k] = -1;
             dd[k] = (int32_t)deg[k];
             const int bn = bin_of(deg[k]);
-            bin[k] = i < g.n && bn > 0 ? bn : -1;
+            bin[k] = i < g.n && bn > 0 && graph_active(c, g, i) ? bn : -1;
             if (i < g.n) {
                 mate[i] = -1;
                 best[i] = -1;
@@ -334,7 +342,7 @@ __device__ __forceinline__ void pick_bin0(const Ctx &c, const DevGraph &g, uint6
                 v = (int32_t)i;
                 rb = g.xadj[v];
                 re = g.xadj[v + 1];
-                act = re - rb >= 1 && re - rb <= BIN_SMALL_MAX;
+                act = re - rb >= 1 && re - rb <= BIN_SMALL_MAX && graph_active(c, g, v);
                 if (act) av = attr_src<R>(g, out, v);
             } else {
                 v = checked_node(ri.in[0].v[i], g.n, c.ctrl);
@@ -347,7 +355,8 @@ __device__ __forceinline__ void pick_bin0(const Ctx &c, const DevGraph &g, uint6
                 }
             }
         }
-        Cand cd = act ? scan_row_small<R, G, FIRST>(g, v, av, sub, rb, re, nrec, out, seed)
+        Cand cd = act ? scan_row_small<R, G, FIRST>(g, v, av, sub, rb, re, nrec, out, seed,
+                                                    local_base(g, v))
                       : cand_none();
         cd = group_reduce<G>(cd, v);
         if (act && sub == 0) {
@@ -370,7 +379,7 @@ __device__ __forceinline__ void pick_bin1(const Ctx &c, const DevGraph &g, uint6
         const int32_t v = checked_node(ri.in[1].v[i], g.n, c.ctrl);
         if (v < 0 || (!FIRST && keeps_choice(ri.in[1].b[i], g.n, nrec))) continue;   // wave-uniform
         const uint32_t av = FIRST ? attr_src<R>(g, out, v) : (uint32_t)nrec[v].x;
-        Cand cd = scan_row<R, WAVE, FIRST>(g, v, av, lane_id(), nrec, out, seed);
+        Cand cd = scan_row<R, WAVE, FIRST>(g, v, av, lane_id(), nrec, out, seed, local_base(g, v));
         cd = group_reduce<WAVE>(cd, v);
         if (lane_id() == 0) {
             best[v] = cd.u;
@@ -390,7 +399,7 @@ __device__ __forceinline__ void pick_bin2(const Ctx &c, const DevGraph &g, uint6
         const int32_t v = checked_node(ri.in[2].v[i], g.n, c.ctrl);
         if (v < 0 || (!FIRST && keeps_choice(ri.in[2].b[i], g.n, nrec))) continue;   // block-uniform
         const uint32_t av = FIRST ? attr_src<R>(g, out, v) : (uint32_t)nrec[v].x;
-        Cand cd = scan_row<R, NT, FIRST>(g, v, av, threadIdx.x, nrec, out, seed);
+        Cand cd = scan_row<R, NT, FIRST>(g, v, av, threadIdx.x, nrec, out, seed, local_base(g, v));
         cd = block_reduce_cand(cd, v, sh);
         if (threadIdx.x == 0) {
             best[v] = cd.u;
@@ -516,6 +525,7 @@ __global__ void __launch_bounds__(BLOCK) match_init_k(Ctx c, int l, int stop_rul
     LevelDesc *L = c.lv + l;
     DevGraph g;
     g.n = L->n; g.nnz = L->nnz; g.xadj = L->xadj; g.adj = L->adj; g.ew = L->ew; g.vw = L->vw;
+    g.gid = L->gid; g.noff = L->noff;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         // the round statistics are zero on entry (the previous level's
         // finisher, or the host before level 0, cleared them)
@@ -689,22 +699,30 @@ struct RepF {
         const LevelDesc *L = c.lv + l;
         return L->phase == PH_CONTRACT ? L->n : -1;
     }
+    // representatives: unmatched nodes and the smaller end of each pair (the
+    // nodes of a stopped graph in a batch are none: they leave the union)
     __device__ int64_t operator()(int64_t i) const {
-        int32_t m = c.lv[l].mate[i];
+        const LevelDesc *L = c.lv + l;
+        const int32_t m = L->mate[i];
+        if (L->gid && !c.b.active[L->gid[i]]) return 0;
         return (m < 0 || i < m) ? 1 : 0;
     }
     __device__ void post(int64_t nc) const {
         LevelDesc *L = c.lv + l, *N = c.lv + l + 1;
         if (L->phase != PH_CONTRACT) return;
+        const bool batch = L->gid != nullptr;
         const uint64_t b4 = (uint64_t)nc * 4;
-        const uint64_t bytes[4] = {b4, (uint64_t)(nc + 1) * 8, b4, b4};
-        void *p[4];
-        const bool ok = arena_alloc_k<4>(c.ctrl, bytes, p);
+        const uint64_t bytes[6] = {b4, (uint64_t)(nc + 1) * 8, b4, b4, batch ? b4 : 0,
+                                   batch ? (uint64_t)(c.b.count + 1) * 4 : 0};
+        void *p[6];
+        const bool ok = arena_alloc_k<6>(c.ctrl, bytes, p);
         N->n = (int32_t)nc;
         N->vw = (uint32_t *)p[0];
         N->xadj = (int64_t *)p[1];
         N->mate = (int32_t *)p[2];
         N->cmap = (int32_t *)p[3];
+        N->gid = batch ? (int32_t *)p[4] : nullptr;
+        N->noff = batch ? (int32_t *)p[5] : nullptr;
         N->adj = nullptr;
         N->ew = nullptr;
         N->phase = PH_IDLE;
@@ -721,32 +739,45 @@ struct RepW {
     struct Pre {
         int32_t w;
         uint32_t cw;
+        int32_t gid;
     };
     struct Bound {
         const int32_t *mate;
         const uint32_t *vw;
         int32_t *cmap, *rep_of, *partner;
         uint32_t *cvw;
+        // batched form (null otherwise)
+        const int32_t *gid;
+        int32_t *cgid, *excl;
         __device__ Pre prefetch(int64_t i, int64_t v) const {
-            Pre p{-1, 0u};
-            if (!v) return p;
+            Pre p{-1, 0u, 0};
             p.w = mate[i];
+            if (!v) return p;
             p.cw = vw[i] + (p.w >= 0 ? vw[p.w] : 0u);
+            if (gid) p.gid = gid[i];
             return p;
         }
         __device__ void operator()(int64_t i, int64_t pre, int64_t v, const Pre &p) const {
-            if (!v) return;
+            if (excl) excl[i] = (int32_t)pre;
+            if (!v) {
+                if (p.w < 0) cmap[i] = -1;   // a stopped graph's node: not carried over
+                return;
+            }
             const int32_t x = (int32_t)pre;
             cmap[i] = x;
             if (p.w >= 0) cmap[p.w] = x;
             rep_of[x] = (int32_t)i;
             partner[x] = p.w;
             cvw[x] = p.cw;
+            if (cgid) cgid[x] = p.gid;
         }
     };
     __device__ Bound bind() const {
-        const LevelDesc *L = c.lv + l;
-        return Bound{L->mate, L->vw, L->cmap, c.cs.rep_of, c.cs.partner, c.lv[l + 1].vw};
+        const LevelDesc *L = c.lv + l, *N = c.lv + l + 1;
+        const bool batch = L->gid != nullptr;
+        return Bound{L->mate,   L->vw,  L->cmap,  c.cs.rep_of,
+                     c.cs.partner, N->vw, L->gid, batch ? N->gid : nullptr,
+                     batch ? c.b.excl : nullptr};
     }
 };
 
@@ -1134,6 +1165,114 @@ __global__ void __launch_bounds__(BLOCK) compact_big_k(Ctx c, int l) {
 }
 
 // ===========================================================================
+// Batched form: per-graph stop rules (one workgroup; graphs are few next to
+// nodes).  A graph's coarsest level and stop reason are recorded when it
+// stops; it is frozen from then on.
+// ===========================================================================
+constexpr int BATCH_THREADS = 1024;
+
+__global__ void __launch_bounds__(BATCH_THREADS) batch_begin_k(Ctx c, int l) {
+    __shared__ int any;
+    Control *ctrl = c.ctrl;
+    LevelDesc *L = c.lv + l;
+    if (ctrl->done || ctrl->nlevels != l + 1 || L->phase != PH_IDLE) return;   // same for all
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    const int32_t *noff = L->noff;
+    const int32_t maxl = ctrl->max_levels;
+    bool mine = false;
+    for (int g = threadIdx.x; g < c.b.count; g += blockDim.x) {
+        if (!c.b.active[g]) continue;
+        const int32_t ng = noff[g + 1] - noff[g];
+        int32_t stop = KAPPA_STOP_NONE;
+        if (ng <= c.b.stop_n[g]) stop = KAPPA_STOP_SIZE;
+        else if (l >= maxl) stop = KAPPA_STOP_MAXLEVEL;
+        if (stop != KAPPA_STOP_NONE) {
+            c.b.active[g] = 0;
+            c.b.coarsest[g] = l;
+            c.b.reason[g] = stop;
+        } else {
+            mine = true;
+        }
+    }
+    if (mine) any = 1;
+    __syncthreads();
+    if (threadIdx.x == 0 && !any) {   // every graph has stopped: so does the union
+        L->stop = KAPPA_STOP_SIZE;
+        L->phase = PH_STOPPED;
+        ctrl->done = 1;
+    }
+}
+
+__global__ void __launch_bounds__(BATCH_THREADS) batch_end_k(Ctx c, int l) {
+    const LevelDesc *L = c.lv + l, *N = c.lv + l + 1;
+    if (L->phase != PH_COMPACT) return;   // the level did not contract
+    const int32_t n = L->n, nc = N->n;
+    const int32_t *noff = L->noff;
+    int32_t *noffN = N->noff;
+    for (int g = threadIdx.x; g <= c.b.count; g += blockDim.x)
+        noffN[g] = noff[g] < n ? c.b.excl[noff[g]] : nc;
+    __syncthreads();
+    for (int g = threadIdx.x; g < c.b.count; g += blockDim.x) {
+        if (!c.b.active[g]) continue;
+        const int64_t ng = noff[g + 1] - noff[g], ngc = noffN[g + 1] - noffN[g];
+        if (ngc == ng) {   // no pair: the level just built is a copy, dropped
+            c.b.active[g] = 0;
+            c.b.coarsest[g] = l;
+            c.b.reason[g] = KAPPA_STOP_EMPTY;
+        } else if (c.b.stall_num > 0 &&
+                   (uint64_t)(ng - ngc) * c.b.stall_den < (uint64_t)c.b.stall_num * (uint64_t)ng) {
+            c.b.active[g] = 0;
+            c.b.coarsest[g] = l + 1;
+            c.b.reason[g] = KAPPA_STOP_STALL;
+        }
+    }
+}
+
+__global__ void batch_gid_k(const int32_t *noff, int32_t count, int32_t *gid) {
+    for (int32_t g = blockIdx.x; g < count; g += gridDim.x)
+        for (int32_t v = noff[g] + threadIdx.x; v < noff[g + 1]; v += blockDim.x) gid[v] = g;
+}
+
+// Rows ascend, so a row stays inside its graph iff its first and last entries do.
+__global__ void batch_check_k(DevGraph g, uint32_t *flags) {
+    bool bad = false;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = g.xadj[v], e = g.xadj[v + 1];
+        if (b == e) continue;
+        const int32_t q = g.gid[v];
+        if (g.adj[b] < g.noff[q] || g.adj[e - 1] >= g.noff[q + 1]) bad = true;
+    }
+    if (__ballot(bad) && lane_id() == 0) atomicOr(flags, 1u);
+}
+
+// One graph's level out of a batch level: node range [a, b) of the union,
+// entries from ea; ids made local (cmap relative to the graph's first node
+// on the next level, cbase; cmap null on the coarsest level).
+__global__ void batch_extract_k(DevGraph u, const int32_t *cmap, const int32_t *mate, int32_t a,
+                                int32_t b, int64_t ea, int32_t cbase, int64_t *xadj, int32_t *adj,
+                                uint32_t *ew, uint32_t *vw, int32_t *cmap_out, int32_t *mate_out) {
+    const int32_t n = b - a;
+    const int64_t nnz = u.xadj[b] - ea;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += stride) {
+        xadj[i] = u.xadj[a + i] - ea;
+        if (i == n) continue;
+        vw[i] = u.vw[a + i];
+        if (cmap) cmap_out[i] = cmap[a + i] - cbase;
+        if (mate) {
+            const int32_t m = mate[a + i];
+            mate_out[i] = m >= 0 ? m - a : -1;
+        }
+    }
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nnz; j += stride) {
+        adj[j] = u.adj[ea + j] - a;
+        ew[j] = u.ew[ea + j];
+    }
+}
+
+// ===========================================================================
 // Host side
 // ===========================================================================
 
@@ -1220,9 +1359,45 @@ void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, h
 
 void launch_level(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, int32_t n_cap,
                   int rounds, hipStream_t s) {
+    if (c.b.count) launch_batch_begin(c, l, s);
     // Out(v) of levels above 0 is written by the previous level's compaction
     launch_level_match(c, l, n_hint, nnz_cap, rounds, true, l == 0, s);
     launch_level_contract(c, l, n_hint, n_cap, s);
+    if (c.b.count) launch_batch_end(c, l, s);
+}
+
+void launch_batch_begin(const Ctx &c, int l, hipStream_t s) {
+    KAPPA_PROF("batch_begin", s);
+    hipLaunchKernelGGL(batch_begin_k, dim3(1), dim3(BATCH_THREADS), 0, s, c, l);
+}
+
+void launch_batch_end(const Ctx &c, int l, hipStream_t s) {
+    KAPPA_PROF("batch_end", s);
+    hipLaunchKernelGGL(batch_end_k, dim3(1), dim3(BATCH_THREADS), 0, s, c, l);
+}
+
+void launch_batch_gid(const int32_t *noff, int32_t count, int32_t *gid, hipStream_t s) {
+    if (count <= 0) return;
+    KAPPA_PROF("batch_gid", s);
+    hipLaunchKernelGGL(batch_gid_k, dim3(grid_for(count, 1, 8192)), dim3(BLOCK), 0, s, noff, count,
+                       gid);
+}
+
+void launch_batch_extract(const DevGraph &u, const int32_t *cmap, const int32_t *mate, int32_t a,
+                          int32_t b, int64_t ea, int64_t nnz, int32_t cbase, int64_t *xadj,
+                          int32_t *adj, uint32_t *ew, uint32_t *vw, int32_t *cmap_out,
+                          int32_t *mate_out, hipStream_t s) {
+    KAPPA_PROF("batch_extract", s);
+    hipLaunchKernelGGL(batch_extract_k, dim3(grid_for(std::max<int64_t>(nnz, b - a + 1), BLOCK, 4096)),
+                       dim3(BLOCK), 0, s, u, cmap, mate, a, b, ea, cbase, xadj, adj, ew, vw,
+                       cmap_out, mate_out);
+}
+
+void launch_batch_check(const DevGraph &g, uint32_t *flags, hipStream_t s) {
+    if (g.n <= 0) return;
+    KAPPA_PROF("batch_check", s);
+    hipLaunchKernelGGL(batch_check_k, dim3(grid_for(g.n, BLOCK, 4096)), dim3(BLOCK), 0, s, g,
+                       flags);
 }
 
 }  // namespace kappa

@@ -48,7 +48,17 @@ struct DevGraph {
     const int32_t *adj;
     const uint32_t *ew;
     const uint32_t *vw;
+    // batched form (a disjoint union of graphs; null for a single graph):
+    // graph of each node, first node of each graph at this level
+    const int32_t *gid = nullptr;
+    const int32_t *noff = nullptr;
 };
+
+// First node of v's graph: tie hashes use graph-local ids, so a graph's
+// hierarchy is the same alone and inside a batch.
+__device__ __forceinline__ int32_t local_base(const DevGraph &g, int32_t v) {
+    return g.gid ? g.noff[g.gid[v]] : 0;
+}
 
 // ---------------------------------------------------------------------------
 // SplitMix64 output function (Steele, Lea, Flood 2014), the tie-break hash.
@@ -62,6 +72,11 @@ __host__ __device__ inline uint64_t mix64(uint64_t z) {
 __host__ __device__ inline uint64_t edge_id(int32_t a, int32_t b) {
     uint32_t lo = (uint32_t)(a < b ? a : b), hi = (uint32_t)(a < b ? b : a);
     return ((uint64_t)lo << 32) | hi;
+}
+
+// The same with ids relative to `base` (the first node of the edge's graph).
+__host__ __device__ inline uint64_t edge_id_local(int32_t a, int32_t b, int32_t base) {
+    return edge_id(a - base, b - base);
 }
 
 // ---------------------------------------------------------------------------
@@ -493,6 +508,8 @@ struct LevelDesc {
     uint32_t *vw;
     int32_t *cmap;    // to the next level
     int32_t *mate;
+    int32_t *gid;     // batched form: graph of each node (null for a single graph)
+    int32_t *noff;    // batched form: first node of each graph, count + 1 entries
     int64_t matched;
     int32_t rounds, stop, phase, pad;
     int64_t stat[STAT_ROUNDS][2];   // per round: nodes with a free neighbour, their degree sum
@@ -550,6 +567,19 @@ struct ContractScratch {
     int64_t hub_words;
 };
 
+// Batched form: per-graph stop rules on a disjoint union of `count` graphs.
+// A graph that stops is frozen: its nodes neither match nor carry over to
+// the next level.
+struct BatchCtx {
+    int32_t count = 0;              // 0: a single graph
+    uint32_t stall_num = 0, stall_den = 1;
+    const int32_t *stop_n = nullptr;   // [count]
+    uint8_t *active = nullptr;         // [count] 1 while the graph coarsens
+    int32_t *coarsest = nullptr;       // [count] level of the graph's coarsest graph
+    int32_t *reason = nullptr;         // [count] kappa_stop of the graph
+    int32_t *excl = nullptr;           // [n] exclusive prefix of the coarse-id scan
+};
+
 struct Ctx {
     Control *ctrl;
     LevelDesc *lv;
@@ -558,6 +588,7 @@ struct Ctx {
     uint64_t seed;
     MatchScratch ms;
     ContractScratch cs;
+    BatchCtx b;
 };
 
 // K bump allocations in the arena with one read and one write of the cursor
@@ -644,6 +675,22 @@ void launch_level_out(const Ctx &c, int l, int64_t nnz_cap, int32_t n_hint, hipS
 // multi-block matching rounds before the one-workgroup finisher.
 void launch_level(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, int32_t n_cap,
                   int rounds, hipStream_t s);
+// Batched form, per level: per-graph size and level-count rules before the
+// level (ends the loop when no graph is left), and per-graph empty-matching
+// and stall rules once the coarse ids are known.
+void launch_batch_begin(const Ctx &c, int l, hipStream_t s);
+void launch_batch_end(const Ctx &c, int l, hipStream_t s);
+// Graph id of every node from the graphs' first nodes (noff, count + 1).
+void launch_batch_gid(const int32_t *noff, int32_t count, int32_t *gid, hipStream_t s);
+// flags |= 1 if some row of g has an entry outside its graph's node range.
+void launch_batch_check(const DevGraph &g, uint32_t *flags, hipStream_t s);
+// Copies nodes [a, b) of union level u (entries from ea, nnz of them) with
+// ids made local; cmap/mate (may be null) shifted as well.
+void launch_batch_extract(const DevGraph &u, const int32_t *cmap, const int32_t *mate, int32_t a,
+                          int32_t b, int64_t ea, int64_t nnz, int32_t cbase, int64_t *xadj,
+                          int32_t *adj, uint32_t *ew, uint32_t *vw, int32_t *cmap_out,
+                          int32_t *mate_out, hipStream_t s);
+
 // Matching only (first kernel: the level gate, which moves an idle level to
 // PH_MATCH unless a stop rule fires; stop_rules = false checks none), e.g.
 // for kappa_match.  out_kernels: compute Out(v) (innerOuter) from the graph;

@@ -34,6 +34,16 @@ def check_hierarchy(g, rating, seed, stop_n, stall=(1, 20), max_levels=64, k=2,
                         max_levels)
     OH = oracle_h or O.coarsen(g, rating, seed, stop_n, stall[0], stall[1], max_levels,
                                round_stats=check_rounds)
+    compare_hierarchy(H, OH, check_rounds=check_rounds, check_uncoarsen=check_uncoarsen, k=k,
+                      part_seed=part_seed, eps=eps, part0=part0)
+    return H, OH
+
+
+def compare_hierarchy(H, OH, check_rounds=True, check_uncoarsen=True, k=2, part_seed=1,
+                      eps=(3, 100), part0=None):
+    """Every level, map, matched count, stop reason (and, optionally, round
+    count, round statistics and the way back up) of the GPU hierarchy H
+    against the oracle hierarchy OH."""
     assert len(H) == len(OH.levels), f"levels {len(H)} != {len(OH.levels)}"
     for l, ol in enumerate(OH.levels):
         lv = H.level(l)
@@ -54,4 +64,3 @@ def check_hierarchy(g, rating, seed, stop_n, stall=(1, 20), max_levels=64, k=2,
         assert np.array_equal(part0.cpu().numpy(), oparts[0])
         for l in range(len(OH.levels)):
             assert res[l].as_tuple() == ores[l].as_tuple(), f"level {l}: cut/balance differs"
-    return H, OH

@@ -16,12 +16,15 @@ Recipes (the workload families of the partitioner's experiments, Section 6):
   * ``batch_graphs`` -- the uneven batch: n log-uniform, half degraded grids
                       (10 % of edges removed), half RGGs of mean degree 8,
                       node and edge weights uniform in [1, 16].
+  * ``union_graphs`` -- the block-diagonal union of a list of graphs (graph
+                      g's nodes follow those of graphs 0 .. g-1), the input
+                      layout of the batched form.
 """
 from __future__ import annotations
 
 import math
 from dataclasses import dataclass
-from typing import List, Optional
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -243,3 +246,27 @@ def batch_graphs(count: int = 4096, seed: int = 4, nmin: float = 1e3, nmax: floa
             sel = tmp.adj > src
             out.append(csr_from_edges(ng, src[sel], tmp.adj[sel].astype(np.int64), w, vw))
     return out
+
+
+def union_graphs(graphs: List[CSR]) -> Tuple[CSR, np.ndarray]:
+    """Block-diagonal union; returns it and node_off (int32, count + 1)."""
+    ns = np.array([g.n for g in graphs], dtype=np.int64)
+    es = np.array([g.nnz for g in graphs], dtype=np.int64)
+    node_off = np.zeros(len(graphs) + 1, dtype=np.int64)
+    node_off[1:] = np.cumsum(ns)
+    ent_off = np.zeros(len(graphs) + 1, dtype=np.int64)
+    ent_off[1:] = np.cumsum(es)
+    n = int(node_off[-1])
+    xadj = np.empty(n + 1, dtype=np.int64)
+    adj = np.empty(int(ent_off[-1]), dtype=np.int32)
+    ew = np.empty(int(ent_off[-1]), dtype=np.uint32)
+    vw = np.empty(n, dtype=np.uint32)
+    for i, g in enumerate(graphs):
+        a, b = int(node_off[i]), int(node_off[i + 1])
+        ea, eb = int(ent_off[i]), int(ent_off[i + 1])
+        xadj[a:b] = g.xadj[:-1] + ea
+        adj[ea:eb] = g.adj.astype(np.int64) + a
+        ew[ea:eb] = g.ew
+        vw[a:b] = g.vw
+    xadj[n] = int(ent_off[-1])
+    return CSR(n, xadj, adj, ew, vw), node_off.astype(np.int32)
