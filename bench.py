@@ -115,6 +115,9 @@ def main():
     ap.add_argument("--k", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-out", default=None)
+    ap.add_argument("--workload", default="rgg20", choices=["rgg20", "batch4096"],
+                    help="rgg20: the headline single-graph workload; batch4096: the batched "
+                         "form on 4096 uneven graphs, against a loop of single calls")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (3x) so that HBM byte counters "
                          "can be scaled against a kernel of known traffic")
@@ -129,6 +132,9 @@ def main():
 
     import paper_0910_2004_amd as K
     from workloads import rgg
+
+    if args.workload == "batch4096":
+        return bench_batch(args)
 
     n = 1 << args.scale
     k = args.k
@@ -249,6 +255,77 @@ def main():
         with open(args.profile_out, "w") as f:
             json.dump({"prof": prof, "model_bytes": mb, "levels": {str(r): lv[r] for r in ratings}},
                       f, indent=1)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    import numpy as np
+    """The batched form on 4096 graphs of uneven size (n log-uniform in
+    [1e3, 6.4e4]; half grids with 10 % of edges removed, half random
+    geometric graphs of mean degree 8; weights uniform in [1, 16];
+    expansion*2, stop at 256 nodes per graph).  A step is one
+    kappa_coarsen_batch call on the union (validation and every level of
+    every graph).  The same graphs coarsened one kappa_coarsen call at a time
+    (the plain path) are timed once beside it."""
+    import torch
+
+    import paper_0910_2004_amd as K
+    from workloads import batch_graphs, union_graphs
+
+    t0 = time.time()
+    graphs = batch_graphs(4096, seed=4, workers=min(16, os.cpu_count() or 1))
+    u, off = union_graphs(graphs)
+    edges = u.m
+    log(f"generated {len(graphs)} graphs, n={u.n} |E|={edges} in {time.time() - t0:.1f}s")
+    torch.cuda.set_device(0)
+    du = K.DeviceGraph.from_csr(u, "cuda:0")
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        B = K.kappa_coarsen_batch(du, off, 0, 4, 256)
+        del B
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        B = K.kappa_coarsen_batch(du, off, 0, 4, 256)
+        levels = [B.info(g)[0] for g in range(len(graphs))]
+        del B
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) * 1e3 / args.steps
+    # the plain path: one call per graph, graphs resident beforehand
+    sub = [K.DeviceGraph.from_csr(g, "cuda:0") for g in graphs]
+    torch.cuda.synchronize()
+    for dg in sub[:64]:
+        H = K.kappa_coarsen(dg, 0, 4, 256)
+        del H
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for dg in sub:
+        H = K.kappa_coarsen(dg, 0, 4, 256)
+        del H
+    torch.cuda.synchronize()
+    loop_ms = (time.perf_counter() - t2) * 1e3
+    out = {
+        "metric": "coarsening edges/s per GPU (batched form, 4096 graphs)",
+        "value": round(edges / (ms / 1e3), 1),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32/u64 (exact integer; 128-bit rating compares)",
+        "data": "synthetic",
+        "config": {"workload": "4096 graphs, n log-uniform [1e3, 6.4e4], half grids minus 10% "
+                               "of edges, half rgg mean degree 8, weights uniform [1, 16], "
+                               "expansion*2, stop n<=256 per graph",
+                   "graphs": len(graphs), "n": u.n, "m": edges, "seed": 4,
+                   "levels_max": int(max(levels)), "levels_mean": round(float(np.mean(levels)), 2)},
+        "plain_loop": {"ms": round(loop_ms, 1), "value": round(edges / (loop_ms / 1e3), 1),
+                       "unit": "edges/s", "kind": "one kappa_coarsen call per graph"},
+        "speedup_vs_plain_loop": round(loop_ms / ms, 2),
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -29,3 +29,30 @@ def test_rgg_2_20_full_hierarchy(rating):
     H, OH = check_hierarchy(g, rating, 42, stop_n=20 * 64, k=64)
     print("levels", [lv.graph.n for lv in OH.levels], flush=True)
     sys.stdout.flush()
+
+
+@pytest.mark.timeout(900)
+def test_batch_4096_sampled_graphs():
+    """The batched workload at full size (4096 uneven graphs, one union):
+    a sample of graphs (smallest, largest, both ends, random ones) compared
+    with the oracle on each graph alone, every level and the way back up."""
+    import os
+
+    import numpy as np
+
+    import paper_0910_2004_amd as K
+    from gpu_util import compare_hierarchy, dev
+    from workloads import batch_graphs, union_graphs
+    graphs = batch_graphs(4096, seed=4, workers=min(16, os.cpu_count() or 1))
+    u, off = union_graphs(graphs)
+    print(f"batch n={u.n} m={u.m}", flush=True)
+    B = K.kappa_coarsen_batch(dev(u), off, O.EXPANSION_STAR2, 4, 256)
+    sizes = np.array([g.n for g in graphs])
+    rng = np.random.default_rng(0)
+    sample = sorted(set(rng.choice(len(graphs), 20, replace=False).tolist())
+                    | {0, 1, len(graphs) - 1, int(sizes.argmax()), int(sizes.argmin())})
+    for g in sample:
+        OH = O.coarsen(graphs[g], O.EXPANSION_STAR2, 4, 256, 1, 20, 64)
+        assert B.info(g) == (len(OH.levels), OH.levels[-1].stop_reason), f"graph {g}"
+        compare_hierarchy(B.hierarchy(g), OH, check_rounds=False, check_uncoarsen=True, k=8)
+        print(f"graph {g}: n={graphs[g].n} levels={len(OH.levels)} ok", flush=True)

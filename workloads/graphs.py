@@ -223,29 +223,34 @@ def complete_graph(n: int, w=None) -> CSR:
     return csr_from_edges(n, a, b, None if w is None else np.asarray(w, dtype=np.uint32))
 
 
+def _batch_member(seed: int, g: int, ng: int, wmax: int) -> CSR:
+    rng = np.random.Generator(np.random.PCG64([seed, g]))
+    if g % 2 == 0:
+        rows = max(2, int(round(math.sqrt(ng))))
+        cols = max(2, int(round(ng / rows)))
+        return degrade_grid(rows, cols, 0.1, rng, wmax)
+    pts = rng.random((ng, 2))
+    tmp = rgg(ng, 0, points=pts)
+    w = rng.integers(1, wmax + 1, size=tmp.m, dtype=np.int64).astype(np.uint32)
+    vw = rng.integers(1, wmax + 1, size=ng, dtype=np.int64).astype(np.uint32)
+    # re-weight: the edge list of tmp in (min,max) order
+    src = np.repeat(np.arange(ng, dtype=np.int64), np.diff(tmp.xadj))
+    sel = tmp.adj > src
+    return csr_from_edges(ng, src[sel], tmp.adj[sel].astype(np.int64), w, vw)
+
+
 def batch_graphs(count: int = 4096, seed: int = 4, nmin: float = 1e3, nmax: float = 6.4e4,
-                 wmax: int = 16) -> List[CSR]:
-    """The uneven batch (see module doc).  Graph g uses sub-seed (seed, g)."""
-    out = []
+                 wmax: int = 16, workers: int = 1) -> List[CSR]:
+    """The uneven batch (see module doc).  Graph g uses sub-seed (seed, g), so
+    the result does not depend on `workers` (processes generating it)."""
     top = np.random.Generator(np.random.PCG64(seed))
     sizes = np.rint(np.exp(top.uniform(math.log(nmin), math.log(nmax), size=count))).astype(np.int64)
-    for g in range(count):
-        rng = np.random.Generator(np.random.PCG64([seed, g]))
-        ng = int(sizes[g])
-        if g % 2 == 0:
-            rows = max(2, int(round(math.sqrt(ng))))
-            cols = max(2, int(round(ng / rows)))
-            out.append(degrade_grid(rows, cols, 0.1, rng, wmax))
-        else:
-            pts = rng.random((ng, 2))
-            tmp = rgg(ng, 0, points=pts)
-            w = rng.integers(1, wmax + 1, size=tmp.m, dtype=np.int64).astype(np.uint32)
-            vw = rng.integers(1, wmax + 1, size=ng, dtype=np.int64).astype(np.uint32)
-            # re-weight: the edge list of tmp in (min,max) order
-            src = np.repeat(np.arange(ng, dtype=np.int64), np.diff(tmp.xadj))
-            sel = tmp.adj > src
-            out.append(csr_from_edges(ng, src[sel], tmp.adj[sel].astype(np.int64), w, vw))
-    return out
+    args = [(seed, g, int(sizes[g]), wmax) for g in range(count)]
+    if workers <= 1:
+        return [_batch_member(*a) for a in args]
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_batch_member, *zip(*args), chunksize=16))
 
 
 def union_graphs(graphs: List[CSR]) -> Tuple[CSR, np.ndarray]:
