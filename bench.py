@@ -115,9 +115,11 @@ def main():
     ap.add_argument("--k", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-out", default=None)
-    ap.add_argument("--workload", default="rgg20", choices=["rgg20", "batch4096"],
+    ap.add_argument("--workload", default="rgg20", choices=["rgg20", "batch4096", "serve"],
                     help="rgg20: the headline single-graph workload; batch4096: the batched "
-                         "form on 4096 uneven graphs, against a loop of single calls")
+                         "form on 4096 uneven graphs, against a loop of single calls; serve: "
+                         "the served form on a Poisson request stream, against FIFO single calls")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (3x) so that HBM byte counters "
                          "can be scaled against a kernel of known traffic")
@@ -135,6 +137,8 @@ def main():
 
     if args.workload == "batch4096":
         return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     n = 1 << args.scale
     k = args.k
@@ -270,15 +274,14 @@ def bench_batch(args):
     import torch
 
     import paper_0910_2004_amd as K
-    from workloads import batch_graphs, union_graphs
+    from workloads import batch_graphs
 
     t0 = time.time()
     graphs = batch_graphs(4096, seed=4, workers=min(16, os.cpu_count() or 1))
-    u, off = union_graphs(graphs)
-    edges = u.m
-    log(f"generated {len(graphs)} graphs, n={u.n} |E|={edges} in {time.time() - t0:.1f}s")
     torch.cuda.set_device(0)
-    du = K.DeviceGraph.from_csr(u, "cuda:0")
+    du, off = K.DeviceGraph.union(graphs, "cuda:0")
+    edges = du.nnz // 2
+    log(f"generated {len(graphs)} graphs, n={du.n} |E|={edges} in {time.time() - t0:.1f}s")
     torch.cuda.synchronize()
     for _ in range(args.warmup):
         B = K.kappa_coarsen_batch(du, off, 0, 4, 256)
@@ -320,11 +323,69 @@ def bench_batch(args):
         "config": {"workload": "4096 graphs, n log-uniform [1e3, 6.4e4], half grids minus 10% "
                                "of edges, half rgg mean degree 8, weights uniform [1, 16], "
                                "expansion*2, stop n<=256 per graph",
-                   "graphs": len(graphs), "n": u.n, "m": edges, "seed": 4,
+                   "graphs": len(graphs), "n": du.n, "m": edges, "seed": 4,
                    "levels_max": int(max(levels)), "levels_mean": round(float(np.mean(levels)), 2)},
         "plain_loop": {"ms": round(loop_ms, 1), "value": round(edges / (loop_ms / 1e3), 1),
                        "unit": "edges/s", "kind": "one kappa_coarsen call per graph"},
         "speedup_vs_plain_loop": round(loop_ms / ms, 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """The served form: `--requests` requests of the served mix (|E|
+    log-uniform in [1e3, 4e6]; grids, random geometric graphs and R-MAT;
+    rating, k in {2, 8, 32, 64}, stop at 20 k, eps 3/100), generated before
+    the clock starts.  The plain path (one request at a time) is first run
+    with every request present to find its sustainable rate; then both paths
+    serve the same Poisson arrival trace at 0.7 of that rate.  Latency is
+    completion minus scheduled arrival; edges/s is all edges over first
+    arrival to last completion."""
+    import numpy as np
+    import torch
+
+    from paper_0910_2004_amd.serve import BatchServer, Request, latency_stats, serve_plain
+    from workloads import serve_requests
+
+    t0 = time.time()
+    mix = serve_requests(args.requests, seed=5, workers=min(16, os.cpu_count() or 1))
+    log(f"generated {len(mix)} requests, |E| total {sum(g.m for g, _, _ in mix)} "
+        f"in {time.time() - t0:.1f}s")
+    torch.cuda.set_device(0)
+    reqs = [Request(i, g, rating, k) for i, (g, rating, k) in enumerate(mix)]
+    serve_plain(reqs[:32])   # warm up
+    t1 = time.perf_counter()
+    serve_plain(reqs)
+    rate = len(reqs) / (time.perf_counter() - t1)
+    lam = 0.7 * rate
+    gaps = np.random.default_rng(5).exponential(1.0 / lam, size=len(reqs))
+    arrivals = np.cumsum(gaps) - gaps[0]
+    trace = [Request(r.rid, r.graph, r.rating, r.k, arrival=float(arrivals[i]))
+             for i, r in enumerate(reqs)]
+    log(f"plain path sustains {rate:.1f} req/s; trace at {lam:.1f} req/s")
+    plain = latency_stats(trace, serve_plain(trace))
+    log(f"plain: {plain}")
+    served = latency_stats(trace, BatchServer(workers=2).run(trace))
+    log(f"served: {served}")
+    out = {
+        "metric": "served coarsening: aggregate edges/s per GPU, p50/p99 latency",
+        "value": served["edges_per_s"],
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": round(served["span_s"] * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32/u64 (exact integer; 128-bit rating compares)",
+        "data": "synthetic",
+        "config": {"workload": "served mix: |E| log-uniform [1e3, 4e6], grid/rgg/rmat, "
+                               "expansion*2 or innerOuter, k in {2,8,32,64}, stop 20k, "
+                               "eps 3/100, Poisson arrivals at 0.7 x the plain path's rate",
+                   "requests": len(trace), "rate_req_s": round(lam, 2), "seed": 5},
+        "served": served,
+        "plain": plain,
     }
     print(json.dumps(out), flush=True)
 

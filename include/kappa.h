@@ -204,8 +204,10 @@ void kappa_hierarchy_free(kappa_hierarchy *h);
    hierarchy equals what kappa_coarsen gives for that graph alone with the
    same parameters (tie hashes use graph-local ids; the size, empty-matching
    and stall rules and max_levels apply per graph).  Returns KAPPA_E_GRAPH if
-   an edge joins two graphs, else as kappa_coarsen.  Synchronous; the batch is
-   library-owned (kappa_batch_free). */
+   an edge joins two graphs, else as kappa_coarsen; the 32-bit limits of
+   kappa_validate on the total edge weight and the total node weight apply to
+   the union as a whole (a caller batches graphs whose sums fit).
+   Synchronous; the batch is library-owned (kappa_batch_free). */
 typedef struct kappa_batch kappa_batch;
 kappa_status kappa_coarsen_batch(const kappa_graph *u, int32_t count, const int32_t *node_off,
                                  const int32_t *stop_n, const kappa_coarsen_params *p,
@@ -276,6 +278,15 @@ kappa_status kappa_cache_release(void);
    on = 0 (the default, measured faster on gfx950) launches every kernel
    directly.  Results do not depend on it. */
 void kappa_graphs_enable(int32_t on);
+
+/* Arena size of the first attempt of kappa_coarsen and kappa_coarsen_batch,
+   in bytes, for every later call in the process (0, the default: sized from
+   level 0, about three times its arrays).  When nonzero, the levels of the
+   first attempt must fit in exactly that many bytes (raised to what level 0
+   itself needs); a call whose levels do not fit starts again with four times
+   the arena, up to five times.  Results do not depend on it: it exists to
+   exercise the arena-overflow path at chosen levels. */
+void kappa_arena_first(uint64_t bytes);
 
 const char *kappa_status_str(kappa_status st);
 const char *kappa_version(void);

@@ -72,12 +72,18 @@ def declared_functions() -> List[str]:
 
 
 def lib():
-    """Loads libkappa.so.  Raises if it is missing: there is no fallback."""
+    """Loads libkappa.so.  Raises if it is missing: there is no fallback.
+
+    torch is imported first: its wheel carries its own HIP runtime, and the
+    library must bind to that one (libamdhip64.so.7 already in the process)
+    rather than load a second runtime from /opt/rocm, whose device memory and
+    streams torch's tensors and streams would not belong to."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_0910_2004_amd/build.py")
+    import torch  # noqa: F401  (loads torch's HIP runtime before the library)
     L = ctypes.CDLL(LIB_PATH)
     P, i32, i64, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
     st = ctypes.c_int
@@ -110,6 +116,7 @@ def lib():
         "kappa_batch_free": (None, [P]),
         "kappa_cache_release": (st, []),
         "kappa_graphs_enable": (None, [i32]),
+        "kappa_arena_first": (None, [u64]),
         "kappa_status_str": (ctypes.c_char_p, [st]),
         "kappa_version": (ctypes.c_char_p, []),
     }
@@ -151,6 +158,7 @@ _hip = None
 def _hip_rt():
     global _hip
     if _hip is None:
+        lib()   # the runtime the library is bound to, not a second one
         _hip = ctypes.CDLL("libamdhip64.so")
         _hip.hipMemcpyAsync.restype = ctypes.c_int
         _hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
@@ -197,6 +205,19 @@ class DeviceGraph:
         ew = torch.from_numpy(np.ascontiguousarray(g.ew).astype(np.uint32).view(np.int32)).to(device)
         vw = torch.from_numpy(np.ascontiguousarray(g.vw).astype(np.uint32).view(np.int32)).to(device)
         return DeviceGraph(int(g.n), int(g.xadj[-1]), xadj, adj, ew, vw)
+
+    @staticmethod
+    def union(graphs, device="cuda"):
+        """The block-diagonal union of host graphs on the device, and its
+        node_off (the batched form's input)."""
+        import numpy as np
+        import torch
+        n, xadj, adj, ew, vw, off = union_csr(graphs)
+        dg = DeviceGraph(n, int(xadj[-1]), torch.from_numpy(xadj).to(device),
+                         torch.from_numpy(adj).to(device),
+                         torch.from_numpy(ew.view(np.int32)).to(device),
+                         torch.from_numpy(vw.view(np.int32)).to(device))
+        return dg, off
 
     def numpy(self):
         """(xadj, adj, ew, vw) as numpy arrays (ew, vw as uint32)."""
@@ -317,6 +338,34 @@ def kappa_coarsen(g: DeviceGraph, rating: int = EXPANSION_STAR2, seed: int = 42,
     return Hierarchy(h, g.xadj.device, g)
 
 
+def union_csr(graphs):
+    """Block-diagonal union of host CSR graphs (objects with n, xadj, adj, ew,
+    vw numpy arrays), the input layout of the batched form: graph g's nodes
+    follow those of graphs 0 .. g-1.  Returns (n, xadj, adj, ew, vw,
+    node_off) as numpy arrays (node_off int32, count + 1)."""
+    import numpy as np
+    ns = np.array([int(g.n) for g in graphs], dtype=np.int64)
+    es = np.array([int(g.xadj[-1]) if len(g.xadj) else 0 for g in graphs], dtype=np.int64)
+    node_off = np.zeros(len(graphs) + 1, dtype=np.int64)
+    node_off[1:] = np.cumsum(ns)
+    ent_off = np.zeros(len(graphs) + 1, dtype=np.int64)
+    ent_off[1:] = np.cumsum(es)
+    n = int(node_off[-1])
+    xadj = np.empty(n + 1, dtype=np.int64)
+    adj = np.empty(int(ent_off[-1]), dtype=np.int32)
+    ew = np.empty(int(ent_off[-1]), dtype=np.uint32)
+    vw = np.empty(n, dtype=np.uint32)
+    for i, g in enumerate(graphs):
+        a, b = int(node_off[i]), int(node_off[i + 1])
+        ea, eb = int(ent_off[i]), int(ent_off[i + 1])
+        xadj[a:b] = np.asarray(g.xadj[:-1], dtype=np.int64) + ea
+        adj[ea:eb] = np.asarray(g.adj, dtype=np.int64) + a
+        ew[ea:eb] = g.ew
+        vw[a:b] = g.vw
+    xadj[n] = int(ent_off[-1])
+    return n, xadj, adj, ew, vw, node_off.astype(np.int32)
+
+
 class Batch:
     """Owns a kappa_batch handle (freed with the object); keeps the union
     graph alive (level 0 of the batch refers to its arrays)."""
@@ -350,7 +399,7 @@ class Batch:
         h = ctypes.c_void_p()
         _check("kappa_batch_hierarchy", lib().kappa_batch_hierarchy(self.handle, g, ctypes.byref(h),
                                                                     _stream()))
-        return Hierarchy(h, self.device, self)
+        return Hierarchy(h, self.device)   # a copy: independent of the batch
 
 
 def kappa_coarsen_batch(u: DeviceGraph, node_off, rating: int = EXPANSION_STAR2, seed: int = 42,
@@ -423,8 +472,15 @@ def kappa_cache_release():
 
 
 def graphs_enable(on: bool = True):
-    """Replay repeated launch sequences as HIP graphs (default) or launch directly."""
+    """Replay repeated launch sequences as HIP graphs (on) or launch every
+    kernel directly (off, the library's default)."""
     lib().kappa_graphs_enable(1 if on else 0)
+
+
+def arena_first(nbytes: int = 0):
+    """First-attempt arena size of kappa_coarsen / kappa_coarsen_batch (0:
+    the default sizing); a tight value sends calls through the retry path."""
+    lib().kappa_arena_first(int(nbytes))
 
 
 def profile_enable(on: bool = True):

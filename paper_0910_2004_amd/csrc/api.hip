@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -114,6 +115,14 @@ extern "C" int32_t kappa_profile_read(const char **names, int64_t *launches, dou
 // ===========================================================================
 namespace {
 
+bool debug_on();
+
+// Under KAPPA_DEBUG, names a failed allocation on stderr.
+void alloc_failed(const char *what, size_t bytes, hipError_t e) {
+    if (debug_on())
+        fprintf(stderr, "kappa: %s of %zu bytes failed: %s\n", what, bytes, hipGetErrorString(e));
+}
+
 std::once_flag g_pool_once;
 
 void pool_init() {
@@ -194,7 +203,11 @@ struct Workspace {
             c->ws_bytes = 0;
             size_t want = bytes + bytes / 4 + 4096;
             void *p = nullptr;
-            if (hipMallocAsync(&p, want, s) != hipSuccess || !p) return;
+            const hipError_t e = hipMallocAsync(&p, want, s);
+            if (e != hipSuccess || !p) {
+                alloc_failed("workspace", want, e);
+                return;
+            }
             c->ws = (char *)p;
             c->ws_bytes = want;
         }
@@ -233,7 +246,11 @@ void *take_arena(hipStream_t s, size_t bytes, size_t *got) {
     }
     pool_init();
     void *p = nullptr;
-    if (hipMallocAsync(&p, bytes, s) != hipSuccess || !p) return nullptr;
+    const hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e != hipSuccess || !p) {
+        alloc_failed("arena", bytes, e);
+        return nullptr;
+    }
     *got = bytes;
     return p;
 }
@@ -330,6 +347,10 @@ hipError_t run_seq(StreamCache *c, hipStream_t s, const std::vector<uint64_t> &k
 
 inline uint64_t pkey(const void *p) { return (uint64_t)(uintptr_t)p; }
 
+// First-attempt arena size of kappa_coarsen / kappa_coarsen_batch (0: sized
+// from level 0), with the cursor capped at exactly that size.
+std::atomic<uint64_t> g_arena_first{0};
+
 // Returns an arena to the stream's cache unless released to a hierarchy.
 struct ArenaHold {
     hipStream_t s;
@@ -352,7 +373,11 @@ void *pinned(size_t bytes, PinnedRegion region = PIN_SMALL) {
     if (bytes > PIN_REGION_BYTES) return nullptr;
     if (!buf) {
         void *p = nullptr;
-        if (hipHostMalloc(&p, 3 * PIN_REGION_BYTES, hipHostMallocDefault) != hipSuccess) return nullptr;
+        const hipError_t e = hipHostMalloc(&p, 3 * PIN_REGION_BYTES, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            alloc_failed("pinned host buffer", 3 * PIN_REGION_BYTES, e);
+            return nullptr;
+        }
         buf = (char *)p;
     }
     return buf + (size_t)region * PIN_REGION_BYTES;
@@ -532,9 +557,6 @@ struct kappa_hierarchy {
 
 namespace {
 
-// One attempt at the whole contraction phase with a given arena size.
-// Returns KAPPA_OK and fills H, or a status; *retry_flags gets the control
-// flags asking for another attempt (arena too small, hub accumulators).
 // Inputs of the batched form (a disjoint union of `count` graphs).
 struct BatchIn {
     int32_t count;
@@ -547,9 +569,16 @@ struct BatchOut {
     std::vector<int32_t> coarsest, reason;    // per graph
 };
 
+// One attempt at the whole contraction phase with an arena of *arena_io
+// bytes (raised to at least what level 0 needs; the size used is written
+// back).  exact_cap: the device cursor stops at that size even if a larger
+// recycled arena is handed out.  Returns KAPPA_OK and fills H, or a status;
+// *retry_flags gets the control flags asking for another attempt (arena too
+// small, hub accumulators).
 kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_coarsen_params *p,
-                             hipStream_t s, uint64_t arena_bytes, bool hubs, const BatchIn *bi,
-                             kappa_hierarchy *H, BatchOut *bo, uint32_t *retry_flags) {
+                             hipStream_t s, uint64_t *arena_io, bool exact_cap, bool hubs,
+                             const BatchIn *bi, kappa_hierarchy *H, BatchOut *bo,
+                             uint32_t *retry_flags) {
     *retry_flags = 0;
     Ctx c;
     c.rating = p->rating;
@@ -576,11 +605,19 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
             }
         }))
         return KAPPA_E_NOMEM;
+    // level 0's mate and cmap (and, batched, its graph ids and offsets)
+    // open the arena
+    const uint64_t n_al = ((uint64_t)d0.n * 4 + 255) & ~(uint64_t)255;
+    const uint64_t g_al = ((uint64_t)(count + 1) * 4 + 255) & ~(uint64_t)255;
+    const uint64_t opening = bi ? 3 * n_al + g_al : 2 * n_al;
+    const uint64_t arena_bytes = std::max<uint64_t>(*arena_io, opening);
+    *arena_io = arena_bytes;
     size_t arena_got = 0;
     void *arena = take_arena(s, arena_bytes, &arena_got);
     if (!arena) return KAPPA_E_NOMEM;
-    arena_bytes = arena_got;
-    ArenaHold hold{s, arena, arena_bytes};
+    // a recycled arena may be larger than asked for: all of it is usable
+    const uint64_t cap = exact_cap ? arena_bytes : arena_got;
+    ArenaHold hold{s, arena, arena_got};
     fill_scratch(d0, c, s);
 
     // control block and level 0
@@ -593,14 +630,10 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     in->ctrl.done = 0;
     in->ctrl.nlevels = 1;
     in->ctrl.flags = 0;
-    // level 0's mate and cmap (and, batched, its graph ids and offsets)
-    // open the arena
-    const uint64_t n_al = ((uint64_t)d0.n * 4 + 255) & ~(uint64_t)255;
-    const uint64_t g_al = ((uint64_t)(count + 1) * 4 + 255) & ~(uint64_t)255;
     int32_t *gid0 = bi ? (int32_t *)((char *)arena + 2 * n_al) : nullptr;
     int32_t *noff0 = bi ? (int32_t *)((char *)arena + 3 * n_al) : nullptr;
-    in->ctrl.cursor = bi ? 3 * n_al + g_al : 2 * n_al;
-    in->ctrl.cap = arena_bytes;
+    in->ctrl.cursor = opening;
+    in->ctrl.cap = cap;
     in->ctrl.base = (char *)arena;
     // batched: size and stall rules apply per graph (batch_begin / batch_end)
     in->ctrl.stop_n = bi ? -1 : p->stop_n;
@@ -738,7 +771,7 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
             }
     }
     H->arena = hold.release();
-    H->arena_bytes = arena_bytes;
+    H->arena_bytes = arena_got;
     return KAPPA_OK;
 }
 
@@ -793,11 +826,16 @@ extern "C" kappa_status kappa_coarsen(const kappa_graph *g, const kappa_coarsen_
     // arena: every level's nodes (vw, xadj, mate, cmap: 24 B) and entries
     // (adj, ew: 8 B), three times level 0 to start with
     uint64_t lvl0 = (uint64_t)d0.n * 24 + (uint64_t)d0.nnz * 8 + 4096;
-    uint64_t arena = 3 * lvl0 + (1u << 20);
+    const uint64_t forced = g_arena_first.load();
+    uint64_t arena = forced ? forced : 3 * lvl0 + (1u << 20);
     bool hubs = 2 * (int64_t)maxdeg - 2 > ROW_MID_MAX / 8;
     for (int attempt = 0; attempt < 6; ++attempt) {
         uint32_t retry = 0;
-        st = coarsen_attempt(d0, maxdeg, p, s, arena, hubs, nullptr, H, nullptr, &retry);
+        st = coarsen_attempt(d0, maxdeg, p, s, &arena, forced != 0, hubs, nullptr, H, nullptr,
+                             &retry);
+        if (debug_on())
+            fprintf(stderr, "kappa: coarsen attempt %d arena %llu: status %d, retry flags 0x%x\n",
+                    attempt, (unsigned long long)arena, (int)st, retry);
         if (st == KAPPA_OK) break;
         if (!retry) break;
         if (retry & CF_ARENA) arena *= 4;
@@ -848,11 +886,16 @@ extern "C" kappa_status kappa_coarsen_batch(const kappa_graph *u, int32_t count,
     // arena: every level's nodes (vw, xadj, mate, cmap, graph id: 28 B),
     // entries (8 B) and graph offsets, three times level 0 to start with
     uint64_t lvl0 = (uint64_t)d0.n * 28 + (uint64_t)d0.nnz * 8 + (uint64_t)(count + 1) * 4 + 8192;
-    uint64_t arena = 3 * lvl0 + (uint64_t)(count + 1) * 4 * 64 + (1u << 20);
+    const uint64_t forced = g_arena_first.load();
+    uint64_t arena = forced ? forced : 3 * lvl0 + (uint64_t)(count + 1) * 4 * 64 + (1u << 20);
     bool hubs = 2 * (int64_t)maxdeg - 2 > ROW_MID_MAX / 8;
     for (int attempt = 0; attempt < 6; ++attempt) {
         uint32_t retry = 0;
-        st = coarsen_attempt(d0, maxdeg, p, s, arena, hubs, &bi, &B->union_h, &B->out, &retry);
+        st = coarsen_attempt(d0, maxdeg, p, s, &arena, forced != 0, hubs, &bi, &B->union_h,
+                             &B->out, &retry);
+        if (debug_on())
+            fprintf(stderr, "kappa: batch attempt %d arena %llu: status %d, retry flags 0x%x\n",
+                    attempt, (unsigned long long)arena, (int)st, retry);
         if (st == KAPPA_OK) break;
         if (!retry) break;
         if (retry & CF_ARENA) arena *= 4;
@@ -1291,6 +1334,8 @@ extern "C" kappa_status kappa_cache_release(void) {
 }
 
 extern "C" void kappa_graphs_enable(int32_t on) { g_graphs_on = on != 0; }
+
+extern "C" void kappa_arena_first(uint64_t bytes) { g_arena_first.store(bytes); }
 
 extern "C" const char *kappa_status_str(kappa_status st) {
     switch (st) {

@@ -375,13 +375,17 @@ __global__ void __launch_bounds__(BLOCK) scan_apply_k(F f, W w, const int64_t *w
 // The same scan in one workgroup, for short inputs (no second launch, no
 // arrival counter): items held in registers when n <= ONE_SCAN_CHUNK, else
 // a reduction pass, post(), then chunked scan-and-apply passes.  post()
-// runs (thread 0) before any apply, as in the two-kernel form.
+// runs (thread 0) before any apply, as in the two-kernel form, and the apply
+// runs only if size() is still positive afterwards (as the apply kernel of
+// the two-kernel form checks): a post() whose arena allocation failed leaves
+// null output pointers and ends the level.
 constexpr int ONE_SCAN_THREADS = 1024, ONE_SCAN_ITEMS = 16;
 constexpr int64_t ONE_SCAN_CHUNK = (int64_t)ONE_SCAN_THREADS * ONE_SCAN_ITEMS;
 
 template <class F, class W>
 __global__ void __launch_bounds__(ONE_SCAN_THREADS) scan_one_block_k(F f, W w, int64_t *total) {
     __shared__ int64_t sh[ONE_SCAN_THREADS / WAVE + 1];
+    __shared__ int go;
     const int64_t n = f.size();
     if (n < 0) return;
     const int64_t first = (int64_t)threadIdx.x * ONE_SCAN_ITEMS;
@@ -398,8 +402,10 @@ __global__ void __launch_bounds__(ONE_SCAN_THREADS) scan_one_block_k(F f, W w, i
         if (threadIdx.x == 0) {
             if (total) *total = tot;
             f.post(tot);
+            go = f.size() > 0;   // post() may end the level (allocation failed, stop rule)
         }
         __syncthreads();
+        if (!go) return;
         const auto wb = w.bind();
         typename W::Pre pf[ONE_SCAN_ITEMS];
 #pragma unroll
@@ -419,8 +425,10 @@ __global__ void __launch_bounds__(ONE_SCAN_THREADS) scan_one_block_k(F f, W w, i
     if (threadIdx.x == 0) {
         if (total) *total = tot;
         f.post(tot);
+        go = f.size() > 0;
     }
     __syncthreads();
+    if (!go) return;
     const auto wb = w.bind();
     int64_t run = 0;
     for (int64_t base = 0; base < n; base += ONE_SCAN_CHUNK) {

@@ -1,0 +1,237 @@
+"""Served form: continuous batching of coarsening requests.
+
+A request is one graph (host CSR) with its rating, k, stop size (20 k by
+default, as in the experiments' 20 nodes per block) and balance tolerance.
+Whenever a worker is free, the dispatcher takes the requests that have
+arrived -- those with the oldest waiting request's rating and seed, in
+arrival order -- until the batch's estimated device footprint reaches the
+worker's budget or its union's weight sums would leave 32 bits, and hands
+them over.  A worker (one host thread, one HIP
+stream) uploads their union, coarsens all of them together
+(kappa_coarsen_batch), then runs each request's way back up (stand-in
+partition, projection, cut and balance) on its own hierarchy.  Workers run
+concurrently, so batches overlap on the device; requests arriving meanwhile
+wait only for the next free worker.  Each result keeps its hierarchy resident
+on the device when asked to.
+
+`serve_plain` is the reference service: one request at a time, in arrival
+order, through kappa_coarsen and kappa_uncoarsen.
+"""
+from __future__ import annotations
+
+import queue
+import threading
+import time
+from collections import deque
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+from . import _lib as K
+
+
+@dataclass
+class Request:
+    rid: int
+    graph: object          # host CSR (workloads.CSR)
+    rating: int
+    k: int
+    arrival: float = 0.0   # seconds after the start of the trace
+    seed: int = 42
+    stop_n: int = 0        # 0: 20 * k
+    eps: tuple = (3, 100)
+    part_seed: int = 1
+
+    @property
+    def stop(self) -> int:
+        return self.stop_n if self.stop_n > 0 else 20 * self.k
+
+
+@dataclass
+class Result:
+    rid: int
+    levels: int
+    stop_reason: int
+    cut: tuple                  # level 0 cut/balance (kappa_cut_result fields)
+    start: float                # when its batch started (trace clock)
+    done: float                 # completion (trace clock)
+    batch: int                  # requests served together with it (itself included)
+    hierarchy: object = None    # the device-resident hierarchy (keep=True)
+
+    def latency(self, arrival: float) -> float:
+        return self.done - arrival
+
+
+def footprint(g) -> int:
+    """Estimated device bytes of one request inside a batch: input, matching
+    and contraction scratch, and the hierarchy (about three times level 0)."""
+    return 140 * int(g.n) + 44 * int(g.nnz) + (1 << 16)
+
+
+WEIGHT_CAP = (1 << 32) - 1   # the union's sum of w over E and sum of c over V
+
+
+def weight_sums(g) -> tuple:
+    """(sum of w over E, sum of c over V) of a host graph: a batch's union
+    must keep both within 32 bits."""
+    import numpy as np
+    return int(np.asarray(g.ew, dtype=np.uint64).sum()) // 2, int(np.asarray(g.vw, dtype=np.uint64).sum())
+
+
+def _finish(r: Request, H, t0: float, start: float, batch: int, keep: bool) -> Result:
+    import torch
+    n0 = int(H.info(0).n)
+    part0 = torch.empty(max(n0, 1), dtype=torch.int32, device=H.device)
+    _, res = K.kappa_uncoarsen(H, r.k, r.part_seed, r.eps[0], r.eps[1], part0=part0)
+    levels = len(H)
+    stop = int(H.info(levels - 1).stop_reason)
+    return Result(r.rid, levels, stop, res[0].as_tuple(), start, time.perf_counter() - t0, batch,
+                  H if keep else None)
+
+
+def _wait_until(t0: float, at: float):
+    d = at - (time.perf_counter() - t0)
+    if d > 0:
+        time.sleep(d)
+
+
+def serve_plain(requests: Sequence[Request], device="cuda", keep: bool = False,
+                t0: Optional[float] = None) -> List[Result]:
+    """One request at a time, in arrival order."""
+    import torch
+    out = []
+    t0 = time.perf_counter() if t0 is None else t0
+    for r in sorted(requests, key=lambda q: q.arrival):
+        _wait_until(t0, r.arrival)
+        start = time.perf_counter() - t0
+        dg = K.DeviceGraph.from_csr(r.graph, device)
+        H = K.kappa_coarsen(dg, r.rating, r.seed, r.stop)
+        out.append(_finish(r, H, t0, start, 1, keep))
+    torch.cuda.synchronize()
+    return out
+
+
+def take_batch(arrived: Sequence[Request], budget: int, max_batch: int, sums: dict):
+    """The next batch out of the arrived requests (in arrival order): those
+    with the first one's rating and seed, as long as the estimated footprint
+    stays within `budget`, the count within `max_batch` and the union's weight
+    sums within 32 bits (the first request is always taken).  `sums` caches
+    weight_sums per request id.  Returns (batch, the requests left)."""
+    key = (arrived[0].rating, arrived[0].seed)
+    batch, rest, used, uw, uc = [], [], 0, 0, 0
+    for r in arrived:
+        if r.rid not in sums:
+            sums[r.rid] = weight_sums(r.graph)
+        w, c = sums[r.rid]
+        fp = footprint(r.graph)
+        fits = (used + fp <= budget and uw + w <= WEIGHT_CAP and uc + c <= WEIGHT_CAP and
+                len(batch) < max_batch)
+        if (r.rating, r.seed) == key and (not batch or fits):
+            batch.append(r)
+            used += fp
+            uw += w
+            uc += c
+        else:
+            rest.append(r)
+    return batch, rest
+
+
+class BatchServer:
+    """Continuous batching over `workers` concurrent workers."""
+
+    def __init__(self, workers: int = 2, budget_bytes: int = 24 << 30, max_batch: int = 512,
+                 device="cuda"):
+        self.workers = workers
+        self.budget = budget_bytes
+        self.max_batch = max_batch
+        self.device = device
+
+    def _run_batch(self, batch: List[Request], t0: float, keep: bool) -> List[Result]:
+        start = time.perf_counter() - t0
+        du, off = K.DeviceGraph.union([r.graph for r in batch], self.device)
+        B = K.kappa_coarsen_batch(du, off, batch[0].rating, batch[0].seed,
+                                  [r.stop for r in batch])
+        return [_finish(r, B.hierarchy(i), t0, start, len(batch), keep)
+                for i, r in enumerate(batch)]
+
+    def run(self, requests: Sequence[Request], keep: bool = False,
+            t0: Optional[float] = None) -> List[Result]:
+        import torch
+        todo = deque(sorted(requests, key=lambda q: q.arrival))
+        arrived: List[Request] = []
+        jobs: "queue.Queue[Optional[List[Request]]]" = queue.Queue()
+        free: "queue.Queue[int]" = queue.Queue()
+        results: List[Result] = []
+        errors: List[BaseException] = []
+        sums = {}
+        lock = threading.Lock()
+        t0 = time.perf_counter() if t0 is None else t0
+
+        def worker(wid: int):
+            torch.cuda.set_device(torch.device(self.device).index or 0)
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                while True:
+                    batch = jobs.get()
+                    if batch is None:
+                        return
+                    try:
+                        res = self._run_batch(batch, t0, keep)
+                        stream.synchronize()
+                        with lock:
+                            results.extend(res)
+                    except BaseException as e:   # reported after the loop
+                        with lock:
+                            errors.append(e)
+                    free.put(wid)
+
+        threads = [threading.Thread(target=worker, args=(i,), daemon=True)
+                   for i in range(self.workers)]
+        for th in threads:
+            th.start()
+        idle = list(range(self.workers))
+        while todo or arrived or len(idle) < self.workers:
+            now = time.perf_counter() - t0
+            while todo and todo[0].arrival <= now:
+                arrived.append(todo.popleft())
+            while True:   # collect finished workers
+                try:
+                    idle.append(free.get_nowait())
+                except queue.Empty:
+                    break
+            if errors:
+                break
+            if arrived and idle:
+                batch, arrived = take_batch(arrived, self.budget, self.max_batch, sums)
+                jobs.put(batch)
+                idle.pop()
+                continue
+            # nothing to hand out: wait for the next arrival or a free worker
+            wait = (todo[0].arrival - now) if (todo and not arrived) else 0.05
+            try:
+                idle.append(free.get(timeout=max(wait, 1e-4)))
+            except queue.Empty:
+                pass
+        for _ in threads:
+            jobs.put(None)
+        for th in threads:
+            th.join()
+        if errors:
+            raise errors[0]
+        torch.cuda.synchronize()
+        return sorted(results, key=lambda q: q.rid)
+
+
+def latency_stats(requests: Sequence[Request], results: Sequence[Result]) -> dict:
+    """p50 / p99 latency (completion minus scheduled arrival, ms) and the
+    aggregate edges/s (all edges over first arrival to last completion)."""
+    import numpy as np
+    arr = {r.rid: r.arrival for r in requests}
+    lat = np.array([res.latency(arr[res.rid]) for res in results]) * 1e3
+    edges = sum(int(r.graph.m) for r in requests)
+    span = max(res.done for res in results) - min(arr.values())
+    return {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_ms": round(float(lat.mean()), 3),
+            "edges_per_s": round(edges / span, 1), "span_s": round(span, 4),
+            "requests": len(results),
+            "mean_batch": round(float(np.mean([res.batch for res in results])), 2)}

@@ -51,3 +51,18 @@ def test_null_arguments_rejected_without_gpu_work():
     g = K._lib.c_graph(0, 0, ctypes.c_void_p(8), None, None, None)
     assert L.kappa_rate(ctypes.byref(g), 7, None, None, None) == K.E_ARG
     L.kappa_hierarchy_free(None)
+
+
+def test_library_binds_torchs_hip_runtime():
+    """Loading the library first (before any torch call) still leaves one HIP
+    runtime in the process: the one torch carries."""
+    import subprocess
+    import sys
+    code = ("import os, sys; sys.path.insert(0, %r); import paper_0910_2004_amd as K; K.lib(); "
+            "m = open('/proc/self/maps').read().splitlines(); "
+            "print(sorted(set(l.split()[-1] for l in m if 'libamdhip64' in l)))"
+            % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    libs = eval(out.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1 and "torch" in libs[0], libs

@@ -11,7 +11,7 @@ import oracle as O
 import paper_0910_2004_amd as K
 from gpu_util import assert_graph_equal, compare_hierarchy, dev, graph_np
 from workloads import (CSR, batch_graphs, complete_graph, cycle_graph, grid2d, path_graph,
-                       random_graph, rgg, rmat, star_graph, union_graphs)
+                       random_graph, rgg, rmat, star_graph)
 
 pytestmark = pytest.mark.gpu
 
@@ -43,10 +43,10 @@ def _mix():
 @pytest.mark.parametrize("rating", [0, 1, 4])
 def test_batch_matches_oracle_per_graph(rating):
     graphs = _mix()
-    u, off = union_graphs(graphs)
+    du, off = K.DeviceGraph.union(graphs)
     stop = [4 + (7 * g) % 40 for g in range(len(graphs))]
-    say(f"batch of {len(graphs)} graphs, n={u.n} nnz={u.nnz}, rating {rating}")
-    B = K.kappa_coarsen_batch(dev(u), off, rating, seed=42, stop_n=stop)
+    say(f"batch of {len(graphs)} graphs, n={du.n} nnz={du.nnz}, rating {rating}")
+    B = K.kappa_coarsen_batch(du, off, rating, seed=42, stop_n=stop)
     assert len(B) == len(graphs)
     for g, G in enumerate(graphs):
         OH = O.coarsen(G, rating, 42, stop[g], 1, 20, 64)
@@ -60,8 +60,8 @@ def test_batch_matches_oracle_per_graph(rating):
 
 def test_batch_equals_single_calls():
     graphs = _mix()[10:]
-    u, off = union_graphs(graphs)
-    B = K.kappa_coarsen_batch(dev(u), off, 1, seed=7, stop_n=30)
+    du, off = K.DeviceGraph.union(graphs)
+    B = K.kappa_coarsen_batch(du, off, 1, seed=7, stop_n=30)
     for g, G in enumerate(graphs):
         H1 = K.kappa_coarsen(dev(G), 1, 7, 30)
         H2 = B.hierarchy(g)
@@ -76,9 +76,9 @@ def test_batch_equals_single_calls():
 
 def test_batch_max_levels_and_stall():
     graphs = [rgg(2000, seed=s) for s in range(5)] + [star_graph(300)]
-    u, off = union_graphs(graphs)
+    du, off = K.DeviceGraph.union(graphs)
     for max_levels in (0, 1, 3):
-        B = K.kappa_coarsen_batch(dev(u), off, 0, seed=3, stop_n=10, max_levels=max_levels)
+        B = K.kappa_coarsen_batch(du, off, 0, seed=3, stop_n=10, max_levels=max_levels)
         for g, G in enumerate(graphs):
             OH = O.coarsen(G, 0, 3, 10, 1, 20, max_levels)
             compare_hierarchy(B.hierarchy(g), OH, check_rounds=False, check_uncoarsen=False)

@@ -41,12 +41,12 @@ def test_batch_4096_sampled_graphs():
     import numpy as np
 
     import paper_0910_2004_amd as K
-    from gpu_util import compare_hierarchy, dev
-    from workloads import batch_graphs, union_graphs
+    from gpu_util import compare_hierarchy
+    from workloads import batch_graphs
     graphs = batch_graphs(4096, seed=4, workers=min(16, os.cpu_count() or 1))
-    u, off = union_graphs(graphs)
-    print(f"batch n={u.n} m={u.m}", flush=True)
-    B = K.kappa_coarsen_batch(dev(u), off, O.EXPANSION_STAR2, 4, 256)
+    du, off = K.DeviceGraph.union(graphs)
+    print(f"batch n={du.n} nnz={du.nnz}", flush=True)
+    B = K.kappa_coarsen_batch(du, off, O.EXPANSION_STAR2, 4, 256)
     sizes = np.array([g.n for g in graphs])
     rng = np.random.default_rng(0)
     sample = sorted(set(rng.choice(len(graphs), 20, replace=False).tolist())

@@ -16,9 +16,12 @@ Recipes (the workload families of the partitioner's experiments, Section 6):
   * ``batch_graphs`` -- the uneven batch: n log-uniform, half degraded grids
                       (10 % of edges removed), half RGGs of mean degree 8,
                       node and edge weights uniform in [1, 16].
-  * ``union_graphs`` -- the block-diagonal union of a list of graphs (graph
-                      g's nodes follow those of graphs 0 .. g-1), the input
-                      layout of the batched form.
+  * ``serve_requests`` -- the served mix: |E| log-uniform, graph type uniform
+                      over {grid of side sqrt(|E|/2); random geometric graph
+                      with n = |E|/4; R-MAT of scale log2(|E|/16) clamped to
+                      [6, 20], edge factor 16, weights in [1, 100]}, rating
+                      uniform over {expansion*2, innerOuter}, k uniform over
+                      {2, 8, 32, 64}.
 """
 from __future__ import annotations
 
@@ -253,25 +256,31 @@ def batch_graphs(count: int = 4096, seed: int = 4, nmin: float = 1e3, nmax: floa
         return list(ex.map(_batch_member, *zip(*args), chunksize=16))
 
 
-def union_graphs(graphs: List[CSR]) -> Tuple[CSR, np.ndarray]:
-    """Block-diagonal union; returns it and node_off (int32, count + 1)."""
-    ns = np.array([g.n for g in graphs], dtype=np.int64)
-    es = np.array([g.nnz for g in graphs], dtype=np.int64)
-    node_off = np.zeros(len(graphs) + 1, dtype=np.int64)
-    node_off[1:] = np.cumsum(ns)
-    ent_off = np.zeros(len(graphs) + 1, dtype=np.int64)
-    ent_off[1:] = np.cumsum(es)
-    n = int(node_off[-1])
-    xadj = np.empty(n + 1, dtype=np.int64)
-    adj = np.empty(int(ent_off[-1]), dtype=np.int32)
-    ew = np.empty(int(ent_off[-1]), dtype=np.uint32)
-    vw = np.empty(n, dtype=np.uint32)
-    for i, g in enumerate(graphs):
-        a, b = int(node_off[i]), int(node_off[i + 1])
-        ea, eb = int(ent_off[i]), int(ent_off[i + 1])
-        xadj[a:b] = g.xadj[:-1] + ea
-        adj[ea:eb] = g.adj.astype(np.int64) + a
-        ew[ea:eb] = g.ew
-        vw[a:b] = g.vw
-    xadj[n] = int(ent_off[-1])
-    return CSR(n, xadj, adj, ew, vw), node_off.astype(np.int32)
+def _serve_member(seed: int, i: int, emin: float, emax: float) -> Tuple[CSR, int, int]:
+    rng = np.random.Generator(np.random.PCG64([seed, i]))
+    e = float(np.exp(rng.uniform(math.log(emin), math.log(emax))))
+    kind = int(rng.integers(0, 3))
+    rating = int(rng.integers(0, 2))
+    k = int((2, 8, 32, 64)[int(rng.integers(0, 4))])
+    sub = int(rng.integers(0, 2**31 - 1))
+    if kind == 0:
+        side = max(2, int(round(math.sqrt(e / 2))))
+        g = grid2d(side, side)
+    elif kind == 1:
+        g = rgg(max(2, int(round(e / 4))), seed=sub)
+    else:
+        scale = min(20, max(6, int(round(math.log2(e / 16)))))
+        g = rmat(scale, 16, seed=sub, wseed=sub + 1)
+    return g, rating, k
+
+
+def serve_requests(count: int = 2000, seed: int = 5, emin: float = 1e3, emax: float = 4e6,
+                   workers: int = 1) -> List[Tuple[CSR, int, int]]:
+    """The served mix (see module doc): (graph, rating, k) per request.
+    Request i uses sub-seed (seed, i), independent of `workers`."""
+    args = [(seed, i, emin, emax) for i in range(count)]
+    if workers <= 1:
+        return [_serve_member(*a) for a in args]
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_serve_member, *zip(*args), chunksize=4))
