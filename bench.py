@@ -57,7 +57,24 @@ def bytes_cut_entries(D):
     return 16 * D
 
 
-MODELS = {"pick_first": "per level: 16 B/node + 12 B/entry (innerOuter 20 + 16)",
+def bytes_pick_round(A, Dr):
+    # a matching round after the first, pick side, over the A nodes that
+    # point (degree sum Dr): per entry adj, w, the neighbour's attribute and
+    # mate (16); per node its two int64 offsets, own attribute, best (24)
+    return 16 * Dr + 24 * A
+
+
+def bytes_mate_round(A):
+    # mutual check: per pointing node its choice, the choice's choice, mate (12)
+    return 12 * A
+
+
+MODELS = {"pick": "per round r >= 2 run as a grid launch: 16 B per entry of the A_r pointing "
+                  "nodes (adj, w, attribute, mate of the neighbour) + 24 B per pointing node "
+                  "(int64 offsets, own attribute, best); A_r and their degree sum from the "
+                  "level's round statistics",
+          "mate": "per round r >= 2 run as a grid launch: 12 B per pointing node",
+          "pick_first": "per level: 16 B/node + 12 B/entry (innerOuter 20 + 16)",
           "fill_small": "per level: 28 B/coarse row + 16 B/matched pair + 12 B/fine entry + 8 B/coarse entry",
           "compact_small": "per level: 24 B/coarse row + 16 B/coarse entry",
           "cut_entries": "per level: 16 B/entry"}
@@ -68,42 +85,136 @@ def counter_traffic(kernel):
     (profiles/<kernel>_counters.json: FETCH_SIZE and WRITE_SIZE per step,
     scaled by a plain copy), or None when the kernel's source changed since
     the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"{kernel}_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    h = hashlib.sha256()
-    for src in rec["sources"]:
-        with open(os.path.join(ROOT, src), "rb") as f:
-            h.update(f.read())
-    if h.hexdigest() != rec["sources_sha256"]:
+    if rec.get("sources") != COUNTER_SOURCES or rec.get("sources_sha256") != _sources_sha():
         return None
     return rec["traffic_bytes_per_launch"]
 
 
 def level_stats(H):
+    """Per level: n, entries, |M|, rounds, rounds run as grid launches, and
+    the per-round (pointing nodes, their degree sum)."""
     out = []
     for l in range(len(H)):
         inf = H.info(l)
-        out.append((int(inf.n), int(inf.nnz), int(inf.matched), int(inf.rounds)))
+        _, p, d = H.round_stats(l)
+        out.append((int(inf.n), int(inf.nnz), int(inf.matched), int(inf.rounds),
+                    int(inf.grid_rounds), [int(x) for x in p], [int(x) for x in d]))
     return out
 
 
-def model_bytes(stats_by_rating, maxbound_ok):
+def model_bytes(stats_by_rating):
     """Total model bytes per kernel class over one step."""
     tot = {k: 0 for k in MODELS}
     for rating, lv in stats_by_rating.items():
         io = rating == 1
-        for l, (n, D, matched, rounds) in enumerate(lv):
+        for l, (n, D, matched, rounds, grid_rounds, pt, dg) in enumerate(lv):
             tot["cut_entries"] += bytes_cut_entries(D)
             if l + 1 < len(lv):
                 nc, Dc = lv[l + 1][0], lv[l + 1][1]
                 tot["pick_first"] += bytes_pick_first(n, D, io)
+                for r in range(2, min(grid_rounds, len(pt)) + 1):
+                    tot["pick"] += bytes_pick_round(pt[r - 1], dg[r - 1])
+                    tot["mate"] += bytes_mate_round(pt[r - 1])
                 tot["fill_small"] += bytes_fill_small(n, D, nc, Dc, matched)
                 tot["compact_small"] += bytes_compact(nc, Dc)
     return tot
+
+
+# rocprofv3 kernel names (namespace, "void " and arguments stripped) of the
+# library's profiler names
+KERNEL_SYMBOLS = {"pick": r"pick_k<\d, false>", "mate": r"mate_k<\d, false>",
+                  "pick_first": r"pick_k<\d, true>", "fill_small": r"fill_small_k",
+                  "compact_small": r"compact_small_k", "cut_entries": r"up_entries_k<(true|false)>"}
+COUNTER_SOURCES = ["paper_0910_2004_amd/csrc/k_level.hip", "paper_0910_2004_amd/csrc/kappa_internal.h",
+                   "paper_0910_2004_amd/csrc/k_graph.hip"]
+WORKLOAD_RGG = "rgg n=2^20 mean degree 8, both ratings, k=64, stop 1280"
+
+
+def _short_name(name):
+    import re
+    return re.sub(r"\(.*", "", name).replace("void ", "").replace("kappa::", "").strip()
+
+
+def _sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for src in COUNTER_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def summarize_pmc(kernel, fetch_dir, write_dir, bench_cmd):
+    """profiles/<kernel>_counters.json and .md from the counter-collection CSVs
+    of a FETCH_SIZE pass and a WRITE_SIZE pass of the same bench command that
+    ended with --copy-calibration: the last three 256 MiB copies give the
+    scale from counter KiB to bytes (each copy reads and writes 256 MiB)."""
+    import csv
+    import glob
+    import re
+    pat = re.compile("^" + KERNEL_SYMBOLS[kernel] + "$")
+    res = {}
+    for ctr, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        rows = [r for f in files for r in csv.DictReader(open(f)) if r["Counter_Name"] == ctr]
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) >= 65536]
+        copies = copies[-3:]
+        vals = [float(r["Counter_Value"]) for r in copies]
+        scale = (256 * 1024) / (sum(vals) / len(vals))
+        ks = [r for r in rows if pat.match(_short_name(r["Kernel_Name"]))]
+        tot_kib = sum(float(r["Counter_Value"]) for r in ks)
+        res[ctr] = {"copy_kib": vals, "scale": scale, "dispatches": len(ks), "raw_kib_total": tot_kib,
+                    "scaled_bytes_per_launch": tot_kib * 1024 * scale / max(len(ks), 1)}
+    traffic = res["FETCH_SIZE"]["scaled_bytes_per_launch"] + res["WRITE_SIZE"]["scaled_bytes_per_launch"]
+    cmds = [f"cd /tmp && timeout -s KILL 120 rocprofv3 --pmc {c} --kernel-trace -d <out> -o run "
+            f"--output-format csv -- python3 <repo>/{bench_cmd}" for c in ("FETCH_SIZE", "WRITE_SIZE")]
+    rec = {"kernel": kernel, "workload": WORKLOAD_RGG, "counters": res,
+           "traffic_bytes_per_launch": traffic, "sources": COUNTER_SOURCES,
+           "sources_sha256": _sources_sha(), "commands": cmds}
+    with open(os.path.join(ROOT, "profiles", f"{kernel}_counters.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    lines = [f"# HBM traffic of `{kernel}` ({KERNEL_SYMBOLS[kernel]}): {WORKLOAD_RGG}", "",
+             "Commands (one counter per run; `<repo>` is the repository root):", ""]
+    lines += ["    " + c for c in cmds]
+    lines += ["", "Summarised by `python bench.py --summarize-pmc " + kernel + " <fetch dir> <write dir>`.",
+              "", "The run ends with three plain 256 MiB device-to-device copies "
+              "(`--copy-calibration`), whose counters give the scale from counter KiB to bytes:", "",
+              "| counter | copy KiB per 256 MiB | scale | dispatches | scaled MB per launch |",
+              "|---|---|---|---|---|"]
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        r = res[ctr]
+        lines.append(f"| {ctr} | {', '.join(f'{v:.1f}' for v in r['copy_kib'])} | {r['scale']:.4f} | "
+                     f"{r['dispatches']} | {r['scaled_bytes_per_launch'] / 1e6:.3f} |")
+    lines += ["", f"Traffic per launch: **{traffic / 1e6:.3f} MB**.  `bench.py` reports it as "
+              f"`roofline.traffic` while the SHA-256 of {', '.join(COUNTER_SOURCES)} equals "
+              f"`{rec['sources_sha256'][:16]}…`, and null once they change."]
+    with open(os.path.join(ROOT, "profiles", f"{kernel}_counters.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    log(f"{kernel}: traffic {traffic / 1e6:.3f} MB per launch "
+        f"({res['FETCH_SIZE']['dispatches']} dispatches)")
+
+
+def summarize_stats(stats_csv, out_md, title, cmd):
+    """A kernel-statistics table (rocprofv3 --stats kernel_stats.csv) as markdown."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    tot = sum(int(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# {title}", "", "Command (`<repo>` is the repository root):", "", "    " + cmd, "",
+             f"Summarised by `python bench.py --summarize-stats <kernel_stats.csv> <out.md>`.", "",
+             f"Total kernel time {tot / 1e6:.3f} ms over the whole run.", "",
+             "| kernel | calls | total ms | avg us | min us | max us | % |",
+             "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| `{_short_name(r['Name'])}` | {r['Calls']} | {int(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {int(r['MinNs']) / 1e3:.2f} | "
+                     f"{int(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
 
 
 def main():
@@ -123,7 +234,25 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (3x) so that HBM byte counters "
                          "can be scaled against a kernel of known traffic")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("KERNEL", "FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/<kernel>_counters.json/.md from two rocprofv3 --pmc runs "
+                         "(no GPU work)")
+    ap.add_argument("--pmc-command", default="bench.py --steps 1 --warmup 1 --no-cpu-baseline "
+                                             "--copy-calibration",
+                    help="the bench command the --pmc runs profiled (recorded in the summary)")
+    ap.add_argument("--summarize-stats", nargs=2, metavar=("STATS_CSV", "OUT_MD"),
+                    help="write a markdown table from rocprofv3 --stats kernel_stats.csv (no GPU work)")
+    ap.add_argument("--stats-title", default=f"Kernel statistics: {WORKLOAD_RGG}")
+    ap.add_argument("--stats-command", default="cd /tmp && rocprofv3 --kernel-trace --stats -d <out> -o run "
+                                               "--output-format csv -- python3 <repo>/bench.py --steps 3 "
+                                               "--warmup 1 --no-cpu-baseline")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        return summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.summarize_pmc[2],
+                             args.pmc_command)
+    if args.summarize_stats:
+        return summarize_stats(args.summarize_stats[0], args.summarize_stats[1], args.stats_title,
+                               args.stats_command)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
@@ -168,13 +297,18 @@ def main():
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    marks = [t1]
     for _ in range(args.steps):
-        stats = step()
+        stats = step()          # every call inside returns after its stream is synchronised
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     ms_step = (t2 - t1) * 1e3 / args.steps
+    med_ms = float(np.median(np.diff(marks))) * 1e3
     edges_step = g.m * len(ratings)
     value = edges_step / (ms_step / 1e3)
+    # all levels' edges (sum over the hierarchy of |E_l|) per second
+    level_edges = sum(x[1] // 2 for r in ratings for x in stats[r][0])
 
     # second timed pass with per-launch HIP events
     K.profile_reset()
@@ -188,7 +322,7 @@ def main():
     K.profile_reset()
 
     lv = {r: stats[r][0] for r in ratings}
-    mb = model_bytes(lv, True)
+    mb = model_bytes(lv)
     total_ms = sum(ms for _, ms in prof.values()) / args.steps
     kern = sorted(prof.items(), key=lambda kv: -kv[1][1])
     log("kernel time per step (ms), launches per step:")
@@ -226,6 +360,7 @@ def main():
                          f"{t4 - t3:.2f} s"}
 
     levels = {("expansion*2" if r == 0 else "innerOuter"): [x[0] for x in lv[r]] for r in ratings}
+    lv_json = {str(r): [list(x[:5]) for x in lv[r]] for r in ratings}
     out = {
         "metric": "coarsening edges/s per GPU (full hierarchy)",
         "value": round(value, 1),
@@ -234,6 +369,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 3),
+        "median_ms_per_step": round(med_ms, 3),
+        "all_levels_edges_per_s": round(level_edges / (ms_step / 1e3), 1),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -257,8 +394,7 @@ def main():
         log(f"copy calibration: 3 x {a.numel() * 4} bytes read and written")
     if args.profile_out:
         with open(args.profile_out, "w") as f:
-            json.dump({"prof": prof, "model_bytes": mb, "levels": {str(r): lv[r] for r in ratings}},
-                      f, indent=1)
+            json.dump({"prof": prof, "model_bytes": mb, "levels": lv_json}, f, indent=1)
     print(json.dumps(out), flush=True)
 
 

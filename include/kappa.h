@@ -132,6 +132,9 @@ typedef struct {
     int32_t rounds;      /* matching rounds spent on this level (0 on the coarsest) */
     int64_t matched;     /* |M| of this level's matching */
     int32_t stop_reason; /* kappa_stop; nonzero only on the coarsest level */
+    int32_t grid_rounds; /* of those rounds, how many ran as grid-wide kernel launches (the
+                            rest ran in one workgroup once few nodes were pending); 0 in a
+                            hierarchy taken out of a batch */
 } kappa_level_info;
 
 typedef struct kappa_hierarchy kappa_hierarchy; /* opaque, library-owned */
@@ -287,6 +290,14 @@ void kappa_graphs_enable(int32_t on);
    the arena, up to five times.  Results do not depend on it: it exists to
    exercise the arena-overflow path at chosen levels. */
 void kappa_arena_first(uint64_t bytes);
+
+/* on = 1: in kappa_coarsen, once a level has at most 16384 nodes and
+   131072 entries, that level and every later one run in a single workgroup
+   in one launch instead of a sequence of grid-wide launches per level.
+   on = 0 (the default, measured faster on gfx950: one workgroup cannot hide
+   the latency of a level's dependent loads) runs every level with the grid
+   kernels.  Results do not depend on it. */
+void kappa_tail_enable(int32_t on);
 
 const char *kappa_status_str(kappa_status st);
 const char *kappa_version(void);

@@ -267,10 +267,13 @@ class Hierarchy:
         return self.levels[-1].stop_reason
 
 
-def coarsen(g, rating: int = EXPANSION_STAR2, seed: int = 42, stop_n: int = 256,
-            stall_num: int = 1, stall_den: int = 20, max_levels: int = 64,
-            cross_check: bool = False, round_stats: bool = False) -> Hierarchy:
-    """Contract until small (Section 2, contraction phase).
+def coarsen_levels(g, rating: int = EXPANSION_STAR2, seed: int = 42, stop_n: int = 256,
+                   stall_num: int = 1, stall_den: int = 20, max_levels: int = 64,
+                   cross_check: bool = False, round_stats: bool = False):
+    """Contract until small (Section 2, contraction phase), one level at a time.
+
+    Yields each level once it is final: with its matching, cmap and |M| if it
+    was contracted, or with its stop reason if it is the coarsest.
 
     Level l is matched with the tie-break seed mix64(seed + l) using Greedy
     (Section 3.2), which under the strict edge order equals the parallel
@@ -283,17 +286,18 @@ def coarsen(g, rating: int = EXPANSION_STAR2, seed: int = 42, stop_n: int = 256,
     contracting, keep level l+1 and stop if it removed fewer than
     stall_num/stall_den of the nodes (STALL).
     """
-    H = Hierarchy([Level(Graph.of(g))])
+    cur = Level(Graph.of(g))
     l = 0
     while True:
-        cur = H.levels[-1]
         G = cur.graph
         if G.n <= stop_n:
             cur.stop_reason = STOP_SIZE
-            break
+            yield cur
+            return
         if l == max_levels:
             cur.stop_reason = STOP_MAXLEVEL
-            break
+            yield cur
+            return
         s = level_seed(seed, l)
         mate, m = match_greedy(G, rating, s)
         if cross_check or round_stats:
@@ -304,15 +308,26 @@ def coarsen(g, rating: int = EXPANSION_STAR2, seed: int = 42, stop_n: int = 256,
         cur.mate, cur.matched = mate, m
         if m == 0:
             cur.stop_reason = STOP_EMPTY
-            break
+            yield cur
+            return
         cmap, coarse = contract(G, mate)
         cur.cmap = cmap
-        H.levels.append(Level(coarse))
+        yield cur
+        nxt = Level(coarse)
         l += 1
         if (G.n - coarse.n) * stall_den < stall_num * G.n:
-            H.levels[-1].stop_reason = STOP_STALL
-            break
-    return H
+            nxt.stop_reason = STOP_STALL
+            yield nxt
+            return
+        cur = nxt
+
+
+def coarsen(g, rating: int = EXPANSION_STAR2, seed: int = 42, stop_n: int = 256,
+            stall_num: int = 1, stall_den: int = 20, max_levels: int = 64,
+            cross_check: bool = False, round_stats: bool = False) -> Hierarchy:
+    """The whole hierarchy of coarsen_levels (same arguments)."""
+    return Hierarchy(list(coarsen_levels(g, rating, seed, stop_n, stall_num, stall_den, max_levels,
+                                         cross_check, round_stats)))
 
 
 def uncoarsen(H: Hierarchy, k: int, part_seed: int = 1, eps_num: int = 3, eps_den: int = 100):

@@ -57,7 +57,8 @@ class c_cut(ctypes.Structure):
 
 class c_level_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("rounds", ctypes.c_int32),
-                ("matched", ctypes.c_int64), ("stop_reason", ctypes.c_int32)]
+                ("matched", ctypes.c_int64), ("stop_reason", ctypes.c_int32),
+                ("grid_rounds", ctypes.c_int32)]
 
 
 _lib = None
@@ -117,6 +118,7 @@ def lib():
         "kappa_cache_release": (st, []),
         "kappa_graphs_enable": (None, [i32]),
         "kappa_arena_first": (None, [u64]),
+        "kappa_tail_enable": (None, [i32]),
         "kappa_status_str": (ctypes.c_char_p, [st]),
         "kappa_version": (ctypes.c_char_p, []),
     }
@@ -475,6 +477,12 @@ def graphs_enable(on: bool = True):
     """Replay repeated launch sequences as HIP graphs (on) or launch every
     kernel directly (off, the library's default)."""
     lib().kappa_graphs_enable(1 if on else 0)
+
+
+def tail_enable(on: bool = True):
+    """Run small levels (and every later one) in one workgroup (on) or every
+    level with the grid kernels (off, the library's default)."""
+    lib().kappa_tail_enable(1 if on else 0)
 
 
 def arena_first(nbytes: int = 0):

@@ -277,6 +277,7 @@ void give_arena(hipStream_t s, void *p, size_t bytes) {
 // ---------------------------------------------------------------------------
 bool debug_on();
 bool g_graphs_on = false;   // measured slower than direct launches on gfx950 (ROCm 7)
+bool g_tail_on = false;     // small levels in one workgroup (tail_k): measured slower
 constexpr size_t KEEP_GRAPHS = 24, KEEP_SEEN = 48;
 
 template <class E>
@@ -541,7 +542,7 @@ struct kappa_level {
     const uint32_t *vw = nullptr;
     int32_t *cmap = nullptr;   // to the next level
     int32_t *mate = nullptr;
-    int32_t rounds = 0;
+    int32_t rounds = 0, grid_rounds = 0;
     int64_t matched = 0;
     int32_t stop = KAPPA_STOP_NONE;
     std::vector<int64_t> pointing, degsum;
@@ -681,16 +682,30 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     int first = (int)std::ceil(std::log(std::max(2.0, (double)n0 / std::max(1, p->stop_n))) /
                                std::log(1.0 / 0.6)) + 2;
     int launched = 0, batch = std::max(1, std::min(first, maxl + 1));
+    // The tail kernel is tried ahead of each level past level 0 whose size
+    // estimate is near its limit; once the estimate is within twice the limit
+    // the batch ends on the tail launch (it most likely finishes the loop).
+    // If it did not take that level, the next batch runs the level in full.
+    const bool tail_on = !bi && g_tail_on;
+    int tail_end = -1;   // level at which the previous batch ended on a tail launch
     Control *hc = (Control *)pinned(sizeof(Control));
     for (;;) {
         const int l_end = std::min(launched + batch, maxl + 1);
+        int next = l_end;
         const std::vector<uint64_t> key = {1, pkey(w->base), (uint64_t)n0, (uint64_t)d0.nnz,
                                            (uint64_t)p->rating, p->seed, (uint64_t)maxl,
                                            (uint64_t)hubs, (uint64_t)launched, (uint64_t)l_end,
-                                           (uint64_t)count};
+                                           (uint64_t)count, (uint64_t)tail_on,
+                                           (uint64_t)(int64_t)tail_end};
         HIPCHK(run_seq(w->c, s, key, [&](hipStream_t q) {
             for (int l = launched; l < l_end; ++l) {
                 int32_t nh = n_hint_of(n0, l);
+                const bool try_tail = tail_on && l >= 1 && nh <= 8 * TAIL_MAX_N;
+                if (try_tail) launch_tail(c, l, q);
+                if (try_tail && nh <= 2 * TAIL_MAX_N && l != tail_end) {
+                    next = l;
+                    break;
+                }
                 // innerOuter on unit input weights ranks edges by degree
                 // sums, which chains level 0 over many rounds; otherwise
                 // rounds shrink the pending set about threefold each (the
@@ -700,7 +715,8 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
                 launch_level(c, l, nh, d0.nnz, n0, rounds, q);
             }
         }));
-        launched += batch;
+        if (next < l_end) tail_end = next;
+        launched = next;
         HIPCHK(hipMemcpyAsync(hc, c.ctrl, sizeof(Control), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (hc->done || launched > maxl) break;
@@ -736,6 +752,7 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
         L.cmap = l + 1 < nl ? hl[l].cmap : nullptr;
         L.mate = hl[l].mate;
         L.rounds = hl[l].rounds;
+        L.grid_rounds = hl[l].grid_rounds;
         L.matched = hl[l].matched;
         L.stop = hl[l].stop;
         if (l + 1 < nl || L.stop == KAPPA_STOP_EMPTY) {
@@ -746,6 +763,7 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
             }
         } else {
             L.rounds = 0;
+            L.grid_rounds = 0;
             L.matched = 0;
         }
         if (l + 1 < nl) L.stop = KAPPA_STOP_NONE;
@@ -1171,6 +1189,7 @@ extern "C" kappa_status kappa_hierarchy_level(const kappa_hierarchy *h, int32_t 
         info->rounds = L.rounds;
         info->matched = L.matched;
         info->stop_reason = L.stop;
+        info->grid_rounds = L.grid_rounds;
     }
     return KAPPA_OK;
 }
@@ -1336,6 +1355,8 @@ extern "C" kappa_status kappa_cache_release(void) {
 extern "C" void kappa_graphs_enable(int32_t on) { g_graphs_on = on != 0; }
 
 extern "C" void kappa_arena_first(uint64_t bytes) { g_arena_first.store(bytes); }
+
+extern "C" void kappa_tail_enable(int32_t on) { g_tail_on = on != 0; }
 
 extern "C" const char *kappa_status_str(kappa_status st) {
     switch (st) {

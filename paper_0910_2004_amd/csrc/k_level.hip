@@ -266,16 +266,18 @@ __device__ __forceinline__ void block_append_mk(const int bin[MK], const int32_t
 
 // mate = best = -1; nodes of bins 1 and 2 go to the round-1 lists (parity 0).
 // Loads of a thread's MK entries are issued before its stores.
+// bid / nb: this block and the number of blocks sharing the work; cnt: the
+// three list counters (global, or LDS when one block does all the work).
 __device__ __forceinline__ void init_phase(const Ctx &c, const DevGraph &g, LevelDesc *L,
-                                           int64_t *sh, int32_t *sbase) {
+                                           int64_t *sh, int32_t *sbase, unsigned bid, unsigned nb,
+                                           int32_t *cnt) {
     int32_t *mate = L->mate, *best = c.ms.best;
-    MatchState *st = c.ms.state;
     const PList ol[3] = {plist(c.ms, g.n, 0, 0), plist(c.ms, g.n, 0, 1), plist(c.ms, g.n, 0, 2)};
     // pass p, slot k of block b covers entries ((p * MK + k) * nb + b) * blockDim.x + t:
     // small inputs spread over every block first
-    const int64_t row = (int64_t)gridDim.x * blockDim.x, per_pass = row * MK;
+    const int64_t row = (int64_t)nb * blockDim.x, per_pass = row * MK;
     for (int64_t base = 0; base < g.n; base += per_pass) {   // block-uniform
-        const int64_t first = base + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const int64_t first = base + (int64_t)bid * blockDim.x + threadIdx.x;
         int bin[MK];
         int32_t vv[MK], bb[MK], dd[MK];
         int64_t deg[MK];
@@ -297,7 +299,7 @@ __device__ __forceinline__ void init_phase(const Ctx &c, const DevGraph &g, Leve
                 best[i] = -1;
             }
         }
-        block_append_mk(bin, vv, bb, dd, ol, &st->cnt[0][0], sh, sbase);
+        block_append_mk(bin, vv, bb, dd, ol, cnt, sh, sbase);
     }
 }
 
@@ -533,7 +535,7 @@ __global__ void __launch_bounds__(BLOCK) match_init_k(Ctx c, int l, int stop_rul
         L->matched = 0;
         L->rounds = 0;
     }
-    init_phase(c, g, L, sh, sbase);
+    init_phase(c, g, L, sh, sbase, blockIdx.x, gridDim.x, &c.ms.state->cnt[0][0]);
 }
 
 struct PickGrid {
@@ -584,6 +586,88 @@ __global__ void __launch_bounds__(BLOCK) mate_k(Ctx c, int l, int r) {
     mate_phase<R, FIRST>(c, g, L, r, ri, st->cnt[r & 3], blockIdx.x, gridDim.x, sh, sbase);
 }
 
+// Rounds r0+1, r0+2, ... of level L in one workgroup of NT threads, with
+// workgroup barriers, until no node is pending; s_cnt[r0 & 1] holds the list
+// sizes round r0 left.  Every round that has a pointing node matches at least
+// one pair, so at most n/2 + 1 rounds remain; returns true only if that cap
+// was hit (broken state).
+template <int R, int NT>
+__device__ bool wg_rounds(const Ctx &c, const DevGraph &g, LevelDesc *L, uint64_t seed, int r0,
+                          int32_t (*s_cnt)[3], Cand *shc, int64_t *sh, int32_t *sbase) {
+    const int64_t r_cap = (int64_t)r0 + 2 + g.n;
+    for (int r = r0 + 1; r <= r_cap; ++r) {
+        const RoundIn ri = round_inputs<false>(c, g, r, s_cnt[(r - 1) & 1]);
+        if ((int64_t)ri.cn[0] + ri.cn[1] + ri.cn[2] == 0) return false;
+        pick_bin0<R, false>(c, g, seed, ri, 0, 1);
+        pick_bin1<R, false>(c, g, seed, ri, 0, 1);
+        __syncthreads();
+        pick_bin2<R, false, NT>(c, g, seed, ri, 0, 1, shc);
+        if (threadIdx.x < 3) s_cnt[r & 1][threadIdx.x] = 0;
+        __syncthreads();
+        mate_phase<R, false>(c, g, L, r, ri, s_cnt[r & 1], 0, 1, sh, sbase);
+        __syncthreads();
+    }
+    return true;
+}
+
+// Closes level L's matching in one workgroup of NT threads: sums the round
+// statistics over the rounds used (one wave per statistic) and leaves them,
+// the list counters and the contraction counters zero; records |M|, the
+// round count and how many rounds ran as grid launches (grid_r0: rounds up to
+// grid_r0 did, -2: all did); ends the level loop on an empty matching.
+template <int NT>
+__device__ void close_matching(const Ctx &c, LevelDesc *L, bool capped, int grid_r0,
+                               int64_t *s_acc) {
+    MatchState *st = c.ms.state;
+    __syncthreads();
+    if (threadIdx.x < WAVE) {
+        const int32_t rr = wave_max(st->sround[lane_id()]);
+        st->sround[lane_id()] = 0;
+        if (lane_id() == 0) {
+            s_acc[0] = 0;
+            s_acc[1] = rr;
+        }
+    }
+    __syncthreads();
+    {
+        const int w = threadIdx.x / WAVE, nw = NT / WAVE;
+        const int slots = (int)min<int64_t>(s_acc[1], STAT_ROUNDS);
+        for (int q = w; q < slots * 3; q += nw) {
+            const int i = q / 3, f = q % 3;
+            int64_t *p = &st->sstat[i][f][lane_id()];
+            const int64_t v = wave_sum(*p);
+            *p = 0;
+            if (lane_id() == 0) {
+                if (f < 2) L->stat[i][f] = v;
+                else if (v) atomicAdd((unsigned long long *)&s_acc[0], (unsigned long long)v);
+            }
+        }
+    }
+    if (threadIdx.x < 4) {
+        c.cs.row_cnt[threadIdx.x] = 0;
+        c.cs.totals[threadIdx.x] = 0;
+    }
+    __syncthreads();   // every read of st->cnt is done
+    if (threadIdx.x < 16) st->cnt[threadIdx.x >> 2][threadIdx.x & 3] = 0;   // next level's lists
+    if (threadIdx.x == 0) {
+        int64_t m = s_acc[0];
+        const int32_t used = (int32_t)s_acc[1];
+        st->handoff = -2;
+        L->matched = m;
+        L->rounds = used;
+        L->grid_rounds = grid_r0 < 0 ? used : min(grid_r0, used);
+        if (capped) c.ctrl->flags |= CF_ROUNDS;
+        if (m == 0 || capped) {
+            L->stop = KAPPA_STOP_EMPTY;
+            L->phase = PH_STOPPED;
+            c.ctrl->done = 1;
+        } else {
+            L->phase = PH_CONTRACT;
+        }
+    }
+    __syncthreads();
+}
+
 // Finisher: one workgroup runs the remaining rounds (from the handoff point,
 // or after round r_last) with workgroup barriers, then closes the level's
 // matching.
@@ -614,72 +698,10 @@ __global__ void __launch_bounds__(FINISH_THREADS) finish_k(Ctx c, int l, int r_l
             s_cnt[(r0 + 1) & 1][threadIdx.x] = 0;
         }
         __syncthreads();
-        // Every round that has a pointing node matches at least one pair, so
-        // at most n/2 + 1 rounds remain; the cap only guards broken state.
-        const int64_t r_cap = (int64_t)r0 + 2 + g.n;
-        capped = true;
-        for (int r = r0 + 1; r <= r_cap; ++r) {
-            const RoundIn ri = round_inputs<false>(c, g, r, s_cnt[(r - 1) & 1]);
-            if ((int64_t)ri.cn[0] + ri.cn[1] + ri.cn[2] == 0) {
-                capped = false;
-                break;
-            }
-            pick_bin0<R, false>(c, g, seed, ri, 0, 1);
-            pick_bin1<R, false>(c, g, seed, ri, 0, 1);
-            __syncthreads();
-            pick_bin2<R, false, FINISH_THREADS>(c, g, seed, ri, 0, 1, shc);
-            if (threadIdx.x < 3) s_cnt[r & 1][threadIdx.x] = 0;
-            __syncthreads();
-            mate_phase<R, false>(c, g, L, r, ri, s_cnt[r & 1], 0, 1, sh, sbase);
-            __syncthreads();
-        }
+        capped = wg_rounds<R, FINISH_THREADS>(c, g, L, seed, r0, s_cnt, shc, sh, sbase);
     }
-    // close the level's matching: sum the shards of the rounds used (one wave
-    // per statistic) and leave them zero for the next level
-    __syncthreads();
-    if (threadIdx.x < WAVE) {
-        const int32_t rr = wave_max(st->sround[lane_id()]);
-        st->sround[lane_id()] = 0;
-        if (lane_id() == 0) {
-            s_acc[0] = 0;
-            s_acc[1] = rr;
-        }
-    }
-    __syncthreads();
-    {
-        const int w = threadIdx.x / WAVE, nw = FINISH_THREADS / WAVE;
-        const int slots = (int)min<int64_t>(s_acc[1], STAT_ROUNDS);
-        for (int q = w; q < slots * 3; q += nw) {
-            const int i = q / 3, f = q % 3;
-            int64_t *p = &st->sstat[i][f][lane_id()];
-            const int64_t v = wave_sum(*p);
-            *p = 0;
-            if (lane_id() == 0) {
-                if (f < 2) L->stat[i][f] = v;
-                else if (v) atomicAdd((unsigned long long *)&s_acc[0], (unsigned long long)v);
-            }
-        }
-    }
-    if (threadIdx.x < 4) {
-        c.cs.row_cnt[threadIdx.x] = 0;
-        c.cs.totals[threadIdx.x] = 0;
-    }
-    __syncthreads();   // every read of st->cnt above is done
-    if (threadIdx.x < 16) st->cnt[threadIdx.x >> 2][threadIdx.x & 3] = 0;   // next level's lists
-    if (threadIdx.x == 0) {
-        int64_t m = s_acc[0];
-        st->handoff = -2;
-        L->matched = m;
-        L->rounds = (int32_t)s_acc[1];
-        if (capped) c.ctrl->flags |= CF_ROUNDS;
-        if (m == 0 || capped) {
-            L->stop = KAPPA_STOP_EMPTY;
-            L->phase = PH_STOPPED;
-            c.ctrl->done = 1;
-        } else {
-            L->phase = PH_CONTRACT;
-        }
-    }
+    // r0 = -2: the round kernels found nothing left, so they ran every round
+    close_matching<FINISH_THREADS>(c, L, capped, r0, s_acc);
 }
 
 // ===========================================================================
@@ -900,10 +922,15 @@ __device__ __forceinline__ void wave_sync_lds() {
 
 // --- 2a. small rows: 16 lanes per row, rank sort; every coarse row passes
 //         here (empty rows get degree 0, bigger rows go to the class lists) --
-__global__ void __launch_bounds__(BLOCK) fill_small_k(Ctx c, int l) {
-    __shared__ uint32_t sk[SM_ROWS][SM_CAP];
-    __shared__ uint32_t sw[SM_ROWS][SM_CAP];
-    __shared__ uint8_t sf[SM_ROWS][SM_CAP];
+// The contraction phases below are written for `nb` blocks of NT threads
+// (block `bid`): the kernels run them over their grid; the tail kernel runs
+// them in one workgroup.
+template <int NT>
+__device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bid, unsigned nb) {
+    constexpr int ROWS = NT / ROW_SMALL_G;
+    __shared__ uint32_t sk[ROWS][SM_CAP];
+    __shared__ uint32_t sw[ROWS][SM_CAP];
+    __shared__ uint8_t sf[ROWS][SM_CAP];
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_CONTRACT, g)) return;
@@ -911,10 +938,10 @@ __global__ void __launch_bounds__(BLOCK) fill_small_k(Ctx c, int l) {
     const int grp = threadIdx.x / ROW_SMALL_G, sub = threadIdx.x % ROW_SMALL_G;
     const int64_t count = c.lv[l + 1].n;
     int32_t *lists1 = c.cs.rows + g.n, *lists2 = c.cs.rows + 2 * (int64_t)g.n;
-    const int64_t gs = (int64_t)gridDim.x * SM_ROWS;
+    const int64_t gs = (int64_t)nb * ROWS;
     const int64_t lim = (count + gs - 1) / gs * gs;   // uniform trip count
     bool need_hubs = false;
-    for (int64_t i = (int64_t)blockIdx.x * SM_ROWS + grp; i < lim; i += gs) {
+    for (int64_t i = (int64_t)bid * ROWS + grp; i < lim; i += gs) {
         const bool live = i < count;
         const int32_t x = live ? (int32_t)i : 0;
         RowSrc r;
@@ -965,23 +992,27 @@ __global__ void __launch_bounds__(BLOCK) fill_small_k(Ctx c, int l) {
     }
     if (__ballot(need_hubs) && lane_id() == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_HUBS);
 }
+__global__ void __launch_bounds__(BLOCK) fill_small_k(Ctx c, int l) {
+    fill_small_body<BLOCK>(c, l, blockIdx.x, gridDim.x);
+}
 
 // --- 2b. mid rows: one block per row, bitonic sort in LDS -------------------------
-__global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l) {
+template <int NT>
+__device__ __forceinline__ void fill_mid_body(const Ctx &c, int l, unsigned bid, unsigned nb) {
     __shared__ uint64_t s[MID_P];
-    __shared__ int64_t sh[BLOCK / WAVE + 1];
+    __shared__ int64_t sh[NT / WAVE + 1];
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_CONTRACT, g)) return;
     const int32_t *cmap = L->cmap;
     const int64_t count = c.cs.row_cnt[1];
-    for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+    for (int64_t i = bid; i < count; i += nb) {
         int32_t x = c.cs.rows[g.n + i];
         RowSrc r = row_src(g, c, x);
         int tot = (int)r.tot;
         int P = 2;
         while (P < tot) P <<= 1;
-        for (int t = threadIdx.x; t < P; t += BLOCK) {
+        for (int t = threadIdx.x; t < P; t += NT) {
             uint64_t val = ~0ull;
             if (t < tot) {
                 uint32_t k, w;
@@ -993,7 +1024,7 @@ __global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l) {
         __syncthreads();
         for (int k = 2; k <= P; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int t = threadIdx.x; t < P; t += BLOCK) {
+                for (int t = threadIdx.x; t < P; t += NT) {
                     int ixj = t ^ j;
                     if (ixj > t) {
                         uint64_t a = s[t], b = s[ixj];
@@ -1005,7 +1036,7 @@ __global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l) {
             }
         }
         // leaders: first entry of each run of equal keys
-        const int ipt = (P + BLOCK - 1) / BLOCK;
+        const int ipt = (P + NT - 1) / NT;
         const int t0 = threadIdx.x * ipt;
         int64_t mine = 0;
         for (int q = 0; q < ipt; ++q) {
@@ -1032,27 +1063,32 @@ __global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l) {
         __syncthreads();
     }
 }
+__global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l) {
+    fill_mid_body<BLOCK>(c, l, blockIdx.x, gridDim.x);
+}
 
 // --- 2c. large rows: dense accumulator per slot --------------------------------------
-__global__ void __launch_bounds__(BLOCK) fill_large_k(Ctx c, int l) {
-    __shared__ int64_t s_wcnt[BLOCK / WAVE + 1];
+// Slot `bid` of the hub accumulators (bid < HUB_SLOTS).
+template <int NT>
+__device__ __forceinline__ void fill_large_body(const Ctx &c, int l, unsigned bid, unsigned nb) {
+    __shared__ int64_t s_wcnt[NT / WAVE + 1];
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_CONTRACT, g)) return;
     if (!c.cs.hub_acc) return;
     const int32_t *cmap = L->cmap;
-    uint32_t *acc = c.cs.hub_acc + (int64_t)blockIdx.x * g.n;
-    uint32_t *bits = c.cs.hub_bits + (int64_t)blockIdx.x * c.cs.hub_words;
+    uint32_t *acc = c.cs.hub_acc + (int64_t)bid * g.n;
+    uint32_t *bits = c.cs.hub_bits + (int64_t)bid * c.cs.hub_words;
     const int64_t nc = c.lv[l + 1].n;
     const int64_t nwords = (nc + 31) / 32;
     const int64_t count = c.cs.row_cnt[2];
-    const int nw = BLOCK / WAVE, wv = threadIdx.x / WAVE;
+    const int nw = NT / WAVE, wv = threadIdx.x / WAVE;
     const int64_t span = (nwords + nw - 1) / nw;
     const int64_t lo = wv * span, hi = lo + span < nwords ? lo + span : nwords;
-    for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+    for (int64_t i = bid; i < count; i += nb) {
         int32_t x = c.cs.rows[2 * (int64_t)g.n + i];
         RowSrc r = row_src(g, c, x);
-        for (int64_t t = threadIdx.x; t < r.tot; t += BLOCK) {
+        for (int64_t t = threadIdx.x; t < r.tot; t += NT) {
             uint32_t k, w;
             row_entry(g, cmap, r, t, k, w);
             if (k == INVALID_KEY) continue;
@@ -1096,11 +1132,16 @@ __global__ void __launch_bounds__(BLOCK) fill_large_k(Ctx c, int l) {
         __syncthreads();
     }
 }
+__global__ void __launch_bounds__(BLOCK) fill_large_k(Ctx c, int l) {
+    fill_large_body<BLOCK>(c, l, blockIdx.x, gridDim.x);
+}
 
 // --- 4. compaction ----------------------------------------------------------------
 // Also writes Out(x) = sum of the coarse row's weights when the rating needs
 // it (innerOuter): the next level's matching reads it.
-__global__ void __launch_bounds__(BLOCK) compact_small_k(Ctx c, int l) {
+template <int NT>
+__device__ __forceinline__ void compact_small_body(const Ctx &c, int l, unsigned bid, unsigned nb) {
+    constexpr int ROWS = NT / ROW_SMALL_G;
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_COMPACT, g)) return;
@@ -1108,9 +1149,9 @@ __global__ void __launch_bounds__(BLOCK) compact_small_k(Ctx c, int l) {
     uint32_t *out = c.rating == KAPPA_INNER_OUTER ? c.ms.out : nullptr;
     const int grp = threadIdx.x / ROW_SMALL_G, sub = threadIdx.x % ROW_SMALL_G;
     const int64_t count = N->n;
-    const int64_t gs = (int64_t)gridDim.x * SM_ROWS;
+    const int64_t gs = (int64_t)nb * ROWS;
     const int64_t lim = (count + gs - 1) / gs * gs;   // uniform trip count (group shuffles)
-    for (int64_t x = (int64_t)blockIdx.x * SM_ROWS + grp; x < lim; x += gs) {
+    for (int64_t x = (int64_t)bid * ROWS + grp; x < lim; x += gs) {
         int32_t len = x < count ? c.cs.cdeg[x] : 0;
         bool mine = len > 0;
         RowSrc r;
@@ -1136,21 +1177,26 @@ __global__ void __launch_bounds__(BLOCK) compact_small_k(Ctx c, int l) {
     }
 }
 
-__global__ void __launch_bounds__(BLOCK) compact_big_k(Ctx c, int l) {
-    __shared__ uint32_t sh[BLOCK / WAVE + 1];
+__global__ void __launch_bounds__(BLOCK) compact_small_k(Ctx c, int l) {
+    compact_small_body<BLOCK>(c, l, blockIdx.x, gridDim.x);
+}
+
+template <int NT>
+__device__ __forceinline__ void compact_big_body(const Ctx &c, int l, unsigned bid, unsigned nb) {
+    __shared__ uint32_t sh[NT / WAVE + 1];
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_COMPACT, g)) return;
     const LevelDesc *N = c.lv + l + 1;
     uint32_t *out = c.rating == KAPPA_INNER_OUTER ? c.ms.out : nullptr;
     const int64_t c1 = c.cs.row_cnt[1], c2 = c.cs.row_cnt[2];
-    for (int64_t i = blockIdx.x; i < c1 + c2; i += gridDim.x) {
+    for (int64_t i = bid; i < c1 + c2; i += nb) {
         int32_t x = i < c1 ? c.cs.rows[g.n + i] : c.cs.rows[2 * (int64_t)g.n + (i - c1)];
         RowSrc r = row_src(g, c, x);
         int64_t dst = N->xadj[x];
         int32_t len = c.cs.cdeg[x];
         uint32_t sum = 0;
-        for (int t = threadIdx.x; t < len; t += BLOCK) {
+        for (int t = threadIdx.x; t < len; t += NT) {
             int64_t at = staged_at(r, t);
             uint32_t w = c.cs.tmp_ew[at];
             N->adj[dst + t] = c.cs.tmp_adj[at];
@@ -1161,6 +1207,120 @@ __global__ void __launch_bounds__(BLOCK) compact_big_k(Ctx c, int l) {
             sum = block_sum(sum, sh);
             if (threadIdx.x == 0) out[x] = sum;
         }
+    }
+}
+__global__ void __launch_bounds__(BLOCK) compact_big_k(Ctx c, int l) {
+    compact_big_body<BLOCK>(c, l, blockIdx.x, gridDim.x);
+}
+
+// ===========================================================================
+// Tail: once a level is small, that level and every later one run in a single
+// workgroup, in one launch.  A deep level is a few thousand nodes; as separate
+// grid launches it pays for some twenty launches (each waiting for the one
+// before), while here its phases are separated by workgroup barriers and its
+// arrays stay in the L2 of one XCD from one level to the next.  The phases
+// and their results are those of the grid kernels (same functions, one block).
+// ===========================================================================
+// One level's matching and contraction, as separate (not inlined) functions
+// so that each phase gets the registers of the whole thread.
+// Matching state shared by the two halves of a tail level's matching.
+struct TailMatchLds {
+    int32_t cnt[2][3];   // list sizes by round parity
+};
+
+template <int R>
+__device__ __noinline__ void tail_round1(const Ctx &c, int l, TailMatchLds &t) {
+    __shared__ Cand shc[TAIL_THREADS / WAVE];
+    __shared__ int64_t sh[3 * (TAIL_THREADS / WAVE) + 1];
+    __shared__ int32_t sbase[3];
+    LevelDesc *L = c.lv + l;
+    DevGraph g;
+    load_level(L, PH_MATCH, g);
+    if (threadIdx.x < 3) t.cnt[0][threadIdx.x] = t.cnt[1][threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        L->matched = 0;
+        L->rounds = 0;
+    }
+    __syncthreads();
+    const uint64_t seed = level_seed(c, l);
+    init_phase(c, g, L, sh, sbase, 0, 1, t.cnt[0]);
+    __syncthreads();
+    const RoundIn ri = round_inputs<true>(c, g, 1, t.cnt[0]);
+    pick_bin0<R, true>(c, g, seed, ri, 0, 1);
+    pick_bin1<R, true>(c, g, seed, ri, 0, 1);
+    __syncthreads();
+    pick_bin2<R, true, TAIL_THREADS>(c, g, seed, ri, 0, 1, shc);
+    __syncthreads();
+    mate_phase<R, true>(c, g, L, 1, ri, t.cnt[1], 0, 1, sh, sbase);
+    __syncthreads();
+}
+
+template <int R>
+__device__ __noinline__ void tail_rounds(const Ctx &c, int l, TailMatchLds &t) {
+    __shared__ Cand shc[TAIL_THREADS / WAVE];
+    __shared__ int64_t sh[3 * (TAIL_THREADS / WAVE) + 1];
+    __shared__ int32_t sbase[3];
+    __shared__ int64_t s_acc[2];
+    LevelDesc *L = c.lv + l;
+    DevGraph g;
+    load_level(L, PH_MATCH, g);
+    const bool capped =
+        wg_rounds<R, TAIL_THREADS>(c, g, L, level_seed(c, l), 1, t.cnt, shc, sh, sbase);
+    close_matching<TAIL_THREADS>(c, L, capped, 0, s_acc);
+}
+
+__device__ __noinline__ void tail_ids(const Ctx &c, int l) {
+    __shared__ int64_t sh[ONE_SCAN_THREADS / WAVE + 1];
+    __shared__ int go;
+    scan_one_block(RepF{c, l}, RepW{c, l}, c.cs.totals + 0, sh, &go);
+    __syncthreads();
+}
+
+__device__ __noinline__ void tail_merge(const Ctx &c, int l) {
+    fill_small_body<TAIL_THREADS>(c, l, 0, 1);
+    __syncthreads();
+    fill_mid_body<TAIL_THREADS>(c, l, 0, 1);
+    __syncthreads();
+    fill_large_body<TAIL_THREADS>(c, l, 0, 1);
+    __syncthreads();
+}
+
+__device__ __noinline__ void tail_offsets(const Ctx &c, int l) {
+    __shared__ int64_t sh[ONE_SCAN_THREADS / WAVE + 1];
+    __shared__ int go;
+    scan_one_block(DegF{c, l}, CoarseOffW{c, l}, c.cs.totals + 2, sh, &go);
+    __syncthreads();
+}
+
+__device__ __noinline__ void tail_compact(const Ctx &c, int l) {
+    compact_small_body<TAIL_THREADS>(c, l, 0, 1);
+    __syncthreads();
+    compact_big_body<TAIL_THREADS>(c, l, 0, 1);
+    __syncthreads();
+}
+
+template <int R>
+__global__ void __launch_bounds__(TAIL_THREADS) tail_k(Ctx c, int l0) {
+    __shared__ int go;
+    __shared__ TailMatchLds t;
+    for (int l = l0; l < MAX_LEVELS; ++l) {
+        if (threadIdx.x == 0) {
+            const LevelDesc *L = c.lv + l;
+            // every later level is no larger, so the tail keeps them all
+            const bool fits = L->n <= TAIL_MAX_N && L->nnz <= TAIL_MAX_NNZ;
+            go = fits && level_gate(c, l, true, true);
+        }
+        __syncthreads();
+        if (!go) return;
+        tail_round1<R>(c, l, t);
+        tail_rounds<R>(c, l, t);
+        tail_ids(c, l);
+        tail_merge(c, l);
+        tail_offsets(c, l);
+        tail_compact(c, l);
+        LevelDesc *L = c.lv + l;
+        if (threadIdx.x == 0 && L->phase == PH_COMPACT) L->phase = PH_DONE;
+        __syncthreads();
     }
 }
 
@@ -1355,6 +1515,17 @@ void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, h
     KAPPA_PROF("compact_big", s);
     hipLaunchKernelGGL(compact_big_k, dim3(grid_for(n_hint, 64, 512)), dim3(BLOCK), 0, s, c, l);
     (void)n_cap;
+}
+
+void launch_tail(const Ctx &c, int l, hipStream_t s) {
+    KAPPA_PROF("tail", s);
+    switch (c.rating) {
+    case KAPPA_INNER_OUTER: hipLaunchKernelGGL(tail_k<KAPPA_INNER_OUTER>, dim3(1), dim3(TAIL_THREADS), 0, s, c, l); break;
+    case KAPPA_WEIGHT: hipLaunchKernelGGL(tail_k<KAPPA_WEIGHT>, dim3(1), dim3(TAIL_THREADS), 0, s, c, l); break;
+    case KAPPA_EXPANSION: hipLaunchKernelGGL(tail_k<KAPPA_EXPANSION>, dim3(1), dim3(TAIL_THREADS), 0, s, c, l); break;
+    case KAPPA_EXPANSION_STAR: hipLaunchKernelGGL(tail_k<KAPPA_EXPANSION_STAR>, dim3(1), dim3(TAIL_THREADS), 0, s, c, l); break;
+    default: hipLaunchKernelGGL(tail_k<KAPPA_EXPANSION_STAR2>, dim3(1), dim3(TAIL_THREADS), 0, s, c, l); break;
+    }
 }
 
 void launch_level(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, int32_t n_cap,

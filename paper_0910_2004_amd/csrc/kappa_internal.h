@@ -23,6 +23,11 @@ constexpr int SMALL_G = 4;
 // still point somewhere.
 constexpr int TAIL_MAX = 128;
 constexpr int FINISH_THREADS = 1024;
+// Levels of at most TAIL_MAX_N nodes and TAIL_MAX_NNZ entries (and every
+// level after them) run in one workgroup of TAIL_THREADS threads.
+constexpr int TAIL_THREADS = 1024;
+constexpr int32_t TAIL_MAX_N = 16384;
+constexpr int64_t TAIL_MAX_NNZ = 131072;
 constexpr int STAT_ROUNDS = 64;     // per-round statistics kept per level (last slot aggregates)
 constexpr int MAX_LEVELS = 256;
 
@@ -382,10 +387,12 @@ __global__ void __launch_bounds__(BLOCK) scan_apply_k(F f, W w, const int64_t *w
 constexpr int ONE_SCAN_THREADS = 1024, ONE_SCAN_ITEMS = 16;
 constexpr int64_t ONE_SCAN_CHUNK = (int64_t)ONE_SCAN_THREADS * ONE_SCAN_ITEMS;
 
+// The body, for one workgroup of ONE_SCAN_THREADS threads; sh: LDS of
+// ONE_SCAN_THREADS / WAVE + 1 int64, go: one int of LDS.  Every thread returns
+// at the same point.
 template <class F, class W>
-__global__ void __launch_bounds__(ONE_SCAN_THREADS) scan_one_block_k(F f, W w, int64_t *total) {
-    __shared__ int64_t sh[ONE_SCAN_THREADS / WAVE + 1];
-    __shared__ int go;
+__device__ __forceinline__ void scan_one_block(F f, W w, int64_t *total, int64_t *sh, int *go_p) {
+    int &go = *go_p;
     const int64_t n = f.size();
     if (n < 0) return;
     const int64_t first = (int64_t)threadIdx.x * ONE_SCAN_ITEMS;
@@ -456,6 +463,13 @@ __global__ void __launch_bounds__(ONE_SCAN_THREADS) scan_one_block_k(F f, W w, i
     }
 }
 
+template <class F, class W>
+__global__ void __launch_bounds__(ONE_SCAN_THREADS) scan_one_block_k(F f, W w, int64_t *total) {
+    __shared__ int64_t sh[ONE_SCAN_THREADS / WAVE + 1];
+    __shared__ int go;
+    scan_one_block(f, w, total, sh, &go);
+}
+
 inline int64_t scan_tiles(int64_t n_max) { return (n_max + SCAN_TILE - 1) / SCAN_TILE; }
 
 inline unsigned grid_for(int64_t items, int per_block, unsigned cap = 65535u * 4) {
@@ -504,6 +518,7 @@ enum LevelPhase : int32_t {
     PH_MATCH = 1,     // matching in progress
     PH_CONTRACT = 2,  // matching done, contraction in progress
     PH_COMPACT = 3,   // next level allocated, rows being copied
+    PH_DONE = 4,      // finished inside the tail kernel (later launches for it are no-ops)
     PH_STOPPED = -1   // a stop rule fired on this level
 };
 
@@ -519,7 +534,8 @@ struct LevelDesc {
     int32_t *gid;     // batched form: graph of each node (null for a single graph)
     int32_t *noff;    // batched form: first node of each graph, count + 1 entries
     int64_t matched;
-    int32_t rounds, stop, phase, pad;
+    int32_t rounds, stop, phase;
+    int32_t grid_rounds;   // rounds run by the multi-block kernels (the rest: the finisher)
     int64_t stat[STAT_ROUNDS][2];   // per round: nodes with a free neighbour, their degree sum
 };
 
@@ -681,6 +697,9 @@ void launch_level_out(const Ctx &c, int l, int64_t nnz_cap, int32_t n_hint, hipS
 // k_level.hip: one level of the multilevel loop, driven by device state.
 // n_hint: host estimate of the level's size (grid sizing only).  rounds:
 // multi-block matching rounds before the one-workgroup finisher.
+// Tries the one-workgroup tail from level l (a no-op unless level l is
+// small, not started, and the loop still runs).
+void launch_tail(const Ctx &c, int l, hipStream_t s);
 void launch_level(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, int32_t n_cap,
                   int rounds, hipStream_t s);
 // Batched form, per level: per-graph size and level-count rules before the

@@ -54,6 +54,8 @@ def compare_hierarchy(H, OH, check_rounds=True, check_uncoarsen=True, k=2, part_
             assert lv.matched == ol.matched
         if check_rounds and ol.mate is not None:
             assert lv.rounds == ol.rounds, f"level {l}: rounds {lv.rounds} != {ol.rounds}"
+            gr = int(H.info(l).grid_rounds)   # 0 on levels the one-workgroup tail ran
+            assert 0 <= gr <= lv.rounds, f"level {l}: grid rounds {gr}"
             r, p, d = H.round_stats(l)
             kk = min(r, 64)
             assert np.array_equal(p, ol.round_active[:kk]), f"level {l}: round activity differs"

@@ -1,7 +1,8 @@
 """Full-size parity: the benchmark's workload (random geometric graph,
 n = 2^20, mean degree 8, unit weights, k = 64, stop at 20k nodes) through the
 same entry points and launch configuration bench.py times, compared with the
-oracle level by level (every array, map, round count, cut and balance)."""
+oracle level by level (every array, map, round count, cut and balance); the
+R-MAT of scale 22; and a sample of the 4096-graph batch."""
 import sys
 
 import pytest
@@ -28,6 +29,46 @@ def test_rgg_2_20_full_hierarchy(rating):
     print(f"rgg n={g.n} m={g.m} rating={rating}", flush=True)
     H, OH = check_hierarchy(g, rating, 42, stop_n=20 * 64, k=64)
     print("levels", [lv.graph.n for lv in OH.levels], flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.timeout(1200)
+def test_rmat_scale22_full_hierarchy():
+    """R-MAT scale 22 (n = 2^22, 16 * 2^22 samples, (a, b, c) = (0.57, 0.19,
+    0.19), w uniform in [1, 100]), expansion*2, k = 256, stop at 20k nodes,
+    stall 1/20: every level of the GPU hierarchy against the oracle's, level
+    by level as the oracle produces them, then the way back up."""
+    import numpy as np
+
+    import paper_0910_2004_amd as K
+    from gpu_util import assert_graph_equal, dev, graph_np
+    from workloads import rmat
+    g = rmat(22, 16, seed=3, wseed=33)
+    k, stop_n = 256, 20 * 256
+    print(f"rmat scale 22: n={g.n} m={g.m}", flush=True)
+    H = K.kappa_coarsen(dev(g), O.EXPANSION_STAR2, 42, stop_n, 1, 20, 64)
+    print(f"GPU levels: {[H.info(l).n for l in range(len(H))]}", flush=True)
+    cmaps = []
+    for l, ol in enumerate(O.coarsen_levels(g, O.EXPANSION_STAR2, 42, stop_n, 1, 20, 64)):
+        assert l < len(H), f"GPU hierarchy has {len(H)} levels, the oracle more"
+        lv = H.level(l)
+        assert_graph_equal(graph_np(lv.graph), ol.graph, f"level {l}")
+        assert lv.stop_reason == ol.stop_reason, f"level {l} stop {lv.stop_reason} != {ol.stop_reason}"
+        if ol.cmap is not None:
+            assert np.array_equal(lv.cmap.cpu().numpy(), ol.cmap), f"level {l}: cmap differs"
+            assert lv.matched == ol.matched
+            cmaps.append(ol.cmap)
+        print(f"level {l}: n={ol.graph.n} |M|={ol.matched} stop={ol.stop_reason} equal", flush=True)
+    assert len(H) == l + 1
+    # the way back up: stand-in partition of the coarsest level, projected to
+    # level 0 through the oracle's maps; cut/balance at level 0
+    part0, res = K.kappa_uncoarsen(H, k, 1, 3, 100)
+    part = O.initial_partition(H.info(len(H) - 1).n, k, 1)
+    for cm in reversed(cmaps):
+        part = O.project(cm, part)
+    assert np.array_equal(part0.cpu().numpy(), part)
+    assert res[0].as_tuple() == O.cut_balance(g, part, k, 3, 100).as_tuple()
+    print("uncoarsen: level-0 partition and cut/balance equal", flush=True)
     sys.stdout.flush()
 
 
