@@ -2,10 +2,11 @@
 
 A step is one pass of the whole path over the random geometric graph
 workload (n = 2^20 points in the unit square, radius for mean degree 8, unit
-weights), once per rating the workload names (expansion*2 and innerOuter):
-validation, matching + contraction level by level down to 20*k nodes (k=64),
-the coarsest-level partition, then projection and cut/balance on every level
-back to level 0.  The graph is resident in HBM before the timed region.
+weights): validation of the input (once), then per rating the workload names
+(expansion*2 and innerOuter) matching + contraction level by level down to
+20*k nodes (k=64), the coarsest-level partition, then projection and
+cut/balance on every level back to level 0.  The graph is resident in HBM
+before the timed region.
 
 Prints one JSON line: edges/s = (undirected input edges per step) / (time per
 step), plus the roofline of the dominant kernel (HIP events on the library's
@@ -76,7 +77,7 @@ MODELS = {"pick": "per round r >= 2 run as a grid launch: 16 B per entry of the 
           "mate": "per round r >= 2 run as a grid launch: 12 B per pointing node",
           "pick_first": "per level: 16 B/node + 12 B/entry (innerOuter 20 + 16)",
           "fill_small": "per level: 28 B/coarse row + 16 B/matched pair + 12 B/fine entry + 8 B/coarse entry",
-          "compact_small": "per level: 24 B/coarse row + 16 B/coarse entry",
+          "compact": "per level: 24 B/coarse row + 16 B/coarse entry",
           "cut_entries": "per level: 16 B/entry"}
 
 
@@ -121,7 +122,7 @@ def model_bytes(stats_by_rating):
                     tot["pick"] += bytes_pick_round(pt[r - 1], dg[r - 1])
                     tot["mate"] += bytes_mate_round(pt[r - 1])
                 tot["fill_small"] += bytes_fill_small(n, D, nc, Dc, matched)
-                tot["compact_small"] += bytes_compact(nc, Dc)
+                tot["compact"] += bytes_compact(nc, Dc)
     return tot
 
 
@@ -129,7 +130,7 @@ def model_bytes(stats_by_rating):
 # library's profiler names
 KERNEL_SYMBOLS = {"pick": r"pick_k<\d, false>", "mate": r"mate_k<\d, false>",
                   "pick_first": r"pick_k<\d, true>", "fill_small": r"fill_small_k",
-                  "compact_small": r"compact_small_k", "cut_entries": r"up_entries_k<(true|false)>"}
+                  "compact": r"compact_k", "cut_entries": r"up_entries_k<(true|false)>"}
 COUNTER_SOURCES = ["paper_0910_2004_amd/csrc/k_level.hip", "paper_0910_2004_amd/csrc/kappa_internal.h",
                    "paper_0910_2004_amd/csrc/k_graph.hip"]
 WORKLOAD_RGG = "rgg n=2^20 mean degree 8, both ratings, k=64, stop 1280"
@@ -285,9 +286,13 @@ def main():
     torch.cuda.synchronize()
 
     def step():
+        # the input is validated once per step, then coarsened with each rating
+        st = K.kappa_validate(dg)
+        if st != K.OK:
+            raise RuntimeError(f"kappa_validate: {st}")
         stats = {}
         for r in ratings:
-            H = K.kappa_coarsen(dg, r, seed, stop_n, 1, 20, 64)
+            H = K.kappa_coarsen(dg, r, seed, stop_n, 1, 20, 64, trusted=True)
             _, res = K.kappa_uncoarsen(H, k, part_seed, eps[0], eps[1], part0=part0)
             stats[r] = (level_stats(H), res[0].as_tuple())
             del H

@@ -108,7 +108,14 @@ typedef struct {
     uint32_t stall_num;   /* stop after a level with (n_l - n_{l+1}) * stall_den */
     uint32_t stall_den;   /*   < stall_num * n_l; stall_num = 0 disables the rule */
     int32_t max_levels;   /* at most this many contractions (<= 256) */
+    uint32_t flags;       /* 0, or KAPPA_COARSEN_TRUSTED */
 } kappa_coarsen_params;
+
+/* The caller has checked the graph with kappa_validate (and not changed it
+   since): only the row offsets and the node-weight sum are checked again.
+   A graph that would fail kappa_validate is undefined behaviour (kernels
+   may read outside its arrays). */
+#define KAPPA_COARSEN_TRUSTED 1u
 
 /* Exact cut/balance of a k-way partition (Section 2; imbalance as in
    Section 5.2).  L_max = (1 + eps) c(V)/k + max_v c(v) = lmax_num / lmax_den

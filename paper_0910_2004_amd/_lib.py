@@ -42,7 +42,10 @@ class c_graph_out(ctypes.Structure):
 class c_params(ctypes.Structure):
     _fields_ = [("rating", ctypes.c_int32), ("seed", ctypes.c_uint64), ("stop_n", ctypes.c_int32),
                 ("stall_num", ctypes.c_uint32), ("stall_den", ctypes.c_uint32),
-                ("max_levels", ctypes.c_int32)]
+                ("max_levels", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+COARSEN_TRUSTED = 1   # the graph passed kappa_validate: only its offsets are checked again
 
 
 class c_cut(ctypes.Structure):
@@ -332,8 +335,12 @@ class Hierarchy:
 
 
 def kappa_coarsen(g: DeviceGraph, rating: int = EXPANSION_STAR2, seed: int = 42, stop_n: int = 256,
-                  stall_num: int = 1, stall_den: int = 20, max_levels: int = 64) -> Hierarchy:
-    p = c_params(rating, seed & (2**64 - 1), stop_n, stall_num, stall_den, max_levels)
+                  stall_num: int = 1, stall_den: int = 20, max_levels: int = 64,
+                  trusted: bool = False) -> Hierarchy:
+    """trusted: g passed kappa_validate and is unchanged since (the full
+    structural check is skipped)."""
+    p = c_params(rating, seed & (2**64 - 1), stop_n, stall_num, stall_den, max_levels,
+                 COARSEN_TRUSTED if trusted else 0)
     h = ctypes.c_void_p()
     _check("kappa_coarsen", lib().kappa_coarsen(ctypes.byref(g.c()), ctypes.byref(p), ctypes.byref(h),
                                                 _stream()))
@@ -417,7 +424,7 @@ def kappa_coarsen_batch(u: DeviceGraph, node_off, rating: int = EXPANSION_STAR2,
     if not np.isscalar(stop_n):
         sn = np.ascontiguousarray(np.asarray(stop_n, dtype=np.int32))
         stop_n = 0
-    p = c_params(rating, seed & (2**64 - 1), int(stop_n), stall_num, stall_den, max_levels)
+    p = c_params(rating, seed & (2**64 - 1), int(stop_n), stall_num, stall_den, max_levels, 0)
     h = ctypes.c_void_p()
     _check("kappa_coarsen_batch", lib().kappa_coarsen_batch(
         ctypes.byref(u.c()), count, off.ctypes.data_as(ctypes.c_void_p),

@@ -217,14 +217,14 @@ __global__ void __launch_bounds__(BLOCK) validate_entries_k(DevGraph g, const in
 }
 
 void launch_validate(const DevGraph &g, int32_t *tile_row, uint32_t *flags, uint64_t *sums,
-                     int32_t *maxdeg, hipStream_t s) {
+                     int32_t *maxdeg, hipStream_t s, bool offsets_only) {
     int64_t nt = etiles(g.nnz);
     {
         KAPPA_PROF("validate_offsets", s);
         hipLaunchKernelGGL(validate_offsets_k, dim3(grid_for((int64_t)g.n + 1, BLOCK * 4, 1024)),
                            dim3(BLOCK), 0, s, g, flags, sums, maxdeg);
     }
-    if (nt == 0) return;
+    if (nt == 0 || offsets_only) return;
     launch_tile_rows(g, tile_row, s);
     KAPPA_PROF("validate_entries", s);
     hipLaunchKernelGGL(validate_entries_k, dim3(grid_for(nt, 1, 8192)), dim3(BLOCK), 0, s, g,

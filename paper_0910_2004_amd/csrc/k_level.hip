@@ -863,6 +863,14 @@ struct CoarseOffW {
     __device__ Bound bind() const { return Bound{c.lv[l + 1].xadj}; }
 };
 
+// The coarse-id scan of level l in the calling workgroup (the tail).
+__device__ __noinline__ void ids_one_block(const Ctx &c, int l) {
+    __shared__ int64_t sh[ONE_SCAN_THREADS / WAVE + 1];
+    __shared__ int go;
+    scan_one_block(RepF{c, l}, RepW{c, l}, c.cs.totals + 0, sh, &go);
+    __syncthreads();
+}
+
 // The fine entries of coarse row x: row u, then row w (partner), each
 // without the contracted edge.  t-th entry -> (coarse key, weight);
 // INVALID_KEY for the contracted edge.  The merged row is staged in the same
@@ -1177,10 +1185,6 @@ __device__ __forceinline__ void compact_small_body(const Ctx &c, int l, unsigned
     }
 }
 
-__global__ void __launch_bounds__(BLOCK) compact_small_k(Ctx c, int l) {
-    compact_small_body<BLOCK>(c, l, blockIdx.x, gridDim.x);
-}
-
 template <int NT>
 __device__ __forceinline__ void compact_big_body(const Ctx &c, int l, unsigned bid, unsigned nb) {
     __shared__ uint32_t sh[NT / WAVE + 1];
@@ -1209,8 +1213,13 @@ __device__ __forceinline__ void compact_big_body(const Ctx &c, int l, unsigned b
         }
     }
 }
-__global__ void __launch_bounds__(BLOCK) compact_big_k(Ctx c, int l) {
-    compact_big_body<BLOCK>(c, l, blockIdx.x, gridDim.x);
+// Both row kinds in one launch: blocks [0, small_blocks) copy the small rows,
+// the rest the rows of the mid and large classes.
+__global__ void __launch_bounds__(BLOCK) compact_k(Ctx c, int l, unsigned small_blocks) {
+    if (blockIdx.x < small_blocks)
+        compact_small_body<BLOCK>(c, l, blockIdx.x, small_blocks);
+    else
+        compact_big_body<BLOCK>(c, l, blockIdx.x - small_blocks, gridDim.x - small_blocks);
 }
 
 // ===========================================================================
@@ -1269,13 +1278,6 @@ __device__ __noinline__ void tail_rounds(const Ctx &c, int l, TailMatchLds &t) {
     close_matching<TAIL_THREADS>(c, L, capped, 0, s_acc);
 }
 
-__device__ __noinline__ void tail_ids(const Ctx &c, int l) {
-    __shared__ int64_t sh[ONE_SCAN_THREADS / WAVE + 1];
-    __shared__ int go;
-    scan_one_block(RepF{c, l}, RepW{c, l}, c.cs.totals + 0, sh, &go);
-    __syncthreads();
-}
-
 __device__ __noinline__ void tail_merge(const Ctx &c, int l) {
     fill_small_body<TAIL_THREADS>(c, l, 0, 1);
     __syncthreads();
@@ -1314,7 +1316,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) tail_k(Ctx c, int l0) {
         if (!go) return;
         tail_round1<R>(c, l, t);
         tail_rounds<R>(c, l, t);
-        tail_ids(c, l);
+        ids_one_block(c, l);
         tail_merge(c, l);
         tail_offsets(c, l);
         tail_compact(c, l);
@@ -1508,12 +1510,10 @@ void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, h
     launch_scan((int64_t)n_hint + 1, DegF{c, l}, CoarseOffW{c, l}, c.cs.partials, c.cs.arrive,
                 c.cs.totals + 2, s);
     {
-        KAPPA_PROF("compact_small", s);
-        hipLaunchKernelGGL(compact_small_k, dim3(grid_for(n_hint, SM_ROWS * 2, 4096)), dim3(BLOCK),
-                           0, s, c, l);
+        KAPPA_PROF("compact", s);
+        const unsigned sb = grid_for(n_hint, SM_ROWS * 2, 4096), bb = grid_for(n_hint, 64, 512);
+        hipLaunchKernelGGL(compact_k, dim3(sb + bb), dim3(BLOCK), 0, s, c, l, sb);
     }
-    KAPPA_PROF("compact_big", s);
-    hipLaunchKernelGGL(compact_big_k, dim3(grid_for(n_hint, 64, 512)), dim3(BLOCK), 0, s, c, l);
     (void)n_cap;
 }
 

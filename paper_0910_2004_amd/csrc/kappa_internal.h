@@ -657,8 +657,9 @@ void launch_tile_rows(const DevGraph &g, int32_t *tile_row, hipStream_t s);
 // [2] / [3] = entries above / below the diagonal (must be equal);
 // maxdeg[NSHARD] (zeroed): max row length per shard.  Computes its own tile
 // rows into tile_row.
+// offsets_only: the offsets pass alone (row offsets, c(V), maximum degree).
 void launch_validate(const DevGraph &g, int32_t *tile_row, uint32_t *flags, uint64_t *sums,
-                     int32_t *maxdeg, hipStream_t s);
+                     int32_t *maxdeg, hipStream_t s, bool offsets_only = false);
 void launch_out(const DevGraph &g, const int32_t *tile_row, uint32_t *out, hipStream_t s);
 void launch_rate(const DevGraph &g, const int32_t *tile_row, int rating, const uint32_t *out,
                  uint64_t *num, uint64_t *den, hipStream_t s);

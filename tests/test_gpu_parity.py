@@ -269,3 +269,26 @@ def test_graph_replays_equal_oracle_and_direct_launches():
             x = torch.arange(1 << 16, device="cuda", dtype=torch.int64)
             assert int((x * 2).sum().item()) == (1 << 16) * ((1 << 16) - 1)
             torch.cuda.synchronize()
+
+
+def test_trusted_input_skips_entry_checks_only():
+    """KAPPA_COARSEN_TRUSTED: the same hierarchy as the checked call; broken
+    row offsets are still rejected; unknown flags are an argument error."""
+    import ctypes
+    g = rgg(5000, seed=21)
+    OH = O.coarsen(g, 0, 42, 64, 1, 20, 64)
+    dg = dev(g)
+    assert K.kappa_validate(dg) == K.OK
+    H = K.kappa_coarsen(dg, 0, 42, 64, trusted=True)
+    from gpu_util import compare_hierarchy
+    compare_hierarchy(H, OH, check_rounds=False, k=4)
+    bad = dev(g)
+    bad.xadj[7] = bad.xadj[8] + 1          # offsets no longer monotone
+    with pytest.raises(K.KappaError) as e:
+        K.kappa_coarsen(bad, 0, 42, 64, trusted=True)
+    assert e.value.status == K.E_GRAPH
+    p = K._lib.c_params(0, 42, 64, 1, 20, 64, 6)
+    h = ctypes.c_void_p()
+    st = K.lib().kappa_coarsen(ctypes.byref(dg.c()), ctypes.byref(p), ctypes.byref(h),
+                               K._lib._stream())
+    assert st == K.E_ARG
