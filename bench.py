@@ -481,7 +481,8 @@ def bench_serve(args):
     with every request present to find its sustainable rate; then both paths
     serve the same Poisson arrival trace at 0.7 of that rate.  Latency is
     completion minus scheduled arrival; edges/s is all edges over first
-    arrival to last completion."""
+    arrival to last completion.  The saturated figures serve every request at
+    once (all present at the start) through both paths."""
     import numpy as np
     import torch
 
@@ -495,9 +496,21 @@ def bench_serve(args):
     torch.cuda.set_device(0)
     reqs = [Request(i, g, rating, k) for i, (g, rating, k) in enumerate(mix)]
     serve_plain(reqs[:32])   # warm up
+    BatchServer(workers=2).run(reqs[:32])
     t1 = time.perf_counter()
     serve_plain(reqs)
-    rate = len(reqs) / (time.perf_counter() - t1)
+    plain_s = time.perf_counter() - t1
+    rate = len(reqs) / plain_s
+    total_edges = sum(int(r.graph.m) for r in reqs)
+    # saturated: every request present at once, served by the batching server
+    t1 = time.perf_counter()
+    BatchServer(workers=2).run(reqs)
+    served_s = time.perf_counter() - t1
+    saturated = {"plain_edges_per_s": round(total_edges / plain_s, 1),
+                 "served_edges_per_s": round(total_edges / served_s, 1),
+                 "plain_s": round(plain_s, 3), "served_s": round(served_s, 3),
+                 "speedup": round(plain_s / served_s, 2)}
+    log(f"saturated: {saturated}")
     lam = 0.7 * rate
     gaps = np.random.default_rng(5).exponential(1.0 / lam, size=len(reqs))
     arrivals = np.cumsum(gaps) - gaps[0]
@@ -527,6 +540,7 @@ def bench_serve(args):
                    "requests": len(trace), "rate_req_s": round(lam, 2), "seed": 5},
         "served": served,
         "plain": plain,
+        "saturated": saturated,
     }
     print(json.dumps(out), flush=True)
 

@@ -222,6 +222,16 @@ typedef struct kappa_batch kappa_batch;
 kappa_status kappa_coarsen_batch(const kappa_graph *u, int32_t count, const int32_t *node_off,
                                  const int32_t *stop_n, const kappa_coarsen_params *p,
                                  kappa_batch **out, kappa_stream_t stream);
+/* The batched form over separate graphs: graphs[0 .. count) (host array of
+   descriptors of device graphs, each valid as for kappa_coarsen) are laid out
+   as one block-diagonal union on the device by the library (graph g's nodes
+   follow those of graphs 0 .. g-1), which it owns with the batch; then as
+   kappa_coarsen_batch.  The input graphs need to stay alive only during the
+   call.  KAPPA_E_ARG if the union would exceed 2^31 - 1 nodes. */
+kappa_status kappa_coarsen_graphs(const kappa_graph *graphs, int32_t count, const int32_t *stop_n,
+                                  const kappa_coarsen_params *p, kappa_batch **out,
+                                  kappa_stream_t stream);
+
 int32_t kappa_batch_count(const kappa_batch *b);
 /* levels (host, may be NULL): graph g's level count; stop_reason: its kappa_stop. */
 kappa_status kappa_batch_graph_info(const kappa_batch *b, int32_t g, int32_t *levels,

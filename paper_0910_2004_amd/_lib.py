@@ -114,6 +114,7 @@ def lib():
         "kappa_profile_read": (i32, [P, P, P, i32]),
         "kappa_coarsen_batch": (st, [ctypes.POINTER(c_graph), i32, P, P, ctypes.POINTER(c_params),
                                      ctypes.POINTER(P), P]),
+        "kappa_coarsen_graphs": (st, [P, i32, P, ctypes.POINTER(c_params), ctypes.POINTER(P), P]),
         "kappa_batch_count": (i32, [P]),
         "kappa_batch_graph_info": (st, [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "kappa_batch_hierarchy": (st, [P, i32, ctypes.POINTER(P), P]),
@@ -205,10 +206,12 @@ class DeviceGraph:
     def from_csr(g, device="cuda") -> "DeviceGraph":
         import numpy as np
         import torch
+        # no host copy when the arrays already have these types (the weights'
+        # uint32 bits travel as int32)
         xadj = torch.from_numpy(np.ascontiguousarray(g.xadj, dtype=np.int64)).to(device)
         adj = torch.from_numpy(np.ascontiguousarray(g.adj, dtype=np.int32)).to(device)
-        ew = torch.from_numpy(np.ascontiguousarray(g.ew).astype(np.uint32).view(np.int32)).to(device)
-        vw = torch.from_numpy(np.ascontiguousarray(g.vw).astype(np.uint32).view(np.int32)).to(device)
+        ew = torch.from_numpy(np.ascontiguousarray(g.ew, dtype=np.uint32).view(np.int32)).to(device)
+        vw = torch.from_numpy(np.ascontiguousarray(g.vw, dtype=np.uint32).view(np.int32)).to(device)
         return DeviceGraph(int(g.n), int(g.xadj[-1]), xadj, adj, ew, vw)
 
     @staticmethod
@@ -431,6 +434,29 @@ def kappa_coarsen_batch(u: DeviceGraph, node_off, rating: int = EXPANSION_STAR2,
         sn.ctypes.data_as(ctypes.c_void_p) if sn is not None else None, ctypes.byref(p),
         ctypes.byref(h), _stream()))
     return Batch(h, u.xadj.device, u, count)
+
+
+def kappa_coarsen_graphs(graphs, rating: int = EXPANSION_STAR2, seed: int = 42, stop_n=256,
+                         stall_num: int = 1, stall_den: int = 20, max_levels: int = 64,
+                         trusted: bool = False) -> Batch:
+    """The batched form over separate device graphs (a list of DeviceGraph):
+    the library builds their union on the device.  stop_n: one int for all
+    graphs or a sequence with one per graph."""
+    import numpy as np
+    count = len(graphs)
+    descs = (c_graph * count)(*[g.c() for g in graphs])
+    sn = None
+    if not np.isscalar(stop_n):
+        sn = np.ascontiguousarray(np.asarray(stop_n, dtype=np.int32))
+        stop_n = 0
+    p = c_params(rating, seed & (2**64 - 1), int(stop_n), stall_num, stall_den, max_levels,
+                 COARSEN_TRUSTED if trusted else 0)
+    h = ctypes.c_void_p()
+    _check("kappa_coarsen_graphs", lib().kappa_coarsen_graphs(
+        ctypes.cast(descs, ctypes.c_void_p), count,
+        sn.ctypes.data_as(ctypes.c_void_p) if sn is not None else None, ctypes.byref(p),
+        ctypes.byref(h), _stream()))
+    return Batch(h, graphs[0].xadj.device, None, count)
 
 
 def kappa_initial_partition(n: int, k: int, seed: int, device="cuda"):

@@ -882,22 +882,24 @@ struct kappa_batch {
     kappa_hierarchy union_h;   // the union's levels (owns the arena)
     int32_t count = 0;
     BatchOut out;
+    // the union itself when the library built it (kappa_coarsen_graphs)
+    void *umem = nullptr;
+    size_t umem_bytes = 0;
+    ~kappa_batch() { give_arena(union_h.s, umem, umem_bytes); }
 };
 
-extern "C" kappa_status kappa_coarsen_batch(const kappa_graph *u, int32_t count,
-                                            const int32_t *node_off, const int32_t *stop_n,
-                                            const kappa_coarsen_params *p, kappa_batch **out,
-                                            kappa_stream_t stream) {
-    if (!out) return KAPPA_E_ARG;
-    *out = nullptr;
-    if (!graph_args_ok(u) || !p || count < 1 || !node_off) return KAPPA_E_ARG;
-    if (p->rating < 0 || p->rating > 4 || p->max_levels < 0 || p->max_levels > MAX_LEVELS ||
-        (p->stall_num > 0 && p->stall_den == 0) || (p->flags & ~(uint32_t)KAPPA_COARSEN_TRUSTED))
-        return KAPPA_E_ARG;
-    if (node_off[0] != 0 || node_off[count] != u->n) return KAPPA_E_ARG;
-    for (int32_t g = 0; g < count; ++g)
-        if (node_off[g + 1] < node_off[g]) return KAPPA_E_ARG;
-    hipStream_t s = S(stream);
+namespace {
+
+bool params_ok(const kappa_coarsen_params *p) {
+    return p && p->rating >= 0 && p->rating <= 4 && p->max_levels >= 0 &&
+           p->max_levels <= MAX_LEVELS && !(p->stall_num > 0 && p->stall_den == 0) &&
+           !(p->flags & ~(uint32_t)KAPPA_COARSEN_TRUSTED);
+}
+
+// The batched coarsening of union u into B (B->union_h.s set); arguments checked.
+kappa_status batch_impl(const kappa_graph *u, int32_t count, const int32_t *node_off,
+                        const int32_t *stop_n, const kappa_coarsen_params *p, kappa_batch *B,
+                        hipStream_t s) {
     DevGraph d0 = dev(u);
     int32_t maxdeg = 0;
     kappa_status st = validate_impl(d0, s, &maxdeg, (p->flags & KAPPA_COARSEN_TRUSTED) != 0);
@@ -905,9 +907,6 @@ extern "C" kappa_status kappa_coarsen_batch(const kappa_graph *u, int32_t count,
     std::vector<int32_t> sn(count, p->stop_n);
     if (stop_n) sn.assign(stop_n, stop_n + count);
     BatchIn bi{count, node_off, sn.data()};
-    kappa_batch *B = new (std::nothrow) kappa_batch();
-    if (!B) return KAPPA_E_NOMEM;
-    B->union_h.s = s;
     B->count = count;
     // arena: every level's nodes (vw, xadj, mate, cmap, graph id: 28 B),
     // entries (8 B) and graph offsets, three times level 0 to start with
@@ -927,6 +926,110 @@ extern "C" kappa_status kappa_coarsen_batch(const kappa_graph *u, int32_t count,
         if (retry & CF_ARENA) arena *= 4;
         if (retry & CF_HUBS) hubs = true;
     }
+    return st;
+}
+
+}  // namespace
+
+extern "C" kappa_status kappa_coarsen_batch(const kappa_graph *u, int32_t count,
+                                            const int32_t *node_off, const int32_t *stop_n,
+                                            const kappa_coarsen_params *p, kappa_batch **out,
+                                            kappa_stream_t stream) {
+    if (!out) return KAPPA_E_ARG;
+    *out = nullptr;
+    if (!graph_args_ok(u) || !params_ok(p) || count < 1 || !node_off) return KAPPA_E_ARG;
+    if (node_off[0] != 0 || node_off[count] != u->n) return KAPPA_E_ARG;
+    for (int32_t g = 0; g < count; ++g)
+        if (node_off[g + 1] < node_off[g]) return KAPPA_E_ARG;
+    hipStream_t s = S(stream);
+    kappa_batch *B = new (std::nothrow) kappa_batch();
+    if (!B) return KAPPA_E_NOMEM;
+    B->union_h.s = s;
+    const kappa_status st = batch_impl(u, count, node_off, stop_n, p, B, s);
+    if (st != KAPPA_OK) {
+        delete B;
+        return st;
+    }
+    *out = B;
+    return KAPPA_OK;
+}
+
+extern "C" kappa_status kappa_coarsen_graphs(const kappa_graph *graphs, int32_t count,
+                                             const int32_t *stop_n, const kappa_coarsen_params *p,
+                                             kappa_batch **out, kappa_stream_t stream) {
+    if (!out) return KAPPA_E_ARG;
+    *out = nullptr;
+    if (!graphs || count < 1 || !params_ok(p)) return KAPPA_E_ARG;
+    std::vector<int64_t> off(2 * ((size_t)count + 1), 0);   // node offsets, then entry offsets
+    int64_t *noff = off.data(), *eoff = off.data() + count + 1;
+    std::vector<UnionSrc> src(count);
+    for (int32_t g = 0; g < count; ++g) {
+        if (!graph_args_ok(&graphs[g])) return KAPPA_E_ARG;
+        noff[g + 1] = noff[g] + graphs[g].n;
+        eoff[g + 1] = eoff[g] + graphs[g].nnz;
+        src[g] = UnionSrc{graphs[g].xadj, graphs[g].adj, graphs[g].ew, graphs[g].vw};
+    }
+    const int64_t n = noff[count], nnz = eoff[count];
+    if (n > INT32_MAX) return KAPPA_E_ARG;
+    std::vector<int32_t> node_off(count + 1);
+    for (int32_t g = 0; g <= count; ++g) node_off[g] = (int32_t)noff[g];
+    hipStream_t s = S(stream);
+    kappa_batch *B = new (std::nothrow) kappa_batch();
+    if (!B) return KAPPA_E_NOMEM;
+    B->union_h.s = s;
+    // the union's arrays (library-owned, freed with the batch)
+    Carve lay;
+    int64_t *uxadj = nullptr;
+    int32_t *uadj = nullptr;
+    uint32_t *uew = nullptr, *uvw = nullptr;
+    auto layout = [&](Carve &cv) {
+        uxadj = cv.get<int64_t>(n + 1);
+        uadj = cv.get<int32_t>(nnz);
+        uew = cv.get<uint32_t>(nnz);
+        uvw = cv.get<uint32_t>(n);
+    };
+    layout(lay);
+    size_t got = 0;
+    B->umem = take_arena(s, lay.off, &got);
+    if (!B->umem) {
+        delete B;
+        return KAPPA_E_NOMEM;
+    }
+    B->umem_bytes = got;
+    Carve real;
+    real.base = (char *)B->umem;
+    layout(real);
+    {
+        UnionSrc *dsrc = nullptr;
+        int64_t *doff = nullptr;
+        std::unique_ptr<Workspace> w;
+        if (!carve_workspace(s, w, [&](Carve &cv) {
+                dsrc = cv.get<UnionSrc>(count);
+                doff = cv.get<int64_t>(2 * ((int64_t)count + 1));
+            })) {
+            delete B;
+            return KAPPA_E_NOMEM;
+        }
+        kappa_status st = KAPPA_OK;
+        if (hipMemcpyAsync(dsrc, src.data(), sizeof(UnionSrc) * count, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(doff, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice,
+                           s) != hipSuccess)
+            st = KAPPA_E_HIP;
+        if (st == KAPPA_OK) {
+            launch_union_build(dsrc, count, doff, doff + count + 1, n, nnz, uxadj, uadj, uew, uvw, s);
+            if (hipGetLastError() != hipSuccess) st = KAPPA_E_HIP;
+        }
+        // the descriptors are read by the union kernels before the next holder
+        // of the workspace (stream order); the host vectors must outlive the
+        // copies, which are staged from pageable memory before they return
+        if (st != KAPPA_OK) {
+            delete B;
+            return st;
+        }
+    }
+    kappa_graph u{(int32_t)n, nnz, uxadj, uadj, uew, uvw};
+    const kappa_status st = batch_impl(&u, count, node_off.data(), stop_n, p, B, s);
     if (st != KAPPA_OK) {
         delete B;
         return st;

@@ -1434,6 +1434,64 @@ __global__ void batch_extract_k(DevGraph u, const int32_t *cmap, const int32_t *
     }
 }
 
+// Union of separate graphs (kappa_coarsen_graphs): graph g's nodes and
+// entries move to offsets noff[g] and eoff[g], its ids and row offsets are
+// shifted by those.  The graph of an item is found by binary search over
+// the offsets (count + 1 ascending values).
+__device__ __forceinline__ int32_t owner_of(const int64_t *off, int32_t count, int64_t i) {
+    int32_t lo = 0, hi = count - 1;   // largest g with off[g] <= i
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo + 1) >> 1);
+        if (off[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(BLOCK) union_nodes_k(const UnionSrc *src, int32_t count,
+                                                       const int64_t *noff, const int64_t *eoff,
+                                                       int64_t *xadj, uint32_t *vw) {
+    const int64_t n = noff[count];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= n; v += stride) {
+        if (v == n) {
+            xadj[n] = eoff[count];
+            continue;
+        }
+        const int32_t g = owner_of(noff, count, v);
+        const int64_t i = v - noff[g];
+        xadj[v] = src[g].xadj[i] + eoff[g];
+        vw[v] = src[g].vw[i];
+    }
+}
+
+__global__ void __launch_bounds__(BLOCK) union_entries_k(const UnionSrc *src, int32_t count,
+                                                         const int64_t *noff, const int64_t *eoff,
+                                                         int32_t *adj, uint32_t *ew) {
+    const int64_t nnz = eoff[count];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nnz; j += stride) {
+        const int32_t g = owner_of(eoff, count, j);
+        const int64_t i = j - eoff[g];
+        adj[j] = src[g].adj[i] + (int32_t)noff[g];
+        ew[j] = src[g].ew[i];
+    }
+}
+
+void launch_union_build(const UnionSrc *src, int32_t count, const int64_t *noff,
+                        const int64_t *eoff, int64_t n, int64_t nnz, int64_t *xadj, int32_t *adj,
+                        uint32_t *ew, uint32_t *vw, hipStream_t s) {
+    {
+        KAPPA_PROF("union_nodes", s);
+        hipLaunchKernelGGL(union_nodes_k, dim3(grid_for(n + 1, BLOCK * 4, 8192)), dim3(BLOCK), 0, s,
+                           src, count, noff, eoff, xadj, vw);
+    }
+    if (nnz > 0) {
+        KAPPA_PROF("union_entries", s);
+        hipLaunchKernelGGL(union_entries_k, dim3(grid_for(nnz, BLOCK * 4, 8192)), dim3(BLOCK), 0, s,
+                           src, count, noff, eoff, adj, ew);
+    }
+}
+
 // ===========================================================================
 // Host side
 // ===========================================================================

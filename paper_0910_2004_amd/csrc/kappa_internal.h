@@ -712,6 +712,18 @@ void launch_batch_end(const Ctx &c, int l, hipStream_t s);
 void launch_batch_gid(const int32_t *noff, int32_t count, int32_t *gid, hipStream_t s);
 // flags |= 1 if some row of g has an entry outside its graph's node range.
 void launch_batch_check(const DevGraph &g, uint32_t *flags, hipStream_t s);
+// One graph of a union to build (device arrays).
+struct UnionSrc {
+    const int64_t *xadj;
+    const int32_t *adj;
+    const uint32_t *ew, *vw;
+};
+// The block-diagonal union of `count` graphs (src, noff, eoff in device
+// memory; noff / eoff: count + 1 node and entry offsets) into xadj[n + 1],
+// adj[nnz], ew[nnz], vw[n].
+void launch_union_build(const UnionSrc *src, int32_t count, const int64_t *noff,
+                        const int64_t *eoff, int64_t n, int64_t nnz, int64_t *xadj, int32_t *adj,
+                        uint32_t *ew, uint32_t *vw, hipStream_t s);
 // Copies nodes [a, b) of union level u (entries from ea, nnz of them) with
 // ids made local; cmap/mate (may be null) shifted as well.
 void launch_batch_extract(const DevGraph &u, const int32_t *cmap, const int32_t *mate, int32_t a,

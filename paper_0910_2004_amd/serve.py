@@ -5,14 +5,16 @@ default, as in the experiments' 20 nodes per block) and balance tolerance.
 Whenever a worker is free, the dispatcher takes the requests that have
 arrived -- those with the oldest waiting request's rating and seed, in
 arrival order -- until the batch's estimated device footprint reaches the
-worker's budget or its union's weight sums would leave 32 bits, and hands
-them over.  A worker (one host thread, one HIP
-stream) uploads their union, coarsens all of them together
-(kappa_coarsen_batch), then runs each request's way back up (stand-in
-partition, projection, cut and balance) on its own hierarchy.  Workers run
-concurrently, so batches overlap on the device; requests arriving meanwhile
-wait only for the next free worker.  Each result keeps its hierarchy resident
-on the device when asked to.
+worker's budget or what is left of the device budget (batches in flight and
+hierarchies kept resident count against it), or its union's weight sums
+would leave 32 bits, and hands them over.  A worker (one host thread, one HIP
+stream) uploads the batch's graphs, coarsens all of them together
+(kappa_coarsen_graphs: the library lays out their union on the device), then
+runs each request's way back up (stand-in partition, projection, cut and
+balance) on its own hierarchy.  Workers run concurrently, so batches overlap
+on the device; requests arriving meanwhile wait only for the next free worker
+and for device memory.  Each result keeps its hierarchy resident on the
+device when asked to, until BatchServer.release(result).
 
 `serve_plain` is the reference service: one request at a time, in arrival
 order, through kappa_coarsen and kappa_uncoarsen.
@@ -65,6 +67,12 @@ def footprint(g) -> int:
     """Estimated device bytes of one request inside a batch: input, matching
     and contraction scratch, and the hierarchy (about three times level 0)."""
     return 140 * int(g.n) + 44 * int(g.nnz) + (1 << 16)
+
+
+def kept_bytes(g) -> int:
+    """Estimated device bytes of one request's hierarchy kept resident
+    (every level's c, offsets, mate, cmap and entries: about three times level 0)."""
+    return 3 * (24 * int(g.n) + 8 * int(g.nnz)) + (1 << 12)
 
 
 WEIGHT_CAP = (1 << 32) - 1   # the union's sum of w over E and sum of c over V
@@ -139,19 +147,31 @@ class BatchServer:
     """Continuous batching over `workers` concurrent workers."""
 
     def __init__(self, workers: int = 2, budget_bytes: int = 24 << 30, max_batch: int = 512,
-                 device="cuda"):
+                 device="cuda", hbm_budget: int = 200 << 30):
         self.workers = workers
-        self.budget = budget_bytes
+        self.budget = budget_bytes        # per batch
+        self.hbm_budget = hbm_budget      # batches in flight + kept hierarchies
         self.max_batch = max_batch
         self.device = device
+        self._mem_lock = threading.Lock()
+        self._kept = 0                    # bytes of kept hierarchies
+        self._kept_of = {}                # request id -> its kept bytes
+        self._inflight = 0                # bytes of batches being served
 
     def _run_batch(self, batch: List[Request], t0: float, keep: bool) -> List[Result]:
         start = time.perf_counter() - t0
-        du, off = K.DeviceGraph.union([r.graph for r in batch], self.device)
-        B = K.kappa_coarsen_batch(du, off, batch[0].rating, batch[0].seed,
-                                  [r.stop for r in batch])
+        dgs = [K.DeviceGraph.from_csr(r.graph, self.device) for r in batch]
+        B = K.kappa_coarsen_graphs(dgs, batch[0].rating, batch[0].seed, [r.stop for r in batch])
+        del dgs
         return [_finish(r, B.hierarchy(i), t0, start, len(batch), keep)
                 for i, r in enumerate(batch)]
+
+    def release(self, result: Result):
+        """Drops a kept hierarchy and returns its device memory to the budget."""
+        if result.hierarchy is not None:
+            result.hierarchy = None
+            with self._mem_lock:
+                self._kept -= self._kept_of.pop(result.rid, 0)
 
     def run(self, requests: Sequence[Request], keep: bool = False,
             t0: Optional[float] = None) -> List[Result]:
@@ -179,9 +199,16 @@ class BatchServer:
                         stream.synchronize()
                         with lock:
                             results.extend(res)
+                        if keep:
+                            with self._mem_lock:
+                                for r in batch:
+                                    self._kept_of[r.rid] = kept_bytes(r.graph)
+                                    self._kept += self._kept_of[r.rid]
                     except BaseException as e:   # reported after the loop
                         with lock:
                             errors.append(e)
+                    with self._mem_lock:
+                        self._inflight -= sum(footprint(r.graph) for r in batch)
                     free.put(wid)
 
         threads = [threading.Thread(target=worker, args=(i,), daemon=True)
@@ -201,10 +228,22 @@ class BatchServer:
             if errors:
                 break
             if arrived and idle:
-                batch, arrived = take_batch(arrived, self.budget, self.max_batch, sums)
-                jobs.put(batch)
-                idle.pop()
-                continue
+                with self._mem_lock:
+                    inflight, kept = self._inflight, self._kept
+                room = self.hbm_budget - inflight - kept
+                fp0 = footprint(arrived[0].graph)
+                if fp0 <= room or (inflight == 0 and kept == 0):
+                    batch, arrived = take_batch(arrived, min(self.budget, room), self.max_batch, sums)
+                    with self._mem_lock:
+                        self._inflight += sum(footprint(r.graph) for r in batch)
+                    jobs.put(batch)
+                    idle.pop()
+                    continue
+                if inflight == 0:   # only kept hierarchies stand in the way
+                    errors.append(MemoryError(
+                        f"request {arrived[0].rid} needs ~{fp0} device bytes; kept hierarchies "
+                        f"hold {kept} of the {self.hbm_budget}-byte budget (release results)"))
+                    break
             # nothing to hand out: wait for the next arrival or a free worker
             wait = (todo[0].arrival - now) if (todo and not arrived) else 0.05
             try:

@@ -92,3 +92,23 @@ def test_batch_rejects_edges_between_graphs():
     with pytest.raises(K.KappaError) as e:
         K.kappa_coarsen_batch(dev(g), np.array([0, 9, 8], np.int32), 0)
     assert e.value.status == K.E_ARG
+
+
+@pytest.mark.parametrize("rating", [0, 1])
+def test_graphs_form_equals_union_form_and_oracle(rating):
+    """kappa_coarsen_graphs (separate device graphs, union built by the
+    library) gives every graph the oracle's hierarchy, and the same levels as
+    kappa_coarsen_batch on a union built on the host."""
+    graphs = _mix()
+    stop = [4 + (5 * g) % 33 for g in range(len(graphs))]
+    dgs = [dev(G) for G in graphs]
+    B = K.kappa_coarsen_graphs(dgs, rating, seed=42, stop_n=stop)
+    del dgs   # the batch owns its union
+    du, off = K.DeviceGraph.union(graphs)
+    B2 = K.kappa_coarsen_batch(du, off, rating, seed=42, stop_n=stop)
+    assert len(B) == len(graphs)
+    for g, G in enumerate(graphs):
+        OH = O.coarsen(G, rating, 42, stop[g], 1, 20, 64)
+        assert B.info(g) == B2.info(g) == (len(OH.levels), OH.levels[-1].stop_reason), f"graph {g}"
+        compare_hierarchy(B.hierarchy(g), OH, check_rounds=False, check_uncoarsen=G.n > 0, k=1 + g % 7)
+    say(f"{len(graphs)} graphs equal, rating {rating}")

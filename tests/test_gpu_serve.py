@@ -51,3 +51,23 @@ def test_budget_splits_batches():
     reqs = _requests(12, 0.0, seed=6)
     served = BatchServer(workers=1, budget_bytes=1).run(reqs)
     assert all(r.batch == 1 for r in served)   # one request per batch under a tiny budget
+
+
+def test_kept_hierarchies_count_against_the_device_budget():
+    """Hierarchies kept on the device hold their share of the device budget
+    until released: a second run that does not fit next to them fails with
+    MemoryError instead of waiting forever, and runs once they are released."""
+    from paper_0910_2004_amd.serve import footprint, kept_bytes
+    reqs = _requests(6, 0.0, seed=7)
+    big = max(reqs, key=lambda r: footprint(r.graph))
+    budget = footprint(big.graph) + sum(kept_bytes(r.graph) for r in reqs) - 1
+    srv = BatchServer(workers=1, hbm_budget=budget)
+    first = srv.run(reqs, keep=True)
+    assert all(r.hierarchy is not None for r in first)
+    again = [Request(100, big.graph, big.rating, big.k)]
+    with pytest.raises(MemoryError):
+        srv.run(again, keep=True)
+    for r in first:
+        srv.release(r)
+    out = srv.run(again)
+    assert out[0].rid == 100
