@@ -362,7 +362,8 @@ def main():
         cpu = {"value": round(edges_step / (t4 - t3), 1), "unit": "edges/s", "cores": 1,
                "kind": "oracle",
                "sample": "one full step (both ratings) of the same workload on one host thread; "
-                         f"{t4 - t3:.2f} s"}
+                         f"{t4 - t3:.2f} s",
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
     levels = {("expansion*2" if r == 0 else "innerOuter"): [x[0] for x in lv[r]] for r in ratings}
     lv_json = {str(r): [list(x[:5]) for x in lv[r]] for r in ratings}
@@ -448,6 +449,9 @@ def bench_batch(args):
         del H
     torch.cuda.synchronize()
     loop_ms = (time.perf_counter() - t2) * 1e3
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = batch_cpu_baseline(graphs)
     out = {
         "metric": "coarsening edges/s per GPU (batched form, 4096 graphs)",
         "value": round(edges / (ms / 1e3), 1),
@@ -469,8 +473,48 @@ def bench_batch(args):
         "plain_loop": {"ms": round(loop_ms, 1), "value": round(edges / (loop_ms / 1e3), 1),
                        "unit": "edges/s", "kind": "one kappa_coarsen call per graph"},
         "speedup_vs_plain_loop": round(loop_ms / ms, 2),
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def _oracle_one(args):
+    import oracle as O
+    g, seed, stop_n = args
+    O.coarsen(g, 0, seed, stop_n, 1, 20, 64)
+    return int(g.m)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def batch_cpu_baseline(graphs, sample=256):
+    """The oracle on a sample of the batch's graphs (every 16th): one host
+    thread, then all host cores with the graphs split over processes."""
+    from concurrent.futures import ProcessPoolExecutor
+    sub = graphs[::max(1, len(graphs) // sample)][:sample]
+    work = [(g, 4, 256) for g in sub]
+    t0 = time.perf_counter()
+    edges = sum(_oracle_one(w) for w in work)
+    one = time.perf_counter() - t0
+    cores = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(_oracle_one, work, chunksize=4))
+    many = time.perf_counter() - t0
+    return {"value": round(edges / one, 1), "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(sub)} of the {len(graphs)} graphs (every {len(graphs) // len(sub)}th), "
+                      f"{edges} edges, {one:.2f} s on one thread",
+            "all_cores": {"value": round(edges / many, 1), "cores": cores, "s": round(many, 2)},
+            "cpu_model": cpu_model()}
 
 
 def bench_serve(args):

@@ -284,6 +284,20 @@ void kappa_profile_reset(void);
    Synchronises the device. */
 int32_t kappa_profile_read(const char **names, int64_t *launches, double *ms, int32_t cap);
 
+/* Device allocator for all memory the library allocates (workspaces,
+   hierarchy arenas, batch unions).  alloc(bytes, stream, ctx) returns a
+   device pointer usable in stream order on `stream` (NULL: out of memory);
+   dealloc(ptr, bytes, stream, ctx) returns it once the work enqueued on
+   `stream` before the call no longer needs it (stream NULL: the device is
+   idle).  Both NULL restores the default, the device's stream-ordered pool
+   (hipMallocAsync / hipFreeAsync).  The call first releases the memory cache
+   (as kappa_cache_release: no call may be running); hierarchies and batches
+   that are still alive return their memory to the allocator they came from.
+   KAPPA_E_ARG if exactly one of alloc and dealloc is NULL. */
+typedef void *(*kappa_alloc_fn)(size_t bytes, kappa_stream_t stream, void *ctx);
+typedef void (*kappa_free_fn)(void *ptr, size_t bytes, kappa_stream_t stream, void *ctx);
+kappa_status kappa_set_allocator(kappa_alloc_fn alloc, kappa_free_fn dealloc, void *ctx);
+
 /* Device memory kept between calls: per stream, one workspace for call-local
    buffers (grown on demand, reused by the next call on that stream) and up
    to four arenas of freed hierarchies (reused by kappa_coarsen on that

@@ -12,5 +12,5 @@ from ._lib import (  # noqa: F401
     declared_functions, lib, status_str, union_csr,
     kappa_validate, kappa_rate, kappa_match, kappa_contract, kappa_coarsen, kappa_coarsen_batch, kappa_coarsen_graphs,
     kappa_initial_partition, kappa_project, kappa_cut_balance, kappa_uncoarsen, kappa_cache_release,
-    graphs_enable, tail_enable, arena_first, profile_enable, profile_reset, profile_read,
+    graphs_enable, tail_enable, arena_first, use_torch_allocator, profile_enable, profile_reset, profile_read,
 )

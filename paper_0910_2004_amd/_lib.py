@@ -66,6 +66,11 @@ class c_level_info(ctypes.Structure):
 
 _lib = None
 
+# kappa_set_allocator callbacks (kept referenced while installed)
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_allocator = None
+
 
 def declared_functions() -> List[str]:
     """Names of the functions declared in include/kappa.h."""
@@ -123,6 +128,7 @@ def lib():
         "kappa_graphs_enable": (None, [i32]),
         "kappa_arena_first": (None, [u64]),
         "kappa_tail_enable": (None, [i32]),
+        "kappa_set_allocator": (st, [_ALLOC_FN, _FREE_FN, P]),
         "kappa_status_str": (ctypes.c_char_p, [st]),
         "kappa_version": (ctypes.c_char_p, []),
     }
@@ -510,6 +516,33 @@ def graphs_enable(on: bool = True):
     """Replay repeated launch sequences as HIP graphs (on) or launch every
     kernel directly (off, the library's default)."""
     lib().kappa_graphs_enable(1 if on else 0)
+
+
+def use_torch_allocator(on: bool = True):
+    """Let the library take its device memory (workspaces, hierarchy arenas,
+    batch unions) from torch's caching allocator, on the stream of each call,
+    so that it shows in torch's memory statistics and shares its pool; off:
+    the device's stream-ordered pool (the library's default).  Switching
+    releases the library's memory cache: no call may be running."""
+    global _allocator
+    import torch
+    if on:
+        def _alloc(nbytes, stream, ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                          int(stream or 0))
+            except Exception:   # out of memory: the library reports KAPPA_E_NOMEM
+                return None
+
+        def _free(ptr, nbytes, stream, ctx):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        cbs = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+        _check("kappa_set_allocator", lib().kappa_set_allocator(cbs[0], cbs[1], None))
+        _allocator = cbs
+    else:
+        _check("kappa_set_allocator", lib().kappa_set_allocator(_ALLOC_FN(), _FREE_FN(), None))
+        _allocator = None
 
 
 def tail_enable(on: bool = True):

@@ -139,6 +139,57 @@ void pool_init() {
 
 constexpr size_t KEEP_ARENAS = 4;
 
+// The device allocator (kappa_set_allocator); the default is the device's
+// stream-ordered pool.  Every block remembers the allocator it came from.
+struct Allocator {
+    kappa_alloc_fn alloc = nullptr;
+    kappa_free_fn dealloc = nullptr;
+    void *ctx = nullptr;
+    bool operator==(const Allocator &o) const {
+        return alloc == o.alloc && dealloc == o.dealloc && ctx == o.ctx;
+    }
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+
+Allocator current_allocator() {
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    return g_alloc;
+}
+
+void *dev_alloc(size_t bytes, hipStream_t s, const Allocator &al, const char *what) {
+    void *p = nullptr;
+    if (al.alloc) {
+        p = al.alloc(bytes, (kappa_stream_t)s, al.ctx);
+        if (!p) alloc_failed(what, bytes, hipErrorOutOfMemory);
+        return p;
+    }
+    pool_init();
+    const hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e != hipSuccess || !p) {
+        alloc_failed(what, bytes, e);
+        return nullptr;
+    }
+    return p;
+}
+
+// idle: the device has no work left that uses p (free at once, no stream).
+void dev_free(void *p, size_t bytes, hipStream_t s, const Allocator &al, bool idle = false) {
+    if (!p) return;
+    if (al.dealloc)
+        al.dealloc(p, bytes, (kappa_stream_t)s, al.ctx);
+    else if (idle)
+        (void)hipFree(p);
+    else
+        (void)hipFreeAsync(p, s);
+}
+
+struct CachedArena {
+    void *p;
+    size_t bytes;
+    Allocator al;
+};
+
 struct GraphEntry {
     std::vector<uint64_t> key;
     hipGraphExec_t exec;      // nullptr: capture failed, run directly
@@ -150,8 +201,9 @@ struct StreamCache {
     std::mutex mu;            // held by the call using `ws` (and the graph cache)
     char *ws = nullptr;
     size_t ws_bytes = 0;
+    Allocator ws_al;          // the allocator of `ws`
     std::mutex amu;           // guards `arenas`
-    std::vector<std::pair<void *, size_t>> arenas;
+    std::vector<CachedArena> arenas;
     // launch sequences replayed as graphs (see run_seq)
     hipStream_t side = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -196,20 +248,17 @@ struct Workspace {
     std::unique_lock<std::mutex> lk;
     char *base = nullptr;
     Workspace(hipStream_t s, size_t bytes) : c(cache_of(s)), lk(c->mu) {
-        pool_init();
-        if (c->ws_bytes < bytes) {
-            if (c->ws) (void)hipFreeAsync(c->ws, s);
+        const Allocator al = current_allocator();
+        if (c->ws_bytes < bytes || !(c->ws_al == al)) {
+            dev_free(c->ws, c->ws_bytes, s, c->ws_al);
             c->ws = nullptr;
             c->ws_bytes = 0;
             size_t want = bytes + bytes / 4 + 4096;
-            void *p = nullptr;
-            const hipError_t e = hipMallocAsync(&p, want, s);
-            if (e != hipSuccess || !p) {
-                alloc_failed("workspace", want, e);
-                return;
-            }
+            void *p = dev_alloc(want, s, al, "workspace");
+            if (!p) return;
             c->ws = (char *)p;
             c->ws_bytes = want;
+            c->ws_al = al;
         }
         base = c->ws;
     }
@@ -228,42 +277,42 @@ bool carve_workspace(hipStream_t s, std::unique_ptr<Workspace> &w, L &&layout) {
     return true;
 }
 
-void *take_arena(hipStream_t s, size_t bytes, size_t *got) {
+// An arena of at least `bytes` from the current allocator (recycled if the
+// stream's cache has one); *got: its size, *al: its allocator.
+void *take_arena(hipStream_t s, size_t bytes, size_t *got, Allocator *al) {
     StreamCache *c = cache_of(s);
+    *al = current_allocator();
     {
         std::lock_guard<std::mutex> g(c->amu);
         int best = -1;
         for (size_t i = 0; i < c->arenas.size(); ++i)
-            if (c->arenas[i].second >= bytes &&
-                (best < 0 || c->arenas[i].second < c->arenas[best].second))
+            if (c->arenas[i].bytes >= bytes && c->arenas[i].al == *al &&
+                (best < 0 || c->arenas[i].bytes < c->arenas[best].bytes))
                 best = (int)i;
         if (best >= 0) {
-            void *p = c->arenas[best].first;
-            *got = c->arenas[best].second;
+            void *p = c->arenas[best].p;
+            *got = c->arenas[best].bytes;
             c->arenas.erase(c->arenas.begin() + best);
             return p;
         }
     }
-    pool_init();
-    void *p = nullptr;
-    const hipError_t e = hipMallocAsync(&p, bytes, s);
-    if (e != hipSuccess || !p) {
-        alloc_failed("arena", bytes, e);
-        return nullptr;
-    }
+    void *p = dev_alloc(bytes, s, *al, "arena");
+    if (!p) return nullptr;
     *got = bytes;
     return p;
 }
 
-void give_arena(hipStream_t s, void *p, size_t bytes) {
+void give_arena(hipStream_t s, void *p, size_t bytes, const Allocator &al) {
     if (!p) return;
     StreamCache *c = cache_of(s);
-    std::lock_guard<std::mutex> g(c->amu);
-    if (c->arenas.size() < KEEP_ARENAS) {
-        c->arenas.emplace_back(p, bytes);
-        return;
+    {
+        std::lock_guard<std::mutex> g(c->amu);
+        if (c->arenas.size() < KEEP_ARENAS && al == current_allocator()) {
+            c->arenas.push_back(CachedArena{p, bytes, al});
+            return;
+        }
     }
-    (void)hipFreeAsync(p, s);
+    dev_free(p, bytes, s, al);
 }
 
 // ---------------------------------------------------------------------------
@@ -357,7 +406,8 @@ struct ArenaHold {
     hipStream_t s;
     void *p;
     size_t bytes;
-    ~ArenaHold() { give_arena(s, p, bytes); }
+    Allocator al;
+    ~ArenaHold() { give_arena(s, p, bytes, al); }
     void *release() {
         void *q = p;
         p = nullptr;
@@ -561,7 +611,8 @@ struct kappa_hierarchy {
     std::vector<kappa_level> levels;
     void *arena = nullptr;
     size_t arena_bytes = 0;
-    ~kappa_hierarchy() { give_arena(s, arena, arena_bytes); }
+    Allocator al;   // the allocator of `arena`
+    ~kappa_hierarchy() { give_arena(s, arena, arena_bytes, al); }
 };
 
 namespace {
@@ -622,11 +673,12 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     const uint64_t arena_bytes = std::max<uint64_t>(*arena_io, opening);
     *arena_io = arena_bytes;
     size_t arena_got = 0;
-    void *arena = take_arena(s, arena_bytes, &arena_got);
+    Allocator arena_al;
+    void *arena = take_arena(s, arena_bytes, &arena_got, &arena_al);
     if (!arena) return KAPPA_E_NOMEM;
     // a recycled arena may be larger than asked for: all of it is usable
     const uint64_t cap = exact_cap ? arena_bytes : arena_got;
-    ArenaHold hold{s, arena, arena_got};
+    ArenaHold hold{s, arena, arena_got, arena_al};
     fill_scratch(d0, c, s);
 
     // control block and level 0
@@ -798,6 +850,7 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     }
     H->arena = hold.release();
     H->arena_bytes = arena_got;
+    H->al = arena_al;
     return KAPPA_OK;
 }
 
@@ -885,7 +938,8 @@ struct kappa_batch {
     // the union itself when the library built it (kappa_coarsen_graphs)
     void *umem = nullptr;
     size_t umem_bytes = 0;
-    ~kappa_batch() { give_arena(union_h.s, umem, umem_bytes); }
+    Allocator umem_al;
+    ~kappa_batch() { give_arena(union_h.s, umem, umem_bytes, umem_al); }
 };
 
 namespace {
@@ -990,7 +1044,7 @@ extern "C" kappa_status kappa_coarsen_graphs(const kappa_graph *graphs, int32_t 
     };
     layout(lay);
     size_t got = 0;
-    B->umem = take_arena(s, lay.off, &got);
+    B->umem = take_arena(s, lay.off, &got, &B->umem_al);
     if (!B->umem) {
         delete B;
         return KAPPA_E_NOMEM;
@@ -1092,7 +1146,7 @@ extern "C" kappa_status kappa_batch_hierarchy(const kappa_batch *b, int32_t g,
     if (!H) return KAPPA_E_NOMEM;
     H->s = s;
     size_t got = 0;
-    void *arena = take_arena(s, lay.off, &got);
+    void *arena = take_arena(s, lay.off, &got, &H->al);
     if (!arena) return KAPPA_E_NOMEM;
     H->arena = arena;
     H->arena_bytes = got;
@@ -1454,12 +1508,26 @@ extern "C" kappa_status kappa_cache_release(void) {
             if (e.exec) (void)hipGraphExecDestroy(e.exec);
         c->graphs.clear();
         c->seen.clear();
-        if (c->ws) (void)hipFree(c->ws);
+        // the device is idle: blocks go back without stream order (the stream
+        // a cache belongs to may no longer exist)
+        dev_free(c->ws, c->ws_bytes, nullptr, c->ws_al, true);
         c->ws = nullptr;
         c->ws_bytes = 0;
-        for (auto &pr : c->arenas) (void)hipFree(pr.first);
+        for (const CachedArena &ca : c->arenas) dev_free(ca.p, ca.bytes, nullptr, ca.al, true);
         c->arenas.clear();
     }
+    return KAPPA_OK;
+}
+
+extern "C" kappa_status kappa_set_allocator(kappa_alloc_fn alloc, kappa_free_fn dealloc,
+                                            void *ctx) {
+    if ((alloc == nullptr) != (dealloc == nullptr)) return KAPPA_E_ARG;
+    const kappa_status st = kappa_cache_release();
+    if (st != KAPPA_OK) return st;
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    g_alloc.alloc = alloc;
+    g_alloc.dealloc = dealloc;
+    g_alloc.ctx = ctx;
     return KAPPA_OK;
 }
 
