@@ -115,10 +115,16 @@ __device__ __forceinline__ Cand cand_none() {
 __device__ __forceinline__ bool cand_better(const Cand &a, const Cand &b, int32_t v) {
     if (a.u < 0) return false;
     if (b.u < 0) return true;
-    uint64_t l_lo = a.num * b.den, l_hi = __umul64hi(a.num, b.den);
-    uint64_t r_lo = b.num * a.den, r_hi = __umul64hi(b.num, a.den);
-    if (l_hi != r_hi) return l_hi > r_hi;
-    if (l_lo != r_lo) return l_lo > r_lo;
+    if (((a.num | a.den | b.num | b.den) >> 32) == 0) {
+        // all four below 2^32: the cross products fit 64 bits
+        const uint64_t l = a.num * b.den, r = b.num * a.den;
+        if (l != r) return l > r;
+    } else {
+        uint64_t l_lo = a.num * b.den, l_hi = __umul64hi(a.num, b.den);
+        uint64_t r_lo = b.num * a.den, r_hi = __umul64hi(b.num, a.den);
+        if (l_hi != r_hi) return l_hi > r_hi;
+        if (l_lo != r_lo) return l_lo > r_lo;
+    }
     if (a.h != b.h) return a.h > b.h;
     return edge_id(v, a.u) < edge_id(v, b.u);
 }
