@@ -225,6 +225,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scale", type=int, default=20, help="log2 of the node count")
     ap.add_argument("--k", type=int, default=64)
+    ap.add_argument("--order", default="generation", choices=["generation", "rcb"],
+                    help="rgg20: node ids in point generation order (the headline) or in "
+                         "recursive coordinate bisection order (locality of a geometric "
+                         "prepartition)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-out", default=None)
     ap.add_argument("--workload", default="rgg20", choices=["rgg20", "batch4096", "serve"],
@@ -280,8 +284,8 @@ def main():
     ratings = [K.EXPANSION_STAR2, K.INNER_OUTER]
 
     t0 = time.time()
-    g = rgg(n, seed=2)
-    log(f"generated rgg n={g.n} |E|={g.m} in {time.time() - t0:.1f}s")
+    g = rgg(n, seed=2, order=args.order)
+    log(f"generated rgg n={g.n} |E|={g.m} ({args.order} order) in {time.time() - t0:.1f}s")
     torch.cuda.set_device(0)
     dg = K.DeviceGraph.from_csr(g, "cuda:0")
     part0 = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
@@ -345,7 +349,8 @@ def main():
         per_launch_bytes = mb[rk] / (cnt / args.steps)
         avg_s = ms / cnt / 1e3
         achieved = per_launch_bytes / avg_s / 1e9
-        traffic = counter_traffic(rk)
+        # the stored counters were taken on the generation-order graph
+        traffic = counter_traffic(rk) if args.order == "generation" else None
         roof = {"bound": "hbm", "kernel": rk, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else int(traffic),
@@ -385,7 +390,10 @@ def main():
         "dtype": "u32/u64 (exact integer; 128-bit rating compares)",
         "data": "synthetic",
         "config": {"workload": f"rgg n=2^{args.scale} mean degree 8, unit weights, both ratings "
-                               f"(expansion*2, innerOuter), k={k}, stop n<={stop_n}, eps=3/100",
+                               f"(expansion*2, innerOuter), k={k}, stop n<={stop_n}, eps=3/100"
+                               + ("" if args.order == "generation" else
+                                  ", node ids in recursive coordinate bisection order"),
+                   "node_order": args.order,
                    "n": g.n, "m": g.m, "edges_per_step": edges_step, "k": k, "stop_n": stop_n,
                    "seed": seed, "graph_seed": 2, "levels_n": levels},
         "roofline": roof,

@@ -162,6 +162,14 @@ def test_medium_rgg_and_rmat(rating):
     check_hierarchy(rmat(13, 16, seed=12, wseed=13), rating, 4, stop_n=20 * 64, k=64)
 
 
+@pytest.mark.parametrize("rating", [0, 1])
+def test_rgg_in_rcb_order(rating):
+    # node ids in recursive coordinate bisection order (the locality a
+    # geometric prepartition gives): the same kernels, the same oracle
+    say("rgg 2^17 rcb order", rating)
+    check_hierarchy(rgg(1 << 17, seed=21, order="rcb"), rating, 42, stop_n=20 * 64, k=64)
+
+
 def test_hub_rows_and_degree_classes():
     """Stars and cliques exercise the one-block pick (deg > 1024) and the mid
     and large coarse-row classes (bounds above 64 and above 4094)."""

@@ -130,14 +130,46 @@ def rgg_points(n: int, seed: int) -> np.ndarray:
     return np.random.Generator(np.random.PCG64(seed)).random((n, 2))
 
 
+def rcb_order(pts: np.ndarray, leaf: int = 32) -> np.ndarray:
+    """Indices of the points in recursive coordinate bisection order (the
+    geometric prepartition of Section 3.3): a box is split at its median
+    x-coordinate at even depths and its median y-coordinate at odd depths,
+    the lower half numbered first, down to boxes of at most `leaf` points
+    (kept in input order)."""
+    n = len(pts)
+    out = np.arange(n)
+    segs = [(0, n)]
+    depth = 0
+    while segs:
+        nxt = []
+        for a, b in segs:
+            if b - a <= leaf:
+                continue
+            sub = out[a:b]
+            mid = (b - a) // 2
+            part = np.argpartition(pts[sub, depth % 2], mid)
+            out[a:b] = sub[part]
+            nxt += [(a, a + mid), (a + mid, b)]
+        segs = nxt
+        depth += 1
+    return out
+
+
 def rgg(n: int, seed: int, radius: Optional[float] = None, mean_degree: float = 8.0,
         ew: Optional[np.ndarray] = None, vw: Optional[np.ndarray] = None,
-        points: Optional[np.ndarray] = None) -> CSR:
-    """Random geometric graph in the unit square; edge iff distance < radius."""
+        points: Optional[np.ndarray] = None, order: str = "generation") -> CSR:
+    """Random geometric graph in the unit square; edge iff distance < radius.
+    order: node ids in the points' generation order, or "rcb" (recursive
+    coordinate bisection order, the geometric prepartition of the paper's
+    partitioner)."""
     from scipy.spatial import cKDTree
     if radius is None:
         radius = math.sqrt(mean_degree / (math.pi * n))
     pts = rgg_points(n, seed) if points is None else points
+    if order == "rcb":
+        pts = pts[rcb_order(pts)]
+    elif order != "generation":
+        raise ValueError(f"unknown order {order!r}")
     pairs = cKDTree(pts).query_pairs(radius, output_type="ndarray")
     if len(pairs):
         d = pts[pairs[:, 0]] - pts[pairs[:, 1]]
