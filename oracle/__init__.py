@@ -63,6 +63,8 @@ def lib():
         L.orc_match_greedy.restype = i64
         L.orc_match_rounds.argtypes = [i32, i64, P, P, P, P, ctypes.c_int, u64, P, P, P, P, i32]
         L.orc_match_rounds.restype = i32
+        L.orc_match_two_phase.argtypes = [i32, i64, P, P, P, P, ctypes.c_int, u64, i32, P, P, P, P]
+        L.orc_match_two_phase.restype = i64
         L.orc_contract.argtypes = [i32, i64, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_contract.restype = i32
         L.orc_initial_partition.argtypes = [i32, i32, u64, P]
@@ -161,6 +163,22 @@ def match_rounds(g, rating: int, seed_l: int, max_rounds: int = 1 << 16):
                                _p(act), _p(deg), max_rounds)
     k = min(r, max_rounds)
     return mate[:g.n], int(matched.value), int(r), act[:k].copy(), deg[:k].copy()
+
+
+def match_two_phase(g, rating: int, seed_l: int, block_bits: int):
+    """The two-phase matcher of Section 3.3 (blocks of 2^block_bits
+    consecutive ids; Greedy inside blocks, then Greedy on the gap graph).
+    Returns (mate, |M|, block matching, gap-graph edges, gap edges matched)."""
+    if not 0 <= block_bits <= 31:
+        raise ValueError("block_bits must be in [0, 31]")
+    g = Graph.of(g)
+    mate = np.empty(max(g.n, 1), dtype=np.int32)
+    loc = np.empty(max(g.n, 1), dtype=np.int32)
+    ge, gm = ctypes.c_int64(0), ctypes.c_int64(0)
+    m = lib().orc_match_two_phase(g.n, g.nnz, _p(g.xadj), _p(g.adj), _p(g.ew), _p(g.vw),
+                                  rating, ctypes.c_uint64(seed_l), block_bits, _p(mate), _p(loc),
+                                  ctypes.byref(ge), ctypes.byref(gm))
+    return mate[:g.n], int(m), loc[:g.n], int(ge.value), int(gm.value)
 
 
 def contract(g, mate: np.ndarray):
@@ -269,7 +287,8 @@ class Hierarchy:
 
 def coarsen_levels(g, rating: int = EXPANSION_STAR2, seed: int = 42, stop_n: int = 256,
                    stall_num: int = 1, stall_den: int = 20, max_levels: int = 64,
-                   cross_check: bool = False, round_stats: bool = False):
+                   cross_check: bool = False, round_stats: bool = False,
+                   block_bits: Optional[int] = None):
     """Contract until small (Section 2, contraction phase), one level at a time.
 
     Yields each level once it is final: with its matching, cmap and |M| if it
@@ -280,6 +299,10 @@ def coarsen_levels(g, rating: int = EXPANSION_STAR2, seed: int = 42, stop_n: int
     local-max scheme of Section 3.3.  ``cross_check`` also runs the round
     formulation and asserts that both give the same matching; ``round_stats``
     records the round statistics (from the round formulation).
+
+    With ``block_bits`` set, every level is matched by the two-phase scheme
+    of Section 3.3 instead (match_two_phase, blocks of 2^block_bits
+    consecutive ids of that level); round statistics are then not recorded.
 
     Stop rules: before matching level l, stop if n_l <= stop_n (SIZE) or
     l == max_levels (MAXLEVEL); if the matching is empty, stop (EMPTY); after
@@ -299,8 +322,11 @@ def coarsen_levels(g, rating: int = EXPANSION_STAR2, seed: int = 42, stop_n: int
             yield cur
             return
         s = level_seed(seed, l)
-        mate, m = match_greedy(G, rating, s)
-        if cross_check or round_stats:
+        if block_bits is not None:
+            mate, m = match_two_phase(G, rating, s, block_bits)[:2]
+        else:
+            mate, m = match_greedy(G, rating, s)
+        if block_bits is None and (cross_check or round_stats):
             mate_b, m_b, r, act, deg = match_rounds(G, rating, s)
             if cross_check:
                 assert m_b == m and np.array_equal(mate_b, mate), "Greedy != local-max rounds"
@@ -324,10 +350,11 @@ def coarsen_levels(g, rating: int = EXPANSION_STAR2, seed: int = 42, stop_n: int
 
 def coarsen(g, rating: int = EXPANSION_STAR2, seed: int = 42, stop_n: int = 256,
             stall_num: int = 1, stall_den: int = 20, max_levels: int = 64,
-            cross_check: bool = False, round_stats: bool = False) -> Hierarchy:
+            cross_check: bool = False, round_stats: bool = False,
+            block_bits: Optional[int] = None) -> Hierarchy:
     """The whole hierarchy of coarsen_levels (same arguments)."""
     return Hierarchy(list(coarsen_levels(g, rating, seed, stop_n, stall_num, stall_den, max_levels,
-                                         cross_check, round_stats)))
+                                         cross_check, round_stats, block_bits)))
 
 
 def uncoarsen(H: Hierarchy, k: int, part_seed: int = 1, eps_num: int = 3, eps_den: int = 100):

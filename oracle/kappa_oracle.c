@@ -299,6 +299,87 @@ int32_t orc_match_rounds(int32_t n, int64_t nnz, const int64_t *xadj, const int3
 }
 
 /* ------------------------------------------------------------------------ */
+/* Matching, formulation C: the two-phase scheme of Section 3.3.            */
+/*   1. A preliminary partition of the nodes into blocks; here the initial  */
+/*      numbering: block(v) = v >> block_bits.                              */
+/*   2. A sequential matcher inside every block: Greedy (Section 3.2) over  */
+/*      the edges whose two ends share a block.                             */
+/*   3. The gap graph: the edges {u,v} between two blocks that are above,   */
+/*      in the strict order, the edge matched in step 2 at u (if any) and   */
+/*      the one at v (if any).                                              */
+/*   4. The parallel matcher on the gap graph: local-max rounds, which      */
+/*      under the strict order equal Greedy on the gap graph.               */
+/*   5. A gap edge replaces the block edges at its ends; a node whose       */
+/*      block partner is taken this way stays unmatched (the paper says no  */
+/*      more about it).                                                     */
+/* mate[v] = partner or -1; loc_out (optional) receives step 2's matching,  */
+/* *gap_out (optional) the number of gap-graph edges and *gap_matched_out   */
+/* (optional) the number matched in step 4.  Returns |M|.                   */
+/* ------------------------------------------------------------------------ */
+int64_t orc_match_two_phase(int32_t n, int64_t nnz, const int64_t *xadj, const int32_t *adj,
+                            const uint32_t *ew, const uint32_t *vw, int kind, uint64_t seed,
+                            int32_t block_bits, int32_t *mate, int32_t *loc_out,
+                            int64_t *gap_out, int64_t *gap_matched_out)
+{
+    size_t n1 = (size_t)(n > 0 ? n : 1);
+    orc_edge *all = (orc_edge *)malloc((size_t)(nnz / 2 + 1) * sizeof(orc_edge));
+    orc_edge *list = (orc_edge *)malloc((size_t)(nnz / 2 + 1) * sizeof(orc_edge));
+    int64_t m = collect_edges(n, xadj, adj, ew, vw, kind, seed, all);
+    int32_t *loc = (int32_t *)malloc(n1 * sizeof(int32_t));
+    int64_t *loc_edge = (int64_t *)malloc(n1 * sizeof(int64_t));   /* index into list */
+    int32_t *gap = (int32_t *)malloc(n1 * sizeof(int32_t));
+#define BLOCK_OF(x) ((int64_t)(x) >> block_bits)
+
+    /* step 2: Greedy over the block-internal edges */
+    int64_t k = 0;
+    for (int64_t i = 0; i < m; ++i)
+        if (BLOCK_OF(all[i].a) == BLOCK_OF(all[i].b)) list[k++] = all[i];
+    qsort(list, (size_t)k, sizeof(orc_edge), edge_cmp_desc);
+    for (int32_t v = 0; v < n; ++v) { loc[v] = -1; loc_edge[v] = -1; }
+    for (int64_t i = 0; i < k; ++i) {
+        int32_t a = list[i].a, b = list[i].b;
+        if (loc[a] < 0 && loc[b] < 0) {
+            loc[a] = b; loc[b] = a;
+            loc_edge[a] = i; loc_edge[b] = i;
+        }
+    }
+
+    /* step 3: the gap graph (kept in `all`, compacted in place) */
+    int64_t g = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        orc_edge e = all[i];
+        if (BLOCK_OF(e.a) == BLOCK_OF(e.b)) continue;
+        if (loc_edge[e.a] >= 0 && edge_cmp(&e, &list[loc_edge[e.a]]) < 0) continue;
+        if (loc_edge[e.b] >= 0 && edge_cmp(&e, &list[loc_edge[e.b]]) < 0) continue;
+        all[g++] = e;
+    }
+
+    /* step 4: Greedy on the gap graph */
+    qsort(all, (size_t)g, sizeof(orc_edge), edge_cmp_desc);
+    for (int32_t v = 0; v < n; ++v) gap[v] = -1;
+    int64_t gm = 0;
+    for (int64_t i = 0; i < g; ++i) {
+        int32_t a = all[i].a, b = all[i].b;
+        if (gap[a] < 0 && gap[b] < 0) { gap[a] = b; gap[b] = a; ++gm; }
+    }
+
+    /* step 5: gap edges first, then the block edges whose two ends are untouched */
+    int64_t matched = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (gap[v] >= 0) mate[v] = gap[v];
+        else if (loc[v] >= 0 && gap[loc[v]] < 0) mate[v] = loc[v];
+        else mate[v] = -1;
+        if (mate[v] > v) ++matched;
+    }
+#undef BLOCK_OF
+    if (loc_out) memcpy(loc_out, loc, (size_t)(n > 0 ? n : 0) * sizeof(int32_t));
+    if (gap_out) *gap_out = g;
+    if (gap_matched_out) *gap_matched_out = gm;
+    free(gap); free(loc_edge); free(loc); free(list); free(all);
+    return matched;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Contraction (Section 2): each matched pair {u,v} becomes one node x with */
 /* c(x) = c(u) + c(v); the edges of u and v move to x; parallel edges are   */
 /* merged with summed weight; the contracted edge itself disappears.        */

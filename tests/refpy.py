@@ -123,3 +123,48 @@ def contract_dict(g, mate):
             ew.append(rows[x][y])
         xadj.append(len(adj))
     return cmap, nc, xadj, adj, ew, cvw
+
+
+def local_max_rounds(n, es, key):
+    """Synchronous rounds: every free node points at its best edge (by
+    `key`) to a free neighbour; edges chosen at both ends are matched."""
+    mate = [-1] * n
+    adj = [[] for _ in range(n)]
+    for e in es:
+        adj[e[0]].append(e)
+        adj[e[1]].append(e)
+    while True:
+        best = {}
+        for v in range(n):
+            if mate[v] >= 0:
+                continue
+            cand = [e for e in adj[v] if mate[e[0] if e[1] == v else e[1]] < 0]
+            if cand:
+                best[v] = max(cand, key=key)
+        if not best:
+            return mate
+        for v, e in best.items():
+            u = e[0] if e[1] == v else e[1]
+            if best.get(u) is e and mate[v] < 0:
+                mate[v], mate[u] = u, v
+
+
+def two_phase_rounds(g, kind, seed, block_bits):
+    """Section 3.3's two-phase matching in its round form: local-max rounds on
+    the block-internal edges (blocks of 2^block_bits consecutive ids), then
+    local-max rounds on the edges between blocks that beat the block edge
+    matched at each end; those replace the block edges at their ends."""
+    outs = out_of(g)
+    key = lambda e: order_key(kind, g, seed, e[0], e[1], e[2], outs)
+    es = edges_of(g)
+    inner = [e for e in es if e[0] >> block_bits == e[1] >> block_bits]
+    loc = local_max_rounds(g.n, inner, key)
+    wloc = {}
+    for a, b, w in inner:
+        if loc[a] == b:
+            wloc[a] = wloc[b] = key((a, b, w))
+    gap = [e for e in es if e[0] >> block_bits != e[1] >> block_bits
+           and all(x not in wloc or key(e) > wloc[x] for x in e[:2])]
+    gm = local_max_rounds(g.n, gap, key)
+    return [gm[v] if gm[v] >= 0 else (loc[v] if loc[v] >= 0 and gm[loc[v]] < 0 else -1)
+            for v in range(g.n)]

@@ -397,3 +397,124 @@ def test_c1_grid_hierarchy_invariants():
                  if lv.mate[v] == G.adj[j] and v < G.adj[j])
         assert int(C.ew.sum()) // 2 == int(G.ew.sum()) // 2 - wM
         assert O.greedy_certificate(G, O.EXPANSION_STAR2, O.level_seed(42, l), lv.mate) == 0
+
+
+# --------------------------------------------------------------------------
+# the two-phase matcher of Section 3.3
+# --------------------------------------------------------------------------
+def test_w7_two_phase_hand_worked():
+    w = gold("w7_two_phase.json")
+    for name in ("p5", "six"):
+        c = w[name]
+        g = graph_from(c["graph"])
+        mate, m, loc, ge, gm = O.match_two_phase(g, O.EXPANSION_STAR2, O.level_seed(42, 0),
+                                                 c["block_bits"])
+        assert loc.tolist() == c["block_matching"], name
+        assert ge == len(c["gap_edges"]), name
+        assert mate.tolist() == c["mate"], name
+        assert m == sum(1 for v, u in enumerate(c["mate"]) if u > v)
+        if "gap_matched" in c:
+            assert gm == c["gap_matched"]
+    c = w["p5"]
+    g = graph_from(c["graph"])
+    gmate, _ = O.match_greedy(g, O.EXPANSION_STAR2, O.level_seed(42, 0))
+    assert gmate.tolist() == c["greedy_mate"] != c["mate"]   # the two schemes differ here
+    cmap, cg = O.contract(g, np.array(c["mate"], dtype=np.int32))
+    assert cmap.tolist() == c["cmap"]
+    k = c["coarse"]
+    assert (cg.n, cg.xadj.tolist(), cg.adj.tolist(), cg.ew.tolist(), cg.vw.tolist()) == \
+        (k["n"], k["xadj"], k["adj"], k["ew"], k["vw"])
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_two_phase_equal_ratings_follow_the_hash(seed):
+    # P4 with unit weights, blocks {0,1} {2,3}: all three edges rate 1, so the
+    # cross edge {1,2} enters the gap graph iff its hash beats both block edges
+    g = path_graph([1, 1, 1])
+    s = O.level_seed(seed, 0)
+    mate, m, loc, ge, gm = O.match_two_phase(g, O.EXPANSION_STAR2, s, 1)
+    assert loc.tolist() == [1, 0, 3, 2]
+    h = lambda a, b: refpy.mix64(s ^ ((a << 32) | b))
+    in_gap = h(1, 2) > h(0, 1) and h(1, 2) > h(2, 3)
+    assert ge == int(in_gap)
+    assert mate.tolist() == ([-1, 2, 1, -1] if in_gap else [1, 0, 3, 2])
+
+
+@pytest.mark.parametrize("rating", RATING_NAMES)
+def test_two_phase_one_block_and_singletons_are_greedy(rating):
+    # one block: no gap edge, the block matcher is Greedy on G; blocks of one
+    # node: no block edge, every edge is a gap edge, Greedy on G again
+    for s, g in _small_graphs():
+        seed = O.level_seed(s, 1)
+        ref, mr = O.match_greedy(g, O.RATINGS[rating], seed)
+        for bb in (0, 31, max(1, int(np.ceil(np.log2(max(g.n, 2)))))):
+            mate, m, loc, ge, gm = O.match_two_phase(g, O.RATINGS[rating], seed, bb)
+            assert np.array_equal(mate, ref) and m == mr, (s, bb)
+            assert (ge == 0) if bb else (loc == -1).all()
+
+
+def test_two_phase_light_cross_edges_give_greedy():
+    # weight rating, every block edge heavier than every cross edge: Greedy
+    # takes the block edges first (blocks do not interact) and then cross
+    # edges between nodes the blocks left free -- exactly the gap graph
+    rng = np.random.default_rng(5)
+    for t in range(30):
+        n, bb = int(rng.integers(8, 200)), int(rng.integers(1, 5))
+        g0 = random_graph(n, int(rng.integers(n, 4 * n)), seed=300 + t, wmax=1)
+        a = np.repeat(np.arange(n), np.diff(g0.xadj))
+        keep = a < g0.adj
+        a, b = a[keep], g0.adj[keep].astype(np.int64)
+        inner = (a >> bb) == (b >> bb)
+        w = np.where(inner, rng.integers(1001, 2000, len(a)), rng.integers(1, 1000, len(a)))
+        g = csr_from_edges(n, a, b, w.astype(np.uint32))
+        seed = O.level_seed(t, 0)
+        mate = O.match_two_phase(g, O.WEIGHT, seed, bb)[0]
+        assert np.array_equal(mate, O.match_greedy(g, O.WEIGHT, seed)[0]), t
+
+
+@pytest.mark.parametrize("rating", RATING_NAMES)
+def test_two_phase_equals_round_form(rating):
+    # the oracle (sorted Greedy per phase) against the round form of both
+    # phases written independently in Python, on many block sizes
+    for s, g in _small_graphs():
+        seed = O.level_seed(s, 2)
+        for bb in (1, 2, 3, 5):
+            mate = O.match_two_phase(g, O.RATINGS[rating], seed, bb)[0]
+            assert mate.tolist() == refpy.two_phase_rounds(g, rating, seed, bb), (s, bb)
+
+
+def test_two_phase_structure():
+    # a matching of graph edges; matched cross edges were gap edges; matched
+    # block edges come from the block matching; every node the block matching
+    # paired is still paired unless its partner took a cross edge
+    for s, g in _small_graphs():
+        for bb in (1, 2, 4):
+            seed = O.level_seed(s, 0)
+            mate, m, loc, ge, gm = O.match_two_phase(g, O.EXPANSION_STAR2, seed, bb)
+            es = {(a, b) for a, b, _ in refpy.edges_of(g)}
+            cross = 0
+            for v, u in enumerate(mate.tolist()):
+                if u < 0:
+                    assert loc[v] < 0 or mate[loc[v]] >= 0 and mate[loc[v]] != v
+                    continue
+                assert mate[u] == v and (min(u, v), max(u, v)) in es
+                if (u >> bb) != (v >> bb):
+                    cross += u > v
+                else:
+                    assert loc[v] == u
+            assert cross == gm and gm <= ge
+
+
+@pytest.mark.parametrize("rating", ["expansion*2", "innerOuter"])
+def test_two_phase_hierarchy_invariants(rating):
+    g = grid2d(40, 40)
+    H = O.coarsen(g, O.RATINGS[rating], 42, 64, block_bits=5)
+    assert H.stop_reason in (O.STOP_SIZE, O.STOP_STALL, O.STOP_EMPTY)
+    total = int(g.vw.sum())
+    for l, lv in enumerate(H.levels[:-1]):
+        nxt = H.levels[l + 1].graph
+        assert nxt.n == lv.graph.n - lv.matched
+        assert int(nxt.vw.sum()) == total
+        assert O.validate(nxt) == O.OK
+        s = O.level_seed(42, l)
+        assert np.array_equal(lv.mate, O.match_two_phase(lv.graph, O.RATINGS[rating], s, 5)[0])
