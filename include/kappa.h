@@ -108,7 +108,8 @@ typedef struct {
     uint32_t stall_num;   /* stop after a level with (n_l - n_{l+1}) * stall_den */
     uint32_t stall_den;   /*   < stall_num * n_l; stall_num = 0 disables the rule */
     int32_t max_levels;   /* at most this many contractions (<= 256) */
-    uint32_t flags;       /* 0, or KAPPA_COARSEN_TRUSTED */
+    uint32_t flags;       /* 0, or KAPPA_COARSEN_TRUSTED and/or KAPPA_COARSEN_TWO_PHASE */
+    int32_t block_bits;   /* KAPPA_COARSEN_TWO_PHASE: blocks of 2^block_bits ids, 0..11 */
 } kappa_coarsen_params;
 
 /* The caller has checked the graph with kappa_validate (and not changed it
@@ -116,6 +117,13 @@ typedef struct {
    A graph that would fail kappa_validate is undefined behaviour (kernels
    may read outside its arrays). */
 #define KAPPA_COARSEN_TRUSTED 1u
+
+/* Every level is matched by the two-phase matcher (kappa_match_two_phase)
+   with blocks of 2^block_bits consecutive ids of that level, instead of the
+   local-max rounds on the whole graph.  Single-graph form only
+   (kappa_coarsen); the batched forms return KAPPA_E_ARG.  A level's
+   `rounds` and round statistics then describe its gap rounds. */
+#define KAPPA_COARSEN_TWO_PHASE 2u
 
 /* Exact cut/balance of a k-way partition (Section 2; imbalance as in
    Section 5.2).  L_max = (1 + eps) c(V)/k + max_v c(v) = lmax_num / lmax_den
@@ -166,6 +174,22 @@ kappa_status kappa_rate(const kappa_graph *g, int32_t rating, uint64_t *num, uin
 kappa_status kappa_match(const kappa_graph *g, int32_t rating, uint64_t level_seed,
                          int32_t *mate, int32_t *rounds_out, int64_t *matched_out,
                          kappa_stream_t stream);
+
+/* Section 3.3, the two-phase scheme: a preliminary partition into blocks
+   (here by the node numbering: block(v) = v >> block_bits, 0 <= block_bits
+   <= 11, so that a locality order such as recursive coordinate bisection
+   makes them geometric blocks); Greedy inside every block (one workgroup
+   per block); then the gap graph -- edges between two blocks that are above
+   the block edge matched at each of their ends -- matched by the parallel
+   local-max rounds.  A gap edge replaces the block edges at its ends; a node
+   whose block partner is taken that way stays unmatched.  mate[n] (device,
+   out): the result; block_mate[n] (device, out, may be NULL): the block
+   phase's matching; matched_out (host, may be NULL): |M|.  The order of
+   edges, seeds and the rest as for kappa_match.  Returns KAPPA_E_ARG for
+   block_bits outside [0, 11].  Synchronous. */
+kappa_status kappa_match_two_phase(const kappa_graph *g, int32_t rating, uint64_t level_seed,
+                                   int32_t block_bits, int32_t *mate, int32_t *block_mate,
+                                   int64_t *matched_out, kappa_stream_t stream);
 
 /* Section 2: contracts the matching `mate` (as written by kappa_match, or any
    valid matching of g).  Coarse ids: a node is a representative if it is

@@ -42,10 +42,13 @@ class c_graph_out(ctypes.Structure):
 class c_params(ctypes.Structure):
     _fields_ = [("rating", ctypes.c_int32), ("seed", ctypes.c_uint64), ("stop_n", ctypes.c_int32),
                 ("stall_num", ctypes.c_uint32), ("stall_den", ctypes.c_uint32),
-                ("max_levels", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("max_levels", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("block_bits", ctypes.c_int32)]
 
 
 COARSEN_TRUSTED = 1   # the graph passed kappa_validate: only its offsets are checked again
+COARSEN_TWO_PHASE = 2   # every level matched by the two-phase matcher (blocks of 2^block_bits ids)
+BLOCK_BITS_MAX = 11
 
 
 class c_cut(ctypes.Structure):
@@ -101,6 +104,8 @@ def lib():
         "kappa_rate": (st, [ctypes.POINTER(c_graph), i32, P, P, P]),
         "kappa_match": (st, [ctypes.POINTER(c_graph), i32, u64, P, ctypes.POINTER(i32),
                              ctypes.POINTER(i64), P]),
+        "kappa_match_two_phase": (st, [ctypes.POINTER(c_graph), i32, u64, i32, P, P,
+                                       ctypes.POINTER(i64), P]),
         "kappa_contract": (st, [ctypes.POINTER(c_graph), P, P, ctypes.POINTER(c_graph_out), P]),
         "kappa_coarsen": (st, [ctypes.POINTER(c_graph), ctypes.POINTER(c_params),
                                ctypes.POINTER(P), P]),
@@ -264,6 +269,19 @@ def kappa_match(g: DeviceGraph, rating: int, level_seed: int):
     return mate[:g.n], int(rounds.value), int(matched.value)
 
 
+def kappa_match_two_phase(g: DeviceGraph, rating: int, level_seed: int, block_bits: int):
+    """Returns (mate, block-phase matching, |M|)."""
+    import torch
+    mate = torch.empty(max(g.n, 1), dtype=torch.int32, device=g.xadj.device)
+    loc = torch.empty(max(g.n, 1), dtype=torch.int32, device=g.xadj.device)
+    matched = ctypes.c_int64(0)
+    _check("kappa_match_two_phase",
+           lib().kappa_match_two_phase(ctypes.byref(g.c()), rating,
+                                       ctypes.c_uint64(level_seed & (2**64 - 1)), block_bits,
+                                       _ptr(mate), _ptr(loc), ctypes.byref(matched), _stream()))
+    return mate[:g.n], loc[:g.n], int(matched.value)
+
+
 def kappa_contract(g: DeviceGraph, mate, cap_n: Optional[int] = None, cap_nnz: Optional[int] = None):
     """Returns (cmap, coarse DeviceGraph)."""
     import torch
@@ -345,11 +363,13 @@ class Hierarchy:
 
 def kappa_coarsen(g: DeviceGraph, rating: int = EXPANSION_STAR2, seed: int = 42, stop_n: int = 256,
                   stall_num: int = 1, stall_den: int = 20, max_levels: int = 64,
-                  trusted: bool = False) -> Hierarchy:
+                  trusted: bool = False, block_bits: Optional[int] = None) -> Hierarchy:
     """trusted: g passed kappa_validate and is unchanged since (the full
-    structural check is skipped)."""
-    p = c_params(rating, seed & (2**64 - 1), stop_n, stall_num, stall_den, max_levels,
-                 COARSEN_TRUSTED if trusted else 0)
+    structural check is skipped).  block_bits: match every level with the
+    two-phase matcher, blocks of 2^block_bits consecutive ids."""
+    flags = (COARSEN_TRUSTED if trusted else 0) | (COARSEN_TWO_PHASE if block_bits is not None else 0)
+    p = c_params(rating, seed & (2**64 - 1), stop_n, stall_num, stall_den, max_levels, flags,
+                 block_bits if block_bits is not None else 0)
     h = ctypes.c_void_p()
     _check("kappa_coarsen", lib().kappa_coarsen(ctypes.byref(g.c()), ctypes.byref(p), ctypes.byref(h),
                                                 _stream()))

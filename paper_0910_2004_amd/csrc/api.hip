@@ -551,6 +551,9 @@ void carve_scratch(Carve &cv, const DevGraph &g, int rating, bool hubs, Ctx &c) 
     cs.hub_words = (int64_t)g.n / 32 + 1;
     cs.hub_acc = hubs ? cv.get<uint32_t>((int64_t)HUB_SLOTS * g.n) : nullptr;
     cs.hub_bits = hubs ? cv.get<uint32_t>((int64_t)HUB_SLOTS * cs.hub_words) : nullptr;
+    // two-phase matcher (c.block_bits set before carving)
+    ms.loc = c.block_bits >= 0 ? cv.get<int32_t>(g.n) : nullptr;
+    ms.lkey = c.block_bits >= 0 ? cv.get<LocKey>(g.n) : nullptr;
 }
 
 void fill_scratch(const DevGraph &g, const Ctx &c, hipStream_t s) {
@@ -558,6 +561,7 @@ void fill_scratch(const DevGraph &g, const Ctx &c, hipStream_t s) {
     launch_fill_u32((uint32_t *)&c.ms.state->cnt[0][0], 16, 0, s);   // round-1 list counters
     launch_fill_u32((uint32_t *)&c.ms.state->sround[0], NSHARD, 0, s);
     launch_fill_u64((uint64_t *)&c.ms.state->sstat[0][0][0], (int64_t)STAT_ROUNDS * 3 * NSHARD, 0, s);
+    launch_fill_u64((uint64_t *)&c.ms.state->spairs[0], NSHARD, 0, s);
     if (c.cs.hub_acc) {
         launch_fill_u32(c.cs.hub_acc, (int64_t)HUB_SLOTS * g.n, 0, s);
         launch_fill_u32(c.cs.hub_bits, (int64_t)HUB_SLOTS * c.cs.hub_words, 0, s);
@@ -644,6 +648,7 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     c.rating = p->rating;
     c.seed = p->seed;
     c.seed_direct = 0;
+    c.block_bits = (p->flags & KAPPA_COARSEN_TWO_PHASE) ? p->block_bits : -1;
     const int maxl = p->max_levels;
     const int32_t count = bi ? bi->count : 0;
     uint32_t *bflag = nullptr;
@@ -746,7 +751,7 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     // estimate is near its limit; once the estimate is within twice the limit
     // the batch ends on the tail launch (it most likely finishes the loop).
     // If it did not take that level, the next batch runs the level in full.
-    const bool tail_on = !bi && g_tail_on;
+    const bool tail_on = !bi && g_tail_on && c.block_bits < 0;
     int tail_end = -1;   // level at which the previous batch ended on a tail launch
     Control *hc = (Control *)pinned(sizeof(Control));
     for (;;) {
@@ -756,7 +761,8 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
                                            (uint64_t)p->rating, p->seed, (uint64_t)maxl,
                                            (uint64_t)hubs, (uint64_t)launched, (uint64_t)l_end,
                                            (uint64_t)count, (uint64_t)tail_on,
-                                           (uint64_t)(int64_t)tail_end};
+                                           (uint64_t)(int64_t)tail_end,
+                                           (uint64_t)(int64_t)c.block_bits};
         HIPCHK(run_seq(w->c, s, key, [&](hipStream_t q) {
             for (int l = launched; l < l_end; ++l) {
                 int32_t nh = n_hint_of(n0, l);
@@ -856,6 +862,18 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
 
 }  // namespace
 
+namespace {
+// two_phase_ok: the two-phase matcher may be asked for (single-graph forms)
+bool params_ok(const kappa_coarsen_params *p, bool two_phase_ok) {
+    const uint32_t known = KAPPA_COARSEN_TRUSTED | (two_phase_ok ? KAPPA_COARSEN_TWO_PHASE : 0u);
+    if (!p || p->rating < 0 || p->rating > 4 || p->max_levels < 0 || p->max_levels > MAX_LEVELS ||
+        (p->stall_num > 0 && p->stall_den == 0) || (p->flags & ~known))
+        return false;
+    return !(p->flags & KAPPA_COARSEN_TWO_PHASE) ||
+           (p->block_bits >= 0 && p->block_bits <= BM_BITS_MAX);
+}
+}  // namespace
+
 // ===========================================================================
 // Entry points
 // ===========================================================================
@@ -890,9 +908,7 @@ extern "C" kappa_status kappa_coarsen(const kappa_graph *g, const kappa_coarsen_
     if (!out) return KAPPA_E_ARG;
     *out = nullptr;
     if (!graph_args_ok(g) || !p) return KAPPA_E_ARG;
-    if (p->rating < 0 || p->rating > 4 || p->max_levels < 0 || p->max_levels > MAX_LEVELS ||
-        (p->stall_num > 0 && p->stall_den == 0) || (p->flags & ~(uint32_t)KAPPA_COARSEN_TRUSTED))
-        return KAPPA_E_ARG;
+    if (!params_ok(p, true)) return KAPPA_E_ARG;
     hipStream_t s = S(stream);
     DevGraph d0 = dev(g);
     int32_t maxdeg = 0;
@@ -944,11 +960,6 @@ struct kappa_batch {
 
 namespace {
 
-bool params_ok(const kappa_coarsen_params *p) {
-    return p && p->rating >= 0 && p->rating <= 4 && p->max_levels >= 0 &&
-           p->max_levels <= MAX_LEVELS && !(p->stall_num > 0 && p->stall_den == 0) &&
-           !(p->flags & ~(uint32_t)KAPPA_COARSEN_TRUSTED);
-}
 
 // The batched coarsening of union u into B (B->union_h.s set); arguments checked.
 kappa_status batch_impl(const kappa_graph *u, int32_t count, const int32_t *node_off,
@@ -991,7 +1002,7 @@ extern "C" kappa_status kappa_coarsen_batch(const kappa_graph *u, int32_t count,
                                             kappa_stream_t stream) {
     if (!out) return KAPPA_E_ARG;
     *out = nullptr;
-    if (!graph_args_ok(u) || !params_ok(p) || count < 1 || !node_off) return KAPPA_E_ARG;
+    if (!graph_args_ok(u) || !params_ok(p, false) || count < 1 || !node_off) return KAPPA_E_ARG;
     if (node_off[0] != 0 || node_off[count] != u->n) return KAPPA_E_ARG;
     for (int32_t g = 0; g < count; ++g)
         if (node_off[g + 1] < node_off[g]) return KAPPA_E_ARG;
@@ -1013,7 +1024,7 @@ extern "C" kappa_status kappa_coarsen_graphs(const kappa_graph *graphs, int32_t 
                                              kappa_batch **out, kappa_stream_t stream) {
     if (!out) return KAPPA_E_ARG;
     *out = nullptr;
-    if (!graphs || count < 1 || !params_ok(p)) return KAPPA_E_ARG;
+    if (!graphs || count < 1 || !params_ok(p, false)) return KAPPA_E_ARG;
     std::vector<int64_t> off(2 * ((size_t)count + 1), 0);   // node offsets, then entry offsets
     int64_t *noff = off.data(), *eoff = off.data() + count + 1;
     std::vector<UnionSrc> src(count);
@@ -1185,9 +1196,12 @@ extern "C" kappa_status kappa_batch_hierarchy(const kappa_batch *b, int32_t g,
 
 extern "C" void kappa_batch_free(kappa_batch *b) { delete b; }
 
-extern "C" kappa_status kappa_match(const kappa_graph *g, int32_t rating, uint64_t level_seed,
-                                    int32_t *mate, int32_t *rounds_out, int64_t *matched_out,
-                                    kappa_stream_t stream) {
+namespace {
+// One matching of g (block_bits < 0: local-max rounds; otherwise the
+// two-phase matcher, whose block matching is copied to block_mate if given).
+kappa_status match_once(const kappa_graph *g, int32_t rating, uint64_t level_seed,
+                        int32_t block_bits, int32_t *mate, int32_t *block_mate,
+                        int32_t *rounds_out, int64_t *matched_out, kappa_stream_t stream) {
     if (!graph_args_ok(g) || rating < 0 || rating > 4) return KAPPA_E_ARG;
     if (g->n > 0 && !mate) return KAPPA_E_ARG;
     hipStream_t s = S(stream);
@@ -1196,6 +1210,7 @@ extern "C" kappa_status kappa_match(const kappa_graph *g, int32_t rating, uint64
     c.rating = rating;
     c.seed = level_seed;   // used as is: h(e) = mix64(level_seed ^ eid)
     c.seed_direct = 1;
+    c.block_bits = block_bits;
     int32_t *cm = nullptr;
     std::unique_ptr<Workspace> w;
     if (!carve_workspace(s, w, [&](Carve &cv) {
@@ -1237,9 +1252,29 @@ extern "C" kappa_status kappa_match(const kappa_graph *g, int32_t rating, uint64
         if (debug_on()) fprintf(stderr, "kappa: match control flags 0x%x\n", hc->flags);
         return KAPPA_E_HIP;
     }
+    if (block_mate && d.n > 0) {
+        HIPCHK(hipMemcpyAsync(block_mate, c.ms.loc, (size_t)d.n * 4, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
     if (rounds_out) *rounds_out = hl->rounds;
     if (matched_out) *matched_out = hl->matched;
     return KAPPA_OK;
+}
+}  // namespace
+
+extern "C" kappa_status kappa_match(const kappa_graph *g, int32_t rating, uint64_t level_seed,
+                                    int32_t *mate, int32_t *rounds_out, int64_t *matched_out,
+                                    kappa_stream_t stream) {
+    return match_once(g, rating, level_seed, -1, mate, nullptr, rounds_out, matched_out, stream);
+}
+
+extern "C" kappa_status kappa_match_two_phase(const kappa_graph *g, int32_t rating,
+                                              uint64_t level_seed, int32_t block_bits,
+                                              int32_t *mate, int32_t *block_mate,
+                                              int64_t *matched_out, kappa_stream_t stream) {
+    if (block_bits < 0 || block_bits > BM_BITS_MAX) return KAPPA_E_ARG;
+    return match_once(g, rating, level_seed, block_bits, mate, block_mate, nullptr, matched_out,
+                      stream);
 }
 
 extern "C" kappa_status kappa_contract(const kappa_graph *g, const int32_t *mate, int32_t *cmap,

@@ -125,15 +125,53 @@ __device__ __forceinline__ uint32_t attr_src(const DevGraph &g, const uint32_t *
     return R == KAPPA_INNER_OUTER ? out[v] : (R == KAPPA_WEIGHT ? 0u : g.vw[v]);
 }
 
+// Two-phase matcher (Section 3.3): the edges its gap rounds may match.
+// F = 0: every edge; F = 1: gap edges only -- {v,u} with v and u in
+// different blocks (blocks of 2^bb consecutive ids) and above, in the strict
+// order, the edge the block phase matched at v and the one at u.
+struct GapView {
+    int32_t bb;
+    const int32_t *loc;
+    const LocKey *key;
+};
+__device__ __forceinline__ GapView gap_view(const Ctx &c) {
+    return GapView{c.block_bits, c.ms.loc, c.ms.lkey};
+}
+// The block edge at x as a candidate incident to x (u = -1: none).
+__device__ __forceinline__ Cand loc_cand(const GapView &gv, int32_t x) {
+    Cand k = cand_none();
+    k.u = gv.loc[x];
+    if (k.u >= 0) {
+        const LocKey q = gv.key[x];
+        k.num = q.num;
+        k.den = q.den;
+        k.h = q.h;
+    }
+    return k;
+}
+__device__ __forceinline__ bool cross_block(const GapView &gv, int32_t v, int32_t u) {
+    return (v >> gv.bb) != (u >> gv.bb);
+}
+// cd: a candidate {v, cd.u} between two blocks; kv: loc_cand(gv, v).
+__device__ __forceinline__ bool above_block_edges(const GapView &gv, const Cand &cd, int32_t v,
+                                                  const Cand &kv) {
+    if (!cand_better(cd, kv, v)) return false;
+    Cand cu = cd;   // the same edge seen from u
+    cu.u = v;
+    return cand_better(cu, loc_cand(gv, cd.u), cd.u);
+}
+
 // Best edge from v to a free neighbour over the entries sub, sub+G, ...
-template <int R, int G, bool FIRST>
+template <int R, int G, bool FIRST, int F = 0>
 __device__ __forceinline__ Cand scan_row(const DevGraph &g, int32_t v, uint32_t av, int sub,
                                          const int2 *nrec, const uint32_t *out, uint64_t seed,
-                                         int32_t base) {
+                                         int32_t base, const GapView &gv) {
     Cand best = cand_none();
     const int64_t b = g.xadj[v], e = g.xadj[v + 1];
+    const Cand kv = F ? loc_cand(gv, v) : cand_none();
     for (int64_t j = b + sub; j < e; j += G) {
         const int32_t u = g.adj[j];
+        if (F && !cross_block(gv, v, u)) continue;
         uint32_t au;
         if (FIRST) {
             au = attr_src<R>(g, out, u);   // round 1: every node is free
@@ -146,6 +184,7 @@ __device__ __forceinline__ Cand scan_row(const DevGraph &g, int32_t v, uint32_t 
         rate<R>(g.ew[j], au, av, au, av, cd.num, cd.den);
         cd.h = mix64(seed ^ edge_id_local(v, u, base));
         cd.u = u;
+        if (F && !above_block_edges(gv, cd, v, kv)) continue;
         if (cand_better(cd, best, v)) best = cd;
     }
     return best;
@@ -153,10 +192,11 @@ __device__ __forceinline__ Cand scan_row(const DevGraph &g, int32_t v, uint32_t 
 
 // The same over a row of at most BIN_SMALL_MAX entries [b, e): every load of
 // a lane's entries is issued before the first comparison.
-template <int R, int G, bool FIRST>
+template <int R, int G, bool FIRST, int F = 0>
 __device__ __forceinline__ Cand scan_row_small(const DevGraph &g, int32_t v, uint32_t av, int sub,
                                                int64_t b, int64_t e, const int2 *nrec,
-                                               const uint32_t *out, uint64_t seed, int32_t base) {
+                                               const uint32_t *out, uint64_t seed, int32_t base,
+                                               const GapView &gv) {
     constexpr int T = BIN_SMALL_MAX / G;
     int32_t u[T];
     uint32_t w[T], au[T];
@@ -170,6 +210,7 @@ __device__ __forceinline__ Cand scan_row_small(const DevGraph &g, int32_t v, uin
     }
 #pragma unroll
     for (int t = 0; t < T; ++t) {
+        if (F) ok[t] = ok[t] && cross_block(gv, v, u[t]);
         if (FIRST) {
             au[t] = ok[t] ? attr_src<R>(g, out, u[t]) : 0u;
         } else {
@@ -179,6 +220,7 @@ __device__ __forceinline__ Cand scan_row_small(const DevGraph &g, int32_t v, uin
         }
     }
     Cand best = cand_none();
+    const Cand kv = F ? loc_cand(gv, v) : cand_none();
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         if (!ok[t]) continue;
@@ -186,6 +228,7 @@ __device__ __forceinline__ Cand scan_row_small(const DevGraph &g, int32_t v, uin
         rate<R>(w[t], au[t], av, au[t], av, cd.num, cd.den);
         cd.h = mix64(seed ^ edge_id_local(v, u[t], base));
         cd.u = u[t];
+        if (F && !above_block_edges(gv, cd, v, kv)) continue;
         if (cand_better(cd, best, v)) best = cd;
     }
     return best;
@@ -322,9 +365,10 @@ __device__ __forceinline__ RoundIn round_inputs(const Ctx &c, const DevGraph &g,
 }
 
 // bin 0: SMALL_G lanes per node
-template <int R, bool FIRST>
+template <int R, bool FIRST, int F = 0>
 __device__ __forceinline__ void pick_bin0(const Ctx &c, const DevGraph &g, uint64_t seed,
                                           const RoundIn &ri, unsigned bid, unsigned nb) {
+    const GapView gv = gap_view(c);
     const int G = SMALL_G;
     int32_t *best = c.ms.best;
     const int2 *nrec = c.ms.nrec;
@@ -357,8 +401,8 @@ __device__ __forceinline__ void pick_bin0(const Ctx &c, const DevGraph &g, uint6
                 }
             }
         }
-        Cand cd = act ? scan_row_small<R, G, FIRST>(g, v, av, sub, rb, re, nrec, out, seed,
-                                                    local_base(g, v))
+        Cand cd = act ? scan_row_small<R, G, FIRST, F>(g, v, av, sub, rb, re, nrec, out, seed,
+                                                       local_base(g, v), gv)
                       : cand_none();
         cd = group_reduce<G>(cd, v);
         if (act && sub == 0) {
@@ -369,9 +413,10 @@ __device__ __forceinline__ void pick_bin0(const Ctx &c, const DevGraph &g, uint6
 }
 
 // bin 1: one wave per node
-template <int R, bool FIRST>
+template <int R, bool FIRST, int F = 0>
 __device__ __forceinline__ void pick_bin1(const Ctx &c, const DevGraph &g, uint64_t seed,
                                           const RoundIn &ri, unsigned bid, unsigned nb) {
+    const GapView gv = gap_view(c);
     int32_t *best = c.ms.best;
     const int2 *nrec = c.ms.nrec;
     const uint32_t *out = c.ms.out;
@@ -381,7 +426,8 @@ __device__ __forceinline__ void pick_bin1(const Ctx &c, const DevGraph &g, uint6
         const int32_t v = checked_node(ri.in[1].v[i], g.n, c.ctrl);
         if (v < 0 || (!FIRST && keeps_choice(ri.in[1].b[i], g.n, nrec))) continue;   // wave-uniform
         const uint32_t av = FIRST ? attr_src<R>(g, out, v) : (uint32_t)nrec[v].x;
-        Cand cd = scan_row<R, WAVE, FIRST>(g, v, av, lane_id(), nrec, out, seed, local_base(g, v));
+        Cand cd = scan_row<R, WAVE, FIRST, F>(g, v, av, lane_id(), nrec, out, seed, local_base(g, v),
+                                              gv);
         cd = group_reduce<WAVE>(cd, v);
         if (lane_id() == 0) {
             best[v] = cd.u;
@@ -391,9 +437,10 @@ __device__ __forceinline__ void pick_bin1(const Ctx &c, const DevGraph &g, uint6
 }
 
 // bin 2: one block per node (blockDim.x lanes, a multiple of 64)
-template <int R, bool FIRST, int NT>
+template <int R, bool FIRST, int NT, int F = 0>
 __device__ __forceinline__ void pick_bin2(const Ctx &c, const DevGraph &g, uint64_t seed,
                                           const RoundIn &ri, unsigned bid, unsigned nb, Cand *sh) {
+    const GapView gv = gap_view(c);
     int32_t *best = c.ms.best;
     const int2 *nrec = c.ms.nrec;
     const uint32_t *out = c.ms.out;
@@ -401,7 +448,8 @@ __device__ __forceinline__ void pick_bin2(const Ctx &c, const DevGraph &g, uint6
         const int32_t v = checked_node(ri.in[2].v[i], g.n, c.ctrl);
         if (v < 0 || (!FIRST && keeps_choice(ri.in[2].b[i], g.n, nrec))) continue;   // block-uniform
         const uint32_t av = FIRST ? attr_src<R>(g, out, v) : (uint32_t)nrec[v].x;
-        Cand cd = scan_row<R, NT, FIRST>(g, v, av, threadIdx.x, nrec, out, seed, local_base(g, v));
+        Cand cd = scan_row<R, NT, FIRST, F>(g, v, av, threadIdx.x, nrec, out, seed,
+                                            local_base(g, v), gv);
         cd = block_reduce_cand(cd, v, sh);
         if (threadIdx.x == 0) {
             best[v] = cd.u;
@@ -517,7 +565,9 @@ __device__ __forceinline__ void mate_phase(const Ctx &c, const DevGraph &g, Leve
 // lists.  Block 0 also resets the matching state (read by later kernels).
 // The list counters and round statistics are zero on entry (reset by the
 // previous level's finisher, or by the host before level 0).
-__global__ void __launch_bounds__(BLOCK) match_init_k(Ctx c, int l, int stop_rules) {
+// lists = 0 (two-phase matcher): gate and resets only; the block phase
+// writes mate, best, the node records and the lists.
+__global__ void __launch_bounds__(BLOCK) match_init_k(Ctx c, int l, int stop_rules, int lists) {
     __shared__ int64_t sh[BLOCK / WAVE + 1];
     __shared__ int32_t sbase[3];
     __shared__ int go;
@@ -535,14 +585,14 @@ __global__ void __launch_bounds__(BLOCK) match_init_k(Ctx c, int l, int stop_rul
         L->matched = 0;
         L->rounds = 0;
     }
-    init_phase(c, g, L, sh, sbase, blockIdx.x, gridDim.x, &c.ms.state->cnt[0][0]);
+    if (lists) init_phase(c, g, L, sh, sbase, blockIdx.x, gridDim.x, &c.ms.state->cnt[0][0]);
 }
 
 struct PickGrid {
     unsigned b0, b1, b2;  // blocks per bin
 };
 
-template <int R, bool FIRST>
+template <int R, bool FIRST, int F = 0>
 __global__ void __launch_bounds__(BLOCK) pick_k(Ctx c, int l, int r, PickGrid pg) {
     __shared__ Cand sh[BLOCK / WAVE];
     DevGraph g;
@@ -564,11 +614,11 @@ __global__ void __launch_bounds__(BLOCK) pick_k(Ctx c, int l, int r, PickGrid pg
     }
     const uint64_t seed = level_seed(c, l);
     unsigned bid = blockIdx.x;
-    if (bid < pg.b0) { pick_bin0<R, FIRST>(c, g, seed, ri, bid, pg.b0); return; }
+    if (bid < pg.b0) { pick_bin0<R, FIRST, F>(c, g, seed, ri, bid, pg.b0); return; }
     bid -= pg.b0;
-    if (bid < pg.b1) { pick_bin1<R, FIRST>(c, g, seed, ri, bid, pg.b1); return; }
+    if (bid < pg.b1) { pick_bin1<R, FIRST, F>(c, g, seed, ri, bid, pg.b1); return; }
     bid -= pg.b1;
-    pick_bin2<R, FIRST, BLOCK>(c, g, seed, ri, bid, pg.b2, sh);
+    pick_bin2<R, FIRST, BLOCK, F>(c, g, seed, ri, bid, pg.b2, sh);
 }
 
 template <int R, bool FIRST>
@@ -591,17 +641,17 @@ __global__ void __launch_bounds__(BLOCK) mate_k(Ctx c, int l, int r) {
 // sizes round r0 left.  Every round that has a pointing node matches at least
 // one pair, so at most n/2 + 1 rounds remain; returns true only if that cap
 // was hit (broken state).
-template <int R, int NT>
+template <int R, int NT, int F = 0>
 __device__ bool wg_rounds(const Ctx &c, const DevGraph &g, LevelDesc *L, uint64_t seed, int r0,
                           int32_t (*s_cnt)[3], Cand *shc, int64_t *sh, int32_t *sbase) {
     const int64_t r_cap = (int64_t)r0 + 2 + g.n;
     for (int r = r0 + 1; r <= r_cap; ++r) {
         const RoundIn ri = round_inputs<false>(c, g, r, s_cnt[(r - 1) & 1]);
         if ((int64_t)ri.cn[0] + ri.cn[1] + ri.cn[2] == 0) return false;
-        pick_bin0<R, false>(c, g, seed, ri, 0, 1);
-        pick_bin1<R, false>(c, g, seed, ri, 0, 1);
+        pick_bin0<R, false, F>(c, g, seed, ri, 0, 1);
+        pick_bin1<R, false, F>(c, g, seed, ri, 0, 1);
         __syncthreads();
-        pick_bin2<R, false, NT>(c, g, seed, ri, 0, 1, shc);
+        pick_bin2<R, false, NT, F>(c, g, seed, ri, 0, 1, shc);
         if (threadIdx.x < 3) s_cnt[r & 1][threadIdx.x] = 0;
         __syncthreads();
         mate_phase<R, false>(c, g, L, r, ri, s_cnt[r & 1], 0, 1, sh, sbase);
@@ -615,9 +665,11 @@ __device__ bool wg_rounds(const Ctx &c, const DevGraph &g, LevelDesc *L, uint64_
 // the list counters and the contraction counters zero; records |M|, the
 // round count and how many rounds ran as grid launches (grid_r0: rounds up to
 // grid_r0 did, -2: all did); ends the level loop on an empty matching.
+// defer (the gap rounds of the two-phase matcher): the level moves to
+// PH_MERGE instead, where the merged matching decides.
 template <int NT>
 __device__ void close_matching(const Ctx &c, LevelDesc *L, bool capped, int grid_r0,
-                               int64_t *s_acc) {
+                               int64_t *s_acc, bool defer = false) {
     MatchState *st = c.ms.state;
     __syncthreads();
     if (threadIdx.x < WAVE) {
@@ -657,7 +709,9 @@ __device__ void close_matching(const Ctx &c, LevelDesc *L, bool capped, int grid
         L->rounds = used;
         L->grid_rounds = grid_r0 < 0 ? used : min(grid_r0, used);
         if (capped) c.ctrl->flags |= CF_ROUNDS;
-        if (m == 0 || capped) {
+        if (defer && !capped) {
+            L->phase = PH_MERGE;
+        } else if (m == 0 || capped) {
             L->stop = KAPPA_STOP_EMPTY;
             L->phase = PH_STOPPED;
             c.ctrl->done = 1;
@@ -671,7 +725,7 @@ __device__ void close_matching(const Ctx &c, LevelDesc *L, bool capped, int grid
 // Finisher: one workgroup runs the remaining rounds (from the handoff point,
 // or after round r_last) with workgroup barriers, then closes the level's
 // matching.
-template <int R>
+template <int R, int F = 0>
 __global__ void __launch_bounds__(FINISH_THREADS) finish_k(Ctx c, int l, int r_last) {
     __shared__ Cand shc[FINISH_THREADS / WAVE];
     __shared__ int64_t sh[3 * (FINISH_THREADS / WAVE) + 1];
@@ -698,10 +752,256 @@ __global__ void __launch_bounds__(FINISH_THREADS) finish_k(Ctx c, int l, int r_l
             s_cnt[(r0 + 1) & 1][threadIdx.x] = 0;
         }
         __syncthreads();
-        capped = wg_rounds<R, FINISH_THREADS>(c, g, L, seed, r0, s_cnt, shc, sh, sbase);
+        capped = wg_rounds<R, FINISH_THREADS, F>(c, g, L, seed, r0, s_cnt, shc, sh, sbase);
     }
     // r0 = -2: the round kernels found nothing left, so they ran every round
-    close_matching<FINISH_THREADS>(c, L, capped, r0, s_acc);
+    close_matching<FINISH_THREADS>(c, L, capped, r0, s_acc, F != 0);
+}
+
+// ===========================================================================
+// Two-phase matcher (Section 3.3)
+// ===========================================================================
+// Block phase.  One workgroup matches the nodes of one block [v0, v0 + nb)
+// of 2^bb consecutive ids: local-max rounds over the edges inside the block,
+// the block's state in LDS and workgroup barriers between rounds.  Under the
+// strict order this is Greedy on the block's edges, the sequential matcher
+// the paper runs per processor.  Then, per node: the block partner (loc),
+// the key of that edge (written by the node's last choice), the node record
+// {attribute, free} and mate = best = -1 for the gap rounds; a node with an
+// edge to another block above its own block edge enters the gap rounds'
+// first lists (a node without one has no gap edge: every gap edge is above
+// the block edges at both ends).
+constexpr int BM_MAX = 1 << BM_BITS_MAX;
+static_assert(MK * BM_THREADS >= BM_MAX, "the list step covers a block in one pass");
+static_assert(BM_MAX <= 32768, "local indices are 16-bit");
+
+// v's best free neighbour inside the block over the entries sub, sub+G, ...
+// of [rb, re).  s_mate: LDS state of the block; s_attr: rating attributes.
+template <int R, int G>
+__device__ __forceinline__ Cand block_scan(const DevGraph &g, int32_t v, int32_t v0, int32_t nb,
+                                           uint32_t av, int64_t rb, int64_t re, int sub,
+                                           const int16_t *s_mate, const uint32_t *s_attr,
+                                           uint64_t seed) {
+    Cand best = cand_none();
+    for (int64_t j = rb + sub; j < re; j += G) {
+        const int32_t u = g.adj[j];
+        const int32_t iu = u - v0;
+        if ((uint32_t)iu >= (uint32_t)nb || s_mate[iu] >= 0) continue;   // other block, or taken
+        Cand cd;
+        rate<R>(g.ew[j], s_attr[iu], av, s_attr[iu], av, cd.num, cd.den);
+        cd.h = mix64(seed ^ edge_id(v, u));
+        cd.u = u;
+        if (cand_better(cd, best, v)) best = cd;
+    }
+    return best;
+}
+
+template <int R>
+__global__ void __launch_bounds__(BM_THREADS) block_match_k(Ctx c, int l) {
+    // s_best: local index of the current choice; -1 none yet, -2 no free
+    // neighbour inside the block left (free sets only shrink)
+    __shared__ int16_t s_mate[BM_MAX], s_best[BM_MAX], s_big[BM_MAX];
+    __shared__ uint32_t s_attr[BM_MAX];
+    __shared__ int32_t s_nbig, s_pt[2];
+    __shared__ int64_t sh[BM_THREADS / WAVE + 1];
+    __shared__ int32_t sbase[3];
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_MATCH, g)) return;
+    const int bb = c.block_bits;
+    const uint64_t seed = level_seed(c, l);
+    const uint32_t *out = c.ms.out;
+    const int64_t nblocks = ((int64_t)g.n + ((int64_t)1 << bb) - 1) >> bb;
+    const PList ol[3] = {plist(c.ms, g.n, 0, 0), plist(c.ms, g.n, 0, 1), plist(c.ms, g.n, 0, 2)};
+    for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {   // block-uniform
+        const int32_t v0 = (int32_t)(blk << bb);
+        const int32_t nb = (int32_t)min<int64_t>((int64_t)1 << bb, (int64_t)g.n - v0);
+        if (threadIdx.x == 0) {
+            s_nbig = 0;
+            s_pt[0] = 0;
+            s_pt[1] = 0;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nb; i += BM_THREADS) {
+            const int32_t v = v0 + i;
+            const int64_t deg = g.xadj[v + 1] - g.xadj[v];
+            s_mate[i] = -1;
+            s_best[i] = deg == 0 ? -2 : -1;
+            s_attr[i] = attr_src<R>(g, out, v);
+            if (deg > BIN_SMALL_MAX) s_big[atomicAdd(&s_nbig, 1)] = (int16_t)i;
+        }
+        __syncthreads();
+        const int nbig = s_nbig;
+        // every round with a pointing node matches the top pair among them,
+        // so at most nb/2 + 1 rounds run
+        for (int r = 0;; ++r) {   // block-uniform
+            const int par = r & 1;
+            {   // small rows: SMALL_G lanes per node
+                constexpr int G = SMALL_G;
+                const int sub = threadIdx.x & (G - 1), gs = BM_THREADS / G;
+                const int lim = (nb + gs - 1) / gs * gs;   // uniform trip count (group shuffles)
+                for (int i = threadIdx.x / G; i < lim; i += gs) {
+                    bool act = false;
+                    int64_t rb = 0, re = 0;
+                    const int32_t v = v0 + i;
+                    if (i < nb && s_mate[i] < 0) {
+                        const int b = s_best[i];
+                        if (b >= 0 && s_mate[b] < 0) {   // keeps its choice: still the best
+                            if (sub == 0) s_pt[par] = 1;
+                        } else if (b != -2) {
+                            rb = g.xadj[v];
+                            re = g.xadj[v + 1];
+                            act = re - rb <= BIN_SMALL_MAX;
+                        }
+                    }
+                    Cand cd = act ? block_scan<R, G>(g, v, v0, nb, s_attr[i], rb, re, sub, s_mate,
+                                                     s_attr, seed)
+                                  : cand_none();
+                    cd = group_reduce<G>(cd, v);
+                    if (act && sub == 0) {
+                        if (cd.u >= 0) {
+                            s_best[i] = (int16_t)(cd.u - v0);
+                            c.ms.lkey[v] = LocKey{cd.num, cd.den, cd.h};
+                            s_pt[par] = 1;
+                        } else {
+                            s_best[i] = -2;
+                        }
+                    }
+                }
+            }
+            {   // larger rows: one wave per node
+                const int w = threadIdx.x / WAVE, nw = BM_THREADS / WAVE;
+                for (int q = w; q < nbig; q += nw) {
+                    const int i = s_big[q];
+                    const int b = s_best[i];
+                    if (s_mate[i] >= 0 || b == -2) continue;   // wave-uniform
+                    if (b >= 0 && s_mate[b] < 0) {
+                        if (lane_id() == 0) s_pt[par] = 1;
+                        continue;
+                    }
+                    const int32_t v = v0 + i;
+                    Cand cd = block_scan<R, WAVE>(g, v, v0, nb, s_attr[i], g.xadj[v], g.xadj[v + 1],
+                                                  lane_id(), s_mate, s_attr, seed);
+                    cd = group_reduce<WAVE>(cd, v);
+                    if (lane_id() == 0) {
+                        if (cd.u >= 0) {
+                            s_best[i] = (int16_t)(cd.u - v0);
+                            c.ms.lkey[v] = LocKey{cd.num, cd.den, cd.h};
+                            s_pt[par] = 1;
+                        } else {
+                            s_best[i] = -2;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            const bool go = s_pt[par] != 0;
+            if (go) {   // pairs that chose each other
+                for (int i = threadIdx.x; i < nb; i += BM_THREADS) {
+                    const int b = s_best[i];
+                    if (s_mate[i] < 0 && b >= 0 && s_best[b] == i) s_mate[i] = (int16_t)b;
+                }
+            }
+            if (threadIdx.x == 0) s_pt[par ^ 1] = 0;   // read again only after the barrier
+            __syncthreads();
+            if (!go) break;
+            if (r > nb / 2 + 2) {   // cannot happen on valid state
+                if (threadIdx.x == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_ROUNDS);
+                break;
+            }
+        }
+        // the block matching, the gap rounds' state and their first lists
+        int bin[MK];
+        int32_t vv[MK], bq[MK], dd[MK];
+#pragma unroll
+        for (int k = 0; k < MK; ++k) {
+            const int i = threadIdx.x + k * BM_THREADS;   // MK * BM_THREADS >= BM_MAX
+            bin[k] = -1;
+            vv[k] = v0 + i;
+            bq[k] = -1;
+            dd[k] = 0;
+            if (i >= nb) continue;
+            const int32_t v = v0 + i;
+            const int m = s_mate[i];
+            const int32_t lc = m >= 0 ? v0 + m : -1;
+            c.ms.loc[v] = lc;
+            L->mate[v] = -1;
+            c.ms.best[v] = -1;
+            c.ms.nrec[v] = make_int2((int32_t)s_attr[i], -1);
+            // an edge to another block above the block edge at v?
+            const int64_t rb = g.xadj[v], re = g.xadj[v + 1];
+            Cand kv = cand_none();
+            if (lc >= 0) {
+                const LocKey q = c.ms.lkey[v];
+                kv.num = q.num;
+                kv.den = q.den;
+                kv.h = q.h;
+                kv.u = lc;
+            }
+            bool gap = false;
+            for (int64_t j = rb; j < re && !gap; ++j) {
+                const int32_t u = g.adj[j];
+                if ((uint32_t)(u - v0) < (uint32_t)nb) continue;
+                Cand cd;
+                const uint32_t au = attr_src<R>(g, out, u);
+                rate<R>(g.ew[j], au, s_attr[i], au, s_attr[i], cd.num, cd.den);
+                cd.h = mix64(seed ^ edge_id(v, u));
+                cd.u = u;
+                gap = cand_better(cd, kv, v);
+            }
+            if (gap) {
+                dd[k] = (int32_t)(re - rb);
+                bin[k] = bin_of(re - rb);
+            }
+        }
+        block_append_mk(bin, vv, bq, dd, ol, &c.ms.state->cnt[0][0], sh, sbase);
+        __syncthreads();   // LDS is reused by the next block
+    }
+}
+
+// Merge: a gap edge replaces the block edges at its ends; a node whose
+// block partner took a gap edge stays unmatched.  Gap partners are read from
+// the node records (their mate field), block partners from loc.
+__global__ void __launch_bounds__(BLOCK) merge_k(Ctx c, int l) {
+    __shared__ int64_t sh[3 * (BLOCK / WAVE) + 1];
+    LevelDesc *L = c.lv + l;
+    if (L->phase != PH_MERGE) return;
+    const int32_t n = L->n;
+    const int2 *nrec = c.ms.nrec;
+    int64_t pairs = 0, z0 = 0, z1 = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t m = nrec[i].y;
+        if (m < 0) {
+            const int32_t lc = c.ms.loc[i];
+            if (lc >= 0 && nrec[lc].y < 0) m = lc;
+        }
+        L->mate[i] = m;
+        pairs += m > i;
+    }
+    block_sum3(pairs, z0, z1, sh);
+    if (threadIdx.x == 0 && pairs)
+        atomicAdd((unsigned long long *)&c.ms.state->spairs[shard_of_block()],
+                  (unsigned long long)pairs);
+}
+
+// |M| of the merged matching; ends the level loop if it is empty.
+__global__ void __launch_bounds__(WAVE) merge_close_k(Ctx c, int l) {
+    LevelDesc *L = c.lv + l;
+    if (L->phase != PH_MERGE) return;
+    int64_t *p = &c.ms.state->spairs[lane_id()];
+    const int64_t m = wave_sum(*p);
+    *p = 0;
+    if (lane_id() == 0) {
+        L->matched = m;
+        if (m == 0) {
+            L->stop = KAPPA_STOP_EMPTY;
+            L->phase = PH_STOPPED;
+            c.ctrl->done = 1;
+        } else {
+            L->phase = PH_CONTRACT;
+        }
+    }
 }
 
 // ===========================================================================
@@ -1531,15 +1831,66 @@ static void match_impl(const Ctx &c, int l, int32_t n_hint, int rounds, hipStrea
     hipLaunchKernelGGL(finish_k<R>, dim3(1), dim3(FINISH_THREADS), 0, s, c, l, rounds);
 }
 
+// Two-phase matcher: the block phase, `rounds` gap rounds as grid launches
+// (the finisher completes any remainder), then the merge.
+template <int R>
+static void two_phase_impl(const Ctx &c, int l, int32_t n_hint, int rounds, hipStream_t s) {
+    {
+        KAPPA_PROF("block_match", s);
+        const int64_t blocks = ((int64_t)n_hint + (1 << c.block_bits) - 1) >> c.block_bits;
+        hipLaunchKernelGGL(block_match_k<R>, dim3(grid_for(blocks, 1, 4096)), dim3(BM_THREADS), 0,
+                           s, c, l);
+    }
+    // the gap rounds start from the lists the block phase wrote (round 1 is
+    // an ordinary later round); a quarter of the nodes is a generous start
+    double est = n_hint / 4.0;
+    for (int r = 1; r <= rounds; ++r, est *= 0.7) {
+        int64_t e = (int64_t)est + 1;
+        PickGrid pg;
+        pg.b0 = grid_for(e, BLOCK / SMALL_G, 2048);
+        pg.b1 = grid_for(e, BLOCK / WAVE * 8, 128);
+        pg.b2 = grid_for(e, 4096, 64);
+        {
+            KAPPA_PROF("gap_pick", s);
+            hipLaunchKernelGGL((pick_k<R, false, 1>), dim3(pg.b0 + pg.b1 + pg.b2), dim3(BLOCK), 0, s,
+                               c, l, r, pg);
+        }
+        KAPPA_PROF("gap_mate", s);
+        hipLaunchKernelGGL((mate_k<R, false>), dim3(grid_for(e, BLOCK, 2048)), dim3(BLOCK), 0, s, c,
+                           l, r);
+    }
+    {
+        KAPPA_PROF("gap_finish", s);
+        hipLaunchKernelGGL((finish_k<R, 1>), dim3(1), dim3(FINISH_THREADS), 0, s, c, l, rounds);
+    }
+    {
+        KAPPA_PROF("merge", s);
+        hipLaunchKernelGGL(merge_k, dim3(grid_for(n_hint, BLOCK, 2048)), dim3(BLOCK), 0, s, c, l);
+    }
+    KAPPA_PROF("merge_close", s);
+    hipLaunchKernelGGL(merge_close_k, dim3(1), dim3(WAVE), 0, s, c, l);
+}
+
 void launch_level_match(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, int rounds,
                         bool stop_rules, bool out_kernels, hipStream_t s) {
     if (rounds < 1) rounds = 1;
+    const bool two = c.block_bits >= 0;
     {
         KAPPA_PROF("match_init", s);
-        hipLaunchKernelGGL(match_init_k, dim3(grid_for(n_hint, BLOCK, 2048)), dim3(BLOCK), 0, s,
-                           c, l, stop_rules ? 1 : 0);
+        hipLaunchKernelGGL(match_init_k, dim3(two ? 1 : grid_for(n_hint, BLOCK, 2048)), dim3(BLOCK),
+                           0, s, c, l, stop_rules ? 1 : 0, two ? 0 : 1);
     }
     if (c.rating == KAPPA_INNER_OUTER && out_kernels) launch_level_out(c, l, nnz_cap, n_hint, s);
+    if (two) {
+        switch (c.rating) {
+        case KAPPA_INNER_OUTER: two_phase_impl<KAPPA_INNER_OUTER>(c, l, n_hint, rounds, s); break;
+        case KAPPA_WEIGHT: two_phase_impl<KAPPA_WEIGHT>(c, l, n_hint, rounds, s); break;
+        case KAPPA_EXPANSION: two_phase_impl<KAPPA_EXPANSION>(c, l, n_hint, rounds, s); break;
+        case KAPPA_EXPANSION_STAR: two_phase_impl<KAPPA_EXPANSION_STAR>(c, l, n_hint, rounds, s); break;
+        default: two_phase_impl<KAPPA_EXPANSION_STAR2>(c, l, n_hint, rounds, s); break;
+        }
+        return;
+    }
     switch (c.rating) {
     case KAPPA_INNER_OUTER: match_impl<KAPPA_INNER_OUTER>(c, l, n_hint, rounds, s); break;
     case KAPPA_WEIGHT: match_impl<KAPPA_WEIGHT>(c, l, n_hint, rounds, s); break;

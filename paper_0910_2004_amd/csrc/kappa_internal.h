@@ -22,6 +22,8 @@ constexpr int SMALL_G = 4;
 // Matching rounds: a single workgroup finishes once at most TAIL_MAX nodes
 // still point somewhere.
 constexpr int TAIL_MAX = 128;
+constexpr int BM_BITS_MAX = 11;     // two-phase matcher: blocks of at most 2^11 nodes
+constexpr int BM_THREADS = 256;     //   matched by one workgroup each
 constexpr int FINISH_THREADS = 1024;
 // Levels of at most TAIL_MAX_N nodes and TAIL_MAX_NNZ entries (and every
 // level after them) run in one workgroup of TAIL_THREADS threads.
@@ -525,6 +527,7 @@ enum LevelPhase : int32_t {
     PH_CONTRACT = 2,  // matching done, contraction in progress
     PH_COMPACT = 3,   // next level allocated, rows being copied
     PH_DONE = 4,      // finished inside the tail kernel (later launches for it are no-ops)
+    PH_MERGE = 5,     // two-phase matcher: gap rounds done, the matchings are merged next
     PH_STOPPED = -1   // a stop rule fired on this level
 };
 
@@ -570,6 +573,13 @@ struct MatchState {
     int32_t pad[3];
     int32_t sround[NSHARD];               // per shard: last round in which some node pointed
     int64_t sstat[STAT_ROUNDS][3][NSHARD];  // per round and shard: pointing nodes, their degree sum, pairs
+    int64_t spairs[NSHARD];                 // two-phase merge: pairs per shard (zero between uses)
+};
+
+// Two-phase matcher: the rating key (num, den, h) of the edge the block
+// phase matched at a node (read only where that node has a block partner).
+struct LocKey {
+    uint64_t num, den, h;
 };
 struct MatchScratch {
     int32_t *best;          // n: current choice of every node (-1: none)
@@ -578,6 +588,8 @@ struct MatchScratch {
     uint32_t *out;          // n (innerOuter)
     int32_t *tile_row;      // tile rows of the level (innerOuter)
     MatchState *state;
+    int32_t *loc;           // two-phase: n, the block phase's partner (-1: none)
+    LocKey *lkey;           // two-phase: n, the key of that edge
 };
 
 // Contraction scratch (sized for level 0).
@@ -619,6 +631,7 @@ struct Ctx {
     MatchScratch ms;
     ContractScratch cs;
     BatchCtx b;
+    int32_t block_bits = -1;   // >= 0: two-phase matcher with blocks of 2^block_bits ids
 };
 
 // K bump allocations in the arena with one read and one write of the cursor

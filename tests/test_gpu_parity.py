@@ -295,7 +295,7 @@ def test_trusted_input_skips_entry_checks_only():
     with pytest.raises(K.KappaError) as e:
         K.kappa_coarsen(bad, 0, 42, 64, trusted=True)
     assert e.value.status == K.E_GRAPH
-    p = K._lib.c_params(0, 42, 64, 1, 20, 64, 6)
+    p = K._lib.c_params(0, 42, 64, 1, 20, 64, 4)   # an unknown flag
     h = ctypes.c_void_p()
     st = K.lib().kappa_coarsen(ctypes.byref(dg.c()), ctypes.byref(p), ctypes.byref(h),
                                K._lib._stream())
