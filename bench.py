@@ -128,8 +128,8 @@ def model_bytes(stats_by_rating):
 
 # rocprofv3 kernel names (namespace, "void " and arguments stripped) of the
 # library's profiler names
-KERNEL_SYMBOLS = {"pick": r"pick_k<\d, false>", "mate": r"mate_k<\d, false>",
-                  "pick_first": r"pick_k<\d, true>", "fill_small": r"fill_small_k",
+KERNEL_SYMBOLS = {"pick": r"pick_k<\d, false, 0>", "mate": r"mate_k<\d, false>",
+                  "pick_first": r"pick_k<\d, true, 0>", "fill_small": r"fill_small_k",
                   "compact": r"compact_k", "cut_entries": r"up_entries_k<(true|false)>"}
 COUNTER_SOURCES = ["paper_0910_2004_amd/csrc/k_level.hip", "paper_0910_2004_amd/csrc/kappa_internal.h",
                    "paper_0910_2004_amd/csrc/k_graph.hip"]
@@ -225,6 +225,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scale", type=int, default=20, help="log2 of the node count")
     ap.add_argument("--k", type=int, default=64)
+    ap.add_argument("--block-bits", type=int, default=None,
+                    help="rgg20: match with the two-phase matcher (Section 3.3), blocks of "
+                         "2^BLOCK_BITS consecutive ids (0..11); default: local-max rounds")
     ap.add_argument("--order", default="generation", choices=["generation", "rcb"],
                     help="rgg20: node ids in point generation order (the headline) or in "
                          "recursive coordinate bisection order (locality of a geometric "
@@ -298,7 +301,8 @@ def main():
             raise RuntimeError(f"kappa_validate: {st}")
         stats = {}
         for r in ratings:
-            H = K.kappa_coarsen(dg, r, seed, stop_n, 1, 20, 64, trusted=True)
+            H = K.kappa_coarsen(dg, r, seed, stop_n, 1, 20, 64, trusted=True,
+                                block_bits=args.block_bits)
             _, res = K.kappa_uncoarsen(H, k, part_seed, eps[0], eps[1], part0=part0)
             stats[r] = (level_stats(H), res[0].as_tuple())
             del H
@@ -350,7 +354,8 @@ def main():
         avg_s = ms / cnt / 1e3
         achieved = per_launch_bytes / avg_s / 1e9
         # the stored counters were taken on the generation-order graph
-        traffic = counter_traffic(rk) if args.order == "generation" else None
+        traffic = counter_traffic(rk) if args.order == "generation" and args.block_bits is None \
+            else None
         roof = {"bound": "hbm", "kernel": rk, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else int(traffic),
@@ -363,7 +368,7 @@ def main():
         import oracle as O
         t3 = time.perf_counter()
         for r in ratings:
-            OH = O.coarsen(g, r, seed, stop_n, 1, 20, 64)
+            OH = O.coarsen(g, r, seed, stop_n, 1, 20, 64, block_bits=args.block_bits)
             O.uncoarsen(OH, k, part_seed, eps[0], eps[1])
         t4 = time.perf_counter()
         cpu = {"value": round(edges_step / (t4 - t3), 1), "unit": "edges/s", "cores": 1,
@@ -392,8 +397,10 @@ def main():
         "config": {"workload": f"rgg n=2^{args.scale} mean degree 8, unit weights, both ratings "
                                f"(expansion*2, innerOuter), k={k}, stop n<={stop_n}, eps=3/100"
                                + ("" if args.order == "generation" else
-                                  ", node ids in recursive coordinate bisection order"),
-                   "node_order": args.order,
+                                  ", node ids in recursive coordinate bisection order")
+                               + ("" if args.block_bits is None else
+                                  f", two-phase matcher with blocks of 2^{args.block_bits}"),
+                   "node_order": args.order, "block_bits": args.block_bits,
                    "n": g.n, "m": g.m, "edges_per_step": edges_step, "k": k, "stop_n": stop_n,
                    "seed": seed, "graph_seed": 2, "levels_n": levels},
         "roofline": roof,

@@ -772,36 +772,103 @@ __global__ void __launch_bounds__(FINISH_THREADS) finish_k(Ctx c, int l, int r_l
 // first lists (a node without one has no gap edge: every gap edge is above
 // the block edges at both ends).
 constexpr int BM_MAX = 1 << BM_BITS_MAX;
+constexpr int BM_STAGE = 8192;   // CSR entries of a block staged in LDS (more: rows read from HBM)
 static_assert(MK * BM_THREADS >= BM_MAX, "the list step covers a block in one pass");
-static_assert(BM_MAX <= 32768, "local indices are 16-bit");
+static_assert(BM_MAX <= 32768 && BM_STAGE <= 32768, "local indices are 16-bit");
+
+// The rows of a block are contiguous in the CSR: entry j of the block is
+// entry e0 + j of the graph.  Staged blocks keep, per entry, the neighbour's
+// local index (-1: another block) and the weight in LDS, and the row
+// offsets relative to e0.
+struct BlockRows {
+    int64_t e0;
+    bool staged;
+    const int16_t *nbr;
+    const uint32_t *w;
+    const int32_t *roff;
+};
+__device__ __forceinline__ void block_row(const DevGraph &g, const BlockRows &br, int32_t v,
+                                          int i, int64_t &rb, int64_t &re) {
+    if (br.staged) {
+        rb = br.roff[i];
+        re = br.roff[i + 1];
+    } else {
+        rb = g.xadj[v] - br.e0;
+        re = g.xadj[v + 1] - br.e0;
+    }
+}
 
 // v's best free neighbour inside the block over the entries sub, sub+G, ...
-// of [rb, re).  s_mate: LDS state of the block; s_attr: rating attributes.
-template <int R, int G>
-__device__ __forceinline__ Cand block_scan(const DevGraph &g, int32_t v, int32_t v0, int32_t nb,
-                                           uint32_t av, int64_t rb, int64_t re, int sub,
-                                           const int16_t *s_mate, const uint32_t *s_attr,
-                                           uint64_t seed) {
+// of [rb, re) (block-relative).  s_mate: LDS state; s_attr: attributes.
+template <int R, int G, bool STAGED>
+__device__ __forceinline__ Cand block_scan(const DevGraph &g, const BlockRows &br, int32_t v,
+                                           int32_t v0, int32_t nb, uint32_t av, int64_t rb,
+                                           int64_t re, int sub, const int16_t *s_mate,
+                                           const uint32_t *s_attr, uint64_t seed) {
     Cand best = cand_none();
     for (int64_t j = rb + sub; j < re; j += G) {
-        const int32_t u = g.adj[j];
-        const int32_t iu = u - v0;
-        if ((uint32_t)iu >= (uint32_t)nb || s_mate[iu] >= 0) continue;   // other block, or taken
+        int32_t iu;
+        uint32_t w;
+        if (STAGED) {
+            iu = br.nbr[j];
+            if (iu < 0) continue;   // another block
+            w = br.w[j];
+        } else {
+            iu = g.adj[br.e0 + j] - v0;
+            if ((uint32_t)iu >= (uint32_t)nb) continue;
+            w = g.ew[br.e0 + j];
+        }
+        if (s_mate[iu] >= 0) continue;   // taken
         Cand cd;
-        rate<R>(g.ew[j], s_attr[iu], av, s_attr[iu], av, cd.num, cd.den);
-        cd.h = mix64(seed ^ edge_id(v, u));
-        cd.u = u;
+        rate<R>(w, s_attr[iu], av, s_attr[iu], av, cd.num, cd.den);
+        cd.u = v0 + iu;
+        cd.h = mix64(seed ^ edge_id(v, cd.u));
         if (cand_better(cd, best, v)) best = cd;
     }
     return best;
 }
 
+// Is some edge from v to another block above kv (v's block edge, or none)?
+// Over the entries sub, sub+G, ... of [rb, re).
+template <int R, int G>
+__device__ __forceinline__ bool block_gap_any(const DevGraph &g, const BlockRows &br, int32_t v,
+                                              int32_t v0, int32_t nb, uint32_t av, int64_t rb,
+                                              int64_t re, int sub, const Cand &kv,
+                                              const uint32_t *out, uint64_t seed) {
+    bool any = false;
+    for (int64_t j = rb + sub; j < re && !any; j += G) {
+        if (br.staged && br.nbr[j] >= 0) continue;
+        const int32_t u = g.adj[br.e0 + j];
+        if ((uint32_t)(u - v0) < (uint32_t)nb) continue;
+        const uint32_t au = attr_src<R>(g, out, u);
+        Cand cd;
+        rate<R>(br.staged ? br.w[j] : g.ew[br.e0 + j], au, av, au, av, cd.num, cd.den);
+        cd.u = u;
+        cd.h = mix64(seed ^ edge_id(v, u));
+        any = cand_better(cd, kv, v);
+    }
+    return any;
+}
+
+template <int G>
+__device__ __forceinline__ bool group_any(bool x) {
+    int a = x ? 1 : 0;
+    for (int off = G / 2; off > 0; off >>= 1) a |= __shfl_xor(a, off, G);
+    return a != 0;
+}
+
+// two workgroups per CU (LDS allows two; registers are held to 128)
 template <int R>
-__global__ void __launch_bounds__(BM_THREADS) block_match_k(Ctx c, int l) {
+__global__ void __launch_bounds__(BM_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+block_match_k(Ctx c, int l) {
     // s_best: local index of the current choice; -1 none yet, -2 no free
-    // neighbour inside the block left (free sets only shrink)
+    // neighbour inside the block left (free sets only shrink).  After the
+    // rounds it holds the gap-list flag.
     __shared__ int16_t s_mate[BM_MAX], s_best[BM_MAX], s_big[BM_MAX];
     __shared__ uint32_t s_attr[BM_MAX];
+    __shared__ int32_t s_roff[BM_MAX + 1];
+    __shared__ int16_t s_nbr[BM_STAGE];
+    __shared__ uint32_t s_w[BM_STAGE];
     __shared__ int32_t s_nbig, s_pt[2];
     __shared__ int64_t sh[BM_THREADS / WAVE + 1];
     __shared__ int32_t sbase[3];
@@ -813,22 +880,40 @@ __global__ void __launch_bounds__(BM_THREADS) block_match_k(Ctx c, int l) {
     const uint32_t *out = c.ms.out;
     const int64_t nblocks = ((int64_t)g.n + ((int64_t)1 << bb) - 1) >> bb;
     const PList ol[3] = {plist(c.ms, g.n, 0, 0), plist(c.ms, g.n, 0, 1), plist(c.ms, g.n, 0, 2)};
+    constexpr int G = SMALL_G, GS = BM_THREADS / G;
+    const int sub = threadIdx.x & (G - 1);
     for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {   // block-uniform
         const int32_t v0 = (int32_t)(blk << bb);
         const int32_t nb = (int32_t)min<int64_t>((int64_t)1 << bb, (int64_t)g.n - v0);
+        BlockRows br;
+        br.e0 = g.xadj[v0];
+        const int64_t ne = g.xadj[v0 + nb] - br.e0;
+        br.staged = ne <= BM_STAGE;   // block-uniform
+        br.nbr = s_nbr;
+        br.w = s_w;
+        br.roff = s_roff;
         if (threadIdx.x == 0) {
             s_nbig = 0;
             s_pt[0] = 0;
             s_pt[1] = 0;
+            if (br.staged) s_roff[nb] = (int32_t)ne;
         }
         __syncthreads();
         for (int i = threadIdx.x; i < nb; i += BM_THREADS) {
             const int32_t v = v0 + i;
-            const int64_t deg = g.xadj[v + 1] - g.xadj[v];
+            const int64_t rb = g.xadj[v], deg = g.xadj[v + 1] - rb;
+            if (br.staged) s_roff[i] = (int32_t)(rb - br.e0);
             s_mate[i] = -1;
             s_best[i] = deg == 0 ? -2 : -1;
             s_attr[i] = attr_src<R>(g, out, v);
             if (deg > BIN_SMALL_MAX) s_big[atomicAdd(&s_nbig, 1)] = (int16_t)i;
+        }
+        if (br.staged) {
+            for (int64_t j = threadIdx.x; j < ne; j += BM_THREADS) {
+                const int32_t iu = g.adj[br.e0 + j] - v0;
+                s_nbr[j] = (uint32_t)iu < (uint32_t)nb ? (int16_t)iu : (int16_t)-1;
+                s_w[j] = g.ew[br.e0 + j];
+            }
         }
         __syncthreads();
         const int nbig = s_nbig;
@@ -836,11 +921,9 @@ __global__ void __launch_bounds__(BM_THREADS) block_match_k(Ctx c, int l) {
         // so at most nb/2 + 1 rounds run
         for (int r = 0;; ++r) {   // block-uniform
             const int par = r & 1;
-            {   // small rows: SMALL_G lanes per node
-                constexpr int G = SMALL_G;
-                const int sub = threadIdx.x & (G - 1), gs = BM_THREADS / G;
-                const int lim = (nb + gs - 1) / gs * gs;   // uniform trip count (group shuffles)
-                for (int i = threadIdx.x / G; i < lim; i += gs) {
+            {   // small rows: G lanes per node
+                const int lim = (nb + GS - 1) / GS * GS;   // uniform trip count (group shuffles)
+                for (int i = threadIdx.x / G; i < lim; i += GS) {
                     bool act = false;
                     int64_t rb = 0, re = 0;
                     const int32_t v = v0 + i;
@@ -849,14 +932,16 @@ __global__ void __launch_bounds__(BM_THREADS) block_match_k(Ctx c, int l) {
                         if (b >= 0 && s_mate[b] < 0) {   // keeps its choice: still the best
                             if (sub == 0) s_pt[par] = 1;
                         } else if (b != -2) {
-                            rb = g.xadj[v];
-                            re = g.xadj[v + 1];
+                            block_row(g, br, v, i, rb, re);
                             act = re - rb <= BIN_SMALL_MAX;
                         }
                     }
-                    Cand cd = act ? block_scan<R, G>(g, v, v0, nb, s_attr[i], rb, re, sub, s_mate,
-                                                     s_attr, seed)
-                                  : cand_none();
+                    Cand cd = cand_none();
+                    if (act)
+                        cd = br.staged ? block_scan<R, G, true>(g, br, v, v0, nb, s_attr[i], rb, re,
+                                                                sub, s_mate, s_attr, seed)
+                                       : block_scan<R, G, false>(g, br, v, v0, nb, s_attr[i], rb, re,
+                                                                 sub, s_mate, s_attr, seed);
                     cd = group_reduce<G>(cd, v);
                     if (act && sub == 0) {
                         if (cd.u >= 0) {
@@ -880,8 +965,14 @@ __global__ void __launch_bounds__(BM_THREADS) block_match_k(Ctx c, int l) {
                         continue;
                     }
                     const int32_t v = v0 + i;
-                    Cand cd = block_scan<R, WAVE>(g, v, v0, nb, s_attr[i], g.xadj[v], g.xadj[v + 1],
-                                                  lane_id(), s_mate, s_attr, seed);
+                    int64_t rb, re;
+                    block_row(g, br, v, i, rb, re);
+                    Cand cd = br.staged ? block_scan<R, WAVE, true>(g, br, v, v0, nb, s_attr[i], rb,
+                                                                    re, lane_id(), s_mate, s_attr,
+                                                                    seed)
+                                        : block_scan<R, WAVE, false>(g, br, v, v0, nb, s_attr[i],
+                                                                     rb, re, lane_id(), s_mate,
+                                                                     s_attr, seed);
                     cd = group_reduce<WAVE>(cd, v);
                     if (lane_id() == 0) {
                         if (cd.u >= 0) {
@@ -910,6 +1001,51 @@ __global__ void __launch_bounds__(BM_THREADS) block_match_k(Ctx c, int l) {
                 break;
             }
         }
+        // gap-list flags (into s_best): an edge to another block above the
+        // node's block edge
+        {
+            const int lim = (nb + GS - 1) / GS * GS;
+            for (int i = threadIdx.x / G; i < lim; i += GS) {
+                bool act = false;
+                int64_t rb = 0, re = 0;
+                const int32_t v = v0 + i;
+                Cand kv = cand_none();
+                if (i < nb) {
+                    block_row(g, br, v, i, rb, re);
+                    act = re - rb <= BIN_SMALL_MAX;
+                    if (act && s_mate[i] >= 0) {
+                        const LocKey q = c.ms.lkey[v];
+                        kv.num = q.num;
+                        kv.den = q.den;
+                        kv.h = q.h;
+                        kv.u = v0 + s_mate[i];
+                    }
+                }
+                const bool any = group_any<G>(
+                    act && block_gap_any<R, G>(g, br, v, v0, nb, s_attr[i], rb, re, sub, kv, out,
+                                               seed));
+                if (act && sub == 0) s_best[i] = any ? 1 : 0;
+            }
+            const int w = threadIdx.x / WAVE, nw = BM_THREADS / WAVE;
+            for (int q = w; q < nbig; q += nw) {
+                const int i = s_big[q];
+                const int32_t v = v0 + i;
+                int64_t rb, re;
+                block_row(g, br, v, i, rb, re);
+                Cand kv = cand_none();
+                if (s_mate[i] >= 0) {
+                    const LocKey k = c.ms.lkey[v];
+                    kv.num = k.num;
+                    kv.den = k.den;
+                    kv.h = k.h;
+                    kv.u = v0 + s_mate[i];
+                }
+                const bool any = __ballot(block_gap_any<R, WAVE>(g, br, v, v0, nb, s_attr[i], rb, re,
+                                                                 lane_id(), kv, out, seed)) != 0;
+                if (lane_id() == 0) s_best[i] = any ? 1 : 0;
+            }
+        }
+        __syncthreads();
         // the block matching, the gap rounds' state and their first lists
         int bin[MK];
         int32_t vv[MK], bq[MK], dd[MK];
@@ -923,35 +1059,14 @@ __global__ void __launch_bounds__(BM_THREADS) block_match_k(Ctx c, int l) {
             if (i >= nb) continue;
             const int32_t v = v0 + i;
             const int m = s_mate[i];
-            const int32_t lc = m >= 0 ? v0 + m : -1;
-            c.ms.loc[v] = lc;
+            c.ms.loc[v] = m >= 0 ? v0 + m : -1;
             L->mate[v] = -1;
             c.ms.best[v] = -1;
             c.ms.nrec[v] = make_int2((int32_t)s_attr[i], -1);
-            // an edge to another block above the block edge at v?
-            const int64_t rb = g.xadj[v], re = g.xadj[v + 1];
-            Cand kv = cand_none();
-            if (lc >= 0) {
-                const LocKey q = c.ms.lkey[v];
-                kv.num = q.num;
-                kv.den = q.den;
-                kv.h = q.h;
-                kv.u = lc;
-            }
-            bool gap = false;
-            for (int64_t j = rb; j < re && !gap; ++j) {
-                const int32_t u = g.adj[j];
-                if ((uint32_t)(u - v0) < (uint32_t)nb) continue;
-                Cand cd;
-                const uint32_t au = attr_src<R>(g, out, u);
-                rate<R>(g.ew[j], au, s_attr[i], au, s_attr[i], cd.num, cd.den);
-                cd.h = mix64(seed ^ edge_id(v, u));
-                cd.u = u;
-                gap = cand_better(cd, kv, v);
-            }
-            if (gap) {
-                dd[k] = (int32_t)(re - rb);
-                bin[k] = bin_of(re - rb);
+            if (s_best[i] == 1) {
+                const int64_t deg = g.xadj[v + 1] - g.xadj[v];
+                dd[k] = (int32_t)deg;
+                bin[k] = bin_of(deg);
             }
         }
         block_append_mk(bin, vv, bq, dd, ol, &c.ms.state->cnt[0][0], sh, sbase);
@@ -1831,10 +1946,12 @@ static void match_impl(const Ctx &c, int l, int32_t n_hint, int rounds, hipStrea
     hipLaunchKernelGGL(finish_k<R>, dim3(1), dim3(FINISH_THREADS), 0, s, c, l, rounds);
 }
 
-// Two-phase matcher: the block phase, `rounds` gap rounds as grid launches
-// (the finisher completes any remainder), then the merge.
+// Two-phase matcher: the block phase, a few gap rounds as grid launches (the
+// gap graph is small: edges between blocks above both block edges; the
+// finisher completes any remainder), then the merge.
 template <int R>
-static void two_phase_impl(const Ctx &c, int l, int32_t n_hint, int rounds, hipStream_t s) {
+static void two_phase_impl(const Ctx &c, int l, int32_t n_hint, hipStream_t s) {
+    const int rounds = n_hint >= (1 << 17) ? 3 : (n_hint >= (1 << 14) ? 2 : 1);
     {
         KAPPA_PROF("block_match", s);
         const int64_t blocks = ((int64_t)n_hint + (1 << c.block_bits) - 1) >> c.block_bits;
@@ -1883,11 +2000,11 @@ void launch_level_match(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, in
     if (c.rating == KAPPA_INNER_OUTER && out_kernels) launch_level_out(c, l, nnz_cap, n_hint, s);
     if (two) {
         switch (c.rating) {
-        case KAPPA_INNER_OUTER: two_phase_impl<KAPPA_INNER_OUTER>(c, l, n_hint, rounds, s); break;
-        case KAPPA_WEIGHT: two_phase_impl<KAPPA_WEIGHT>(c, l, n_hint, rounds, s); break;
-        case KAPPA_EXPANSION: two_phase_impl<KAPPA_EXPANSION>(c, l, n_hint, rounds, s); break;
-        case KAPPA_EXPANSION_STAR: two_phase_impl<KAPPA_EXPANSION_STAR>(c, l, n_hint, rounds, s); break;
-        default: two_phase_impl<KAPPA_EXPANSION_STAR2>(c, l, n_hint, rounds, s); break;
+        case KAPPA_INNER_OUTER: two_phase_impl<KAPPA_INNER_OUTER>(c, l, n_hint, s); break;
+        case KAPPA_WEIGHT: two_phase_impl<KAPPA_WEIGHT>(c, l, n_hint, s); break;
+        case KAPPA_EXPANSION: two_phase_impl<KAPPA_EXPANSION>(c, l, n_hint, s); break;
+        case KAPPA_EXPANSION_STAR: two_phase_impl<KAPPA_EXPANSION_STAR>(c, l, n_hint, s); break;
+        default: two_phase_impl<KAPPA_EXPANSION_STAR2>(c, l, n_hint, s); break;
         }
         return;
     }

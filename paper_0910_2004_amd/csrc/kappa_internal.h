@@ -23,7 +23,7 @@ constexpr int SMALL_G = 4;
 // still point somewhere.
 constexpr int TAIL_MAX = 128;
 constexpr int BM_BITS_MAX = 11;     // two-phase matcher: blocks of at most 2^11 nodes
-constexpr int BM_THREADS = 256;     //   matched by one workgroup each
+constexpr int BM_THREADS = 512;     //   matched by one workgroup each
 constexpr int FINISH_THREADS = 1024;
 // Levels of at most TAIL_MAX_N nodes and TAIL_MAX_NNZ entries (and every
 // level after them) run in one workgroup of TAIL_THREADS threads.
