@@ -481,32 +481,28 @@ bool debug_on() {
 // c(V) and the maximum degree), and no entry is checked.
 kappa_status validate_impl(const DevGraph &g, hipStream_t s, int32_t *maxdeg_out,
                            bool trusted = false) {
-    uint32_t *flags = nullptr;
-    int32_t *mdeg = nullptr;
-    uint64_t *sums = nullptr;
-    int32_t *tr = nullptr;
-    std::unique_ptr<Workspace> w;
-    bool ok = carve_workspace(s, w, [&](Carve &cv) {
-        flags = cv.get<uint32_t>(1);
-        mdeg = cv.get<int32_t>(NSHARD);
-        sums = cv.get<uint64_t>(4 * NSHARD);
-        tr = cv.get<int32_t>(tile_rows_needed(g.nnz));
-    });
-    if (!ok) return KAPPA_E_NOMEM;
-    launch_fill_u32(flags, 1, 0, s);
-    launch_fill_u32((uint32_t *)mdeg, NSHARD, 0, s);
-    launch_fill_u64(sums, 4 * NSHARD, 0, s);
-    launch_validate(g, tr, flags, sums, mdeg, s, trusted);
+    // the kernels' outputs in one block: zeroed by one launch, read back by one copy
     struct RB {
         uint32_t flags;
         int32_t mdeg[NSHARD];
         uint64_t sums[4 * NSHARD];
     };
+    static_assert(sizeof(RB) % 4 == 0, "zeroed as words");
+    RB *dv = nullptr;
+    int32_t *tr = nullptr;
+    std::unique_ptr<Workspace> w;
+    bool ok = carve_workspace(s, w, [&](Carve &cv) {
+        dv = cv.get<RB>(1);
+        tr = cv.get<int32_t>(tile_rows_needed(g.nnz));
+    });
+    if (!ok) return KAPPA_E_NOMEM;
+    ZeroRanges z;
+    z.add(dv, sizeof(RB) / 4);
+    launch_zero(z, s);
+    launch_validate(g, tr, &dv->flags, dv->sums, dv->mdeg, s, trusted);
     RB *rb = (RB *)pinned(sizeof(RB));
     if (!rb) return KAPPA_E_NOMEM;
-    HIPCHK(hipMemcpyAsync(&rb->flags, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(rb->mdeg, mdeg, sizeof(rb->mdeg), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(rb->sums, sums, sizeof(rb->sums), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(rb, dv, sizeof(RB), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     uint64_t tot[4] = {0, 0, 0, 0};
     int32_t md = 0;
@@ -557,15 +553,18 @@ void carve_scratch(Carve &cv, const DevGraph &g, int rating, bool hubs, Ctx &c) 
 }
 
 void fill_scratch(const DevGraph &g, const Ctx &c, hipStream_t s) {
-    launch_fill_u32(c.cs.arrive, ARRIVE_WORDS, 0, s);
-    launch_fill_u32((uint32_t *)&c.ms.state->cnt[0][0], 16, 0, s);   // round-1 list counters
-    launch_fill_u32((uint32_t *)&c.ms.state->sround[0], NSHARD, 0, s);
-    launch_fill_u64((uint64_t *)&c.ms.state->sstat[0][0][0], (int64_t)STAT_ROUNDS * 3 * NSHARD, 0, s);
-    launch_fill_u64((uint64_t *)&c.ms.state->spairs[0], NSHARD, 0, s);
+    ZeroRanges z;
+    z.add(c.cs.arrive, ARRIVE_WORDS);
+    z.add(c.cs.row_cnt, 4);
+    z.add(c.cs.totals, 4 * 2);
+    // the matching state: list counters, round statistics, merge counts
+    static_assert(sizeof(MatchState) % 4 == 0, "zeroed as words");
+    z.add(c.ms.state, sizeof(MatchState) / 4);
     if (c.cs.hub_acc) {
-        launch_fill_u32(c.cs.hub_acc, (int64_t)HUB_SLOTS * g.n, 0, s);
-        launch_fill_u32(c.cs.hub_bits, (int64_t)HUB_SLOTS * c.cs.hub_words, 0, s);
+        z.add(c.cs.hub_acc, (int64_t)HUB_SLOTS * g.n);
+        z.add(c.cs.hub_bits, (int64_t)HUB_SLOTS * c.cs.hub_words);
     }
+    launch_zero(z, s);
 }
 
 // Host-side level size estimate (grid sizing only; any value is correct).
@@ -736,11 +735,9 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
         HIPCHK(hipStreamSynchronize(s));
         if (*hf) return KAPPA_E_GRAPH;   // an edge joins two graphs of the batch
     }
-    // every descriptor starts idle (zero): kernels of levels not built yet are no-ops
-    HIPCHK(hipMemsetAsync(c.lv, 0, (size_t)(maxl + 2) * sizeof(LevelDesc), s));
-    HIPCHK(hipMemcpyAsync(c.ctrl, &in->ctrl, sizeof(Control), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(c.lv, &in->l0, sizeof(LevelDesc), hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));   // `in` is reused below
+    // every descriptor past level 0 starts idle (zero): kernels of levels not
+    // built yet are no-ops
+    launch_init_levels(c.ctrl, c.lv, maxl + 2, in->ctrl, in->l0, s);
 
     // levels in batches; one read-back per batch
     const int32_t n0 = d0.n;
@@ -1239,9 +1236,7 @@ kappa_status match_once(const kappa_graph *g, int32_t rating, uint64_t level_see
     in->l0.mate = mate;
     in->l0.cmap = cm;
     in->l0.phase = PH_IDLE;
-    HIPCHK(hipMemsetAsync(c.lv, 0, 2 * sizeof(LevelDesc), s));
-    HIPCHK(hipMemcpyAsync(c.ctrl, &in->ctrl, sizeof(Control), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(c.lv, &in->l0, sizeof(LevelDesc), hipMemcpyHostToDevice, s));
+    launch_init_levels(c.ctrl, c.lv, 2, in->ctrl, in->l0, s);
     launch_level_match(c, 0, d.n, d.nnz, 24, false, true, s);
     LevelDesc *hl = (LevelDesc *)pinned(sizeof(LevelDesc), PIN_LEVELS);
     Control *hc = (Control *)pinned(sizeof(Control));
@@ -1332,11 +1327,7 @@ extern "C" kappa_status kappa_contract(const kappa_graph *g, const int32_t *mate
         in->l0.mate = const_cast<int32_t *>(mate);
         in->l0.cmap = cmap;
         in->l0.phase = PH_CONTRACT;
-        HIPCHK(hipMemsetAsync(c.lv, 0, 2 * sizeof(LevelDesc), s));
-        HIPCHK(hipMemcpyAsync(c.ctrl, &in->ctrl, sizeof(Control), hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(c.lv, &in->l0, sizeof(LevelDesc), hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemsetAsync(c.cs.row_cnt, 0, 4 * sizeof(int32_t), s));
-        HIPCHK(hipMemsetAsync(c.cs.totals, 0, 4 * sizeof(int64_t), s));
+        launch_init_levels(c.ctrl, c.lv, 2, in->ctrl, in->l0, s);
         launch_level_contract(c, 0, d.n, d.n, s);
         struct RB {
             Control ctrl;

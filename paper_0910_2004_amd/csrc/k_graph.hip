@@ -26,6 +26,50 @@ __global__ void fill_u64_k(uint64_t *p, int64_t n, uint64_t v) {
          i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
+// Zero up to ZERO_MAX ranges of 4-byte words in one launch.
+__global__ void zero_ranges_k(ZeroRanges z) {
+    for (int r = 0; r < z.count; ++r) {
+        uint32_t *p = z.p[r];
+        const int64_t n = z.words[r];
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+             i += (int64_t)gridDim.x * blockDim.x)
+            p[i] = 0u;
+    }
+}
+void launch_zero(const ZeroRanges &z, hipStream_t s) {
+    int64_t most = 0;
+    for (int r = 0; r < z.count; ++r) most = z.words[r] > most ? z.words[r] : most;
+    if (most <= 0) return;
+    KAPPA_PROF("fill", s);
+    hipLaunchKernelGGL(zero_ranges_k, dim3(grid_for(most, BLOCK, 4096)), dim3(BLOCK), 0, s, z);
+}
+
+// The control block and the level descriptors of a call: ctrl, lv[0] = l0,
+// lv[1 .. nlv-1] zero (idle), in one launch.
+__global__ void init_levels_k(Control *dctrl, LevelDesc *lv, int32_t nlv, Control ctrl,
+                              LevelDesc l0) {
+    constexpr int W = (int)(sizeof(LevelDesc) / 4);
+    static_assert(sizeof(LevelDesc) % 4 == 0, "descriptor words");
+    uint32_t *p = (uint32_t *)(lv + 1);
+    const int64_t words = (int64_t)(nlv - 1) * W;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+    if (blockIdx.x == 0) {
+        const uint32_t *src = (const uint32_t *)&l0;
+        uint32_t *dst = (uint32_t *)lv;
+        for (int i = threadIdx.x; i < W; i += blockDim.x) dst[i] = src[i];
+        if (threadIdx.x == 0) *dctrl = ctrl;
+    }
+}
+void launch_init_levels(Control *dctrl, LevelDesc *lv, int32_t nlv, const Control &ctrl,
+                        const LevelDesc &l0, hipStream_t s) {
+    KAPPA_PROF("init_levels", s);
+    const int64_t words = (int64_t)(nlv - 1) * (int64_t)(sizeof(LevelDesc) / 4);
+    hipLaunchKernelGGL(init_levels_k, dim3(grid_for(words, BLOCK, 64)), dim3(BLOCK), 0, s, dctrl,
+                       lv, nlv, ctrl, l0);
+}
+
 void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
     if (n <= 0) return;
     KAPPA_PROF("fill", s);
@@ -651,10 +695,12 @@ void launch_up_level(const DevGraph &g, int mode, const int32_t *cmap, int32_t n
 }
 
 void launch_up_clear(const UpAcc &a, int32_t k, hipStream_t s) {
-    launch_fill_u64(a.bw, (int64_t)BW_SHARDS * k, 0, s);
-    launch_fill_u64(a.acc, 3 * NSHARD, 0, s);
-    launch_fill_u32(a.arrive, ARRIVE_WORDS, 0, s);
-    launch_fill_u32(a.flag, 1, 0, s);
+    ZeroRanges z;
+    z.add(a.bw, (int64_t)BW_SHARDS * k * 2);
+    z.add(a.acc, 3 * NSHARD * 2);
+    z.add(a.arrive, ARRIVE_WORDS);
+    z.add(a.flag, 1);
+    launch_zero(z, s);
 }
 
 }  // namespace kappa

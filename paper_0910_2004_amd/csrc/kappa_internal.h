@@ -665,6 +665,23 @@ __device__ __forceinline__ bool arena_alloc_k(Control *c, const uint64_t (&bytes
 // Launch wrappers (host functions) per translation unit
 // ---------------------------------------------------------------------------
 // k_graph.hip
+// Up to ZERO_MAX ranges of 4-byte words zeroed by one launch.
+constexpr int ZERO_MAX = 8;
+struct ZeroRanges {
+    uint32_t *p[ZERO_MAX];
+    int64_t words[ZERO_MAX];
+    int32_t count = 0;
+    void add(void *ptr, int64_t n) {   // n 4-byte words; ignored if empty
+        if (!ptr || n <= 0) return;
+        p[count] = (uint32_t *)ptr;
+        words[count] = n;
+        ++count;
+    }
+};
+void launch_zero(const ZeroRanges &z, hipStream_t s);
+// ctrl and lv[0] = l0 written, lv[1 .. nlv-1] zeroed, in one launch.
+void launch_init_levels(Control *dctrl, LevelDesc *lv, int32_t nlv, const Control &ctrl,
+                        const LevelDesc &l0, hipStream_t s);
 void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 // Entry tiles: tile_row[t] = row holding CSR entry t * 2048.  Needs
