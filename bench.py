@@ -228,6 +228,9 @@ def main():
     ap.add_argument("--block-bits", type=int, default=None,
                     help="rgg20: match with the two-phase matcher (Section 3.3), blocks of "
                          "2^BLOCK_BITS consecutive ids (0..11); default: local-max rounds")
+    ap.add_argument("--serial-ratings", action="store_true",
+                    help="rgg20: coarsen the two ratings one after the other on one stream "
+                         "(default: concurrently, one stream and host thread per rating)")
     ap.add_argument("--order", default="generation", choices=["generation", "rcb"],
                     help="rgg20: node ids in point generation order (the headline) or in "
                          "recursive coordinate bisection order (locality of a geometric "
@@ -291,22 +294,35 @@ def main():
     log(f"generated rgg n={g.n} |E|={g.m} ({args.order} order) in {time.time() - t0:.1f}s")
     torch.cuda.set_device(0)
     dg = K.DeviceGraph.from_csr(g, "cuda:0")
-    part0 = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
+    # one stream (default priority) and one level-0 partition buffer per rating
+    streams = [torch.cuda.Stream(device="cuda:0") for _ in ratings]
+    part0s = [torch.empty(g.n, dtype=torch.int32, device="cuda:0") for _ in ratings]
     torch.cuda.synchronize()
+    from concurrent.futures import ThreadPoolExecutor
+    pool = ThreadPoolExecutor(max_workers=len(ratings))
 
-    def step():
-        # the input is validated once per step, then coarsened with each rating
+    def hierarchy(i):
+        # the whole hierarchy of rating i and the way back up, on stream i
+        with torch.cuda.stream(streams[i]):
+            H = K.kappa_coarsen(dg, ratings[i], seed, stop_n, 1, 20, 64, trusted=True,
+                                block_bits=args.block_bits)
+            _, res = K.kappa_uncoarsen(H, k, part_seed, eps[0], eps[1], part0=part0s[i])
+            out = (level_stats(H), res[0].as_tuple())
+            del H
+        return out
+
+    def step(serial=False):
+        # the input is validated once per step (synchronous), then coarsened
+        # with each rating: concurrently, one host thread and stream each
+        # (independent hierarchies of the same graph), or one after the other
         st = K.kappa_validate(dg)
         if st != K.OK:
             raise RuntimeError(f"kappa_validate: {st}")
-        stats = {}
-        for r in ratings:
-            H = K.kappa_coarsen(dg, r, seed, stop_n, 1, 20, 64, trusted=True,
-                                block_bits=args.block_bits)
-            _, res = K.kappa_uncoarsen(H, k, part_seed, eps[0], eps[1], part0=part0)
-            stats[r] = (level_stats(H), res[0].as_tuple())
-            del H
-        return stats
+        if serial or args.serial_ratings:
+            res = [hierarchy(i) for i in range(len(ratings))]
+        else:
+            res = [f.result() for f in [pool.submit(hierarchy, i) for i in range(len(ratings))]]
+        return {r: res[i] for i, r in enumerate(ratings)}
 
     for _ in range(args.warmup):
         step()
@@ -325,12 +341,13 @@ def main():
     # all levels' edges (sum over the hierarchy of |E_l|) per second
     level_edges = sum(x[1] // 2 for r in ratings for x in stats[r][0])
 
-    # second timed pass with per-launch HIP events
+    # second timed pass with per-launch HIP events, the ratings one after the
+    # other (a launch's events then bracket that launch alone)
     K.profile_reset()
     K.profile_enable(True)
     torch.cuda.synchronize()
     for _ in range(args.steps):
-        step()
+        step(serial=True)
     torch.cuda.synchronize()
     K.profile_enable(False)
     prof = K.profile_read()
@@ -401,6 +418,7 @@ def main():
                                + ("" if args.block_bits is None else
                                   f", two-phase matcher with blocks of 2^{args.block_bits}"),
                    "node_order": args.order, "block_bits": args.block_bits,
+                   "ratings_concurrent": not args.serial_ratings,
                    "n": g.n, "m": g.m, "edges_per_step": edges_step, "k": k, "stop_n": stop_n,
                    "seed": seed, "graph_seed": 2, "levels_n": levels},
         "roofline": roof,

@@ -32,7 +32,8 @@ struct ProfRec {
     hipEvent_t a, b;
 };
 struct Profiler {
-    bool on = false;
+    std::atomic<bool> on{false};
+    std::mutex mu;   // records are taken by every thread that launches
     std::vector<const char *> names;
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
@@ -75,27 +76,32 @@ Profiler g_prof;
 }  // namespace
 
 namespace kappa {
-ProfScope::ProfScope(const char *name, hipStream_t st) : id(-1), s(st) {
+ProfScope::ProfScope(const char *name, hipStream_t st) : id(-1), rec(0), s(st) {
     if (!g_prof.on) return;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
     id = g_prof.id_of(name);
     ProfRec r{id, g_prof.take(), g_prof.take()};
     (void)hipEventRecord(r.a, s);
+    rec = g_prof.recs.size();
     g_prof.recs.push_back(r);
 }
 ProfScope::~ProfScope() {
     if (id < 0) return;
-    (void)hipEventRecord(g_prof.recs.back().b, s);
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    (void)hipEventRecord(g_prof.recs[rec].b, s);
 }
 }  // namespace kappa
 
 extern "C" void kappa_profile_enable(int32_t on) { g_prof.on = on != 0; }
 extern "C" void kappa_profile_reset(void) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
     g_prof.collect();
     std::fill(g_prof.launches.begin(), g_prof.launches.end(), 0);
     std::fill(g_prof.ms.begin(), g_prof.ms.end(), 0.0);
 }
 extern "C" int32_t kappa_profile_read(const char **names, int64_t *launches, double *ms,
                                       int32_t cap) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
     g_prof.collect();
     int32_t n = (int32_t)g_prof.names.size();
     for (int32_t i = 0; i < n && i < cap; ++i) {

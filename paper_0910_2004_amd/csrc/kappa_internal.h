@@ -492,6 +492,7 @@ inline unsigned grid_for(int64_t items, int per_block, unsigned cap = 65535u * 4
 // ---------------------------------------------------------------------------
 struct ProfScope {
     int id;
+    size_t rec;   // this launch's record (launches from several threads interleave)
     hipStream_t s;
     ProfScope(const char *name, hipStream_t s);
     ~ProfScope();
