@@ -50,6 +50,11 @@ def test_null_arguments_rejected_without_gpu_work():
     assert L.kappa_match(ctypes.byref(g), 0, 1, None, None, None, None) == K.E_ARG
     g = K._lib.c_graph(0, 0, ctypes.c_void_p(8), None, None, None)
     assert L.kappa_rate(ctypes.byref(g), 7, None, None, None) == K.E_ARG
+    # two-phase matcher: block sizes outside [0, 11] and a bad graph
+    for bb in (-1, 12):
+        assert L.kappa_match_two_phase(ctypes.byref(g), 0, 1, bb, None, None, None, None) == K.E_ARG
+    g = K._lib.c_graph(4, 6, None, None, None, None)
+    assert L.kappa_match_two_phase(ctypes.byref(g), 0, 1, 4, None, None, None, None) == K.E_ARG
     L.kappa_hierarchy_free(None)
 
 
