@@ -1351,9 +1351,9 @@ __device__ __forceinline__ void wave_sync_lds() {
 template <int NT>
 __device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bid, unsigned nb) {
     constexpr int ROWS = NT / ROW_SMALL_G;
-    __shared__ uint32_t sk[ROWS][SM_CAP];
-    __shared__ uint32_t sw[ROWS][SM_CAP];
-    __shared__ uint8_t sf[ROWS][SM_CAP];
+    __shared__ uint32_t sk[ROWS][SM_CAP];   // renamed entries
+    __shared__ uint32_t sr[ROWS][SM_CAP];   // first occurrences only (others INVALID_KEY)
+    __shared__ uint32_t sw[ROWS][SM_CAP];   // weights; a first occurrence collects its duplicates'
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_CONTRACT, g)) return;
@@ -1386,27 +1386,26 @@ __device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bi
             sw[grp][t] = w;
         }
         wave_sync_lds();
+        // the first occurrence of a key leads; a later one adds its weight
+        // to it (only leaders receive, only non-leaders send)
         for (int t = sub; t < tot; t += ROW_SMALL_G) {
-            uint32_t k = sk[grp][t];
+            const uint32_t k = sk[grp][t];
             bool lead = k != INVALID_KEY;
-            for (int q = 0; q < t && lead; ++q) lead = sk[grp][q] != k;
-            sf[grp][t] = lead;
+            int q = 0;
+            for (; q < t && lead; ++q) lead = sk[grp][q] != k;
+            sr[grp][t] = lead ? k : INVALID_KEY;
+            if (!lead && k != INVALID_KEY) atomicAdd(&sw[grp][q - 1], sw[grp][t]);
         }
         wave_sync_lds();
         int nl = 0;
         for (int t = sub; t < tot; t += ROW_SMALL_G) {
-            if (!sf[grp][t]) continue;
-            uint32_t k = sk[grp][t];
-            int rank = 0;
-            uint32_t sum = 0;
-            for (int q = 0; q < tot; ++q) {
-                uint32_t kq = sk[grp][q];
-                rank += (sf[grp][q] && kq < k) ? 1 : 0;
-                sum += kq == k ? sw[grp][q] : 0u;
-            }
+            const uint32_t k = sr[grp][t];
+            if (k == INVALID_KEY) continue;
+            int rank = 0;   // distinct keys below k
+            for (int q = 0; q < tot; ++q) rank += sr[grp][q] < k ? 1 : 0;
             int64_t at = staged_at(r, rank);
             c.cs.tmp_adj[at] = (int32_t)k;
-            c.cs.tmp_ew[at] = sum;
+            c.cs.tmp_ew[at] = sw[grp][t];
             ++nl;
         }
         for (int o = ROW_SMALL_G / 2; o > 0; o >>= 1) nl += __shfl_xor(nl, o, ROW_SMALL_G);
