@@ -1,6 +1,7 @@
 """Full-size parity: the benchmark's workload (random geometric graph,
 n = 2^20, mean degree 8, unit weights, k = 64, stop at 20k nodes) through the
-same entry points and launch configuration bench.py times, compared with the
+same entry points and launch configuration bench.py times (each rating alone,
+and both at once on two streams as in the timed step), compared with the
 oracle level by level (every array, map, round count, cut and balance); the
 R-MAT of scale 22; and a sample of the 4096-graph batch."""
 import sys
@@ -30,6 +31,45 @@ def test_rgg_2_20_full_hierarchy(rating):
     H, OH = check_hierarchy(g, rating, 42, stop_n=20 * 64, k=64)
     print("levels", [lv.graph.n for lv in OH.levels], flush=True)
     sys.stdout.flush()
+
+
+@pytest.mark.timeout(600)
+def test_rgg_2_20_both_ratings_on_two_streams():
+    # the timed step itself: one validation, then both ratings' hierarchies
+    # and uncoarsenings at once, one host thread and stream each
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+    import torch
+
+    import paper_0910_2004_amd as K
+    from gpu_util import compare_hierarchy, dev
+    g = _graph()
+    ratings = [O.EXPANSION_STAR2, O.INNER_OUTER]
+    OH = {r: O.coarsen(g, r, 42, 1280, 1, 20, 64, round_stats=True) for r in ratings}
+    OP = {r: O.uncoarsen(OH[r], 64, 1, 3, 100) for r in ratings}
+    dg = dev(g)
+    assert K.kappa_validate(dg) == K.OK
+    streams = [torch.cuda.Stream() for _ in ratings]
+    part0s = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in ratings]
+    torch.cuda.synchronize()
+
+    def one(i):
+        with torch.cuda.stream(streams[i]):
+            H = K.kappa_coarsen(dg, ratings[i], 42, 1280, 1, 20, 64, trusted=True)
+            part, res = K.kappa_uncoarsen(H, 64, 1, 3, 100, part0=part0s[i])
+            torch.cuda.current_stream().synchronize()
+            return H, part.cpu().numpy(), [x.as_tuple() for x in res]
+
+    with ThreadPoolExecutor(max_workers=2) as pool:
+        got = [f.result() for f in [pool.submit(one, i) for i in range(2)]]
+    for i, r in enumerate(ratings):
+        H, part, res = got[i]
+        print(f"rating {r}: levels {len(H)}", flush=True)
+        compare_hierarchy(H, OH[r], check_rounds=True, check_uncoarsen=False)
+        oparts, ores = OP[r]
+        assert np.array_equal(part, oparts[0])
+        assert [x for x in res] == [x.as_tuple() for x in ores]
 
 
 @pytest.mark.timeout(1200)
