@@ -231,10 +231,11 @@ def main():
     ap.add_argument("--serial-ratings", action="store_true",
                     help="rgg20: coarsen the two ratings one after the other on one stream "
                          "(default: concurrently, one stream and host thread per rating)")
-    ap.add_argument("--order", default="generation", choices=["generation", "rcb"],
-                    help="rgg20: node ids in point generation order (the headline) or in "
+    ap.add_argument("--order", default="generation", choices=["generation", "rcb", "rcb-device"],
+                    help="rgg20: node ids in point generation order (the headline), in "
                          "recursive coordinate bisection order (locality of a geometric "
-                         "prepartition)")
+                         "prepartition), or renumbered so on the device before the timed "
+                         "steps (kappa_rcb_order + kappa_relabel, timed apart)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-out", default=None)
     ap.add_argument("--workload", default="rgg20", choices=["rgg20", "batch4096", "serve"],
@@ -290,10 +291,28 @@ def main():
     ratings = [K.EXPANSION_STAR2, K.INNER_OUTER]
 
     t0 = time.time()
-    g = rgg(n, seed=2, order=args.order)
+    g = rgg(n, seed=2, order="rcb" if args.order == "rcb" else "generation")
     log(f"generated rgg n={g.n} |E|={g.m} ({args.order} order) in {time.time() - t0:.1f}s")
     torch.cuda.set_device(0)
     dg = K.DeviceGraph.from_csr(g, "cuda:0")
+    relabel_ms = None
+    if args.order == "rcb-device":
+        # the points' RCB order and the renumbered graph, on the device
+        from workloads import rgg_points
+        xy = torch.from_numpy(rgg_points(n, 2)).to("cuda:0")
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            t_a = time.perf_counter()
+            order = K.kappa_rcb_order(xy, 32)
+            dr = K.kappa_relabel(dg, order)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t_a) * 1e3)
+        relabel_ms = round(min(ts), 3)
+        log(f"device relabelling: {relabel_ms} ms (best of 3)")
+        dg = dr
+        from workloads import relabel as host_relabel, rcb_order
+        g = host_relabel(g, rcb_order(rgg_points(n, 2)))   # the same graph, for the oracle
     # one stream (default priority) and one level-0 partition buffer per rating
     streams = [torch.cuda.Stream(device="cuda:0") for _ in ratings]
     part0s = [torch.empty(g.n, dtype=torch.int32, device="cuda:0") for _ in ratings]
@@ -414,10 +433,13 @@ def main():
         "config": {"workload": f"rgg n=2^{args.scale} mean degree 8, unit weights, both ratings "
                                f"(expansion*2, innerOuter), k={k}, stop n<={stop_n}, eps=3/100"
                                + ("" if args.order == "generation" else
-                                  ", node ids in recursive coordinate bisection order")
+                                  ", node ids in recursive coordinate bisection order"
+                                  + (" (renumbered on the device before the timed steps)"
+                                     if args.order == "rcb-device" else ""))
                                + ("" if args.block_bits is None else
                                   f", two-phase matcher with blocks of 2^{args.block_bits}"),
                    "node_order": args.order, "block_bits": args.block_bits,
+                   "relabel_ms": relabel_ms,
                    "ratings_concurrent": not args.serial_ratings,
                    "n": g.n, "m": g.m, "edges_per_step": edges_step, "k": k, "stop_n": stop_n,
                    "seed": seed, "graph_seed": 2, "levels_n": levels},

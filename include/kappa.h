@@ -191,6 +191,27 @@ kappa_status kappa_match_two_phase(const kappa_graph *g, int32_t rating, uint64_
                                    int32_t block_bits, int32_t *mate, int32_t *block_mate,
                                    int64_t *matched_out, kappa_stream_t stream);
 
+/* Section 3.3 (the preliminary partition from 2D coordinates): the recursive
+   coordinate bisection order of n points.  xy (device, 2n doubles, x and y
+   of point i at 2i and 2i+1).  Every box of more than `leaf` points (leaf >=
+   1) is sorted stably by x at even depths and by y at odd depths, then cut
+   after its first half (its first len/2 points, rounded down), the lower half
+   first; a box of at most `leaf` points keeps its order.  order[n] (device,
+   out): order[x] = the point at position x.  -0.0 sorts as +0.0.  Returns
+   KAPPA_E_ARG for n < 0, leaf < 1 or a missing array.  Synchronous. */
+kappa_status kappa_rcb_order(const double *xy, int32_t n, int32_t leaf, int32_t *order,
+                             kappa_stream_t stream);
+
+/* Renumbers g by an order of its nodes (for instance kappa_rcb_order's):
+   node x of `out` is node order[x] of g, with its node weight, its edges
+   renamed through the inverse and its row sorted again.  out (host struct,
+   device arrays, caller-owned, capacities cap_n >= n and cap_nnz >= nnz)
+   receives n, nnz, xadj, adj, ew and vw.  Returns KAPPA_E_ARG if order is not
+   a permutation of 0..n-1 (nothing else is written then), KAPPA_E_CAPACITY
+   if out is too small.  g must be valid.  Synchronous. */
+kappa_status kappa_relabel(const kappa_graph *g, const int32_t *order, kappa_graph_out *out,
+                           kappa_stream_t stream);
+
 /* Section 2: contracts the matching `mate` (as written by kappa_match, or any
    valid matching of g).  Coarse ids: a node is a representative if it is
    unmatched or the smaller end of its matched edge; representatives are

@@ -10,7 +10,8 @@ from ._lib import (  # noqa: F401
     EXPANSION, EXPANSION_STAR, STOP_NONE, STOP_SIZE, STOP_EMPTY, STOP_STALL, STOP_MAXLEVEL,
     OK, E_ARG, E_GRAPH, E_RANGE, E_NOMEM, E_CAPACITY, E_HIP,
     declared_functions, lib, status_str, union_csr,
-    kappa_validate, kappa_rate, kappa_match, kappa_match_two_phase, kappa_contract, kappa_coarsen, kappa_coarsen_batch, kappa_coarsen_graphs,
+    kappa_validate, kappa_rate, kappa_match, kappa_match_two_phase, kappa_rcb_order, kappa_relabel,
+    kappa_contract, kappa_coarsen, kappa_coarsen_batch, kappa_coarsen_graphs,
     kappa_initial_partition, kappa_project, kappa_cut_balance, kappa_uncoarsen, kappa_cache_release,
     graphs_enable, tail_enable, arena_first, use_torch_allocator, profile_enable, profile_reset, profile_read,
 )

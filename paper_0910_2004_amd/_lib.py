@@ -106,6 +106,8 @@ def lib():
                              ctypes.POINTER(i64), P]),
         "kappa_match_two_phase": (st, [ctypes.POINTER(c_graph), i32, u64, i32, P, P,
                                        ctypes.POINTER(i64), P]),
+        "kappa_rcb_order": (st, [P, i32, i32, P, P]),
+        "kappa_relabel": (st, [ctypes.POINTER(c_graph), P, ctypes.POINTER(c_graph_out), P]),
         "kappa_contract": (st, [ctypes.POINTER(c_graph), P, P, ctypes.POINTER(c_graph_out), P]),
         "kappa_coarsen": (st, [ctypes.POINTER(c_graph), ctypes.POINTER(c_params),
                                ctypes.POINTER(P), P]),
@@ -280,6 +282,32 @@ def kappa_match_two_phase(g: DeviceGraph, rating: int, level_seed: int, block_bi
                                        ctypes.c_uint64(level_seed & (2**64 - 1)), block_bits,
                                        _ptr(mate), _ptr(loc), ctypes.byref(matched), _stream()))
     return mate[:g.n], loc[:g.n], int(matched.value)
+
+
+def kappa_rcb_order(xy, leaf: int = 32):
+    """Recursive coordinate bisection order of the points xy (float64 device
+    tensor [n, 2]); returns order (int32 [n]), order[x] = the point at x."""
+    import torch
+    xy = xy.to(torch.float64).contiguous()
+    n = int(xy.shape[0])
+    order = torch.empty(max(n, 1), dtype=torch.int32, device=xy.device)
+    _check("kappa_rcb_order", lib().kappa_rcb_order(_ptr(xy), n, leaf, _ptr(order), _stream()))
+    return order[:n]
+
+
+def kappa_relabel(g: DeviceGraph, order) -> DeviceGraph:
+    """g renumbered: node x of the result is node order[x] of g."""
+    import torch
+    dev = g.xadj.device
+    cx = torch.empty(g.n + 1, dtype=torch.int64, device=dev)
+    ca = torch.empty(max(g.nnz, 1), dtype=torch.int32, device=dev)
+    ce = torch.empty(max(g.nnz, 1), dtype=torch.int32, device=dev)
+    cv = torch.empty(max(g.n, 1), dtype=torch.int32, device=dev)
+    order = order.to(torch.int32).contiguous()
+    out = c_graph_out(0, 0, g.n, g.nnz, cx.data_ptr(), ca.data_ptr(), ce.data_ptr(), cv.data_ptr())
+    _check("kappa_relabel", lib().kappa_relabel(ctypes.byref(g.c()), _ptr(order), ctypes.byref(out),
+                                                _stream()))
+    return DeviceGraph(g.n, g.nnz, cx, ca[:g.nnz], ce[:g.nnz], cv[:g.n])
 
 
 def kappa_contract(g: DeviceGraph, mate, cap_n: Optional[int] = None, cap_nnz: Optional[int] = None):

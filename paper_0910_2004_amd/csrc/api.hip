@@ -1278,6 +1278,45 @@ extern "C" kappa_status kappa_match_two_phase(const kappa_graph *g, int32_t rati
                       stream);
 }
 
+extern "C" kappa_status kappa_rcb_order(const double *xy, int32_t n, int32_t leaf, int32_t *order,
+                                        kappa_stream_t stream) {
+    if (n < 0 || leaf < 1 || (n > 0 && (!xy || !order))) return KAPPA_E_ARG;
+    hipStream_t s = S(stream);
+    size_t need = 0;
+    kappa_status st = rcb_order_impl(xy, n, leaf, order, s, nullptr, 0, &need);
+    if (st != KAPPA_OK) return st;
+    char *buf = nullptr;
+    std::unique_ptr<Workspace> w;
+    if (!carve_workspace(s, w, [&](Carve &cv) { buf = cv.get<char>((int64_t)need); }))
+        return KAPPA_E_NOMEM;
+    return rcb_order_impl(xy, n, leaf, order, s, buf, need, &need);
+}
+
+extern "C" kappa_status kappa_relabel(const kappa_graph *g, const int32_t *order,
+                                      kappa_graph_out *out, kappa_stream_t stream) {
+    if (!graph_args_ok(g) || !out) return KAPPA_E_ARG;
+    if (g->n > 0 && (!order || !out->vw)) return KAPPA_E_ARG;
+    if (!out->xadj || (g->nnz > 0 && (!out->adj || !out->ew))) return KAPPA_E_ARG;
+    if (out->cap_n < g->n || out->cap_nnz < g->nnz) return KAPPA_E_CAPACITY;
+    hipStream_t s = S(stream);
+    DevGraph d = dev(g);
+    size_t need = 0;
+    kappa_status st = relabel_impl(d, order, out->xadj, out->adj, out->ew, out->vw, s, nullptr, 0,
+                                   &need, nullptr);
+    if (st != KAPPA_OK) return st;
+    uint32_t *hflag = (uint32_t *)pinned(sizeof(uint32_t));
+    if (!hflag) return KAPPA_E_NOMEM;
+    char *buf = nullptr;
+    std::unique_ptr<Workspace> w;
+    if (!carve_workspace(s, w, [&](Carve &cv) { buf = cv.get<char>((int64_t)need); }))
+        return KAPPA_E_NOMEM;
+    st = relabel_impl(d, order, out->xadj, out->adj, out->ew, out->vw, s, buf, need, &need, hflag);
+    if (st != KAPPA_OK) return st;
+    out->n = g->n;
+    out->nnz = g->nnz;
+    return KAPPA_OK;
+}
+
 extern "C" kappa_status kappa_contract(const kappa_graph *g, const int32_t *mate, int32_t *cmap,
                                        kappa_graph_out *coarse, kappa_stream_t stream) {
     if (!graph_args_ok(g) || !coarse) return KAPPA_E_ARG;

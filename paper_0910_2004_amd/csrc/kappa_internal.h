@@ -775,6 +775,14 @@ void launch_batch_extract(const DevGraph &u, const int32_t *cmap, const int32_t 
 // level's compaction).  Needs st->cnt zero on entry.
 void launch_level_match(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, int rounds,
                         bool stop_rules, bool out_kernels, hipStream_t s);
+// Recursive coordinate bisection order of n points (xy interleaved, device)
+// and the relabelling of a graph by an order (k_relabel.hip).  ws == nullptr
+// asks for the workspace size only (*need).  Both synchronise the stream.
+kappa_status rcb_order_impl(const double *xy, int32_t n, int32_t leaf, int32_t *order,
+                            hipStream_t s, char *ws, size_t ws_bytes, size_t *need);
+kappa_status relabel_impl(const DevGraph &g, const int32_t *order, int64_t *nx, int32_t *nadj,
+                          uint32_t *new_ew, uint32_t *nvw, hipStream_t s, char *ws,
+                          size_t ws_bytes, size_t *need, uint32_t *hflag);
 // Contraction only (level phase PH_CONTRACT, mate set), e.g. for kappa_contract.
 void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, hipStream_t s);
 

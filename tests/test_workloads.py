@@ -80,3 +80,19 @@ def test_rcb_order_is_a_relabelling_with_locality():
     # ids of neighbours are close in rcb order, far in generation order
     gap = lambda x, s: np.abs(s - x.adj).mean()
     assert gap(h, np.repeat(np.arange(n), np.diff(h.xadj))) * 20 < gap(g, src)
+
+
+def test_relabel_reference():
+    from workloads import rcb_order, relabel, rgg_points
+    n = 1 << 13
+    pts = rgg_points(n, 4)
+    o = rcb_order(pts)
+    h = relabel(rgg(n, seed=4), o)
+    r = rgg(n, seed=4, order="rcb")
+    assert np.array_equal(h.xadj, r.xadj) and np.array_equal(h.adj, r.adj)
+    assert np.array_equal(h.ew, r.ew) and np.array_equal(h.vw, r.vw)
+    g = rmat(10, 8, seed=1, wseed=2)
+    perm = np.random.default_rng(3).permutation(g.n)
+    back = relabel(relabel(g, perm), np.argsort(perm))
+    assert np.array_equal(back.xadj, g.xadj) and np.array_equal(back.adj, g.adj)
+    assert np.array_equal(back.ew, g.ew) and np.array_equal(back.vw, g.vw)
