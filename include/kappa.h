@@ -207,8 +207,8 @@ kappa_status kappa_rcb_order(const double *xy, int32_t n, int32_t leaf, int32_t 
    renamed through the inverse and its row sorted again.  out (host struct,
    device arrays, caller-owned, capacities cap_n >= n and cap_nnz >= nnz)
    receives n, nnz, xadj, adj, ew and vw.  Returns KAPPA_E_ARG if order is not
-   a permutation of 0..n-1 (nothing else is written then), KAPPA_E_CAPACITY
-   if out is too small.  g must be valid.  Synchronous. */
+   a permutation of 0..n-1 (nothing else is written then) or nnz > 2^31 - 1,
+   KAPPA_E_CAPACITY if out is too small.  g must be valid.  Synchronous. */
 kappa_status kappa_relabel(const kappa_graph *g, const int32_t *order, kappa_graph_out *out,
                            kappa_stream_t stream);
 

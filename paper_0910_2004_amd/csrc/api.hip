@@ -1297,6 +1297,7 @@ extern "C" kappa_status kappa_relabel(const kappa_graph *g, const int32_t *order
     if (!graph_args_ok(g) || !out) return KAPPA_E_ARG;
     if (g->n > 0 && (!order || !out->vw)) return KAPPA_E_ARG;
     if (!out->xadj || (g->nnz > 0 && (!out->adj || !out->ew))) return KAPPA_E_ARG;
+    if (g->nnz > INT32_MAX) return KAPPA_E_ARG;   // the radix sorts count items in int
     if (out->cap_n < g->n || out->cap_nnz < g->nnz) return KAPPA_E_CAPACITY;
     hipStream_t s = S(stream);
     DevGraph d = dev(g);
