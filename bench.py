@@ -238,7 +238,7 @@ def main():
                          "steps (kappa_rcb_order + kappa_relabel, timed apart)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-out", default=None)
-    ap.add_argument("--workload", default="rgg20", choices=["rgg20", "batch4096", "serve"],
+    ap.add_argument("--workload", default="rgg20", choices=["rgg20", "rmat22", "batch4096", "serve"],
                     help="rgg20: the headline single-graph workload; batch4096: the batched "
                          "form on 4096 uneven graphs, against a loop of single calls; serve: "
                          "the served form on a Poisson request stream, against FIFO single calls")
@@ -289,10 +289,24 @@ def main():
     eps = (3, 100)
     seed, part_seed = 42, 1
     ratings = [K.EXPANSION_STAR2, K.INNER_OUTER]
+    rmat_mode = args.workload == "rmat22"
+    if rmat_mode:
+        # R-MAT of scale 22, edge factor 16, weights in [1, 100]; expansion*2,
+        # k = 256, stop at 5120 nodes (or on the stall rule)
+        if args.order != "generation" or args.block_bits is not None:
+            print("bench.py: --workload rmat22 has no point coordinates and runs the default "
+                  "matcher", file=sys.stderr)
+            sys.exit(2)
+        k, stop_n, ratings = 256, 5120, [K.EXPANSION_STAR2]
 
     t0 = time.time()
-    g = rgg(n, seed=2, order="rcb" if args.order == "rcb" else "generation")
-    log(f"generated rgg n={g.n} |E|={g.m} ({args.order} order) in {time.time() - t0:.1f}s")
+    if rmat_mode:
+        from workloads import rmat
+        g = rmat(22, 16, seed=3, wseed=33)
+        log(f"generated rmat scale 22 n={g.n} |E|={g.m} in {time.time() - t0:.1f}s")
+    else:
+        g = rgg(n, seed=2, order="rcb" if args.order == "rcb" else "generation")
+        log(f"generated rgg n={g.n} |E|={g.m} ({args.order} order) in {time.time() - t0:.1f}s")
     torch.cuda.set_device(0)
     dg = K.DeviceGraph.from_csr(g, "cuda:0")
     relabel_ms = None
@@ -391,7 +405,7 @@ def main():
         achieved = per_launch_bytes / avg_s / 1e9
         # the stored counters were taken on the generation-order graph
         traffic = counter_traffic(rk) if args.order == "generation" and args.block_bits is None \
-            else None
+            and not rmat_mode else None
         roof = {"bound": "hbm", "kernel": rk, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else int(traffic),
@@ -402,15 +416,23 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
+        if rmat_mode:
+            # the full scale-22 hierarchy takes the oracle minutes: the same
+            # generator at scale 18 (a sixteenth of the edges), whole hierarchy
+            from workloads import rmat
+            gs = rmat(18, 16, seed=3, wseed=33)
+            sample = f"R-MAT scale 18 (|E|={gs.m}), same generator and parameters, whole " \
+                     "hierarchy and way back up on one host thread"
+        else:
+            gs = g
+            sample = "one full step (both ratings) of the same workload on one host thread"
         t3 = time.perf_counter()
         for r in ratings:
-            OH = O.coarsen(g, r, seed, stop_n, 1, 20, 64, block_bits=args.block_bits)
+            OH = O.coarsen(gs, r, seed, stop_n, 1, 20, 64, block_bits=args.block_bits)
             O.uncoarsen(OH, k, part_seed, eps[0], eps[1])
         t4 = time.perf_counter()
-        cpu = {"value": round(edges_step / (t4 - t3), 1), "unit": "edges/s", "cores": 1,
-               "kind": "oracle",
-               "sample": "one full step (both ratings) of the same workload on one host thread; "
-                         f"{t4 - t3:.2f} s",
+        cpu = {"value": round(gs.m * len(ratings) / (t4 - t3), 1), "unit": "edges/s", "cores": 1,
+               "kind": "oracle", "sample": f"{sample}; {t4 - t3:.2f} s",
                "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
     levels = {("expansion*2" if r == 0 else "innerOuter"): [x[0] for x in lv[r]] for r in ratings}
@@ -430,7 +452,10 @@ def main():
         "vs_baseline": None,
         "dtype": "u32/u64 (exact integer; 128-bit rating compares)",
         "data": "synthetic",
-        "config": {"workload": f"rgg n=2^{args.scale} mean degree 8, unit weights, both ratings "
+        "config": {"workload": ("rmat scale 22 edge factor 16 (a, b, c) = (0.57, 0.19, 0.19), "
+                                "weights in [1, 100], expansion*2, k=256, stop n<=5120 or "
+                                "stall 1/20, eps=3/100") if rmat_mode else
+                               f"rgg n=2^{args.scale} mean degree 8, unit weights, both ratings "
                                f"(expansion*2, innerOuter), k={k}, stop n<={stop_n}, eps=3/100"
                                + ("" if args.order == "generation" else
                                   ", node ids in recursive coordinate bisection order"
@@ -442,7 +467,7 @@ def main():
                    "relabel_ms": relabel_ms,
                    "ratings_concurrent": not args.serial_ratings,
                    "n": g.n, "m": g.m, "edges_per_step": edges_step, "k": k, "stop_n": stop_n,
-                   "seed": seed, "graph_seed": 2, "levels_n": levels},
+                   "seed": seed, "graph_seed": (3, 33) if rmat_mode else 2, "levels_n": levels},
         "roofline": roof,
         "cpu_baseline": cpu,
         "kernel_ms_per_step": {name: round(ms / args.steps, 4) for name, (cnt, ms) in kern},

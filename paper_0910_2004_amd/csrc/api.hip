@@ -551,8 +551,12 @@ void carve_scratch(Carve &cv, const DevGraph &g, int rating, bool hubs, Ctx &c) 
     cs.arrive = cv.get<unsigned>(ARRIVE_WORDS);
     cs.totals = cv.get<int64_t>(4);
     cs.hub_words = (int64_t)g.n / 32 + 1;
-    cs.hub_acc = hubs ? cv.get<uint32_t>((int64_t)HUB_SLOTS * g.n) : nullptr;
-    cs.hub_bits = hubs ? cv.get<uint32_t>((int64_t)HUB_SLOTS * cs.hub_words) : nullptr;
+    // as many hub slots as the accumulator budget allows (more long rows
+    // merged at once), between HUB_SLOTS and HUB_SLOTS_MAX
+    cs.hub_slots = (int32_t)std::max<int64_t>(
+        HUB_SLOTS, std::min<int64_t>(HUB_SLOTS_MAX, HUB_BUDGET / (4 * ((int64_t)g.n + 1))));
+    cs.hub_acc = hubs ? cv.get<uint32_t>((int64_t)cs.hub_slots * g.n) : nullptr;
+    cs.hub_bits = hubs ? cv.get<uint32_t>((int64_t)cs.hub_slots * cs.hub_words) : nullptr;
     // two-phase matcher (c.block_bits set before carving)
     ms.loc = c.block_bits >= 0 ? cv.get<int32_t>(g.n) : nullptr;
     ms.lkey = c.block_bits >= 0 ? cv.get<LocKey>(g.n) : nullptr;
@@ -567,8 +571,8 @@ void fill_scratch(const DevGraph &g, const Ctx &c, hipStream_t s) {
     static_assert(sizeof(MatchState) % 4 == 0, "zeroed as words");
     z.add(c.ms.state, sizeof(MatchState) / 4);
     if (c.cs.hub_acc) {
-        z.add(c.cs.hub_acc, (int64_t)HUB_SLOTS * g.n);
-        z.add(c.cs.hub_bits, (int64_t)HUB_SLOTS * c.cs.hub_words);
+        z.add(c.cs.hub_acc, (int64_t)c.cs.hub_slots * g.n);
+        z.add(c.cs.hub_bits, (int64_t)c.cs.hub_slots * c.cs.hub_words);
     }
     launch_zero(z, s);
 }
@@ -654,6 +658,9 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     c.seed = p->seed;
     c.seed_direct = 0;
     c.block_bits = (p->flags & KAPPA_COARSEN_TWO_PHASE) ? p->block_bits : -1;
+    // rows above BIN_MID_MAX get a block each per round: many blocks when the
+    // graph has many (power-law graphs), few otherwise
+    c.big_blocks = maxdeg0 > BIN_MID_MAX ? 1024 : 64;
     const int maxl = p->max_levels;
     const int32_t count = bi ? bi->count : 0;
     uint32_t *bflag = nullptr;
@@ -756,6 +763,9 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     // If it did not take that level, the next batch runs the level in full.
     const bool tail_on = !bi && g_tail_on && c.block_bits < 0;
     int tail_end = -1;   // level at which the previous batch ended on a tail launch
+    // a level whose finisher handed it back (CF_EXTEND): the next batch
+    // starts by giving it more grid rounds after round ext_round
+    int ext_level = -1, ext_round = 0;
     Control *hc = (Control *)pinned(sizeof(Control));
     for (;;) {
         const int l_end = std::min(launched + batch, maxl + 1);
@@ -765,10 +775,15 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
                                            (uint64_t)hubs, (uint64_t)launched, (uint64_t)l_end,
                                            (uint64_t)count, (uint64_t)tail_on,
                                            (uint64_t)(int64_t)tail_end,
-                                           (uint64_t)(int64_t)c.block_bits};
+                                           (uint64_t)(int64_t)c.block_bits,
+                                           (uint64_t)(int64_t)ext_level, (uint64_t)ext_round};
         HIPCHK(run_seq(w->c, s, key, [&](hipStream_t q) {
             for (int l = launched; l < l_end; ++l) {
                 int32_t nh = n_hint_of(n0, l);
+                if (l == ext_level) {
+                    launch_level_extend(c, l, nh, n0, ext_round, true, q);
+                    continue;
+                }
                 const bool try_tail = tail_on && l >= 1 && nh <= 8 * TAIL_MAX_N;
                 if (try_tail) launch_tail(c, l, q);
                 if (try_tail && nh <= 2 * TAIL_MAX_N && l != tail_end) {
@@ -788,6 +803,19 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
         launched = next;
         HIPCHK(hipMemcpyAsync(hc, c.ctrl, sizeof(Control), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        ext_level = -1;
+        if ((hc->flags & CF_EXTEND) && !(hc->flags & ~(uint32_t)CF_EXTEND)) {
+            // resume the level on the grid; the kernels after it in this
+            // batch were no-ops (the level was still matching)
+            ext_level = hc->ext_level;
+            ext_round = hc->ext_round;
+            hc->flags &= ~(uint32_t)CF_EXTEND;
+            hc->done = 0;
+            HIPCHK(hipMemcpyAsync(c.ctrl, hc, sizeof(Control), hipMemcpyHostToDevice, s));
+            launched = ext_level;
+            batch = 4;
+            continue;
+        }
         if (hc->done || launched > maxl) break;
         batch = 4;
     }
@@ -925,7 +953,9 @@ extern "C" kappa_status kappa_coarsen(const kappa_graph *g, const kappa_coarsen_
     // (adj, ew: 8 B), three times level 0 to start with
     uint64_t lvl0 = (uint64_t)d0.n * 24 + (uint64_t)d0.nnz * 8 + 4096;
     const uint64_t forced = g_arena_first.load();
-    uint64_t arena = forced ? forced : 3 * lvl0 + (1u << 20);
+    // graphs with rows above BIN_MID_MAX entries (power-law graphs) shrink
+    // slowly: their hierarchies take five to six times level 0
+    uint64_t arena = forced ? forced : (maxdeg > BIN_MID_MAX ? 8 : 3) * lvl0 + (1u << 20);
     bool hubs = 2 * (int64_t)maxdeg - 2 > ROW_MID_MAX / 8;
     for (int attempt = 0; attempt < 6; ++attempt) {
         uint32_t retry = 0;
@@ -1246,9 +1276,18 @@ kappa_status match_once(const kappa_graph *g, int32_t rating, uint64_t level_see
     launch_level_match(c, 0, d.n, d.nnz, 24, false, true, s);
     LevelDesc *hl = (LevelDesc *)pinned(sizeof(LevelDesc), PIN_LEVELS);
     Control *hc = (Control *)pinned(sizeof(Control));
-    HIPCHK(hipMemcpyAsync(hl, c.lv, sizeof(LevelDesc), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hc, c.ctrl, sizeof(Control), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    for (;;) {
+        HIPCHK(hipMemcpyAsync(hl, c.lv, sizeof(LevelDesc), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hc, c.ctrl, sizeof(Control), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (!(hc->flags & CF_EXTEND)) break;
+        // the finisher handed the matching back: more grid rounds
+        const int r_from = hc->ext_round;
+        hc->flags &= ~(uint32_t)CF_EXTEND;
+        hc->done = 0;
+        HIPCHK(hipMemcpyAsync(c.ctrl, hc, sizeof(Control), hipMemcpyHostToDevice, s));
+        launch_level_extend(c, 0, d.n, d.n, r_from, false, s);
+    }
     if (hc->flags & (CF_ROUNDS | CF_STATE)) {
         if (debug_on()) fprintf(stderr, "kappa: match control flags 0x%x\n", hc->flags);
         return KAPPA_E_HIP;

@@ -40,6 +40,7 @@
 //      allocates the next level's edge arrays and checks the stall rule
 //   4. compact: copy merged rows into the exact-size coarse arrays
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 
@@ -752,6 +753,22 @@ __global__ void __launch_bounds__(FINISH_THREADS) finish_k(Ctx c, int l, int r_l
             s_cnt[(r0 + 1) & 1][threadIdx.x] = 0;
         }
         __syncthreads();
+        // the launched grid rounds ran out with many nodes pending (graphs
+        // whose matching needs more rounds than the host planned, such as
+        // power-law graphs): one workgroup would crawl through them, so the
+        // level goes back to the host for more grid rounds.  The level stays
+        // in PH_MATCH; `done` ends this batch of levels.
+        const int32_t pend = s_cnt[r0 & 1][0] + s_cnt[r0 & 1][1] + s_cnt[r0 & 1][2];
+        if (F == 0 && st->handoff == -1 && r0 == r_last &&
+            (pend > FINISH_MAX || s_cnt[r0 & 1][2] > FINISH_MAX_BIG)) {
+            if (threadIdx.x == 0) {
+                c.ctrl->ext_level = l;
+                c.ctrl->ext_round = r_last;
+                c.ctrl->flags |= CF_EXTEND;
+                c.ctrl->done = 1;
+            }
+            return;
+        }
         capped = wg_rounds<R, FINISH_THREADS, F>(c, g, L, seed, r0, s_cnt, shc, sh, sbase);
     }
     // r0 = -2: the round kernels found nothing left, so they ran every round
@@ -1490,7 +1507,7 @@ __global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l) {
 }
 
 // --- 2c. large rows: dense accumulator per slot --------------------------------------
-// Slot `bid` of the hub accumulators (bid < HUB_SLOTS).
+// Slot `bid` of the hub accumulators (bid < hub_slots).
 template <int NT>
 __device__ __forceinline__ void fill_large_body(const Ctx &c, int l, unsigned bid, unsigned nb) {
     __shared__ int64_t s_wcnt[NT / WAVE + 1];
@@ -1920,7 +1937,7 @@ static void match_impl(const Ctx &c, int l, int32_t n_hint, int rounds, hipStrea
         PickGrid pg;
         pg.b0 = grid_for(e, BLOCK / SMALL_G, 2048);
         pg.b1 = grid_for(e, BLOCK / WAVE * 8, 128);
-        pg.b2 = grid_for(e, 4096, 64);
+        pg.b2 = grid_for(e, 4096, (unsigned)c.big_blocks);
         const unsigned pick_blocks = pg.b0 + pg.b1 + pg.b2;
         const unsigned mate_blocks = grid_for(e, BLOCK, 2048);
         if (r == 1) {
@@ -1965,7 +1982,7 @@ static void two_phase_impl(const Ctx &c, int l, int32_t n_hint, hipStream_t s) {
         PickGrid pg;
         pg.b0 = grid_for(e, BLOCK / SMALL_G, 2048);
         pg.b1 = grid_for(e, BLOCK / WAVE * 8, 128);
-        pg.b2 = grid_for(e, 4096, 64);
+        pg.b2 = grid_for(e, 4096, (unsigned)c.big_blocks);
         {
             KAPPA_PROF("gap_pick", s);
             hipLaunchKernelGGL((pick_k<R, false, 1>), dim3(pg.b0 + pg.b1 + pg.b2), dim3(BLOCK), 0, s,
@@ -1985,6 +2002,45 @@ static void two_phase_impl(const Ctx &c, int l, int32_t n_hint, hipStream_t s) {
     }
     KAPPA_PROF("merge_close", s);
     hipLaunchKernelGGL(merge_close_k, dim3(1), dim3(WAVE), 0, s, c, l);
+}
+
+// More grid rounds for a level the finisher handed back (CF_EXTEND): rounds
+// r_from+1 .. r_from+count, the finisher, then the level's contraction (and,
+// batched, its end).
+template <int R>
+static void extend_impl(const Ctx &c, int l, int32_t n_hint, int r_from, int count, hipStream_t s) {
+    double est = n_hint * std::pow(0.7, r_from);
+    for (int r = r_from + 1; r <= r_from + count; ++r, est *= 0.7) {
+        int64_t e = (int64_t)est + 1;
+        PickGrid pg;
+        pg.b0 = grid_for(e, BLOCK / SMALL_G, 2048);
+        pg.b1 = grid_for(e, BLOCK / WAVE * 8, 128);
+        pg.b2 = grid_for(e, 4096, (unsigned)c.big_blocks);
+        {
+            KAPPA_PROF("pick", s);
+            hipLaunchKernelGGL((pick_k<R, false>), dim3(pg.b0 + pg.b1 + pg.b2), dim3(BLOCK), 0, s, c,
+                               l, r, pg);
+        }
+        KAPPA_PROF("mate", s);
+        hipLaunchKernelGGL((mate_k<R, false>), dim3(grid_for(e, BLOCK, 2048)), dim3(BLOCK), 0, s, c,
+                           l, r);
+    }
+    KAPPA_PROF("match_finish", s);
+    hipLaunchKernelGGL(finish_k<R>, dim3(1), dim3(FINISH_THREADS), 0, s, c, l, r_from + count);
+}
+
+void launch_level_extend(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, int r_from,
+                         bool contract, hipStream_t s) {
+    switch (c.rating) {
+    case KAPPA_INNER_OUTER: extend_impl<KAPPA_INNER_OUTER>(c, l, n_hint, r_from, EXTEND_ROUNDS, s); break;
+    case KAPPA_WEIGHT: extend_impl<KAPPA_WEIGHT>(c, l, n_hint, r_from, EXTEND_ROUNDS, s); break;
+    case KAPPA_EXPANSION: extend_impl<KAPPA_EXPANSION>(c, l, n_hint, r_from, EXTEND_ROUNDS, s); break;
+    case KAPPA_EXPANSION_STAR: extend_impl<KAPPA_EXPANSION_STAR>(c, l, n_hint, r_from, EXTEND_ROUNDS, s); break;
+    default: extend_impl<KAPPA_EXPANSION_STAR2>(c, l, n_hint, r_from, EXTEND_ROUNDS, s); break;
+    }
+    if (!contract) return;
+    launch_level_contract(c, l, n_hint, n_cap, s);
+    if (c.b.count) launch_batch_end(c, l, s);
 }
 
 void launch_level_match(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, int rounds,
@@ -2030,7 +2086,7 @@ void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, h
     }
     if (c.cs.hub_acc) {
         KAPPA_PROF("fill_large", s);
-        hipLaunchKernelGGL(fill_large_k, dim3(HUB_SLOTS), dim3(BLOCK), 0, s, c, l);
+        hipLaunchKernelGGL(fill_large_k, dim3(c.cs.hub_slots), dim3(BLOCK), 0, s, c, l);
     }
     launch_scan((int64_t)n_hint + 1, DegF{c, l}, CoarseOffW{c, l}, c.cs.partials, c.cs.arrive,
                 c.cs.totals + 2, s);

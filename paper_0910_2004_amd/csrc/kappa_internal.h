@@ -22,6 +22,12 @@ constexpr int SMALL_G = 4;
 // Matching rounds: a single workgroup finishes once at most TAIL_MAX nodes
 // still point somewhere.
 constexpr int TAIL_MAX = 128;
+// The finisher takes a level whose launched grid rounds ran out only while at
+// most FINISH_MAX nodes (and FINISH_MAX_BIG of degree above BIN_MID_MAX) are
+// pending; otherwise it hands the level back for more grid rounds.
+constexpr int FINISH_MAX = 4096;
+constexpr int FINISH_MAX_BIG = 64;
+constexpr int EXTEND_ROUNDS = 8;
 constexpr int BM_BITS_MAX = 11;     // two-phase matcher: blocks of at most 2^11 nodes
 constexpr int BM_THREADS = 512;     //   matched by one workgroup each
 constexpr int FINISH_THREADS = 1024;
@@ -37,7 +43,9 @@ constexpr int MAX_LEVELS = 256;
 constexpr int ROW_SMALL_MAX = 64;   // 16 lanes per row, rank sort in LDS
 constexpr int ROW_SMALL_G = 16;
 constexpr int ROW_MID_MAX = 4094;   // one block per row, bitonic sort of <= 4096 in LDS
-constexpr int HUB_SLOTS = 32;       // rows above ROW_MID_MAX: dense accumulators
+constexpr int HUB_SLOTS = 32;       // rows above ROW_MID_MAX: dense accumulators (at least)
+constexpr int HUB_SLOTS_MAX = 256;  //   and at most, within HUB_BUDGET bytes of accumulators
+constexpr int64_t HUB_BUDGET = (int64_t)4 << 30;
 
 // Device-scope atomics on one address from many blocks serialise where the
 // XCDs meet (about 10 ns each), so kernel-wide accumulators are split over
@@ -554,13 +562,15 @@ enum ControlFlags : uint32_t {
     CF_HUBS = 2u,       // a coarse row needs the hub accumulators, which are not allocated
     CF_ROUNDS = 4u,     // round cap hit (cannot happen on valid state)
     CF_STATE = 8u,      // a list held a node id out of range (cannot happen on valid state)
+    CF_EXTEND = 16u,    // level ext_level needs grid rounds after ext_round (the host resumes it)
 };
 
 struct Control {
     int32_t done;       // no further level starts
     int32_t nlevels;    // levels built (level nlevels-1 is the coarsest so far)
     uint32_t flags;
-    int32_t pad;
+    int32_t ext_level;  // CF_EXTEND: the level whose matching continues on the host's
+    int32_t ext_round;  //   next launch, and the last round it ran
     uint64_t cursor, cap;   // arena bytes used / available
     char *base;
     int32_t stop_n, max_levels;
@@ -605,9 +615,10 @@ struct ContractScratch {
     int64_t *partials;    // scan workspace: tile sums
     unsigned *arrive;     // ARRIVE_WORDS arrival counters of the scans (zero between uses)
     int64_t *totals;      // [0] n', [1] unused, [2] nnz', [3] unused
-    uint32_t *hub_acc;    // HUB_SLOTS * n, zero between uses (may be null)
-    uint32_t *hub_bits;   // HUB_SLOTS * hub_words, zero between uses
+    uint32_t *hub_acc;    // hub_slots * n, zero between uses (may be null)
+    uint32_t *hub_bits;   // hub_slots * hub_words, zero between uses
     int64_t hub_words;
+    int32_t hub_slots;    // rows merged at once in the hub accumulators
 };
 
 // Batched form: per-graph stop rules on a disjoint union of `count` graphs.
@@ -633,6 +644,7 @@ struct Ctx {
     ContractScratch cs;
     BatchCtx b;
     int32_t block_bits = -1;   // >= 0: two-phase matcher with blocks of 2^block_bits ids
+    int32_t big_blocks = 64;   // blocks per round launch for rows above BIN_MID_MAX entries
 };
 
 // K bump allocations in the arena with one read and one write of the cursor
@@ -783,6 +795,10 @@ kappa_status rcb_order_impl(const double *xy, int32_t n, int32_t leaf, int32_t *
 kappa_status relabel_impl(const DevGraph &g, const int32_t *order, int64_t *nx, int32_t *nadj,
                           uint32_t *new_ew, uint32_t *nvw, hipStream_t s, char *ws,
                           size_t ws_bytes, size_t *need, uint32_t *hflag);
+// The rest of a level the finisher handed back (CF_EXTEND after round
+// r_from): more grid rounds, the finisher and, if `contract`, the contraction.
+void launch_level_extend(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, int r_from,
+                         bool contract, hipStream_t s);
 // Contraction only (level phase PH_CONTRACT, mate set), e.g. for kappa_contract.
 void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, hipStream_t s);
 
