@@ -765,7 +765,10 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     int tail_end = -1;   // level at which the previous batch ended on a tail launch
     // a level whose finisher handed it back (CF_EXTEND): the next batch
     // starts by giving it more grid rounds after round ext_round
-    int ext_level = -1, ext_round = 0;
+    int ext_level = -1, ext_round = 0, ext_times = 0, ext_seen = -1;
+    // power-law graphs hand levels back: small batches keep the levels
+    // launched behind a handed-back one (no-ops then) few
+    if (c.big_blocks > 64) batch = std::min(batch, 2);
     Control *hc = (Control *)pinned(sizeof(Control));
     for (;;) {
         const int l_end = std::min(launched + batch, maxl + 1);
@@ -781,7 +784,8 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
             for (int l = launched; l < l_end; ++l) {
                 int32_t nh = n_hint_of(n0, l);
                 if (l == ext_level) {
-                    launch_level_extend(c, l, nh, n0, ext_round, true, q);
+                    launch_level_extend(c, l, nh, n0, ext_round,
+                                        EXTEND_ROUNDS << std::min(ext_times, 3), true, q);
                     continue;
                 }
                 const bool try_tail = tail_on && l >= 1 && nh <= 8 * TAIL_MAX_N;
@@ -809,15 +813,17 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
             // batch were no-ops (the level was still matching)
             ext_level = hc->ext_level;
             ext_round = hc->ext_round;
+            ext_times = ext_level == ext_seen ? ext_times + 1 : 0;
+            ext_seen = ext_level;
             hc->flags &= ~(uint32_t)CF_EXTEND;
             hc->done = 0;
             HIPCHK(hipMemcpyAsync(c.ctrl, hc, sizeof(Control), hipMemcpyHostToDevice, s));
             launched = ext_level;
-            batch = 4;
+            batch = 1;   // the resumed level alone: it may be handed back again
             continue;
         }
         if (hc->done || launched > maxl) break;
-        batch = 4;
+        batch = c.big_blocks > 64 ? 2 : 4;
     }
     if (hc->flags && debug_on())
         fprintf(stderr, "kappa: coarsen control flags 0x%x (levels %d)\n", hc->flags, hc->nlevels);
@@ -1286,7 +1292,7 @@ kappa_status match_once(const kappa_graph *g, int32_t rating, uint64_t level_see
         hc->flags &= ~(uint32_t)CF_EXTEND;
         hc->done = 0;
         HIPCHK(hipMemcpyAsync(c.ctrl, hc, sizeof(Control), hipMemcpyHostToDevice, s));
-        launch_level_extend(c, 0, d.n, d.n, r_from, false, s);
+        launch_level_extend(c, 0, d.n, d.n, r_from, EXTEND_ROUNDS, false, s);
     }
     if (hc->flags & (CF_ROUNDS | CF_STATE)) {
         if (debug_on()) fprintf(stderr, "kappa: match control flags 0x%x\n", hc->flags);

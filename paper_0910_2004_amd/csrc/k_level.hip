@@ -1936,8 +1936,8 @@ static void match_impl(const Ctx &c, int l, int32_t n_hint, int rounds, hipStrea
         int64_t e = (int64_t)est + 1;
         PickGrid pg;
         pg.b0 = grid_for(e, BLOCK / SMALL_G, 2048);
-        pg.b1 = grid_for(e, BLOCK / WAVE * 8, 128);
-        pg.b2 = grid_for(e, 4096, (unsigned)c.big_blocks);
+        pg.b1 = c.big_blocks > 64 ? (unsigned)c.big_blocks : grid_for(e, BLOCK / WAVE * 8, 128);
+        pg.b2 = c.big_blocks > 64 ? (unsigned)c.big_blocks : grid_for(e, 4096, 64);
         const unsigned pick_blocks = pg.b0 + pg.b1 + pg.b2;
         const unsigned mate_blocks = grid_for(e, BLOCK, 2048);
         if (r == 1) {
@@ -1981,8 +1981,8 @@ static void two_phase_impl(const Ctx &c, int l, int32_t n_hint, hipStream_t s) {
         int64_t e = (int64_t)est + 1;
         PickGrid pg;
         pg.b0 = grid_for(e, BLOCK / SMALL_G, 2048);
-        pg.b1 = grid_for(e, BLOCK / WAVE * 8, 128);
-        pg.b2 = grid_for(e, 4096, (unsigned)c.big_blocks);
+        pg.b1 = c.big_blocks > 64 ? (unsigned)c.big_blocks : grid_for(e, BLOCK / WAVE * 8, 128);
+        pg.b2 = c.big_blocks > 64 ? (unsigned)c.big_blocks : grid_for(e, 4096, 64);
         {
             KAPPA_PROF("gap_pick", s);
             hipLaunchKernelGGL((pick_k<R, false, 1>), dim3(pg.b0 + pg.b1 + pg.b2), dim3(BLOCK), 0, s,
@@ -2014,8 +2014,8 @@ static void extend_impl(const Ctx &c, int l, int32_t n_hint, int r_from, int cou
         int64_t e = (int64_t)est + 1;
         PickGrid pg;
         pg.b0 = grid_for(e, BLOCK / SMALL_G, 2048);
-        pg.b1 = grid_for(e, BLOCK / WAVE * 8, 128);
-        pg.b2 = grid_for(e, 4096, (unsigned)c.big_blocks);
+        pg.b1 = c.big_blocks > 64 ? (unsigned)c.big_blocks : grid_for(e, BLOCK / WAVE * 8, 128);
+        pg.b2 = c.big_blocks > 64 ? (unsigned)c.big_blocks : grid_for(e, 4096, 64);
         {
             KAPPA_PROF("pick", s);
             hipLaunchKernelGGL((pick_k<R, false>), dim3(pg.b0 + pg.b1 + pg.b2), dim3(BLOCK), 0, s, c,
@@ -2030,13 +2030,13 @@ static void extend_impl(const Ctx &c, int l, int32_t n_hint, int r_from, int cou
 }
 
 void launch_level_extend(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, int r_from,
-                         bool contract, hipStream_t s) {
+                         int count, bool contract, hipStream_t s) {
     switch (c.rating) {
-    case KAPPA_INNER_OUTER: extend_impl<KAPPA_INNER_OUTER>(c, l, n_hint, r_from, EXTEND_ROUNDS, s); break;
-    case KAPPA_WEIGHT: extend_impl<KAPPA_WEIGHT>(c, l, n_hint, r_from, EXTEND_ROUNDS, s); break;
-    case KAPPA_EXPANSION: extend_impl<KAPPA_EXPANSION>(c, l, n_hint, r_from, EXTEND_ROUNDS, s); break;
-    case KAPPA_EXPANSION_STAR: extend_impl<KAPPA_EXPANSION_STAR>(c, l, n_hint, r_from, EXTEND_ROUNDS, s); break;
-    default: extend_impl<KAPPA_EXPANSION_STAR2>(c, l, n_hint, r_from, EXTEND_ROUNDS, s); break;
+    case KAPPA_INNER_OUTER: extend_impl<KAPPA_INNER_OUTER>(c, l, n_hint, r_from, count, s); break;
+    case KAPPA_WEIGHT: extend_impl<KAPPA_WEIGHT>(c, l, n_hint, r_from, count, s); break;
+    case KAPPA_EXPANSION: extend_impl<KAPPA_EXPANSION>(c, l, n_hint, r_from, count, s); break;
+    case KAPPA_EXPANSION_STAR: extend_impl<KAPPA_EXPANSION_STAR>(c, l, n_hint, r_from, count, s); break;
+    default: extend_impl<KAPPA_EXPANSION_STAR2>(c, l, n_hint, r_from, count, s); break;
     }
     if (!contract) return;
     launch_level_contract(c, l, n_hint, n_cap, s);

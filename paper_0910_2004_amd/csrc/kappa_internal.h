@@ -27,7 +27,7 @@ constexpr int TAIL_MAX = 128;
 // pending; otherwise it hands the level back for more grid rounds.
 constexpr int FINISH_MAX = 4096;
 constexpr int FINISH_MAX_BIG = 64;
-constexpr int EXTEND_ROUNDS = 8;
+constexpr int EXTEND_ROUNDS = 8;   // doubled on every further hand-back of a level, up to 64
 constexpr int BM_BITS_MAX = 11;     // two-phase matcher: blocks of at most 2^11 nodes
 constexpr int BM_THREADS = 512;     //   matched by one workgroup each
 constexpr int FINISH_THREADS = 1024;
@@ -796,9 +796,10 @@ kappa_status relabel_impl(const DevGraph &g, const int32_t *order, int64_t *nx, 
                           uint32_t *new_ew, uint32_t *nvw, hipStream_t s, char *ws,
                           size_t ws_bytes, size_t *need, uint32_t *hflag);
 // The rest of a level the finisher handed back (CF_EXTEND after round
-// r_from): more grid rounds, the finisher and, if `contract`, the contraction.
+// r_from): `count` more grid rounds, the finisher and, if `contract`, the
+// contraction.
 void launch_level_extend(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, int r_from,
-                         bool contract, hipStream_t s);
+                         int count, bool contract, hipStream_t s);
 // Contraction only (level phase PH_CONTRACT, mate set), e.g. for kappa_contract.
 void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, hipStream_t s);
 
