@@ -75,6 +75,16 @@ def lib():
         L.orc_cut_balance.restype = ctypes.c_int
         L.orc_greedy_certificate.argtypes = [i32, P, P, P, P, ctypes.c_int, u64, P]
         L.orc_greedy_certificate.restype = i64
+        L.orc_quotient_colouring.argtypes = [i32, P, P, P, i32, P, P, P, P]
+        L.orc_quotient_colouring.restype = i32
+        L.orc_fm_pair.argtypes = [i32, P, P, P, P, P, i32, i32, i32, u32, u32, u64, u32, u32, i32,
+                                  P, P]
+        L.orc_fm_pair.restype = ctypes.c_int
+        L.orc_run_seed.argtypes = [u64, i32, i32, i32, i32, i32]
+        L.orc_run_seed.restype = u64
+        L.orc_refine.argtypes = [i32, P, P, P, P, P, i32, u32, u32, u64, u32, u32, i32, i32, i32,
+                                 i32, P]
+        L.orc_refine.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -371,3 +381,99 @@ def uncoarsen(H: Hierarchy, k: int, part_seed: int = 1, eps_num: int = 3, eps_de
         parts[l] = project(H.levels[l].cmap, parts[l + 1])
         res[l] = cut_balance(H.levels[l].graph, parts[l], k, eps_num, eps_den)
     return parts, res
+
+
+# ---------------------------------------------------------------------------
+# Pairwise refinement (Section 5); the readings are listed in kappa_oracle.c.
+# ---------------------------------------------------------------------------
+
+@dataclass
+class RefineParams:
+    """Parameters of the refinement (Table 2 names the presets)."""
+    seed: int = 1
+    alpha_num: int = 5          # FM patience alpha = alpha_num / alpha_den
+    alpha_den: int = 100
+    depth: int = 5              # BFS search depth
+    max_local: int = 3          # local iterations
+    max_global: int = 15        # max. global iterations
+    stop_after: int = 1         # global iterations in a row without change that end it
+
+    @staticmethod
+    def preset(name: str) -> "RefineParams":
+        """Table 2: minimal, fast, strong."""
+        return {"minimal": RefineParams(alpha_num=1, depth=1, max_local=1, max_global=1),
+                "fast": RefineParams(),
+                "strong": RefineParams(alpha_num=20, depth=20, max_local=5, stop_after=2)}[name]
+
+
+def quotient_colouring(g, part: np.ndarray, k: int):
+    """Q's edges (a < b, ascending) with their greedy colours; returns
+    (pairs int32[m, 2], colour int32[m], number of colours)."""
+    g = Graph.of(g)
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    cap = k * k // 2 + 1
+    pa, pb, pc = (np.zeros(cap, np.int32) for _ in range(3))
+    m = ctypes.c_int32(0)
+    nc = lib().orc_quotient_colouring(g.n, _p(g.xadj), _p(g.adj), _p(part), k, _p(pa), _p(pb),
+                                      _p(pc), ctypes.byref(m))
+    m = m.value
+    return np.stack([pa[:m], pb[:m]], 1), pc[:m].copy(), int(nc)
+
+
+def run_seed(seed: int, g: int, a: int, b: int, t: int, r: int) -> int:
+    return int(lib().orc_run_seed(ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), g, a, b, t, r))
+
+
+def fm_pair(g, part: np.ndarray, k: int, a: int, b: int, run_seed_: int, alpha_num: int = 5,
+            alpha_den: int = 100, depth: int = 5, eps_num: int = 3, eps_den: int = 100):
+    """One two-block local search (Section 5.2) on blocks a < b.  Returns
+    (moves int32[made], dict) with the start/end (imbalance, cut) and the
+    number of moves kept after the rollback; part is not changed."""
+    g = Graph.of(g)
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    moves = np.zeros(max(g.n, 1), np.int32)
+    res = np.zeros(6, np.int64)
+    st = lib().orc_fm_pair(g.n, _p(g.xadj), _p(g.adj), _p(g.ew), _p(g.vw), _p(part), k, a, b,
+                           eps_num, eps_den, ctypes.c_uint64(run_seed_), alpha_num, alpha_den,
+                           depth, _p(moves), _p(res))
+    if st != OK:
+        raise ValueError(f"oracle fm_pair failed: {st}")
+    r = [int(x) for x in res]
+    return moves[:r[4]].copy(), {"start": (r[0], r[1]), "end": (r[2], r[3]), "made": r[4],
+                                 "kept": r[5]}
+
+
+def refine(g, part: np.ndarray, k: int, eps_num: int = 3, eps_den: int = 100,
+           params: Optional[RefineParams] = None):
+    """Pairwise refinement of one level (Section 5).  Returns (new part,
+    stats dict); the input array is not changed."""
+    p = params or RefineParams()
+    g = Graph.of(g)
+    out = np.array(part, dtype=np.int32, copy=True)
+    st = np.zeros(6, np.int64)
+    rc = lib().orc_refine(g.n, _p(g.xadj), _p(g.adj), _p(g.ew), _p(g.vw), _p(out), k, eps_num,
+                          eps_den, ctypes.c_uint64(p.seed), p.alpha_num, p.alpha_den, p.depth,
+                          p.max_local, p.max_global, p.stop_after, _p(st))
+    if rc != OK:
+        raise ValueError(f"oracle refine failed: {rc}")
+    keys = ("global_iterations", "searches", "moves", "kept", "adoptions", "colours")
+    return out, dict(zip(keys, (int(x) for x in st)))
+
+
+def uncoarsen_refined(H: Hierarchy, k: int, part_seed: int = 1, eps_num: int = 3,
+                      eps_den: int = 100, params: Optional[RefineParams] = None):
+    """The way back up with refinement: coarsest partition (stand-in), then
+    per level from the coarsest down: project, refine, cut/balance.  The
+    refinement seed of level l is mix64(params.seed + l).  Returns (parts,
+    results, stats) per level."""
+    p = params or RefineParams()
+    L = len(H.levels) - 1
+    parts, res, stats = [None] * (L + 1), [None] * (L + 1), [None] * (L + 1)
+    for l in range(L, -1, -1):
+        g = H.levels[l].graph
+        start = (initial_partition(g.n, k, part_seed) if l == L
+                 else project(H.levels[l].cmap, parts[l + 1]))
+        pl = RefineParams(**{**p.__dict__, "seed": level_seed(p.seed, l)})
+        parts[l], stats[l] = refine(g, start, k, eps_num, eps_den, pl)
+        res[l] = cut_balance(g, parts[l], k, eps_num, eps_den)
+    return parts, res, stats

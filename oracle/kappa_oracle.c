@@ -1,7 +1,8 @@
 /*
  * kappa_oracle.c -- sequential CPU oracle for the coarsening hierarchy of the
  * multilevel partitioner in "Engineering a Scalable High Quality Graph
- * Partitioner" (Holtgrewe, Sanders, Schulz).
+ * Partitioner" (Holtgrewe, Sanders, Schulz), and for the pairwise refinement
+ * of its uncoarsening phase (Section 5).
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library includes, links or
  * calls this file; only the test suite, the smoke check and the CPU baseline of
@@ -559,4 +560,324 @@ int64_t orc_greedy_certificate(int32_t n, const int64_t *xadj, const int32_t *ad
     free(mw);
     free(out);
     return bad;
+}
+
+/* ======================================================================== */
+/* Refinement between pairs of blocks (Section 5).                          */
+/*                                                                          */
+/* Readings (the paper leaves these open; the GPU library follows the same  */
+/* readings, written down in the design notes):                            */
+/*   - Q has an edge {a, b} (a < b) iff some edge of G joins blocks a and b.  */
+/*     Q's edges are coloured by the sequential greedy edge colouring that  */
+/*     Section 5.1 parallelises: edges in ascending (a, b) order, each     */
+/*     taking the smallest colour unused at both ends.  Pairs of one colour */
+/*     share no block, so their local searches are independent.             */
+/*   - gain(v) = w(v, other block) - w(v, own block), counting only the    */
+/*     neighbours inside the two blocks (Section 5.2).                      */
+/*   - the queue order is: larger gain, then larger mix64(run_seed ^ v),    */
+/*     then smaller v (the paper breaks ties at random).                    */
+/*   - the search area is the bounded BFS of Section 5.2: inside each block,*/
+/*     the nodes within `depth` same-block hops of a node adjacent to the   */
+/*     other block.  Queues start with the boundary nodes (distance 0); a  */
+/*     node of the area enters its queue when a neighbour moves.             */
+/*   - queue selection TopGain: the larger top under the queue order; when  */
+/*     one block is overloaded (c > L_max) and the weights differ, MaxLoad: */
+/*     the heavier block gives (the other queue if the heavier one is      */
+/*     empty).  Moves are never refused; the rollback keeps balance.        */
+/*   - the search stops when both queues are empty or when more than        */
+/*     alpha * min(|A|, |B|) moves (node counts at the start) followed the  */
+/*     last improvement; it is rolled back to the first state with the      */
+/*     lexicographically smallest (imbalance, cut), where imbalance =      */
+/*     max(0, c(A) - L_max, c(B) - L_max), scaled by k * eps_den.           */
+/*   - each local search runs twice, with run seeds r = 0 and 1 (the two    */
+/*     PEs of Section 5); the better end state is adopted (r = 0 on a tie). */
+/*     A pair repeats local searches (local iterations) until one brings   */
+/*     no strict improvement or max_local were run; a global iteration     */
+/*     walks all colours in ascending order; global iterations repeat until */
+/*     stop_after of them in a row improved nothing (Table 2: "no change"  */
+/*     is 1, "2x no change" is 2) or max_global were run.                   */
+/*   - run seed = mix64(mix64(mix64(seed + g) ^ ((a << 32) | b)) + 2 t + r) */
+/*     for global iteration g, pair (a, b), local iteration t, run r.       */
+/* ======================================================================== */
+
+/* Q and its greedy edge colouring.  Writes the pairs in ascending (a, b)
+   order with their colours; returns the number of colours (at most 2k - 3
+   for k >= 2: greedy needs at most 2 * maxdeg(Q) - 1). */
+int32_t orc_quotient_colouring(int32_t n, const int64_t *xadj, const int32_t *adj,
+                               const int32_t *part, int32_t k, int32_t *pair_a,
+                               int32_t *pair_b, int32_t *colour, int32_t *npairs)
+{
+    uint8_t *q = (uint8_t *)calloc((size_t)k * k, 1);
+    for (int32_t v = 0; v < n; ++v)
+        for (int64_t j = xadj[v]; j < xadj[v + 1]; ++j) {
+            int32_t a = part[v], b = part[adj[j]];
+            if (a < b) q[(size_t)a * k + b] = 1;
+        }
+    int32_t ncol_cap = 2 * k;
+    uint8_t *used = (uint8_t *)calloc((size_t)k * ncol_cap, 1);
+    int32_t m = 0, ncol = 0;
+    for (int32_t a = 0; a < k; ++a)
+        for (int32_t b = a + 1; b < k; ++b) {
+            if (!q[(size_t)a * k + b]) continue;
+            int32_t c = 0;
+            while (used[(size_t)a * ncol_cap + c] || used[(size_t)b * ncol_cap + c]) ++c;
+            used[(size_t)a * ncol_cap + c] = used[(size_t)b * ncol_cap + c] = 1;
+            pair_a[m] = a;
+            pair_b[m] = b;
+            colour[m] = c;
+            ++m;
+            if (c + 1 > ncol) ncol = c + 1;
+        }
+    free(used);
+    free(q);
+    *npairs = m;
+    return ncol;
+}
+
+/* (imbalance, cut) order: is (i1, c1) strictly below (i2, c2)? */
+static int state_below(int64_t i1, int64_t c1, int64_t i2, int64_t c2)
+{
+    return i1 < i2 || (i1 == i2 && c1 < c2);
+}
+
+/* scaled imbalance of a pair: max(0, S c(A) - L, S c(B) - L) with
+   S = k eps_den and L = (eps_den + eps_num) c(V) + S max_v c(v) */
+static int64_t pair_imbalance(int64_t wa, int64_t wb, int64_t s, int64_t l)
+{
+    int64_t x = s * (wa > wb ? wa : wb) - l;
+    return x > 0 ? x : 0;
+}
+
+/* is queue entry (g1, h1, v1) above (g2, h2, v2)? */
+static int entry_above(int64_t g1, uint64_t h1, int32_t v1, int64_t g2, uint64_t h2, int32_t v2)
+{
+    if (g1 != g2) return g1 > g2;
+    if (h1 != h2) return h1 > h2;
+    return v1 < v2;
+}
+
+/* One two-block local search on blocks a and b of part (part is not
+   changed).  moves (capacity |A| + |B|) receives the moved nodes in order.
+   res: start imbalance, start cut, end imbalance, end cut, moves made, moves
+   kept (the rolled-back prefix), with imbalances scaled by s. */
+static void fm_pair(int32_t n, const int64_t *xadj, const int32_t *adj, const uint32_t *ew,
+                    const uint32_t *vw, const int32_t *part, int32_t a, int32_t b, int64_t wa,
+                    int64_t wb, int64_t s, int64_t l, uint64_t run_seed, uint32_t alpha_num,
+                    uint32_t alpha_den, int32_t depth, int32_t *moves, int64_t *res)
+{
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    int8_t *side = (int8_t *)malloc(nn);
+    int8_t *status = (int8_t *)calloc(nn, 1); /* 0 idle, 1 queued, 2 moved */
+    int64_t *gain = (int64_t *)calloc(nn, sizeof(int64_t));
+    int32_t *dist = (int32_t *)malloc(nn * sizeof(int32_t));
+    int32_t *list = (int32_t *)malloc(nn * sizeof(int32_t)); /* queued nodes, both sides */
+    int32_t *bfs = (int32_t *)malloc(nn * sizeof(int32_t));
+    int64_t cnt[2] = {0, 0}, cut = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        side[v] = part[v] == a ? 0 : part[v] == b ? 1 : -1;
+        dist[v] = -1;
+        if (side[v] >= 0) ++cnt[side[v]];
+    }
+    /* gains, boundary, cut */
+    int32_t head = 0, tail = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (side[v] < 0) continue;
+        int boundary = 0;
+        for (int64_t j = xadj[v]; j < xadj[v + 1]; ++j) {
+            int32_t u = adj[j];
+            if (side[u] < 0) continue;
+            if (side[u] != side[v]) {
+                gain[v] += ew[j];
+                boundary = 1;
+                if (side[v] == 0) cut += ew[j];
+            } else {
+                gain[v] -= ew[j];
+            }
+        }
+        if (boundary) { dist[v] = 0; bfs[tail++] = v; }
+    }
+    /* bounded BFS inside each block from its boundary */
+    while (head < tail) {
+        int32_t v = bfs[head++];
+        if (dist[v] >= depth) continue;
+        for (int64_t j = xadj[v]; j < xadj[v + 1]; ++j) {
+            int32_t u = adj[j];
+            if (side[u] == side[v] && dist[u] < 0) { dist[u] = dist[v] + 1; bfs[tail++] = u; }
+        }
+    }
+    int32_t qn = 0;
+    for (int32_t v = 0; v < n; ++v)
+        if (side[v] >= 0 && dist[v] == 0) { status[v] = 1; list[qn++] = v; }
+
+    int64_t w[2] = {wa, wb};
+    int64_t best_imb = pair_imbalance(w[0], w[1], s, l), best_cut = cut;
+    res[0] = best_imb;
+    res[1] = best_cut;
+    int32_t m = 0, kept = 0;
+    int64_t since = 0, smaller = cnt[0] < cnt[1] ? cnt[0] : cnt[1];
+    for (;;) {
+        /* the top of each queue */
+        int32_t top[2] = {-1, -1};
+        uint64_t th[2] = {0, 0};
+        for (int32_t i = 0; i < qn; ++i) {
+            int32_t v = list[i];
+            if (status[v] != 1) continue;
+            uint64_t h = orc_mix64(run_seed ^ (uint64_t)v);
+            int sd = side[v];
+            if (top[sd] < 0 || entry_above(gain[v], h, v, gain[top[sd]], th[sd], top[sd])) {
+                top[sd] = v;
+                th[sd] = h;
+            }
+        }
+        if (top[0] < 0 && top[1] < 0) break;
+        int from;
+        int overloaded = s * w[0] > l || s * w[1] > l;
+        if (overloaded && w[0] != w[1]) {
+            from = w[0] > w[1] ? 0 : 1;                 /* MaxLoad */
+            if (top[from] < 0) from = 1 - from;
+        } else if (top[0] < 0 || top[1] < 0) {
+            from = top[0] < 0 ? 1 : 0;
+        } else {                                         /* TopGain */
+            from = entry_above(gain[top[0]], th[0], top[0], gain[top[1]], th[1], top[1]) ? 0 : 1;
+        }
+        int32_t v = top[from];
+        int to = 1 - from;
+        status[v] = 2;
+        side[v] = (int8_t)to;
+        w[from] -= vw[v];
+        w[to] += vw[v];
+        cut -= gain[v];
+        moves[m++] = v;
+        for (int64_t j = xadj[v]; j < xadj[v + 1]; ++j) {
+            int32_t u = adj[j];
+            if (side[u] < 0 || status[u] == 2) continue;
+            if (side[u] == to) gain[u] -= 2 * (int64_t)ew[j];
+            else gain[u] += 2 * (int64_t)ew[j];
+            if (status[u] == 0 && dist[u] >= 0) { status[u] = 1; list[qn++] = u; }
+        }
+        int64_t imb = pair_imbalance(w[0], w[1], s, l);
+        if (state_below(imb, cut, best_imb, best_cut)) {
+            best_imb = imb;
+            best_cut = cut;
+            kept = m;
+            since = 0;
+        } else {
+            ++since;
+        }
+        if (since * (int64_t)alpha_den > (int64_t)alpha_num * smaller) break;
+    }
+    res[2] = best_imb;
+    res[3] = best_cut;
+    res[4] = m;
+    res[5] = kept;
+    free(side); free(status); free(gain); free(dist); free(list); free(bfs);
+}
+
+static int refine_args_ok(int32_t k, uint32_t eps_num, uint32_t eps_den, uint32_t alpha_den,
+                          int32_t depth)
+{
+    return k >= 1 && k <= 256 && eps_den >= 1 && eps_den <= 1000000u &&
+           eps_num <= 16000000u && alpha_den >= 1 && depth >= 0;
+}
+
+/* S = k eps_den and L = (eps_den + eps_num) c(V) + S max_v c(v), and the
+   block weights */
+static void refine_scale(int32_t n, const uint32_t *vw, const int32_t *part, int32_t k,
+                         uint32_t eps_num, uint32_t eps_den, int64_t *bw, int64_t *s, int64_t *l)
+{
+    int64_t total = 0, maxc = 0;
+    for (int32_t i = 0; i < k; ++i) bw[i] = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        bw[part[v]] += vw[v];
+        total += vw[v];
+        if ((int64_t)vw[v] > maxc) maxc = vw[v];
+    }
+    *s = (int64_t)k * eps_den;
+    *l = ((int64_t)eps_den + eps_num) * total + *s * maxc;
+}
+
+/* One local search on blocks a < b with the given run seed (for tests). */
+int orc_fm_pair(int32_t n, const int64_t *xadj, const int32_t *adj, const uint32_t *ew,
+                const uint32_t *vw, const int32_t *part, int32_t k, int32_t a, int32_t b,
+                uint32_t eps_num, uint32_t eps_den, uint64_t run_seed, uint32_t alpha_num,
+                uint32_t alpha_den, int32_t depth, int32_t *moves, int64_t *res)
+{
+    if (!refine_args_ok(k, eps_num, eps_den, alpha_den, depth) || a < 0 || b <= a || b >= k)
+        return ORC_E_ARG;
+    for (int32_t v = 0; v < n; ++v)
+        if (part[v] < 0 || part[v] >= k) return ORC_E_RANGE;
+    int64_t *bw = (int64_t *)malloc((size_t)k * sizeof(int64_t)), s, l;
+    refine_scale(n, vw, part, k, eps_num, eps_den, bw, &s, &l);
+    fm_pair(n, xadj, adj, ew, vw, part, a, b, bw[a], bw[b], s, l, run_seed, alpha_num, alpha_den,
+            depth, moves, res);
+    free(bw);
+    return ORC_OK;
+}
+
+uint64_t orc_run_seed(uint64_t seed, int32_t g, int32_t a, int32_t b, int32_t t, int32_t r)
+{
+    uint64_t h = orc_mix64(seed + (uint64_t)g);
+    h = orc_mix64(h ^ (((uint64_t)(uint32_t)a << 32) | (uint32_t)b));
+    return orc_mix64(h + 2 * (uint64_t)t + (uint64_t)r);
+}
+
+/* Pairwise refinement of one level, in place on part.  stats: global
+   iterations run, local searches run, moves made, moves kept, adoptions
+   (local iterations that improved), colours summed over global iterations. */
+int orc_refine(int32_t n, const int64_t *xadj, const int32_t *adj, const uint32_t *ew,
+               const uint32_t *vw, int32_t *part, int32_t k, uint32_t eps_num, uint32_t eps_den,
+               uint64_t seed, uint32_t alpha_num, uint32_t alpha_den, int32_t depth,
+               int32_t max_local, int32_t max_global, int32_t stop_after, int64_t *stats)
+{
+    if (!refine_args_ok(k, eps_num, eps_den, alpha_den, depth) || max_local < 1 ||
+        max_global < 0 || stop_after < 1)
+        return ORC_E_ARG;
+    for (int32_t v = 0; v < n; ++v)
+        if (part[v] < 0 || part[v] >= k) return ORC_E_RANGE;
+    for (int i = 0; i < 6; ++i) stats[i] = 0;
+    int64_t *bw = (int64_t *)malloc((size_t)k * sizeof(int64_t)), s, l;
+    refine_scale(n, vw, part, k, eps_num, eps_den, bw, &s, &l);
+    size_t kk = (size_t)k * k / 2 + 1, nn = (size_t)(n > 0 ? n : 1);
+    int32_t *pa = (int32_t *)malloc(kk * sizeof(int32_t));
+    int32_t *pb = (int32_t *)malloc(kk * sizeof(int32_t));
+    int32_t *pc = (int32_t *)malloc(kk * sizeof(int32_t));
+    int32_t *mv[2] = {(int32_t *)malloc(nn * sizeof(int32_t)), (int32_t *)malloc(nn * sizeof(int32_t))};
+    int32_t idle = 0;
+    for (int32_t g = 0; g < max_global; ++g) {
+        int32_t np;
+        int32_t ncol = orc_quotient_colouring(n, xadj, adj, part, k, pa, pb, pc, &np);
+        stats[0] += 1;
+        stats[5] += ncol;
+        int improved = 0;
+        for (int32_t c = 0; c < ncol; ++c)
+            for (int32_t p = 0; p < np; ++p) {
+                if (pc[p] != c) continue;
+                int32_t a = pa[p], b = pb[p];
+                for (int32_t t = 0; t < max_local; ++t) {
+                    int64_t res[2][6];
+                    for (int r = 0; r < 2; ++r)
+                        fm_pair(n, xadj, adj, ew, vw, part, a, b, bw[a], bw[b], s, l,
+                                orc_run_seed(seed, g, a, b, t, r), alpha_num, alpha_den, depth,
+                                mv[r], res[r]);
+                    stats[1] += 2;
+                    stats[2] += res[0][4] + res[1][4];
+                    int r = state_below(res[1][2], res[1][3], res[0][2], res[0][3]) ? 1 : 0;
+                    if (!state_below(res[r][2], res[r][3], res[r][0], res[r][1])) break;
+                    for (int64_t i = 0; i < res[r][5]; ++i) {
+                        int32_t v = mv[r][i];
+                        int32_t to = part[v] == a ? b : a;
+                        bw[part[v]] -= vw[v];
+                        bw[to] += vw[v];
+                        part[v] = to;
+                    }
+                    stats[3] += res[r][5];
+                    stats[4] += 1;
+                    improved = 1;
+                }
+            }
+        idle = improved ? 0 : idle + 1;
+        if (idle >= stop_after) break;
+    }
+    free(pa); free(pb); free(pc); free(mv[0]); free(mv[1]); free(bw);
+    return ORC_OK;
 }

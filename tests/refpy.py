@@ -168,3 +168,80 @@ def two_phase_rounds(g, kind, seed, block_bits):
     gm = local_max_rounds(g.n, gap, key)
     return [gm[v] if gm[v] >= 0 else (loc[v] if loc[v] >= 0 and gm[loc[v]] < 0 else -1)
             for v in range(g.n)]
+
+
+def fm_pair_ref(g, part, k, a, b, run_seed, alpha, depth, eps):
+    """A second, dictionary-based writing of one two-block local search
+    (Section 5.2) with the same readings as the oracle: gains over the two
+    blocks, bounded BFS area, TopGain with the MaxLoad exception, patience
+    alpha * min(|A|, |B|), rollback to the smallest (imbalance, cut).
+    Returns (moves, kept).  For tiny graphs only."""
+    nbr = {v: {} for v in range(g.n)}
+    for v in range(g.n):
+        for j in range(int(g.xadj[v]), int(g.xadj[v + 1])):
+            nbr[v][int(g.adj[j])] = int(g.ew[j])
+    c = [int(x) for x in g.vw]
+    where = {v: (0 if part[v] == a else 1) for v in range(g.n) if part[v] in (a, b)}
+    total, maxc = sum(c), max(c) if c else 0
+    S = k * eps.denominator
+    L = (eps.denominator + eps.numerator) * total + S * maxc
+    w = [sum(c[v] for v in where if where[v] == s) for s in (0, 1)]
+    size = [sum(1 for v in where if where[v] == s) for s in (0, 1)]
+
+    def imb():
+        return max(0, S * max(w) - L)
+
+    def gain(v):
+        return sum(x if where[u] != where[v] else -x for u, x in nbr[v].items() if u in where)
+
+    def cut():
+        return sum(x for v in where for u, x in nbr[v].items()
+                   if u in where and where[v] == 0 and where[u] == 1)
+
+    # bounded BFS inside each block from the boundary
+    dist = {v: 0 for v in where if any(u in where and where[u] != where[v] for u in nbr[v])}
+    frontier = sorted(dist)
+    for d in range(1, depth + 1):
+        nxt = []
+        for v in frontier:
+            for u in nbr[v]:
+                if u in where and where[u] == where[v] and u not in dist:
+                    dist[u] = d
+                    nxt.append(u)
+        frontier = nxt
+    queued = {v for v in dist if dist[v] == 0}
+    moved = []
+    best, kept, since = (imb(), cut()), 0, 0
+    while True:
+        tops = []
+        for s in (0, 1):
+            cand = [v for v in queued if where[v] == s]
+            tops.append(max(cand, key=lambda v: (gain(v), mix64(run_seed ^ v), -v)) if cand else None)
+        if tops[0] is None and tops[1] is None:
+            break
+        key = lambda v: (gain(v), mix64(run_seed ^ v), -v)
+        if (S * w[0] > L or S * w[1] > L) and w[0] != w[1]:
+            s = 0 if w[0] > w[1] else 1
+            if tops[s] is None:
+                s = 1 - s
+        elif tops[0] is None or tops[1] is None:
+            s = 0 if tops[1] is None else 1
+        else:
+            s = 0 if key(tops[0]) > key(tops[1]) else 1
+        v = tops[s]
+        queued.discard(v)
+        where[v] = 1 - s
+        w[s] -= c[v]
+        w[1 - s] += c[v]
+        moved.append(v)
+        for u in nbr[v]:
+            if u in dist and u not in queued and u not in moved:
+                queued.add(u)
+        now = (imb(), cut())
+        if now < best:
+            best, kept, since = now, len(moved), 0
+        else:
+            since += 1
+        if since > alpha * min(size):
+            break
+    return moved, kept
