@@ -319,6 +319,66 @@ kappa_status kappa_uncoarsen(const kappa_hierarchy *h, int32_t k, uint64_t part_
                              uint32_t eps_num, uint32_t eps_den, int32_t *part0,
                              kappa_cut_result *results, kappa_stream_t stream);
 
+/* Parameters of the pairwise refinement (Section 5; Table 2 names the
+   presets minimal / fast / strong). */
+typedef struct {
+    uint64_t seed;        /* tie-break seed of the local searches */
+    uint32_t alpha_num;   /* FM patience alpha = alpha_num / alpha_den (>= 1): a search */
+    uint32_t alpha_den;   /*   stops after more than alpha * min(|A|, |B|) moves without gain */
+    int32_t depth;        /* BFS search depth (>= 0) around the boundary of each block */
+    int32_t max_local;    /* local iterations per pair (>= 1) */
+    int32_t max_global;   /* max. global iterations (>= 0) */
+    int32_t stop_after;   /* global iterations in a row without change that end it (>= 1) */
+} kappa_refine_params;
+
+typedef struct {
+    int64_t global_iterations; /* global iterations run */
+    int64_t searches;          /* two-block local searches run (two per local iteration) */
+    int64_t moves;             /* node moves made by them */
+    int64_t kept;              /* moves kept after the rollbacks of adopted searches */
+    int64_t adoptions;         /* local iterations whose better search improved the pair */
+    int64_t colours;           /* colours of Q summed over the global iterations */
+} kappa_refine_stats;
+
+/* Pairwise refinement of the k-way partition part (Section 5), in place.
+   Each global iteration colours the quotient graph Q greedily (Section 5.1:
+   Q's edges in ascending (a, b) order, each taking the smallest colour free
+   at both ends) and walks the colours in order; the pairs of one colour run
+   side by side.  A pair runs local iterations: two two-block FM searches
+   (Section 5.2) with the run seeds
+     mix64(mix64(mix64(seed + g) ^ ((a << 32) | b)) + 2 t + r),  r = 0, 1,
+   for global iteration g and local iteration t; each queue orders nodes by
+   gain (w to the other block - w to the own block, neighbours of the two
+   blocks only), then by mix64(run seed ^ v), then by the smaller id; queues
+   start with the boundary nodes and admit nodes within `depth` same-block
+   hops of it; TopGain picks the queue with the larger top, except that the
+   heavier block gives when a block is overloaded (c > L_max) and the two
+   weights differ; the search stops when both queues are empty or after
+   more than alpha * min(|A|, |B|) moves without improvement, and rolls back
+   to the first state with the smallest (imbalance, cut), imbalance =
+   max(0, c(A) - L_max, c(B) - L_max).  The better search (r = 0 on a tie)
+   is adopted if it improves on the start; otherwise the pair is done.
+   Global iterations stop after stop_after in a row without an adoption or
+   after max_global.  k in [1, 256]; eps as in kappa_cut_balance.  part
+   (device, n entries, in/out); stats (host, may be NULL).
+   KAPPA_E_RANGE (part unchanged) if a block id lies outside [0, k).
+   Synchronous. */
+kappa_status kappa_refine(const kappa_graph *g, int32_t *part, int32_t k, uint32_t eps_num,
+                          uint32_t eps_den, const kappa_refine_params *params,
+                          kappa_refine_stats *stats, kappa_stream_t stream);
+
+/* The way back up with refinement: the coarsest level of h is partitioned
+   by kappa_initial_partition(part_seed); then from the coarsest level down,
+   each level is projected from the one above (not the coarsest), refined
+   by kappa_refine with the seed mix64(params->seed + l), and evaluated.
+   part0 (device, n_0 entries, out): the level-0 partition.  results and
+   stats (host, one entry per level, may be NULL).  Synchronous. */
+kappa_status kappa_uncoarsen_refined(const kappa_hierarchy *h, int32_t k, uint64_t part_seed,
+                                     uint32_t eps_num, uint32_t eps_den,
+                                     const kappa_refine_params *params, int32_t *part0,
+                                     kappa_cut_result *results, kappa_refine_stats *stats,
+                                     kappa_stream_t stream);
+
 /* Per-kernel timing with HIP events on the launch stream.  While enabled,
    every kernel launch of the library is bracketed by two events; read the
    totals with kappa_profile_read.  Not thread-safe. */

@@ -61,6 +61,38 @@ class c_cut(ctypes.Structure):
                 self.imb_num, self.bal_num, self.bal_den, int(self.feasible))
 
 
+class c_refine_params(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("alpha_num", ctypes.c_uint32),
+                ("alpha_den", ctypes.c_uint32), ("depth", ctypes.c_int32),
+                ("max_local", ctypes.c_int32), ("max_global", ctypes.c_int32),
+                ("stop_after", ctypes.c_int32)]
+
+
+class c_refine_stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("global_iterations", "searches", "moves", "kept",
+                                               "adoptions", "colours")]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+# Presets of Table 2 (minimal, fast, strong): alpha, BFS depth, local
+# iterations, max. global iterations, global iterations without change that end it
+REFINE_PRESETS = {
+    "minimal": dict(alpha_num=1, alpha_den=100, depth=1, max_local=1, max_global=1, stop_after=1),
+    "fast": dict(alpha_num=5, alpha_den=100, depth=5, max_local=3, max_global=15, stop_after=1),
+    "strong": dict(alpha_num=20, alpha_den=100, depth=20, max_local=5, max_global=15,
+                   stop_after=2),
+}
+REFINE_K_MAX = 256
+
+
+def refine_params(preset: str = "fast", seed: int = 1, **over) -> c_refine_params:
+    d = dict(REFINE_PRESETS[preset])
+    d.update(over)
+    return c_refine_params(seed=seed & 0xFFFFFFFFFFFFFFFF, **d)
+
+
 class c_level_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("rounds", ctypes.c_int32),
                 ("matched", ctypes.c_int64), ("stop_reason", ctypes.c_int32),
@@ -121,6 +153,10 @@ def lib():
         "kappa_cut_balance": (st, [ctypes.POINTER(c_graph), P, i32, u32, u32, P,
                                    ctypes.POINTER(c_cut), P]),
         "kappa_uncoarsen": (st, [P, i32, u64, u32, u32, P, P, P]),
+        "kappa_refine": (st, [ctypes.POINTER(c_graph), P, i32, u32, u32,
+                              ctypes.POINTER(c_refine_params), ctypes.POINTER(c_refine_stats), P]),
+        "kappa_uncoarsen_refined": (st, [P, i32, u64, u32, u32, ctypes.POINTER(c_refine_params),
+                                         P, P, P, P]),
         "kappa_profile_enable": (None, [i32]),
         "kappa_profile_reset": (None, []),
         "kappa_profile_read": (i32, [P, P, P, i32]),
@@ -553,6 +589,36 @@ def kappa_uncoarsen(h: Hierarchy, k: int, part_seed: int = 1, eps_num: int = 3, 
     _check("kappa_uncoarsen", lib().kappa_uncoarsen(h.handle, k, ctypes.c_uint64(part_seed), eps_num,
                                                     eps_den, _ptr(part0), res, _stream()))
     return part0[:n0], list(res)
+
+
+def kappa_refine(g: DeviceGraph, part, k: int, eps_num: int = 3, eps_den: int = 100,
+                 preset: str = "fast", seed: int = 1, **over):
+    """Pairwise refinement (Section 5) of the device partition `part`, in
+    place.  Returns the stats as a dict."""
+    p = refine_params(preset, seed, **over)
+    out = c_refine_stats()
+    _check("kappa_refine", lib().kappa_refine(ctypes.byref(g.c()), _ptr(part), k, eps_num, eps_den,
+                                              ctypes.byref(p), ctypes.byref(out), _stream()))
+    return out.as_dict()
+
+
+def kappa_uncoarsen_refined(h: Hierarchy, k: int, part_seed: int = 1, eps_num: int = 3,
+                            eps_den: int = 100, preset: str = "fast", seed: int = 1, part0=None,
+                            **over):
+    """The way back up with refinement.  Returns (level-0 partition tensor,
+    [c_cut per level], [stats dict per level])."""
+    import torch
+    n0 = int(h.info(0).n)
+    if part0 is None:
+        part0 = torch.empty(max(n0, 1), dtype=torch.int32, device=h.device)
+    L = len(h)
+    res = (c_cut * L)()
+    sts = (c_refine_stats * L)()
+    p = refine_params(preset, seed, **over)
+    _check("kappa_uncoarsen_refined",
+           lib().kappa_uncoarsen_refined(h.handle, k, ctypes.c_uint64(part_seed), eps_num, eps_den,
+                                         ctypes.byref(p), _ptr(part0), res, sts, _stream()))
+    return part0[:n0], list(res), [x.as_dict() for x in sts]
 
 
 def kappa_cache_release():

@@ -1616,6 +1616,171 @@ extern "C" kappa_status kappa_uncoarsen(const kappa_hierarchy *h, int32_t k, uin
     return KAPPA_OK;
 }
 
+namespace {
+
+bool refine_args_ok(int32_t k, uint32_t eps_num, uint32_t eps_den, const kappa_refine_params *p) {
+    return p && k >= 1 && k <= REFINE_K_MAX && cut_args_ok(k, eps_num, eps_den) &&
+           p->alpha_den >= 1 && p->depth >= 0 && p->max_local >= 1 && p->max_global >= 0 &&
+           p->stop_after >= 1;
+}
+
+kappa_status refine_impl(const DevGraph &d, int32_t *part, int32_t k, uint32_t eps_num,
+                         uint32_t eps_den, const kappa_refine_params *p, kappa_refine_stats *out,
+                         hipStream_t s) {
+    const int64_t n = d.n, maxp = std::max<int64_t>(1, (int64_t)k * (k - 1) / 2);
+    RefineLaunch R{};
+    unsigned long long *qbits = nullptr;
+    int32_t *tmp_pair = nullptr, *tmp_col = nullptr;
+    // the control block and the colour offsets, read back together
+    struct Head {
+        RefineCtl ctl;
+        int32_t col_off[REFINE_COLOURS + 1];
+    };
+    Head *head = nullptr;
+    std::unique_ptr<Workspace> w;
+    if (!carve_workspace(s, w, [&](Carve &cv) {
+            head = cv.get<Head>(1);
+            R.bw = cv.get<int64_t>(k);
+            R.bc = cv.get<int32_t>(k);
+            qbits = cv.get<unsigned long long>((int64_t)k * REFINE_QW);
+            tmp_pair = cv.get<int32_t>(maxp);
+            tmp_col = cv.get<int32_t>(maxp);
+            R.cpairs = cv.get<int32_t>(maxp);
+            R.fill = cv.get<int32_t>(maxp);
+            R.poff = cv.get<int32_t>(maxp);
+            R.region = cv.get<int32_t>(n);
+            R.dist = cv.get<int32_t>(n);
+            R.gain = cv.get<int64_t>(2 * n);
+            R.status = cv.get<uint8_t>(2 * n);
+            R.qlist = cv.get<int32_t>(2 * n);
+            R.mlog = cv.get<int32_t>(2 * n);
+        }))
+        return KAPPA_E_NOMEM;
+    R.xadj = d.xadj; R.adj = d.adj; R.ew = d.ew; R.vw = d.vw; R.part = part;
+    R.n = d.n; R.k = k; R.eps_num = eps_num; R.eps_den = eps_den; R.seed = p->seed;
+    R.alpha_num = p->alpha_num; R.alpha_den = p->alpha_den; R.depth = p->depth;
+    R.max_local = p->max_local;
+    R.ctl = &head->ctl;
+    R.col_off = head->col_off;
+    {
+        ZeroRanges z;
+        z.add((uint32_t *)head, sizeof(Head) / 4);
+        z.add((uint32_t *)R.bw, 2 * (int64_t)k);
+        z.add((uint32_t *)R.bc, k);
+        launch_zero(z, s);
+    }
+    launch_refine_weights(part, d.vw, d.n, k, R.bw, R.bc, R.ctl, s);
+    Head *rb = (Head *)pinned(sizeof(Head));
+    if (!rb) return KAPPA_E_NOMEM;
+    kappa_refine_stats st{};
+    unsigned long long adopted = 0;
+    int32_t idle = 0;
+    bool pending = false;   // launched searches whose outcome has not been read
+    for (int32_t gi = 0;; ++gi) {
+        // the colouring of the next global iteration is launched before it is
+        // known whether that iteration runs: one read-back per iteration
+        if (gi < p->max_global) {
+            ZeroRanges z;
+            z.add((uint32_t *)qbits, (int64_t)k * REFINE_QW * 2);
+            launch_zero(z, s);
+            launch_refine_colouring(d.xadj, d.adj, part, d.n, k, qbits, tmp_pair, tmp_col,
+                                    R.cpairs, R.col_off, R.fill, R.ctl, s);
+        }
+        HIPCHK(hipMemcpyAsync(rb, head, sizeof(Head), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (gi == 0 && (rb->ctl.flags & 1u)) return KAPPA_E_RANGE;
+        if (rb->ctl.flags & 2u) {
+            if (debug_on()) fprintf(stderr, "kappa: refine: block counts disagree with part\n");
+            return KAPPA_E_HIP;
+        }
+        if (pending) {
+            idle = rb->ctl.stats[4] > adopted ? 0 : idle + 1;
+            adopted = rb->ctl.stats[4];
+            pending = false;
+            if (idle >= p->stop_after) break;
+        }
+        if (gi >= p->max_global) break;
+        const int32_t ncol = rb->ctl.ncol;
+        st.global_iterations += 1;
+        st.colours += ncol;
+        for (int32_t c = 0; c < ncol; ++c)
+            if (rb->col_off[c + 1] > rb->col_off[c])
+                launch_refine_colour(R, gi, c, rb->col_off[c + 1] - rb->col_off[c], s);
+        HIPCHK(hipGetLastError());
+        pending = true;
+    }
+    st.searches = (int64_t)rb->ctl.stats[1];
+    st.moves = (int64_t)rb->ctl.stats[2];
+    st.kept = (int64_t)rb->ctl.stats[3];
+    st.adoptions = (int64_t)rb->ctl.stats[4];
+    if (out) *out = st;
+    return KAPPA_OK;
+}
+
+}  // namespace
+
+extern "C" kappa_status kappa_refine(const kappa_graph *g, int32_t *part, int32_t k,
+                                     uint32_t eps_num, uint32_t eps_den,
+                                     const kappa_refine_params *params, kappa_refine_stats *stats,
+                                     kappa_stream_t stream) {
+    if (!graph_args_ok(g) || !refine_args_ok(k, eps_num, eps_den, params)) return KAPPA_E_ARG;
+    if (g->n > 0 && !part) return KAPPA_E_ARG;
+    return refine_impl(dev(g), part, k, eps_num, eps_den, params, stats, S(stream));
+}
+
+extern "C" kappa_status kappa_uncoarsen_refined(const kappa_hierarchy *h, int32_t k,
+                                                uint64_t part_seed, uint32_t eps_num,
+                                                uint32_t eps_den,
+                                                const kappa_refine_params *params,
+                                                int32_t *part0, kappa_cut_result *results,
+                                                kappa_refine_stats *stats, kappa_stream_t stream) {
+    if (!h || h->levels.empty() || !refine_args_ok(k, eps_num, eps_den, params))
+        return KAPPA_E_ARG;
+    if (h->levels[0].n > 0 && !part0) return KAPPA_E_ARG;
+    hipStream_t s = S(stream);
+    const int32_t nl = (int32_t)h->levels.size(), L = nl - 1;
+    // the coarse levels' partitions in one arena (the workspace is taken by
+    // the calls below)
+    std::vector<size_t> off(nl, 0);
+    size_t bytes = 256;
+    for (int32_t l = 1; l < nl; ++l) {
+        off[l] = bytes;
+        bytes += ((size_t)std::max(1, h->levels[l].n) * sizeof(int32_t) + 255) & ~(size_t)255;
+    }
+    size_t got = 0;
+    Allocator al;
+    char *arena = (char *)take_arena(s, bytes, &got, &al);
+    if (!arena) return KAPPA_E_NOMEM;
+    struct Give {
+        hipStream_t s; void *p; size_t b; Allocator al;
+        ~Give() { give_arena(s, p, b, al); }
+    } give{s, arena, got, al};
+    std::vector<int32_t *> part(nl, nullptr);
+    part[0] = part0;
+    for (int32_t l = 1; l < nl; ++l) part[l] = (int32_t *)(arena + off[l]);
+    for (int32_t l = L; l >= 0; --l) {
+        const kappa_level &lv = h->levels[l];
+        kappa_graph g{};
+        g.n = lv.n; g.nnz = lv.nnz; g.xadj = lv.xadj; g.adj = lv.adj; g.ew = lv.ew; g.vw = lv.vw;
+        kappa_status st;
+        if (l == L)
+            st = kappa_initial_partition(lv.n, k, part_seed, part[l], stream);
+        else
+            st = kappa_project(lv.cmap, lv.n, h->levels[l + 1].n, part[l + 1], part[l], stream);
+        if (st != KAPPA_OK) return st;
+        kappa_refine_params pl = *params;
+        pl.seed = mix64(params->seed + (uint64_t)l);
+        st = refine_impl(dev(&g), part[l], k, eps_num, eps_den, &pl, stats ? stats + l : nullptr,
+                         s);
+        if (st != KAPPA_OK) return st;
+        if (results) {
+            st = kappa_cut_balance(&g, part[l], k, eps_num, eps_den, nullptr, results + l, stream);
+            if (st != KAPPA_OK) return st;
+        }
+    }
+    return KAPPA_OK;
+}
+
 extern "C" kappa_status kappa_cache_release(void) {
     HIPCHK(hipDeviceSynchronize());
     std::lock_guard<std::mutex> g(g_cache_mu);

@@ -1,0 +1,548 @@
+// Pairwise refinement of a k-way partition (Section 5).
+//
+//   quotient:  Q has an edge {a, b} (a < b) when an edge of G joins blocks a
+//              and b; a k x k bitmap built with LDS-aggregated ORs.
+//   colouring: Q's edges in ascending (a, b) order, each taking the smallest
+//              colour free at both ends (the sequential greedy colouring that
+//              Section 5.1 parallelises); one workgroup, since each choice
+//              depends on all earlier ones.  Pairs of one colour share no
+//              block, so their local searches touch disjoint node sets and
+//              disjoint block weights and run side by side.
+//   collect:   per colour, the nodes of each pair's two blocks into one
+//              region per pair (order inside a region does not matter).
+//   fm:        one workgroup per pair of the colour.  Its two halves run the
+//              two local searches of a local iteration (run seeds r = 0, 1)
+//              in lockstep, one move per step: a reduction over the queued
+//              nodes finds each queue's top under the strict order (gain,
+//              then mix64(run_seed ^ v), then the smaller id), one lane picks
+//              the queue (TopGain, MaxLoad when a block is overloaded) and
+//              books the move, and the half updates the neighbours' gains
+//              and queues (Section 5.2).  The better run is adopted; the
+//              workgroup repeats local iterations until one improves nothing.
+//
+// Every choice is a maximum under a strict total order, so the result does
+// not depend on the order of reductions or of the region: it is bit-exact
+// with the sequential definition.
+#include <algorithm>
+
+#include "kappa_internal.h"
+
+namespace kappa {
+
+namespace {
+
+constexpr int RQ_THREADS = 256;
+constexpr int RC_ITEMS = 16;           // nodes per thread in collect
+constexpr int FM_THREADS = 1024;       // two halves of 512, one per run
+constexpr int FM_HALF = FM_THREADS / 2;
+constexpr int FM_WAVES = FM_HALF / WAVE;
+
+__device__ __forceinline__ uint64_t run_seed_of(uint64_t seed, int32_t g, int32_t a, int32_t b,
+                                                int32_t t, int32_t r) {
+    uint64_t h = mix64(seed + (uint64_t)(uint32_t)g);
+    h = mix64(h ^ (((uint64_t)(uint32_t)a << 32) | (uint32_t)b));
+    return mix64(h + 2 * (uint64_t)(uint32_t)t + (uint64_t)(uint32_t)r);
+}
+
+// (gain, hash, id) above (gain, hash, id); id < 0 is "none", below all
+__device__ __forceinline__ bool key_above(int64_t g1, uint64_t h1, int32_t v1, int64_t g2,
+                                          uint64_t h2, int32_t v2) {
+    if (v2 < 0) return v1 >= 0;
+    if (v1 < 0) return false;
+    if (g1 != g2) return g1 > g2;
+    if (h1 != h2) return h1 > h2;
+    return v1 < v2;
+}
+
+__device__ __forceinline__ bool state_below(int64_t i1, int64_t c1, int64_t i2, int64_t c2) {
+    return i1 < i2 || (i1 == i2 && c1 < c2);
+}
+
+__device__ __forceinline__ int64_t pair_imb(int64_t w0, int64_t w1, int64_t S, int64_t L) {
+    const int64_t x = S * (w0 > w1 ? w0 : w1) - L;
+    return x > 0 ? x : 0;
+}
+
+// block weights and node counts, c(V), max c(v); flags a block id outside [0, k)
+__global__ void __launch_bounds__(RQ_THREADS)
+    ref_weights_k(const int32_t *__restrict__ part, const uint32_t *__restrict__ vw, int32_t n,
+                  int32_t k, int64_t *bw, int32_t *bc, RefineCtl *ctl) {
+    __shared__ unsigned long long s_w[REFINE_K_MAX];
+    __shared__ int32_t s_c[REFINE_K_MAX];
+    __shared__ unsigned long long s_tot, s_max;
+    __shared__ uint32_t s_bad;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) { s_w[i] = 0; s_c[i] = 0; }
+    if (threadIdx.x == 0) { s_tot = 0; s_max = 0; s_bad = 0; }
+    __syncthreads();
+    unsigned long long tot = 0, mx = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t p = part[v];
+        const uint32_t c = vw[v];
+        tot += c;
+        mx = c > mx ? c : mx;
+        if (p < 0 || p >= k) { s_bad = 1; continue; }
+        atomicAdd(&s_w[p], (unsigned long long)c);
+        atomicAdd(&s_c[p], 1);
+    }
+    atomicAdd(&s_tot, tot);
+    atomicMax(&s_max, mx);
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+        if (s_c[i]) {
+            atomicAdd((unsigned long long *)&bw[i], s_w[i]);
+            atomicAdd(&bc[i], s_c[i]);
+        }
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(&ctl->total, s_tot);
+        atomicMax(&ctl->max_node, s_max);
+        if (s_bad) atomicOr(&ctl->flags, 1u);
+    }
+}
+
+// Q as a bitmap: row a, bit b for a < b
+__global__ void __launch_bounds__(RQ_THREADS)
+    ref_quotient_k(const int64_t *__restrict__ xadj, const int32_t *__restrict__ adj,
+                   const int32_t *__restrict__ part, int32_t n, int32_t k,
+                   unsigned long long *qbits) {
+    __shared__ unsigned long long s_q[REFINE_K_MAX * REFINE_QW];
+    const int qw = (k + 63) / 64;
+    for (int i = threadIdx.x; i < k * qw; i += blockDim.x) s_q[i] = 0;
+    __syncthreads();
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = part[v];
+        if (a < 0 || a >= k) continue;   // reported by the weights pass
+        for (int64_t j = xadj[v]; j < xadj[v + 1]; ++j) {
+            const int32_t b = part[adj[j]];
+            if (a < b && b < k) atomicOr(&s_q[a * qw + (b >> 6)], 1ull << (b & 63));
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < k * qw; i += blockDim.x)
+        if (s_q[i]) atomicOr(&qbits[i], s_q[i]);
+}
+
+// greedy edge colouring of Q; pairs sorted by colour (ascending (a, b) inside
+// a colour) into cpairs, colour c at [col_off[c], col_off[c + 1])
+__global__ void __launch_bounds__(RQ_THREADS)
+    ref_colour_k(const unsigned long long *__restrict__ qbits, int32_t k, int32_t *tmp_pair,
+                 int32_t *tmp_col, int32_t *cpairs, int32_t *col_off, int32_t *fill,
+                 RefineCtl *ctl) {
+    __shared__ unsigned long long s_used[REFINE_K_MAX * REFINE_CW];
+    __shared__ int32_t s_cnt[REFINE_COLOURS + 1];
+    const int qw = (k + 63) / 64;
+    for (int i = threadIdx.x; i < k * REFINE_CW; i += blockDim.x) s_used[i] = 0;
+    for (int i = threadIdx.x; i <= REFINE_COLOURS; i += blockDim.x) s_cnt[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t m = 0, ncol = 0;
+        for (int32_t a = 0; a < k; ++a)
+            for (int w = 0; w < qw; ++w) {
+                unsigned long long bits = qbits[a * qw + w];
+                while (bits) {
+                    const int32_t b = w * 64 + __builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    int32_t c = 0;
+                    for (int x = 0; x < REFINE_CW; ++x) {
+                        const unsigned long long fr = ~(s_used[a * REFINE_CW + x] |
+                                                        s_used[b * REFINE_CW + x]);
+                        if (fr) { c = x * 64 + __builtin_ctzll(fr); break; }
+                    }
+                    s_used[a * REFINE_CW + (c >> 6)] |= 1ull << (c & 63);
+                    s_used[b * REFINE_CW + (c >> 6)] |= 1ull << (c & 63);
+                    tmp_pair[m] = a | (b << 16);
+                    tmp_col[m] = c;
+                    ++s_cnt[c];
+                    ++m;
+                    ncol = c + 1 > ncol ? c + 1 : ncol;
+                }
+            }
+        int32_t acc = 0;
+        for (int32_t c = 0; c < ncol; ++c) {
+            col_off[c] = acc;
+            acc += s_cnt[c];
+            s_cnt[c] = col_off[c];
+        }
+        col_off[ncol] = acc;
+        for (int32_t i = 0; i < m; ++i) cpairs[s_cnt[tmp_col[i]]++] = tmp_pair[i];
+        ctl->ncol = ncol;
+        ctl->npairs = m;
+    }
+    __syncthreads();
+    const int32_t m = ctl->npairs;
+    for (int32_t i = threadIdx.x; i < m; i += blockDim.x) fill[i] = 0;
+}
+
+__global__ void __launch_bounds__(RQ_THREADS)
+    ref_collect_k(const int32_t *__restrict__ part, int32_t n, int32_t k, int32_t c,
+                  const int32_t *__restrict__ cpairs, const int32_t *__restrict__ col_off,
+                  const int32_t *__restrict__ bc, int32_t *fill, int32_t *poff,
+                  int32_t *region) {
+    __shared__ int32_t s_map[REFINE_K_MAX];
+    __shared__ int32_t s_off[REFINE_K_MAX / 2];
+    __shared__ int32_t s_cnt[REFINE_K_MAX / 2];
+    __shared__ int32_t s_base[REFINE_K_MAX / 2];
+    const int32_t p0 = col_off[c], np = col_off[c + 1] - p0;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) s_map[i] = -1;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) s_cnt[i] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        s_map[cpairs[p0 + i] & 0xffff] = i;
+        s_map[cpairs[p0 + i] >> 16] = i;
+    }
+    if (threadIdx.x == 0) {
+        int32_t off = 0;
+        for (int32_t i = 0; i < np; ++i) {
+            s_off[i] = off;
+            off += bc[cpairs[p0 + i] & 0xffff] + bc[cpairs[p0 + i] >> 16];
+            if (blockIdx.x == 0) poff[p0 + i] = s_off[i];
+        }
+    }
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * blockDim.x * RC_ITEMS;
+    const int64_t hi = std::min<int64_t>(lo + (int64_t)blockDim.x * RC_ITEMS, n);
+    for (int64_t v = lo + threadIdx.x; v < hi; v += blockDim.x) {
+        const int32_t j = s_map[part[v]];
+        if (j >= 0) atomicAdd(&s_cnt[j], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        s_base[i] = s_cnt[i] ? atomicAdd(&fill[p0 + i], s_cnt[i]) : 0;
+        s_cnt[i] = 0;
+    }
+    __syncthreads();
+    for (int64_t v = lo + threadIdx.x; v < hi; v += blockDim.x) {
+        const int32_t j = s_map[part[v]];
+        if (j < 0) continue;
+        const int64_t pos = (int64_t)s_off[j] + s_base[j] + atomicAdd(&s_cnt[j], 1);
+        if (pos < n) region[pos] = (int32_t)v;   // counts agree with part unless state is broken
+    }
+}
+
+struct FmArgs {
+    const int64_t *xadj;
+    const int32_t *adj;
+    const uint32_t *ew;
+    const uint32_t *vw;
+    int32_t *part;
+    int32_t n, k;
+    uint32_t eps_num, eps_den;
+    uint64_t seed;
+    uint32_t alpha_num, alpha_den;
+    int32_t depth, max_local;
+    const int32_t *cpairs, *col_off, *poff, *fill;
+    int64_t *bw;
+    int32_t *bc;
+    const int32_t *region;
+    int32_t *dist;
+    int64_t *gain;       // [2][n]
+    uint8_t *status;     // [2][n]: 0 idle, 1 queued, 2 moved
+    int32_t *qlist;      // [2][n] region-relative
+    int32_t *mlog;       // [2][n] region-relative
+    RefineCtl *ctl;
+};
+
+// per-run state of one local search, in LDS
+struct RunState {
+    int64_t w[2], cut, best_imb, best_cut, best_w[2], since;
+    int32_t cnt[2], best_cnt[2], qn, m, kept, done, v, to;
+};
+
+__device__ __forceinline__ void wave_best(int64_t &g, uint64_t &h, int32_t &v) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        const int64_t g2 = __shfl_xor(g, o);
+        const uint64_t h2 = __shfl_xor(h, o);
+        const int32_t v2 = __shfl_xor(v, o);
+        if (key_above(g2, h2, v2, g, h, v)) { g = g2; h = h2; v = v2; }
+    }
+}
+
+__global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int32_t c) {
+    __shared__ RunState rs[2];
+    __shared__ int64_t s_wg[2][2][FM_WAVES];
+    __shared__ uint64_t s_wh[2][2][FM_WAVES];
+    __shared__ int32_t s_wv[2][2][FM_WAVES];
+    __shared__ int32_t s_off, s_len, s_na, s_nb, s_changed, s_stop, s_pick, s_bc[2];
+    __shared__ int64_t s_bw[2];
+    __shared__ unsigned long long s_cut;
+    const int32_t j = blockIdx.x, p = A.col_off[c] + j;
+    const int32_t a = A.cpairs[p] & 0xffff, b = A.cpairs[p] >> 16;
+    const int tid = threadIdx.x, r = tid / FM_HALF, lt = tid % FM_HALF;
+    const int lane = lt % WAVE, wv = lt / WAVE;
+    if (tid == 0) {
+        s_off = A.poff[p];
+        s_bc[0] = A.bc[a];
+        s_bc[1] = A.bc[b];
+        s_bw[0] = A.bw[a];
+        s_bw[1] = A.bw[b];
+        s_len = s_bc[0] + s_bc[1];
+    }
+    __syncthreads();
+    const int32_t off = s_off, len = s_len;
+    if (A.fill[p] != len || (int64_t)off + len > A.n) {   // the region is not what the counts say
+        if (tid == 0) atomicOr(&A.ctl->flags, 2u);
+        return;
+    }
+    const int32_t *reg = A.region + off;
+    const int64_t S = (int64_t)A.k * A.eps_den;
+    const int64_t L = ((int64_t)A.eps_den + A.eps_num) * (int64_t)A.ctl->total +
+                      S * (int64_t)A.ctl->max_node;
+    int64_t *gain_r = A.gain + (size_t)r * A.n;
+    uint8_t *st_r = A.status + (size_t)r * A.n;
+    int32_t *q_r = A.qlist + (size_t)r * A.n + off;
+    int32_t *m_r = A.mlog + (size_t)r * A.n + off;
+
+    for (int32_t t = 0; t < A.max_local; ++t) {
+        // gains, boundary, cut, node counts of the current partition
+        if (tid == 0) { s_cut = 0; s_na = 0; s_nb = 0; rs[0].qn = rs[1].qn = 0; }
+        __syncthreads();
+        unsigned long long cut = 0;
+        int32_t na = 0, nb = 0;
+        for (int32_t i = tid; i < len; i += FM_THREADS) {
+            const int32_t v = reg[i], pv = A.part[v];
+            int64_t g = 0;
+            bool bnd = false;
+            for (int64_t e = A.xadj[v]; e < A.xadj[v + 1]; ++e) {
+                const int32_t pu = A.part[A.adj[e]];
+                if (pu != a && pu != b) continue;
+                if (pu != pv) {
+                    g += A.ew[e];
+                    bnd = true;
+                    if (pv == a) cut += A.ew[e];
+                } else {
+                    g -= A.ew[e];
+                }
+            }
+            A.gain[v] = g;
+            A.gain[(size_t)A.n + v] = g;
+            A.status[v] = 0;
+            A.status[(size_t)A.n + v] = 0;
+            A.dist[v] = bnd ? 0 : -1;
+            if (pv == a) ++na; else ++nb;
+        }
+        atomicAdd(&s_cut, cut);
+        atomicAdd(&s_na, na);
+        atomicAdd(&s_nb, nb);
+        __syncthreads();
+        // bounded BFS inside each block from its boundary
+        for (int32_t d = 1; d <= A.depth; ++d) {
+            if (tid == 0) s_changed = 0;
+            __syncthreads();
+            bool ch = false;
+            for (int32_t i = tid; i < len; i += FM_THREADS) {
+                const int32_t v = reg[i];
+                if (A.dist[v] >= 0) continue;
+                const int32_t pv = A.part[v];
+                for (int64_t e = A.xadj[v]; e < A.xadj[v + 1]; ++e) {
+                    const int32_t u = A.adj[e];
+                    if (A.part[u] == pv && A.dist[u] == d - 1) { A.dist[v] = d; ch = true; break; }
+                }
+            }
+            if (ch) s_changed = 1;
+            __syncthreads();
+            const bool more = s_changed != 0;
+            __syncthreads();   // everyone has read the flag before it is cleared again
+            if (!more) break;
+        }
+        // both runs: queues start with the boundary
+        for (int32_t i = lt; i < len; i += FM_HALF) {
+            const int32_t v = reg[i];
+            if (A.dist[v] == 0) {
+                st_r[v] = 1;
+                q_r[atomicAdd(&rs[r].qn, 1)] = v;
+            }
+        }
+        if (lt == 0) {
+            RunState &R = rs[r];
+            R.w[0] = s_bw[0];
+            R.w[1] = s_bw[1];
+            R.cnt[0] = s_na;
+            R.cnt[1] = s_nb;
+            R.cut = (int64_t)s_cut;
+            R.best_imb = pair_imb(R.w[0], R.w[1], S, L);
+            R.best_cut = R.cut;
+            R.best_w[0] = R.w[0]; R.best_w[1] = R.w[1];
+            R.best_cnt[0] = R.cnt[0]; R.best_cnt[1] = R.cnt[1];
+            R.since = 0; R.m = 0; R.kept = 0; R.done = 0; R.v = -1;
+        }
+        __syncthreads();
+        const int64_t start_imb = rs[0].best_imb, start_cut = rs[0].best_cut;
+        const int64_t smaller = min(s_na, s_nb);
+        const uint64_t rseed = run_seed_of(A.seed, gi, a, b, t, r);
+        // the moves, both runs in lockstep
+        for (;;) {
+            if (rs[0].done && rs[1].done) break;
+            const bool live = !rs[r].done;
+            int64_t bg[2] = {0, 0};
+            uint64_t bh[2] = {0, 0};
+            int32_t bv[2] = {-1, -1};
+            if (live) {
+                const int32_t qn = rs[r].qn;
+                for (int32_t i = lt; i < qn; i += FM_HALF) {
+                    const int32_t v = q_r[i];
+                    if (st_r[v] != 1) continue;
+                    const int sd = A.part[v] == b;
+                    const int64_t g = gain_r[v];
+                    const uint64_t h = mix64(rseed ^ (uint64_t)(uint32_t)v);
+                    if (key_above(g, h, v, bg[sd], bh[sd], bv[sd])) { bg[sd] = g; bh[sd] = h; bv[sd] = v; }
+                }
+            }
+            for (int sd = 0; sd < 2; ++sd) {
+                wave_best(bg[sd], bh[sd], bv[sd]);
+                if (lane == 0) { s_wg[r][sd][wv] = bg[sd]; s_wh[r][sd][wv] = bh[sd]; s_wv[r][sd][wv] = bv[sd]; }
+            }
+            __syncthreads();
+            if (lt == 0 && live) {
+                RunState &R = rs[r];
+                int64_t tg[2];
+                uint64_t th[2];
+                int32_t tv[2];
+                for (int sd = 0; sd < 2; ++sd) {
+                    tg[sd] = 0; th[sd] = 0; tv[sd] = -1;
+                    for (int x = 0; x < FM_WAVES; ++x)
+                        if (key_above(s_wg[r][sd][x], s_wh[r][sd][x], s_wv[r][sd][x], tg[sd], th[sd], tv[sd])) {
+                            tg[sd] = s_wg[r][sd][x]; th[sd] = s_wh[r][sd][x]; tv[sd] = s_wv[r][sd][x];
+                        }
+                }
+                if (tv[0] < 0 && tv[1] < 0) {
+                    R.done = 1;
+                    R.v = -1;
+                } else {
+                    int from;
+                    const bool over = S * R.w[0] > L || S * R.w[1] > L;
+                    if (over && R.w[0] != R.w[1]) {
+                        from = R.w[0] > R.w[1] ? 0 : 1;
+                        if (tv[from] < 0) from = 1 - from;
+                    } else if (tv[0] < 0 || tv[1] < 0) {
+                        from = tv[0] < 0 ? 1 : 0;
+                    } else {
+                        from = key_above(tg[0], th[0], tv[0], tg[1], th[1], tv[1]) ? 0 : 1;
+                    }
+                    const int32_t v = tv[from];
+                    const int to = 1 - from;
+                    st_r[v] = 2;
+                    const int64_t cv = A.vw[v];
+                    R.w[from] -= cv;
+                    R.w[to] += cv;
+                    R.cnt[from] -= 1;
+                    R.cnt[to] += 1;
+                    R.cut -= tg[from];
+                    m_r[R.m++] = v;
+                    R.v = v;
+                    R.to = to;
+                    const int64_t imb = pair_imb(R.w[0], R.w[1], S, L);
+                    if (state_below(imb, R.cut, R.best_imb, R.best_cut)) {
+                        R.best_imb = imb; R.best_cut = R.cut;
+                        R.best_w[0] = R.w[0]; R.best_w[1] = R.w[1];
+                        R.best_cnt[0] = R.cnt[0]; R.best_cnt[1] = R.cnt[1];
+                        R.kept = R.m;
+                        R.since = 0;
+                    } else {
+                        R.since += 1;
+                    }
+                    if (R.since * (int64_t)A.alpha_den > (int64_t)A.alpha_num * smaller) R.done = 1;
+                }
+            }
+            __syncthreads();
+            // neighbours of the moved node (its own side is not re-read: it is moved)
+            const int32_t v = live ? rs[r].v : -1;
+            if (v >= 0) {
+                const int to = rs[r].to;
+                for (int64_t e = A.xadj[v] + lt; e < A.xadj[v + 1]; e += FM_HALF) {
+                    const int32_t u = A.adj[e];
+                    const int32_t pu = A.part[u];
+                    if (pu != a && pu != b) continue;
+                    if (st_r[u] == 2) continue;
+                    const int su = pu == b;
+                    gain_r[u] += su == to ? -2 * (int64_t)A.ew[e] : 2 * (int64_t)A.ew[e];
+                    if (st_r[u] == 0 && A.dist[u] >= 0) {
+                        st_r[u] = 1;
+                        q_r[atomicAdd(&rs[r].qn, 1)] = u;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // adopt the better run if it improves on the start
+        if (tid == 0) {
+            const int rb = state_below(rs[1].best_imb, rs[1].best_cut, rs[0].best_imb, rs[0].best_cut) ? 1 : 0;
+            const bool imp = state_below(rs[rb].best_imb, rs[rb].best_cut, start_imb, start_cut);
+            atomicAdd(&A.ctl->stats[1], 2ull);
+            atomicAdd(&A.ctl->stats[2], (unsigned long long)(rs[0].m + rs[1].m));
+            if (imp) {
+                atomicAdd(&A.ctl->stats[3], (unsigned long long)rs[rb].kept);
+                atomicAdd(&A.ctl->stats[4], 1ull);
+                s_bw[0] = rs[rb].best_w[0];
+                s_bw[1] = rs[rb].best_w[1];
+                s_bc[0] = rs[rb].best_cnt[0];
+                s_bc[1] = rs[rb].best_cnt[1];
+                A.bw[a] = s_bw[0];
+                A.bw[b] = s_bw[1];
+                A.bc[a] = s_bc[0];
+                A.bc[b] = s_bc[1];
+            }
+            s_stop = imp ? 0 : 1;
+            s_pick = rb;
+        }
+        __syncthreads();
+        if (s_stop) break;
+        {
+            const int rb = s_pick;
+            const int32_t *mb = A.mlog + (size_t)rb * A.n + off;
+            const int32_t kept = rs[rb].kept;
+            for (int32_t i = tid; i < kept; i += FM_THREADS) {
+                const int32_t v = mb[i];
+                A.part[v] = A.part[v] == a ? b : a;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+void launch_refine_weights(const int32_t *part, const uint32_t *vw, int32_t n, int32_t k,
+                           int64_t *bw, int32_t *bc, RefineCtl *ctl, hipStream_t s) {
+    KAPPA_PROF("refine_weights", s);
+    hipLaunchKernelGGL(ref_weights_k, dim3(grid_for(n, RQ_THREADS * 8, 1024)), dim3(RQ_THREADS), 0,
+                       s, part, vw, n, k, bw, bc, ctl);
+}
+
+void launch_refine_colouring(const int64_t *xadj, const int32_t *adj, const int32_t *part,
+                             int32_t n, int32_t k, unsigned long long *qbits, int32_t *tmp_pair,
+                             int32_t *tmp_col, int32_t *cpairs, int32_t *col_off, int32_t *fill,
+                             RefineCtl *ctl, hipStream_t s) {
+    {
+        KAPPA_PROF("refine_quotient", s);
+        hipLaunchKernelGGL(ref_quotient_k, dim3(grid_for(n, RQ_THREADS * 8, 1024)),
+                           dim3(RQ_THREADS), 0, s, xadj, adj, part, n, k, qbits);
+    }
+    KAPPA_PROF("refine_colour", s);
+    hipLaunchKernelGGL(ref_colour_k, dim3(1), dim3(RQ_THREADS), 0, s, qbits, k, tmp_pair, tmp_col,
+                       cpairs, col_off, fill, ctl);
+}
+
+void launch_refine_colour(const RefineLaunch &R, int32_t gi, int32_t c, int32_t npairs,
+                          hipStream_t s) {
+    {
+        KAPPA_PROF("refine_collect", s);
+        hipLaunchKernelGGL(ref_collect_k, dim3(grid_for(R.n, RQ_THREADS * RC_ITEMS, 1u << 30)),
+                           dim3(RQ_THREADS), 0, s, R.part, R.n, R.k, c, R.cpairs, R.col_off, R.bc,
+                           R.fill, R.poff, R.region);
+    }
+    FmArgs A;
+    A.xadj = R.xadj; A.adj = R.adj; A.ew = R.ew; A.vw = R.vw; A.part = R.part;
+    A.n = R.n; A.k = R.k; A.eps_num = R.eps_num; A.eps_den = R.eps_den; A.seed = R.seed;
+    A.alpha_num = R.alpha_num; A.alpha_den = R.alpha_den; A.depth = R.depth;
+    A.max_local = R.max_local; A.cpairs = R.cpairs; A.col_off = R.col_off; A.poff = R.poff;
+    A.fill = R.fill;
+    A.bw = R.bw;
+    A.bc = R.bc; A.region = R.region; A.dist = R.dist; A.gain = R.gain; A.status = R.status;
+    A.qlist = R.qlist; A.mlog = R.mlog; A.ctl = R.ctl;
+    KAPPA_PROF("refine_fm", s);
+    hipLaunchKernelGGL(ref_fm_k, dim3(npairs), dim3(FM_THREADS), 0, s, A, gi, c);
+}
+
+}  // namespace kappa

@@ -803,4 +803,51 @@ void launch_level_extend(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, int
 // Contraction only (level phase PH_CONTRACT, mate set), e.g. for kappa_contract.
 void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, hipStream_t s);
 
+
+// ---- pairwise refinement (k_refine.hip) -----------------------------------
+constexpr int REFINE_K_MAX = 256;                  // blocks
+constexpr int REFINE_QW = REFINE_K_MAX / 64;       // bitmap words per row of Q
+constexpr int REFINE_COLOURS = 512;                // greedy colouring needs at most 2k - 3
+constexpr int REFINE_CW = REFINE_COLOURS / 64;
+
+struct RefineCtl {
+    unsigned long long total;     // c(V)
+    unsigned long long max_node;  // max_v c(v)
+    uint32_t flags;               // 1: a block id outside [0, k); 2: block counts disagree with part
+    int32_t ncol, npairs, pad;
+    unsigned long long stats[6];  // [1] searches, [2] moves, [3] kept, [4] adoptions
+};
+
+struct RefineLaunch {
+    const int64_t *xadj;
+    const int32_t *adj;
+    const uint32_t *ew;
+    const uint32_t *vw;
+    int32_t *part;
+    int32_t n, k;
+    uint32_t eps_num, eps_den;
+    uint64_t seed;
+    uint32_t alpha_num, alpha_den;
+    int32_t depth, max_local;
+    int32_t *cpairs, *col_off, *poff, *fill;
+    int64_t *bw;
+    int32_t *bc;
+    int32_t *region, *dist;
+    int64_t *gain;
+    uint8_t *status;
+    int32_t *qlist, *mlog;
+    RefineCtl *ctl;
+};
+
+void launch_refine_weights(const int32_t *part, const uint32_t *vw, int32_t n, int32_t k,
+                           int64_t *bw, int32_t *bc, RefineCtl *ctl, hipStream_t s);
+// Q of the current partition and its greedy colouring (qbits must be zero).
+void launch_refine_colouring(const int64_t *xadj, const int32_t *adj, const int32_t *part,
+                             int32_t n, int32_t k, unsigned long long *qbits, int32_t *tmp_pair,
+                             int32_t *tmp_col, int32_t *cpairs, int32_t *col_off, int32_t *fill,
+                             RefineCtl *ctl, hipStream_t s);
+// the local searches of colour c (npairs pairs) of global iteration gi
+void launch_refine_colour(const RefineLaunch &R, int32_t gi, int32_t c, int32_t npairs,
+                          hipStream_t s);
+
 }  // namespace kappa
