@@ -130,10 +130,13 @@ def model_bytes(stats_by_rating):
 # library's profiler names
 KERNEL_SYMBOLS = {"pick": r"pick_k<\d, false, 0>", "mate": r"mate_k<\d, false>",
                   "pick_first": r"pick_k<\d, true, 0>", "fill_small": r"fill_small_k",
-                  "compact": r"compact_k", "cut_entries": r"up_entries_k<(true|false)>"}
+                  "compact": r"compact_k", "cut_entries": r"up_entries_k<(true|false)>",
+                  "refine_fm": r"ref_fm_k"}
 COUNTER_SOURCES = ["paper_0910_2004_amd/csrc/k_level.hip", "paper_0910_2004_amd/csrc/kappa_internal.h",
-                   "paper_0910_2004_amd/csrc/k_graph.hip"]
+                   "paper_0910_2004_amd/csrc/k_graph.hip", "paper_0910_2004_amd/csrc/k_refine.hip"]
 WORKLOAD_RGG = "rgg n=2^20 mean degree 8, both ratings, k=64, stop 1280"
+WORKLOAD_REFINE = ("the way back up with pairwise refinement (preset fast) on the expansion*2 "
+                   "hierarchy of rgg n=2^20 mean degree 8, k=64, stop 1280")
 
 
 def _short_name(name):
@@ -174,12 +177,13 @@ def summarize_pmc(kernel, fetch_dir, write_dir, bench_cmd):
     traffic = res["FETCH_SIZE"]["scaled_bytes_per_launch"] + res["WRITE_SIZE"]["scaled_bytes_per_launch"]
     cmds = [f"cd /tmp && timeout -s KILL 120 rocprofv3 --pmc {c} --kernel-trace -d <out> -o run "
             f"--output-format csv -- python3 <repo>/{bench_cmd}" for c in ("FETCH_SIZE", "WRITE_SIZE")]
-    rec = {"kernel": kernel, "workload": WORKLOAD_RGG, "counters": res,
+    workload = WORKLOAD_REFINE if kernel.startswith("refine") else WORKLOAD_RGG
+    rec = {"kernel": kernel, "workload": workload, "counters": res,
            "traffic_bytes_per_launch": traffic, "sources": COUNTER_SOURCES,
            "sources_sha256": _sources_sha(), "commands": cmds}
     with open(os.path.join(ROOT, "profiles", f"{kernel}_counters.json"), "w") as f:
         json.dump(rec, f, indent=1)
-    lines = [f"# HBM traffic of `{kernel}` ({KERNEL_SYMBOLS[kernel]}): {WORKLOAD_RGG}", "",
+    lines = [f"# HBM traffic of `{kernel}` ({KERNEL_SYMBOLS[kernel]}): {workload}", "",
              "Commands (one counter per run; `<repo>` is the repository root):", ""]
     lines += ["    " + c for c in cmds]
     lines += ["", "Summarised by `python bench.py --summarize-pmc " + kernel + " <fetch dir> <write dir>`.",
@@ -238,10 +242,15 @@ def main():
                          "steps (kappa_rcb_order + kappa_relabel, timed apart)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-out", default=None)
-    ap.add_argument("--workload", default="rgg20", choices=["rgg20", "rmat22", "batch4096", "serve"],
+    ap.add_argument("--workload", default="rgg20",
+                    choices=["rgg20", "rmat22", "batch4096", "serve", "refine"],
                     help="rgg20: the headline single-graph workload; batch4096: the batched "
                          "form on 4096 uneven graphs, against a loop of single calls; serve: "
-                         "the served form on a Poisson request stream, against FIFO single calls")
+                         "the served form on a Poisson request stream, against FIFO single "
+                         "calls; refine: the way back up with pairwise refinement (Section 5) "
+                         "on the rgg20 hierarchy")
+    ap.add_argument("--preset", default="fast", choices=["minimal", "fast", "strong"],
+                    help="refine: the refinement preset of Table 2")
     ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
     ap.add_argument("--no-plain-loop", action="store_true",
                     help="batch4096: skip the loop of single calls")
@@ -282,6 +291,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "refine":
+        return bench_refine(args)
 
     n = 1 << args.scale
     k = args.k
@@ -548,6 +559,132 @@ def bench_batch(args):
         "speedup_vs_plain_loop": None if plain is None else round(plain / ms, 2),
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_refine(args):
+    """The way back up with pairwise refinement (Section 5) on the hierarchy
+    of the rgg20 workload (n = 2^scale, mean degree 8, expansion*2, k = 64,
+    stop at 20 k nodes), built once before the timed steps.  A step is one
+    kappa_uncoarsen_refined call: the stand-in coarsest partition, then per
+    level projection, refinement (Table 2 preset) and cut/balance.  The
+    plain way back up (projection only) is timed beside it."""
+    import numpy as np
+    import torch
+
+    import paper_0910_2004_amd as K
+    from workloads import rgg
+
+    n, k = 1 << args.scale, args.k
+    stop_n, eps, seed, part_seed, rseed = 20 * k, (3, 100), 42, 1, 1
+    t0 = time.time()
+    g = rgg(n, seed=2)
+    torch.cuda.set_device(0)
+    dg = K.DeviceGraph.from_csr(g, "cuda:0")
+    H = K.kappa_coarsen(dg, K.EXPANSION_STAR2, seed, stop_n)
+    part0 = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    log(f"rgg n={n} |E|={g.m}, {len(H)} levels in {time.time() - t0:.1f}s")
+
+    def step():
+        return K.kappa_uncoarsen_refined(H, k, part_seed, eps[0], eps[1], args.preset, rseed,
+                                         part0=part0)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        _, res, st = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) * 1e3 / args.steps
+    tp = time.perf_counter()
+    for _ in range(args.steps):
+        _, plain = K.kappa_uncoarsen(H, k, part_seed, eps[0], eps[1])
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - tp) * 1e3 / args.steps
+
+    K.profile_reset()
+    K.profile_enable(True)
+    torch.cuda.synchronize()
+    step()
+    torch.cuda.synchronize()
+    K.profile_enable(False)
+    prof = K.profile_read()
+    K.profile_reset()
+    kern = sorted(prof.items(), key=lambda kv: -kv[1][1])
+    log("kernel time per step (ms), launches per step:")
+    for name, (cnt, kms) in kern:
+        log(f"  {name:20s} {kms:8.3f} ms  {cnt:7.0f}")
+    total_ms = sum(kms for _, kms in prof.values())
+    cnt, fm_ms = prof.get("refine_fm", (0, 0.0))
+    fm_bytes = sum(x["bytes"] for x in st)
+    moves = sum(x["moves"] for x in st)
+    roof = None
+    if cnt:
+        avg_s = fm_ms / cnt / 1e3
+        achieved = fm_bytes / cnt / avg_s / 1e9
+        traffic = counter_traffic("refine_fm") if (args.scale, k, args.preset) == (20, 64, "fast") \
+            else None
+        roof = {"bound": "hbm", "kernel": "refine_fm", "achieved": round(achieved, 2),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": None if traffic is None else int(traffic),
+                "avg_launch_us": round(avg_s * 1e6, 2),
+                "bytes_per_launch": int(fm_bytes / cnt),
+                "model": "per local search 40 B per node of the two blocks + 12 B per row entry; "
+                         "per move 17 B per queued node scanned + 25 B per entry of the moved "
+                         "node's row; 12 B per kept move (counted by the kernel)",
+                "time_share": round(fm_ms / total_ms, 3),
+                "dominant_kernel": kern[0][0],
+                "us_per_move_step": round(fm_ms * 1e3 / max(1, moves / 2), 3)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        gs = rgg(1 << 16, seed=2)
+        OH = O.coarsen(gs, O.EXPANSION_STAR2, seed, stop_n)
+        prm = O.RefineParams(seed=rseed, **K.REFINE_PRESETS[args.preset])
+        t3 = time.perf_counter()
+        O.uncoarsen_refined(OH, k, part_seed, eps[0], eps[1], prm)
+        t4 = time.perf_counter()
+        cpu = {"value": round(gs.m / (t4 - t3), 1), "unit": "edges/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"rgg n=2^16 (|E|={gs.m}), same generator, k={k}, the way back up with "
+                         f"refinement on one host thread; {t4 - t3:.2f} s",
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    out = {
+        "metric": "refined uncoarsening edges/s per GPU (level-0 edges)",
+        "value": round(g.m / (ms / 1e3), 1),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64 gains, exact integer balance",
+        "data": "synthetic",
+        "config": {"workload": f"rgg n=2^{args.scale} mean degree 8, unit weights, expansion*2 "
+                               f"hierarchy (stop n<={stop_n}), k={k}, eps=3/100, pairwise "
+                               f"refinement preset {args.preset}",
+                   "n": g.n, "m": g.m, "levels": len(H), "preset": args.preset,
+                   "params": K.REFINE_PRESETS[args.preset]},
+        "cut_refined": int(res[0].cut), "cut_projected": int(plain[0].cut),
+        "feasible": bool(res[0].feasible), "max_block": int(res[0].max_block),
+        "plain_uncoarsen_ms": round(plain_ms, 3),
+        "refine_stats": {key: sum(x[key] for x in st) for key in st[0]},
+        "refine_levels": [[H.info(l).n, x["searches"], x["moves"], round(x["init_ticks"] / 1e5, 1),
+                           round(x["move_ticks"] / 1e5, 1)] for l, x in enumerate(st)],
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernel_ms_per_step": {name: round(kms, 4) for name, (c, kms) in kern},
+    }
+    if args.copy_calibration:
+        a = torch.ones(64 << 20, dtype=torch.int32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {a.numel() * 4} bytes read and written")
     print(json.dumps(out), flush=True)
 
 

@@ -338,6 +338,14 @@ typedef struct {
     int64_t kept;              /* moves kept after the rollbacks of adopted searches */
     int64_t adoptions;         /* local iterations whose better search improved the pair */
     int64_t colours;           /* colours of Q summed over the global iterations */
+    int64_t bytes;             /* memory the local searches touch, by a fixed model (for
+                                  measurement): per search 40 B per node of the two blocks
+                                  + 12 B per entry of their rows; per move 17 B per queued
+                                  node scanned + 25 B per entry of the moved node's row;
+                                  12 B per kept move of an adopted search */
+    int64_t init_ticks;        /* device wall-clock ticks (100 MHz) that the pair workgroups spent
+                                  preparing searches (gains, boundary, BFS), summed over them */
+    int64_t move_ticks;        /* the same for the moves, rollbacks and adoptions */
 } kappa_refine_stats;
 
 /* Pairwise refinement of the k-way partition part (Section 5), in place.

@@ -70,7 +70,8 @@ class c_refine_params(ctypes.Structure):
 
 class c_refine_stats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in ("global_iterations", "searches", "moves", "kept",
-                                               "adoptions", "colours")]
+                                               "adoptions", "colours", "bytes", "init_ticks",
+                                               "move_ticks")]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -1654,12 +1654,17 @@ kappa_status refine_impl(const DevGraph &d, int32_t *part, int32_t k, uint32_t e
             R.status = cv.get<uint8_t>(2 * n);
             R.qlist = cv.get<int32_t>(2 * n);
             R.mlog = cv.get<int32_t>(2 * n);
+            R.slot = cv.get<int32_t>(2 * n);
         }))
         return KAPPA_E_NOMEM;
     R.xadj = d.xadj; R.adj = d.adj; R.ew = d.ew; R.vw = d.vw; R.part = part;
     R.n = d.n; R.k = k; R.eps_num = eps_num; R.eps_den = eps_den; R.seed = p->seed;
     R.alpha_num = p->alpha_num; R.alpha_den = p->alpha_den; R.depth = p->depth;
     R.max_local = p->max_local;
+    // KAPPA_REFINE_QCAP (tests): fewer on-chip queue entries, to exercise the
+    // entries kept in memory
+    const char *qc = getenv("KAPPA_REFINE_QCAP");
+    R.qcap = qc ? atoi(qc) : -1;
     R.ctl = &head->ctl;
     R.col_off = head->col_off;
     {
@@ -1713,6 +1718,9 @@ kappa_status refine_impl(const DevGraph &d, int32_t *part, int32_t k, uint32_t e
     st.moves = (int64_t)rb->ctl.stats[2];
     st.kept = (int64_t)rb->ctl.stats[3];
     st.adoptions = (int64_t)rb->ctl.stats[4];
+    st.bytes = (int64_t)rb->ctl.stats[5];
+    st.init_ticks = (int64_t)rb->ctl.stats[6];
+    st.move_ticks = (int64_t)rb->ctl.stats[7];
     if (out) *out = st;
     return KAPPA_OK;
 }

@@ -29,13 +29,12 @@
 
 namespace kappa {
 
-namespace {
-
 constexpr int RQ_THREADS = 256;
 constexpr int RC_ITEMS = 16;           // nodes per thread in collect
 constexpr int FM_THREADS = 1024;       // two halves of 512, one per run
 constexpr int FM_HALF = FM_THREADS / 2;
 constexpr int FM_WAVES = FM_HALF / WAVE;
+constexpr int FM_QCAP = 2048;          // queue entries per run kept in LDS (the rest in memory)
 
 __device__ __forceinline__ uint64_t run_seed_of(uint64_t seed, int32_t g, int32_t a, int32_t b,
                                                 int32_t t, int32_t r) {
@@ -239,23 +238,49 @@ struct FmArgs {
     int32_t *dist;
     int64_t *gain;       // [2][n]
     uint8_t *status;     // [2][n]: 0 idle, 1 queued, 2 moved
-    int32_t *qlist;      // [2][n] region-relative
+    int32_t *qlist;      // [2][n] region-relative; entries from qcap on
     int32_t *mlog;       // [2][n] region-relative
+    int32_t *slot;       // [2][n]: queue position of a queued node
+    int32_t qcap;        // queue positions below qcap live in LDS (<= FM_QCAP)
     RefineCtl *ctl;
 };
 
 // per-run state of one local search, in LDS
+// a finished search, published for the adoption
 struct RunState {
-    int64_t w[2], cut, best_imb, best_cut, best_w[2], since;
-    int32_t cnt[2], best_cnt[2], qn, m, kept, done, v, to;
+    int64_t best_imb, best_cut, best_w[2];
+    int32_t best_cnt[2], qn, m, kept;
 };
 
-__device__ __forceinline__ void wave_best(int64_t &g, uint64_t &h, int32_t &v) {
+// a thread's best queue entry of one block under (gain, hash, id); the hash
+// is computed only when gains tie
+struct Best {
+    int64_t g = 0;
+    uint64_t h = 0;
+    int32_t v = -1, q = -1;
+    bool hv = false;
+    __device__ __forceinline__ void offer(int64_t g2, int32_t v2, int32_t q2, uint64_t seed) {
+        if (v < 0 || g2 > g) {
+            g = g2; v = v2; q = q2; hv = false;
+        } else if (g2 == g) {
+            if (!hv) { h = mix64(seed ^ (uint64_t)(uint32_t)v); hv = true; }
+            const uint64_t h2 = mix64(seed ^ (uint64_t)(uint32_t)v2);
+            if (h2 > h || (h2 == h && v2 < v)) { h = h2; v = v2; q = q2; }
+        }
+    }
+    __device__ __forceinline__ void finish(uint64_t seed) {
+        if (v >= 0 && !hv) { h = mix64(seed ^ (uint64_t)(uint32_t)v); hv = true; }
+    }
+};
+
+// the wave's best (gain, hash, id), carrying the queue position
+__device__ __forceinline__ void wave_best(int64_t &g, uint64_t &h, int32_t &v, int32_t &q) {
     for (int o = WAVE / 2; o > 0; o >>= 1) {
         const int64_t g2 = __shfl_xor(g, o);
         const uint64_t h2 = __shfl_xor(h, o);
         const int32_t v2 = __shfl_xor(v, o);
-        if (key_above(g2, h2, v2, g, h, v)) { g = g2; h = h2; v = v2; }
+        const int32_t q2 = __shfl_xor(q, o);
+        if (key_above(g2, h2, v2, g, h, v)) { g = g2; h = h2; v = v2; q = q2; }
     }
 }
 
@@ -264,14 +289,27 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
     __shared__ int64_t s_wg[2][2][FM_WAVES];
     __shared__ uint64_t s_wh[2][2][FM_WAVES];
     __shared__ int32_t s_wv[2][2][FM_WAVES];
-    __shared__ int32_t s_off, s_len, s_na, s_nb, s_changed, s_stop, s_pick, s_bc[2];
+    __shared__ int32_t s_wq[2][2][FM_WAVES];
+    // queue entries below qcap: gain, node, bit 0 side (1: block b), bit 1 moved
+    // with c(v), the row start and the degree, so that a move needs no memory
+    // access before the neighbours' rows
+    __shared__ int64_t q_g[2][FM_QCAP];
+    __shared__ int64_t q_x[2][FM_QCAP];
+    __shared__ int32_t q_v[2][FM_QCAP];
+    __shared__ uint32_t q_c[2][FM_QCAP];
+    __shared__ int32_t q_d[2][FM_QCAP];
+    __shared__ uint8_t q_s[2][FM_QCAP];
+    __shared__ int32_t s_off, s_len, s_na, s_nb, s_nf, s_stop, s_pick, s_bc[2];
+    __shared__ int32_t s_done[2], s_v[2], s_to[2], s_deg[2];
+    __shared__ int64_t s_x0[2];
     __shared__ int64_t s_bw[2];
-    __shared__ unsigned long long s_cut;
+    __shared__ unsigned long long s_cut, s_bytes;
     const int32_t j = blockIdx.x, p = A.col_off[c] + j;
     const int32_t a = A.cpairs[p] & 0xffff, b = A.cpairs[p] >> 16;
     const int tid = threadIdx.x, r = tid / FM_HALF, lt = tid % FM_HALF;
     const int lane = lt % WAVE, wv = lt / WAVE;
     if (tid == 0) {
+        s_bytes = 0;
         s_off = A.poff[p];
         s_bc[0] = A.bc[a];
         s_bc[1] = A.bc[b];
@@ -293,12 +331,26 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
     uint8_t *st_r = A.status + (size_t)r * A.n;
     int32_t *q_r = A.qlist + (size_t)r * A.n + off;
     int32_t *m_r = A.mlog + (size_t)r * A.n + off;
+    int32_t *sl_r = A.slot + (size_t)r * A.n;
+    const int32_t qcap = A.qcap;
+    int64_t *qg = q_g[r], *qx = q_x[r];
+    int32_t *qv = q_v[r], *qd = q_d[r];
+    uint32_t *qcw = q_c[r];
+    uint8_t *qs = q_s[r];
 
+    unsigned long long ticks_init = 0, ticks_moves = 0, t0 = 0;
+    // the BFS frontiers use the two move logs, which are free until the moves
+    int32_t *fr[2] = {A.mlog + off, A.mlog + (size_t)A.n + off};
     for (int32_t t = 0; t < A.max_local; ++t) {
-        // gains, boundary, cut, node counts of the current partition
-        if (tid == 0) { s_cut = 0; s_na = 0; s_nb = 0; rs[0].qn = rs[1].qn = 0; }
+        if (tid == 0) {
+            s_cut = 0; s_na = 0; s_nb = 0; s_nf = 0;
+            rs[0].qn = rs[1].qn = 0;
+            t0 = wall_clock64();
+        }
         __syncthreads();
-        unsigned long long cut = 0;
+        // gains, boundary, cut and node counts of the current partition; the
+        // boundary is the BFS's first frontier
+        unsigned long long cut = 0, touched = 0;
         int32_t na = 0, nb = 0;
         for (int32_t i = tid; i < len; i += FM_THREADS) {
             const int32_t v = reg[i], pv = A.part[v];
@@ -320,158 +372,239 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
             A.status[v] = 0;
             A.status[(size_t)A.n + v] = 0;
             A.dist[v] = bnd ? 0 : -1;
+            if (bnd) fr[0][atomicAdd(&s_nf, 1)] = v;
             if (pv == a) ++na; else ++nb;
+            touched += 40 + 12 * (unsigned long long)(A.xadj[v + 1] - A.xadj[v]);
         }
+        atomicAdd(&s_bytes, touched);
         atomicAdd(&s_cut, cut);
         atomicAdd(&s_na, na);
         atomicAdd(&s_nb, nb);
         __syncthreads();
-        // bounded BFS inside each block from its boundary
-        for (int32_t d = 1; d <= A.depth; ++d) {
-            if (tid == 0) s_changed = 0;
+        // bounded BFS inside each block, one frontier per distance
+        int32_t nf = s_nf;
+        for (int32_t d = 1; d <= A.depth && nf > 0; ++d) {
+            const int32_t *cur = fr[(d - 1) & 1];
+            int32_t *nxt = fr[d & 1];
+            if (tid == 0) s_nf = 0;
             __syncthreads();
-            bool ch = false;
-            for (int32_t i = tid; i < len; i += FM_THREADS) {
-                const int32_t v = reg[i];
-                if (A.dist[v] >= 0) continue;
-                const int32_t pv = A.part[v];
+            for (int32_t i = tid; i < nf; i += FM_THREADS) {
+                const int32_t v = cur[i], pv = A.part[v];
                 for (int64_t e = A.xadj[v]; e < A.xadj[v + 1]; ++e) {
                     const int32_t u = A.adj[e];
-                    if (A.part[u] == pv && A.dist[u] == d - 1) { A.dist[v] = d; ch = true; break; }
+                    if (A.part[u] == pv && atomicCAS(&A.dist[u], -1, d) == -1)
+                        nxt[atomicAdd(&s_nf, 1)] = u;
                 }
             }
-            if (ch) s_changed = 1;
             __syncthreads();
-            const bool more = s_changed != 0;
-            __syncthreads();   // everyone has read the flag before it is cleared again
-            if (!more) break;
+            nf = s_nf;
+            __syncthreads();   // everyone has read the count before it is cleared
         }
         // both runs: queues start with the boundary
         for (int32_t i = lt; i < len; i += FM_HALF) {
             const int32_t v = reg[i];
             if (A.dist[v] == 0) {
                 st_r[v] = 1;
-                q_r[atomicAdd(&rs[r].qn, 1)] = v;
+                const int32_t pos = atomicAdd(&rs[r].qn, 1);
+                sl_r[v] = pos;
+                if (pos < qcap) {
+                    qv[pos] = v;
+                    qg[pos] = gain_r[v];
+                    qs[pos] = A.part[v] == b;
+                    qx[pos] = A.xadj[v];
+                    qd[pos] = (int32_t)(A.xadj[v + 1] - A.xadj[v]);
+                    qcw[pos] = A.vw[v];
+                } else {
+                    q_r[pos] = v;
+                }
             }
         }
-        if (lt == 0) {
-            RunState &R = rs[r];
-            R.w[0] = s_bw[0];
-            R.w[1] = s_bw[1];
-            R.cnt[0] = s_na;
-            R.cnt[1] = s_nb;
-            R.cut = (int64_t)s_cut;
-            R.best_imb = pair_imb(R.w[0], R.w[1], S, L);
-            R.best_cut = R.cut;
-            R.best_w[0] = R.w[0]; R.best_w[1] = R.w[1];
-            R.best_cnt[0] = R.cnt[0]; R.best_cnt[1] = R.cnt[1];
-            R.since = 0; R.m = 0; R.kept = 0; R.done = 0; R.v = -1;
-        }
+        if (tid == 0) { s_done[0] = 0; s_done[1] = 0; }
         __syncthreads();
-        const int64_t start_imb = rs[0].best_imb, start_cut = rs[0].best_cut;
         const int64_t smaller = min(s_na, s_nb);
+        const int64_t start_imb = pair_imb(s_bw[0], s_bw[1], S, L), start_cut = (int64_t)s_cut;
         const uint64_t rseed = run_seed_of(A.seed, gi, a, b, t, r);
+        // the state of a search, kept in the registers of its half's lane 0
+        int64_t w0 = s_bw[0], w1 = s_bw[1], cur_cut = start_cut, best_imb = start_imb;
+        int64_t best_cut = start_cut, bw0 = w0, bw1 = w1, since = 0;
+        int32_t c0 = s_na, c1 = s_nb, bc0 = c0, bc1 = c1, m = 0, kept = 0;
+        if (tid == 0) {
+            const unsigned long long t1 = wall_clock64();
+            ticks_init += t1 - t0;
+            t0 = t1;
+        }
         // the moves, both runs in lockstep
         for (;;) {
-            if (rs[0].done && rs[1].done) break;
-            const bool live = !rs[r].done;
-            int64_t bg[2] = {0, 0};
-            uint64_t bh[2] = {0, 0};
-            int32_t bv[2] = {-1, -1};
+            if (s_done[0] && s_done[1]) break;
+            const bool live = !s_done[r];
+            Best b0, b1;   // the best queued node of block a and of block b
             if (live) {
-                const int32_t qn = rs[r].qn;
-                for (int32_t i = lt; i < qn; i += FM_HALF) {
+                const int32_t qn = rs[r].qn, qc = min(qn, qcap);
+                for (int32_t i = lt; i < qc; i += FM_HALF) {
+                    const uint8_t st = qs[i];
+                    if (st & 2) continue;
+                    if (st & 1) b1.offer(qg[i], qv[i], i, rseed);
+                    else b0.offer(qg[i], qv[i], i, rseed);
+                }
+                for (int32_t i = qcap + lt; i < qn; i += FM_HALF) {
                     const int32_t v = q_r[i];
                     if (st_r[v] != 1) continue;
-                    const int sd = A.part[v] == b;
-                    const int64_t g = gain_r[v];
-                    const uint64_t h = mix64(rseed ^ (uint64_t)(uint32_t)v);
-                    if (key_above(g, h, v, bg[sd], bh[sd], bv[sd])) { bg[sd] = g; bh[sd] = h; bv[sd] = v; }
+                    if (A.part[v] == b) b1.offer(gain_r[v], v, i, rseed);
+                    else b0.offer(gain_r[v], v, i, rseed);
                 }
+                b0.finish(rseed);
+                b1.finish(rseed);
             }
-            for (int sd = 0; sd < 2; ++sd) {
-                wave_best(bg[sd], bh[sd], bv[sd]);
-                if (lane == 0) { s_wg[r][sd][wv] = bg[sd]; s_wh[r][sd][wv] = bh[sd]; s_wv[r][sd][wv] = bv[sd]; }
+            wave_best(b0.g, b0.h, b0.v, b0.q);
+            wave_best(b1.g, b1.h, b1.v, b1.q);
+            if (lane == 0) {
+                s_wg[r][0][wv] = b0.g; s_wh[r][0][wv] = b0.h; s_wv[r][0][wv] = b0.v; s_wq[r][0][wv] = b0.q;
+                s_wg[r][1][wv] = b1.g; s_wh[r][1][wv] = b1.h; s_wv[r][1][wv] = b1.v; s_wq[r][1][wv] = b1.q;
             }
             __syncthreads();
-            if (lt == 0 && live) {
-                RunState &R = rs[r];
-                int64_t tg[2];
-                uint64_t th[2];
-                int32_t tv[2];
-                for (int sd = 0; sd < 2; ++sd) {
-                    tg[sd] = 0; th[sd] = 0; tv[sd] = -1;
-                    for (int x = 0; x < FM_WAVES; ++x)
-                        if (key_above(s_wg[r][sd][x], s_wh[r][sd][x], s_wv[r][sd][x], tg[sd], th[sd], tv[sd])) {
-                            tg[sd] = s_wg[r][sd][x]; th[sd] = s_wh[r][sd][x]; tv[sd] = s_wv[r][sd][x];
-                        }
+            if (wv == 0 && live) {
+                // lanes 0-7 take side 0 of the half's eight waves, lanes 8-15 side 1
+                int64_t g = 0;
+                uint64_t h = 0;
+                int32_t v = -1, q = -1;
+                if (lane < 2 * FM_WAVES) {
+                    const int sd = lane / FM_WAVES, x = lane % FM_WAVES;
+                    g = s_wg[r][sd][x]; h = s_wh[r][sd][x]; v = s_wv[r][sd][x]; q = s_wq[r][sd][x];
                 }
-                if (tv[0] < 0 && tv[1] < 0) {
-                    R.done = 1;
-                    R.v = -1;
-                } else {
-                    int from;
-                    const bool over = S * R.w[0] > L || S * R.w[1] > L;
-                    if (over && R.w[0] != R.w[1]) {
-                        from = R.w[0] > R.w[1] ? 0 : 1;
-                        if (tv[from] < 0) from = 1 - from;
-                    } else if (tv[0] < 0 || tv[1] < 0) {
-                        from = tv[0] < 0 ? 1 : 0;
+                for (int o = FM_WAVES / 2; o > 0; o >>= 1) {
+                    const int64_t g2 = __shfl_xor(g, o);
+                    const uint64_t h2 = __shfl_xor(h, o);
+                    const int32_t v2 = __shfl_xor(v, o), q2 = __shfl_xor(q, o);
+                    if (key_above(g2, h2, v2, g, h, v)) { g = g2; h = h2; v = v2; q = q2; }
+                }
+                const int64_t g1 = __shfl(g, FM_WAVES);
+                const uint64_t h1 = __shfl(h, FM_WAVES);
+                const int32_t v1 = __shfl(v, FM_WAVES), q1 = __shfl(q, FM_WAVES);
+                if (lane == 0) {
+                    int32_t mv = -1;
+                    bool stop = false;
+                    if (v < 0 && v1 < 0) {
+                        stop = true;
                     } else {
-                        from = key_above(tg[0], th[0], tv[0], tg[1], th[1], tv[1]) ? 0 : 1;
+                        int from;
+                        const bool over = S * w0 > L || S * w1 > L;
+                        if (over && w0 != w1) {                           // MaxLoad
+                            from = w0 > w1 ? 0 : 1;
+                            if ((from ? v1 : v) < 0) from = 1 - from;
+                        } else if (v < 0 || v1 < 0) {
+                            from = v < 0 ? 1 : 0;
+                        } else {                                          // TopGain
+                            from = key_above(g, h, v, g1, h1, v1) ? 0 : 1;
+                        }
+                        mv = from ? v1 : v;
+                        const int32_t mq = from ? q1 : q;
+                        const int64_t mg = from ? g1 : g;
+                        const int to = 1 - from;
+                        st_r[mv] = 2;
+                        int64_t cv, x0;
+                        int32_t deg;
+                        if (mq < qcap) {
+                            qs[mq] |= 2;
+                            cv = qcw[mq];
+                            x0 = qx[mq];
+                            deg = qd[mq];
+                        } else {
+                            cv = A.vw[mv];
+                            x0 = A.xadj[mv];
+                            deg = (int32_t)(A.xadj[mv + 1] - x0);
+                        }
+                        if (from == 0) { w0 -= cv; w1 += cv; --c0; ++c1; }
+                        else { w1 -= cv; w0 += cv; --c1; ++c0; }
+                        cur_cut -= mg;
+                        m_r[m++] = mv;
+                        atomicAdd(&s_bytes, 17ull * (unsigned long long)rs[r].qn +
+                                                25ull * (unsigned long long)deg);
+                        s_to[r] = to;
+                        s_x0[r] = x0;
+                        s_deg[r] = deg;
+                        const int64_t imb = pair_imb(w0, w1, S, L);
+                        if (state_below(imb, cur_cut, best_imb, best_cut)) {
+                            best_imb = imb; best_cut = cur_cut;
+                            bw0 = w0; bw1 = w1;
+                            bc0 = c0; bc1 = c1;
+                            kept = m;
+                            since = 0;
+                        } else {
+                            since += 1;
+                        }
+                        if (since * (int64_t)A.alpha_den > (int64_t)A.alpha_num * smaller) stop = true;
                     }
-                    const int32_t v = tv[from];
-                    const int to = 1 - from;
-                    st_r[v] = 2;
-                    const int64_t cv = A.vw[v];
-                    R.w[from] -= cv;
-                    R.w[to] += cv;
-                    R.cnt[from] -= 1;
-                    R.cnt[to] += 1;
-                    R.cut -= tg[from];
-                    m_r[R.m++] = v;
-                    R.v = v;
-                    R.to = to;
-                    const int64_t imb = pair_imb(R.w[0], R.w[1], S, L);
-                    if (state_below(imb, R.cut, R.best_imb, R.best_cut)) {
-                        R.best_imb = imb; R.best_cut = R.cut;
-                        R.best_w[0] = R.w[0]; R.best_w[1] = R.w[1];
-                        R.best_cnt[0] = R.cnt[0]; R.best_cnt[1] = R.cnt[1];
-                        R.kept = R.m;
-                        R.since = 0;
-                    } else {
-                        R.since += 1;
-                    }
-                    if (R.since * (int64_t)A.alpha_den > (int64_t)A.alpha_num * smaller) R.done = 1;
+                    s_v[r] = mv;
+                    if (stop) s_done[r] = 1;
                 }
             }
             __syncthreads();
             // neighbours of the moved node (its own side is not re-read: it is moved)
-            const int32_t v = live ? rs[r].v : -1;
+            const int32_t v = live ? s_v[r] : -1;
             if (v >= 0) {
-                const int to = rs[r].to;
-                for (int64_t e = A.xadj[v] + lt; e < A.xadj[v + 1]; e += FM_HALF) {
+                const int to = s_to[r];
+                const int64_t x0 = s_x0[r], x1 = x0 + s_deg[r];
+                for (int64_t e = x0 + lt; e < x1; e += FM_HALF) {
                     const int32_t u = A.adj[e];
+                    const uint32_t wu = A.ew[e];
+                    // everything about u in one round of loads (some unused)
                     const int32_t pu = A.part[u];
+                    const uint8_t su_st = st_r[u];
+                    const int32_t du = A.dist[u];
+                    const int32_t sl = sl_r[u];
+                    const int64_t gu = gain_r[u];
+                    const int64_t ux0 = A.xadj[u], ux1 = A.xadj[u + 1];
+                    const uint32_t cu = A.vw[u];
                     if (pu != a && pu != b) continue;
-                    if (st_r[u] == 2) continue;
+                    if (su_st == 2) continue;
                     const int su = pu == b;
-                    gain_r[u] += su == to ? -2 * (int64_t)A.ew[e] : 2 * (int64_t)A.ew[e];
-                    if (st_r[u] == 0 && A.dist[u] >= 0) {
-                        st_r[u] = 1;
-                        q_r[atomicAdd(&rs[r].qn, 1)] = u;
+                    const int64_t delta = su == to ? -2 * (int64_t)wu : 2 * (int64_t)wu;
+                    if (su_st == 1) {
+                        if (sl < qcap) qg[sl] += delta;
+                        else gain_r[u] = gu + delta;
+                    } else {
+                        const int64_t g = gu + delta;
+                        if (du >= 0) {
+                            st_r[u] = 1;
+                            const int32_t pos = atomicAdd(&rs[r].qn, 1);
+                            sl_r[u] = pos;
+                            if (pos < qcap) {
+                                qv[pos] = u;
+                                qg[pos] = g;
+                                qs[pos] = (uint8_t)su;
+                                qx[pos] = ux0;
+                                qd[pos] = (int32_t)(ux1 - ux0);
+                                qcw[pos] = cu;
+                            } else {
+                                q_r[pos] = u;
+                                gain_r[u] = g;
+                            }
+                        } else {
+                            gain_r[u] = g;
+                        }
                     }
                 }
             }
             __syncthreads();
         }
+        // each half's lane 0 publishes its search
+        if (lt == 0) {
+            RunState &R = rs[r];
+            R.best_imb = best_imb; R.best_cut = best_cut;
+            R.best_w[0] = bw0; R.best_w[1] = bw1;
+            R.best_cnt[0] = bc0; R.best_cnt[1] = bc1;
+            R.kept = kept; R.m = m;
+        }
+        __syncthreads();
         // adopt the better run if it improves on the start
         if (tid == 0) {
+            ticks_moves += wall_clock64() - t0;
             const int rb = state_below(rs[1].best_imb, rs[1].best_cut, rs[0].best_imb, rs[0].best_cut) ? 1 : 0;
             const bool imp = state_below(rs[rb].best_imb, rs[rb].best_cut, start_imb, start_cut);
             atomicAdd(&A.ctl->stats[1], 2ull);
             atomicAdd(&A.ctl->stats[2], (unsigned long long)(rs[0].m + rs[1].m));
             if (imp) {
+                s_bytes += 12ull * (unsigned long long)rs[rb].kept;
                 atomicAdd(&A.ctl->stats[3], (unsigned long long)rs[rb].kept);
                 atomicAdd(&A.ctl->stats[4], 1ull);
                 s_bw[0] = rs[rb].best_w[0];
@@ -491,17 +624,20 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
         {
             const int rb = s_pick;
             const int32_t *mb = A.mlog + (size_t)rb * A.n + off;
-            const int32_t kept = rs[rb].kept;
-            for (int32_t i = tid; i < kept; i += FM_THREADS) {
+            const int32_t kk = rs[rb].kept;
+            for (int32_t i = tid; i < kk; i += FM_THREADS) {
                 const int32_t v = mb[i];
                 A.part[v] = A.part[v] == a ? b : a;
             }
         }
         __syncthreads();
     }
+    if (tid == 0) {
+        atomicAdd(&A.ctl->stats[5], s_bytes);
+        atomicAdd(&A.ctl->stats[6], ticks_init);
+        atomicAdd(&A.ctl->stats[7], ticks_moves);
+    }
 }
-
-}  // namespace
 
 void launch_refine_weights(const int32_t *part, const uint32_t *vw, int32_t n, int32_t k,
                            int64_t *bw, int32_t *bc, RefineCtl *ctl, hipStream_t s) {
@@ -541,6 +677,8 @@ void launch_refine_colour(const RefineLaunch &R, int32_t gi, int32_t c, int32_t 
     A.bw = R.bw;
     A.bc = R.bc; A.region = R.region; A.dist = R.dist; A.gain = R.gain; A.status = R.status;
     A.qlist = R.qlist; A.mlog = R.mlog; A.ctl = R.ctl;
+    A.slot = R.slot;
+    A.qcap = R.qcap < 0 || R.qcap > FM_QCAP ? FM_QCAP : R.qcap;
     KAPPA_PROF("refine_fm", s);
     hipLaunchKernelGGL(ref_fm_k, dim3(npairs), dim3(FM_THREADS), 0, s, A, gi, c);
 }

@@ -815,7 +815,8 @@ struct RefineCtl {
     unsigned long long max_node;  // max_v c(v)
     uint32_t flags;               // 1: a block id outside [0, k); 2: block counts disagree with part
     int32_t ncol, npairs, pad;
-    unsigned long long stats[6];  // [1] searches, [2] moves, [3] kept, [4] adoptions
+    unsigned long long stats[8];  // [1] searches, [2] moves, [3] kept, [4] adoptions, [5] bytes,
+                                  // [6] / [7] clock ticks in initialisation / moves
 };
 
 struct RefineLaunch {
@@ -835,7 +836,8 @@ struct RefineLaunch {
     int32_t *region, *dist;
     int64_t *gain;
     uint8_t *status;
-    int32_t *qlist, *mlog;
+    int32_t *qlist, *mlog, *slot;
+    int32_t qcap;   // queue entries per search kept on chip (-1: the kernel's maximum)
     RefineCtl *ctl;
 };
 

@@ -46,6 +46,7 @@ def check_refine(g, part, k, preset="fast", seed=1, eps=(3, 100), what="", **ove
     st = K.kappa_refine(dev(g), p, k, eps[0], eps[1], preset, seed, **over)
     got = p.cpu().numpy()[:g.n]
     assert np.array_equal(got, want), f"{what}: partition differs ({(got != want).sum()} nodes)"
+    assert st.pop("bytes") >= 0 and st.pop("init_ticks") >= 0 and st.pop("move_ticks") >= 0
     assert st == wst, f"{what}: stats {st} != {wst}"
     return want, wst
 
@@ -106,6 +107,7 @@ def test_degenerate_and_errors():
     empty = csr_from_edges(0, np.zeros(0, np.int64), np.zeros(0, np.int64))
     st = K.kappa_refine(dev(empty), torch.zeros(1, dtype=torch.int32, device="cuda"), 4)
     wst = O.refine(empty, np.zeros(0, np.int32), 4)[1]
+    assert st.pop("bytes") == 0 and st.pop("init_ticks") == 0 and st.pop("move_ticks") == 0
     assert st == wst
     part = np.random.default_rng(1).integers(0, 4, 64).astype(np.int32)
     check_refine(g, part, 4, max_global=0, what="no global iteration")
@@ -139,5 +141,18 @@ def test_uncoarsen_refined_equals_oracle(k):
     assert np.array_equal(part0.cpu().numpy(), parts[0])
     for l in range(len(res)):
         assert got[l].as_tuple() == res[l].as_tuple(), l
+        assert gst[l].pop("bytes") > 0 or stats[l]["searches"] == 0
+        gst[l].pop("init_ticks"), gst[l].pop("move_ticks")
         assert gst[l] == stats[l], l
     say(f"rgg 2^15 k={k}: cut {res[0].cut}, levels {len(res)}")
+
+
+@pytest.mark.parametrize("qcap", [0, 1, 7, 100])
+def test_queue_entries_in_memory(qcap, monkeypatch):
+    # the kernel keeps the first queue entries of a search on chip and the rest
+    # in memory; a small on-chip capacity sends most entries through memory
+    monkeypatch.setenv("KAPPA_REFINE_QCAP", str(qcap))
+    for name, g in cases()[:3]:
+        for k in (2, 16):
+            part = np.random.default_rng(k + qcap).integers(0, k, g.n).astype(np.int32)
+            check_refine(g, part, k, "strong", seed=qcap, what=f"{name} k={k} qcap={qcap}")
