@@ -252,24 +252,13 @@ struct RunState {
     int32_t best_cnt[2], qn, m, kept;
 };
 
-// a thread's best queue entry of one block under (gain, hash, id); the hash
-// is computed only when gains tie
+// a thread's best queue entry of one block under (gain, hash, id)
 struct Best {
     int64_t g = 0;
     uint64_t h = 0;
     int32_t v = -1, q = -1;
-    bool hv = false;
-    __device__ __forceinline__ void offer(int64_t g2, int32_t v2, int32_t q2, uint64_t seed) {
-        if (v < 0 || g2 > g) {
-            g = g2; v = v2; q = q2; hv = false;
-        } else if (g2 == g) {
-            if (!hv) { h = mix64(seed ^ (uint64_t)(uint32_t)v); hv = true; }
-            const uint64_t h2 = mix64(seed ^ (uint64_t)(uint32_t)v2);
-            if (h2 > h || (h2 == h && v2 < v)) { h = h2; v = v2; q = q2; }
-        }
-    }
-    __device__ __forceinline__ void finish(uint64_t seed) {
-        if (v >= 0 && !hv) { h = mix64(seed ^ (uint64_t)(uint32_t)v); hv = true; }
+    __device__ __forceinline__ void offer(int64_t g2, uint64_t h2, int32_t v2, int32_t q2) {
+        if (key_above(g2, h2, v2, g, h, v)) { g = g2; h = h2; v = v2; q = q2; }
     }
 };
 
@@ -295,6 +284,7 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
     // access before the neighbours' rows
     __shared__ int64_t q_g[2][FM_QCAP];
     __shared__ int64_t q_x[2][FM_QCAP];
+    __shared__ uint64_t q_h[2][FM_QCAP];   // mix64(run seed ^ node)
     __shared__ int32_t q_v[2][FM_QCAP];
     __shared__ uint32_t q_c[2][FM_QCAP];
     __shared__ int32_t q_d[2][FM_QCAP];
@@ -334,6 +324,7 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
     int32_t *sl_r = A.slot + (size_t)r * A.n;
     const int32_t qcap = A.qcap;
     int64_t *qg = q_g[r], *qx = q_x[r];
+    uint64_t *qh = q_h[r];
     int32_t *qv = q_v[r], *qd = q_d[r];
     uint32_t *qcw = q_c[r];
     uint8_t *qs = q_s[r];
@@ -401,6 +392,7 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
             __syncthreads();   // everyone has read the count before it is cleared
         }
         // both runs: queues start with the boundary
+        const uint64_t rseed = run_seed_of(A.seed, gi, a, b, t, r);
         for (int32_t i = lt; i < len; i += FM_HALF) {
             const int32_t v = reg[i];
             if (A.dist[v] == 0) {
@@ -410,6 +402,7 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
                 if (pos < qcap) {
                     qv[pos] = v;
                     qg[pos] = gain_r[v];
+                    qh[pos] = mix64(rseed ^ (uint64_t)(uint32_t)v);
                     qs[pos] = A.part[v] == b;
                     qx[pos] = A.xadj[v];
                     qd[pos] = (int32_t)(A.xadj[v + 1] - A.xadj[v]);
@@ -423,7 +416,6 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
         __syncthreads();
         const int64_t smaller = min(s_na, s_nb);
         const int64_t start_imb = pair_imb(s_bw[0], s_bw[1], S, L), start_cut = (int64_t)s_cut;
-        const uint64_t rseed = run_seed_of(A.seed, gi, a, b, t, r);
         // the state of a search, kept in the registers of its half's lane 0
         int64_t w0 = s_bw[0], w1 = s_bw[1], cur_cut = start_cut, best_imb = start_imb;
         int64_t best_cut = start_cut, bw0 = w0, bw1 = w1, since = 0;
@@ -443,17 +435,16 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
                 for (int32_t i = lt; i < qc; i += FM_HALF) {
                     const uint8_t st = qs[i];
                     if (st & 2) continue;
-                    if (st & 1) b1.offer(qg[i], qv[i], i, rseed);
-                    else b0.offer(qg[i], qv[i], i, rseed);
+                    if (st & 1) b1.offer(qg[i], qh[i], qv[i], i);
+                    else b0.offer(qg[i], qh[i], qv[i], i);
                 }
                 for (int32_t i = qcap + lt; i < qn; i += FM_HALF) {
                     const int32_t v = q_r[i];
                     if (st_r[v] != 1) continue;
-                    if (A.part[v] == b) b1.offer(gain_r[v], v, i, rseed);
-                    else b0.offer(gain_r[v], v, i, rseed);
+                    const uint64_t h = mix64(rseed ^ (uint64_t)(uint32_t)v);
+                    if (A.part[v] == b) b1.offer(gain_r[v], h, v, i);
+                    else b0.offer(gain_r[v], h, v, i);
                 }
-                b0.finish(rseed);
-                b1.finish(rseed);
             }
             wave_best(b0.g, b0.h, b0.v, b0.q);
             wave_best(b1.g, b1.h, b1.v, b1.q);
@@ -571,6 +562,7 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
                             if (pos < qcap) {
                                 qv[pos] = u;
                                 qg[pos] = g;
+                                qh[pos] = mix64(rseed ^ (uint64_t)(uint32_t)u);
                                 qs[pos] = (uint8_t)su;
                                 qx[pos] = ux0;
                                 qd[pos] = (int32_t)(ux1 - ux0);

@@ -55,6 +55,22 @@ def test_null_arguments_rejected_without_gpu_work():
         assert L.kappa_match_two_phase(ctypes.byref(g), 0, 1, bb, None, None, None, None) == K.E_ARG
     g = K._lib.c_graph(4, 6, None, None, None, None)
     assert L.kappa_match_two_phase(ctypes.byref(g), 0, 1, 4, None, None, None, None) == K.E_ARG
+    # refinement: missing parameters, k outside [1, 256], bad presets, a bad graph
+    g = K._lib.c_graph(0, 0, ctypes.c_void_p(8), None, None, None)
+    p = K.refine_params("fast")
+    assert L.kappa_refine(ctypes.byref(g), None, 4, 3, 100, None, None, None) == K.E_ARG
+    for k in (0, 257):
+        assert L.kappa_refine(ctypes.byref(g), None, k, 3, 100, ctypes.byref(p), None, None) == K.E_ARG
+    for over in (dict(alpha_den=0), dict(depth=-1), dict(max_local=0), dict(max_global=-1),
+                 dict(stop_after=0)):
+        bad = K.refine_params("fast", **over)
+        assert L.kappa_refine(ctypes.byref(g), None, 4, 3, 100, ctypes.byref(bad), None,
+                              None) == K.E_ARG, over
+    assert L.kappa_refine(ctypes.byref(g), None, 4, 3, 0, ctypes.byref(p), None, None) == K.E_ARG
+    g = K._lib.c_graph(4, 6, None, None, None, None)
+    assert L.kappa_refine(ctypes.byref(g), None, 4, 3, 100, ctypes.byref(p), None, None) == K.E_ARG
+    assert L.kappa_uncoarsen_refined(None, 4, 1, 3, 100, ctypes.byref(p), None, None, None,
+                                     None) == K.E_ARG
     L.kappa_hierarchy_free(None)
 
 
