@@ -19,6 +19,10 @@
 //              books the move, and the half updates the neighbours' gains
 //              and queues (Section 5.2).  The better run is adopted; the
 //              workgroup repeats local iterations until one improves nothing.
+//              A run's first FM_QCAP queue entries live in LDS with everything
+//              a move needs (gain, hash, id, side/moved, c(v), row start and
+//              degree), so a move touches memory only for the neighbours'
+//              rows; later entries stay in memory with the same meaning.
 //
 // Every choice is a maximum under a strict total order, so the result does
 // not depend on the order of reductions or of the region: it is bit-exact
