@@ -277,8 +277,8 @@ def main():
         return summarize_stats(args.summarize_stats[0], args.summarize_stats[1], args.stats_title,
                                args.stats_command)
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
