@@ -20,9 +20,11 @@
 //              and queues (Section 5.2).  The better run is adopted; the
 //              workgroup repeats local iterations until one improves nothing.
 //              A run's first FM_QCAP queue entries live in LDS with everything
-//              a move needs (gain, hash, id, side/moved, c(v), row start and
+//              a move needs (gain, hash, id, side, c(v), row start and
 //              degree), so a move touches memory only for the neighbours'
-//              rows; later entries stay in memory with the same meaning.
+//              rows; later entries stay in memory with the same meaning.  A
+//              moved node's entry is replaced by the last one, so the queue
+//              holds only nodes that may still move.
 //
 // Every choice is a maximum under a strict total order, so the result does
 // not depend on the order of reductions or of the region: it is bit-exact
@@ -499,7 +501,6 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
                         int64_t cv, x0;
                         int32_t deg;
                         if (mq < qcap) {
-                            qs[mq] |= 2;
                             cv = qcw[mq];
                             x0 = qx[mq];
                             deg = qd[mq];
@@ -508,12 +509,40 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
                             x0 = A.xadj[mv];
                             deg = (int32_t)(A.xadj[mv + 1] - x0);
                         }
+                        const int32_t qn = rs[r].qn;
+                        atomicAdd(&s_bytes, 17ull * (unsigned long long)qn +
+                                                25ull * (unsigned long long)deg);
+                        // the queue stays dense: the last entry takes the moved
+                        // node's place (the order of entries decides nothing)
+                        const int32_t last = qn - 1;
+                        if (mq != last) {
+                            if (last < qcap) {
+                                const int32_t lv = qv[last];
+                                qv[mq] = lv; qg[mq] = qg[last]; qh[mq] = qh[last]; qs[mq] = qs[last];
+                                qx[mq] = qx[last]; qd[mq] = qd[last]; qcw[mq] = qcw[last];
+                                sl_r[lv] = mq;
+                            } else {
+                                const int32_t lv = q_r[last];
+                                if (mq < qcap) {   // a memory entry moves on chip
+                                    const int64_t lx0 = A.xadj[lv];
+                                    qv[mq] = lv;
+                                    qg[mq] = gain_r[lv];
+                                    qh[mq] = mix64(rseed ^ (uint64_t)(uint32_t)lv);
+                                    qs[mq] = A.part[lv] == b;
+                                    qx[mq] = lx0;
+                                    qd[mq] = (int32_t)(A.xadj[lv + 1] - lx0);
+                                    qcw[mq] = A.vw[lv];
+                                } else {
+                                    q_r[mq] = lv;
+                                }
+                                sl_r[lv] = mq;
+                            }
+                        }
+                        rs[r].qn = last;
                         if (from == 0) { w0 -= cv; w1 += cv; --c0; ++c1; }
                         else { w1 -= cv; w0 += cv; --c1; ++c0; }
                         cur_cut -= mg;
                         m_r[m++] = mv;
-                        atomicAdd(&s_bytes, 17ull * (unsigned long long)rs[r].qn +
-                                                25ull * (unsigned long long)deg);
                         s_to[r] = to;
                         s_x0[r] = x0;
                         s_deg[r] = deg;
