@@ -37,7 +37,7 @@ namespace kappa {
 
 constexpr int RQ_THREADS = 256;
 constexpr int RC_ITEMS = 16;           // nodes per thread in collect
-constexpr int FM_THREADS = 1024;       // two halves of 512, one per run
+constexpr int FM_THREADS = 512;        // two halves of 256, one per run
 constexpr int FM_HALF = FM_THREADS / 2;
 constexpr int FM_WAVES = FM_HALF / WAVE;
 constexpr int FM_QCAP = 2048;          // queue entries per run kept in LDS (the rest in memory)
