@@ -91,7 +91,8 @@ def counter_traffic(kernel):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("sources") != COUNTER_SOURCES or rec.get("sources_sha256") != _sources_sha():
+    srcs = counter_sources(kernel)
+    if rec.get("sources") != srcs or rec.get("sources_sha256") != _sources_sha(srcs):
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -132,8 +133,15 @@ KERNEL_SYMBOLS = {"pick": r"pick_k<\d, false, 0>", "mate": r"mate_k<\d, false>",
                   "pick_first": r"pick_k<\d, true, 0>", "fill_small": r"fill_small_k",
                   "compact": r"compact_k", "cut_entries": r"up_entries_k<(true|false)>",
                   "refine_fm": r"ref_fm_k"}
+# the sources a kernel's stored counters depend on (they go stale when these change)
 COUNTER_SOURCES = ["paper_0910_2004_amd/csrc/k_level.hip", "paper_0910_2004_amd/csrc/kappa_internal.h",
-                   "paper_0910_2004_amd/csrc/k_graph.hip", "paper_0910_2004_amd/csrc/k_refine.hip"]
+                   "paper_0910_2004_amd/csrc/k_graph.hip"]
+REFINE_COUNTER_SOURCES = ["paper_0910_2004_amd/csrc/k_refine.hip",
+                          "paper_0910_2004_amd/csrc/kappa_internal.h"]
+
+
+def counter_sources(kernel):
+    return REFINE_COUNTER_SOURCES if kernel.startswith("refine") else COUNTER_SOURCES
 WORKLOAD_RGG = "rgg n=2^20 mean degree 8, both ratings, k=64, stop 1280"
 WORKLOAD_REFINE = ("the way back up with pairwise refinement (preset fast) on the expansion*2 "
                    "hierarchy of rgg n=2^20 mean degree 8, k=64, stop 1280")
@@ -144,10 +152,10 @@ def _short_name(name):
     return re.sub(r"\(.*", "", name).replace("void ", "").replace("kappa::", "").strip()
 
 
-def _sources_sha():
+def _sources_sha(sources):
     import hashlib
     h = hashlib.sha256()
-    for src in COUNTER_SOURCES:
+    for src in sources:
         with open(os.path.join(ROOT, src), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -179,8 +187,8 @@ def summarize_pmc(kernel, fetch_dir, write_dir, bench_cmd):
             f"--output-format csv -- python3 <repo>/{bench_cmd}" for c in ("FETCH_SIZE", "WRITE_SIZE")]
     workload = WORKLOAD_REFINE if kernel.startswith("refine") else WORKLOAD_RGG
     rec = {"kernel": kernel, "workload": workload, "counters": res,
-           "traffic_bytes_per_launch": traffic, "sources": COUNTER_SOURCES,
-           "sources_sha256": _sources_sha(), "commands": cmds}
+           "traffic_bytes_per_launch": traffic, "sources": counter_sources(kernel),
+           "sources_sha256": _sources_sha(counter_sources(kernel)), "commands": cmds}
     with open(os.path.join(ROOT, "profiles", f"{kernel}_counters.json"), "w") as f:
         json.dump(rec, f, indent=1)
     lines = [f"# HBM traffic of `{kernel}` ({KERNEL_SYMBOLS[kernel]}): {workload}", "",
@@ -196,7 +204,7 @@ def summarize_pmc(kernel, fetch_dir, write_dir, bench_cmd):
         lines.append(f"| {ctr} | {', '.join(f'{v:.1f}' for v in r['copy_kib'])} | {r['scale']:.4f} | "
                      f"{r['dispatches']} | {r['scaled_bytes_per_launch'] / 1e6:.3f} |")
     lines += ["", f"Traffic per launch: **{traffic / 1e6:.3f} MB**.  `bench.py` reports it as "
-              f"`roofline.traffic` while the SHA-256 of {', '.join(COUNTER_SOURCES)} equals "
+              f"`roofline.traffic` while the SHA-256 of {', '.join(counter_sources(kernel))} equals "
               f"`{rec['sources_sha256'][:16]}…`, and null once they change."]
     with open(os.path.join(ROOT, "profiles", f"{kernel}_counters.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
