@@ -269,8 +269,33 @@ struct Best {
 };
 
 // the wave's best (gain, hash, id), carrying the queue position
+// DPP lane moves inside a row of 16 lanes: quad_perm swaps of neighbours and
+// of pairs, the mirror of each half-row, the mirror of the row.  Each pairs
+// every lane with another, so after the four steps every lane holds its row's
+// maximum.
+constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ int32_t dpp_i32(int32_t x) {
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void best_step_dpp(int64_t &g, uint64_t &h, int32_t &v, int32_t &q) {
+    const int64_t g2 = (int64_t)(((uint64_t)(uint32_t)dpp_i32<CTRL>((int32_t)(g >> 32)) << 32) |
+                                 (uint32_t)dpp_i32<CTRL>((int32_t)g));
+    const uint64_t h2 = ((uint64_t)(uint32_t)dpp_i32<CTRL>((int32_t)(h >> 32)) << 32) |
+                        (uint32_t)dpp_i32<CTRL>((int32_t)h);
+    const int32_t v2 = dpp_i32<CTRL>(v), q2 = dpp_i32<CTRL>(q);
+    if (key_above(g2, h2, v2, g, h, v)) { g = g2; h = h2; v = v2; q = q2; }
+}
+
 __device__ __forceinline__ void wave_best(int64_t &g, uint64_t &h, int32_t &v, int32_t &q) {
-    for (int o = WAVE / 2; o > 0; o >>= 1) {
+    best_step_dpp<DPP_XOR1>(g, h, v, q);
+    best_step_dpp<DPP_XOR2>(g, h, v, q);
+    best_step_dpp<DPP_HALF_MIRROR>(g, h, v, q);
+    best_step_dpp<DPP_MIRROR>(g, h, v, q);
+    for (int o = 16; o < WAVE; o <<= 1) {   // across rows
         const int64_t g2 = __shfl_xor(g, o);
         const uint64_t h2 = __shfl_xor(h, o);
         const int32_t v2 = __shfl_xor(v, o);
