@@ -485,7 +485,9 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
             }
             __syncthreads();
             if (wv == 0 && live) {
-                // lanes 0-7 take side 0 of the half's eight waves, lanes 8-15 side 1
+                // lanes 0-3 take side 0 of the half's four waves, lanes 4-7
+                // side 1; two quad swaps leave each side's best in lanes 0 and 4
+                static_assert(FM_WAVES == 4, "one quad per side");
                 int64_t g = 0;
                 uint64_t h = 0;
                 int32_t v = -1, q = -1;
@@ -493,15 +495,14 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
                     const int sd = lane / FM_WAVES, x = lane % FM_WAVES;
                     g = s_wg[r][sd][x]; h = s_wh[r][sd][x]; v = s_wv[r][sd][x]; q = s_wq[r][sd][x];
                 }
-                for (int o = FM_WAVES / 2; o > 0; o >>= 1) {
-                    const int64_t g2 = __shfl_xor(g, o);
-                    const uint64_t h2 = __shfl_xor(h, o);
-                    const int32_t v2 = __shfl_xor(v, o), q2 = __shfl_xor(q, o);
-                    if (key_above(g2, h2, v2, g, h, v)) { g = g2; h = h2; v = v2; q = q2; }
-                }
-                const int64_t g1 = __shfl(g, FM_WAVES);
-                const uint64_t h1 = __shfl(h, FM_WAVES);
-                const int32_t v1 = __shfl(v, FM_WAVES), q1 = __shfl(q, FM_WAVES);
+                best_step_dpp<DPP_XOR2>(g, h, v, q);
+                best_step_dpp<DPP_XOR1>(g, h, v, q);
+                const int64_t g1 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int32_t)(g >> 32), FM_WAVES) << 32) |
+                                             (uint32_t)__builtin_amdgcn_readlane((int32_t)g, FM_WAVES));
+                const uint64_t h1 = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int32_t)(h >> 32), FM_WAVES) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readlane((int32_t)h, FM_WAVES);
+                const int32_t v1 = __builtin_amdgcn_readlane(v, FM_WAVES);
+                const int32_t q1 = __builtin_amdgcn_readlane(q, FM_WAVES);
                 if (lane == 0) {
                     int32_t mv = -1;
                     bool stop = false;
