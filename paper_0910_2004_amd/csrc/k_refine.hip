@@ -252,6 +252,25 @@ struct FmArgs {
 };
 
 // per-run state of one local search, in LDS
+constexpr int ROW_CHUNK = 8;
+
+// the blocks and weights of row entries [e0, min(e0 + ROW_CHUNK, x1)): all
+// neighbour loads first, then all block loads, so they overlap; entries past
+// the row get block -1
+__device__ __forceinline__ void row_chunk(const int32_t *adj, const uint32_t *ew,
+                                          const int32_t *part, int64_t e0, int64_t x1,
+                                          int32_t *pu, uint32_t *wu) {
+    int32_t uu[ROW_CHUNK];
+#pragma unroll
+    for (int k = 0; k < ROW_CHUNK; ++k) {
+        const bool in = e0 + k < x1;
+        uu[k] = in ? adj[e0 + k] : -1;
+        wu[k] = in ? ew[e0 + k] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < ROW_CHUNK; ++k) pu[k] = uu[k] >= 0 ? part[uu[k]] : -1;
+}
+
 // a finished search, published for the adoption
 struct RunState {
     int64_t best_imb, best_cut, best_w[2];
@@ -376,17 +395,24 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
         int32_t na = 0, nb = 0;
         for (int32_t i = tid; i < len; i += FM_THREADS) {
             const int32_t v = reg[i], pv = A.part[v];
+            const int64_t x0 = A.xadj[v], x1 = A.xadj[v + 1];
             int64_t g = 0;
             bool bnd = false;
-            for (int64_t e = A.xadj[v]; e < A.xadj[v + 1]; ++e) {
-                const int32_t pu = A.part[A.adj[e]];
-                if (pu != a && pu != b) continue;
-                if (pu != pv) {
-                    g += A.ew[e];
-                    bnd = true;
-                    if (pv == a) cut += A.ew[e];
-                } else {
-                    g -= A.ew[e];
+            // rows in chunks of ROW_CHUNK entries, each chunk's loads issued together
+            for (int64_t e0 = x0; e0 < x1; e0 += ROW_CHUNK) {
+                int32_t pu[ROW_CHUNK];
+                uint32_t wu[ROW_CHUNK];
+                row_chunk(A.adj, A.ew, A.part, e0, x1, pu, wu);
+#pragma unroll
+                for (int k = 0; k < ROW_CHUNK; ++k) {
+                    if (pu[k] != a && pu[k] != b) continue;   // also the chunk's tail (-1)
+                    if (pu[k] != pv) {
+                        g += wu[k];
+                        bnd = true;
+                        if (pv == a) cut += wu[k];
+                    } else {
+                        g -= wu[k];
+                    }
                 }
             }
             A.gain[v] = g;
@@ -396,7 +422,7 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
             A.dist[v] = bnd ? 0 : -1;
             if (bnd) fr[0][atomicAdd(&s_nf, 1)] = v;
             if (pv == a) ++na; else ++nb;
-            touched += 40 + 12 * (unsigned long long)(A.xadj[v + 1] - A.xadj[v]);
+            touched += 40 + 12 * (unsigned long long)(x1 - x0);
         }
         atomicAdd(&s_bytes, touched);
         atomicAdd(&s_cut, cut);
@@ -412,10 +438,17 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
             __syncthreads();
             for (int32_t i = tid; i < nf; i += FM_THREADS) {
                 const int32_t v = cur[i], pv = A.part[v];
-                for (int64_t e = A.xadj[v]; e < A.xadj[v + 1]; ++e) {
-                    const int32_t u = A.adj[e];
-                    if (A.part[u] == pv && atomicCAS(&A.dist[u], -1, d) == -1)
-                        nxt[atomicAdd(&s_nf, 1)] = u;
+                const int64_t x1 = A.xadj[v + 1];
+                for (int64_t e0 = A.xadj[v]; e0 < x1; e0 += ROW_CHUNK) {
+                    int32_t uu[ROW_CHUNK], pu[ROW_CHUNK];
+#pragma unroll
+                    for (int k = 0; k < ROW_CHUNK; ++k) uu[k] = e0 + k < x1 ? A.adj[e0 + k] : -1;
+#pragma unroll
+                    for (int k = 0; k < ROW_CHUNK; ++k) pu[k] = uu[k] >= 0 ? A.part[uu[k]] : -1;
+#pragma unroll
+                    for (int k = 0; k < ROW_CHUNK; ++k)
+                        if (pu[k] == pv && atomicCAS(&A.dist[uu[k]], -1, d) == -1)
+                            nxt[atomicAdd(&s_nf, 1)] = uu[k];
                 }
             }
             __syncthreads();
