@@ -177,3 +177,33 @@ def test_full_size_refined_way_back_up_properties():
     for x in st:
         assert x["kept"] <= x["moves"] and x["searches"] % 2 == 0 and x["global_iterations"] <= 15
     say(f"rgg 2^20 k=64: cut {plain[0].cut} -> {res[0].cut}, levels {len(res)}")
+
+
+def test_k256_random_partition():
+    # the largest k: a random partition makes Q dense (160 colours here) and
+    # every block pair small
+    g = rgg(4096, seed=31)
+    part = np.random.default_rng(5).integers(0, 256, g.n).astype(np.int32)
+    check_refine(g, part, 256, "minimal", seed=2, what="k=256 minimal")
+    check_refine(g, part, 256, "fast", seed=3, what="k=256 fast")
+
+
+@pytest.mark.parametrize("name,make,k", [
+    ("rmat12", lambda: rmat(12, 16, seed=7, wseed=8, wmax=50), 16),
+    ("grid100", lambda: grid2d(100, 100), 8),
+])
+def test_uncoarsen_refined_strong_equals_oracle(name, make, k):
+    # power-law rows (hubs in the searches) and a mesh, with the strong preset
+    g = make()
+    H = K.kappa_coarsen(dev(g), O.EXPANSION_STAR2, 42, 20 * k)
+    OH = O.coarsen(g, O.EXPANSION_STAR2, 42, 20 * k)
+    prm = oracle_params("strong", 4)
+    parts, res, stats = O.uncoarsen_refined(OH, k, 1, 3, 100, prm)
+    part0, got, gst = K.kappa_uncoarsen_refined(H, k, 1, 3, 100, "strong", 4)
+    assert np.array_equal(part0.cpu().numpy(), parts[0]), name
+    for l in range(len(res)):
+        assert got[l].as_tuple() == res[l].as_tuple(), (name, l)
+        for key in ("bytes", "init_ticks", "move_ticks"):
+            gst[l].pop(key)
+        assert gst[l] == stats[l], (name, l)
+    say(f"{name} k={k} strong: cut {res[0].cut}")
