@@ -431,6 +431,9 @@ def main():
                 "avg_launch_us": round(avg_s * 1e6, 2), "bytes_per_launch": int(per_launch_bytes),
                 "model": MODELS[rk], "time_share": round(ms / args.steps / total_ms, 3),
                 "dominant_kernel": dom}
+        cc = copy_ceiling_gbs(torch)
+        roof["copy_ceiling_gbs"] = cc
+        roof["frac_of_copy"] = round(achieved / cc, 4)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -503,6 +506,25 @@ def main():
         with open(args.profile_out, "w") as f:
             json.dump({"prof": prof, "model_bytes": mb, "levels": lv_json}, f, indent=1)
     print(json.dumps(out), flush=True)
+
+
+def copy_ceiling_gbs(torch, mib=1024, reps=5):
+    """Context for the roofline: a plain device-to-device copy of `mib` MiB,
+    timed with events; read + written bytes per second (GB/s)."""
+    a = torch.ones(mib << 18, dtype=torch.int32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * a.numel() * 4 * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
 
 
 def bench_batch(args):
@@ -644,6 +666,9 @@ def bench_refine(args):
                 "time_share": round(fm_ms / total_ms, 3),
                 "dominant_kernel": kern[0][0],
                 "us_per_move_step": round(fm_ms * 1e3 / max(1, moves / 2), 3)}
+        cc = copy_ceiling_gbs(torch)
+        roof["copy_ceiling_gbs"] = cc
+        roof["frac_of_copy"] = round(achieved / cc, 5)
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
