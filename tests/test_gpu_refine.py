@@ -207,3 +207,12 @@ def test_uncoarsen_refined_strong_equals_oracle(name, make, k):
             gst[l].pop(key)
         assert gst[l] == stats[l], (name, l)
     say(f"{name} k={k} strong: cut {res[0].cut}")
+
+
+def test_more_blocks_than_nodes():
+    # k > n: most blocks are empty, Q covers only the occupied ones
+    g = random_graph(30, 80, seed=12, wmax=5, cmax=3, cmin=0)
+    for k in (64, 256):
+        part = np.random.default_rng(k).integers(0, k, g.n).astype(np.int32)
+        for preset in ("minimal", "strong"):
+            check_refine(g, part, k, preset, seed=k, what=f"k={k} {preset}")
