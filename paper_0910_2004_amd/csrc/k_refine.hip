@@ -431,6 +431,7 @@ __global__ void __launch_bounds__(FM_THREADS) ref_fm_k(FmArgs A, int32_t gi, int
         __syncthreads();
         // bounded BFS inside each block, one frontier per distance
         int32_t nf = s_nf;
+        __syncthreads();   // every thread has read the count before the first step clears it
         for (int32_t d = 1; d <= A.depth && nf > 0; ++d) {
             const int32_t *cur = fr[(d - 1) & 1];
             int32_t *nxt = fr[d & 1];

@@ -53,6 +53,37 @@ def test_mix64_is_a_bijection_sample():
     assert len(hs) == len(xs)
 
 
+# The stand-in coarsest partition: part(x) = mix64(seed + x) mod k.  The
+# published SplitMix64 stream with state 0 outputs mix64(i * gamma) at step i,
+# so a seed of i * gamma - x puts that output at node x.  A seed mixed by XOR,
+# a missing mix, or a reduction other than the remainder fails here.
+GAMMA = 0x9E3779B97F4A7C15
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 7, 64, 100, 255, 256])
+def test_initial_partition_published_stream(k):
+    g = gold("splitmix64.json")
+    assert g["state"] == 0
+    for i, h in enumerate(g["outputs"], start=1):
+        for x in (0, 1, 2, 5, 1000):
+            seed = (i * GAMMA - x) % (1 << 64)
+            part = O.initial_partition(x + 1, k, seed)
+            assert int(part[x]) == int(h, 16) % k, (i, x, k)
+    # seed = gamma: node 0 takes the first output
+    assert int(O.initial_partition(1, k, GAMMA)[0]) == 0xE220A8397B1DCDAF % k
+
+
+def test_initial_partition_matches_python_mix64():
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        seed = int(rng.integers(0, 1 << 63)) * 2 + int(rng.integers(0, 2))
+        k = int(rng.integers(1, 257))
+        n = int(rng.integers(0, 300))
+        part = O.initial_partition(n, k, seed)
+        want = [refpy.mix64((seed + x) % (1 << 64)) % k for x in range(n)]
+        assert part.tolist() == want
+
+
 # --------------------------------------------------------------------------
 # W1: P4 with weights 3, 4, 2 -- ratings, every level, projection, L_max
 # --------------------------------------------------------------------------
@@ -68,7 +99,7 @@ def test_w1_csr_and_ratings():
         assert num.tolist() == want["num"] and den.tolist() == want["den"], name
 
 
-@pytest.mark.parametrize("rating", ["expansion*2", "innerOuter"])
+@pytest.mark.parametrize("rating", RATING_NAMES)
 def test_w1_hierarchy(rating):
     w = gold("w1_p4.json")
     g = graph_from(w["graph"])
@@ -113,7 +144,8 @@ def test_w2_monotone_path_rounds():
     g = graph_from(w["graph"])
     mate, m, rounds, act, deg = O.match_rounds(g, O.EXPANSION_STAR2, O.level_seed(42, 0))
     assert mate.tolist() == w["mate"] and rounds == w["rounds"] and m == 2
-    assert act.tolist() == [5, 3]      # pointing nodes per round
+    assert act.tolist() == w["round_active"]      # pointing nodes per round
+    assert deg.tolist() == w["round_degree"]      # their degree sums (full degrees)
     gm, gmm = O.match_greedy(g, O.EXPANSION_STAR2, O.level_seed(42, 0))
     assert gm.tolist() == w["mate"]
     cmap, cg = O.contract(g, mate)
@@ -216,7 +248,7 @@ def test_maximal_and_half_of_optimum(rating):
         for v in range(g.n):
             if mate[v] >= 0:
                 assert mate[mate[v]] == v
-        # maximal: no edge with two free ends ("until no more edges can be matched")
+        # maximal: no edge with two free ends (Section 3.3: rounds go on while an edge can be matched)
         for a, b, _ in es:
             assert mate[a] >= 0 or mate[b] >= 0
         outs = refpy.out_of(g)
