@@ -529,7 +529,11 @@ kappa_status validate_impl(const DevGraph &g, hipStream_t s, int32_t *maxdeg_out
 // workspace.  After the real pass the caller zeroes `arrive` (and the hub
 // arrays) with fill_scratch.
 // ---------------------------------------------------------------------------
-void carve_scratch(Carve &cv, const DevGraph &g, int rating, bool hubs, Ctx &c) {
+// chunks: scan rows above BIN_MID_MAX entries in chunks of HUB_CHUNK (the
+// graph has such rows at level 0; coarse levels of other graphs rarely do,
+// and their long rows are then scanned by one block each).
+void carve_scratch(Carve &cv, const DevGraph &g, int rating, bool hubs, Ctx &c,
+                   bool chunks = false) {
     MatchScratch &ms = c.ms;
     ContractScratch &cs = c.cs;
     ms.best = cv.get<int32_t>(g.n);
@@ -543,14 +547,15 @@ void carve_scratch(Carve &cv, const DevGraph &g, int rating, bool hubs, Ctx &c) 
     cs.rep_of = cv.get<int32_t>(g.n);
     cs.partner = cv.get<int32_t>(g.n);
     cs.cdeg = cv.get<int32_t>(g.n);
-    cs.rows = cv.get<int32_t>(3 * (int64_t)g.n);
-    cs.row_cnt = cv.get<int32_t>(4);
+    cs.rows = cv.get<int32_t>(4 * (int64_t)g.n);
+    cs.row_cnt = cv.get<int32_t>(8);
     cs.tmp_adj = cv.get<int32_t>(g.nnz);
     cs.tmp_ew = cv.get<uint32_t>(g.nnz);
     cs.partials = cv.get<int64_t>(scan_tiles((int64_t)g.n + 1) + 1);
     cs.arrive = cv.get<unsigned>(ARRIVE_WORDS);
     cs.totals = cv.get<int64_t>(4);
-    cs.hub_words = (int64_t)g.n / 32 + 1;
+    cs.hub_w1 = (int64_t)g.n / 32 + 1;
+    cs.hub_words = cs.hub_w1 + cs.hub_w1 / 32 + 1;
     // as many hub slots as the accumulator budget allows (more long rows
     // merged at once), between HUB_SLOTS and HUB_SLOTS_MAX
     cs.hub_slots = (int32_t)std::max<int64_t>(
@@ -560,12 +565,20 @@ void carve_scratch(Carve &cv, const DevGraph &g, int rating, bool hubs, Ctx &c) 
     // two-phase matcher (c.block_bits set before carving)
     ms.loc = c.block_bits >= 0 ? cv.get<int32_t>(g.n) : nullptr;
     ms.lkey = c.block_bits >= 0 ? cv.get<LocKey>(g.n) : nullptr;
+    ms.hub = HubChunks{nullptr, nullptr, nullptr, 0, nullptr};
+    if (chunks) {
+        ms.hub.cap = hub_chunk_cap(g.nnz);
+        ms.hub.rec = cv.get<int2>(2 * ms.hub.cap);
+        ms.hub.first = cv.get<int32_t>(2 * (int64_t)g.n);
+        ms.hub.part = cv.get<Cand>(ms.hub.cap);
+        ms.hub.scan = cv.get<int2>(2 * (int64_t)g.n);
+    }
 }
 
 void fill_scratch(const DevGraph &g, const Ctx &c, hipStream_t s) {
     ZeroRanges z;
     z.add(c.cs.arrive, ARRIVE_WORDS);
-    z.add(c.cs.row_cnt, 4);
+    z.add(c.cs.row_cnt, 8);
     z.add(c.cs.totals, 4 * 2);
     // the matching state: list counters, round statistics, merge counts
     static_assert(sizeof(MatchState) % 4 == 0, "zeroed as words");
@@ -577,11 +590,26 @@ void fill_scratch(const DevGraph &g, const Ctx &c, hipStream_t s) {
     launch_zero(z, s);
 }
 
-// Host-side level size estimate (grid sizing only; any value is correct).
-inline int32_t n_hint_of(int32_t n0, int l) {
-    double v = (double)n0 * std::pow(0.6, l);
-    return (int32_t)std::max(1.0, std::min((double)n0, v));
-}
+// Host-side level size estimate (grid sizing only; any value is correct):
+// the newest level size the host has read back, shrunk geometrically by the
+// ratio observed so far (0.6 per level before any read-back; power-law graphs
+// shrink far more slowly than meshes).
+struct SizeHint {
+    int32_t n0, known_l = 0, known_n;
+    double ratio = 0.6;
+    explicit SizeHint(int32_t n) : n0(n), known_n(n) {}
+    int32_t at(int l) const {
+        double v = (double)known_n * std::pow(ratio, std::max(0, l - known_l));
+        return (int32_t)std::max(1.0, std::min((double)n0, v));
+    }
+    void seen(int l, int32_t n) {
+        if (l <= known_l || n <= 0) return;
+        double r = std::pow((double)n / std::max(1, known_n), 1.0 / (l - known_l));
+        ratio = std::min(1.0, std::max(0.3, r));
+        known_l = l;
+        known_n = n;
+    }
+};
 
 // Multi-block matching rounds before the one-workgroup finisher.  Measured on
 // random geometric graphs: three rounds bring a level of ~2 K nodes below the
@@ -668,7 +696,7 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     if (!carve_workspace(s, w, [&](Carve &cv) {
             c.ctrl = cv.get<Control>(1);
             c.lv = cv.get<LevelDesc>(maxl + 2);
-            carve_scratch(cv, d0, p->rating, hubs, c);
+            carve_scratch(cv, d0, p->rating, hubs, c, maxdeg0 > BIN_MID_MAX);
             if (bi) {
                 c.b.count = count;
                 c.b.stall_num = p->stall_num;
@@ -770,10 +798,14 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     // launched behind a handed-back one (no-ops then) few
     if (c.big_blocks > 64) batch = std::min(batch, 2);
     Control *hc = (Control *)pinned(sizeof(Control));
+    SizeHint hint(n0);
     for (;;) {
         const int l_end = std::min(launched + batch, maxl + 1);
         int next = l_end;
+        uint64_t ratio_bits;
+        std::memcpy(&ratio_bits, &hint.ratio, sizeof ratio_bits);
         const std::vector<uint64_t> key = {1, pkey(w->base), (uint64_t)n0, (uint64_t)d0.nnz,
+                                           (uint64_t)hint.known_l, (uint64_t)hint.known_n, ratio_bits,
                                            (uint64_t)p->rating, p->seed, (uint64_t)maxl,
                                            (uint64_t)hubs, (uint64_t)launched, (uint64_t)l_end,
                                            (uint64_t)count, (uint64_t)tail_on,
@@ -782,7 +814,7 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
                                            (uint64_t)(int64_t)ext_level, (uint64_t)ext_round};
         HIPCHK(run_seq(w->c, s, key, [&](hipStream_t q) {
             for (int l = launched; l < l_end; ++l) {
-                int32_t nh = n_hint_of(n0, l);
+                int32_t nh = hint.at(l);
                 if (l == ext_level) {
                     launch_level_extend(c, l, nh, n0, ext_round,
                                         EXTEND_ROUNDS << std::min(ext_times, 3), true, q);
@@ -807,6 +839,7 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
         launched = next;
         HIPCHK(hipMemcpyAsync(hc, c.ctrl, sizeof(Control), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        hint.seen(hc->nlevels - 1, hc->last_n);
         ext_level = -1;
         if ((hc->flags & CF_EXTEND) && !(hc->flags & ~(uint32_t)CF_EXTEND)) {
             // resume the level on the grid; the kernels after it in this
@@ -1256,7 +1289,7 @@ kappa_status match_once(const kappa_graph *g, int32_t rating, uint64_t level_see
             c.ctrl = cv.get<Control>(1);
             c.lv = cv.get<LevelDesc>(2);
             cm = cv.get<int32_t>(d.n);
-            carve_scratch(cv, d, rating, false, c);
+            carve_scratch(cv, d, rating, false, c, true);
         }))
         return KAPPA_E_NOMEM;
     fill_scratch(d, c, s);

@@ -162,33 +162,58 @@ __device__ __forceinline__ bool above_block_edges(const GapView &gv, const Cand 
     return cand_better(cu, loc_cand(gv, cd.u), cd.u);
 }
 
-// Best edge from v to a free neighbour over the entries sub, sub+G, ...
+// Best edge from v to a free neighbour over the entries sub, sub+G, ... of
+// [b, e).  A lane keeps SCAN_UNROLL entries in flight: their loads, then
+// their neighbours' records, are issued before the first comparison.
+constexpr int SCAN_UNROLL = 4;
+template <int R, int G, bool FIRST, int F = 0>
+__device__ __forceinline__ Cand scan_range(const DevGraph &g, int32_t v, uint32_t av, int sub,
+                                           int64_t b, int64_t e, const int2 *nrec,
+                                           const uint32_t *out, uint64_t seed, int32_t base,
+                                           const GapView &gv) {
+    Cand best = cand_none();
+    const Cand kv = F ? loc_cand(gv, v) : cand_none();
+    for (int64_t j0 = b + sub; j0 < e; j0 += (int64_t)G * SCAN_UNROLL) {
+        int32_t u[SCAN_UNROLL];
+        uint32_t w[SCAN_UNROLL], au[SCAN_UNROLL];
+        bool ok[SCAN_UNROLL];
+#pragma unroll
+        for (int t = 0; t < SCAN_UNROLL; ++t) {
+            const int64_t j = j0 + (int64_t)t * G;
+            ok[t] = j < e;
+            u[t] = ok[t] ? g.adj[j] : 0;
+            w[t] = ok[t] ? g.ew[j] : 0u;
+        }
+#pragma unroll
+        for (int t = 0; t < SCAN_UNROLL; ++t) {
+            if (F) ok[t] = ok[t] && cross_block(gv, v, u[t]);
+            if (FIRST) {
+                au[t] = ok[t] ? attr_src<R>(g, out, u[t]) : 0u;   // round 1: every node is free
+            } else {
+                const int2 rec = ok[t] ? nrec[u[t]] : make_int2(0, 0);
+                ok[t] = ok[t] && rec.y < 0;
+                au[t] = (uint32_t)rec.x;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < SCAN_UNROLL; ++t) {
+            if (!ok[t]) continue;
+            Cand cd;
+            rate<R>(w[t], au[t], av, au[t], av, cd.num, cd.den);
+            cd.h = mix64(seed ^ edge_id_local(v, u[t], base));
+            cd.u = u[t];
+            if (F && !above_block_edges(gv, cd, v, kv)) continue;
+            if (cand_better(cd, best, v)) best = cd;
+        }
+    }
+    return best;
+}
 template <int R, int G, bool FIRST, int F = 0>
 __device__ __forceinline__ Cand scan_row(const DevGraph &g, int32_t v, uint32_t av, int sub,
                                          const int2 *nrec, const uint32_t *out, uint64_t seed,
                                          int32_t base, const GapView &gv) {
-    Cand best = cand_none();
-    const int64_t b = g.xadj[v], e = g.xadj[v + 1];
-    const Cand kv = F ? loc_cand(gv, v) : cand_none();
-    for (int64_t j = b + sub; j < e; j += G) {
-        const int32_t u = g.adj[j];
-        if (F && !cross_block(gv, v, u)) continue;
-        uint32_t au;
-        if (FIRST) {
-            au = attr_src<R>(g, out, u);   // round 1: every node is free
-        } else {
-            const int2 rec = nrec[u];
-            if (rec.y >= 0) continue;
-            au = (uint32_t)rec.x;
-        }
-        Cand cd;
-        rate<R>(g.ew[j], au, av, au, av, cd.num, cd.den);
-        cd.h = mix64(seed ^ edge_id_local(v, u, base));
-        cd.u = u;
-        if (F && !above_block_edges(gv, cd, v, kv)) continue;
-        if (cand_better(cd, best, v)) best = cd;
-    }
-    return best;
+    return scan_range<R, G, FIRST, F>(g, v, av, sub, g.xadj[v], g.xadj[v + 1], nrec, out, seed,
+                                      base, gv);
 }
 
 // The same over a row of at most BIN_SMALL_MAX entries [b, e): every load of
@@ -273,10 +298,43 @@ __device__ __forceinline__ uint64_t level_seed(const Ctx &c, int l) {
 // int64, sbase: 3 int32 of LDS.  Order inside a list is not deterministic;
 // no consumer depends on it.
 constexpr int MK = 8;
+// Where the chunk records of appended bin-2 entries go (rec == nullptr: none;
+// the one-workgroup finisher scans long rows whole).  cnt: the record counter.
+struct HubOut {
+    int2 *rec;
+    int32_t *first;
+    int32_t *cnt;
+    int64_t cap;
+};
+__device__ __forceinline__ HubOut hub_out(const Ctx &c, int32_t n, int par, int32_t *cnt3) {
+    HubOut h{nullptr, nullptr, nullptr, 0};
+    if (!c.ms.hub.rec) return h;
+    h.rec = c.ms.hub.rec + (int64_t)par * c.ms.hub.cap;
+    h.first = c.ms.hub.first + (int64_t)par * n;
+    h.cnt = cnt3 + 3;
+    h.cap = c.ms.hub.cap;
+    return h;
+}
+__device__ __forceinline__ int32_t hub_chunks_of(int64_t deg) {
+    return (int32_t)((deg + HUB_CHUNK - 1) / HUB_CHUNK);
+}
+// Records {p, 0 .. k-1} for the bin-2 entry at list position p of degree d.
+__device__ __forceinline__ void hub_emit(const HubOut &h, int32_t p, int32_t d, Control *ctrl) {
+    const int32_t k = hub_chunks_of(d);
+    const int32_t base = atomicAdd(h.cnt, k);
+    if ((int64_t)base + k > h.cap) {   // cannot happen: the capacity bounds every level
+        atomicOr(&ctrl->flags, (uint32_t)CF_STATE);
+        h.first[p] = -1;
+        return;
+    }
+    h.first[p] = base;
+    for (int32_t q = 0; q < k; ++q) h.rec[base + q] = make_int2(p, q);
+}
 __device__ __forceinline__ void block_append_mk(const int bin[MK], const int32_t v[MK],
                                                 const int32_t b[MK], const int32_t d[MK],
                                                 const PList ol[3], int32_t *cnt, int64_t *sh,
-                                                int32_t *sbase) {
+                                                int32_t *sbase, const HubOut &ho = HubOut{},
+                                                Control *ctrl = nullptr) {
     constexpr int64_t M = 0x1fffff;   // 21 bits per bin: at most 1024 * MK entries per block
     int64_t packed = 0;
 #pragma unroll
@@ -302,6 +360,7 @@ __device__ __forceinline__ void block_append_mk(const int bin[MK], const int32_t
         o.v[p] = v[k];
         o.b[p] = b[k];
         o.d[p] = d[k];
+        if (bin[k] == 2 && ho.rec) hub_emit(ho, p, d[k], ctrl);
     }
     __syncthreads();   // sbase is reused by the next call
 }
@@ -314,9 +373,12 @@ __device__ __forceinline__ void block_append_mk(const int bin[MK], const int32_t
 // three list counters (global, or LDS when one block does all the work).
 __device__ __forceinline__ void init_phase(const Ctx &c, const DevGraph &g, LevelDesc *L,
                                            int64_t *sh, int32_t *sbase, unsigned bid, unsigned nb,
-                                           int32_t *cnt) {
+                                           int32_t *cnt, bool grid) {
     int32_t *mate = L->mate, *best = c.ms.best;
     const PList ol[3] = {plist(c.ms, g.n, 0, 0), plist(c.ms, g.n, 0, 1), plist(c.ms, g.n, 0, 2)};
+    // chunk records only for the grid rounds (a one-workgroup caller scans
+    // long rows whole, and its counters have no chunk slot)
+    const HubOut ho = grid ? hub_out(c, g.n, 0, cnt) : HubOut{};
     // pass p, slot k of block b covers entries ((p * MK + k) * nb + b) * blockDim.x + t:
     // small inputs spread over every block first
     const int64_t row = (int64_t)nb * blockDim.x, per_pass = row * MK;
@@ -343,14 +405,21 @@ __device__ __forceinline__ void init_phase(const Ctx &c, const DevGraph &g, Leve
                 best[i] = -1;
             }
         }
-        block_append_mk(bin, vv, bb, dd, ol, cnt, sh, sbase);
+        block_append_mk(bin, vv, bb, dd, ol, cnt, sh, sbase, ho, c.ctrl);
     }
 }
 
-// Inputs of round r: lists and their sizes (round 1: bin 0 is every node).
+// Inputs of round r: lists and their sizes (round 1: bin 0 is every node),
+// and the chunk records of the bin-2 list (grid rounds only).
 struct RoundIn {
     PList in[3];
     int32_t cn[3];
+    int32_t nrec;
+    const int2 *rec;
+    const int32_t *first;
+    // rounds >= 2 with a preparation launch: the rows to rescan
+    const int2 *scan[2];
+    int32_t scn[2];
 };
 template <bool FIRST>
 __device__ __forceinline__ RoundIn round_inputs(const Ctx &c, const DevGraph &g, int r,
@@ -362,6 +431,25 @@ __device__ __forceinline__ RoundIn round_inputs(const Ctx &c, const DevGraph &g,
         ri.cn[b] = min(cnt3[b], g.n);
     }
     if (FIRST) ri.cn[0] = g.n;
+    ri.nrec = 0;
+    ri.rec = nullptr;
+    ri.first = nullptr;
+    ri.scan[0] = ri.scan[1] = nullptr;
+    ri.scn[0] = ri.scn[1] = 0;
+    if (c.ms.hub.rec) {
+        // round 1: records of every bin-2 row (the init lists); later rounds:
+        // records and scan lists of the rows the preparation found to rescan
+        const int32_t *sc = FIRST ? cnt3 : c.ms.state->scnt[r & 3];
+        ri.nrec = (int32_t)min<int64_t>(sc[3], c.ms.hub.cap);
+        ri.rec = c.ms.hub.rec + (int64_t)par * c.ms.hub.cap;
+        ri.first = c.ms.hub.first + (int64_t)par * g.n;
+        if (!FIRST) {
+            for (int b = 0; b < 2; ++b) {
+                ri.scan[b] = c.ms.hub.scan + (int64_t)b * g.n;
+                ri.scn[b] = min(sc[b], g.n);
+            }
+        }
+    }
     return ri;
 }
 
@@ -455,6 +543,136 @@ __device__ __forceinline__ void pick_bin2(const Ctx &c, const DevGraph &g, uint6
         if (threadIdx.x == 0) {
             best[v] = cd.u;
             ri.in[2].b[i] = cd.u;
+        }
+    }
+}
+
+// Rounds >= 2 after a preparation: bins 0 and 1 over the rows to rescan
+// ({node, list position}); the list's choice field is updated for the mutual
+// check.
+template <int R>
+__device__ __forceinline__ void pick_scan0(const Ctx &c, const DevGraph &g, uint64_t seed,
+                                           const RoundIn &ri, unsigned bid, unsigned nb) {
+    const GapView gv = gap_view(c);
+    const int G = SMALL_G;
+    int32_t *best = c.ms.best;
+    const int2 *nrec = c.ms.nrec;
+    const int sub = threadIdx.x & (G - 1);
+    const int64_t gi = (int64_t)bid * (blockDim.x / G) + threadIdx.x / G;
+    const int64_t gs = (int64_t)nb * (blockDim.x / G);
+    const int64_t cnt = ri.scn[0];
+    const int64_t lim = (cnt + gs - 1) / gs * gs;   // uniform trip count (group shuffles)
+    for (int64_t i = gi; i < lim; i += gs) {
+        int2 e = make_int2(-1, -1);
+        bool act = false;
+        uint32_t av = 0;
+        int64_t rb = 0, re = 0;
+        if (i < cnt) {
+            e = ri.scan[0][i];
+            act = (uint32_t)e.x < (uint32_t)g.n && (uint32_t)e.y < (uint32_t)ri.cn[0];
+            if (act) {
+                av = (uint32_t)nrec[e.x].x;
+                rb = g.xadj[e.x];
+                re = g.xadj[e.x + 1];
+                if (re - rb > BIN_SMALL_MAX) re = rb + BIN_SMALL_MAX;   // valid lists never
+            }
+        }
+        Cand cd = act ? scan_row_small<R, G, false>(g, e.x, av, sub, rb, re, nrec, nullptr, seed,
+                                                    local_base(g, e.x), gv)
+                      : cand_none();
+        cd = group_reduce<G>(cd, e.x);
+        if (act && sub == 0) {
+            best[e.x] = cd.u;
+            ri.in[0].b[e.y] = cd.u;
+        }
+    }
+}
+template <int R>
+__device__ __forceinline__ void pick_scan1(const Ctx &c, const DevGraph &g, uint64_t seed,
+                                           const RoundIn &ri, unsigned bid, unsigned nb) {
+    const GapView gv = gap_view(c);
+    int32_t *best = c.ms.best;
+    const int2 *nrec = c.ms.nrec;
+    const int64_t gi = (int64_t)bid * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int64_t gs = (int64_t)nb * (blockDim.x / WAVE);
+    for (int64_t i = gi; i < ri.scn[1]; i += gs) {   // wave-uniform
+        const int2 e = ri.scan[1][i];
+        if ((uint32_t)e.x >= (uint32_t)g.n || (uint32_t)e.y >= (uint32_t)ri.cn[1]) continue;
+        const uint32_t av = (uint32_t)nrec[e.x].x;
+        Cand cd = scan_row<R, WAVE, false>(g, e.x, av, lane_id(), nrec, nullptr, seed,
+                                           local_base(g, e.x), gv);
+        cd = group_reduce<WAVE>(cd, e.x);
+        if (lane_id() == 0) {
+            best[e.x] = cd.u;
+            ri.in[1].b[e.y] = cd.u;
+        }
+    }
+}
+
+// bin 2 in the grid rounds: one block per chunk of HUB_CHUNK entries.  A row
+// of one chunk gets its choice at once; longer rows leave one maximum per
+// chunk in hub.part for hub_reduce_k.  Records exist only for rows that scan
+// this round (round 1: every row; later rounds: the rows whose choice was
+// matched away, found by prep_k).
+template <int R, bool FIRST>
+__device__ __forceinline__ void pick_bin2_chunks(const Ctx &c, const DevGraph &g, uint64_t seed,
+                                                 const RoundIn &ri, unsigned bid, unsigned nb,
+                                                 Cand *sh) {
+    constexpr int T = HUB_CHUNK / BLOCK;
+    static_assert(T * BLOCK == HUB_CHUNK, "a chunk is T entries per thread");
+    int32_t *best = c.ms.best;
+    const int2 *nrec = c.ms.nrec;
+    const uint32_t *out = c.ms.out;
+    for (int64_t q = bid; q < ri.nrec; q += nb) {   // block-uniform
+        const int2 rc = ri.rec[q];
+        if ((uint32_t)rc.x >= (uint32_t)ri.cn[2]) continue;   // valid records never
+        const int32_t v = checked_node(ri.in[2].v[rc.x], g.n, c.ctrl);
+        if (v < 0) continue;
+        const int64_t rb = g.xadj[v], re = g.xadj[v + 1];
+        const int64_t j0 = rb + (int64_t)rc.y * HUB_CHUNK;
+        const int64_t j1 = min(re, j0 + HUB_CHUNK);
+        const uint32_t av = FIRST ? attr_src<R>(g, out, v) : (uint32_t)nrec[v].x;
+        const int32_t base = local_base(g, v);
+        // T entries per thread, strided by the block for coalesced row loads
+        int32_t u[T];
+        uint32_t w[T], au[T];
+        bool ok[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const int64_t j = j0 + (int64_t)t * BLOCK + threadIdx.x;
+            ok[t] = j < j1;
+            u[t] = ok[t] ? g.adj[j] : 0;
+            w[t] = ok[t] ? g.ew[j] : 0u;
+        }
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            if (FIRST) {
+                au[t] = ok[t] ? attr_src<R>(g, out, u[t]) : 0u;
+            } else {
+                const int2 rec = ok[t] ? nrec[u[t]] : make_int2(0, 0);
+                ok[t] = ok[t] && rec.y < 0;
+                au[t] = (uint32_t)rec.x;
+            }
+        }
+        Cand cd = cand_none();
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            if (!ok[t]) continue;
+            Cand e;
+            rate<R>(w[t], au[t], av, au[t], av, e.num, e.den);
+            e.h = mix64(seed ^ edge_id_local(v, u[t], base));
+            e.u = u[t];
+            if (cand_better(e, cd, v)) cd = e;
+        }
+        cd = block_reduce_cand(cd, v, sh);
+        if (threadIdx.x == 0) {
+            if (hub_chunks_of(re - rb) == 1) {
+                best[v] = cd.u;
+                ri.in[2].b[rc.x] = cd.u;
+            } else {
+                const int32_t f = ri.first[rc.x];
+                if (f >= 0) c.ms.hub.part[f + rc.y] = cd;
+            }
         }
     }
 }
@@ -586,14 +804,15 @@ __global__ void __launch_bounds__(BLOCK) match_init_k(Ctx c, int l, int stop_rul
         L->matched = 0;
         L->rounds = 0;
     }
-    if (lists) init_phase(c, g, L, sh, sbase, blockIdx.x, gridDim.x, &c.ms.state->cnt[0][0]);
+    if (lists) init_phase(c, g, L, sh, sbase, blockIdx.x, gridDim.x, &c.ms.state->cnt[0][0], true);
 }
 
 struct PickGrid {
     unsigned b0, b1, b2;  // blocks per bin
 };
 
-template <int R, bool FIRST, int F = 0>
+// SCAN (rounds >= 2, long rows in chunks): the rows prep_k found to rescan.
+template <int R, bool FIRST, int F = 0, bool SCAN = false>
 __global__ void __launch_bounds__(BLOCK) pick_k(Ctx c, int l, int r, PickGrid pg) {
     __shared__ Cand sh[BLOCK / WAVE];
     DevGraph g;
@@ -615,11 +834,140 @@ __global__ void __launch_bounds__(BLOCK) pick_k(Ctx c, int l, int r, PickGrid pg
     }
     const uint64_t seed = level_seed(c, l);
     unsigned bid = blockIdx.x;
+    if (SCAN) {
+        if (bid < pg.b0) { pick_scan0<R>(c, g, seed, ri, bid, pg.b0); return; }
+        bid -= pg.b0;
+        if (bid < pg.b1) { pick_scan1<R>(c, g, seed, ri, bid, pg.b1); return; }
+        bid -= pg.b1;
+        pick_bin2_chunks<R, false>(c, g, seed, ri, bid, pg.b2, sh);
+        return;
+    }
     if (bid < pg.b0) { pick_bin0<R, FIRST, F>(c, g, seed, ri, bid, pg.b0); return; }
     bid -= pg.b0;
     if (bid < pg.b1) { pick_bin1<R, FIRST, F>(c, g, seed, ri, bid, pg.b1); return; }
     bid -= pg.b1;
-    pick_bin2<R, FIRST, BLOCK, F>(c, g, seed, ri, bid, pg.b2, sh);
+    if (F == 0 && ri.rec)
+        pick_bin2_chunks<R, FIRST>(c, g, seed, ri, bid, pg.b2, sh);
+    else
+        pick_bin2<R, FIRST, BLOCK, F>(c, g, seed, ri, bid, pg.b2, sh);
+}
+
+// Preparation of round r >= 2 (long rows in chunks): every pending entry
+// whose choice was matched away in round r - 1 must rescan its row.  Rows of
+// bins 0 and 1 go to the scan lists ({node, list position}); bin-2 rows get
+// their chunk records (first = the row's first record, -1 for a row that
+// keeps its choice).  Also applies the hand-over tests of the round (nothing
+// pending, or few enough for the finisher).  A thread's MK entries are loaded
+// together.
+__global__ void __launch_bounds__(BLOCK) prep_k(Ctx c, int l, int r) {
+    __shared__ int64_t sh[BLOCK / WAVE + 1];
+    __shared__ int32_t sbase[2];
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_MATCH, g)) return;
+    MatchState *st = c.ms.state;
+    if (st->handoff != -1 || !c.ms.hub.rec) return;
+    const RoundIn ri = round_inputs<false>(c, g, r, st->cnt[(r - 1) & 3]);
+    const int32_t c0 = ri.cn[0], c1 = ri.cn[1];
+    const int64_t total = (int64_t)c0 + c1 + ri.cn[2];
+    if (total == 0 || total <= TAIL_MAX) {
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            atomicCAS(&st->handoff, -1, total == 0 ? -2 : r - 1);
+        return;
+    }
+    int32_t *sc = st->scnt[r & 3];
+    int2 *const scan0 = c.ms.hub.scan, *const scan1 = c.ms.hub.scan + g.n;
+    const int par = (r - 1) & 1;
+    const HubOut ho{c.ms.hub.rec + (int64_t)par * c.ms.hub.cap,
+                    c.ms.hub.first + (int64_t)par * g.n, sc + 3, c.ms.hub.cap};
+    const int2 *nrec = c.ms.nrec;
+    const int64_t row = (int64_t)gridDim.x * blockDim.x, per_pass = row * MK;
+    for (int64_t base = 0; base < total; base += per_pass) {   // block-uniform
+        const int64_t first = base + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        int32_t vv[MK], bb[MK], dd[MK], jj[MK], bin[MK];
+        bool resc[MK];
+#pragma unroll
+        for (int k = 0; k < MK; ++k) {
+            const int64_t i = first + (int64_t)k * row;
+            bin[k] = -1;
+            vv[k] = bb[k] = -1;
+            dd[k] = 0;
+            jj[k] = 0;
+            if (i >= total) continue;
+            PList src;
+            if (i < c0) { src = ri.in[0]; jj[k] = (int32_t)i; bin[k] = 0; }
+            else if (i < (int64_t)c0 + c1) { src = ri.in[1]; jj[k] = (int32_t)(i - c0); bin[k] = 1; }
+            else { src = ri.in[2]; jj[k] = (int32_t)(i - c0 - c1); bin[k] = 2; }
+            vv[k] = src.v[jj[k]];
+            bb[k] = src.b[jj[k]];
+            dd[k] = src.d[jj[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < MK; ++k) {
+            const bool live = bin[k] >= 0 && (uint32_t)vv[k] < (uint32_t)g.n;
+            resc[k] = live && !keeps_choice(bb[k], g.n, nrec);
+            if (bin[k] >= 0 && !live) bin[k] = -1;   // valid lists never
+        }
+        // rows of bins 0 and 1 that rescan: block-aggregated append
+        int64_t packed = 0;
+#pragma unroll
+        for (int k = 0; k < MK; ++k)
+            if (resc[k] && bin[k] < 2) packed += (int64_t)1 << (21 * bin[k]);
+        int64_t tot;
+        const int64_t pre = block_excl_scan(packed, sh, &tot);
+        if (threadIdx.x < 2) {
+            const int32_t t = (int32_t)((tot >> (21 * threadIdx.x)) & 0x1fffff);
+            sbase[threadIdx.x] = t ? atomicAdd(&sc[threadIdx.x], t) : 0;
+        }
+        __syncthreads();
+        int32_t p0 = sbase[0] + (int32_t)(pre & 0x1fffff);
+        int32_t p1 = sbase[1] + (int32_t)((pre >> 21) & 0x1fffff);
+#pragma unroll
+        for (int k = 0; k < MK; ++k) {
+            if (bin[k] == 2) {
+                if (resc[k]) hub_emit(ho, jj[k], dd[k], c.ctrl);
+                else ho.first[jj[k]] = -1;
+            } else if (resc[k]) {
+                if (bin[k] == 0) scan0[p0++] = make_int2(vv[k], jj[k]);
+                else scan1[p1++] = make_int2(vv[k], jj[k]);
+            }
+        }
+        __syncthreads();   // sbase is reused by the next pass
+    }
+}
+
+// The choices of bin-2 rows of more than one chunk: the best of their
+// chunks' maxima (one wave per row).  Runs between the pick and the mate
+// launches of a grid round, under the same gates.
+template <bool FIRST>
+__global__ void __launch_bounds__(BLOCK) hub_reduce_k(Ctx c, int l, int r) {
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_MATCH, g)) return;
+    MatchState *st = c.ms.state;
+    if (st->handoff != -1 || !c.ms.hub.rec) return;
+    const RoundIn ri = round_inputs<FIRST>(c, g, r, st->cnt[FIRST ? 0 : (r - 1) & 3]);
+    int32_t *best = c.ms.best;
+    const int64_t gi = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE;
+    const int64_t gs = (int64_t)gridDim.x * (BLOCK / WAVE);
+    for (int64_t i = gi; i < ri.cn[2]; i += gs) {   // wave-uniform
+        const int32_t f = ri.first[i];   // -1: the row keeps its choice (prep_k)
+        if (f < 0) continue;
+        const int32_t v = ri.in[2].v[i];
+        if ((uint32_t)v >= (uint32_t)g.n) continue;   // flagged by the pick
+        const int32_t k = hub_chunks_of(g.xadj[v + 1] - g.xadj[v]);
+        if (k <= 1) continue;
+        Cand cd = cand_none();
+        for (int32_t q = lane_id(); q < k; q += WAVE) {
+            const Cand o = c.ms.hub.part[f + q];
+            if (cand_better(o, cd, v)) cd = o;
+        }
+        cd = group_reduce<WAVE>(cd, v);
+        if (lane_id() == 0) {
+            best[v] = cd.u;
+            ri.in[2].b[i] = cd.u;
+        }
+    }
 }
 
 template <int R, bool FIRST>
@@ -632,8 +980,12 @@ __global__ void __launch_bounds__(BLOCK) mate_k(Ctx c, int l, int r) {
     MatchState *st = c.ms.state;
     if (st->handoff != -1) return;
     const RoundIn ri = round_inputs<FIRST>(c, g, r, st->cnt[FIRST ? 0 : (r - 1) & 3]);
-    // the counters of round r + 2 were last read by round r - 1
-    if (blockIdx.x == 0 && threadIdx.x < 3) st->cnt[(r + 2) & 3][threadIdx.x] = 0;
+    // the counters of round r + 2 were last read by round r - 1 (list sizes)
+    // and round r - 2 (rescan counts)
+    if (blockIdx.x == 0 && threadIdx.x < 4) {
+        st->cnt[(r + 2) & 3][threadIdx.x] = 0;
+        st->scnt[(r + 2) & 3][threadIdx.x] = 0;
+    }
     mate_phase<R, FIRST>(c, g, L, r, ri, st->cnt[r & 3], blockIdx.x, gridDim.x, sh, sbase);
 }
 
@@ -644,7 +996,7 @@ __global__ void __launch_bounds__(BLOCK) mate_k(Ctx c, int l, int r) {
 // was hit (broken state).
 template <int R, int NT, int F = 0>
 __device__ bool wg_rounds(const Ctx &c, const DevGraph &g, LevelDesc *L, uint64_t seed, int r0,
-                          int32_t (*s_cnt)[3], Cand *shc, int64_t *sh, int32_t *sbase) {
+                          int32_t (*s_cnt)[4], Cand *shc, int64_t *sh, int32_t *sbase) {
     const int64_t r_cap = (int64_t)r0 + 2 + g.n;
     for (int r = r0 + 1; r <= r_cap; ++r) {
         const RoundIn ri = round_inputs<false>(c, g, r, s_cnt[(r - 1) & 1]);
@@ -696,12 +1048,13 @@ __device__ void close_matching(const Ctx &c, LevelDesc *L, bool capped, int grid
             }
         }
     }
-    if (threadIdx.x < 4) {
-        c.cs.row_cnt[threadIdx.x] = 0;
-        c.cs.totals[threadIdx.x] = 0;
-    }
+    if (threadIdx.x < 8) c.cs.row_cnt[threadIdx.x] = 0;
+    if (threadIdx.x < 4) c.cs.totals[threadIdx.x] = 0;
     __syncthreads();   // every read of st->cnt is done
-    if (threadIdx.x < 16) st->cnt[threadIdx.x >> 2][threadIdx.x & 3] = 0;   // next level's lists
+    if (threadIdx.x < 16) {   // next level's lists
+        st->cnt[threadIdx.x >> 2][threadIdx.x & 3] = 0;
+        st->scnt[threadIdx.x >> 2][threadIdx.x & 3] = 0;
+    }
     if (threadIdx.x == 0) {
         int64_t m = s_acc[0];
         const int32_t used = (int32_t)s_acc[1];
@@ -730,7 +1083,7 @@ template <int R, int F = 0>
 __global__ void __launch_bounds__(FINISH_THREADS) finish_k(Ctx c, int l, int r_last) {
     __shared__ Cand shc[FINISH_THREADS / WAVE];
     __shared__ int64_t sh[3 * (FINISH_THREADS / WAVE) + 1];
-    __shared__ int32_t s_cnt[2][3];
+    __shared__ int32_t s_cnt[2][4];
     __shared__ int32_t sbase[3];
     __shared__ int64_t s_acc[2];
     __shared__ int32_t s_r0;
@@ -1276,6 +1629,7 @@ struct DegF {
         }
         L->phase = PH_COMPACT;
         ctrl->nlevels = l + 2;
+        ctrl->last_n = (int32_t)nc;
         if (stall_num > 0 && (uint64_t)(n - nc) * stall_den < (uint64_t)stall_num * (uint64_t)n) {
             N->stop = KAPPA_STOP_STALL;
             N->phase = PH_STOPPED;
@@ -1349,8 +1703,18 @@ __device__ __forceinline__ void row_entry(const DevGraph &g, const int32_t *cmap
     }
 }
 
+// Merge classes by the bound on the merged row: 0 small (16 lanes), 1 one
+// wave, 3 one block, 2 large (hub accumulators); -1 empty.
 __device__ __forceinline__ int row_class(int64_t bound) {
-    return bound == 0 ? -1 : (bound <= ROW_SMALL_MAX ? 0 : (bound <= ROW_MID_MAX ? 1 : 2));
+    if (bound == 0) return -1;
+    if (bound <= ROW_SMALL_MAX) return 0;
+    if (bound <= ROW_WAVE_MAX) return 1;
+    if (bound <= ROW_MID_MAX) return 3;
+    return bound <= ROW_BIG_MAX ? 4 : 2;
+}
+__device__ __forceinline__ int32_t *class_list(const ContractScratch &cs, int32_t n, int cls) {
+    const int slot = cls == 3 ? 0 : (cls == 1 ? 1 : (cls == 2 ? 2 : 3));
+    return cs.rows + (int64_t)slot * n;
 }
 
 // Orders the LDS traffic of one wave (all lanes of the wave call it).
@@ -1365,7 +1729,8 @@ __device__ __forceinline__ void wave_sync_lds() {
 // The contraction phases below are written for `nb` blocks of NT threads
 // (block `bid`): the kernels run them over their grid; the tail kernel runs
 // them in one workgroup.
-template <int NT>
+// BIG: rows of the big class get their own list (false: they join the large rows).
+template <int NT, bool BIG = true>
 __device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bid, unsigned nb) {
     constexpr int ROWS = NT / ROW_SMALL_G;
     __shared__ uint32_t sk[ROWS][SM_CAP];   // renamed entries
@@ -1377,7 +1742,8 @@ __device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bi
     const int32_t *cmap = L->cmap;
     const int grp = threadIdx.x / ROW_SMALL_G, sub = threadIdx.x % ROW_SMALL_G;
     const int64_t count = c.lv[l + 1].n;
-    int32_t *lists1 = c.cs.rows + g.n, *lists2 = c.cs.rows + 2 * (int64_t)g.n;
+    int32_t *lists1 = class_list(c.cs, g.n, 1), *lists2 = class_list(c.cs, g.n, 2),
+            *lists3 = class_list(c.cs, g.n, 3), *lists4 = class_list(c.cs, g.n, 4);
     const int64_t gs = (int64_t)nb * ROWS;
     const int64_t lim = (count + gs - 1) / gs * gs;   // uniform trip count
     bool need_hubs = false;
@@ -1391,10 +1757,13 @@ __device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bi
         if (live) {
             r = row_src(g, c, x);
             cls = row_class(row_bound(r));
+            if (!BIG && cls == 4) cls = 2;
             if (cls == 2 && !c.cs.hub_acc) need_hubs = true;
         }
         wave_append(sub == 0 && cls == 1, x, lists1, &c.cs.row_cnt[1]);
         wave_append(sub == 0 && cls == 2, x, lists2, &c.cs.row_cnt[2]);
+        wave_append(sub == 0 && cls == 3, x, lists3, &c.cs.row_cnt[3]);
+        wave_append(sub == 0 && cls == 4, x, lists4, &c.cs.row_cnt[4]);
         const int tot = cls == 0 ? (int)r.tot : 0;
         for (int t = sub; t < tot; t += ROW_SMALL_G) {
             uint32_t k, w;
@@ -1435,45 +1804,82 @@ __global__ void __launch_bounds__(BLOCK) fill_small_k(Ctx c, int l) {
     fill_small_body<BLOCK>(c, l, blockIdx.x, gridDim.x);
 }
 
-// --- 2b. mid rows: one block per row, bitonic sort in LDS -------------------------
-template <int NT>
-__device__ __forceinline__ void fill_mid_body(const Ctx &c, int l, unsigned bid, unsigned nb) {
-    __shared__ uint64_t s[MID_P];
+// --- 2b. mid and big rows: one block per row, bitonic sort in LDS ------------------
+// The sort's stages whose compare distance stays inside one wave's contiguous
+// slice of the array (P / waves elements) need only that wave's LDS order;
+// only the few wider stages take a block barrier.  s: PMAX entries of LDS.
+template <int NT, int PMAX>
+__device__ __forceinline__ void fill_block_body(const Ctx &c, int l, unsigned bid, unsigned nb,
+                                                int cls, uint64_t *s) {
     __shared__ int64_t sh[NT / WAVE + 1];
+    constexpr int NW = NT / WAVE;
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_CONTRACT, g)) return;
     const int32_t *cmap = L->cmap;
-    const int64_t count = c.cs.row_cnt[1];
+    const int64_t count = c.cs.row_cnt[cls];
+    const int32_t *list = class_list(c.cs, g.n, cls);
+    const int wv = threadIdx.x / WAVE, lane = lane_id();
     for (int64_t i = bid; i < count; i += nb) {
-        int32_t x = c.cs.rows[g.n + i];
-        RowSrc r = row_src(g, c, x);
-        int tot = (int)r.tot;
+        const int32_t x = list[i];
+        const RowSrc r = row_src(g, c, x);
+        const int tot = (int)r.tot;
         int P = 2;
         while (P < tot) P <<= 1;
-        for (int t = threadIdx.x; t < P; t += NT) {
-            uint64_t val = ~0ull;
-            if (t < tot) {
-                uint32_t k, w;
-                row_entry(g, cmap, r, t, k, w);
-                val = ((uint64_t)k << 32) | w;
+        if (P > PMAX) {   // valid class lists never
+            if (threadIdx.x == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_STATE);
+            continue;
+        }
+        for (int t0 = threadIdx.x; t0 < P; t0 += NT * 4) {
+            uint64_t val[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + u * NT;
+                val[u] = ~0ull;
+                if (t < tot) {
+                    uint32_t k, w;
+                    row_entry(g, cmap, r, t, k, w);
+                    val[u] = ((uint64_t)k << 32) | w;
+                }
             }
-            s[t] = val;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (t0 + u * NT < P) s[t0 + u * NT] = val[u];
         }
         __syncthreads();
+        const int chunk = P / NW;             // a wave's slice
+        const bool wave_stages = chunk >= WAVE;
+        bool synced = true;                   // every wave's LDS writes seen by the block
         for (int k = 2; k <= P; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int t = threadIdx.x; t < P; t += NT) {
-                    int ixj = t ^ j;
-                    if (ixj > t) {
-                        uint64_t a = s[t], b = s[ixj];
-                        bool up = (t & k) == 0;
-                        if ((a > b) == up) { s[t] = b; s[ixj] = a; }
+                if (!wave_stages || j >= chunk) {
+                    if (!synced) __syncthreads();
+                    for (int t = threadIdx.x; t < P; t += NT) {
+                        const int ixj = t ^ j;
+                        if (ixj > t) {
+                            const uint64_t a = s[t], b = s[ixj];
+                            const bool up = (t & k) == 0;
+                            if ((a > b) == up) { s[t] = b; s[ixj] = a; }
+                        }
                     }
+                    __syncthreads();
+                    synced = true;
+                } else {
+                    const int lo = wv * chunk;
+                    for (int t = lo + lane; t < lo + chunk; t += WAVE) {
+                        const int ixj = t ^ j;
+                        if (ixj > t) {
+                            const uint64_t a = s[t], b = s[ixj];
+                            const bool up = (t & k) == 0;
+                            if ((a > b) == up) { s[t] = b; s[ixj] = a; }
+                        }
+                    }
+                    wave_sync_lds();
+                    synced = false;
                 }
-                __syncthreads();
             }
         }
+        if (!synced) __syncthreads();
         // leaders: first entry of each run of equal keys
         const int ipt = (P + NT - 1) / NT;
         const int t0 = threadIdx.x * ipt;
@@ -1502,15 +1908,124 @@ __device__ __forceinline__ void fill_mid_body(const Ctx &c, int l, unsigned bid,
         __syncthreads();
     }
 }
-__global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l) {
-    fill_mid_body<BLOCK>(c, l, blockIdx.x, gridDim.x);
+template <int NT>
+__device__ __forceinline__ void fill_mid_body(const Ctx &c, int l, unsigned bid, unsigned nb,
+                                              int cls = 3) {
+    __shared__ uint64_t s[MID_P];
+    fill_block_body<NT, MID_P>(c, l, bid, nb, cls, s);
+}
+
+// Rows of 4095..16382 entries: one block of BIG_THREADS per row, the whole
+// row sorted in 128 KiB of LDS (one block per CU).
+constexpr int BIG_P = ROW_BIG_MAX + 2;
+constexpr int BIG_THREADS = 1024;
+static_assert((BIG_P & (BIG_P - 1)) == 0, "big-row sort size");
+__global__ void __launch_bounds__(BIG_THREADS) fill_big_k(Ctx c, int l) {
+    __shared__ uint64_t s[BIG_P];
+    fill_block_body<BIG_THREADS, BIG_P>(c, l, blockIdx.x, gridDim.x, 4, s);
+}
+// --- 2a'. rows of 65..512 entries: one wave per row, bitonic sort of the
+//          renamed entries in the wave's LDS slice, then a leader scan -------------
+constexpr int WR_P = ROW_WAVE_MAX;   // sort size of a wave row (power of two)
+template <int NT>
+__device__ __forceinline__ void fill_wave_body(const Ctx &c, int l, unsigned bid, unsigned nb,
+                                               uint64_t *lds) {
+    static_assert((WR_P & (WR_P - 1)) == 0 && WR_P % WAVE == 0, "wave sort size");
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_CONTRACT, g)) return;
+    const int32_t *cmap = L->cmap;
+    const int64_t count = c.cs.row_cnt[1];
+    const int32_t *list = class_list(c.cs, g.n, 1);
+    const int wv = threadIdx.x / WAVE, lane = lane_id();
+    uint64_t *s = lds + (int64_t)wv * WR_P;
+    const int64_t gw = (int64_t)bid * (NT / WAVE) + wv, gs = (int64_t)nb * (NT / WAVE);
+    for (int64_t i = gw; i < count; i += gs) {   // wave-uniform
+        const int32_t x = list[i];
+        const RowSrc r = row_src(g, c, x);
+        // the renamed entries without the contracted edge (at most the row's
+        // bound, <= WR_P of them), packed to the front of the slice
+        const int tot = (int)r.tot;
+        int q = 0;
+        for (int t0 = 0; t0 < tot; t0 += WAVE) {
+            const int t = t0 + lane;
+            uint32_t k = INVALID_KEY, w = 0;
+            if (t < tot) row_entry(g, cmap, r, t, k, w);
+            const bool keep = k != INVALID_KEY;
+            const uint64_t m = __ballot(keep);
+            if (keep) s[q + __popcll(m & lanemask_lt())] = ((uint64_t)k << 32) | w;
+            q += (int)__popcll(m);
+        }
+        int P = WAVE;
+        while (P < q) P <<= 1;
+        for (int t = q + lane; t < P; t += WAVE) s[t] = ~0ull;   // padding sorts last
+        wave_sync_lds();
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int t = lane; t < P; t += WAVE) {
+                    const int ixj = t ^ j;
+                    if (ixj > t) {
+                        const uint64_t a = s[t], b = s[ixj];
+                        const bool up = (t & k) == 0;
+                        if ((a > b) == up) { s[t] = b; s[ixj] = a; }
+                    }
+                }
+                wave_sync_lds();
+            }
+        }
+        // leaders (first entry of each run of equal keys) in order; runs summed
+        int32_t rank = 0;
+        for (int t0 = 0; t0 < P; t0 += WAVE) {
+            const int t = t0 + lane;
+            const uint32_t k = (uint32_t)(s[t] >> 32);
+            const bool lead = k != INVALID_KEY && (t == 0 || (uint32_t)(s[t - 1] >> 32) != k);
+            const uint64_t m = __ballot(lead);
+            if (lead) {
+                uint32_t sum = 0;
+                for (int e = t; e < P && (uint32_t)(s[e] >> 32) == k; ++e) sum += (uint32_t)s[e];
+                const int64_t at = staged_at(r, rank + (int32_t)__popcll(m & lanemask_lt()));
+                c.cs.tmp_adj[at] = (int32_t)k;
+                c.cs.tmp_ew[at] = sum;
+            }
+            rank += (int32_t)__popcll(m);
+        }
+        if (lane == 0) c.cs.cdeg[x] = rank;
+        wave_sync_lds();   // the slice is rewritten by the next row
+    }
+}
+
+// Both mid classes in one launch: blocks [0, wave_blocks) merge the rows of
+// 65..512 entries one wave each, the rest the rows of 513..4094 one block each.
+__global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l, unsigned wave_blocks) {
+    static_assert((BLOCK / WAVE) * WR_P <= MID_P, "the wave rows' slices fit the block rows' array");
+    __shared__ uint64_t s[MID_P];
+    if (blockIdx.x < wave_blocks)
+        fill_wave_body<BLOCK>(c, l, blockIdx.x, wave_blocks, s);
+    else
+        fill_block_body<BLOCK, MID_P>(c, l, blockIdx.x - wave_blocks, gridDim.x - wave_blocks, 3, s);
 }
 
 // --- 2c. large rows: dense accumulator per slot --------------------------------------
-// Slot `bid` of the hub accumulators (bid < hub_slots).
+// Slot `bid` of the hub accumulators (bid < hub_slots): a dense sum per
+// coarse id, a bitmap of the ids present (one bit per id) and a summary
+// bitmap (one bit per nonzero bitmap word).  The read-back walks the summary
+// in chunks of LG_SUM summary words, gathers the chunk's nonzero bitmap words
+// into LDS, and hands out the chunk's ids by rank (a thread finds the word
+// holding its rank by a binary search over the words' prefix counts), so the
+// work follows the ids present rather than the id range and is spread evenly
+// over the block.  Every array is left zero for the next row.
+constexpr int LG_SUM = 128;                 // summary words per chunk
+constexpr int LG_WORDS = LG_SUM * 32;       // nonzero bitmap words of a chunk, at most
+constexpr int LG_IDS = 4;                   // ids per thread in flight (read-back)
+constexpr int LG_ACC = 8;                   // entries per thread in flight (accumulation)
 template <int NT>
 __device__ __forceinline__ void fill_large_body(const Ctx &c, int l, unsigned bid, unsigned nb) {
-    __shared__ int64_t s_wcnt[NT / WAVE + 1];
+    static_assert(NT >= LG_SUM && LG_WORDS % NT == 0, "chunk layout");
+    constexpr int WPT = LG_WORDS / NT;       // bitmap words per thread of a chunk
+    __shared__ int32_t s_word[LG_WORDS];     // the chunk's nonzero bitmap words: index
+    __shared__ uint32_t s_bits[LG_WORDS];    //   and value
+    __shared__ int32_t s_pre[LG_WORDS];      //   and the ids in the words before it
+    __shared__ int64_t sh[NT / WAVE + 1];
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_CONTRACT, g)) return;
@@ -1518,55 +2033,123 @@ __device__ __forceinline__ void fill_large_body(const Ctx &c, int l, unsigned bi
     const int32_t *cmap = L->cmap;
     uint32_t *acc = c.cs.hub_acc + (int64_t)bid * g.n;
     uint32_t *bits = c.cs.hub_bits + (int64_t)bid * c.cs.hub_words;
+    uint32_t *sbits = bits + c.cs.hub_w1;
     const int64_t nc = c.lv[l + 1].n;
-    const int64_t nwords = (nc + 31) / 32;
+    const int64_t nwords = (nc + 31) / 32, nsum = (nwords + 31) / 32;
     const int64_t count = c.cs.row_cnt[2];
-    const int nw = NT / WAVE, wv = threadIdx.x / WAVE;
-    const int64_t span = (nwords + nw - 1) / nw;
-    const int64_t lo = wv * span, hi = lo + span < nwords ? lo + span : nwords;
     for (int64_t i = bid; i < count; i += nb) {
-        int32_t x = c.cs.rows[2 * (int64_t)g.n + i];
-        RowSrc r = row_src(g, c, x);
-        for (int64_t t = threadIdx.x; t < r.tot; t += NT) {
-            uint32_t k, w;
-            row_entry(g, cmap, r, t, k, w);
-            if (k == INVALID_KEY) continue;
-            atomicAdd(&acc[k], w);
-            atomicOr(&bits[k >> 5], 1u << (k & 31));
+        const int32_t x = c.cs.rows[2 * (int64_t)g.n + i];
+        const RowSrc r = row_src(g, c, x);
+        // LG_ACC entries per thread in flight: their loads, renames and
+        // atomics are issued before any result is waited for
+        for (int64_t t0 = threadIdx.x; t0 < r.tot; t0 += (int64_t)NT * LG_ACC) {
+            uint32_t k[LG_ACC], w[LG_ACC], old[LG_ACC];
+#pragma unroll
+            for (int u = 0; u < LG_ACC; ++u) {
+                const int64_t t = t0 + (int64_t)u * NT;
+                k[u] = INVALID_KEY;
+                w[u] = 0;
+                if (t < r.tot) row_entry(g, cmap, r, t, k[u], w[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < LG_ACC; ++u) {
+                old[u] = 1;
+                if (k[u] == INVALID_KEY) continue;
+                atomicAdd(&acc[k[u]], w[u]);
+                old[u] = atomicOr(&bits[k[u] >> 5], 1u << (k[u] & 31));
+            }
+#pragma unroll
+            for (int u = 0; u < LG_ACC; ++u)
+                if (old[u] == 0) atomicOr(&sbits[k[u] >> 10], 1u << ((k[u] >> 5) & 31));
         }
         __threadfence();
         __syncthreads();
-        // pass 1: set bits per wave range (L1-bypassing loads)
-        int64_t cntw = 0;
-        for (int64_t q = lo + lane_id(); q < hi; q += WAVE)
-            cntw += __popc(__hip_atomic_load(&bits[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        cntw = wave_sum(cntw);
-        if (lane_id() == 0) s_wcnt[wv] = cntw;
-        __syncthreads();
-        int64_t base = 0, total = 0;
-        for (int q = 0; q < nw; ++q) {
-            if (q < wv) base += s_wcnt[q];
-            total += s_wcnt[q];
-        }
-        // pass 2: ascending walk, read-and-clear bits and accumulators
-        for (int64_t q0 = lo; q0 < hi; q0 += WAVE) {
-            int64_t q = q0 + lane_id();
-            uint32_t word = q < hi ? atomicExch(&bits[q], 0u) : 0u;
-            int64_t pc = __popc(word);
-            int64_t inc = wave_incl_scan(pc);
-            int64_t pos = base + inc - pc;
-            while (word) {
-                int b = __ffs(word) - 1;
-                word &= word - 1;
-                uint32_t key = (uint32_t)(q * 32 + b);
-                int64_t at = staged_at(r, pos);
-                c.cs.tmp_adj[at] = (int32_t)key;
-                c.cs.tmp_ew[at] = atomicExch(&acc[key], 0u);
-                ++pos;
+        int64_t pos = 0;   // ids written so far (block-uniform)
+        for (int64_t s0 = 0; s0 < nsum; s0 += LG_SUM) {
+            // 1. the chunk's nonzero bitmap words in ascending order
+            uint32_t sw = 0;
+            if (threadIdx.x < LG_SUM && s0 + threadIdx.x < nsum) {
+                uint32_t *p = &sbits[s0 + threadIdx.x];
+                sw = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (sw) *p = 0u;
             }
-            base += __shfl(inc, WAVE - 1, WAVE);
+            int64_t nw_tot;
+            const int64_t at = block_excl_scan((int64_t)__popc(sw), sh, &nw_tot);
+            if (nw_tot == 0) continue;   // block-uniform; nothing was written to LDS
+            {
+                int32_t q = (int32_t)at;
+                uint32_t m = sw;
+                while (m) {
+                    const int b = __ffs(m) - 1;
+                    m &= m - 1;
+                    s_word[q++] = (int32_t)((s0 + threadIdx.x) * 32 + b);
+                }
+            }
+            __syncthreads();
+            // 2. the words themselves (WPT consecutive list entries per thread)
+            const int nw = (int)nw_tot;
+            uint32_t wv[WPT];
+#pragma unroll
+            for (int j = 0; j < WPT; ++j) {
+                const int q = threadIdx.x * WPT + j;
+                wv[j] = q < nw ? __hip_atomic_load(&bits[s_word[q]], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT)
+                               : 0u;
+            }
+            int64_t mine = 0;
+#pragma unroll
+            for (int j = 0; j < WPT; ++j) mine += __popc(wv[j]);
+            int64_t ids_tot;
+            int64_t run = block_excl_scan(mine, sh, &ids_tot);
+#pragma unroll
+            for (int j = 0; j < WPT; ++j) {
+                const int q = threadIdx.x * WPT + j;
+                if (q < nw) {
+                    s_pre[q] = (int32_t)run;
+                    s_bits[q] = wv[j];
+                    bits[s_word[q]] = 0u;
+                }
+                run += __popc(wv[j]);
+            }
+            __syncthreads();
+            // 3. ids by rank: the word holding rank k, then the bit within it
+            const int32_t kt = (int32_t)ids_tot;
+            for (int32_t k0 = 0; k0 < kt; k0 += NT * LG_IDS) {
+                uint32_t key[LG_IDS], val[LG_IDS];
+                bool ok[LG_IDS];
+#pragma unroll
+                for (int u = 0; u < LG_IDS; ++u) {
+                    const int32_t k = k0 + u * NT + (int32_t)threadIdx.x;
+                    ok[u] = k < kt;
+                    key[u] = 0;
+                    if (!ok[u]) continue;
+                    int lo = 0, hi = nw - 1;   // the last word with s_pre <= k
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_pre[mid] <= k) lo = mid; else hi = mid - 1;
+                    }
+                    uint32_t wb = s_bits[lo];
+                    for (int z = k - s_pre[lo]; z > 0; --z) wb &= wb - 1;
+                    key[u] = (uint32_t)s_word[lo] * 32u + (uint32_t)(__ffs(wb) - 1);
+                }
+#pragma unroll
+                for (int u = 0; u < LG_IDS; ++u)
+                    val[u] = ok[u] ? __hip_atomic_load(&acc[key[u]], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT)
+                                   : 0u;
+#pragma unroll
+                for (int u = 0; u < LG_IDS; ++u) {
+                    if (!ok[u]) continue;
+                    const int64_t st = staged_at(r, pos + k0 + u * NT + threadIdx.x);
+                    c.cs.tmp_adj[st] = (int32_t)key[u];
+                    c.cs.tmp_ew[st] = val[u];
+                    acc[key[u]] = 0u;
+                }
+            }
+            pos += kt;
+            __syncthreads();   // the chunk's LDS lists are read before the next chunk writes them
         }
-        if (threadIdx.x == 0) c.cs.cdeg[x] = (int32_t)total;
+        if (threadIdx.x == 0) c.cs.cdeg[x] = (int32_t)pos;
         __threadfence();
         __syncthreads();
     }
@@ -1624,9 +2207,13 @@ __device__ __forceinline__ void compact_big_body(const Ctx &c, int l, unsigned b
     if (!load_level(L, PH_COMPACT, g)) return;
     const LevelDesc *N = c.lv + l + 1;
     uint32_t *out = c.rating == KAPPA_INNER_OUTER ? c.ms.out : nullptr;
-    const int64_t c1 = c.cs.row_cnt[1], c2 = c.cs.row_cnt[2];
-    for (int64_t i = bid; i < c1 + c2; i += nb) {
-        int32_t x = i < c1 ? c.cs.rows[g.n + i] : c.cs.rows[2 * (int64_t)g.n + (i - c1)];
+    const int64_t c1 = c.cs.row_cnt[1], c2 = c.cs.row_cnt[2], c3 = c.cs.row_cnt[3],
+                  c4 = c.cs.row_cnt[4];
+    for (int64_t i = bid; i < c1 + c2 + c3 + c4; i += nb) {
+        const int32_t x = i < c1 ? class_list(c.cs, g.n, 1)[i]
+                        : i < c1 + c2 ? class_list(c.cs, g.n, 2)[i - c1]
+                        : i < c1 + c2 + c3 ? class_list(c.cs, g.n, 3)[i - c1 - c2]
+                                           : class_list(c.cs, g.n, 4)[i - c1 - c2 - c3];
         RowSrc r = row_src(g, c, x);
         int64_t dst = N->xadj[x];
         int32_t len = c.cs.cdeg[x];
@@ -1665,7 +2252,7 @@ __global__ void __launch_bounds__(BLOCK) compact_k(Ctx c, int l, unsigned small_
 // so that each phase gets the registers of the whole thread.
 // Matching state shared by the two halves of a tail level's matching.
 struct TailMatchLds {
-    int32_t cnt[2][3];   // list sizes by round parity
+    int32_t cnt[2][4];   // list sizes by round parity ([.][3] unused)
 };
 
 template <int R>
@@ -1676,14 +2263,14 @@ __device__ __noinline__ void tail_round1(const Ctx &c, int l, TailMatchLds &t) {
     LevelDesc *L = c.lv + l;
     DevGraph g;
     load_level(L, PH_MATCH, g);
-    if (threadIdx.x < 3) t.cnt[0][threadIdx.x] = t.cnt[1][threadIdx.x] = 0;
+    if (threadIdx.x < 4) t.cnt[0][threadIdx.x] = t.cnt[1][threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         L->matched = 0;
         L->rounds = 0;
     }
     __syncthreads();
     const uint64_t seed = level_seed(c, l);
-    init_phase(c, g, L, sh, sbase, 0, 1, t.cnt[0]);
+    init_phase(c, g, L, sh, sbase, 0, 1, t.cnt[0], false);
     __syncthreads();
     const RoundIn ri = round_inputs<true>(c, g, 1, t.cnt[0]);
     pick_bin0<R, true>(c, g, seed, ri, 0, 1);
@@ -1710,7 +2297,11 @@ __device__ __noinline__ void tail_rounds(const Ctx &c, int l, TailMatchLds &t) {
 }
 
 __device__ __noinline__ void tail_merge(const Ctx &c, int l) {
-    fill_small_body<TAIL_THREADS>(c, l, 0, 1);
+    // no LDS for the big-row sort next to the other phases: those rows take
+    // the large rows' accumulators
+    fill_small_body<TAIL_THREADS, false>(c, l, 0, 1);
+    __syncthreads();
+    fill_mid_body<TAIL_THREADS>(c, l, 0, 1, 1);   // the wave class by the block sort here
     __syncthreads();
     fill_mid_body<TAIL_THREADS>(c, l, 0, 1);
     __syncthreads();
@@ -1927,16 +2518,56 @@ void launch_union_build(const UnionSrc *src, int32_t count, const int64_t *noff,
 // Host side
 // ===========================================================================
 
+// Launched only when the long rows of the level are scanned in chunks.
+template <bool FIRST>
+static void launch_hub_reduce(const Ctx &c, int l, int r, hipStream_t s) {
+    if (!c.ms.hub.rec) return;
+    KAPPA_PROF("hub_reduce", s);
+    hipLaunchKernelGGL(hub_reduce_k<FIRST>, dim3(256), dim3(BLOCK), 0, s, c, l, r);
+}
+
+// Grid round r >= 2 (e: estimate of the pending entries).  With long rows in
+// chunks: preparation (the rows that rescan), pick over those, reduction of
+// the chunked rows, mutual check; otherwise pick over the pending lists and
+// the mutual check.
+template <int R>
+static void launch_later_round(const Ctx &c, int l, int r, const PickGrid &pg, int64_t e,
+                               hipStream_t s) {
+    const unsigned pick_blocks = pg.b0 + pg.b1 + pg.b2;
+    const unsigned list_blocks = grid_for(e, BLOCK, 2048);
+    if (c.ms.hub.rec) {
+        {
+            KAPPA_PROF("prep", s);
+            hipLaunchKernelGGL(prep_k, dim3(grid_for(e, BLOCK * MK, 2048)), dim3(BLOCK), 0, s, c,
+                               l, r);
+        }
+        {
+            KAPPA_PROF("pick", s);
+            hipLaunchKernelGGL((pick_k<R, false, 0, true>), dim3(pick_blocks), dim3(BLOCK), 0, s,
+                               c, l, r, pg);
+        }
+        launch_hub_reduce<false>(c, l, r, s);
+    } else {
+        KAPPA_PROF("pick", s);
+        hipLaunchKernelGGL((pick_k<R, false>), dim3(pick_blocks), dim3(BLOCK), 0, s, c, l, r, pg);
+    }
+    KAPPA_PROF("mate", s);
+    hipLaunchKernelGGL((mate_k<R, false>), dim3(list_blocks), dim3(BLOCK), 0, s, c, l, r);
+}
+
 template <int R>
 static void match_impl(const Ctx &c, int l, int32_t n_hint, int rounds, hipStream_t s) {
     // per-round kernels; round r's grid follows a geometric estimate of the
     // pending count (any grid is correct: all loops stride)
+    // power-law graphs keep most of their pending nodes for many rounds (hubs
+    // wait on each other), so their grids do not shrink with the rounds
+    const double decay = c.big_blocks > 64 ? 1.0 : 0.7;
     double est = n_hint;
-    for (int r = 1; r <= rounds; ++r, est *= 0.7) {
+    for (int r = 1; r <= rounds; ++r, est *= decay) {
         int64_t e = (int64_t)est + 1;
         PickGrid pg;
         pg.b0 = grid_for(e, BLOCK / SMALL_G, 2048);
-        pg.b1 = c.big_blocks > 64 ? (unsigned)c.big_blocks : grid_for(e, BLOCK / WAVE * 8, 128);
+        pg.b1 = c.big_blocks > 64 ? 2u * c.big_blocks : grid_for(e, BLOCK / WAVE * 8, 128);
         pg.b2 = c.big_blocks > 64 ? (unsigned)c.big_blocks : grid_for(e, 4096, 64);
         const unsigned pick_blocks = pg.b0 + pg.b1 + pg.b2;
         const unsigned mate_blocks = grid_for(e, BLOCK, 2048);
@@ -1946,16 +2577,11 @@ static void match_impl(const Ctx &c, int l, int32_t n_hint, int rounds, hipStrea
                 hipLaunchKernelGGL((pick_k<R, true>), dim3(pick_blocks), dim3(BLOCK), 0, s, c, l, r,
                                    pg);
             }
+            launch_hub_reduce<true>(c, l, r, s);
             KAPPA_PROF("mate_first", s);
             hipLaunchKernelGGL((mate_k<R, true>), dim3(mate_blocks), dim3(BLOCK), 0, s, c, l, r);
         } else {
-            {
-                KAPPA_PROF("pick", s);
-                hipLaunchKernelGGL((pick_k<R, false>), dim3(pick_blocks), dim3(BLOCK), 0, s, c, l, r,
-                                   pg);
-            }
-            KAPPA_PROF("mate", s);
-            hipLaunchKernelGGL((mate_k<R, false>), dim3(mate_blocks), dim3(BLOCK), 0, s, c, l, r);
+            launch_later_round<R>(c, l, r, pg, e, s);
         }
     }
     KAPPA_PROF("match_finish", s);
@@ -1981,7 +2607,7 @@ static void two_phase_impl(const Ctx &c, int l, int32_t n_hint, hipStream_t s) {
         int64_t e = (int64_t)est + 1;
         PickGrid pg;
         pg.b0 = grid_for(e, BLOCK / SMALL_G, 2048);
-        pg.b1 = c.big_blocks > 64 ? (unsigned)c.big_blocks : grid_for(e, BLOCK / WAVE * 8, 128);
+        pg.b1 = c.big_blocks > 64 ? 2u * c.big_blocks : grid_for(e, BLOCK / WAVE * 8, 128);
         pg.b2 = c.big_blocks > 64 ? (unsigned)c.big_blocks : grid_for(e, 4096, 64);
         {
             KAPPA_PROF("gap_pick", s);
@@ -2009,21 +2635,15 @@ static void two_phase_impl(const Ctx &c, int l, int32_t n_hint, hipStream_t s) {
 // batched, its end).
 template <int R>
 static void extend_impl(const Ctx &c, int l, int32_t n_hint, int r_from, int count, hipStream_t s) {
-    double est = n_hint * std::pow(0.7, r_from);
-    for (int r = r_from + 1; r <= r_from + count; ++r, est *= 0.7) {
+    const double decay = c.big_blocks > 64 ? 1.0 : 0.7;
+    double est = n_hint * std::pow(decay, r_from);
+    for (int r = r_from + 1; r <= r_from + count; ++r, est *= decay) {
         int64_t e = (int64_t)est + 1;
         PickGrid pg;
         pg.b0 = grid_for(e, BLOCK / SMALL_G, 2048);
-        pg.b1 = c.big_blocks > 64 ? (unsigned)c.big_blocks : grid_for(e, BLOCK / WAVE * 8, 128);
+        pg.b1 = c.big_blocks > 64 ? 2u * c.big_blocks : grid_for(e, BLOCK / WAVE * 8, 128);
         pg.b2 = c.big_blocks > 64 ? (unsigned)c.big_blocks : grid_for(e, 4096, 64);
-        {
-            KAPPA_PROF("pick", s);
-            hipLaunchKernelGGL((pick_k<R, false>), dim3(pg.b0 + pg.b1 + pg.b2), dim3(BLOCK), 0, s, c,
-                               l, r, pg);
-        }
-        KAPPA_PROF("mate", s);
-        hipLaunchKernelGGL((mate_k<R, false>), dim3(grid_for(e, BLOCK, 2048)), dim3(BLOCK), 0, s, c,
-                           l, r);
+        launch_later_round<R>(c, l, r, pg, e, s);
     }
     KAPPA_PROF("match_finish", s);
     hipLaunchKernelGGL(finish_k<R>, dim3(1), dim3(FINISH_THREADS), 0, s, c, l, r_from + count);
@@ -2082,7 +2702,13 @@ void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, h
     }
     {
         KAPPA_PROF("fill_mid", s);
-        hipLaunchKernelGGL(fill_mid_k, dim3(grid_for(n_hint, 64, 512)), dim3(BLOCK), 0, s, c, l);
+        const unsigned wb = grid_for(n_hint, 64, 2048), mb = grid_for(n_hint, 256, 1024);
+        hipLaunchKernelGGL(fill_mid_k, dim3(wb + mb), dim3(BLOCK), 0, s, c, l, wb);
+    }
+    {
+        KAPPA_PROF("fill_big", s);
+        hipLaunchKernelGGL(fill_big_k, dim3(grid_for(n_hint, 4096, 256)), dim3(BIG_THREADS), 0, s,
+                           c, l);
     }
     if (c.cs.hub_acc) {
         KAPPA_PROF("fill_large", s);
@@ -2092,7 +2718,7 @@ void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, h
                 c.cs.totals + 2, s);
     {
         KAPPA_PROF("compact", s);
-        const unsigned sb = grid_for(n_hint, SM_ROWS * 2, 4096), bb = grid_for(n_hint, 64, 512);
+        const unsigned sb = grid_for(n_hint, SM_ROWS * 2, 4096), bb = grid_for(n_hint, 64, 2048);
         hipLaunchKernelGGL(compact_k, dim3(sb + bb), dim3(BLOCK), 0, s, c, l, sb);
     }
     (void)n_cap;

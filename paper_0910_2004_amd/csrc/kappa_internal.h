@@ -42,7 +42,9 @@ constexpr int MAX_LEVELS = 256;
 // Row classes of the contraction (bound = deg(u) + deg(v) - 2 for a pair).
 constexpr int ROW_SMALL_MAX = 64;   // 16 lanes per row, rank sort in LDS
 constexpr int ROW_SMALL_G = 16;
+constexpr int ROW_WAVE_MAX = 512;   // one wave per row, bitonic sort of <= 512 in LDS
 constexpr int ROW_MID_MAX = 4094;   // one block per row, bitonic sort of <= 4096 in LDS
+constexpr int ROW_BIG_MAX = 16382;  // one 1024-thread block per row, sort of <= 16384 in LDS
 constexpr int HUB_SLOTS = 32;       // rows above ROW_MID_MAX: dense accumulators (at least)
 constexpr int HUB_SLOTS_MAX = 256;  //   and at most, within HUB_BUDGET bytes of accumulators
 constexpr int64_t HUB_BUDGET = (int64_t)4 << 30;
@@ -575,11 +577,14 @@ struct Control {
     char *base;
     int32_t stop_n, max_levels;
     uint32_t stall_num, stall_den;
+    int32_t last_n;     // node count of the newest level built (host grid sizing)
 };
 
 // Matching scratch (sized for level 0; reused by every level).
 struct MatchState {
     int32_t cnt[4][4];      // [round & 3][bin]: sizes of the pending lists written by a round
+                            // ([0][3]: chunk records of round 1's bin-2 list)
+    int32_t scnt[4][4];     // [round & 3][bin]: rows round r rescans ([.][3]: chunk records)
     int32_t handoff;        // -1: rounds continue; r >= 0: the finisher resumes after round r; -2: done
     int32_t pad[3];
     int32_t sround[NSHARD];               // per shard: last round in which some node pointed
@@ -592,6 +597,24 @@ struct MatchState {
 struct LocKey {
     uint64_t num, den, h;
 };
+// Rows above BIN_MID_MAX entries are scanned in chunks of HUB_CHUNK entries,
+// one block per chunk, so that a round's latency does not grow with the
+// longest row; the chunks' partial maxima are reduced per row by a separate
+// launch before the mutual check.
+constexpr int HUB_CHUNK = 2048;
+// Chunk records of a level's bin-2 lists, per list parity: at most one per
+// HUB_CHUNK entries of a row plus one per row, and every bin-2 row has more
+// than BIN_MID_MAX entries, so nnz / 512 + 64 records always suffice.
+inline int64_t hub_chunk_cap(int64_t nnz) { return nnz / 512 + 64; }
+struct HubChunks {
+    int2 *rec;       // 2 * cap: per parity, {position in the bin-2 list, chunk index}
+    int32_t *first;  // 2 * n: per parity and bin-2 list position, the row's first record
+                     // (-1: the row keeps its choice this round)
+    Cand *part;      // cap: the chunks' maxima of the current round
+    int64_t cap;
+    int2 *scan;      // 2 * n: per bin 0 / 1, {node, list position} of the rows a round
+                     // rescans (written by the round's preparation)
+};
 struct MatchScratch {
     int32_t *best;          // n: current choice of every node (-1: none)
     int32_t *lv, *lb, *ld;  // 6n each: pending lists [parity][bin] (node, choice, degree)
@@ -601,6 +624,7 @@ struct MatchScratch {
     MatchState *state;
     int32_t *loc;           // two-phase: n, the block phase's partner (-1: none)
     LocKey *lkey;           // two-phase: n, the key of that edge
+    HubChunks hub;          // rec == nullptr: long rows are scanned by one block each
 };
 
 // Contraction scratch (sized for level 0).
@@ -608,16 +632,18 @@ struct ContractScratch {
     int32_t *rep_of;      // n   coarse -> representative fine node
     int32_t *partner;     // n   coarse -> partner of the representative (-1)
     int32_t *cdeg;        // n   coarse degrees
-    int32_t *rows;        // 3n  row-class lists (classes 1 and 2 are used)
-    int32_t *row_cnt;     // 4   row-class counts
+    int32_t *rows;        // 4n  row-class lists: [0, n) class 3, [n, 2n) class 1,
+                          //     [2n, 3n) class 2, [3n, 4n) class 4
+    int32_t *row_cnt;     // 8   row-class counts (classes 1 to 4)
     int32_t *tmp_adj;     // nnz
     uint32_t *tmp_ew;     // nnz
     int64_t *partials;    // scan workspace: tile sums
     unsigned *arrive;     // ARRIVE_WORDS arrival counters of the scans (zero between uses)
     int64_t *totals;      // [0] n', [1] unused, [2] nnz', [3] unused
     uint32_t *hub_acc;    // hub_slots * n, zero between uses (may be null)
-    uint32_t *hub_bits;   // hub_slots * hub_words, zero between uses
-    int64_t hub_words;
+    uint32_t *hub_bits;   // hub_slots * hub_words, zero between uses: per slot the id
+                          // bitmap (hub_w1 words), then its summary (a bit per word)
+    int64_t hub_words, hub_w1;
     int32_t hub_slots;    // rows merged at once in the hub accumulators
 };
 
