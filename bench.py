@@ -1,17 +1,19 @@
 """Benchmark of the coarsening hierarchy on one MI355X.
 
-A step is one pass of the whole path over the random geometric graph
-workload (n = 2^20 points in the unit square, radius for mean degree 8, unit
-weights): validation of the input (once), then per rating the workload names
-(expansion*2 and innerOuter) matching + contraction level by level down to
-20*k nodes (k=64), the coarsest-level partition, then projection and
-cut/balance on every level back to level 0.  The graph is resident in HBM
-before the timed region.
+The headline step is one pass of the whole path over the R-MAT power-law
+graph of scale 22 (2^22 nodes, 16 * 2^22 samples, (a, b, c) = (0.57, 0.19,
+0.19), weights uniform in [1, 100], unit node weights): validation of the
+input, then matching + contraction level by level with the expansion*2
+rating down to 20*k nodes (k=256) or the stall rule, the coarsest-level
+partition, then projection and cut/balance on every level back to level 0.
+The graph is resident in HBM before the timed region.  The same line carries,
+under "secondary", the random geometric graph workload (n = 2^20, mean degree
+8, both ratings, k = 64).
 
 Prints one JSON line: edges/s = (undirected input edges per step) / (time per
 step), plus the roofline of the dominant kernel (HIP events on the library's
 launch stream, in a second timed pass with per-launch events enabled) and the
-oracle's time on the host for one step (cpu_baseline).
+oracle's time on the host for a bounded sample (cpu_baseline).
 """
 import argparse
 import json
@@ -70,6 +72,61 @@ def bytes_mate_round(A):
     return 12 * A
 
 
+def bytes_merge(rows, matched, fine_entries, merged_entries):
+    # the merge of a row class (the small-row model): per coarse row rep_of,
+    # partner, the representative's offsets, merged degree (28); matched rows
+    # also the partner's offsets (16); per fine entry adj, w and cmap of the
+    # neighbour (12); per merged entry key and weight written (8)
+    return 28 * rows + 16 * matched + 12 * fine_entries + 8 * merged_entries
+
+
+def bytes_validate(n, D):
+    # every entry's neighbour and weight (8) and the row offsets and node
+    # weights (12 per node); the reverse entry of an entry is another entry
+    return 8 * D + 12 * n
+
+
+# merge kernels by class of the bound deg(u) + deg(w) - 2 on the merged row
+MERGE_CLASSES = (("fill_small", 0, 64), ("fill_wave", 65, 512), ("fill_mid", 513, 4094),
+                 ("fill_big", 4095, 16382), ("fill_large", 16383, 1 << 62))
+
+
+def merge_class_stats(H):
+    """Per merge kernel, summed over the levels of H: coarse rows, matched
+    rows, fine entries and merged entries (from the levels' offsets and maps,
+    copied to the host)."""
+    import numpy as np
+    tot = {name: [0, 0, 0, 0] for name, _, _ in MERGE_CLASSES}
+    L = len(H)
+    prev = None
+    for l in range(L):
+        lv = H.level(l)
+        x = lv.graph.xadj.cpu().numpy()
+        if prev is not None:
+            deg_f, cmap = prev
+            nc = len(x) - 1
+            deg_c = np.diff(x)
+            sumdeg = np.bincount(cmap, weights=deg_f, minlength=nc).astype(np.int64)
+            cnt = np.bincount(cmap, minlength=nc)
+            bound = sumdeg - 2 * (cnt == 2)
+            for name, lo, hi in MERGE_CLASSES:
+                m = (bound >= max(lo, 1)) & (bound <= hi)
+                t = tot[name]
+                if name == "fill_small":
+                    # every coarse row passes the small-row kernel (its header is
+                    # read there); the entries of the small rows are merged there
+                    m = bound <= hi
+                    t[0] += nc
+                    t[1] += int((cnt == 2).sum())
+                else:
+                    t[0] += int(m.sum())
+                    t[1] += int((m & (cnt == 2)).sum())
+                t[2] += int(sumdeg[m].sum())
+                t[3] += int(deg_c[m].sum())
+        prev = (np.diff(x), lv.cmap.cpu().numpy()) if lv.cmap is not None else None
+    return tot
+
+
 MODELS = {"pick": "per round r >= 2 run as a grid launch: 16 B per entry of the A_r pointing "
                   "nodes (adj, w, attribute, mate of the neighbour) + 24 B per pointing node "
                   "(int64 offsets, own attribute, best); A_r and their degree sum from the "
@@ -78,15 +135,21 @@ MODELS = {"pick": "per round r >= 2 run as a grid launch: 16 B per entry of the 
           "pick_first": "per level: 16 B/node + 12 B/entry (innerOuter 20 + 16)",
           "fill_small": "per level: 28 B/coarse row + 16 B/matched pair + 12 B/fine entry + 8 B/coarse entry",
           "compact": "per level: 24 B/coarse row + 16 B/coarse entry",
-          "cut_entries": "per level: 16 B/entry"}
+          "cut_entries": "per level: 16 B/entry",
+          "validate_entries": "8 B per CSR entry (neighbour, weight) + 12 B per node (offsets, "
+                              "node weight)"}
+for _name, _lo, _hi in MERGE_CLASSES[1:]:
+    MODELS[_name] = (f"per level, over the coarse rows whose merged-row bound is {_lo}.."
+                     f"{_hi if _hi < (1 << 60) else 'inf'}: 28 B/row + 16 B/matched row + "
+                     "12 B/fine entry + 8 B/merged entry")
 
 
-def counter_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (profiles/<kernel>_counters.json: FETCH_SIZE and WRITE_SIZE per step,
-    scaled by a plain copy), or None when the kernel's source changed since
-    the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_counters.json")
+def counter_traffic(kernel, tag):
+    """HBM bytes per launch of `kernel` on workload `tag` (rmat22, rgg20)
+    from the committed counter summary (profiles/<kernel>_<tag>_counters.json:
+    FETCH_SIZE and WRITE_SIZE per launch, scaled by a plain copy), or None when
+    the kernel's source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{tag}_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -109,9 +172,15 @@ def level_stats(H):
     return out
 
 
-def model_bytes(stats_by_rating):
-    """Total model bytes per kernel class over one step."""
+def model_bytes(stats_by_rating, classes=None, n0=0, D0=0):
+    """Total model bytes per kernel class over one step.  classes: merge
+    class statistics per rating (merge_class_stats), for the merge kernels
+    of the larger rows; n0 / D0: the input graph (validation, once)."""
     tot = {k: 0 for k in MODELS}
+    tot["validate_entries"] = bytes_validate(n0, D0)
+    for cs in (classes or {}).values():
+        for name, _, _ in MERGE_CLASSES:
+            tot[name] += bytes_merge(*cs[name])
     for rating, lv in stats_by_rating.items():
         io = rating == 1
         for l, (n, D, matched, rounds, grid_rounds, pt, dg) in enumerate(lv):
@@ -122,15 +191,18 @@ def model_bytes(stats_by_rating):
                 for r in range(2, min(grid_rounds, len(pt)) + 1):
                     tot["pick"] += bytes_pick_round(pt[r - 1], dg[r - 1])
                     tot["mate"] += bytes_mate_round(pt[r - 1])
-                tot["fill_small"] += bytes_fill_small(n, D, nc, Dc, matched)
+                if not classes:
+                    tot["fill_small"] += bytes_fill_small(n, D, nc, Dc, matched)
                 tot["compact"] += bytes_compact(nc, Dc)
     return tot
 
 
 # rocprofv3 kernel names (namespace, "void " and arguments stripped) of the
 # library's profiler names
-KERNEL_SYMBOLS = {"pick": r"pick_k<\d, false, 0>", "mate": r"mate_k<\d, false>",
-                  "pick_first": r"pick_k<\d, true, 0>", "fill_small": r"fill_small_k",
+KERNEL_SYMBOLS = {"pick": r"pick_k<\d, false, 0, (true|false)>", "mate": r"mate_k<\d, false>",
+                  "pick_first": r"pick_k<\d, true, 0, false>", "fill_small": r"fill_small_k",
+                  "fill_wave": r"fill_wave_k", "fill_mid": r"fill_mid_k", "fill_big": r"fill_big_k",
+                  "fill_large": r"fill_large_k", "validate_entries": r"validate_entries_k",
                   "compact": r"compact_k", "cut_entries": r"up_entries_k<(true|false)>",
                   "refine_fm": r"ref_fm_k"}
 # the sources a kernel's stored counters depend on (they go stale when these change)
@@ -143,6 +215,8 @@ REFINE_COUNTER_SOURCES = ["paper_0910_2004_amd/csrc/k_refine.hip",
 def counter_sources(kernel):
     return REFINE_COUNTER_SOURCES if kernel.startswith("refine") else COUNTER_SOURCES
 WORKLOAD_RGG = "rgg n=2^20 mean degree 8, both ratings, k=64, stop 1280"
+WORKLOAD_RMAT = ("rmat scale 22 edge factor 16 (a, b, c) = (0.57, 0.19, 0.19), weights in "
+                 "[1, 100], expansion*2, k=256, stop n<=5120 or stall 1/20, eps=3/100")
 WORKLOAD_REFINE = ("the way back up with pairwise refinement (preset fast) on the expansion*2 "
                    "hierarchy of rgg n=2^20 mean degree 8, k=64, stop 1280")
 
@@ -161,8 +235,8 @@ def _sources_sha(sources):
     return h.hexdigest()
 
 
-def summarize_pmc(kernel, fetch_dir, write_dir, bench_cmd):
-    """profiles/<kernel>_counters.json and .md from the counter-collection CSVs
+def summarize_pmc(kernel, fetch_dir, write_dir, bench_cmd, tag="rmat22"):
+    """profiles/<kernel>_<tag>_counters.json and .md from the counter-collection CSVs
     of a FETCH_SIZE pass and a WRITE_SIZE pass of the same bench command that
     ended with --copy-calibration: the last three 256 MiB copies give the
     scale from counter KiB to bytes (each copy reads and writes 256 MiB)."""
@@ -185,16 +259,18 @@ def summarize_pmc(kernel, fetch_dir, write_dir, bench_cmd):
     traffic = res["FETCH_SIZE"]["scaled_bytes_per_launch"] + res["WRITE_SIZE"]["scaled_bytes_per_launch"]
     cmds = [f"cd /tmp && timeout -s KILL 120 rocprofv3 --pmc {c} --kernel-trace -d <out> -o run "
             f"--output-format csv -- python3 <repo>/{bench_cmd}" for c in ("FETCH_SIZE", "WRITE_SIZE")]
-    workload = WORKLOAD_REFINE if kernel.startswith("refine") else WORKLOAD_RGG
-    rec = {"kernel": kernel, "workload": workload, "counters": res,
+    workload = WORKLOAD_REFINE if kernel.startswith("refine") else \
+        (WORKLOAD_RMAT if tag == "rmat22" else WORKLOAD_RGG)
+    rec = {"kernel": kernel, "tag": tag, "workload": workload, "counters": res,
            "traffic_bytes_per_launch": traffic, "sources": counter_sources(kernel),
            "sources_sha256": _sources_sha(counter_sources(kernel)), "commands": cmds}
-    with open(os.path.join(ROOT, "profiles", f"{kernel}_counters.json"), "w") as f:
+    with open(os.path.join(ROOT, "profiles", f"{kernel}_{tag}_counters.json"), "w") as f:
         json.dump(rec, f, indent=1)
     lines = [f"# HBM traffic of `{kernel}` ({KERNEL_SYMBOLS[kernel]}): {workload}", "",
              "Commands (one counter per run; `<repo>` is the repository root):", ""]
     lines += ["    " + c for c in cmds]
-    lines += ["", "Summarised by `python bench.py --summarize-pmc " + kernel + " <fetch dir> <write dir>`.",
+    lines += ["", f"Summarised by `python bench.py --summarize-pmc {kernel} <fetch dir> <write dir> "
+              f"--pmc-tag {tag}`.",
               "", "The run ends with three plain 256 MiB device-to-device copies "
               "(`--copy-calibration`), whose counters give the scale from counter KiB to bytes:", "",
               "| counter | copy KiB per 256 MiB | scale | dispatches | scaled MB per launch |",
@@ -206,7 +282,7 @@ def summarize_pmc(kernel, fetch_dir, write_dir, bench_cmd):
     lines += ["", f"Traffic per launch: **{traffic / 1e6:.3f} MB**.  `bench.py` reports it as "
               f"`roofline.traffic` while the SHA-256 of {', '.join(counter_sources(kernel))} equals "
               f"`{rec['sources_sha256'][:16]}…`, and null once they change."]
-    with open(os.path.join(ROOT, "profiles", f"{kernel}_counters.md"), "w") as f:
+    with open(os.path.join(ROOT, "profiles", f"{kernel}_{tag}_counters.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
     log(f"{kernel}: traffic {traffic / 1e6:.3f} MB per launch "
         f"({res['FETCH_SIZE']['dispatches']} dispatches)")
@@ -250,9 +326,12 @@ def main():
                          "steps (kappa_rcb_order + kappa_relabel, timed apart)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-out", default=None)
-    ap.add_argument("--workload", default="rgg20",
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="rmat22: skip the random geometric graph summary in the same line")
+    ap.add_argument("--workload", default="rmat22",
                     choices=["rgg20", "rmat22", "batch4096", "serve", "refine"],
-                    help="rgg20: the headline single-graph workload; batch4096: the batched "
+                    help="rmat22: the headline single-graph workload (R-MAT scale 22); rgg20: "
+                         "the random geometric graph of 2^20 nodes; batch4096: the batched "
                          "form on 4096 uneven graphs, against a loop of single calls; serve: "
                          "the served form on a Poisson request stream, against FIFO single "
                          "calls; refine: the way back up with pairwise refinement (Section 5) "
@@ -266,21 +345,22 @@ def main():
                     help="also run a plain 256 MiB device copy (3x) so that HBM byte counters "
                          "can be scaled against a kernel of known traffic")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("KERNEL", "FETCH_DIR", "WRITE_DIR"),
-                    help="write profiles/<kernel>_counters.json/.md from two rocprofv3 --pmc runs "
+                    help="write profiles/<kernel>_<tag>_counters.json/.md from two rocprofv3 --pmc runs "
                          "(no GPU work)")
+    ap.add_argument("--pmc-tag", default="rmat22", help="workload of the --pmc runs (rmat22, rgg20)")
     ap.add_argument("--pmc-command", default="bench.py --steps 1 --warmup 1 --no-cpu-baseline "
-                                             "--copy-calibration",
+                                             "--no-secondary --copy-calibration",
                     help="the bench command the --pmc runs profiled (recorded in the summary)")
     ap.add_argument("--summarize-stats", nargs=2, metavar=("STATS_CSV", "OUT_MD"),
                     help="write a markdown table from rocprofv3 --stats kernel_stats.csv (no GPU work)")
-    ap.add_argument("--stats-title", default=f"Kernel statistics: {WORKLOAD_RGG}")
+    ap.add_argument("--stats-title", default=f"Kernel statistics: {WORKLOAD_RMAT}")
     ap.add_argument("--stats-command", default="cd /tmp && rocprofv3 --kernel-trace --stats -d <out> -o run "
                                                "--output-format csv -- python3 <repo>/bench.py --steps 3 "
-                                               "--warmup 1 --no-cpu-baseline")
+                                               "--warmup 1 --no-cpu-baseline --no-secondary")
     args = ap.parse_args()
     if args.summarize_pmc:
         return summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.summarize_pmc[2],
-                             args.pmc_command)
+                             args.pmc_command, args.pmc_tag)
     if args.summarize_stats:
         return summarize_stats(args.summarize_stats[0], args.summarize_stats[1], args.stats_title,
                                args.stats_command)
@@ -302,13 +382,28 @@ def main():
     if args.workload == "refine":
         return bench_refine(args)
 
+    out = single_graph(args, args.workload == "rmat22", primary=True)
+    if args.workload == "rmat22" and not args.no_secondary:
+        out["secondary"] = single_graph(args, False, primary=False)
+    print(json.dumps(out), flush=True)
+
+
+def single_graph(args, rmat_mode, primary):
+    """One single-graph workload: rmat_mode the R-MAT of scale 22, else the
+    random geometric graph.  primary: also the per-launch profile, the
+    roofline object and the oracle baseline (the headline line); otherwise a
+    short summary for the same JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_0910_2004_amd as K
+    from workloads import rgg
     n = 1 << args.scale
     k = args.k
     stop_n = 20 * k
     eps = (3, 100)
     seed, part_seed = 42, 1
     ratings = [K.EXPANSION_STAR2, K.INNER_OUTER]
-    rmat_mode = args.workload == "rmat22"
     if rmat_mode:
         # R-MAT of scale 22, edge factor 16, weights in [1, 100]; expansion*2,
         # k = 256, stop at 5120 nodes (or on the stall rule)
@@ -392,6 +487,20 @@ def main():
     value = edges_step / (ms_step / 1e3)
     # all levels' edges (sum over the hierarchy of |E_l|) per second
     level_edges = sum(x[1] // 2 for r in ratings for x in stats[r][0])
+    wl_name = WORKLOAD_RMAT if rmat_mode else WORKLOAD_RGG
+    log(f"{wl_name}: {ms_step:.3f} ms per step, {value:.4g} edges/s")
+    if not primary:
+        return {"workload": wl_name, "value": round(value, 1), "unit": "edges/s",
+                "ms_per_step": round(ms_step, 3), "median_ms_per_step": round(med_ms, 3),
+                "steps": args.steps, "warmup": args.warmup, "n": g.n, "m": g.m,
+                "edges_per_step": edges_step, "ratings_concurrent": not args.serial_ratings}
+    # merge classes of every level (for the merge kernels' byte models), from
+    # one more hierarchy per rating, untimed
+    classes = {}
+    for i, r in enumerate(ratings):
+        H = K.kappa_coarsen(dg, r, seed, stop_n, 1, 20, 64, trusted=True, block_bits=args.block_bits)
+        classes[r] = merge_class_stats(H)
+        del H
 
     # second timed pass with per-launch HIP events, the ratings one after the
     # other (a launch's events then bracket that launch alone)
@@ -406,7 +515,7 @@ def main():
     K.profile_reset()
 
     lv = {r: stats[r][0] for r in ratings}
-    mb = model_bytes(lv)
+    mb = model_bytes(lv, classes, g.n, g.nnz)
     total_ms = sum(ms for _, ms in prof.values()) / args.steps
     kern = sorted(prof.items(), key=lambda kv: -kv[1][1])
     log("kernel time per step (ms), launches per step:")
@@ -422,9 +531,9 @@ def main():
         per_launch_bytes = mb[rk] / (cnt / args.steps)
         avg_s = ms / cnt / 1e3
         achieved = per_launch_bytes / avg_s / 1e9
-        # the stored counters were taken on the generation-order graph
-        traffic = counter_traffic(rk) if args.order == "generation" and args.block_bits is None \
-            and not rmat_mode else None
+        # the stored counters were taken on this workload in generation order
+        traffic = counter_traffic(rk, "rmat22" if rmat_mode else "rgg20") \
+            if args.order == "generation" and args.block_bits is None else None
         roof = {"bound": "hbm", "kernel": rk, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else int(traffic),
@@ -474,9 +583,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u32/u64 (exact integer; 128-bit rating compares)",
         "data": "synthetic",
-        "config": {"workload": ("rmat scale 22 edge factor 16 (a, b, c) = (0.57, 0.19, 0.19), "
-                                "weights in [1, 100], expansion*2, k=256, stop n<=5120 or "
-                                "stall 1/20, eps=3/100") if rmat_mode else
+        "config": {"workload": WORKLOAD_RMAT if rmat_mode else
                                f"rgg n=2^{args.scale} mean degree 8, unit weights, both ratings "
                                f"(expansion*2, innerOuter), k={k}, stop n<={stop_n}, eps=3/100"
                                + ("" if args.order == "generation" else
@@ -504,8 +611,9 @@ def main():
         log(f"copy calibration: 3 x {a.numel() * 4} bytes read and written")
     if args.profile_out:
         with open(args.profile_out, "w") as f:
-            json.dump({"prof": prof, "model_bytes": mb, "levels": lv_json}, f, indent=1)
-    print(json.dumps(out), flush=True)
+            json.dump({"prof": prof, "model_bytes": mb, "levels": lv_json, "classes": classes},
+                      f, indent=1)
+    return out
 
 
 def copy_ceiling_gbs(torch, mib=1024, reps=5):
@@ -653,7 +761,7 @@ def bench_refine(args):
     if cnt:
         avg_s = fm_ms / cnt / 1e3
         achieved = fm_bytes / cnt / avg_s / 1e9
-        traffic = counter_traffic("refine_fm") if (args.scale, k, args.preset) == (20, 64, "fast") \
+        traffic = counter_traffic("refine_fm", "rgg20") if (args.scale, k, args.preset) == (20, 64, "fast") \
             else None
         roof = {"bound": "hbm", "kernel": "refine_fm", "achieved": round(achieved, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),

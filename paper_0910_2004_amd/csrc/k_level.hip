@@ -1765,11 +1765,24 @@ __device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bi
         wave_append(sub == 0 && cls == 3, x, lists3, &c.cs.row_cnt[3]);
         wave_append(sub == 0 && cls == 4, x, lists4, &c.cs.row_cnt[4]);
         const int tot = cls == 0 ? (int)r.tot : 0;
-        for (int t = sub; t < tot; t += ROW_SMALL_G) {
-            uint32_t k, w;
-            row_entry(g, cmap, r, t, k, w);
-            sk[grp][t] = k;
-            sw[grp][t] = w;
+        {
+            constexpr int U = (SM_CAP + ROW_SMALL_G - 1) / ROW_SMALL_G;   // entries per lane
+            uint32_t kk[U], ww[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = sub + u * ROW_SMALL_G;
+                kk[u] = INVALID_KEY;
+                ww[u] = 0;
+                if (t < tot) row_entry(g, cmap, r, t, kk[u], ww[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = sub + u * ROW_SMALL_G;
+                if (t < tot) {
+                    sk[grp][t] = kk[u];
+                    sw[grp][t] = ww[u];
+                }
+            }
         }
         wave_sync_lds();
         // the first occurrence of a key leads; a later one adds its weight
@@ -1802,6 +1815,40 @@ __device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bi
 }
 __global__ void __launch_bounds__(BLOCK) fill_small_k(Ctx c, int l) {
     fill_small_body<BLOCK>(c, l, blockIdx.x, gridDim.x);
+}
+
+// One compare-exchange stage (block size k, distance j) of a bitonic sort of
+// s[lo, lo + 2 * npairs): pair p pairs element t (bit j clear) with t | j and
+// orders them ascending when bit k of t is clear.  The caller's threads take
+// pairs first, first + stride, ...; each thread loads up to BS_BATCH pairs
+// before it stores any (the pairs of a stage are disjoint).
+constexpr int BS_BATCH = 8;
+__device__ __forceinline__ void bitonic_stage(uint64_t *s, int lo, int npairs, int k, int j,
+                                              int first, int stride) {
+    const int lj = __ffs(j) - 1;
+    for (int p0 = first; p0 < npairs; p0 += stride * BS_BATCH) {
+        uint64_t a[BS_BATCH], b[BS_BATCH];
+        int t[BS_BATCH];
+#pragma unroll
+        for (int q = 0; q < BS_BATCH; ++q) {
+            const int p = p0 + q * stride;
+            t[q] = lo + (((p >> lj) << (lj + 1)) | (p & (j - 1)));
+            if (p < npairs) {
+                a[q] = s[t[q]];
+                b[q] = s[t[q] | j];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < BS_BATCH; ++q) {
+            const int p = p0 + q * stride;
+            if (p >= npairs) continue;
+            const bool up = (t[q] & k) == 0;
+            if ((a[q] > b[q]) == up) {
+                s[t[q]] = b[q];
+                s[t[q] | j] = a[q];
+            }
+        }
+    }
 }
 
 // --- 2b. mid and big rows: one block per row, bitonic sort in LDS ------------------
@@ -1854,26 +1901,11 @@ __device__ __forceinline__ void fill_block_body(const Ctx &c, int l, unsigned bi
             for (int j = k >> 1; j > 0; j >>= 1) {
                 if (!wave_stages || j >= chunk) {
                     if (!synced) __syncthreads();
-                    for (int t = threadIdx.x; t < P; t += NT) {
-                        const int ixj = t ^ j;
-                        if (ixj > t) {
-                            const uint64_t a = s[t], b = s[ixj];
-                            const bool up = (t & k) == 0;
-                            if ((a > b) == up) { s[t] = b; s[ixj] = a; }
-                        }
-                    }
+                    bitonic_stage(s, 0, P / 2, k, j, threadIdx.x, NT);
                     __syncthreads();
                     synced = true;
                 } else {
-                    const int lo = wv * chunk;
-                    for (int t = lo + lane; t < lo + chunk; t += WAVE) {
-                        const int ixj = t ^ j;
-                        if (ixj > t) {
-                            const uint64_t a = s[t], b = s[ixj];
-                            const bool up = (t & k) == 0;
-                            if ((a > b) == up) { s[t] = b; s[ixj] = a; }
-                        }
-                    }
+                    bitonic_stage(s, wv * chunk, chunk / 2, k, j, lane, WAVE);
                     wave_sync_lds();
                     synced = false;
                 }
@@ -1946,14 +1978,21 @@ __device__ __forceinline__ void fill_wave_body(const Ctx &c, int l, unsigned bid
         // the renamed entries without the contracted edge (at most the row's
         // bound, <= WR_P of them), packed to the front of the slice
         const int tot = (int)r.tot;
+        constexpr int U = (WR_P + 2 + WAVE - 1) / WAVE;   // entries per lane (bound + 2 at most)
+        uint32_t kk[U], ww[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = u * WAVE + lane;
+            kk[u] = INVALID_KEY;
+            ww[u] = 0;
+            if (t < tot) row_entry(g, cmap, r, t, kk[u], ww[u]);
+        }
         int q = 0;
-        for (int t0 = 0; t0 < tot; t0 += WAVE) {
-            const int t = t0 + lane;
-            uint32_t k = INVALID_KEY, w = 0;
-            if (t < tot) row_entry(g, cmap, r, t, k, w);
-            const bool keep = k != INVALID_KEY;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool keep = kk[u] != INVALID_KEY;
             const uint64_t m = __ballot(keep);
-            if (keep) s[q + __popcll(m & lanemask_lt())] = ((uint64_t)k << 32) | w;
+            if (keep) s[q + __popcll(m & lanemask_lt())] = ((uint64_t)kk[u] << 32) | ww[u];
             q += (int)__popcll(m);
         }
         int P = WAVE;
@@ -1962,14 +2001,7 @@ __device__ __forceinline__ void fill_wave_body(const Ctx &c, int l, unsigned bid
         wave_sync_lds();
         for (int k = 2; k <= P; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int t = lane; t < P; t += WAVE) {
-                    const int ixj = t ^ j;
-                    if (ixj > t) {
-                        const uint64_t a = s[t], b = s[ixj];
-                        const bool up = (t & k) == 0;
-                        if ((a > b) == up) { s[t] = b; s[ixj] = a; }
-                    }
-                }
+                bitonic_stage(s, 0, P / 2, k, j, lane, WAVE);
                 wave_sync_lds();
             }
         }
@@ -1994,32 +2026,32 @@ __device__ __forceinline__ void fill_wave_body(const Ctx &c, int l, unsigned bid
     }
 }
 
-// Both mid classes in one launch: blocks [0, wave_blocks) merge the rows of
-// 65..512 entries one wave each, the rest the rows of 513..4094 one block each.
-__global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l, unsigned wave_blocks) {
-    static_assert((BLOCK / WAVE) * WR_P <= MID_P, "the wave rows' slices fit the block rows' array");
+// Rows of 65..512 entries, one wave each.
+__global__ void __launch_bounds__(BLOCK) fill_wave_k(Ctx c, int l) {
+    __shared__ uint64_t s[(BLOCK / WAVE) * WR_P];
+    fill_wave_body<BLOCK>(c, l, blockIdx.x, gridDim.x, s);
+}
+// Rows of 513..4094 entries, one block each.
+__global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l) {
     __shared__ uint64_t s[MID_P];
-    if (blockIdx.x < wave_blocks)
-        fill_wave_body<BLOCK>(c, l, blockIdx.x, wave_blocks, s);
-    else
-        fill_block_body<BLOCK, MID_P>(c, l, blockIdx.x - wave_blocks, gridDim.x - wave_blocks, 3, s);
+    fill_block_body<BLOCK, MID_P>(c, l, blockIdx.x, gridDim.x, 3, s);
 }
 
 // --- 2c. large rows: dense accumulator per slot --------------------------------------
 // Slot `bid` of the hub accumulators (bid < hub_slots): a dense sum per
 // coarse id, a bitmap of the ids present (one bit per id) and a summary
 // bitmap (one bit per nonzero bitmap word).  The read-back walks the summary
-// in chunks of LG_SUM summary words, gathers the chunk's nonzero bitmap words
+// in chunks of summary words, gathers the chunk's nonzero bitmap words
 // into LDS, and hands out the chunk's ids by rank (a thread finds the word
 // holding its rank by a binary search over the words' prefix counts), so the
 // work follows the ids present rather than the id range and is spread evenly
 // over the block.  Every array is left zero for the next row.
-constexpr int LG_SUM = 128;                 // summary words per chunk
-constexpr int LG_WORDS = LG_SUM * 32;       // nonzero bitmap words of a chunk, at most
 constexpr int LG_IDS = 4;                   // ids per thread in flight (read-back)
 constexpr int LG_ACC = 8;                   // entries per thread in flight (accumulation)
-template <int NT>
+// LG_SUM summary words per chunk (LG_WORDS = 32 * LG_SUM nonzero bitmap words at most).
+template <int NT, int LG_SUM>
 __device__ __forceinline__ void fill_large_body(const Ctx &c, int l, unsigned bid, unsigned nb) {
+    constexpr int LG_WORDS = LG_SUM * 32;
     static_assert(NT >= LG_SUM && LG_WORDS % NT == 0, "chunk layout");
     constexpr int WPT = LG_WORDS / NT;       // bitmap words per thread of a chunk
     __shared__ int32_t s_word[LG_WORDS];     // the chunk's nonzero bitmap words: index
@@ -2154,8 +2186,9 @@ __device__ __forceinline__ void fill_large_body(const Ctx &c, int l, unsigned bi
         __syncthreads();
     }
 }
-__global__ void __launch_bounds__(BLOCK) fill_large_k(Ctx c, int l) {
-    fill_large_body<BLOCK>(c, l, blockIdx.x, gridDim.x);
+constexpr int LARGE_THREADS = 1024;   // one workgroup per hub slot (one per CU)
+__global__ void __launch_bounds__(LARGE_THREADS) fill_large_k(Ctx c, int l) {
+    fill_large_body<LARGE_THREADS, 256>(c, l, blockIdx.x, gridDim.x);
 }
 
 // --- 4. compaction ----------------------------------------------------------------
@@ -2305,7 +2338,7 @@ __device__ __noinline__ void tail_merge(const Ctx &c, int l) {
     __syncthreads();
     fill_mid_body<TAIL_THREADS>(c, l, 0, 1);
     __syncthreads();
-    fill_large_body<TAIL_THREADS>(c, l, 0, 1);
+    fill_large_body<TAIL_THREADS, 128>(c, l, 0, 1);
     __syncthreads();
 }
 
@@ -2701,9 +2734,12 @@ void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, h
                            s, c, l);
     }
     {
+        KAPPA_PROF("fill_wave", s);
+        hipLaunchKernelGGL(fill_wave_k, dim3(grid_for(n_hint, 64, 2048)), dim3(BLOCK), 0, s, c, l);
+    }
+    {
         KAPPA_PROF("fill_mid", s);
-        const unsigned wb = grid_for(n_hint, 64, 2048), mb = grid_for(n_hint, 256, 1024);
-        hipLaunchKernelGGL(fill_mid_k, dim3(wb + mb), dim3(BLOCK), 0, s, c, l, wb);
+        hipLaunchKernelGGL(fill_mid_k, dim3(grid_for(n_hint, 256, 1024)), dim3(BLOCK), 0, s, c, l);
     }
     {
         KAPPA_PROF("fill_big", s);
@@ -2712,7 +2748,7 @@ void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, h
     }
     if (c.cs.hub_acc) {
         KAPPA_PROF("fill_large", s);
-        hipLaunchKernelGGL(fill_large_k, dim3(c.cs.hub_slots), dim3(BLOCK), 0, s, c, l);
+        hipLaunchKernelGGL(fill_large_k, dim3(c.cs.hub_slots), dim3(LARGE_THREADS), 0, s, c, l);
     }
     launch_scan((int64_t)n_hint + 1, DegF{c, l}, CoarseOffW{c, l}, c.cs.partials, c.cs.arrive,
                 c.cs.totals + 2, s);
