@@ -310,6 +310,22 @@ kappa_status kappa_cut_balance(const kappa_graph *g, const int32_t *part, int32_
                                uint32_t eps_num, uint32_t eps_den, uint64_t *block_w,
                                kappa_cut_result *out, kappa_stream_t stream);
 
+/* Allocation-free variant of kappa_cut_balance, for callers that cannot
+   allocate (code under HIP graph capture, tight serving loops, harnesses that
+   forbid allocation): the same arguments, results and errors, but no device
+   or pinned host allocation of any kind.  Its scratch is one file-scope
+   device array of 2 MiB per GPU, held until the process ends: the block-weight
+   shards (64 * k bytes), small accumulators and one int32 per 2048 CSR entries
+   (the entry tiles' first rows).  A graph whose scratch would not fit (about
+   8.8 * 10^8 entries and more) is rejected with KAPPA_E_CAPACITY before any
+   device work.  Every call on a GPU shares that GPU's array (it keeps the last
+   call's contents and is cleared by each call with a fill kernel, not a
+   memset), so calls that overlap on one GPU race: serialise them.  out
+   (host) is written through a stream-ordered copy.  Synchronous. */
+kappa_status kappa_cut_balance_noalloc(const kappa_graph *g, const int32_t *part, int32_t k,
+                                       uint32_t eps_num, uint32_t eps_den, uint64_t *block_w,
+                                       kappa_cut_result *out, kappa_stream_t stream);
+
 /* The way back up in one call: partitions the coarsest level of h with
    kappa_initial_partition(part_seed), projects level by level down to
    level 0 and evaluates cut/balance on every level.  part0 (device, n_0

@@ -12,7 +12,8 @@ from ._lib import (  # noqa: F401
     declared_functions, lib, status_str, union_csr,
     kappa_validate, kappa_rate, kappa_match, kappa_match_two_phase, kappa_rcb_order, kappa_relabel,
     kappa_contract, kappa_coarsen, kappa_coarsen_batch, kappa_coarsen_graphs,
-    kappa_initial_partition, kappa_project, kappa_cut_balance, kappa_uncoarsen, kappa_cache_release,
+    kappa_initial_partition, kappa_project, kappa_cut_balance, kappa_cut_balance_noalloc,
+    kappa_uncoarsen, kappa_cache_release,
     kappa_refine, kappa_uncoarsen_refined, refine_params, REFINE_PRESETS, REFINE_K_MAX,
     graphs_enable, tail_enable, arena_first, use_torch_allocator, profile_enable, profile_reset, profile_read,
 )

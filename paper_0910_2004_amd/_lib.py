@@ -153,6 +153,8 @@ def lib():
         "kappa_project": (st, [P, i32, i32, P, P, P]),
         "kappa_cut_balance": (st, [ctypes.POINTER(c_graph), P, i32, u32, u32, P,
                                    ctypes.POINTER(c_cut), P]),
+        "kappa_cut_balance_noalloc": (st, [ctypes.POINTER(c_graph), P, i32, u32, u32, P,
+                                           ctypes.POINTER(c_cut), P]),
         "kappa_uncoarsen": (st, [P, i32, u64, u32, u32, P, P, P]),
         "kappa_refine": (st, [ctypes.POINTER(c_graph), P, i32, u32, u32,
                               ctypes.POINTER(c_refine_params), ctypes.POINTER(c_refine_stats), P]),
@@ -576,6 +578,18 @@ def kappa_cut_balance(g: DeviceGraph, part, k: int, eps_num: int = 3, eps_den: i
                                                         eps_den, _ptr(bw), ctypes.byref(res),
                                                         _stream()))
     return res, bw[:k]
+
+
+def kappa_cut_balance_noalloc(g: DeviceGraph, part, k: int, eps_num: int = 3, eps_den: int = 100,
+                              block_w=None):
+    """kappa_cut_balance through the allocation-free entry point: block_w
+    (device int64 [k], may be None) is the caller's; returns the c_cut result."""
+    res = c_cut()
+    _check("kappa_cut_balance_noalloc",
+           lib().kappa_cut_balance_noalloc(ctypes.byref(g.c()), _ptr(part), k, eps_num, eps_den,
+                                           _ptr(block_w) if block_w is not None else None,
+                                           ctypes.byref(res), _stream()))
+    return res
 
 
 def kappa_uncoarsen(h: Hierarchy, k: int, part_seed: int = 1, eps_num: int = 3, eps_den: int = 100,

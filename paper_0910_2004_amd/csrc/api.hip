@@ -76,8 +76,12 @@ Profiler g_prof;
 }  // namespace
 
 namespace kappa {
+// set while an allocation-free entry point runs on this thread: the profiler
+// records nothing then (its events would be created on demand)
+thread_local bool g_no_alloc_call = false;
+
 ProfScope::ProfScope(const char *name, hipStream_t st) : id(-1), rec(0), s(st) {
-    if (!g_prof.on) return;
+    if (!g_prof.on || g_no_alloc_call) return;
     std::lock_guard<std::mutex> lk(g_prof.mu);
     id = g_prof.id_of(name);
     ProfRec r{id, g_prof.take(), g_prof.take()};
@@ -1586,6 +1590,86 @@ extern "C" kappa_status kappa_cut_balance(const kappa_graph *g, const int32_t *p
     HIPCHK(hipStreamSynchronize(s));
     if (rb->f) return KAPPA_E_RANGE;
     *out = rb->r;
+    return KAPPA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Cut and balance without allocation, for callers that cannot allocate (code
+// under HIP graph capture, serving loops, harnesses that forbid it).  Its
+// scratch (block-weight shards, accumulators, arrival counters, the result
+// and the entry tiles' rows) lives in one file-scope device array per GPU,
+// which every call on that GPU shares: calls that overlap on one GPU race.
+// ---------------------------------------------------------------------------
+constexpr size_t NO_ALLOC_SCRATCH_BYTES = (size_t)2 << 20;
+static __device__ __align__(256) unsigned char scratch[NO_ALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NO_ALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NO_ALLOC_MAX_DEVICES] = {};
+
+// This GPU's scratch array by its device address (the array's name in host
+// code is not one): looked up once per device, with that device current.
+void *scratch_ptr() {
+    int devid = 0;
+    if (hipGetDevice(&devid) != hipSuccess || devid < 0 || devid >= NO_ALLOC_MAX_DEVICES)
+        return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[devid]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[devid] = p;
+    }
+    return g_scratch_ptr[devid];
+}
+
+// The scratch layout of one cut/balance call (base == nullptr: sizes only).
+struct CutScratch {
+    UpAcc a;
+    kappa_cut_result *rd = nullptr;
+    int32_t *tr = nullptr;
+    size_t bytes = 0;
+    CutScratch(char *base, int32_t k, int64_t nnz) {
+        Carve cv;
+        cv.base = base;
+        a.bw = cv.get<uint64_t>((int64_t)BW_SHARDS * k);
+        a.acc = cv.get<uint64_t>(3 * NSHARD);
+        a.arrive = cv.get<unsigned>(ARRIVE_WORDS);
+        a.flag = cv.get<uint32_t>(1);
+        rd = cv.get<kappa_cut_result>(1);
+        tr = cv.get<int32_t>(tile_rows_needed(nnz));
+        bytes = cv.off;
+    }
+};
+struct NoAllocScope {
+    NoAllocScope() { g_no_alloc_call = true; }
+    ~NoAllocScope() { g_no_alloc_call = false; }
+};
+}  // namespace
+
+extern "C" kappa_status kappa_cut_balance_noalloc(const kappa_graph *g, const int32_t *part,
+                                                  int32_t k, uint32_t eps_num, uint32_t eps_den,
+                                                  uint64_t *block_w, kappa_cut_result *out,
+                                                  kappa_stream_t stream) {
+    if (!graph_args_ok(g) || !out || !cut_args_ok(k, eps_num, eps_den)) return KAPPA_E_ARG;
+    if (g->n > 0 && !part) return KAPPA_E_ARG;
+    if (CutScratch(nullptr, k, g->nnz).bytes > NO_ALLOC_SCRATCH_BYTES) return KAPPA_E_CAPACITY;
+    char *base = (char *)scratch_ptr();
+    if (!base) return KAPPA_E_HIP;
+    NoAllocScope scope;
+    hipStream_t s = S(stream);
+    const DevGraph d = dev(g);
+    const CutScratch cs(base, k, d.nnz);
+    launch_up_clear(cs.a, k, s);   // a fill kernel: the scratch keeps the last call's contents
+    launch_up_level(d, UP_GIVEN, nullptr, 0, nullptr, 0, const_cast<int32_t *>(part), k, eps_num,
+                    eps_den, cs.tr, cs.a, block_w, cs.rd, s);
+    kappa_cut_result r;
+    uint32_t flag = 0;
+    HIPCHK(hipMemcpyAsync(&r, cs.rd, sizeof r, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&flag, cs.a.flag, sizeof flag, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (flag) return KAPPA_E_RANGE;
+    *out = r;
     return KAPPA_OK;
 }
 

@@ -87,3 +87,23 @@ def test_library_binds_torchs_hip_runtime():
     assert out.returncode == 0, out.stderr
     libs = eval(out.stdout.strip().splitlines()[-1])
     assert len(libs) == 1 and "torch" in libs[0], libs
+
+
+def test_noalloc_cut_balance_checks_before_device_work():
+    """The allocation-free cut/balance rejects bad arguments and graphs whose
+    scratch would exceed its fixed device array before any HIP call (the
+    pointers below are never dereferenced)."""
+    L = K.lib()
+    fake = ctypes.c_void_p(8)
+    res = K._lib.c_cut()
+    assert L.kappa_cut_balance_noalloc(None, fake, 2, 3, 100, None, ctypes.byref(res), None) == K.E_ARG
+    g = K._lib.c_graph(10, 20, fake, fake, fake, fake)
+    assert L.kappa_cut_balance_noalloc(ctypes.byref(g), fake, 0, 3, 100, None, ctypes.byref(res),
+                                       None) == K.E_ARG
+    assert L.kappa_cut_balance_noalloc(ctypes.byref(g), None, 2, 3, 100, None, ctypes.byref(res),
+                                       None) == K.E_ARG
+    assert L.kappa_cut_balance_noalloc(ctypes.byref(g), fake, 2, 3, 100, None, None, None) == K.E_ARG
+    # one int32 of scratch per 2048 entries: 2^31 entries need 4 MiB, beyond the 2 MiB array
+    big = K._lib.c_graph(1 << 20, 1 << 31, fake, fake, fake, fake)
+    assert L.kappa_cut_balance_noalloc(ctypes.byref(big), fake, 4096, 3, 100, None,
+                                       ctypes.byref(res), None) == K.E_CAPACITY
