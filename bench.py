@@ -87,7 +87,7 @@ def bytes_validate(n, D):
 
 
 # merge kernels by class of the bound deg(u) + deg(w) - 2 on the merged row
-MERGE_CLASSES = (("fill_small", 0, 64), ("fill_wave", 65, 512), ("fill_mid", 513, 4094),
+MERGE_CLASSES = (("fill_small", 0, 64), ("fill_mid", 65, 4094),
                  ("fill_big", 4095, 16382), ("fill_large", 16383, 1 << 62))
 
 
@@ -201,7 +201,7 @@ def model_bytes(stats_by_rating, classes=None, n0=0, D0=0):
 # library's profiler names
 KERNEL_SYMBOLS = {"pick": r"pick_k<\d, false, 0, (true|false)>", "mate": r"mate_k<\d, false>",
                   "pick_first": r"pick_k<\d, true, 0, false>", "fill_small": r"fill_small_k",
-                  "fill_wave": r"fill_wave_k", "fill_mid": r"fill_mid_k", "fill_big": r"fill_big_k",
+                  "fill_mid": r"fill_mid_k", "fill_big": r"fill_big_k",
                   "fill_large": r"fill_large_k", "validate_entries": r"validate_entries_k",
                   "compact": r"compact_k", "cut_entries": r"up_entries_k<(true|false)>",
                   "refine_fm": r"ref_fm_k"}
@@ -320,10 +320,11 @@ def main():
                     help="rgg20: coarsen the two ratings one after the other on one stream "
                          "(default: concurrently, one stream and host thread per rating)")
     ap.add_argument("--order", default="generation", choices=["generation", "rcb", "rcb-device"],
-                    help="rgg20: node ids in point generation order (the headline), in "
+                    help="rgg20: node ids in point generation order, or renumbered in "
                          "recursive coordinate bisection order (locality of a geometric "
-                         "prepartition), or renumbered so on the device before the timed "
-                         "steps (kappa_rcb_order + kappa_relabel, timed apart)")
+                         "prepartition) on the device before the timed steps "
+                         "(kappa_rcb_order + kappa_relabel, timed apart; rcb and rcb-device "
+                         "are the same)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-out", default=None)
     ap.add_argument("--no-secondary", action="store_true",
@@ -419,12 +420,12 @@ def single_graph(args, rmat_mode, primary):
         g = rmat(22, 16, seed=3, wseed=33)
         log(f"generated rmat scale 22 n={g.n} |E|={g.m} in {time.time() - t0:.1f}s")
     else:
-        g = rgg(n, seed=2, order="rcb" if args.order == "rcb" else "generation")
-        log(f"generated rgg n={g.n} |E|={g.m} ({args.order} order) in {time.time() - t0:.1f}s")
+        g = rgg(n, seed=2)
+        log(f"generated rgg n={g.n} |E|={g.m} in {time.time() - t0:.1f}s")
     torch.cuda.set_device(0)
     dg = K.DeviceGraph.from_csr(g, "cuda:0")
     relabel_ms = None
-    if args.order == "rcb-device":
+    if args.order != "generation" and not rmat_mode:
         # the points' RCB order and the renumbered graph, on the device
         from workloads import rgg_points
         xy = torch.from_numpy(rgg_points(n, 2)).to("cuda:0")
@@ -439,8 +440,6 @@ def single_graph(args, rmat_mode, primary):
         relabel_ms = round(min(ts), 3)
         log(f"device relabelling: {relabel_ms} ms (best of 3)")
         dg = dr
-        from workloads import relabel as host_relabel, rcb_order
-        g = host_relabel(g, rcb_order(rgg_points(n, 2)))   # the same graph, for the oracle
     # one stream (default priority) and one level-0 partition buffer per rating
     streams = [torch.cuda.Stream(device="cuda:0") for _ in ratings]
     part0s = [torch.empty(g.n, dtype=torch.int32, device="cuda:0") for _ in ratings]
@@ -556,6 +555,10 @@ def single_graph(args, rmat_mode, primary):
                      "hierarchy and way back up on one host thread"
         else:
             gs = g
+            if args.order != "generation":   # the same renumbered graph, by the oracle's reference
+                from oracle.rcb import rcb_order, relabel
+                from workloads import rgg_points
+                gs = relabel(O.Graph.of(g), rcb_order(rgg_points(n, 2)))
             sample = "one full step (both ratings) of the same workload on one host thread"
         t3 = time.perf_counter()
         for r in ratings:
@@ -589,7 +592,7 @@ def single_graph(args, rmat_mode, primary):
                                + ("" if args.order == "generation" else
                                   ", node ids in recursive coordinate bisection order"
                                   + (" (renumbered on the device before the timed steps)"
-                                     if args.order == "rcb-device" else ""))
+                                     if args.order != "generation" else ""))
                                + ("" if args.block_bits is None else
                                   f", two-phase matcher with blocks of 2^{args.block_bits}"),
                    "node_order": args.order, "block_bits": args.block_bits,

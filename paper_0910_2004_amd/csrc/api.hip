@@ -693,6 +693,9 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     // rows above BIN_MID_MAX get a block each per round: many blocks when the
     // graph has many (power-law graphs), few otherwise
     c.big_blocks = maxdeg0 > BIN_MID_MAX ? 1024 : 64;
+    // graphs without long rows at level 0 rarely grow rows of thousands of
+    // entries: such rows then take the hub accumulators (no big-row launch)
+    c.big_rows = maxdeg0 > BIN_MID_MAX ? 1 : 0;
     const int maxl = p->max_levels;
     const int32_t count = bi ? bi->count : 0;
     uint32_t *bflag = nullptr;

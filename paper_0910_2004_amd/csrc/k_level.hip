@@ -1757,7 +1757,7 @@ __device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bi
         if (live) {
             r = row_src(g, c, x);
             cls = row_class(row_bound(r));
-            if (!BIG && cls == 4) cls = 2;
+            if ((!BIG || !c.big_rows) && cls == 4) cls = 2;
             if (cls == 2 && !c.cs.hub_acc) need_hubs = true;
         }
         wave_append(sub == 0 && cls == 1, x, lists1, &c.cs.row_cnt[1]);
@@ -2026,15 +2026,16 @@ __device__ __forceinline__ void fill_wave_body(const Ctx &c, int l, unsigned bid
     }
 }
 
-// Rows of 65..512 entries, one wave each.
-__global__ void __launch_bounds__(BLOCK) fill_wave_k(Ctx c, int l) {
-    __shared__ uint64_t s[(BLOCK / WAVE) * WR_P];
-    fill_wave_body<BLOCK>(c, l, blockIdx.x, gridDim.x, s);
-}
-// Rows of 513..4094 entries, one block each.
-__global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l) {
+// Both mid classes in one class-partitioned grid: blocks [0, wave_blocks)
+// merge the rows of 65..512 entries one wave each, the others the rows of
+// 513..4094 entries one block each (one LDS array serves either).
+__global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l, unsigned wave_blocks) {
+    static_assert((BLOCK / WAVE) * WR_P <= MID_P, "the wave rows' slices fit the block rows' array");
     __shared__ uint64_t s[MID_P];
-    fill_block_body<BLOCK, MID_P>(c, l, blockIdx.x, gridDim.x, 3, s);
+    if (blockIdx.x < wave_blocks)
+        fill_wave_body<BLOCK>(c, l, blockIdx.x, wave_blocks, s);
+    else
+        fill_block_body<BLOCK, MID_P>(c, l, blockIdx.x - wave_blocks, gridDim.x - wave_blocks, 3, s);
 }
 
 // --- 2c. large rows: dense accumulator per slot --------------------------------------
@@ -2734,14 +2735,11 @@ void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, h
                            s, c, l);
     }
     {
-        KAPPA_PROF("fill_wave", s);
-        hipLaunchKernelGGL(fill_wave_k, dim3(grid_for(n_hint, 64, 2048)), dim3(BLOCK), 0, s, c, l);
-    }
-    {
         KAPPA_PROF("fill_mid", s);
-        hipLaunchKernelGGL(fill_mid_k, dim3(grid_for(n_hint, 256, 1024)), dim3(BLOCK), 0, s, c, l);
+        const unsigned wb = grid_for(n_hint, 64, 2048), mb = grid_for(n_hint, 256, 1024);
+        hipLaunchKernelGGL(fill_mid_k, dim3(wb + mb), dim3(BLOCK), 0, s, c, l, wb);
     }
-    {
+    if (c.big_rows) {
         KAPPA_PROF("fill_big", s);
         hipLaunchKernelGGL(fill_big_k, dim3(grid_for(n_hint, 4096, 256)), dim3(BIG_THREADS), 0, s,
                            c, l);

@@ -13,11 +13,9 @@
 //               the entries are sorted by (row, new neighbour): by neighbour,
 //               then stably by row.
 //
-// The sorts are rocPRIM's (through hipCUB): stable LSD radix sorts over all
-// items, a library primitive for what is a preprocessing step.
+// The sorts are the library's own stable LSD radix sorts (k_sort.hip), the
+// offsets its device exclusive sum.
 #include <vector>
-
-#include <hipcub/hipcub.hpp>
 
 #include "kappa_internal.h"
 
@@ -185,13 +183,7 @@ kappa_status rcb_order_impl(const double *xy, int32_t n, int32_t leaf, int32_t *
     size_t maxbox = 1;
     for (auto &b : beg) maxbox = std::max(maxbox, b.size());
     const size_t nn = (size_t)std::max(n, 1);
-    size_t t1 = 0, t2 = 0;
-    HCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, t1, (const uint64_t *)nullptr,
-                                            (uint64_t *)nullptr, (const int32_t *)nullptr,
-                                            (int32_t *)nullptr, (int)nn, 0, 64, s));
-    HCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, t2, (const uint32_t *)nullptr,
-                                            (uint32_t *)nullptr, (const int32_t *)nullptr,
-                                            (int32_t *)nullptr, (int)nn, 0, 32, s));
+    const size_t t1 = radix_sort_ws_bytes((int64_t)nn, 8), t2 = radix_sort_ws_bytes((int64_t)nn, 4);
     const size_t o_k0 = 0, o_k1 = al256(o_k0 + 8 * nn), o_p0 = al256(o_k1 + 8 * nn),
                  o_p1 = al256(o_p0 + 4 * nn), o_b0 = al256(o_p1 + 4 * nn),
                  o_b1 = al256(o_b0 + 4 * nn), o_p2 = al256(o_b1 + 4 * nn),
@@ -217,12 +209,14 @@ kappa_status rcb_order_impl(const double *xy, int32_t n, int32_t leaf, int32_t *
         HCHK(hipMemcpyAsync(dcut, cut[d].data(), (size_t)nbox, hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(rcb_keys_k, dim3(grid_for(n, BLOCK, 4096)), dim3(BLOCK), 0, s, xy, order,
                            dbeg, dcut, nbox, n, (int)(d & 1), k0, p0);
-        size_t tb = t1;
-        HCHK(hipcub::DeviceRadixSort::SortPairs(tmp, tb, k0, k1, p0, p1, n, 0, 64, s));
+        kappa_status st = radix_sort_pairs<uint64_t>(k0, k1, (const uint32_t *)p0, (uint32_t *)p1,
+                                                     n, 0, 64, (char *)tmp, s);
+        if (st != KAPPA_OK) return st;
         hipLaunchKernelGGL(rcb_box_keys_k, dim3(grid_for(n, BLOCK, 4096)), dim3(BLOCK), 0, s, p1,
                            dbeg, nbox, n, b0);
-        tb = t2;
-        HCHK(hipcub::DeviceRadixSort::SortPairs(tmp, tb, b0, b1, p1, p2, n, 0, bits_for(nbox), s));
+        st = radix_sort_pairs<uint32_t>(b0, b1, (const uint32_t *)p1, (uint32_t *)p2, n, 0,
+                                        bits_for(nbox), (char *)tmp, s);
+        if (st != KAPPA_OK) return st;
         hipLaunchKernelGGL(gather_i32_k, dim3(grid_for(n, BLOCK, 4096)), dim3(BLOCK), 0, s, order,
                            p2, (int64_t)n, ord2);
         HCHK(hipMemcpyAsync(order, ord2, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
@@ -237,12 +231,7 @@ kappa_status relabel_impl(const DevGraph &g, const int32_t *order, int64_t *nx, 
                           uint32_t *new_ew, uint32_t *nvw, hipStream_t s, char *ws,
                           size_t ws_bytes, size_t *need, uint32_t *hflag) {
     const size_t nn = (size_t)std::max(g.n, 1), ne = (size_t)std::max<int64_t>(g.nnz, 1);
-    size_t ts = 0, t1 = 0;
-    HCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, ts, (const int64_t *)nullptr, (int64_t *)nullptr,
-                                          (int)nn + 1, s));
-    HCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, t1, (const uint32_t *)nullptr,
-                                            (uint32_t *)nullptr, (const int32_t *)nullptr,
-                                            (int32_t *)nullptr, (int)ne, 0, 32, s));
+    const size_t ts = exclusive_sum_ws_bytes((int64_t)nn + 1), t1 = radix_sort_ws_bytes((int64_t)ne, 4);
     const size_t o_inv = 0, o_seen = al256(4 * nn), o_flag = al256(o_seen + 4 * nn),
                  o_deg = al256(o_flag + 4), o_a = al256(o_deg + 8 * (nn + 1)),
                  o_w = al256(o_a + 4 * ne), o_row = al256(o_w + 4 * ne),
@@ -273,20 +262,20 @@ kappa_status relabel_impl(const DevGraph &g, const int32_t *order, int64_t *nx, 
     if (*hflag) return KAPPA_E_ARG;   // not a permutation of 0 .. n-1
     hipLaunchKernelGGL(relabel_rows_k, dim3(grid_for((int64_t)g.n + 1, BLOCK, 4096)), dim3(BLOCK), 0,
                        s, g, order, deg, nvw);
-    size_t tb = ts;
-    HCHK(hipcub::DeviceScan::ExclusiveSum(tmp, tb, deg, nx, g.n + 1, s));
+    kappa_status st = exclusive_sum_i64(deg, nx, (int64_t)g.n + 1, (char *)tmp, s);
+    if (st != KAPPA_OK) return st;
     if (g.n > 0 && g.nnz > 0) {
         hipLaunchKernelGGL(relabel_fill_k, dim3(grid_for(g.n, BLOCK / WAVE, 4096)), dim3(BLOCK), 0, s,
                            g, order, inv, nx, a0, w0, row, p0);
         // by new neighbour, then stably by row
-        tb = t1;
-        HCHK(hipcub::DeviceRadixSort::SortPairs(tmp, tb, (const uint32_t *)a0, k1, p0, p1,
-                                                (int)g.nnz, 0, bits_for(g.n), s));
+        st = radix_sort_pairs<uint32_t>((const uint32_t *)a0, k1, (const uint32_t *)p0,
+                                        (uint32_t *)p1, g.nnz, 0, bits_for(g.n), (char *)tmp, s);
+        if (st != KAPPA_OK) return st;
         hipLaunchKernelGGL(gather_i32_k, dim3(grid_for(g.nnz, BLOCK, 4096)), dim3(BLOCK), 0, s,
                            (const int32_t *)row, p1, g.nnz, (int32_t *)k1);
-        tb = t1;
-        HCHK(hipcub::DeviceRadixSort::SortPairs(tmp, tb, k1, r1, p1, p2, (int)g.nnz, 0,
-                                                bits_for(g.n), s));
+        st = radix_sort_pairs<uint32_t>(k1, r1, (const uint32_t *)p1, (uint32_t *)p2, g.nnz, 0,
+                                        bits_for(g.n), (char *)tmp, s);
+        if (st != KAPPA_OK) return st;
         hipLaunchKernelGGL(relabel_gather_k, dim3(grid_for(g.nnz, BLOCK, 4096)), dim3(BLOCK), 0, s,
                            a0, w0, p2, g.nnz, nadj, new_ew);
     }

@@ -671,6 +671,8 @@ struct Ctx {
     BatchCtx b;
     int32_t block_bits = -1;   // >= 0: two-phase matcher with blocks of 2^block_bits ids
     int32_t big_blocks = 64;   // blocks per round launch for rows above BIN_MID_MAX entries
+    int32_t big_rows = 1;      // 1: rows of 4095..16382 entries get the big-row sort launch;
+                               // 0: they join the large rows (hub accumulators)
 };
 
 // K bump allocations in the arena with one read and one write of the cursor
@@ -813,6 +815,17 @@ void launch_batch_extract(const DevGraph &u, const int32_t *cmap, const int32_t 
 // level's compaction).  Needs st->cnt zero on entry.
 void launch_level_match(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, int rounds,
                         bool stop_rules, bool out_kernels, hipStream_t s);
+// k_sort.hip: stable LSD radix sort of n < 2^31 (key, 32-bit value) pairs by
+// key bits [begin_bit, end_bit), 8 bits per pass (KT uint32_t or uint64_t;
+// kin != kout, vin != vout; the input is not modified); ws holds
+// radix_sort_ws_bytes(n, sizeof(KT)) bytes.  Stream-ordered.
+size_t radix_sort_ws_bytes(int64_t n, size_t key_bytes);
+template <class KT>
+kappa_status radix_sort_pairs(const KT *kin, KT *kout, const uint32_t *vin, uint32_t *vout,
+                              int64_t n, int begin_bit, int end_bit, char *ws, hipStream_t s);
+// Exclusive sum of n int64 (out may not alias in); ws: exclusive_sum_ws_bytes(n).
+size_t exclusive_sum_ws_bytes(int64_t n);
+kappa_status exclusive_sum_i64(const int64_t *in, int64_t *out, int64_t n, char *ws, hipStream_t s);
 // Recursive coordinate bisection order of n points (xy interleaved, device)
 // and the relabelling of a graph by an order (k_relabel.hip).  ws == nullptr
 // asks for the workspace size only (*need).  Both synchronise the stream.

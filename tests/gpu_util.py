@@ -66,3 +66,12 @@ def compare_hierarchy(H, OH, check_rounds=True, check_uncoarsen=True, k=2, part_
         assert np.array_equal(part0.cpu().numpy(), oparts[0])
         for l in range(len(OH.levels)):
             assert res[l].as_tuple() == ores[l].as_tuple(), f"level {l}: cut/balance differs"
+
+
+def rgg_rcb(n, seed):
+    """The random geometric graph of n points (seed) with its nodes renamed in
+    recursive coordinate bisection order (the oracle's reference order)."""
+    from oracle.rcb import rcb_order, relabel
+    from workloads import rgg, rgg_points
+    return relabel(O.Graph.of(rgg(n, seed=seed)), rcb_order(rgg_points(n, seed)))
+

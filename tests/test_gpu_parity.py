@@ -13,7 +13,7 @@ import pytest
 
 import oracle as O
 import paper_0910_2004_amd as K
-from gpu_util import assert_graph_equal, check_hierarchy, dev, graph_np
+from gpu_util import rgg_rcb, assert_graph_equal, check_hierarchy, dev, graph_np
 from workloads import (complete_graph, csr_from_edges, cycle_graph, grid2d, path_graph,
                        random_graph, rgg, rmat, star_graph)
 
@@ -167,7 +167,7 @@ def test_rgg_in_rcb_order(rating):
     # node ids in recursive coordinate bisection order (the locality a
     # geometric prepartition gives): the same kernels, the same oracle
     say("rgg 2^17 rcb order", rating)
-    check_hierarchy(rgg(1 << 17, seed=21, order="rcb"), rating, 42, stop_n=20 * 64, k=64)
+    check_hierarchy(rgg_rcb(1 << 17, 21), rating, 42, stop_n=20 * 64, k=64)
 
 
 def test_hub_rows_and_degree_classes():

@@ -1,5 +1,5 @@
 """The locality relabelling on the device (kappa_rcb_order, kappa_relabel)
-against the host reference (workloads.rcb_order, workloads.relabel), and the
+against the oracle's reference (oracle.rcb.rcb_order, oracle.rcb.relabel), and the
 whole hierarchy of a device-relabelled graph against the oracle on the host-
 relabelled one: the relabelling is exact, so the comparison is bit-exact."""
 import sys
@@ -10,7 +10,8 @@ import pytest
 import oracle as O
 import paper_0910_2004_amd as K
 from gpu_util import check_hierarchy, dev, graph_np
-from workloads import grid2d, rcb_order, relabel, rgg, rgg_points, rmat, star_graph
+from oracle.rcb import rcb_order, relabel
+from workloads import grid2d, rgg, rgg_points, rmat, star_graph
 
 pytestmark = pytest.mark.gpu
 
@@ -83,6 +84,6 @@ def test_device_relabelled_hierarchy_equals_oracle(rating):
     g = rgg(n, seed=21)
     order = K.kappa_rcb_order(torch.from_numpy(pts).cuda(), 32)
     dr = K.kappa_relabel(dev(g), order)
-    host = rgg(n, seed=21, order="rcb")
+    host = relabel(O.Graph.of(rgg(n, seed=21)), rcb_order(pts))
     say(f"rgg 2^17: device order equals host: {np.array_equal(order.cpu().numpy(), rcb_order(pts))}")
     check_hierarchy(host, rating, 42, stop_n=20 * 64, k=64, dg=dr)

@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 import paper_0910_2004_amd as K
-from gpu_util import compare_hierarchy, dev
+from gpu_util import rgg_rcb, compare_hierarchy, dev
 from workloads import (complete_graph, csr_from_edges, cycle_graph, grid2d, path_graph,
                        random_graph, rgg, rmat, star_graph)
 
@@ -80,7 +80,7 @@ def test_one_block_is_greedy():
 
 @pytest.mark.parametrize("rating", [0, 1, 4])
 def test_medium_graphs(rating):
-    cases = [("rgg2^15 rcb", rgg(1 << 15, seed=11, order="rcb"), (6, 8, 10, 11)),
+    cases = [("rgg2^15 rcb", rgg_rcb(1 << 15, 11), (6, 8, 10, 11)),
              ("rgg2^15", rgg(1 << 15, seed=11), (10,)),
              ("grid150", grid2d(150, 150), (4, 7, 11)),
              ("rmat13", rmat(13, 16, seed=12, wseed=13), (5, 9, 11))]
@@ -135,7 +135,7 @@ def test_flag_rules():
 
 
 HIER = [("grid128", lambda: grid2d(128, 128), 64, (6, 10)),
-        ("rgg2^16 rcb", lambda: rgg(1 << 16, seed=21, order="rcb"), 1280, (8, 11)),
+        ("rgg2^16 rcb", lambda: rgg_rcb(1 << 16, 21), 1280, (8, 11)),
         ("rmat13", lambda: rmat(13, 16, seed=5, wseed=6), 256, (9,)),
         ("random", lambda: random_graph(20000, 70000, seed=8, wmax=9, cmax=4, cmin=0), 64, (5,))]
 
@@ -155,7 +155,7 @@ def test_hierarchy_equals_oracle(name, make, stop_n, bbs, rating):
 @pytest.mark.parametrize("rating", [0, 1])
 def test_full_size_rgg_rcb(rating):
     # the benchmark graph in recursive coordinate bisection order, blocks of 1024
-    g = rgg(1 << 20, seed=2, order="rcb")
+    g = rgg_rcb(1 << 20, 2)
     OH = O.coarsen(g, rating, 42, 1280, 1, 20, 64, block_bits=10)
     H = K.kappa_coarsen(dev(g), rating, 42, 1280, block_bits=10)
     say(f"rgg 2^20 rcb rating {rating}: levels {[H.info(l).n for l in range(len(H))]}")

@@ -51,48 +51,3 @@ def test_random_graph_and_batch():
         assert O.validate(b) == O.OK
         assert 1 <= b.ew.min() and b.ew.max() <= 16 and 1 <= b.vw.min() and b.vw.max() <= 16
         assert 700 <= b.n <= 4500
-
-
-def test_rcb_order_is_a_relabelling_with_locality():
-    from workloads.graphs import rcb_order, rgg_points
-    n = 1 << 14
-    pts = rgg_points(n, 9)
-    o = rcb_order(pts, leaf=32)
-    assert np.array_equal(np.sort(o), np.arange(n))
-    # every bisection: the lower half of a box lies at or below the upper
-    # half along x at even depths, along y at odd depths
-    q = pts[o]
-    size, depth = n, 0
-    while size > 32:
-        for a in range(0, n, size):
-            lo, hi = q[a:a + size // 2], q[a + size // 2:a + size]
-            assert lo[:, depth % 2].max() <= hi[:, depth % 2].min()
-        size, depth = size // 2, depth + 1
-    # the rcb graph is the generation-order graph with node i renamed inv[i]
-    g, h = rgg(n, seed=9), rgg(n, seed=9, order="rcb")
-    assert O.validate(h) == O.OK and _symmetric(h) and h.m == g.m
-    inv = np.empty(n, dtype=np.int64)
-    inv[o] = np.arange(n)
-    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.xadj))
-    eg = np.sort(inv[src] * n + inv[g.adj])
-    eh = np.sort(np.repeat(np.arange(n, dtype=np.int64), np.diff(h.xadj)) * n + h.adj)
-    assert np.array_equal(eg, eh)
-    # ids of neighbours are close in rcb order, far in generation order
-    gap = lambda x, s: np.abs(s - x.adj).mean()
-    assert gap(h, np.repeat(np.arange(n), np.diff(h.xadj))) * 20 < gap(g, src)
-
-
-def test_relabel_reference():
-    from workloads import rcb_order, relabel, rgg_points
-    n = 1 << 13
-    pts = rgg_points(n, 4)
-    o = rcb_order(pts)
-    h = relabel(rgg(n, seed=4), o)
-    r = rgg(n, seed=4, order="rcb")
-    assert np.array_equal(h.xadj, r.xadj) and np.array_equal(h.adj, r.adj)
-    assert np.array_equal(h.ew, r.ew) and np.array_equal(h.vw, r.vw)
-    g = rmat(10, 8, seed=1, wseed=2)
-    perm = np.random.default_rng(3).permutation(g.n)
-    back = relabel(relabel(g, perm), np.argsort(perm))
-    assert np.array_equal(back.xadj, g.xadj) and np.array_equal(back.adj, g.adj)
-    assert np.array_equal(back.ew, g.ew) and np.array_equal(back.vw, g.vw)

@@ -3,4 +3,4 @@ the benchmark.  This package holds no arithmetic of the coarsening method:
 it only builds input graphs (symmetric CSR with integer weights)."""
 from .graphs import (CSR, csr_from_edges, grid2d, rgg, rmat, random_graph,  # noqa: F401
                      path_graph, cycle_graph, star_graph, complete_graph, batch_graphs,
-                     degrade_grid, serve_requests, rcb_order, rgg_points, relabel)
+                     degrade_grid, serve_requests, rgg_points)

@@ -130,58 +130,15 @@ def rgg_points(n: int, seed: int) -> np.ndarray:
     return np.random.Generator(np.random.PCG64(seed)).random((n, 2))
 
 
-def rcb_order(pts: np.ndarray, leaf: int = 32) -> np.ndarray:
-    """Indices of the points in recursive coordinate bisection order (the
-    geometric prepartition of Section 3.3).  Every box of more than `leaf`
-    points is sorted stably by its x-coordinate at even depths and its
-    y-coordinate at odd depths and cut after its first half (the first
-    len // 2 points); the lower half is numbered first.  Depth d cuts every
-    box of that depth, so the boxes of a depth are the segments
-    [a, a + len // 2) and [a + len // 2, b) of the ones before."""
-    n = len(pts)
-    out = np.arange(n)
-    segs = [(0, n)]
-    depth = 0
-    while segs:
-        nxt = []
-        for a, b in segs:
-            if b - a <= leaf:
-                continue
-            sub = out[a:b]
-            out[a:b] = sub[np.argsort(pts[sub, depth % 2], kind="stable")]
-            mid = (b - a) // 2
-            nxt += [(a, a + mid), (a + mid, b)]
-        segs = nxt
-        depth += 1
-    return out
-
-
-def relabel(g: CSR, order: np.ndarray) -> CSR:
-    """g renumbered: node x of the result is node order[x] of g."""
-    order = np.asarray(order, dtype=np.int64)
-    inv = np.empty(g.n, dtype=np.int64)
-    inv[order] = np.arange(g.n)
-    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.xadj))
-    keep = src < g.adj
-    a, b = inv[src[keep]], inv[g.adj[keep].astype(np.int64)]
-    return csr_from_edges(g.n, a, b, g.ew[keep], np.asarray(g.vw)[order])
-
-
 def rgg(n: int, seed: int, radius: Optional[float] = None, mean_degree: float = 8.0,
         ew: Optional[np.ndarray] = None, vw: Optional[np.ndarray] = None,
-        points: Optional[np.ndarray] = None, order: str = "generation") -> CSR:
-    """Random geometric graph in the unit square; edge iff distance < radius.
-    order: node ids in the points' generation order, or "rcb" (recursive
-    coordinate bisection order, the geometric prepartition of the paper's
-    partitioner)."""
+        points: Optional[np.ndarray] = None) -> CSR:
+    """Random geometric graph in the unit square; edge iff distance < radius;
+    node ids in the points' generation order."""
     from scipy.spatial import cKDTree
     if radius is None:
         radius = math.sqrt(mean_degree / (math.pi * n))
     pts = rgg_points(n, seed) if points is None else points
-    if order == "rcb":
-        pts = pts[rcb_order(pts)]
-    elif order != "generation":
-        raise ValueError(f"unknown order {order!r}")
     pairs = cKDTree(pts).query_pairs(radius, output_type="ndarray")
     if len(pairs):
         d = pts[pairs[:, 0]] - pts[pairs[:, 1]]
