@@ -656,32 +656,121 @@ static int entry_above(int64_t g1, uint64_t h1, int32_t v1, int64_t g2, uint64_t
     return v1 < v2;
 }
 
-/* One two-block local search on blocks a and b of part (part is not
-   changed).  moves (capacity |A| + |B|) receives the moved nodes in order.
-   res: start imbalance, start cut, end imbalance, end cut, moves made, moves
-   kept (the rolled-back prefix), with imbalances scaled by s. */
-static void fm_pair(int32_t n, const int64_t *xadj, const int32_t *adj, const uint32_t *ew,
-                    const uint32_t *vw, const int32_t *part, int32_t a, int32_t b, int64_t wa,
-                    int64_t wb, int64_t s, int64_t l, uint64_t run_seed, uint32_t alpha_num,
-                    uint32_t alpha_den, int32_t depth, int32_t *moves, int64_t *res)
+/* Work arrays of the local searches, indexed by node id and allocated once
+   per refinement call: side[] is -1 and status[], gain[], dist[] are zero /
+   zero / -1 for every node outside a running search (each search resets the
+   nodes of its two blocks when it ends). */
+typedef struct {
+    int64_t g;
+    uint64_t h;
+    int32_t v;
+} fm_entry;
+typedef struct {
+    fm_entry *e;
+    int64_t n, cap;
+} fm_heap;
+typedef struct {
+    int8_t *side, *status; /* status: 0 idle, 1 queued, 2 moved */
+    int64_t *gain;
+    int32_t *dist, *bfs;
+    fm_heap q[2];
+} fm_work;
+
+static void fm_work_init(fm_work *w, int32_t n)
 {
     size_t nn = (size_t)(n > 0 ? n : 1);
-    int8_t *side = (int8_t *)malloc(nn);
-    int8_t *status = (int8_t *)calloc(nn, 1); /* 0 idle, 1 queued, 2 moved */
-    int64_t *gain = (int64_t *)calloc(nn, sizeof(int64_t));
-    int32_t *dist = (int32_t *)malloc(nn * sizeof(int32_t));
-    int32_t *list = (int32_t *)malloc(nn * sizeof(int32_t)); /* queued nodes, both sides */
-    int32_t *bfs = (int32_t *)malloc(nn * sizeof(int32_t));
+    w->side = (int8_t *)malloc(nn);
+    w->status = (int8_t *)calloc(nn, 1);
+    w->gain = (int64_t *)calloc(nn, sizeof(int64_t));
+    w->dist = (int32_t *)malloc(nn * sizeof(int32_t));
+    w->bfs = (int32_t *)malloc(nn * sizeof(int32_t));
+    for (size_t v = 0; v < nn; ++v) { w->side[v] = -1; w->dist[v] = -1; }
+    for (int i = 0; i < 2; ++i) {
+        w->q[i].cap = 1024;
+        w->q[i].n = 0;
+        w->q[i].e = (fm_entry *)malloc((size_t)w->q[i].cap * sizeof(fm_entry));
+    }
+}
+
+static void fm_work_free(fm_work *w)
+{
+    free(w->side); free(w->status); free(w->gain); free(w->dist); free(w->bfs);
+    free(w->q[0].e); free(w->q[1].e);
+}
+
+/* Binary max-heap under the queue order (entry_above); a node whose gain
+   changes while queued gets a new entry, and entries whose node moved or
+   whose gain is no longer current are dropped when they reach the top. */
+static void heap_push(fm_heap *q, int64_t g, uint64_t h, int32_t v)
+{
+    if (q->n == q->cap) {
+        q->cap *= 2;
+        q->e = (fm_entry *)realloc(q->e, (size_t)q->cap * sizeof(fm_entry));
+    }
+    int64_t i = q->n++;
+    fm_entry x = {g, h, v};
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (!entry_above(x.g, x.h, x.v, q->e[p].g, q->e[p].h, q->e[p].v)) break;
+        q->e[i] = q->e[p];
+        i = p;
+    }
+    q->e[i] = x;
+}
+
+static void heap_pop(fm_heap *q)
+{
+    fm_entry x = q->e[--q->n];
+    int64_t i = 0;
+    for (;;) {
+        int64_t c = 2 * i + 1;
+        if (c >= q->n) break;
+        if (c + 1 < q->n && entry_above(q->e[c + 1].g, q->e[c + 1].h, q->e[c + 1].v, q->e[c].g,
+                                        q->e[c].h, q->e[c].v))
+            ++c;
+        if (!entry_above(q->e[c].g, q->e[c].h, q->e[c].v, x.g, x.h, x.v)) break;
+        q->e[i] = q->e[c];
+        i = c;
+    }
+    if (q->n > 0) q->e[i] = x;
+}
+
+/* The queued node with the largest (gain, hash, smaller id), or -1. */
+static int32_t heap_top(fm_heap *q, const int8_t *status, const int64_t *gain)
+{
+    while (q->n > 0) {
+        fm_entry t = q->e[0];
+        if (status[t.v] == 1 && gain[t.v] == t.g) return t.v;
+        heap_pop(q);
+    }
+    return -1;
+}
+
+/* One two-block local search on blocks a and b of part (part is not
+   changed); nodes[0 .. nn) are the nodes of the two blocks.  moves (capacity
+   nn) receives the moved nodes in order.  res: start imbalance, start cut,
+   end imbalance, end cut, moves made, moves kept (the rolled-back prefix),
+   with imbalances scaled by s. */
+static void fm_pair(fm_work *W, const int64_t *xadj, const int32_t *adj, const uint32_t *ew,
+                    const uint32_t *vw, const int32_t *part, const int32_t *nodes, int64_t nn,
+                    int32_t a, int32_t b, int64_t wa, int64_t wb, int64_t s, int64_t l,
+                    uint64_t run_seed, uint32_t alpha_num, uint32_t alpha_den, int32_t depth,
+                    int32_t *moves, int64_t *res)
+{
+    (void)b;   // side 1 is every listed node not in block a
+    int8_t *side = W->side, *status = W->status;
+    int64_t *gain = W->gain;
+    int32_t *dist = W->dist, *bfs = W->bfs;
     int64_t cnt[2] = {0, 0}, cut = 0;
-    for (int32_t v = 0; v < n; ++v) {
-        side[v] = part[v] == a ? 0 : part[v] == b ? 1 : -1;
-        dist[v] = -1;
-        if (side[v] >= 0) ++cnt[side[v]];
+    for (int64_t i = 0; i < nn; ++i) {
+        int32_t v = nodes[i];
+        side[v] = part[v] == a ? 0 : 1;
+        ++cnt[side[v]];
     }
     /* gains, boundary, cut */
     int32_t head = 0, tail = 0;
-    for (int32_t v = 0; v < n; ++v) {
-        if (side[v] < 0) continue;
+    for (int64_t i = 0; i < nn; ++i) {
+        int32_t v = nodes[i];
         int boundary = 0;
         for (int64_t j = xadj[v]; j < xadj[v + 1]; ++j) {
             int32_t u = adj[j];
@@ -705,9 +794,15 @@ static void fm_pair(int32_t n, const int64_t *xadj, const int32_t *adj, const ui
             if (side[u] == side[v] && dist[u] < 0) { dist[u] = dist[v] + 1; bfs[tail++] = u; }
         }
     }
-    int32_t qn = 0;
-    for (int32_t v = 0; v < n; ++v)
-        if (side[v] >= 0 && dist[v] == 0) { status[v] = 1; list[qn++] = v; }
+    /* the queues start with the boundary */
+    W->q[0].n = W->q[1].n = 0;
+    for (int64_t i = 0; i < nn; ++i) {
+        int32_t v = nodes[i];
+        if (dist[v] == 0) {
+            status[v] = 1;
+            heap_push(&W->q[side[v]], gain[v], orc_mix64(run_seed ^ (uint64_t)v), v);
+        }
+    }
 
     int64_t w[2] = {wa, wb};
     int64_t best_imb = pair_imbalance(w[0], w[1], s, l), best_cut = cut;
@@ -717,18 +812,7 @@ static void fm_pair(int32_t n, const int64_t *xadj, const int32_t *adj, const ui
     int64_t since = 0, smaller = cnt[0] < cnt[1] ? cnt[0] : cnt[1];
     for (;;) {
         /* the top of each queue */
-        int32_t top[2] = {-1, -1};
-        uint64_t th[2] = {0, 0};
-        for (int32_t i = 0; i < qn; ++i) {
-            int32_t v = list[i];
-            if (status[v] != 1) continue;
-            uint64_t h = orc_mix64(run_seed ^ (uint64_t)v);
-            int sd = side[v];
-            if (top[sd] < 0 || entry_above(gain[v], h, v, gain[top[sd]], th[sd], top[sd])) {
-                top[sd] = v;
-                th[sd] = h;
-            }
-        }
+        int32_t top[2] = {heap_top(&W->q[0], status, gain), heap_top(&W->q[1], status, gain)};
         if (top[0] < 0 && top[1] < 0) break;
         int from;
         int overloaded = s * w[0] > l || s * w[1] > l;
@@ -738,7 +822,9 @@ static void fm_pair(int32_t n, const int64_t *xadj, const int32_t *adj, const ui
         } else if (top[0] < 0 || top[1] < 0) {
             from = top[0] < 0 ? 1 : 0;
         } else {                                         /* TopGain */
-            from = entry_above(gain[top[0]], th[0], top[0], gain[top[1]], th[1], top[1]) ? 0 : 1;
+            uint64_t h0 = orc_mix64(run_seed ^ (uint64_t)top[0]);
+            uint64_t h1 = orc_mix64(run_seed ^ (uint64_t)top[1]);
+            from = entry_above(gain[top[0]], h0, top[0], gain[top[1]], h1, top[1]) ? 0 : 1;
         }
         int32_t v = top[from];
         int to = 1 - from;
@@ -753,7 +839,9 @@ static void fm_pair(int32_t n, const int64_t *xadj, const int32_t *adj, const ui
             if (side[u] < 0 || status[u] == 2) continue;
             if (side[u] == to) gain[u] -= 2 * (int64_t)ew[j];
             else gain[u] += 2 * (int64_t)ew[j];
-            if (status[u] == 0 && dist[u] >= 0) { status[u] = 1; list[qn++] = u; }
+            if (status[u] == 0 && dist[u] >= 0) status[u] = 1;
+            if (status[u] == 1)
+                heap_push(&W->q[side[u]], gain[u], orc_mix64(run_seed ^ (uint64_t)u), u);
         }
         int64_t imb = pair_imbalance(w[0], w[1], s, l);
         if (state_below(imb, cut, best_imb, best_cut)) {
@@ -770,7 +858,13 @@ static void fm_pair(int32_t n, const int64_t *xadj, const int32_t *adj, const ui
     res[3] = best_cut;
     res[4] = m;
     res[5] = kept;
-    free(side); free(status); free(gain); free(dist); free(list); free(bfs);
+    for (int64_t i = 0; i < nn; ++i) {   /* leave the work arrays clean */
+        int32_t v = nodes[i];
+        side[v] = -1;
+        status[v] = 0;
+        gain[v] = 0;
+        dist[v] = -1;
+    }
 }
 
 static int refine_args_ok(int32_t k, uint32_t eps_num, uint32_t eps_den, uint32_t alpha_den,
@@ -808,8 +902,16 @@ int orc_fm_pair(int32_t n, const int64_t *xadj, const int32_t *adj, const uint32
         if (part[v] < 0 || part[v] >= k) return ORC_E_RANGE;
     int64_t *bw = (int64_t *)malloc((size_t)k * sizeof(int64_t)), s, l;
     refine_scale(n, vw, part, k, eps_num, eps_den, bw, &s, &l);
-    fm_pair(n, xadj, adj, ew, vw, part, a, b, bw[a], bw[b], s, l, run_seed, alpha_num, alpha_den,
-            depth, moves, res);
+    int32_t *nodes = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int64_t nn = 0;
+    for (int32_t v = 0; v < n; ++v)
+        if (part[v] == a || part[v] == b) nodes[nn++] = v;
+    fm_work W;
+    fm_work_init(&W, n);
+    fm_pair(&W, xadj, adj, ew, vw, part, nodes, nn, a, b, bw[a], bw[b], s, l, run_seed, alpha_num,
+            alpha_den, depth, moves, res);
+    fm_work_free(&W);
+    free(nodes);
     free(bw);
     return ORC_OK;
 }
@@ -842,22 +944,44 @@ int orc_refine(int32_t n, const int64_t *xadj, const int32_t *adj, const uint32_
     int32_t *pb = (int32_t *)malloc(kk * sizeof(int32_t));
     int32_t *pc = (int32_t *)malloc(kk * sizeof(int32_t));
     int32_t *mv[2] = {(int32_t *)malloc(nn * sizeof(int32_t)), (int32_t *)malloc(nn * sizeof(int32_t))};
+    /* the nodes of every block, ascending (blocks a and b change together,
+       after an adoption in their pair) */
+    int32_t **bl = (int32_t **)calloc((size_t)k, sizeof(int32_t *));
+    int64_t *bn = (int64_t *)calloc((size_t)k, sizeof(int64_t));
+    int32_t *pnodes = (int32_t *)malloc(nn * sizeof(int32_t));
+    fm_work W;
+    fm_work_init(&W, n);
     int32_t idle = 0;
     for (int32_t g = 0; g < max_global; ++g) {
         int32_t np;
         int32_t ncol = orc_quotient_colouring(n, xadj, adj, part, k, pa, pb, pc, &np);
         stats[0] += 1;
         stats[5] += ncol;
+        for (int32_t i = 0; i < k; ++i) bn[i] = 0;
+        for (int32_t v = 0; v < n; ++v) ++bn[part[v]];
+        for (int32_t i = 0; i < k; ++i) {
+            bl[i] = (int32_t *)realloc(bl[i], (size_t)(bn[i] > 0 ? bn[i] : 1) * sizeof(int32_t));
+            bn[i] = 0;
+        }
+        for (int32_t v = 0; v < n; ++v) bl[part[v]][bn[part[v]]++] = v;
         int improved = 0;
         for (int32_t c = 0; c < ncol; ++c)
             for (int32_t p = 0; p < np; ++p) {
                 if (pc[p] != c) continue;
                 int32_t a = pa[p], b = pb[p];
                 for (int32_t t = 0; t < max_local; ++t) {
+                    /* the nodes of blocks a and b, in ascending id order */
+                    int64_t na = bn[a], nb = bn[b], nab = 0;
+                    {
+                        int64_t i = 0, j = 0;
+                        const int32_t *la = bl[a], *lb = bl[b];
+                        while (i < na || j < nb)
+                            pnodes[nab++] = (j >= nb || (i < na && la[i] < lb[j])) ? la[i++] : lb[j++];
+                    }
                     int64_t res[2][6];
                     for (int r = 0; r < 2; ++r)
-                        fm_pair(n, xadj, adj, ew, vw, part, a, b, bw[a], bw[b], s, l,
-                                orc_run_seed(seed, g, a, b, t, r), alpha_num, alpha_den, depth,
+                        fm_pair(&W, xadj, adj, ew, vw, part, pnodes, nab, a, b, bw[a], bw[b], s,
+                                l, orc_run_seed(seed, g, a, b, t, r), alpha_num, alpha_den, depth,
                                 mv[r], res[r]);
                     stats[1] += 2;
                     stats[2] += res[0][4] + res[1][4];
@@ -870,6 +994,14 @@ int orc_refine(int32_t n, const int64_t *xadj, const int32_t *adj, const uint32_
                         bw[to] += vw[v];
                         part[v] = to;
                     }
+                    /* the two blocks' node lists after the moves */
+                    bl[a] = (int32_t *)realloc(bl[a], (size_t)(nab > 0 ? nab : 1) * sizeof(int32_t));
+                    bl[b] = (int32_t *)realloc(bl[b], (size_t)(nab > 0 ? nab : 1) * sizeof(int32_t));
+                    bn[a] = bn[b] = 0;
+                    for (int64_t i = 0; i < nab; ++i) {
+                        int32_t v = pnodes[i];
+                        if (part[v] == a) bl[a][bn[a]++] = v; else bl[b][bn[b]++] = v;
+                    }
                     stats[3] += res[r][5];
                     stats[4] += 1;
                     improved = 1;
@@ -878,6 +1010,9 @@ int orc_refine(int32_t n, const int64_t *xadj, const int32_t *adj, const uint32_
         idle = improved ? 0 : idle + 1;
         if (idle >= stop_after) break;
     }
+    fm_work_free(&W);
+    for (int32_t i = 0; i < k; ++i) free(bl[i]);
+    free(bl); free(bn); free(pnodes);
     free(pa); free(pb); free(pc); free(mv[0]); free(mv[1]); free(bw);
     return ORC_OK;
 }

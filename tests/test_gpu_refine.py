@@ -158,25 +158,26 @@ def test_queue_entries_in_memory(qcap, monkeypatch):
             check_refine(g, part, k, "strong", seed=qcap, what=f"{name} k={k} qcap={qcap}")
 
 
-def test_full_size_refined_way_back_up_properties():
+@pytest.mark.timeout(600)
+def test_full_size_refined_way_back_up_equals_oracle():
     # the workload the benchmark times (rgg 2^20, expansion*2 hierarchy, k = 64,
-    # preset fast): the oracle cannot refine it in test time, so check what holds
-    # at any size against the oracle's cut/balance of the returned partition
+    # preset fast, refinement seed 1): the level-0 partition, every level's
+    # cut/balance and every level's search statistics against the oracle's
+    # way back up (about 40 s on one host core)
     g = rgg(1 << 20, seed=2)
     H = K.kappa_coarsen(dev(g), O.EXPANSION_STAR2, 42, 20 * 64)
-    part0, res, st = K.kappa_uncoarsen_refined(H, 64, 1, 3, 100, "fast", 1)
+    OH = O.coarsen(g, O.EXPANSION_STAR2, 42, 20 * 64)
+    parts, res, stats = O.uncoarsen_refined(OH, 64, 1, 3, 100, oracle_params("fast", 1))
+    part0, got, gst = K.kappa_uncoarsen_refined(H, 64, 1, 3, 100, "fast", 1)
+    assert np.array_equal(part0.cpu().numpy(), parts[0])
+    for l in range(len(res)):
+        assert got[l].as_tuple() == res[l].as_tuple(), l
+        for key in ("bytes", "init_ticks", "move_ticks"):
+            gst[l].pop(key)
+        assert gst[l] == stats[l], l
     _, plain = K.kappa_uncoarsen(H, 64, 1, 3, 100)
-    p = part0.cpu().numpy()
-    assert p.min() >= 0 and p.max() < 64
-    want = O.cut_balance(g, p, 64, 3, 100)
-    assert res[0].as_tuple() == want.as_tuple()
-    assert int(want.block_w.sum()) == g.n
-    # the coarsest level starts from the plain way back up's partition
-    assert (res[-1].imb_num, res[-1].cut) <= (plain[-1].imb_num, plain[-1].cut)
     assert res[0].cut < plain[0].cut // 2
-    for x in st:
-        assert x["kept"] <= x["moves"] and x["searches"] % 2 == 0 and x["global_iterations"] <= 15
-    say(f"rgg 2^20 k=64: cut {plain[0].cut} -> {res[0].cut}, levels {len(res)}")
+    say(f"rgg 2^20 k=64 fast: cut {plain[0].cut} -> {res[0].cut}, levels {len(res)}, equal to the oracle")
 
 
 def test_k256_random_partition():
