@@ -892,16 +892,22 @@ def bench_serve(args):
     """The served form: `--requests` requests of the served mix (|E|
     log-uniform in [1e3, 4e6]; grids, random geometric graphs and R-MAT;
     rating, k in {2, 8, 32, 64}, stop at 20 k, eps 3/100), generated before
-    the clock starts.  The plain path (one request at a time) is first run
-    with every request present to find its sustainable rate; then both paths
-    serve the same Poisson arrival trace at 0.7 of that rate.  Latency is
-    completion minus scheduled arrival; edges/s is all edges over first
-    arrival to last completion.  The saturated figures serve every request at
-    once (all present at the start) through both paths."""
+    the clock starts.  Three services: the plain path (one request at a time,
+    kappa_coarsen), request-granular batches (BatchServer: kappa_coarsen_graphs
+    per batch, two workers) and level-granular continuous batching
+    (LevelServer: kappa_server_*, one engine per rating).  The plain path is
+    first run with every request present to find its sustainable rate; then
+    every service serves the same Poisson arrival trace at 0.7 of that rate.
+    Latency is completion minus scheduled arrival; edges/s is all edges over
+    first arrival to last completion.  The saturated figures serve every
+    request at once (all present at the start).  `value` is the
+    level-granular server's."""
     import numpy as np
     import torch
 
-    from paper_0910_2004_amd.serve import BatchServer, Request, latency_stats, serve_plain
+    import paper_0910_2004_amd as K
+    from paper_0910_2004_amd.serve import (BatchServer, LevelServer, Request, latency_stats,
+                                           serve_plain)
     from workloads import serve_requests
 
     t0 = time.time()
@@ -910,21 +916,50 @@ def bench_serve(args):
         f"in {time.time() - t0:.1f}s")
     torch.cuda.set_device(0)
     reqs = [Request(i, g, rating, k) for i, (g, rating, k) in enumerate(mix)]
+    last = {}
+
+    def level_run(rs):
+        last["level"] = LevelServer()
+        return last["level"].run(rs)
+
+    def level_profile():   # per engine: steps, mean step time, mean active requests
+        out = {}
+        for (rating, seed, big), p in sorted(last["level"].profile.items()):
+            steps = max(p["steps"], 1)
+            out[f"rating{rating}_{'large' if big else 'small'}"] = {
+                "steps": p["steps"], "step_ms": round(1e3 * p["step_s"] / steps, 3),
+                "admit_ms": round(1e3 * p["admit_s"] / steps, 3),
+                "active": round(p["active_sum"] / steps, 2)}
+        return out
+
+    services = {"batch": lambda rs: BatchServer(workers=2).run(rs), "level": level_run}
     serve_plain(reqs[:32])   # warm up
-    BatchServer(workers=2).run(reqs[:32])
+    for run in services.values():
+        run(reqs[:32])
+    total_edges = sum(int(r.graph.m) for r in reqs)
     t1 = time.perf_counter()
     serve_plain(reqs)
     plain_s = time.perf_counter() - t1
     rate = len(reqs) / plain_s
-    total_edges = sum(int(r.graph.m) for r in reqs)
-    # saturated: every request present at once, served by the batching server
-    t1 = time.perf_counter()
-    BatchServer(workers=2).run(reqs)
-    served_s = time.perf_counter() - t1
-    saturated = {"plain_edges_per_s": round(total_edges / plain_s, 1),
-                 "served_edges_per_s": round(total_edges / served_s, 1),
-                 "plain_s": round(plain_s, 3), "served_s": round(served_s, 3),
-                 "speedup": round(plain_s / served_s, 2)}
+    saturated = {"plain_edges_per_s": round(total_edges / plain_s, 1), "plain_s": round(plain_s, 3)}
+    log(f"saturated plain: {plain_s:.2f} s")
+    def clean():   # every service starts from an empty device cache
+        torch.cuda.synchronize()
+        K.kappa_cache_release()
+        torch.cuda.empty_cache()
+
+    for name, run in services.items():   # every request present at once
+        clean()
+        t1 = time.perf_counter()
+        res = run(reqs)
+        sec = time.perf_counter() - t1
+        saturated[f"{name}_edges_per_s"] = round(total_edges / sec, 1)
+        saturated[f"{name}_s"] = round(sec, 3)
+        saturated[f"{name}_speedup"] = round(plain_s / sec, 2)
+        saturated[f"{name}_mean_batch"] = round(float(np.mean([r.batch for r in res])), 2)
+        log(f"saturated {name}: {sec:.2f} s")
+        if name == "level":
+            saturated["level_engines"] = level_profile()
     log(f"saturated: {saturated}")
     lam = 0.7 * rate
     gaps = np.random.default_rng(5).exponential(1.0 / lam, size=len(reqs))
@@ -932,10 +967,15 @@ def bench_serve(args):
     trace = [Request(r.rid, r.graph, r.rating, r.k, arrival=float(arrivals[i]))
              for i, r in enumerate(reqs)]
     log(f"plain path sustains {rate:.1f} req/s; trace at {lam:.1f} req/s")
-    plain = latency_stats(trace, serve_plain(trace))
-    log(f"plain: {plain}")
-    served = latency_stats(trace, BatchServer(workers=2).run(trace))
-    log(f"served: {served}")
+    stats = {"plain": latency_stats(trace, serve_plain(trace))}
+    log(f"plain: {stats['plain']}")
+    for name, run in services.items():
+        clean()
+        stats[name] = latency_stats(trace, run(trace))
+        if name == "level":
+            stats[name]["engines"] = level_profile()
+        log(f"{name}: {stats[name]}")
+    served = stats["level"]
     out = {
         "metric": "served coarsening: aggregate edges/s per GPU, p50/p99 latency",
         "value": served["edges_per_s"],
@@ -952,9 +992,11 @@ def bench_serve(args):
         "config": {"workload": "served mix: |E| log-uniform [1e3, 4e6], grid/rgg/rmat, "
                                "expansion*2 or innerOuter, k in {2,8,32,64}, stop 20k, "
                                "eps 3/100, Poisson arrivals at 0.7 x the plain path's rate",
-                   "requests": len(trace), "rate_req_s": round(lam, 2), "seed": 5},
+                   "requests": len(trace), "rate_req_s": round(lam, 2), "seed": 5,
+                   "server": "level-granular (kappa_server_*), one engine per rating"},
         "served": served,
-        "plain": plain,
+        "batch_granular": stats["batch"],
+        "plain": stats["plain"],
         "saturated": saturated,
     }
     print(json.dumps(out), flush=True)

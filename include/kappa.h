@@ -289,6 +289,49 @@ kappa_status kappa_batch_hierarchy(const kappa_batch *b, int32_t g, kappa_hierar
                                    kappa_stream_t stream);
 void kappa_batch_free(kappa_batch *b);
 
+/* Served form: level-granular continuous batching of coarsening requests.
+   A server holds the requests of one rating (p->rating, seed, stall rule and
+   max_levels apply to every request; p->stop_n is unused) on one stream.
+   kappa_server_step advances every active request in one batched pass over
+   the union of their current levels (the work of the batched form; each
+   graph with the tie-break seeds mix64(seed + level) of its own levels, so
+   that its hierarchy is the one kappa_coarsen gives it alone).  A step runs
+   level after level on the device and ends at the first level boundary at
+   which some request's hierarchy has ended (by a stop rule of Section 2 / 4)
+   or kappa_server_interrupt has been raised: requests join and leave the
+   active set at level boundaries, between steps.  Requests admitted since
+   the last step join it at their level 0.  Each request's levels stay on the
+   device (library memory) until its hierarchy is taken and freed.  All calls
+   but kappa_server_interrupt are synchronous on the server's stream and must
+   come from one thread at a time. */
+typedef struct kappa_server kappa_server;
+kappa_status kappa_server_create(const kappa_coarsen_params *p, kappa_server **out,
+                                 kappa_stream_t stream);
+/* Validates g (as kappa_validate, unless p->flags has KAPPA_COARSEN_TRUSTED),
+   copies it into library memory (the caller may free g afterwards) and adds
+   it to the active set with its own stop size; *id (host) names it. */
+kappa_status kappa_server_admit(kappa_server *v, const kappa_graph *g, int32_t stop_n,
+                                int64_t *id);
+int32_t kappa_server_active(const kappa_server *v);
+/* set != 0: the running step (or the next one) ends at its next level
+   boundary, e.g. because a request waits to be admitted; set = 0 clears the
+   request.  The flag stays as set until changed.  May be called from any
+   thread, also while a step runs. */
+kappa_status kappa_server_interrupt(kappa_server *v, int32_t set);
+/* One step for every active request (at least one level each, unless it
+   stops before its first).  finished (host, cap entries, may be NULL when cap
+   is 0) receives the ids of the requests whose hierarchy ended in this step;
+   *nfinished (host) their count (ids beyond cap are not listed but are
+   finished all the same). */
+kappa_status kappa_server_step(kappa_server *v, int64_t *finished, int32_t cap,
+                               int32_t *nfinished);
+/* The hierarchy of finished request id, as a library-owned kappa_hierarchy
+   (for kappa_hierarchy_level, kappa_uncoarsen, ...; per-level round counts
+   are 0: rounds are shared by a step).  KAPPA_E_ARG if id has not finished or
+   was taken already. */
+kappa_status kappa_server_take(kappa_server *v, int64_t id, kappa_hierarchy **out);
+void kappa_server_free(kappa_server *v);
+
 /* Stand-in for the initial partitioning of Section 4 (which runs external
    partitioners): part[x] = mix64(seed + x) mod k for x < n.  k in [1, 4096]. */
 kappa_status kappa_initial_partition(int32_t n, int32_t k, uint64_t seed, int32_t *part,

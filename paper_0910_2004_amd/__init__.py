@@ -6,7 +6,7 @@ does not touch the GPU; the first call loads the library and raises if it is
 missing (there is no CPU fallback).
 """
 from ._lib import (  # noqa: F401
-    Batch, DeviceGraph, Hierarchy, KappaError, LevelView, RATINGS, EXPANSION_STAR2, INNER_OUTER, WEIGHT,
+    Batch, DeviceGraph, Hierarchy, KappaError, Server, LevelView, RATINGS, EXPANSION_STAR2, INNER_OUTER, WEIGHT,
     EXPANSION, EXPANSION_STAR, STOP_NONE, STOP_SIZE, STOP_EMPTY, STOP_STALL, STOP_MAXLEVEL,
     OK, E_ARG, E_GRAPH, E_RANGE, E_NOMEM, E_CAPACITY, E_HIP,
     declared_functions, lib, status_str, union_csr,

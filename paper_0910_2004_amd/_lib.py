@@ -166,6 +166,13 @@ def lib():
         "kappa_coarsen_batch": (st, [ctypes.POINTER(c_graph), i32, P, P, ctypes.POINTER(c_params),
                                      ctypes.POINTER(P), P]),
         "kappa_coarsen_graphs": (st, [P, i32, P, ctypes.POINTER(c_params), ctypes.POINTER(P), P]),
+        "kappa_server_create": (st, [ctypes.POINTER(c_params), ctypes.POINTER(P), P]),
+        "kappa_server_admit": (st, [P, ctypes.POINTER(c_graph), i32, ctypes.POINTER(ctypes.c_int64)]),
+        "kappa_server_active": (i32, [P]),
+        "kappa_server_step": (st, [P, P, i32, ctypes.POINTER(i32)]),
+        "kappa_server_interrupt": (st, [P, i32]),
+        "kappa_server_take": (st, [P, ctypes.c_int64, ctypes.POINTER(P)]),
+        "kappa_server_free": (None, [P]),
         "kappa_batch_count": (i32, [P]),
         "kappa_batch_graph_info": (st, [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "kappa_batch_hierarchy": (st, [P, i32, ctypes.POINTER(P), P]),
@@ -550,6 +557,65 @@ def kappa_coarsen_graphs(graphs, rating: int = EXPANSION_STAR2, seed: int = 42, 
         sn.ctypes.data_as(ctypes.c_void_p) if sn is not None else None, ctypes.byref(p),
         ctypes.byref(h), _stream()))
     return Batch(h, graphs[0].xadj.device, None, count)
+
+
+class Server:
+    """Level-granular continuous batching (kappa_server_*): the requests of
+    one rating on one stream (the current stream when created).  admit()
+    takes a device graph (copied by the library) and returns an id; step()
+    advances every active request in one batched pass, up to the first level
+    boundary at which a request finishes or an interrupt() was raised, and
+    returns the ids that finished; take(id) gives a finished request's
+    Hierarchy.  One thread drives a server; interrupt() may come from any."""
+
+    def __init__(self, rating: int = EXPANSION_STAR2, seed: int = 42, stall_num: int = 1,
+                 stall_den: int = 20, max_levels: int = 64, trusted: bool = False, device="cuda"):
+        self.device = device
+        p = c_params(rating, seed & (2**64 - 1), 0, stall_num, stall_den, max_levels,
+                     COARSEN_TRUSTED if trusted else 0)
+        h = ctypes.c_void_p()
+        self.stream = _stream()
+        _check("kappa_server_create", lib().kappa_server_create(ctypes.byref(p), ctypes.byref(h),
+                                                                self.stream))
+        self.handle = h
+        self._fin = (ctypes.c_int64 * 4096)()
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().kappa_server_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    def admit(self, g: "DeviceGraph", stop_n: int) -> int:
+        rid = ctypes.c_int64()
+        _check("kappa_server_admit", lib().kappa_server_admit(self.handle, ctypes.byref(g.c()),
+                                                              int(stop_n), ctypes.byref(rid)))
+        return int(rid.value)
+
+    def active(self) -> int:
+        return int(lib().kappa_server_active(self.handle))
+
+    def interrupt(self, on: bool = True):
+        """Ask the running (or next) step to end at its next level boundary;
+        on=False clears the request.  Safe from any thread."""
+        _check("kappa_server_interrupt", lib().kappa_server_interrupt(self.handle, 1 if on else 0))
+
+    def step(self):
+        nf = ctypes.c_int32()
+        cap = max(1, self.active())   # no step finishes more requests than are active
+        if len(self._fin) < cap:
+            self._fin = (ctypes.c_int64 * cap)()
+        _check("kappa_server_step", lib().kappa_server_step(
+            self.handle, ctypes.cast(self._fin, ctypes.c_void_p), cap, ctypes.byref(nf)))
+        return [int(self._fin[i]) for i in range(nf.value)]
+
+    def take(self, rid: int) -> Hierarchy:
+        h = ctypes.c_void_p()
+        _check("kappa_server_take", lib().kappa_server_take(self.handle, ctypes.c_int64(rid),
+                                                            ctypes.byref(h)))
+        return Hierarchy(h, self.device)
 
 
 def kappa_initial_partition(n: int, k: int, seed: int, device="cuda"):

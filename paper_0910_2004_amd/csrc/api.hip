@@ -645,6 +645,7 @@ struct kappa_level {
     const uint32_t *vw = nullptr;
     int32_t *cmap = nullptr;   // to the next level
     int32_t *mate = nullptr;
+    const int32_t *gid = nullptr;   // batched levels: graph of each node
     int32_t rounds = 0, grid_rounds = 0;
     int64_t matched = 0;
     int32_t stop = KAPPA_STOP_NONE;
@@ -657,6 +658,7 @@ struct kappa_hierarchy {
     void *arena = nullptr;
     size_t arena_bytes = 0;
     Allocator al;   // the allocator of `arena`
+    std::vector<std::shared_ptr<void>> holds;   // served form: the step arenas its levels live in
     ~kappa_hierarchy() { give_arena(s, arena, arena_bytes, al); }
 };
 
@@ -667,6 +669,12 @@ struct BatchIn {
     int32_t count;
     const int32_t *node_off;   // host, count + 1
     const int32_t *stop_n;     // host, count
+    // served steps (BatchCtx): host arrays of count entries, the host flag
+    // (device-visible address) and the levels of the first launch batch
+    const uint64_t *gbase = nullptr;
+    const int32_t *lmax = nullptr;
+    const uint32_t *interrupt = nullptr;
+    int first_batch = 0;
 };
 // Per-graph results of the batched form.
 struct BatchOut {
@@ -713,6 +721,13 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
                 c.b.coarsest = cv.get<int32_t>(count);
                 c.b.reason = cv.get<int32_t>(count);
                 c.b.excl = cv.get<int32_t>(d0.n);
+                if (bi->gbase) {
+                    c.b.gbase = cv.get<uint64_t>(count);
+                    c.b.gseed = cv.get<uint64_t>(count);
+                    c.b.lmax = cv.get<int32_t>(count);
+                    c.b.stop_seen = cv.get<uint32_t>(1);
+                    c.b.interrupt = bi->interrupt;
+                }
                 bflag = cv.get<uint32_t>(1);
             }
         }))
@@ -769,6 +784,13 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
         HIPCHK(hipMemcpyAsync(noff0, bi->node_off, (size_t)(count + 1) * 4, hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync((void *)c.b.stop_n, bi->stop_n, (size_t)count * 4,
                               hipMemcpyHostToDevice, s));
+        if (bi->gbase) {
+            HIPCHK(hipMemcpyAsync((void *)c.b.gbase, bi->gbase, (size_t)count * 8,
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync((void *)c.b.lmax, bi->lmax, (size_t)count * 4,
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemsetAsync(c.b.stop_seen, 0, sizeof(uint32_t), s));
+        }
         HIPCHK(hipMemsetAsync(c.b.active, 1, (size_t)count, s));
         HIPCHK(hipMemsetAsync(c.b.coarsest, 0xff, (size_t)count * 4, s));
         HIPCHK(hipMemsetAsync(c.b.reason, 0, (size_t)count * 4, s));
@@ -791,6 +813,7 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     const int32_t n0 = d0.n;
     int first = (int)std::ceil(std::log(std::max(2.0, (double)n0 / std::max(1, p->stop_n))) /
                                std::log(1.0 / 0.6)) + 2;
+    if (bi && bi->first_batch > 0) first = bi->first_batch;
     int launched = 0, batch = std::max(1, std::min(first, maxl + 1));
     // The tail kernel is tried ahead of each level past level 0 whose size
     // estimate is near its limit; once the estimate is within twice the limit
@@ -894,6 +917,7 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
         L.vw = hl[l].vw;
         L.cmap = l + 1 < nl ? hl[l].cmap : nullptr;
         L.mate = hl[l].mate;
+        L.gid = hl[l].gid;
         L.rounds = hl[l].rounds;
         L.grid_rounds = hl[l].grid_rounds;
         L.matched = hl[l].matched;
@@ -1908,6 +1932,380 @@ extern "C" kappa_status kappa_uncoarsen_refined(const kappa_hierarchy *h, int32_
     }
     return KAPPA_OK;
 }
+
+// ===========================================================================
+// Served form: level-granular continuous batching.  The server holds the
+// requests of one rating on one stream.  A step advances every active request
+// by one level in one batched pass over the union of their current levels
+// (each graph with the tie-break seed of its own depth); requests admitted
+// since the last step join it at their level 0, and a request leaves as soon
+// as a stop rule ends its hierarchy.  Each request's levels stay on the device
+// in the step arenas that produced them, shared by the requests of a step.
+// ===========================================================================
+namespace {
+// One block of a request's levels (or of a step's union), released when the
+// last level carved from it is.  Taken from the allocator directly, not from
+// the stream's arena cache: a cached arena may be far larger than asked for,
+// and these blocks live as long as the requests holding them.
+struct SrvMem {
+    hipStream_t s = nullptr;
+    void *p = nullptr;
+    size_t bytes = 0;
+    Allocator al;
+    ~SrvMem() { dev_free(p, bytes, s, al); }
+};
+std::shared_ptr<SrvMem> srv_mem(hipStream_t s, size_t bytes) {
+    auto m = std::make_shared<SrvMem>();
+    m->s = s;
+    m->al = current_allocator();
+    m->bytes = std::max<size_t>(bytes, 256);
+    m->p = dev_alloc(m->bytes, s, m->al, "served level");
+    if (!m->p) return nullptr;
+    return m;
+}
+struct SrvLevel {
+    kappa_level lv;
+    std::vector<std::shared_ptr<void>> holds;
+};
+struct SrvReq {
+    int64_t id = 0;
+    int32_t stop_n = 0;
+    int32_t depth = 0;   // levels built below level 0
+    std::vector<SrvLevel> levels;   // the last one is the current level
+};
+}  // namespace
+
+struct kappa_server {
+    hipStream_t s = nullptr;
+    kappa_coarsen_params p{};
+    std::vector<std::unique_ptr<SrvReq>> active, done;
+    int64_t next_id = 0;
+    uint32_t *interrupt = nullptr;       // host memory, coherent with the device
+    const uint32_t *interrupt_dev = nullptr;
+    ~kappa_server() {
+        if (interrupt) (void)hipHostFree(interrupt);
+    }
+};
+
+extern "C" kappa_status kappa_server_create(const kappa_coarsen_params *p, kappa_server **out,
+                                            kappa_stream_t stream) {
+    if (!out) return KAPPA_E_ARG;
+    *out = nullptr;
+    if (!params_ok(p, false)) return KAPPA_E_ARG;
+    std::unique_ptr<kappa_server> v(new (std::nothrow) kappa_server());
+    if (!v) return KAPPA_E_NOMEM;
+    v->s = S(stream);
+    v->p = *p;
+    if (hipHostMalloc((void **)&v->interrupt, sizeof(uint32_t), hipHostMallocCoherent) != hipSuccess)
+        return KAPPA_E_NOMEM;
+    __atomic_store_n(v->interrupt, 0u, __ATOMIC_RELEASE);
+    void *dp = nullptr;
+    HIPCHK(hipHostGetDevicePointer(&dp, v->interrupt, 0));
+    v->interrupt_dev = (const uint32_t *)dp;
+    *out = v.release();
+    return KAPPA_OK;
+}
+
+extern "C" kappa_status kappa_server_interrupt(kappa_server *v, int32_t set) {
+    if (!v) return KAPPA_E_ARG;
+    __atomic_store_n(v->interrupt, set ? 1u : 0u, __ATOMIC_RELEASE);
+    return KAPPA_OK;
+}
+
+extern "C" kappa_status kappa_server_admit(kappa_server *v, const kappa_graph *g, int32_t stop_n,
+                                           int64_t *id) {
+    if (!v || !id || !graph_args_ok(g)) return KAPPA_E_ARG;
+    hipStream_t s = v->s;
+    const DevGraph d = dev(g);
+    int32_t maxdeg = 0;
+    kappa_status st = validate_impl(d, s, &maxdeg, (v->p.flags & KAPPA_COARSEN_TRUSTED) != 0);
+    if (st != KAPPA_OK) return st;
+    // the request's level 0: a copy in the library's memory
+    int64_t *xadj = nullptr;
+    int32_t *adj = nullptr;
+    uint32_t *ew = nullptr, *vw = nullptr;
+    auto layout = [&](Carve &cv) {
+        xadj = cv.get<int64_t>((int64_t)d.n + 1);
+        adj = cv.get<int32_t>(d.nnz);
+        ew = cv.get<uint32_t>(d.nnz);
+        vw = cv.get<uint32_t>(d.n);
+    };
+    Carve lay;
+    layout(lay);
+    auto m = srv_mem(s, lay.off);
+    if (!m) return KAPPA_E_NOMEM;
+    Carve real;
+    real.base = (char *)m->p;
+    layout(real);
+    HIPCHK(hipMemcpyAsync(xadj, d.xadj, 8 * ((size_t)d.n + 1), hipMemcpyDeviceToDevice, s));
+    if (d.nnz > 0) {
+        HIPCHK(hipMemcpyAsync(adj, d.adj, 4 * (size_t)d.nnz, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(ew, d.ew, 4 * (size_t)d.nnz, hipMemcpyDeviceToDevice, s));
+    }
+    if (d.n > 0) HIPCHK(hipMemcpyAsync(vw, d.vw, 4 * (size_t)d.n, hipMemcpyDeviceToDevice, s));
+    std::unique_ptr<SrvReq> r(new (std::nothrow) SrvReq());
+    if (!r) return KAPPA_E_NOMEM;
+    r->id = v->next_id++;
+    r->stop_n = stop_n;
+    SrvLevel l0;
+    l0.lv.n = d.n;
+    l0.lv.nnz = d.nnz;
+    l0.lv.maxdeg = maxdeg;
+    l0.lv.xadj = xadj;
+    l0.lv.adj = adj;
+    l0.lv.ew = ew;
+    l0.lv.vw = vw;
+    l0.holds.push_back(m);
+    r->levels.push_back(std::move(l0));
+    *id = r->id;
+    v->active.push_back(std::move(r));
+    return KAPPA_OK;
+}
+
+extern "C" int32_t kappa_server_active(const kappa_server *v) {
+    return v ? (int32_t)v->active.size() : 0;
+}
+
+namespace {
+// Levels the geometric shrink of 0.6 per level (the usual one on meshes)
+// needs to take n nodes to stop_n, plus one.
+int levels_to_stop(int64_t n, int32_t stop_n) {
+    const double r = std::max(1.0, (double)n / std::max(1, stop_n));
+    return (int)std::ceil(std::log(r) / std::log(1.0 / 0.6)) + 1;
+}
+
+// One step of the server (arguments checked).  Finished request ids go to
+// fin (host), at most cap of them are reported; *nfin gets how many finished.
+kappa_status server_step(kappa_server *v, int64_t *fin, int32_t cap, int32_t *nfin) {
+    hipStream_t s = v->s;
+    int32_t nf = 0;
+    auto finish = [&](std::unique_ptr<SrvReq> r) {
+        if (nf < cap && fin) fin[nf] = r->id;
+        ++nf;
+        v->done.push_back(std::move(r));
+    };
+    // requests at the last level allowed stop there (the size rule first, as
+    // at every level start; after a step it has been checked already)
+    {
+        std::vector<std::unique_ptr<SrvReq>> keep;
+        for (auto &r : v->active) {
+            if (r->depth >= v->p.max_levels) {
+                kappa_level &cur = r->levels.back().lv;
+                cur.stop = cur.n <= r->stop_n ? KAPPA_STOP_SIZE : KAPPA_STOP_MAXLEVEL;
+                finish(std::move(r));
+            } else {
+                keep.push_back(std::move(r));
+            }
+        }
+        v->active.swap(keep);
+    }
+    const int32_t count = (int32_t)v->active.size();
+    *nfin = nf;
+    if (count == 0) return KAPPA_OK;
+    // the union of the current levels
+    std::vector<int64_t> off(2 * ((size_t)count + 1), 0);
+    int64_t *noff = off.data(), *eoff = off.data() + count + 1;
+    std::vector<UnionSrc> src(count);
+    std::vector<int32_t> stop(count), lmax(count);
+    std::vector<uint64_t> gbase(count);
+    int32_t maxdeg = 0, maxl = 1, first = 64;
+    for (int32_t g = 0; g < count; ++g) {
+        const SrvReq &r = *v->active[g];
+        const kappa_level &cur = r.levels.back().lv;
+        noff[g + 1] = noff[g] + cur.n;
+        eoff[g + 1] = eoff[g] + cur.nnz;
+        src[g] = UnionSrc{cur.xadj, cur.adj, cur.ew, cur.vw};
+        stop[g] = r.stop_n;
+        gbase[g] = v->p.seed + (uint64_t)r.depth;
+        lmax[g] = v->p.max_levels - r.depth;
+        maxl = std::max(maxl, lmax[g]);
+        first = std::min(first, std::min(lmax[g], levels_to_stop(cur.n, r.stop_n)));
+        maxdeg = std::max(maxdeg, cur.maxdeg);
+    }
+    const int64_t n = noff[count], nnz = eoff[count];
+    if (n > INT32_MAX) return KAPPA_E_ARG;
+    std::vector<int32_t> node_off(count + 1);
+    for (int32_t g = 0; g <= count; ++g) node_off[g] = (int32_t)noff[g];
+    int64_t *uxadj = nullptr;
+    int32_t *uadj = nullptr;
+    uint32_t *uew = nullptr, *uvw = nullptr;
+    auto ulayout = [&](Carve &cv) {
+        uxadj = cv.get<int64_t>(n + 1);
+        uadj = cv.get<int32_t>(nnz);
+        uew = cv.get<uint32_t>(nnz);
+        uvw = cv.get<uint32_t>(n);
+    };
+    Carve ulay;
+    ulayout(ulay);
+    auto um = srv_mem(s, ulay.off);
+    if (!um) return KAPPA_E_NOMEM;
+    Carve ureal;
+    ureal.base = (char *)um->p;
+    ulayout(ureal);
+    {
+        UnionSrc *dsrc = nullptr;
+        int64_t *doff = nullptr;
+        std::unique_ptr<Workspace> w;
+        if (!carve_workspace(s, w, [&](Carve &cv) {
+                dsrc = cv.get<UnionSrc>(count);
+                doff = cv.get<int64_t>(2 * ((int64_t)count + 1));
+            }))
+            return KAPPA_E_NOMEM;
+        HIPCHK(hipMemcpyAsync(dsrc, src.data(), sizeof(UnionSrc) * count, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(doff, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice,
+                              s));
+        launch_union_build(dsrc, count, doff, doff + count + 1, n, nnz, uxadj, uadj, uew, uvw, s);
+        HIPCHK(hipGetLastError());
+    }
+    // levels of the batched form over the union, each graph with its own
+    // depth's seeds and level cap, up to the first level boundary at which a
+    // graph stops or the host interrupts the step
+    kappa_coarsen_params pp = v->p;
+    pp.max_levels = maxl;
+    pp.flags |= KAPPA_COARSEN_TRUSTED;   // every request was validated when it was admitted
+    BatchIn bi{count, node_off.data(), stop.data()};
+    bi.gbase = gbase.data();
+    bi.lmax = lmax.data();
+    bi.interrupt = v->interrupt_dev;
+    bi.first_batch = std::max(1, first);
+    kappa_hierarchy UH;
+    UH.s = s;
+    BatchOut bo;
+    const DevGraph d0{(int32_t)n, nnz, uxadj, uadj, uew, uvw};
+    const uint64_t lvl0 = (uint64_t)n * 28 + (uint64_t)nnz * 8 + (uint64_t)(count + 1) * 8 + 8192;
+    uint64_t arena = (maxdeg > BIN_MID_MAX ? 8 : 3) * lvl0 + (1u << 20);
+    bool hubs = 2 * (int64_t)maxdeg - 2 > ROW_MID_MAX / 8;
+    kappa_status st = KAPPA_OK;
+    for (int attempt = 0; attempt < 6; ++attempt) {
+        uint32_t retry = 0;
+        st = coarsen_attempt(d0, maxdeg, &pp, s, &arena, false, hubs, &bi, &UH, &bo, &retry);
+        if (st == KAPPA_OK || !retry) break;
+        if (retry & CF_ARENA) arena *= 4;
+        if (retry & CF_HUBS) hubs = true;
+    }
+    if (st != KAPPA_OK) return st;
+    // every union level built, per graph with local ids, in one step block:
+    // level j's row offsets, entries, node weights, the cmap of level j - 1,
+    // and per graph its first entry and largest degree on level j
+    const int J = (int)UH.levels.size() - 1;
+    struct XL {
+        int64_t *xadj = nullptr;
+        int32_t *adj = nullptr, *cmap = nullptr, *noff = nullptr;
+        uint32_t *ew = nullptr, *vw = nullptr;
+    };
+    std::vector<XL> xl(J + 1);
+    int64_t *info = nullptr;   // per level j >= 1: eoff[count + 1], then dmax[count] as int32
+    const int64_t info_words = (int64_t)count + 1 + ((int64_t)count + 1) / 2;
+    std::shared_ptr<SrvMem> xm;
+    std::vector<int64_t> hinfo;
+    if (J >= 1) {
+        auto xlayout = [&](Carve &cv) {
+            for (int j = 1; j <= J; ++j) {
+                const kappa_level &U = UH.levels[j], &P = UH.levels[j - 1];
+                xl[j].xadj = cv.get<int64_t>((int64_t)U.n + count);
+                xl[j].adj = cv.get<int32_t>(U.nnz);
+                xl[j].ew = cv.get<uint32_t>(U.nnz);
+                xl[j].vw = cv.get<uint32_t>(U.n);
+                xl[j - 1].cmap = cv.get<int32_t>(P.n);
+                xl[j].noff = cv.get<int32_t>((int64_t)count + 1);
+            }
+            info = cv.get<int64_t>(info_words * J);
+        };
+        Carve xlay;
+        xlayout(xlay);
+        xm = srv_mem(s, xlay.off);
+        if (!xm) return KAPPA_E_NOMEM;
+        Carve xreal;
+        xreal.base = (char *)xm->p;
+        xlayout(xreal);
+        ZeroRanges z;
+        z.add(info, (size_t)(2 * info_words * J));
+        launch_zero(z, s);
+        for (int j = 1; j <= J; ++j) {
+            const kappa_level &U = UH.levels[j], &P = UH.levels[j - 1];
+            HIPCHK(hipMemcpyAsync(xl[j].noff, bo.noff[j].data(), 4 * ((size_t)count + 1),
+                                  hipMemcpyHostToDevice, s));
+            DevGraph u{U.n, U.nnz, U.xadj, U.adj, U.ew, U.vw};
+            u.gid = U.gid;
+            int64_t *ij = info + info_words * (j - 1);
+            launch_serve_extract(u, xl[j].noff, count, P.cmap, P.gid, P.n, xl[j].xadj, xl[j].adj,
+                                 xl[j].ew, xl[j].vw, xl[j - 1].cmap, ij, (int32_t *)(ij + count + 1),
+                                 s);
+            HIPCHK(hipGetLastError());
+        }
+        hinfo.resize((size_t)info_words * J);
+        HIPCHK(hipMemcpyAsync(hinfo.data(), info, 8 * hinfo.size(), hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    for (int32_t g = 0; g < count; ++g) {   // every graph ended the step somewhere
+        const int32_t c = bo.coarsest[g], why = bo.reason[g];
+        if (c < 0 || c > J || (c == 0 && why == KAPPA_STOP_NONE)) return KAPPA_E_HIP;
+    }
+    std::vector<std::unique_ptr<SrvReq>> keep;
+    for (int32_t g = 0; g < count; ++g) {
+        std::unique_ptr<SrvReq> r = std::move(v->active[g]);
+        const int32_t c = bo.coarsest[g], why = bo.reason[g];
+        for (int j = 1; j <= c; ++j) {
+            const int32_t a = bo.noff[j][g], b = bo.noff[j][g + 1];
+            const int64_t *ij = hinfo.data() + (size_t)info_words * (j - 1);
+            const int32_t *dmax = (const int32_t *)(ij + count + 1);
+            SrvLevel &cur = r->levels.back();
+            cur.lv.cmap = xl[j - 1].cmap + bo.noff[j - 1][g];
+            cur.lv.matched = (int64_t)cur.lv.n - (b - a);
+            cur.holds.push_back(xm);
+            SrvLevel nx;
+            nx.lv.n = b - a;
+            nx.lv.nnz = ij[g + 1] - ij[g];
+            nx.lv.maxdeg = dmax[g];
+            nx.lv.xadj = xl[j].xadj + a + g;
+            nx.lv.adj = xl[j].adj + ij[g];
+            nx.lv.ew = xl[j].ew + ij[g];
+            nx.lv.vw = xl[j].vw + a;
+            nx.holds.push_back(xm);
+            r->levels.push_back(std::move(nx));
+        }
+        r->depth += c;
+        if (why == KAPPA_STOP_NONE) {   // the step ended before its hierarchy did
+            keep.push_back(std::move(r));
+        } else {
+            r->levels.back().lv.stop = why;
+            finish(std::move(r));
+        }
+    }
+    v->active.swap(keep);
+    *nfin = nf;
+    return KAPPA_OK;
+}
+}  // namespace
+
+extern "C" kappa_status kappa_server_step(kappa_server *v, int64_t *finished, int32_t cap,
+                                          int32_t *nfinished) {
+    if (!v || !nfinished || cap < 0 || (cap > 0 && !finished)) return KAPPA_E_ARG;
+    *nfinished = 0;
+    return server_step(v, finished, cap, nfinished);
+}
+
+extern "C" kappa_status kappa_server_take(kappa_server *v, int64_t id, kappa_hierarchy **out) {
+    if (!v || !out) return KAPPA_E_ARG;
+    *out = nullptr;
+    for (size_t i = 0; i < v->done.size(); ++i) {
+        if (v->done[i]->id != id) continue;
+        std::unique_ptr<SrvReq> r = std::move(v->done[i]);
+        v->done.erase(v->done.begin() + (ptrdiff_t)i);
+        kappa_hierarchy *H = new (std::nothrow) kappa_hierarchy();
+        if (!H) return KAPPA_E_NOMEM;
+        H->s = v->s;
+        for (auto &l : r->levels) {
+            H->levels.push_back(l.lv);
+            for (auto &h : l.holds) H->holds.push_back(h);
+        }
+        *out = H;
+        return KAPPA_OK;
+    }
+    return KAPPA_E_ARG;   // not finished, or already taken
+}
+
+extern "C" void kappa_server_free(kappa_server *v) { delete v; }
 
 extern "C" kappa_status kappa_cache_release(void) {
     HIPCHK(hipDeviceSynchronize());

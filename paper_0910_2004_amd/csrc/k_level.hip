@@ -292,6 +292,13 @@ __device__ __forceinline__ uint64_t level_seed(const Ctx &c, int l) {
     return c.seed_direct ? c.seed : mix64(c.seed + (uint64_t)l);
 }
 
+// The tie-break seed of v's graph: in a served step every graph carries the
+// seed of its own hierarchy level, which differs from the union's level.
+__device__ __forceinline__ uint64_t row_seed(const Ctx &c, const DevGraph &g, int32_t v,
+                                             uint64_t seed) {
+    return (c.b.gseed && g.gid) ? c.b.gseed[g.gid[v]] : seed;
+}
+
 // Block-aggregated append of up to MK entries per thread into the three bin
 // lists `ol` (bin < 0: none); counters cnt[3] may be global or LDS.  Every
 // thread of the block calls it; sh: BLOCK/WAVE + 1 (blockDim.x/WAVE + 1)
@@ -490,7 +497,8 @@ __device__ __forceinline__ void pick_bin0(const Ctx &c, const DevGraph &g, uint6
                 }
             }
         }
-        Cand cd = act ? scan_row_small<R, G, FIRST, F>(g, v, av, sub, rb, re, nrec, out, seed,
+        Cand cd = act ? scan_row_small<R, G, FIRST, F>(g, v, av, sub, rb, re, nrec, out,
+                                                       row_seed(c, g, v, seed),
                                                        local_base(g, v), gv)
                       : cand_none();
         cd = group_reduce<G>(cd, v);
@@ -515,7 +523,8 @@ __device__ __forceinline__ void pick_bin1(const Ctx &c, const DevGraph &g, uint6
         const int32_t v = checked_node(ri.in[1].v[i], g.n, c.ctrl);
         if (v < 0 || (!FIRST && keeps_choice(ri.in[1].b[i], g.n, nrec))) continue;   // wave-uniform
         const uint32_t av = FIRST ? attr_src<R>(g, out, v) : (uint32_t)nrec[v].x;
-        Cand cd = scan_row<R, WAVE, FIRST, F>(g, v, av, lane_id(), nrec, out, seed, local_base(g, v),
+        Cand cd = scan_row<R, WAVE, FIRST, F>(g, v, av, lane_id(), nrec, out, row_seed(c, g, v, seed),
+                                              local_base(g, v),
                                               gv);
         cd = group_reduce<WAVE>(cd, v);
         if (lane_id() == 0) {
@@ -537,7 +546,7 @@ __device__ __forceinline__ void pick_bin2(const Ctx &c, const DevGraph &g, uint6
         const int32_t v = checked_node(ri.in[2].v[i], g.n, c.ctrl);
         if (v < 0 || (!FIRST && keeps_choice(ri.in[2].b[i], g.n, nrec))) continue;   // block-uniform
         const uint32_t av = FIRST ? attr_src<R>(g, out, v) : (uint32_t)nrec[v].x;
-        Cand cd = scan_row<R, NT, FIRST, F>(g, v, av, threadIdx.x, nrec, out, seed,
+        Cand cd = scan_row<R, NT, FIRST, F>(g, v, av, threadIdx.x, nrec, out, row_seed(c, g, v, seed),
                                             local_base(g, v), gv);
         cd = block_reduce_cand(cd, v, sh);
         if (threadIdx.x == 0) {
@@ -577,7 +586,8 @@ __device__ __forceinline__ void pick_scan0(const Ctx &c, const DevGraph &g, uint
                 if (re - rb > BIN_SMALL_MAX) re = rb + BIN_SMALL_MAX;   // valid lists never
             }
         }
-        Cand cd = act ? scan_row_small<R, G, false>(g, e.x, av, sub, rb, re, nrec, nullptr, seed,
+        Cand cd = act ? scan_row_small<R, G, false>(g, e.x, av, sub, rb, re, nrec, nullptr,
+                                                    row_seed(c, g, e.x, seed),
                                                     local_base(g, e.x), gv)
                       : cand_none();
         cd = group_reduce<G>(cd, e.x);
@@ -599,7 +609,7 @@ __device__ __forceinline__ void pick_scan1(const Ctx &c, const DevGraph &g, uint
         const int2 e = ri.scan[1][i];
         if ((uint32_t)e.x >= (uint32_t)g.n || (uint32_t)e.y >= (uint32_t)ri.cn[1]) continue;
         const uint32_t av = (uint32_t)nrec[e.x].x;
-        Cand cd = scan_row<R, WAVE, false>(g, e.x, av, lane_id(), nrec, nullptr, seed,
+        Cand cd = scan_row<R, WAVE, false>(g, e.x, av, lane_id(), nrec, nullptr, row_seed(c, g, e.x, seed),
                                            local_base(g, e.x), gv);
         cd = group_reduce<WAVE>(cd, e.x);
         if (lane_id() == 0) {
@@ -633,6 +643,7 @@ __device__ __forceinline__ void pick_bin2_chunks(const Ctx &c, const DevGraph &g
         const int64_t j1 = min(re, j0 + HUB_CHUNK);
         const uint32_t av = FIRST ? attr_src<R>(g, out, v) : (uint32_t)nrec[v].x;
         const int32_t base = local_base(g, v);
+        const uint64_t sv = row_seed(c, g, v, seed);
         // T entries per thread, strided by the block for coalesced row loads
         int32_t u[T];
         uint32_t w[T], au[T];
@@ -660,7 +671,7 @@ __device__ __forceinline__ void pick_bin2_chunks(const Ctx &c, const DevGraph &g
             if (!ok[t]) continue;
             Cand e;
             rate<R>(w[t], au[t], av, au[t], av, e.num, e.den);
-            e.h = mix64(seed ^ edge_id_local(v, u[t], base));
+            e.h = mix64(sv ^ edge_id_local(v, u[t], base));
             e.u = u[t];
             if (cand_better(e, cd, v)) cd = e;
         }
@@ -2390,32 +2401,57 @@ __global__ void __launch_bounds__(TAIL_THREADS) tail_k(Ctx c, int l0) {
 constexpr int BATCH_THREADS = 1024;
 
 __global__ void __launch_bounds__(BATCH_THREADS) batch_begin_k(Ctx c, int l) {
-    __shared__ int any;
+    __shared__ int any, stopped, cut;
     Control *ctrl = c.ctrl;
     LevelDesc *L = c.lv + l;
     if (ctrl->done || ctrl->nlevels != l + 1 || L->phase != PH_IDLE) return;   // same for all
-    if (threadIdx.x == 0) any = 0;
+    if (threadIdx.x == 0) {
+        any = 0;
+        stopped = 0;
+    }
     __syncthreads();
     const int32_t *noff = L->noff;
     const int32_t maxl = ctrl->max_levels;
-    bool mine = false;
+    bool mine = false, st = false;
     for (int g = threadIdx.x; g < c.b.count; g += blockDim.x) {
         if (!c.b.active[g]) continue;
         const int32_t ng = noff[g + 1] - noff[g];
+        const int32_t lim = c.b.lmax ? c.b.lmax[g] : maxl;
         int32_t stop = KAPPA_STOP_NONE;
         if (ng <= c.b.stop_n[g]) stop = KAPPA_STOP_SIZE;
-        else if (l >= maxl) stop = KAPPA_STOP_MAXLEVEL;
+        else if (l >= lim) stop = KAPPA_STOP_MAXLEVEL;
         if (stop != KAPPA_STOP_NONE) {
             c.b.active[g] = 0;
             c.b.coarsest[g] = l;
             c.b.reason[g] = stop;
+            st = true;
         } else {
             mine = true;
+            if (c.b.gbase) c.b.gseed[g] = mix64(c.b.gbase[g] + (uint64_t)l);
         }
     }
     if (mine) any = 1;
+    if (st) stopped = 1;
     __syncthreads();
-    if (threadIdx.x == 0 && !any) {   // every graph has stopped: so does the union
+    // a served step ends here if a graph has stopped in it or the host asks
+    // for a boundary (one read of each flag, shared by the block)
+    if (threadIdx.x == 0) {
+        cut = 0;
+        if (c.b.stop_seen && l > 0 && any)
+            cut = stopped || *c.b.stop_seen ||
+                  (c.b.interrupt &&
+                   __hip_atomic_load(c.b.interrupt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+    }
+    __syncthreads();
+    if (cut) {
+        for (int g = threadIdx.x; g < c.b.count; g += blockDim.x) {
+            if (!c.b.active[g]) continue;
+            c.b.active[g] = 0;
+            c.b.coarsest[g] = l;
+            c.b.reason[g] = KAPPA_STOP_NONE;   // goes on in the next step
+        }
+    }
+    if (threadIdx.x == 0 && (!any || cut)) {   // every graph has stopped: so does the union
         L->stop = KAPPA_STOP_SIZE;
         L->phase = PH_STOPPED;
         ctrl->done = 1;
@@ -2438,11 +2474,13 @@ __global__ void __launch_bounds__(BATCH_THREADS) batch_end_k(Ctx c, int l) {
             c.b.active[g] = 0;
             c.b.coarsest[g] = l;
             c.b.reason[g] = KAPPA_STOP_EMPTY;
+            if (c.b.stop_seen) *c.b.stop_seen = 1;
         } else if (c.b.stall_num > 0 &&
                    (uint64_t)(ng - ngc) * c.b.stall_den < (uint64_t)c.b.stall_num * (uint64_t)ng) {
             c.b.active[g] = 0;
             c.b.coarsest[g] = l + 1;
             c.b.reason[g] = KAPPA_STOP_STALL;
+            if (c.b.stop_seen) *c.b.stop_seen = 1;
         }
     }
 }
@@ -2488,6 +2526,74 @@ __global__ void batch_extract_k(DevGraph u, const int32_t *cmap, const int32_t *
         adj[j] = u.adj[ea + j] - a;
         ew[j] = u.ew[ea + j];
     }
+}
+
+// Served steps: level j of every graph of a step's union, with ids made
+// local, in one pass (and each graph's largest degree there, in dmax, which
+// starts at zero).  Graph g's arrays keep their place in the union
+// (nodes from noff1[g], entries from the union's offsets); its row offsets
+// need one slot more per graph, so they start at noff1[g] + g.  cmap of the
+// union's level j - 1 is made local as well (-1 for nodes of graphs that
+// stopped).
+__global__ void __launch_bounds__(BLOCK) serve_extract_k(DevGraph u1, const int32_t *noff1,
+                                                         int32_t count, int64_t *xadj,
+                                                         int32_t *adj, uint32_t *ew,
+                                                         uint32_t *vw, int32_t *dmax) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = t0; i < u1.n; i += stride) {
+        const int32_t g = u1.gid[i];
+        const int32_t a = noff1[g];
+        const int64_t e0 = u1.xadj[a];
+        const int64_t x = u1.xadj[i];
+        xadj[i + g] = x - e0;
+        vw[i] = u1.vw[i];
+        const int32_t d = (int32_t)(u1.xadj[i + 1] - x);
+        if (d > 0) atomicMax(&dmax[g], d);
+    }
+    for (int64_t g = t0; g < count; g += stride) {   // each graph's closing offset
+        const int32_t a = noff1[g], b = noff1[g + 1];
+        xadj[(int64_t)b + g] = u1.xadj[b] - u1.xadj[a];
+    }
+    for (int64_t j = t0; j < u1.nnz; j += stride) {
+        const int32_t w = u1.adj[j];
+        adj[j] = w - noff1[u1.gid[w]];
+        ew[j] = u1.ew[j];
+    }
+}
+
+__global__ void __launch_bounds__(BLOCK) serve_cmap_k(const int32_t *cmap0, const int32_t *gid0,
+                                                      int32_t n0, const int32_t *noff1,
+                                                      int32_t *cmap) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n0;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t x = cmap0[i];
+        cmap[i] = x >= 0 ? x - noff1[gid0[i]] : -1;
+    }
+}
+
+// The first entry of every graph on a level: e[g] = xadj[noff[g]], g <= count.
+__global__ void __launch_bounds__(BLOCK) serve_eoff_k(const int64_t *xadj, const int32_t *noff,
+                                                      int32_t count, int64_t *e) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g <= count;
+         g += (int64_t)gridDim.x * blockDim.x)
+        e[g] = xadj[noff[g]];
+}
+
+void launch_serve_extract(const DevGraph &u1, const int32_t *noff1, int32_t count,
+                          const int32_t *cmap0, const int32_t *gid0, int32_t n0, int64_t *xadj,
+                          int32_t *adj, uint32_t *ew, uint32_t *vw, int32_t *cmap, int64_t *eoff1,
+                          int32_t *dmax, hipStream_t s) {
+    KAPPA_PROF("serve_extract", s);
+    const int64_t items = std::max<int64_t>(std::max<int64_t>(u1.n, u1.nnz), count + 1);
+    if (u1.n > 0 || count > 0)
+        hipLaunchKernelGGL(serve_extract_k, dim3(grid_for(items, BLOCK * 4, 4096)), dim3(BLOCK), 0, s,
+                           u1, noff1, count, xadj, adj, ew, vw, dmax);
+    if (n0 > 0)
+        hipLaunchKernelGGL(serve_cmap_k, dim3(grid_for(n0, BLOCK * 4, 4096)), dim3(BLOCK), 0, s,
+                           cmap0, gid0, n0, noff1, cmap);
+    hipLaunchKernelGGL(serve_eoff_k, dim3(grid_for(count + 1, BLOCK, 64)), dim3(BLOCK), 0, s,
+                       u1.xadj, noff1, count, eoff1);
 }
 
 // Union of separate graphs (kappa_coarsen_graphs): graph g's nodes and

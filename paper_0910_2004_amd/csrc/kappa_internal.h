@@ -658,6 +658,18 @@ struct BatchCtx {
     int32_t *coarsest = nullptr;       // [count] level of the graph's coarsest graph
     int32_t *reason = nullptr;         // [count] kappa_stop of the graph
     int32_t *excl = nullptr;           // [n] exclusive prefix of the coarse-id scan
+    // Served steps (all null otherwise).  A graph of the union is somewhere
+    // down its own hierarchy: gbase[g] is the seed plus its depth, and every
+    // level start writes gseed[g] = mix64(gbase[g] + level); lmax[g] is how
+    // many levels it may still build.  The step ends at the first level
+    // boundary after a graph stopped (stop_seen, or a stop at that boundary)
+    // or the host raised *interrupt (host memory): graphs still coarsening
+    // get reason KAPPA_STOP_NONE there.
+    const uint64_t *gbase = nullptr;   // [count]
+    uint64_t *gseed = nullptr;         // [count]
+    const int32_t *lmax = nullptr;     // [count]
+    const uint32_t *interrupt = nullptr;
+    uint32_t *stop_seen = nullptr;
 };
 
 struct Ctx {
@@ -801,6 +813,14 @@ struct UnionSrc {
 void launch_union_build(const UnionSrc *src, int32_t count, const int64_t *noff,
                         const int64_t *eoff, int64_t n, int64_t nnz, int64_t *xadj, int32_t *adj,
                         uint32_t *ew, uint32_t *vw, hipStream_t s);
+// Served steps (a union advanced by one level): every graph's next level with
+// local ids (graph g's nodes at noff1[g], its row offsets at noff1[g] + g,
+// its entries where the union has them), level 0's map made local, and each
+// graph's first entry on the next level (eoff1, count + 1 values).
+void launch_serve_extract(const DevGraph &u1, const int32_t *noff1, int32_t count,
+                          const int32_t *cmap0, const int32_t *gid0, int32_t n0, int64_t *xadj,
+                          int32_t *adj, uint32_t *ew, uint32_t *vw, int32_t *cmap, int64_t *eoff1,
+                          int32_t *dmax, hipStream_t s);
 // Copies nodes [a, b) of union level u (entries from ea, nnz of them) with
 // ids made local; cmap/mate (may be null) shifted as well.
 void launch_batch_extract(const DevGraph &u, const int32_t *cmap, const int32_t *mate, int32_t a,

@@ -16,6 +16,11 @@ on the device; requests arriving meanwhile wait only for the next free worker
 and for device memory.  Each result keeps its hierarchy resident on the
 device when asked to, until BatchServer.release(result).
 
+`LevelServer` batches at level granularity instead (the library's
+kappa_server_*): every step advances all active requests of a rating by one
+level in one batched pass, requests join at the next step after they arrive,
+and each leaves as soon as its hierarchy ends.
+
 `serve_plain` is the reference service: one request at a time, in arrival
 order, through kappa_coarsen and kappa_uncoarsen.
 """
@@ -56,7 +61,8 @@ class Result:
     cut: tuple                  # level 0 cut/balance (kappa_cut_result fields)
     start: float                # when its batch started (trace clock)
     done: float                 # completion (trace clock)
-    batch: int                  # requests served together with it (itself included)
+    batch: float                # requests served together with it (itself included; the
+                                # level-granular server: their mean over its steps)
     hierarchy: object = None    # the device-resident hierarchy (keep=True)
 
     def latency(self, arrival: float) -> float:
@@ -252,6 +258,192 @@ class BatchServer:
                 pass
         for _ in threads:
             jobs.put(None)
+        for th in threads:
+            th.join()
+        if errors:
+            raise errors[0]
+        torch.cuda.synchronize()
+        return sorted(results, key=lambda q: q.rid)
+
+
+class LevelServer:
+    """Level-granular continuous batching over the library's servers
+    (kappa_server_*: K.Server).
+
+    Three kinds of host threads, each with its own HIP stream (a step runs
+    level after level on the device until some request finishes or the
+    uploader interrupts it because a request of its class waits):
+      * the uploader takes requests in arrival order while the device budget
+        allows (each is charged its estimated footprint until its result is
+        recorded), copies the graph to the device and validates it there;
+      * one engine per (rating, seed, size class) owns a server: it admits the
+        uploaded requests of its class (trusted: validated already) while its
+        active set stays within max_entries level-0 entries, then advances all
+        of its active requests together, one batched pass per level; a
+        request uploaded while a step runs joins at the next level boundary
+        (at its level 0), and a request whose hierarchy ends leaves at once;
+      * one finisher per engine runs the way back up (stand-in partition,
+        projection, cut and balance) of each finished request on its own
+        hierarchy and records the result, so that engines only step.
+    Requests with more than split_entries level-0 entries step in engines of
+    their own: a step lasts as long as its largest level, and small requests
+    would otherwise wait on the large ones at every level.  Result.batch is
+    the mean number of requests of the steps a request took part in."""
+
+    def __init__(self, device="cuda", hbm_budget: int = 200 << 30, max_active: int = 4096,
+                 max_entries: int = 1 << 27, split_entries: int = 1 << 18):
+        self.device = device
+        self.hbm_budget = hbm_budget
+        self.max_active = max_active
+        self.max_entries = max_entries
+        self.split_entries = split_entries
+        self.profile = {}   # engine class -> {"steps", "step_s", "admit_s", "active_sum"}
+
+    def _class(self, r: Request):
+        return (r.rating, r.seed, int(r.graph.nnz) > self.split_entries)
+
+    def run(self, requests: Sequence[Request], keep: bool = False,
+            t0: Optional[float] = None) -> List[Result]:
+        import torch
+        t0 = time.perf_counter() if t0 is None else t0
+        todo = sorted(requests, key=lambda q: q.arrival)
+        classes = sorted({self._class(r) for r in todo})
+        feeds = {c: queue.Queue() for c in classes}
+        done_q = {c: queue.Queue() for c in classes}
+        arrivals: queue.Queue = queue.Queue()
+        results: List[Result] = []
+        errors: List[BaseException] = []
+        lock = threading.Lock()
+        mem = threading.Condition()
+        charged = [0]
+        servers = {}   # class -> its engine's server, once created
+        dev_index = torch.device(self.device).index or 0
+
+        def fail(e):
+            with lock:
+                errors.append(e)
+            with mem:
+                mem.notify_all()
+
+        def uploader():
+            torch.cuda.set_device(dev_index)
+            stream = torch.cuda.Stream()
+            try:
+                with torch.cuda.stream(stream):
+                    while True:
+                        r = arrivals.get()
+                        if r is None:
+                            break
+                        fp = footprint(r.graph)
+                        with mem:   # wait for device memory (a lone request always fits)
+                            while not errors and charged[0] > 0 and charged[0] + fp > self.hbm_budget:
+                                mem.wait()
+                            charged[0] += fp
+                        if errors:
+                            break
+                        dg = K.DeviceGraph.from_csr(r.graph, self.device)
+                        st = K.kappa_validate(dg)
+                        if st != K.OK:
+                            raise K.KappaError("kappa_validate", st)
+                        cls = self._class(r)
+                        feeds[cls].put((r, dg))
+                        srv = servers.get(cls)
+                        if srv is not None:   # a running step ends at its next level boundary
+                            srv.interrupt(True)
+            except BaseException as e:
+                fail(e)
+            for c in classes:
+                feeds[c].put(None)
+
+        def finisher(cls):
+            torch.cuda.set_device(dev_index)
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                while True:
+                    item = done_q[cls].get()
+                    if item is None:
+                        break
+                    r, H, start, sizes = item
+                    try:
+                        res = _finish(r, H, t0, start, 1, keep)
+                        res.batch = float(sum(sizes)) / len(sizes)
+                        with lock:
+                            results.append(res)
+                    except BaseException as e:
+                        fail(e)
+                    del H
+                    with mem:
+                        charged[0] -= footprint(r.graph)
+                        mem.notify_all()
+
+        def engine(cls):
+            rating, seed, _ = cls
+            torch.cuda.set_device(dev_index)
+            stream = torch.cuda.Stream()
+            prof = {"steps": 0, "step_s": 0.0, "admit_s": 0.0, "active_sum": 0}
+            try:
+                with torch.cuda.stream(stream):
+                    srv = K.Server(rating, seed, trusted=True, device=self.device)
+                    servers[cls] = srv
+                    waiting: deque = deque()
+                    live = {}        # server id -> (request, start, [step sizes])
+                    entries = 0      # level-0 entries of the active set
+                    ended = False
+                    while not (ended and not waiting and not live) and not errors:
+                        srv.interrupt(False)   # before looking: no arrival goes unseen
+                        while not ended:   # uploaded requests (block only when idle)
+                            try:
+                                item = feeds[cls].get(block=not live and not waiting)
+                            except queue.Empty:
+                                break
+                            if item is None:
+                                ended = True
+                            else:
+                                waiting.append(item)
+                        ta = time.perf_counter()
+                        while waiting and len(live) < self.max_active:
+                            r, dg = waiting[0]
+                            if live and entries + int(r.graph.nnz) > self.max_entries:
+                                break
+                            waiting.popleft()
+                            for t in (dg.xadj, dg.adj, dg.ew, dg.vw):
+                                t.record_stream(stream)   # read by the admission copy
+                            sid = srv.admit(dg, r.stop)
+                            live[sid] = (r, time.perf_counter() - t0, [])
+                            entries += int(r.graph.nnz)
+                        prof["admit_s"] += time.perf_counter() - ta
+                        if not live:
+                            continue
+                        size = len(live)
+                        for v in live.values():
+                            v[2].append(size)
+                        ts = time.perf_counter()
+                        fin = srv.step()
+                        prof["step_s"] += time.perf_counter() - ts
+                        prof["steps"] += 1
+                        prof["active_sum"] += size
+                        for sid in fin:
+                            r, start, sizes = live.pop(sid)
+                            entries -= int(r.graph.nnz)
+                            done_q[cls].put((r, srv.take(sid), start, sizes))
+                    stream.synchronize()
+            except BaseException as e:
+                fail(e)
+            done_q[cls].put(None)
+            with lock:
+                self.profile[cls] = prof
+
+        threads = [threading.Thread(target=uploader, daemon=True)]
+        threads += [threading.Thread(target=engine, args=(c,), daemon=True) for c in classes]
+        threads += [threading.Thread(target=finisher, args=(c,), daemon=True) for c in classes]
+        for th in threads:
+            th.start()
+        for r in todo:   # the dispatcher: hand each request over at its arrival
+            _wait_until(t0, r.arrival)
+            if errors:
+                break
+            arrivals.put(r)
+        arrivals.put(None)
         for th in threads:
             th.join()
         if errors:

@@ -75,3 +75,20 @@ def rgg_rcb(n, seed):
     from workloads import rgg, rgg_points
     return relabel(O.Graph.of(rgg(n, seed=seed)), rcb_order(rgg_points(n, seed)))
 
+
+
+def gpu_hierarchy_digest(H, k, part_seed=1, eps=(3, 100)):
+    """The digests of oracle_digest.hierarchy_digest for a GPU hierarchy and
+    its way back up (stand-in partition with k, part_seed, eps)."""
+    from oracle_digest import digest
+    lvls = []
+    for l in range(len(H)):
+        lv = H.level(l)
+        x, a, e, v = lv.graph.numpy()
+        lvls.append((int(lv.graph.n), int(x[-1]) if len(x) else 0, digest(x, np.int64),
+                     digest(a, np.int32), digest(e, np.uint32), digest(v, np.uint32),
+                     None if lv.cmap is None else digest(lv.cmap.cpu().numpy(), np.int32),
+                     int(lv.matched), int(lv.stop_reason)))
+    part0, res = K.kappa_uncoarsen(H, k, part_seed, eps[0], eps[1])
+    return (lvls, digest(part0.cpu().numpy(), np.int32),
+            [tuple(int(t) for t in r.as_tuple()) for r in res])

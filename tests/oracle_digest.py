@@ -38,3 +38,30 @@ def batch_member_digest(args):
     H = O.coarsen(gr, rating, cseed, stop_n, 1, 20, 64)
     parts, res = O.uncoarsen(H, k, 1, 3, 100)
     return hierarchy_digest(H.levels, parts, res)
+
+
+def served_graph(spec):
+    """A graph of the served tests by its recipe: ("mix", seed, i, emin, emax)
+    is member i of the served mix, ("grid", side), ("rgg", n, seed) and
+    ("rmat", scale, seed, wseed) the generators' own graphs."""
+    from workloads import grid2d, rgg, rmat
+    from workloads.graphs import _serve_member
+    kind = spec[0]
+    if kind == "mix":
+        return _serve_member(*spec[1:])[0]
+    if kind == "grid":
+        return grid2d(spec[1], spec[1])
+    if kind == "rgg":
+        return rgg(spec[1], seed=spec[2])
+    return rmat(spec[1], 16, seed=spec[2], wseed=spec[3])
+
+
+def served_digest(args):
+    """A served request run by the oracle alone: the graph of `spec`
+    coarsened with (rating, seed, stop_n, stall 1/20, max_levels), then its
+    way back up with the stand-in partition (k, part seed 1, eps 3/100)."""
+    spec, rating, cseed, stop_n, max_levels, k = args
+    g = served_graph(spec)
+    H = O.coarsen(g, rating, cseed, stop_n, 1, 20, max_levels)
+    parts, res = O.uncoarsen(H, k, 1, 3, 100)
+    return hierarchy_digest(H.levels, parts, res)
