@@ -340,6 +340,11 @@ def main():
     ap.add_argument("--preset", default="fast", choices=["minimal", "fast", "strong"],
                     help="refine: the refinement preset of Table 2")
     ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
+    ap.add_argument("--serve-split", type=int, default=1 << 18,
+                    help="serve: level-0 entries above which requests step in engines of their "
+                         "own (0: one engine per rating)")
+    ap.add_argument("--uploaders", type=int, default=2, help="serve: upload threads of the "
+                                                             "level-granular server")
     ap.add_argument("--no-plain-loop", action="store_true",
                     help="batch4096: skip the loop of single calls")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -919,7 +924,8 @@ def bench_serve(args):
     last = {}
 
     def level_run(rs):
-        last["level"] = LevelServer()
+        last["level"] = LevelServer(split_entries=args.serve_split if args.serve_split > 0
+                                    else 1 << 62, uploaders=args.uploaders)
         return last["level"].run(rs)
 
     def level_profile():   # per engine: steps, mean step time, mean active requests
@@ -993,7 +999,10 @@ def bench_serve(args):
                                "expansion*2 or innerOuter, k in {2,8,32,64}, stop 20k, "
                                "eps 3/100, Poisson arrivals at 0.7 x the plain path's rate",
                    "requests": len(trace), "rate_req_s": round(lam, 2), "seed": 5,
-                   "server": "level-granular (kappa_server_*), one engine per rating"},
+                   "server": "level-granular (kappa_server_*), one engine per rating" +
+                             (f" and size class (split at {args.serve_split} entries)"
+                              if args.serve_split > 0 else ""),
+                   "uploaders": args.uploaders},
         "served": served,
         "batch_granular": stats["batch"],
         "plain": stats["plain"],

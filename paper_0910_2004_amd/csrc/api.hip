@@ -674,6 +674,7 @@ struct BatchIn {
     const uint64_t *gbase = nullptr;
     const int32_t *lmax = nullptr;
     const uint32_t *interrupt = nullptr;
+    const uint32_t *interrupt_host = nullptr;   // the same flag, host address
     int first_batch = 0;
 };
 // Per-graph results of the batched form.
@@ -795,7 +796,7 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
         HIPCHK(hipMemsetAsync(c.b.coarsest, 0xff, (size_t)count * 4, s));
         HIPCHK(hipMemsetAsync(c.b.reason, 0, (size_t)count * 4, s));
         HIPCHK(hipMemsetAsync(bflag, 0, sizeof(uint32_t), s));
-        launch_batch_gid(noff0, count, gid0, s);
+        launch_batch_gid(noff0, count, d0.n, gid0, s);
         DevGraph db = d0;
         db.gid = gid0;
         db.noff = noff0;
@@ -824,6 +825,9 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     // a level whose finisher handed it back (CF_EXTEND): the next batch
     // starts by giving it more grid rounds after round ext_round
     int ext_level = -1, ext_round = 0, ext_times = 0, ext_seen = -1;
+    // served steps: the host saw the interrupt, so the next launch is the
+    // next level's start alone (it ends the step there)
+    bool begin_only = false;
     // power-law graphs hand levels back: small batches keep the levels
     // launched behind a handed-back one (no-ops then) few
     if (c.big_blocks > 64) batch = std::min(batch, 2);
@@ -841,8 +845,14 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
                                            (uint64_t)count, (uint64_t)tail_on,
                                            (uint64_t)(int64_t)tail_end,
                                            (uint64_t)(int64_t)c.block_bits,
-                                           (uint64_t)(int64_t)ext_level, (uint64_t)ext_round};
+                                           (uint64_t)(int64_t)ext_level, (uint64_t)ext_round,
+                                           (uint64_t)begin_only};
         HIPCHK(run_seq(w->c, s, key, [&](hipStream_t q) {
+            if (begin_only) {
+                launch_batch_begin(c, launched, q);
+                next = launched;
+                return;
+            }
             for (int l = launched; l < l_end; ++l) {
                 int32_t nh = hint.at(l);
                 if (l == ext_level) {
@@ -865,7 +875,7 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
                 launch_level(c, l, nh, d0.nnz, n0, rounds, q);
             }
         }));
-        if (next < l_end) tail_end = next;
+        if (next < l_end && !begin_only) tail_end = next;
         launched = next;
         HIPCHK(hipMemcpyAsync(hc, c.ctrl, sizeof(Control), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -887,6 +897,17 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
         }
         if (hc->done || launched > maxl) break;
         batch = c.big_blocks > 64 ? 2 : 4;
+        if (bi && bi->gbase) {
+            // served steps end at the next boundary once a graph stops or the
+            // host interrupts: launch two levels at a time (each launched
+            // level costs its kernels' launches even when it turns out idle),
+            // and only the next level's start once the host has interrupted
+            // (if that start did not end the step, the level runs in full)
+            const bool intr = !begin_only && launched > 0 && bi->interrupt_host &&
+                              __atomic_load_n(bi->interrupt_host, __ATOMIC_ACQUIRE) != 0;
+            begin_only = intr;
+            batch = 2;
+        }
     }
     if (hc->flags && debug_on())
         fprintf(stderr, "kappa: coarsen control flags 0x%x (levels %d)\n", hc->flags, hc->nlevels);
@@ -2167,7 +2188,8 @@ kappa_status server_step(kappa_server *v, int64_t *fin, int32_t cap, int32_t *nf
     bi.gbase = gbase.data();
     bi.lmax = lmax.data();
     bi.interrupt = v->interrupt_dev;
-    bi.first_batch = std::max(1, first);
+    bi.interrupt_host = v->interrupt;
+    bi.first_batch = std::max(1, std::min(first, 3));
     kappa_hierarchy UH;
     UH.s = s;
     BatchOut bo;
@@ -2179,6 +2201,10 @@ kappa_status server_step(kappa_server *v, int64_t *fin, int32_t cap, int32_t *nf
     for (int attempt = 0; attempt < 6; ++attempt) {
         uint32_t retry = 0;
         st = coarsen_attempt(d0, maxdeg, &pp, s, &arena, false, hubs, &bi, &UH, &bo, &retry);
+        if (debug_on())
+            fprintf(stderr, "kappa: served step of %d requests (n %lld) attempt %d arena %llu: "
+                    "status %d, retry flags 0x%x, levels %zu\n", count, (long long)n, attempt,
+                    (unsigned long long)arena, (int)st, retry, UH.levels.size());
         if (st == KAPPA_OK || !retry) break;
         if (retry & CF_ARENA) arena *= 4;
         if (retry & CF_HUBS) hubs = true;

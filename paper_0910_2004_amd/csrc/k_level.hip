@@ -2485,9 +2485,20 @@ __global__ void __launch_bounds__(BATCH_THREADS) batch_end_k(Ctx c, int l) {
     }
 }
 
-__global__ void batch_gid_k(const int32_t *noff, int32_t count, int32_t *gid) {
-    for (int32_t g = blockIdx.x; g < count; g += gridDim.x)
-        for (int32_t v = noff[g] + threadIdx.x; v < noff[g + 1]; v += blockDim.x) gid[v] = g;
+// gid[v] = the graph of node v: the last g with noff[g] <= v (binary search
+// over the count + 1 ascending offsets; empty graphs are skipped).
+__global__ void __launch_bounds__(BLOCK) batch_gid_k(const int32_t *noff, int32_t count, int32_t n,
+                                                     int32_t *gid) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        int32_t lo = 0, hi = count - 1;   // noff[lo] <= v < noff[hi + 1]
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (noff[mid] <= v) lo = mid;
+            else hi = mid - 1;
+        }
+        gid[v] = lo;
+    }
 }
 
 // Rows ascend, so a row stays inside its graph iff its first and last entries do.
@@ -2541,15 +2552,29 @@ __global__ void __launch_bounds__(BLOCK) serve_extract_k(DevGraph u1, const int3
                                                          uint32_t *vw, int32_t *dmax) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int64_t i = t0; i < u1.n; i += stride) {
-        const int32_t g = u1.gid[i];
-        const int32_t a = noff1[g];
-        const int64_t e0 = u1.xadj[a];
-        const int64_t x = u1.xadj[i];
-        xadj[i + g] = x - e0;
-        vw[i] = u1.vw[i];
-        const int32_t d = (int32_t)(u1.xadj[i + 1] - x);
-        if (d > 0) atomicMax(&dmax[g], d);
+    // nodes: a block-uniform loop, so that whole waves take part in the
+    // degree maximum (one atomic per wave whose nodes share a graph, the
+    // usual case: a graph's nodes are consecutive)
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < u1.n; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        const bool live = i < u1.n;
+        int32_t g = -1, d = 0;
+        if (live) {
+            g = u1.gid[i];
+            const int32_t a = noff1[g];
+            const int64_t e0 = u1.xadj[a];
+            const int64_t x = u1.xadj[i];
+            xadj[i + g] = x - e0;
+            vw[i] = u1.vw[i];
+            d = (int32_t)(u1.xadj[i + 1] - x);
+        }
+        const int32_t g0 = __shfl(g, 0, WAVE);
+        if (__all(!live || g == g0)) {
+            const int32_t m = wave_max(d);
+            if (lane_id() == 0 && g0 >= 0 && m > 0) atomicMax(&dmax[g0], m);
+        } else if (live && d > 0) {
+            atomicMax(&dmax[g], d);
+        }
     }
     for (int64_t g = t0; g < count; g += stride) {   // each graph's closing offset
         const int32_t a = noff1[g], b = noff1[g + 1];
@@ -2894,11 +2919,11 @@ void launch_batch_end(const Ctx &c, int l, hipStream_t s) {
     hipLaunchKernelGGL(batch_end_k, dim3(1), dim3(BATCH_THREADS), 0, s, c, l);
 }
 
-void launch_batch_gid(const int32_t *noff, int32_t count, int32_t *gid, hipStream_t s) {
-    if (count <= 0) return;
+void launch_batch_gid(const int32_t *noff, int32_t count, int32_t n, int32_t *gid, hipStream_t s) {
+    if (count <= 0 || n <= 0) return;
     KAPPA_PROF("batch_gid", s);
-    hipLaunchKernelGGL(batch_gid_k, dim3(grid_for(count, 1, 8192)), dim3(BLOCK), 0, s, noff, count,
-                       gid);
+    hipLaunchKernelGGL(batch_gid_k, dim3(grid_for(n, BLOCK * 4, 4096)), dim3(BLOCK), 0, s, noff,
+                       count, n, gid);
 }
 
 void launch_batch_extract(const DevGraph &u, const int32_t *cmap, const int32_t *mate, int32_t a,

@@ -798,7 +798,7 @@ void launch_level(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, int32_t 
 void launch_batch_begin(const Ctx &c, int l, hipStream_t s);
 void launch_batch_end(const Ctx &c, int l, hipStream_t s);
 // Graph id of every node from the graphs' first nodes (noff, count + 1).
-void launch_batch_gid(const int32_t *noff, int32_t count, int32_t *gid, hipStream_t s);
+void launch_batch_gid(const int32_t *noff, int32_t count, int32_t n, int32_t *gid, hipStream_t s);
 // flags |= 1 if some row of g has an entry outside its graph's node range.
 void launch_batch_check(const DevGraph &g, uint32_t *flags, hipStream_t s);
 // One graph of a union to build (device arrays).

@@ -272,10 +272,11 @@ class LevelServer:
 
     Three kinds of host threads, each with its own HIP stream (a step runs
     level after level on the device until some request finishes or the
-    uploader interrupts it because a request of its class waits):
-      * the uploader takes requests in arrival order while the device budget
-        allows (each is charged its estimated footprint until its result is
-        recorded), copies the graph to the device and validates it there;
+    uploaders interrupt it because a request of its class waits):
+      * `uploaders` uploaders take requests in arrival order while the device
+        budget allows (each is charged its estimated footprint until its
+        result is recorded), copy the graph to the device and validate
+        it there;
       * one engine per (rating, seed, size class) owns a server: it admits the
         uploaded requests of its class (trusted: validated already) while its
         active set stays within max_entries level-0 entries, then advances all
@@ -291,8 +292,9 @@ class LevelServer:
     the mean number of requests of the steps a request took part in."""
 
     def __init__(self, device="cuda", hbm_budget: int = 200 << 30, max_active: int = 4096,
-                 max_entries: int = 1 << 27, split_entries: int = 1 << 18):
+                 max_entries: int = 1 << 27, split_entries: int = 1 << 18, uploaders: int = 2):
         self.device = device
+        self.uploaders = uploaders
         self.hbm_budget = hbm_budget
         self.max_active = max_active
         self.max_entries = max_entries
@@ -317,6 +319,7 @@ class LevelServer:
         mem = threading.Condition()
         charged = [0]
         servers = {}   # class -> its engine's server, once created
+        left = [self.uploaders]
         dev_index = torch.device(self.device).index or 0
 
         def fail(e):
@@ -352,8 +355,12 @@ class LevelServer:
                             srv.interrupt(True)
             except BaseException as e:
                 fail(e)
-            for c in classes:
-                feeds[c].put(None)
+            with lock:   # the last uploader to leave closes the feeds
+                left[0] -= 1
+                last = left[0] == 0
+            if last:
+                for c in classes:
+                    feeds[c].put(None)
 
         def finisher(cls):
             torch.cuda.set_device(dev_index)
@@ -433,7 +440,7 @@ class LevelServer:
             with lock:
                 self.profile[cls] = prof
 
-        threads = [threading.Thread(target=uploader, daemon=True)]
+        threads = [threading.Thread(target=uploader, daemon=True) for _ in range(self.uploaders)]
         threads += [threading.Thread(target=engine, args=(c,), daemon=True) for c in classes]
         threads += [threading.Thread(target=finisher, args=(c,), daemon=True) for c in classes]
         for th in threads:
@@ -443,7 +450,8 @@ class LevelServer:
             if errors:
                 break
             arrivals.put(r)
-        arrivals.put(None)
+        for _ in range(self.uploaders):
+            arrivals.put(None)
         for th in threads:
             th.join()
         if errors:
