@@ -1862,10 +1862,103 @@ __device__ __forceinline__ void bitonic_stage(uint64_t *s, int lo, int npairs, i
     }
 }
 
-// --- 2b. mid and big rows: one block per row, bitonic sort in LDS ------------------
-// The sort's stages whose compare distance stays inside one wave's contiguous
-// slice of the array (P / waves elements) need only that wave's LDS order;
-// only the few wider stages take a block barrier.  s: PMAX entries of LDS.
+// Bitonic sort of P = E * NT values held in registers, E per thread: thread
+// `tid` holds positions tid * E + e.  Stages whose partner distance j is
+// below E pair two registers of one thread; below E * WAVE, the partner is
+// lane ^ (j / E) of the same wave (shuffles); wider stages exchange through
+// LDS s (P entries, stored slot e * NT + tid so that a wave's accesses hit
+// consecutive slots) between block barriers.  Every loop has a constant trip
+// count and unrolls, so j, k and the register indices are constants.
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, WAVE);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, WAVE);
+    return ((uint64_t)hi << 32) | lo;
+}
+template <int E, int NT>
+__device__ __forceinline__ void reg_bitonic(uint64_t (&v)[E], int tid, uint64_t *s) {
+    constexpr int P = E * NT;
+    constexpr int LOGP = __builtin_ctz(P);
+    static_assert((E & (E - 1)) == 0 && (NT & (NT - 1)) == 0 && NT >= WAVE, "sort shape");
+#pragma unroll
+    for (int lk = 1; lk <= LOGP; ++lk) {
+        const int k = 1 << lk;
+#pragma unroll
+        for (int lj = lk - 1; lj >= 0; --lj) {
+            const int j = 1 << lj;
+            if (j < E) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    if ((e & j) != 0) continue;
+                    const bool up = (((tid * E + e) & k) == 0);
+                    const uint64_t a = v[e], b = v[e | j];
+                    const bool lt = a < b;
+                    const uint64_t lo = lt ? a : b, hi = lt ? b : a;
+                    v[e] = up ? lo : hi;
+                    v[e | j] = up ? hi : lo;
+                }
+            } else if (j < E * WAVE) {
+                const int m = j / E;
+                const bool lower = (tid & m) == 0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const bool up = (((tid * E + e) & k) == 0);
+                    const uint64_t o = shfl_xor64(v[e], m);
+                    const bool take_min = lower == up;
+                    const bool lt = v[e] < o;
+                    v[e] = take_min ? (lt ? v[e] : o) : (lt ? o : v[e]);
+                }
+            } else {
+                const int m = j / E;
+                const bool lower = (tid & m) == 0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) s[e * NT + tid] = v[e];
+                __syncthreads();
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const bool up = (((tid * E + e) & k) == 0);
+                    const uint64_t o = s[e * NT + (tid ^ m)];
+                    const bool take_min = lower == up;
+                    const bool lt = v[e] < o;
+                    v[e] = take_min ? (lt ? v[e] : o) : (lt ? o : v[e]);
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
+// Sorts s[0, P) (P = E * NT, every thread of the block calling) through
+// registers: slot tid + e * NT is read as position tid * E + e (any initial
+// placement sorts), and the sorted positions are written back in order.
+template <int E, int NT>
+__device__ __forceinline__ void block_sort_regs(uint64_t *s, int tid) {
+    uint64_t v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = s[tid + e * NT];
+    if (E * NT > E * WAVE) __syncthreads();   // the LDS stages overwrite s
+    reg_bitonic<E, NT>(v, tid, s);
+    if (E * NT > E * WAVE) __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) s[tid * E + e] = v[e];
+}
+
+// The register sort for P = E * NT with E in {4, 8, 16}; false: not such a P
+// (the caller sorts in LDS instead).
+template <int NT>
+__device__ __forceinline__ bool block_sort_regs_p(uint64_t *s, int P) {
+    if (P == 4 * NT) block_sort_regs<4, NT>(s, threadIdx.x);
+    else if (P == 8 * NT) block_sort_regs<8, NT>(s, threadIdx.x);
+    else if (P == 16 * NT) block_sort_regs<16, NT>(s, threadIdx.x);
+    else return false;
+    return true;
+}
+
+// --- 2b. mid and big rows: one block per row, bitonic sort ---------------------------
+// The row is staged in LDS and sorted in registers (4, 8 or 16 values per
+// thread) where P allows; otherwise in LDS, where the stages whose compare
+// distance stays inside one wave's contiguous slice of the array (P / waves
+// elements) need only that wave's LDS order and only the few wider stages
+// take a block barrier.  s: PMAX entries of LDS.
 template <int NT, int PMAX>
 __device__ __forceinline__ void fill_block_body(const Ctx &c, int l, unsigned bid, unsigned nb,
                                                 int cls, uint64_t *s) {
@@ -1905,24 +1998,28 @@ __device__ __forceinline__ void fill_block_body(const Ctx &c, int l, unsigned bi
                 if (t0 + u * NT < P) s[t0 + u * NT] = val[u];
         }
         __syncthreads();
-        const int chunk = P / NW;             // a wave's slice
-        const bool wave_stages = chunk >= WAVE;
-        bool synced = true;                   // every wave's LDS writes seen by the block
-        for (int k = 2; k <= P; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                if (!wave_stages || j >= chunk) {
-                    if (!synced) __syncthreads();
-                    bitonic_stage(s, 0, P / 2, k, j, threadIdx.x, NT);
-                    __syncthreads();
-                    synced = true;
-                } else {
-                    bitonic_stage(s, wv * chunk, chunk / 2, k, j, lane, WAVE);
-                    wave_sync_lds();
-                    synced = false;
+        if (block_sort_regs_p<NT>(s, P)) {
+            __syncthreads();
+        } else {
+            const int chunk = P / NW;             // a wave's slice
+            const bool wave_stages = chunk >= WAVE;
+            bool synced = true;                   // every wave's LDS writes seen by the block
+            for (int k = 2; k <= P; k <<= 1) {
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    if (!wave_stages || j >= chunk) {
+                        if (!synced) __syncthreads();
+                        bitonic_stage(s, 0, P / 2, k, j, threadIdx.x, NT);
+                        __syncthreads();
+                        synced = true;
+                    } else {
+                        bitonic_stage(s, wv * chunk, chunk / 2, k, j, lane, WAVE);
+                        wave_sync_lds();
+                        synced = false;
+                    }
                 }
             }
+            if (!synced) __syncthreads();
         }
-        if (!synced) __syncthreads();
         // leaders: first entry of each run of equal keys
         const int ipt = (P + NT - 1) / NT;
         const int t0 = threadIdx.x * ipt;
@@ -1967,8 +2064,9 @@ __global__ void __launch_bounds__(BIG_THREADS) fill_big_k(Ctx c, int l) {
     __shared__ uint64_t s[BIG_P];
     fill_block_body<BIG_THREADS, BIG_P>(c, l, blockIdx.x, gridDim.x, 4, s);
 }
-// --- 2a'. rows of 65..512 entries: one wave per row, bitonic sort of the
-//          renamed entries in the wave's LDS slice, then a leader scan -------------
+// --- 2a'. rows of 65..512 entries: one wave per row; the renamed entries are
+//          compacted into the wave's LDS slice, bitonic-sorted in registers and
+//          lane shuffles, written back in order, then a leader scan ------------------
 constexpr int WR_P = ROW_WAVE_MAX;   // sort size of a wave row (power of two)
 template <int NT>
 __device__ __forceinline__ void fill_wave_body(const Ctx &c, int l, unsigned bid, unsigned nb,
@@ -2010,12 +2108,12 @@ __device__ __forceinline__ void fill_wave_body(const Ctx &c, int l, unsigned bid
         while (P < q) P <<= 1;
         for (int t = q + lane; t < P; t += WAVE) s[t] = ~0ull;   // padding sorts last
         wave_sync_lds();
-        for (int k = 2; k <= P; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                bitonic_stage(s, 0, P / 2, k, j, lane, WAVE);
-                wave_sync_lds();
-            }
-        }
+        // in registers and lane shuffles (P / WAVE values per lane)
+        if (P == WAVE) block_sort_regs<1, WAVE>(s, lane);
+        else if (P == 2 * WAVE) block_sort_regs<2, WAVE>(s, lane);
+        else if (P == 4 * WAVE) block_sort_regs<4, WAVE>(s, lane);
+        else block_sort_regs<8, WAVE>(s, lane);
+        wave_sync_lds();
         // leaders (first entry of each run of equal keys) in order; runs summed
         int32_t rank = 0;
         for (int t0 = 0; t0 < P; t0 += WAVE) {
