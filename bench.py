@@ -345,6 +345,9 @@ def main():
                          "own (0: one engine per rating)")
     ap.add_argument("--uploaders", type=int, default=2, help="serve: upload threads of the "
                                                              "level-granular server")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay repeated launch sequences as HIP graphs (kappa_graphs_enable; "
+                         "the library's default is direct launches)")
     ap.add_argument("--no-plain-loop", action="store_true",
                     help="batch4096: skip the loop of single calls")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -381,6 +384,9 @@ def main():
     import paper_0910_2004_amd as K
     from workloads import rgg
 
+    if args.graphs:
+        import paper_0910_2004_amd as K
+        K.graphs_enable(True)
     if args.workload == "batch4096":
         return bench_batch(args)
     if args.workload == "serve":
@@ -602,7 +608,7 @@ def single_graph(args, rmat_mode, primary):
                                   f", two-phase matcher with blocks of 2^{args.block_bits}"),
                    "node_order": args.order, "block_bits": args.block_bits,
                    "relabel_ms": relabel_ms,
-                   "ratings_concurrent": not args.serial_ratings,
+                   "ratings_concurrent": not args.serial_ratings, "graph_replay": bool(args.graphs),
                    "n": g.n, "m": g.m, "edges_per_step": edges_step, "k": k, "stop_n": stop_n,
                    "seed": seed, "graph_seed": (3, 33) if rmat_mode else 2, "levels_n": levels},
         "roofline": roof,
@@ -698,6 +704,7 @@ def bench_batch(args):
                                "of edges, half rgg mean degree 8, weights uniform [1, 16], "
                                "expansion*2, stop n<=256 per graph",
                    "graphs": len(graphs), "n": du.n, "m": edges, "seed": 4,
+                   "graph_replay": bool(args.graphs),
                    "levels_max": int(max(levels)), "levels_mean": round(float(np.mean(levels)), 2)},
         "plain_loop": None if plain is None else
         {"ms": round(plain, 1), "value": round(edges / (plain / 1e3), 1), "unit": "edges/s",

@@ -502,6 +502,45 @@ void kappa_arena_first(uint64_t bytes);
    kernels.  Results do not depend on it. */
 void kappa_tail_enable(int32_t on);
 
+/* Tunable thresholds of the level kernels.  None changes a result (every
+   hierarchy and partition is the same under any valid table); they move
+   work between kernels.  Valid ranges in brackets; the compiled defaults in
+   parentheses.  At load the library reads the table at $KAPPA_TUNING (a
+   path; "none" keeps the defaults) or else kappa_tuning.txt beside the
+   library, if present (paper_0910_2004_amd/autotune.py measures and writes
+   it).  A table applies to calls started after it is set; setting it while
+   calls run on other threads is allowed but those calls may use either. */
+typedef struct {
+    int32_t bin_small_max;      /* matching: rows of at most this many entries take the 4-lane
+                                   path, longer ones a wave [1, 16] (16) */
+    int32_t tail_max;           /* matching: a level goes to the one-workgroup finisher once at
+                                   most this many nodes still point somewhere [0, 4096] (128) */
+    int32_t finish_max;         /* the finisher takes a level whose grid rounds ran out only with
+                                   at most this many nodes pending [0, 2^20] (4096) */
+    int32_t finish_max_big;     /*   and at most this many of them with rows above 1024
+                                   entries [0, 2^16] (64); else the level gets more grid rounds */
+    int32_t row_small_max;      /* contraction: coarse rows whose entry bound is at most this
+                                   are merged by 16 lanes, longer ones by a wave [2, 64] (64) */
+    int32_t scan_one_block_max; /* prefix sums of at most this many items run in one
+                                   workgroup, longer ones in two grid launches [0, 2^22] (16384) */
+    int32_t rounds_base;        /* grid matching rounds launched per level: rounds_base for a
+                                   level of at most rounds_n0 nodes [1, 16] (3), */
+    int32_t rounds_n0;          /*   [1, 2^24] (2048), */
+    int32_t rounds_growth;      /*   one more per factor rounds_growth in nodes [2, 1024] (8), */
+    int32_t rounds_cap;         /*   at most rounds_cap [rounds_base, 32] (8) */
+} kappa_tuning;
+/* The current table (host). */
+kappa_status kappa_tuning_get(kappa_tuning *out);
+/* Replaces the table; KAPPA_E_RANGE (table unchanged) if a field is out of
+   range. */
+kappa_status kappa_tuning_set(const kappa_tuning *t);
+/* Reads "name value" lines (names as the fields above, '#' starts a comment;
+   fields not named keep their current values) from path and sets the table:
+   KAPPA_E_ARG if the file cannot be read or holds an unknown name or a
+   malformed line, KAPPA_E_RANGE if a value is out of range (table
+   unchanged in both cases). */
+kappa_status kappa_tuning_load(const char *path);
+
 const char *kappa_status_str(kappa_status st);
 const char *kappa_version(void);
 

@@ -16,4 +16,5 @@ from ._lib import (  # noqa: F401
     kappa_uncoarsen, kappa_cache_release,
     kappa_refine, kappa_uncoarsen_refined, refine_params, REFINE_PRESETS, REFINE_K_MAX,
     graphs_enable, tail_enable, arena_first, use_torch_allocator, profile_enable, profile_reset, profile_read,
+    tuning_get, tuning_set, tuning_load, TUNING_FIELDS,
 )

@@ -28,6 +28,14 @@ class KappaError(RuntimeError):
         super().__init__(f"{fn} failed: {status} ({status_str(status)})")
 
 
+TUNING_FIELDS = ("bin_small_max", "tail_max", "finish_max", "finish_max_big", "row_small_max",
+                 "scan_one_block_max", "rounds_base", "rounds_n0", "rounds_growth", "rounds_cap")
+
+
+class c_tuning(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in TUNING_FIELDS]
+
+
 class c_graph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("xadj", ctypes.c_void_p),
                 ("adj", ctypes.c_void_p), ("ew", ctypes.c_void_p), ("vw", ctypes.c_void_p)]
@@ -171,6 +179,9 @@ def lib():
         "kappa_server_active": (i32, [P]),
         "kappa_server_step": (st, [P, P, i32, ctypes.POINTER(i32)]),
         "kappa_server_interrupt": (st, [P, i32]),
+        "kappa_tuning_get": (st, [ctypes.POINTER(c_tuning)]),
+        "kappa_tuning_set": (st, [ctypes.POINTER(c_tuning)]),
+        "kappa_tuning_load": (st, [ctypes.c_char_p]),
         "kappa_server_take": (st, [P, ctypes.c_int64, ctypes.POINTER(P)]),
         "kappa_server_free": (None, [P]),
         "kappa_batch_count": (i32, [P]),
@@ -705,6 +716,30 @@ def kappa_uncoarsen_refined(h: Hierarchy, k: int, part_seed: int = 1, eps_num: i
 def kappa_cache_release():
     """Frees the device memory the library keeps between calls."""
     _check("kappa_cache_release", lib().kappa_cache_release())
+
+
+def tuning_get() -> dict:
+    """The library's tuning table (kappa_tuning) as a dict."""
+    t = c_tuning()
+    _check("kappa_tuning_get", lib().kappa_tuning_get(ctypes.byref(t)))
+    return {f: int(getattr(t, f)) for f in TUNING_FIELDS}
+
+
+def tuning_set(table: Optional[dict] = None, **fields):
+    """Sets the fields given (the others keep their values); raises
+    KappaError (E_RANGE) on a value out of range."""
+    cur = tuning_get()
+    cur.update(table or {})
+    cur.update(fields)
+    unknown = set(cur) - set(TUNING_FIELDS)
+    if unknown:
+        raise KeyError(f"unknown tuning fields {sorted(unknown)}")
+    t = c_tuning(*[int(cur[f]) for f in TUNING_FIELDS])
+    _check("kappa_tuning_set", lib().kappa_tuning_set(ctypes.byref(t)))
+
+
+def tuning_load(path: str):
+    _check("kappa_tuning_load", lib().kappa_tuning_load(str(path).encode()))
 
 
 def graphs_enable(on: bool = True):

@@ -18,9 +18,148 @@
 #include <new>
 #include <vector>
 
+#include <dlfcn.h>
+
+#include <string>
+
 #include "kappa_internal.h"
 
 using namespace kappa;
+
+// ===========================================================================
+// Tuning table: the thresholds of kappa_tuning.  Defaults are the compiled
+// values; at load the library reads the table at $KAPPA_TUNING (a path;
+// "none" skips it) or else kappa_tuning.txt beside the library, if present.
+// A bad file leaves the defaults.
+// ===========================================================================
+namespace {
+std::mutex g_tune_mu;
+Tune g_tune;
+
+bool tune_ok(const kappa_tuning &t) {
+    return t.bin_small_max >= 1 && t.bin_small_max <= BIN_SMALL_MAX && t.tail_max >= 0 &&
+           t.tail_max <= FINISH_MAX && t.finish_max >= 0 && t.finish_max <= (1 << 20) &&
+           t.finish_max_big >= 0 && t.finish_max_big <= (1 << 16) && t.row_small_max >= 2 &&
+           t.row_small_max <= ROW_SMALL_MAX && t.scan_one_block_max >= 0 &&
+           t.scan_one_block_max <= (1 << 22) && t.rounds_base >= 1 && t.rounds_base <= 16 &&
+           t.rounds_n0 >= 1 && t.rounds_n0 <= (1 << 24) && t.rounds_growth >= 2 &&
+           t.rounds_growth <= 1024 && t.rounds_cap >= t.rounds_base && t.rounds_cap <= 32;
+}
+kappa_tuning to_abi(const Tune &u) {
+    kappa_tuning t;
+    t.bin_small_max = u.bin_small_max;
+    t.tail_max = u.tail_max;
+    t.finish_max = u.finish_max;
+    t.finish_max_big = u.finish_max_big;
+    t.row_small_max = u.row_small_max;
+    t.scan_one_block_max = u.scan_one_block_max;
+    t.rounds_base = u.rounds_base;
+    t.rounds_n0 = u.rounds_n0;
+    t.rounds_growth = u.rounds_growth;
+    t.rounds_cap = u.rounds_cap;
+    return t;
+}
+Tune from_abi(const kappa_tuning &t) {
+    Tune u;
+    u.bin_small_max = t.bin_small_max;
+    u.tail_max = t.tail_max;
+    u.finish_max = t.finish_max;
+    u.finish_max_big = t.finish_max_big;
+    u.row_small_max = t.row_small_max;
+    u.scan_one_block_max = t.scan_one_block_max;
+    u.rounds_base = t.rounds_base;
+    u.rounds_n0 = t.rounds_n0;
+    u.rounds_growth = t.rounds_growth;
+    u.rounds_cap = t.rounds_cap;
+    return u;
+}
+// "name value" lines ('#' starts a comment); every name must be known.
+kappa_status tune_parse(const char *path, kappa_tuning *out) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return KAPPA_E_ARG;
+    kappa_tuning t = *out;
+    struct Field {
+        const char *name;
+        int32_t *p;
+    } fields[] = {{"bin_small_max", &t.bin_small_max},   {"tail_max", &t.tail_max},
+                  {"finish_max", &t.finish_max},         {"finish_max_big", &t.finish_max_big},
+                  {"row_small_max", &t.row_small_max},   {"scan_one_block_max", &t.scan_one_block_max},
+                  {"rounds_base", &t.rounds_base},       {"rounds_n0", &t.rounds_n0},
+                  {"rounds_growth", &t.rounds_growth},   {"rounds_cap", &t.rounds_cap}};
+    char line[512];
+    kappa_status st = KAPPA_OK;
+    while (st == KAPPA_OK && std::fgets(line, sizeof line, f)) {
+        char *hash = std::strchr(line, '#');
+        if (hash) *hash = 0;
+        char name[128];
+        long long v = 0;
+        char extra[8];
+        const int got = std::sscanf(line, "%127s %lld %7s", name, &v, extra);
+        if (got <= 0) continue;   // blank or comment
+        if (got != 2 || v < INT32_MIN || v > INT32_MAX) {
+            st = KAPPA_E_ARG;
+            break;
+        }
+        bool known = false;
+        for (auto &fd : fields)
+            if (std::strcmp(fd.name, name) == 0) {
+                *fd.p = (int32_t)v;
+                known = true;
+            }
+        if (!known) st = KAPPA_E_ARG;
+    }
+    std::fclose(f);
+    if (st == KAPPA_OK && !tune_ok(t)) st = KAPPA_E_RANGE;
+    if (st == KAPPA_OK) *out = t;
+    return st;
+}
+struct TuneInit {
+    TuneInit() {
+        const char *e = std::getenv("KAPPA_TUNING");
+        std::string path;
+        if (e && e[0]) {
+            if (std::strcmp(e, "none") == 0) return;
+            path = e;
+        } else {
+            Dl_info info;
+            if (!dladdr((void *)&tune_ok, &info) || !info.dli_fname) return;
+            path = info.dli_fname;
+            const size_t slash = path.rfind('/');
+            path = (slash == std::string::npos ? std::string(".") : path.substr(0, slash)) +
+                   "/kappa_tuning.txt";
+        }
+        kappa_tuning t = to_abi(Tune{});
+        if (tune_parse(path.c_str(), &t) == KAPPA_OK) g_tune = from_abi(t);
+    }
+} g_tune_init;
+}  // namespace
+
+Tune kappa::tuning_now() {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    return g_tune;
+}
+
+extern "C" kappa_status kappa_tuning_get(kappa_tuning *out) {
+    if (!out) return KAPPA_E_ARG;
+    *out = to_abi(tuning_now());
+    return KAPPA_OK;
+}
+
+extern "C" kappa_status kappa_tuning_set(const kappa_tuning *t) {
+    if (!t) return KAPPA_E_ARG;
+    if (!tune_ok(*t)) return KAPPA_E_RANGE;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune = from_abi(*t);
+    return KAPPA_OK;
+}
+
+extern "C" kappa_status kappa_tuning_load(const char *path) {
+    if (!path) return KAPPA_E_ARG;
+    kappa_tuning t = to_abi(tuning_now());
+    const kappa_status st = tune_parse(path, &t);
+    if (st != KAPPA_OK) return st;
+    return kappa_tuning_set(&t);
+}
 
 // ===========================================================================
 // Profiling: HIP events around library launches (enabled on request).
@@ -615,15 +754,18 @@ struct SizeHint {
     }
 };
 
-// Multi-block matching rounds before the one-workgroup finisher.  Measured on
-// random geometric graphs: three rounds bring a level of ~2 K nodes below the
-// finisher's threshold, and each further round covers about 8x more nodes.
-// A round launched after the pending set is small is a no-op of two launches;
-// one not launched leaves a few hundred more nodes to the finisher.
-inline int rounds_for(int32_t n_hint) {
-    if (n_hint <= 2048) return 3;
-    int r = 3 + (int)std::ceil(std::log((double)n_hint / 2048) / std::log(8.0));
-    return std::min(r, 8);
+// Multi-block matching rounds before the one-workgroup finisher: rounds_base
+// for a level of at most rounds_n0 nodes, one more per factor rounds_growth,
+// at most rounds_cap (the tuning table).  The compiled defaults (3, 2048, 8,
+// 8) were measured on random geometric graphs: three rounds bring a level of
+// ~2 K nodes below the finisher's threshold, and each further round covers
+// about 8x more nodes.  A round launched after the pending set is small is a
+// no-op of two launches; one not launched leaves more nodes to the finisher.
+inline int rounds_for(int32_t n_hint, const Tune &t) {
+    if (n_hint <= t.rounds_n0) return t.rounds_base;
+    int r = t.rounds_base +
+            (int)std::ceil(std::log((double)n_hint / t.rounds_n0) / std::log((double)t.rounds_growth));
+    return std::min(r, t.rounds_cap);
 }
 
 struct HostControl {
@@ -870,7 +1012,7 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
                 // sums, which chains level 0 over many rounds (17 grid rounds
                 // on the random geometric graph of 2^20 nodes); the finisher
                 // completes any remainder
-                int rounds = rounds_for(nh);
+                int rounds = rounds_for(nh, c.t);
                 if (l == 0 && p->rating == KAPPA_INNER_OUTER) rounds = 18;
                 launch_level(c, l, nh, d0.nnz, n0, rounds, q);
             }

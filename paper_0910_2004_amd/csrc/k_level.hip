@@ -63,8 +63,8 @@ __device__ __forceinline__ bool graph_active(const Ctx &c, const DevGraph &g, in
     return !g.gid || c.b.active[g.gid[v]];
 }
 
-__device__ __forceinline__ int bin_of(int64_t deg) {
-    return deg <= BIN_SMALL_MAX ? 0 : (deg <= BIN_MID_MAX ? 1 : 2);
+__device__ __forceinline__ int bin_of(const Ctx &c, int64_t deg) {
+    return deg <= c.t.bin_small_max ? 0 : (deg <= BIN_MID_MAX ? 1 : 2);
 }
 
 
@@ -405,7 +405,7 @@ __device__ __forceinline__ void init_phase(const Ctx &c, const DevGraph &g, Leve
             vv[k] = (int32_t)i;
             bb[k] = -1;
             dd[k] = (int32_t)deg[k];
-            const int bn = bin_of(deg[k]);
+            const int bn = bin_of(c, deg[k]);
             bin[k] = i < g.n && bn > 0 && graph_active(c, g, i) ? bn : -1;
             if (i < g.n) {
                 mate[i] = -1;
@@ -484,7 +484,7 @@ __device__ __forceinline__ void pick_bin0(const Ctx &c, const DevGraph &g, uint6
                 v = (int32_t)i;
                 rb = g.xadj[v];
                 re = g.xadj[v + 1];
-                act = re - rb >= 1 && re - rb <= BIN_SMALL_MAX && graph_active(c, g, v);
+                act = re - rb >= 1 && re - rb <= c.t.bin_small_max && graph_active(c, g, v);
                 if (act) av = attr_src<R>(g, out, v);
             } else {
                 v = checked_node(ri.in[0].v[i], g.n, c.ctrl);
@@ -766,7 +766,7 @@ __device__ __forceinline__ void mate_phase(const Ctx &c, const DevGraph &g, Leve
                     m = b;
                     if (v < b) ++pairs;
                 } else {
-                    bin[k] = bin_of(dd[k]);
+                    bin[k] = bin_of(c, dd[k]);
                 }
             }
             if (FIRST) {
@@ -838,7 +838,7 @@ __global__ void __launch_bounds__(BLOCK) pick_k(Ctx c, int l, int r, PickGrid pg
             if (blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(&st->handoff, -1, -2);
             return;
         }
-        if (total <= TAIL_MAX) {
+        if (total <= c.t.tail_max) {
             if (blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(&st->handoff, -1, r - 1);
             return;
         }
@@ -881,7 +881,7 @@ __global__ void __launch_bounds__(BLOCK) prep_k(Ctx c, int l, int r) {
     const RoundIn ri = round_inputs<false>(c, g, r, st->cnt[(r - 1) & 3]);
     const int32_t c0 = ri.cn[0], c1 = ri.cn[1];
     const int64_t total = (int64_t)c0 + c1 + ri.cn[2];
-    if (total == 0 || total <= TAIL_MAX) {
+    if (total == 0 || total <= c.t.tail_max) {
         if (blockIdx.x == 0 && threadIdx.x == 0)
             atomicCAS(&st->handoff, -1, total == 0 ? -2 : r - 1);
         return;
@@ -1124,7 +1124,7 @@ __global__ void __launch_bounds__(FINISH_THREADS) finish_k(Ctx c, int l, int r_l
         // in PH_MATCH; `done` ends this batch of levels.
         const int32_t pend = s_cnt[r0 & 1][0] + s_cnt[r0 & 1][1] + s_cnt[r0 & 1][2];
         if (F == 0 && st->handoff == -1 && r0 == r_last &&
-            (pend > FINISH_MAX || s_cnt[r0 & 1][2] > FINISH_MAX_BIG)) {
+            (pend > c.t.finish_max || s_cnt[r0 & 1][2] > c.t.finish_max_big)) {
             if (threadIdx.x == 0) {
                 c.ctrl->ext_level = l;
                 c.ctrl->ext_round = r_last;
@@ -1447,7 +1447,7 @@ block_match_k(Ctx c, int l) {
             if (s_best[i] == 1) {
                 const int64_t deg = g.xadj[v + 1] - g.xadj[v];
                 dd[k] = (int32_t)deg;
-                bin[k] = bin_of(deg);
+                bin[k] = bin_of(c, deg);
             }
         }
         block_append_mk(bin, vv, bq, dd, ol, &c.ms.state->cnt[0][0], sh, sbase);
@@ -1716,9 +1716,9 @@ __device__ __forceinline__ void row_entry(const DevGraph &g, const int32_t *cmap
 
 // Merge classes by the bound on the merged row: 0 small (16 lanes), 1 one
 // wave, 3 one block, 2 large (hub accumulators); -1 empty.
-__device__ __forceinline__ int row_class(int64_t bound) {
+__device__ __forceinline__ int row_class(int64_t bound, int32_t small_max) {
     if (bound == 0) return -1;
-    if (bound <= ROW_SMALL_MAX) return 0;
+    if (bound <= small_max) return 0;
     if (bound <= ROW_WAVE_MAX) return 1;
     if (bound <= ROW_MID_MAX) return 3;
     return bound <= ROW_BIG_MAX ? 4 : 2;
@@ -1767,7 +1767,7 @@ __device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bi
         int cls = -1;
         if (live) {
             r = row_src(g, c, x);
-            cls = row_class(row_bound(r));
+            cls = row_class(row_bound(r), c.t.row_small_max);
             if ((!BIG || !c.big_rows) && cls == 4) cls = 2;
             if (cls == 2 && !c.cs.hub_acc) need_hubs = true;
         }
@@ -2322,7 +2322,7 @@ __device__ __forceinline__ void compact_small_body(const Ctx &c, int l, unsigned
         RowSrc r;
         if (mine) {
             r = row_src(g, c, (int32_t)x);
-            mine = row_bound(r) <= ROW_SMALL_MAX;   // else compact_big copies it
+            mine = row_bound(r) <= c.t.row_small_max;   // else compact_big copies it
         }
         uint32_t sum = 0;
         if (mine) {
@@ -2583,19 +2583,33 @@ __global__ void __launch_bounds__(BATCH_THREADS) batch_end_k(Ctx c, int l) {
     }
 }
 
-// gid[v] = the graph of node v: the last g with noff[g] <= v (binary search
-// over the count + 1 ascending offsets; empty graphs are skipped).
+// gid[v] = the graph of node v: the last g with noff[g] <= v (empty graphs
+// are skipped).  Per block-sized tile of nodes, one binary search over the
+// count + 1 ascending offsets finds the graph of the tile's first node; each
+// thread walks on from there (a tile spans few graphs).
+__device__ __forceinline__ int32_t graph_of(const int32_t *noff, int32_t count, int64_t v) {
+    int32_t lo = 0, hi = count - 1;   // noff[lo] <= v < noff[hi + 1]
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (noff[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 __global__ void __launch_bounds__(BLOCK) batch_gid_k(const int32_t *noff, int32_t count, int32_t n,
                                                      int32_t *gid) {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * blockDim.x) {
-        int32_t lo = 0, hi = count - 1;   // noff[lo] <= v < noff[hi + 1]
-        while (lo < hi) {
-            const int32_t mid = (lo + hi + 1) >> 1;
-            if (noff[mid] <= v) lo = mid;
-            else hi = mid - 1;
+    __shared__ int32_t g0;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n;
+         base += (int64_t)gridDim.x * blockDim.x) {   // block-uniform
+        if (threadIdx.x == 0) g0 = graph_of(noff, count, base);
+        __syncthreads();
+        const int64_t v = base + threadIdx.x;
+        if (v < n) {
+            int32_t g = g0;
+            while (g + 1 < count && noff[g + 1] <= v) ++g;
+            gid[v] = g;
         }
-        gid[v] = lo;
+        __syncthreads();   // g0 is rewritten for the next tile
     }
 }
 

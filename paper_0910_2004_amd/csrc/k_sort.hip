@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(RS_THREADS) rs_scatter_k(const KT *kin, const 
     __shared__ int32_t base_of[RS_BINS];          // this tile's first output position per digit
     __shared__ int32_t wcnt[RS_WAVES][RS_BINS];   // items of a digit per wave in the current step
     const int64_t tiles = (n + RS_TILE - 1) / RS_TILE;
-    const int wv = threadIdx.x / WAVE, lane = lane_id();
+    const int wv = threadIdx.x / WAVE;
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {   // block-uniform
         base_of[threadIdx.x] = hist[(int64_t)threadIdx.x * tiles + tile];
         for (int w = 0; w < RS_WAVES; ++w) wcnt[w][threadIdx.x] = 0;

@@ -49,6 +49,20 @@ constexpr int HUB_SLOTS = 32;       // rows above ROW_MID_MAX: dense accumulator
 constexpr int HUB_SLOTS_MAX = 256;  //   and at most, within HUB_BUDGET bytes of accumulators
 constexpr int64_t HUB_BUDGET = (int64_t)4 << 30;
 
+// The tunable thresholds (kappa_tuning), copied into every launch context.
+// Compile-time sizes bound them: bin_small_max <= BIN_SMALL_MAX and
+// row_small_max <= ROW_SMALL_MAX (register and LDS arrays).
+struct Tune {
+    int32_t bin_small_max = BIN_SMALL_MAX;
+    int32_t tail_max = TAIL_MAX;
+    int32_t finish_max = FINISH_MAX;
+    int32_t finish_max_big = FINISH_MAX_BIG;
+    int32_t row_small_max = ROW_SMALL_MAX;
+    int32_t scan_one_block_max = 16384;
+    int32_t rounds_base = 3, rounds_n0 = 2048, rounds_growth = 8, rounds_cap = 8;
+};
+Tune tuning_now();   // the library's current table (host)
+
 // Device-scope atomics on one address from many blocks serialise where the
 // XCDs meet (about 10 ns each), so kernel-wide accumulators are split over
 // NSHARD slots picked by block index and summed by their consumer, and
@@ -514,7 +528,7 @@ struct ProfScope {
 template <class F, class W>
 inline void launch_scan(int64_t n_hint, F f, W w, int64_t *ws, unsigned *arr, int64_t *total,
                         hipStream_t s) {
-    if (n_hint <= ONE_SCAN_CHUNK) {   // any n is correct; short ones are fast
+    if (n_hint <= tuning_now().scan_one_block_max) {   // any n is correct; short ones are fast
         KAPPA_PROF("scan_one_block", s);
         hipLaunchKernelGGL((scan_one_block_k<F, W>), dim3(1), dim3(ONE_SCAN_THREADS), 0, s, f, w,
                            total);
@@ -673,6 +687,7 @@ struct BatchCtx {
 };
 
 struct Ctx {
+    Tune t = tuning_now();
     Control *ctrl;
     LevelDesc *lv;
     int32_t rating;

@@ -107,3 +107,73 @@ def test_noalloc_cut_balance_checks_before_device_work():
     big = K._lib.c_graph(1 << 20, 1 << 31, fake, fake, fake, fake)
     assert L.kappa_cut_balance_noalloc(ctypes.byref(big), fake, 4096, 3, 100, None,
                                        ctypes.byref(res), None) == K.E_CAPACITY
+
+
+DEFAULT_TUNING = {"bin_small_max": 16, "tail_max": 128, "finish_max": 4096, "finish_max_big": 64,
+                  "row_small_max": 64, "scan_one_block_max": 16384, "rounds_base": 3,
+                  "rounds_n0": 2048, "rounds_growth": 8, "rounds_cap": 8}
+
+
+def test_tuning_table_set_get_and_ranges():
+    saved = K.tuning_get()
+    try:
+        K.tuning_set(DEFAULT_TUNING)
+        assert K.tuning_get() == DEFAULT_TUNING
+        K.tuning_set(tail_max=0, row_small_max=8, rounds_base=1, rounds_cap=1)
+        t = K.tuning_get()
+        assert (t["tail_max"], t["row_small_max"], t["rounds_base"], t["rounds_cap"]) == (0, 8, 1, 1)
+        for bad in ({"bin_small_max": 17}, {"bin_small_max": 0}, {"row_small_max": 65},
+                    {"row_small_max": 1}, {"tail_max": 4097}, {"rounds_growth": 1},
+                    {"rounds_base": 4, "rounds_cap": 3}, {"scan_one_block_max": -1}):
+            before = K.tuning_get()
+            with pytest.raises(K.KappaError) as e:
+                K.tuning_set(bad)
+            assert e.value.status == K.E_RANGE and K.tuning_get() == before   # unchanged
+        assert K.lib().kappa_tuning_set(None) == K.E_ARG
+        assert K.lib().kappa_tuning_get(None) == K.E_ARG
+    finally:
+        K.tuning_set(saved)
+
+
+def test_tuning_table_files(tmp_path):
+    saved = K.tuning_get()
+    try:
+        K.tuning_set(DEFAULT_TUNING)
+        good = tmp_path / "t.txt"
+        good.write_text("# measured table\n\ntail_max 256   # comment\nrounds_n0 4096\n")
+        K.tuning_load(str(good))
+        t = K.tuning_get()
+        assert t["tail_max"] == 256 and t["rounds_n0"] == 4096
+        assert t["finish_max"] == DEFAULT_TUNING["finish_max"]   # fields not named are kept
+        for text, status in (("no_such_field 3\n", K.E_ARG), ("tail_max\n", K.E_ARG),
+                             ("tail_max 3 4\n", K.E_ARG), ("tail_max x\n", K.E_ARG),
+                             ("tail_max 999999\n", K.E_RANGE)):
+            bad = tmp_path / "bad.txt"
+            bad.write_text(text)
+            before = K.tuning_get()
+            with pytest.raises(K.KappaError) as e:
+                K.tuning_load(str(bad))
+            assert e.value.status == status, text
+            assert K.tuning_get() == before
+        with pytest.raises(K.KappaError):
+            K.tuning_load(str(tmp_path / "missing.txt"))
+    finally:
+        K.tuning_set(saved)
+
+
+def test_tuning_table_read_at_load(tmp_path):
+    """A fresh process reads the table named by KAPPA_TUNING when the library
+    loads, and keeps the compiled defaults with KAPPA_TUNING=none."""
+    import json
+    import subprocess
+    import sys
+    f = tmp_path / "t.txt"
+    f.write_text("finish_max 1000\nbin_small_max 8\n")
+    code = ("import json, paper_0910_2004_amd as K; print(json.dumps(K.tuning_get()))")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(K.__file__)))
+    for env, want in ((str(f), dict(DEFAULT_TUNING, finish_max=1000, bin_small_max=8)),
+                      ("none", DEFAULT_TUNING)):
+        out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True,
+                             text=True, env=dict(os.environ, KAPPA_TUNING=env), timeout=300)
+        assert out.returncode == 0, out.stderr
+        assert json.loads(out.stdout.strip().splitlines()[-1]) == want
