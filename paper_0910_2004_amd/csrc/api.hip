@@ -676,7 +676,7 @@ kappa_status validate_impl(const DevGraph &g, hipStream_t s, int32_t *maxdeg_out
 // graph has such rows at level 0; coarse levels of other graphs rarely do,
 // and their long rows are then scanned by one block each).
 void carve_scratch(Carve &cv, const DevGraph &g, int rating, bool hubs, Ctx &c,
-                   bool chunks = false) {
+                   bool chunks = false, bool tail = false) {
     MatchScratch &ms = c.ms;
     ContractScratch &cs = c.cs;
     ms.best = cv.get<int32_t>(g.n);
@@ -703,8 +703,23 @@ void carve_scratch(Carve &cv, const DevGraph &g, int rating, bool hubs, Ctx &c,
     // merged at once), between HUB_SLOTS and HUB_SLOTS_MAX
     cs.hub_slots = (int32_t)std::max<int64_t>(
         HUB_SLOTS, std::min<int64_t>(HUB_SLOTS_MAX, HUB_BUDGET / (4 * ((int64_t)g.n + 1))));
-    cs.hub_acc = hubs ? cv.get<uint32_t>((int64_t)cs.hub_slots * g.n) : nullptr;
-    cs.hub_bits = hubs ? cv.get<uint32_t>((int64_t)cs.hub_slots * cs.hub_words) : nullptr;
+    // large rows: the key-bucket merge wherever it applies (graphs with long
+    // rows, or any graph once a large row has turned up); the dense hub
+    // accumulators only where it may not (more than HUGE_NC_MAX nodes) and
+    // for the one-workgroup tail, which merges every large row densely
+    c.huge = (hubs || c.big_rows) ? 1 : 0;
+    const bool dense = hubs && (g.n > HUGE_NC_MAX || tail);
+    cs.hub_acc = dense ? cv.get<uint32_t>((int64_t)cs.hub_slots * g.n) : nullptr;
+    cs.hub_bits = dense ? cv.get<uint32_t>((int64_t)cs.hub_slots * cs.hub_words) : nullptr;
+    cs.hg_rows = g.nnz / (ROW_BIG_MAX + 1) + 64;             // large rows at most
+    cs.hg_cap = g.nnz / HG_WIN_MIN + 2 * cs.hg_rows;         // groups at most
+    cs.hg_adj = c.huge ? cv.get<int32_t>(g.nnz) : nullptr;
+    cs.hg_ew = c.huge ? cv.get<uint32_t>(g.nnz) : nullptr;
+    cs.hg_small = c.huge ? cv.get<int4>(cs.hg_cap) : nullptr;
+    cs.hg_big = c.huge ? cv.get<int4>(cs.hg_cap) : nullptr;
+    cs.hg_slot = c.huge ? cv.get<int2>(cs.hg_cap) : nullptr;
+    cs.hg_row = c.huge ? cv.get<int2>(cs.hg_rows) : nullptr;
+    cs.hg_cnt = c.huge ? cv.get<int32_t>(4) : nullptr;
     // two-phase matcher (c.block_bits set before carving)
     ms.loc = c.block_bits >= 0 ? cv.get<int32_t>(g.n) : nullptr;
     ms.lkey = c.block_bits >= 0 ? cv.get<LocKey>(g.n) : nullptr;
@@ -723,6 +738,7 @@ void fill_scratch(const DevGraph &g, const Ctx &c, hipStream_t s) {
     z.add(c.cs.arrive, ARRIVE_WORDS);
     z.add(c.cs.row_cnt, 8);
     z.add(c.cs.totals, 4 * 2);
+    z.add(c.cs.hg_cnt, 4);
     // the matching state: list counters, round statistics, merge counts
     static_assert(sizeof(MatchState) % 4 == 0, "zeroed as words");
     z.add(c.ms.state, sizeof(MatchState) / 4);
@@ -854,7 +870,8 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     if (!carve_workspace(s, w, [&](Carve &cv) {
             c.ctrl = cv.get<Control>(1);
             c.lv = cv.get<LevelDesc>(maxl + 2);
-            carve_scratch(cv, d0, p->rating, hubs, c, maxdeg0 > BIN_MID_MAX);
+            carve_scratch(cv, d0, p->rating, hubs, c, maxdeg0 > BIN_MID_MAX,
+                          !bi && g_tail_on && c.block_bits < 0);
             if (bi) {
                 c.b.count = count;
                 c.b.stall_num = p->stall_num;

@@ -1060,6 +1060,7 @@ __device__ void close_matching(const Ctx &c, LevelDesc *L, bool capped, int grid
         }
     }
     if (threadIdx.x < 8) c.cs.row_cnt[threadIdx.x] = 0;
+    if (threadIdx.x < 4 && c.cs.hg_cnt) c.cs.hg_cnt[threadIdx.x] = 0;
     if (threadIdx.x < 4) c.cs.totals[threadIdx.x] = 0;
     __syncthreads();   // every read of st->cnt is done
     if (threadIdx.x < 16) {   // next level's lists
@@ -1728,6 +1729,12 @@ __device__ __forceinline__ int32_t *class_list(const ContractScratch &cs, int32_
     return cs.rows + (int64_t)slot * n;
 }
 
+// A large row of a level whose next level has nc nodes is merged by key
+// buckets (fill_huge_*) rather than by the dense hub accumulators.
+__device__ __forceinline__ bool huge_row(int64_t nc, int64_t tot) {
+    return nc <= HUGE_NC_MAX && tot <= HUGE_ROW_MAX;
+}
+
 // Orders the LDS traffic of one wave (all lanes of the wave call it).
 __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -1769,7 +1776,8 @@ __device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bi
             r = row_src(g, c, x);
             cls = row_class(row_bound(r), c.t.row_small_max);
             if ((!BIG || !c.big_rows) && cls == 4) cls = 2;
-            if (cls == 2 && !c.cs.hub_acc) need_hubs = true;
+            if (cls == 2 && !c.cs.hub_acc && !(BIG && c.huge && huge_row(count, r.tot)))
+                need_hubs = true;
         }
         wave_append(sub == 0 && cls == 1, x, lists1, &c.cs.row_cnt[1]);
         wave_append(sub == 0 && cls == 2, x, lists2, &c.cs.row_cnt[2]);
@@ -1953,24 +1961,51 @@ __device__ __forceinline__ bool block_sort_regs_p(uint64_t *s, int P) {
     return true;
 }
 
-// --- 2b. mid and big rows: one block per row, bitonic sort ---------------------------
-// The row is staged in LDS and sorted in registers (4, 8 or 16 values per
-// thread) where P allows; otherwise in LDS, where the stages whose compare
-// distance stays inside one wave's contiguous slice of the array (P / waves
-// elements) need only that wave's LDS order and only the few wider stages
-// take a block barrier.  s: PMAX entries of LDS.
+// Sorts s[0, P) ascending (P a power of two, 2 <= P) with the block's NT
+// threads: in registers where P = 4, 8 or 16 per thread, else in LDS, where
+// the stages whose compare distance stays inside one wave's contiguous slice
+// of the array (P / waves elements) need only that wave's LDS order and only
+// the few wider stages take a block barrier.  Ends with a block barrier.
+template <int NT>
+__device__ __forceinline__ void block_sort(uint64_t *s, int P) {
+    constexpr int NW = NT / WAVE;
+    if (block_sort_regs_p<NT>(s, P)) {
+        __syncthreads();
+        return;
+    }
+    const int wv = threadIdx.x / WAVE, lane = lane_id();
+    const int chunk = P / NW;             // a wave's slice
+    const bool wave_stages = chunk >= WAVE;
+    bool synced = true;                   // every wave's LDS writes seen by the block
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (!wave_stages || j >= chunk) {
+                if (!synced) __syncthreads();
+                bitonic_stage(s, 0, P / 2, k, j, threadIdx.x, NT);
+                __syncthreads();
+                synced = true;
+            } else {
+                bitonic_stage(s, wv * chunk, chunk / 2, k, j, lane, WAVE);
+                wave_sync_lds();
+                synced = false;
+            }
+        }
+    }
+    if (!synced) __syncthreads();
+}
+
+// --- 2b. mid and big rows: one block per row, the row staged in LDS and sorted
+//         (block_sort), then a leader scan.  s: PMAX entries of LDS. ----------------
 template <int NT, int PMAX>
 __device__ __forceinline__ void fill_block_body(const Ctx &c, int l, unsigned bid, unsigned nb,
                                                 int cls, uint64_t *s) {
     __shared__ int64_t sh[NT / WAVE + 1];
-    constexpr int NW = NT / WAVE;
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_CONTRACT, g)) return;
     const int32_t *cmap = L->cmap;
     const int64_t count = c.cs.row_cnt[cls];
     const int32_t *list = class_list(c.cs, g.n, cls);
-    const int wv = threadIdx.x / WAVE, lane = lane_id();
     for (int64_t i = bid; i < count; i += nb) {
         const int32_t x = list[i];
         const RowSrc r = row_src(g, c, x);
@@ -1998,28 +2033,7 @@ __device__ __forceinline__ void fill_block_body(const Ctx &c, int l, unsigned bi
                 if (t0 + u * NT < P) s[t0 + u * NT] = val[u];
         }
         __syncthreads();
-        if (block_sort_regs_p<NT>(s, P)) {
-            __syncthreads();
-        } else {
-            const int chunk = P / NW;             // a wave's slice
-            const bool wave_stages = chunk >= WAVE;
-            bool synced = true;                   // every wave's LDS writes seen by the block
-            for (int k = 2; k <= P; k <<= 1) {
-                for (int j = k >> 1; j > 0; j >>= 1) {
-                    if (!wave_stages || j >= chunk) {
-                        if (!synced) __syncthreads();
-                        bitonic_stage(s, 0, P / 2, k, j, threadIdx.x, NT);
-                        __syncthreads();
-                        synced = true;
-                    } else {
-                        bitonic_stage(s, wv * chunk, chunk / 2, k, j, lane, WAVE);
-                        wave_sync_lds();
-                        synced = false;
-                    }
-                }
-            }
-            if (!synced) __syncthreads();
-        }
+        block_sort<NT>(s, P);
         // leaders: first entry of each run of equal keys
         const int ipt = (P + NT - 1) / NT;
         const int t0 = threadIdx.x * ipt;
@@ -2160,7 +2174,8 @@ constexpr int LG_IDS = 4;                   // ids per thread in flight (read-ba
 constexpr int LG_ACC = 8;                   // entries per thread in flight (accumulation)
 // LG_SUM summary words per chunk (LG_WORDS = 32 * LG_SUM nonzero bitmap words at most).
 template <int NT, int LG_SUM>
-__device__ __forceinline__ void fill_large_body(const Ctx &c, int l, unsigned bid, unsigned nb) {
+__device__ __forceinline__ void fill_large_body(const Ctx &c, int l, unsigned bid, unsigned nb,
+                                                bool skip_bucketed = false) {
     constexpr int LG_WORDS = LG_SUM * 32;
     static_assert(NT >= LG_SUM && LG_WORDS % NT == 0, "chunk layout");
     constexpr int WPT = LG_WORDS / NT;       // bitmap words per thread of a chunk
@@ -2182,6 +2197,7 @@ __device__ __forceinline__ void fill_large_body(const Ctx &c, int l, unsigned bi
     for (int64_t i = bid; i < count; i += nb) {
         const int32_t x = c.cs.rows[2 * (int64_t)g.n + i];
         const RowSrc r = row_src(g, c, x);
+        if (skip_bucketed && c.huge && huge_row(nc, r.tot)) continue;   // the key buckets merge it
         // LG_ACC entries per thread in flight: their loads, renames and
         // atomics are issued before any result is waited for
         for (int64_t t0 = threadIdx.x; t0 < r.tot; t0 += (int64_t)NT * LG_ACC) {
@@ -2298,7 +2314,342 @@ __device__ __forceinline__ void fill_large_body(const Ctx &c, int l, unsigned bi
 }
 constexpr int LARGE_THREADS = 1024;   // one workgroup per hub slot (one per CU)
 __global__ void __launch_bounds__(LARGE_THREADS) fill_large_k(Ctx c, int l) {
-    fill_large_body<LARGE_THREADS, 256>(c, l, blockIdx.x, gridDim.x);
+    fill_large_body<LARGE_THREADS, 256>(c, l, blockIdx.x, gridDim.x, true);
+}
+
+// --- 2d. large rows by key buckets, in four launches ------------------------------
+// prep (a block per row): a histogram of the row's keys over HG_BINS buckets
+//   of 2^shb consecutive keys (a key occurs at most four times in a row: from
+//   u and w, each through a node and its partner, so a bucket holds at most
+//   2^(shb+2) <= 8192 entries), its exclusive scan, the groups (the buckets
+//   whose first entry falls in one window of `win` positions; win >= 256
+//   keeps at most HG_WINS groups, and a group has fewer than win + 8192 <=
+//   16384 entries), the entries scattered into bucket order in the row's
+//   staging slots, and one descriptor per group (in the small list when it
+//   has at most WR_P entries);
+// merge_small (a wave per group) and merge_big (a block per group): the group
+//   sorted and merged into hg_adj / hg_ew from its own first position on;
+// pack (a block per row): the groups' merged counts scanned, and every merged
+//   entry copied to its place in the row's staging slots.
+// Equal keys share a bucket, so runs never cross groups; the merge output is
+// in a separate array, so the copy needs no ordering between its threads.
+constexpr int HUGE_THREADS = 1024;
+constexpr int HG_U = 8;   // entries per thread in flight
+__global__ void __launch_bounds__(HUGE_THREADS) fill_huge_prep_k(Ctx c, int l) {
+    constexpr int NT = HUGE_THREADS;
+    static_assert(HG_BINS % NT == 0, "buckets per thread");
+    __shared__ int32_t hist[HG_BINS];
+    __shared__ int32_t fs[HG_WINS + 1];
+    __shared__ int64_t sh[NT / WAVE + 1];
+    __shared__ int32_t s_base, s_cnt[2];
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_CONTRACT, g)) return;
+    const int64_t nc = c.lv[l + 1].n;
+    if (nc > HUGE_NC_MAX) return;   // the dense accumulators take every large row
+    const int32_t *cmap = L->cmap;
+    int shb = 0;
+    while ((((nc > 0 ? nc : 1) - 1) >> shb) >= HG_BINS) ++shb;   // keys < nc -> buckets < HG_BINS
+    const int64_t count = c.cs.row_cnt[2];
+    const int32_t *list = class_list(c.cs, g.n, 2);
+    for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const int32_t x = list[i];
+        const RowSrc r = row_src(g, c, x);
+        if (!huge_row(nc, r.tot)) continue;   // block-uniform
+        for (int b = threadIdx.x; b < HG_BINS; b += NT) hist[b] = 0;
+        __syncthreads();
+        // histogram
+        for (int64_t t0 = threadIdx.x; t0 < r.tot; t0 += (int64_t)NT * HG_U) {
+            uint32_t k[HG_U], w[HG_U];
+#pragma unroll
+            for (int u = 0; u < HG_U; ++u) {
+                const int64_t t = t0 + (int64_t)u * NT;
+                k[u] = INVALID_KEY;
+                if (t < r.tot) row_entry(g, cmap, r, t, k[u], w[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < HG_U; ++u)
+                if (k[u] != INVALID_KEY) atomicAdd(&hist[k[u] >> shb], 1);
+        }
+        __syncthreads();
+        // exclusive scan (HG_BINS / NT consecutive buckets per thread)
+        constexpr int BPT = HG_BINS / NT;
+        int32_t cnt[BPT];
+        int64_t mine = 0;
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            cnt[q] = hist[threadIdx.x * BPT + q];
+            mine += cnt[q];
+        }
+        int64_t valid;
+        int64_t run = block_excl_scan(mine, sh, &valid);
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            hist[threadIdx.x * BPT + q] = (int32_t)run;
+            run += cnt[q];
+        }
+        __syncthreads();
+        // the groups' first positions
+        int32_t win = HG_WIN_MIN;
+        while ((int64_t)win * HG_WINS < valid) win <<= 1;
+        const int32_t nwin = (int32_t)((valid + win - 1) / win);
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            const int b = threadIdx.x * BPT + q;
+            const int32_t st = hist[b];
+            const int32_t wp = b > 0 ? hist[b - 1] / win : -1;
+            const int32_t wb = min(st / win, nwin - 1);
+            for (int32_t j = wp + 1; j <= wb; ++j) fs[j] = st;
+        }
+        if (threadIdx.x == 0) {
+            fs[nwin] = (int32_t)valid;
+            s_base = atomicAdd(&c.cs.hg_cnt[2], nwin);   // the row's group slots
+            if (i >= c.cs.hg_rows || (int64_t)s_base + nwin > c.cs.hg_cap) {   // valid state never
+                atomicOr(&c.ctrl->flags, (uint32_t)CF_STATE);
+                if (i < c.cs.hg_rows) c.cs.hg_row[i] = make_int2(-1, 0);
+                s_base = -1;
+            } else {
+                c.cs.hg_row[i] = make_int2(s_base, nwin);
+            }
+        }
+        __syncthreads();
+        if (s_base < 0) continue;   // block-uniform
+        // scatter into bucket order (hist as cursors)
+        for (int64_t t0 = threadIdx.x; t0 < r.tot; t0 += (int64_t)NT * HG_U) {
+            uint32_t k[HG_U], w[HG_U];
+#pragma unroll
+            for (int u = 0; u < HG_U; ++u) {
+                const int64_t t = t0 + (int64_t)u * NT;
+                k[u] = INVALID_KEY;
+                if (t < r.tot) row_entry(g, cmap, r, t, k[u], w[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < HG_U; ++u) {
+                if (k[u] == INVALID_KEY) continue;
+                const int32_t pos = atomicAdd(&hist[k[u] >> shb], 1);
+                const int64_t at = staged_at(r, pos);
+                c.cs.tmp_adj[at] = (int32_t)k[u];
+                c.cs.tmp_ew[at] = w[u];
+            }
+        }
+        // group descriptors: small ones (<= WR_P entries) and the others
+        if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
+        __syncthreads();
+        constexpr int WPT = (HG_WINS + NT - 1) / NT;
+        int kind[WPT], at_k[WPT];
+#pragma unroll
+        for (int q = 0; q < WPT; ++q) {
+            const int j = threadIdx.x * WPT + q;
+            kind[q] = -1;
+            if (j < nwin) {
+                const int32_t m = fs[j + 1] - fs[j];
+                kind[q] = m <= 0 ? -1 : (m <= WR_P ? 0 : 1);
+                if (kind[q] >= 0) at_k[q] = atomicAdd(&s_cnt[kind[q]], 1);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 2) {
+            const int32_t n_k = s_cnt[threadIdx.x];
+            const int32_t b_k = atomicAdd(&c.cs.hg_cnt[threadIdx.x], n_k);
+            if ((int64_t)b_k + n_k > c.cs.hg_cap) atomicOr(&c.ctrl->flags, (uint32_t)CF_STATE);
+            s_cnt[threadIdx.x] = b_k;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < WPT; ++q) {
+            const int j = threadIdx.x * WPT + q;
+            if (j >= nwin) continue;
+            const int32_t a = fs[j], m = fs[j + 1] - a;
+            c.cs.hg_slot[s_base + j] = make_int2(a, 0);
+            if (kind[q] < 0) continue;
+            int4 *lst = kind[q] == 0 ? c.cs.hg_small : c.cs.hg_big;
+            const int64_t at = (int64_t)s_cnt[kind[q]] + at_k[q];
+            if (at < c.cs.hg_cap) lst[at] = make_int4((int32_t)i, a, m, s_base + j);
+        }
+        __syncthreads();   // hist, fs and the counters are reset for the next row
+    }
+}
+
+// The merged entries of a sorted group s[0, P) (NT threads, a block or one
+// wave) into hg_adj / hg_ew at positions a, a + 1, ... of row r; returns how
+// many (every thread).  sh: NT / WAVE + 1 int64 of LDS (a block only).
+template <int NT>
+__device__ __forceinline__ int32_t hg_emit(const Ctx &c, const uint64_t *s, int P, const RowSrc &r,
+                                           int32_t a, int64_t *sh) {
+    const int tid = NT == WAVE ? lane_id() : (int)threadIdx.x;
+    const int ipt = (P + NT - 1) / NT;
+    const int t0 = tid * ipt;
+    int64_t mine = 0;
+    for (int q = 0; q < ipt; ++q) {
+        const int t = t0 + q;
+        if (t >= P) break;
+        const uint32_t k = (uint32_t)(s[t] >> 32);
+        if (k != INVALID_KEY && (t == 0 || (uint32_t)(s[t - 1] >> 32) != k)) ++mine;
+    }
+    int64_t total, rank;
+    if (NT == WAVE) {
+        const int64_t inc = wave_incl_scan(mine);
+        total = __shfl(inc, WAVE - 1, WAVE);
+        rank = inc - mine;
+    } else {
+        rank = block_excl_scan(mine, sh, &total);
+    }
+    for (int q = 0; q < ipt; ++q) {
+        const int t = t0 + q;
+        if (t >= P) break;
+        const uint32_t k = (uint32_t)(s[t] >> 32);
+        if (k == INVALID_KEY || (t > 0 && (uint32_t)(s[t - 1] >> 32) == k)) continue;
+        uint32_t sum = 0;
+        for (int e = t; e < P && (uint32_t)(s[e] >> 32) == k; ++e) sum += (uint32_t)s[e];
+        const int64_t at = staged_at(r, a + rank);
+        c.cs.hg_adj[at] = (int32_t)k;
+        c.cs.hg_ew[at] = sum;
+        ++rank;
+    }
+    return (int32_t)total;
+}
+
+// Groups of at most WR_P entries: one wave each, sorted in registers.
+__global__ void __launch_bounds__(BLOCK) fill_huge_small_k(Ctx c, int l) {
+    __shared__ uint64_t lds[(BLOCK / WAVE) * WR_P];
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_CONTRACT, g)) return;
+    if (c.lv[l + 1].n > HUGE_NC_MAX) return;
+    const int wv = threadIdx.x / WAVE, lane = lane_id();
+    uint64_t *sl = lds + wv * WR_P;
+    const int32_t *list = class_list(c.cs, g.n, 2);
+    const int64_t count = min<int64_t>(c.cs.hg_cnt[0], c.cs.hg_cap);
+    for (int64_t q = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv; q < count;
+         q += (int64_t)gridDim.x * (BLOCK / WAVE)) {   // wave-uniform
+        const int4 d = c.cs.hg_small[q];
+        const RowSrc r = row_src(g, c, list[d.x]);
+        const int32_t a = d.y, m = d.z;
+        int P = WAVE;
+        while (P < m) P <<= 1;
+        for (int t = lane; t < P; t += WAVE) {
+            uint64_t v = ~0ull;
+            if (t < m) {
+                const int64_t at = staged_at(r, a + t);
+                v = ((uint64_t)(uint32_t)c.cs.tmp_adj[at] << 32) | c.cs.tmp_ew[at];
+            }
+            sl[t] = v;
+        }
+        wave_sync_lds();
+        if (P == WAVE) block_sort_regs<1, WAVE>(sl, lane);
+        else if (P == 2 * WAVE) block_sort_regs<2, WAVE>(sl, lane);
+        else if (P == 4 * WAVE) block_sort_regs<4, WAVE>(sl, lane);
+        else block_sort_regs<8, WAVE>(sl, lane);
+        wave_sync_lds();
+        const int32_t merged = hg_emit<WAVE>(c, sl, P, r, a, nullptr);
+        if (lane == 0) c.cs.hg_slot[d.w].y = merged;
+        wave_sync_lds();   // the slice is reloaded for the wave's next group
+    }
+}
+
+// The larger groups: one block each.
+__global__ void __launch_bounds__(HUGE_THREADS) fill_huge_big_k(Ctx c, int l) {
+    constexpr int NT = HUGE_THREADS;
+    __shared__ uint64_t s[BIG_P];
+    __shared__ int64_t sh[NT / WAVE + 1];
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_CONTRACT, g)) return;
+    if (c.lv[l + 1].n > HUGE_NC_MAX) return;
+    const int32_t *list = class_list(c.cs, g.n, 2);
+    const int64_t count = min<int64_t>(c.cs.hg_cnt[1], c.cs.hg_cap);
+    for (int64_t q = blockIdx.x; q < count; q += gridDim.x) {   // block-uniform
+        const int4 d = c.cs.hg_big[q];
+        const RowSrc r = row_src(g, c, list[d.x]);
+        const int32_t a = d.y, m = d.z;
+        int P = 2;
+        while (P < m) P <<= 1;
+        if (P > BIG_P) {   // valid groups never
+            if (threadIdx.x == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_STATE);
+            continue;
+        }
+        for (int t0 = threadIdx.x; t0 < P; t0 += NT * 4) {
+            uint64_t val[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + u * NT;
+                val[u] = ~0ull;
+                if (t < m) {
+                    const int64_t at = staged_at(r, a + t);
+                    val[u] = ((uint64_t)(uint32_t)c.cs.tmp_adj[at] << 32) | c.cs.tmp_ew[at];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (t0 + u * NT < P) s[t0 + u * NT] = val[u];
+        }
+        __syncthreads();
+        block_sort<NT>(s, P);
+        const int32_t merged = hg_emit<NT>(c, s, P, r, a, sh);
+        if (threadIdx.x == 0) c.cs.hg_slot[d.w].y = merged;
+        __syncthreads();   // s is reloaded for the block's next group
+    }
+}
+
+// Each large row's merged groups packed from position 0 on.
+__global__ void __launch_bounds__(HUGE_THREADS) fill_huge_pack_k(Ctx c, int l) {
+    constexpr int NT = HUGE_THREADS;
+    constexpr int WPT = (HG_WINS + NT - 1) / NT;
+    __shared__ int32_t off[HG_WINS + 1], first[HG_WINS];
+    __shared__ int64_t sh[NT / WAVE + 1];
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_CONTRACT, g)) return;
+    const int64_t nc = c.lv[l + 1].n;
+    if (nc > HUGE_NC_MAX) return;
+    const int64_t count = c.cs.row_cnt[2];
+    const int32_t *list = class_list(c.cs, g.n, 2);
+    for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const int32_t x = list[i];
+        const RowSrc r = row_src(g, c, x);
+        if (!huge_row(nc, r.tot)) continue;   // block-uniform
+        if (i >= c.cs.hg_rows) continue;   // flagged by the prep
+        const int2 ri = c.cs.hg_row[i];
+        if (ri.x < 0 || ri.y > HG_WINS || (int64_t)ri.x + ri.y > c.cs.hg_cap) continue;
+        const int32_t nwin = ri.y;
+        int32_t gv[WPT];
+        int64_t gsum = 0;
+#pragma unroll
+        for (int q = 0; q < WPT; ++q) {
+            const int j = threadIdx.x * WPT + q;
+            gv[q] = 0;
+            if (j < nwin) {
+                const int2 sl = c.cs.hg_slot[ri.x + j];
+                first[j] = sl.x;
+                gv[q] = sl.y;
+            }
+            gsum += gv[q];
+        }
+        int64_t total;
+        int64_t o = block_excl_scan(gsum, sh, &total);
+#pragma unroll
+        for (int q = 0; q < WPT; ++q) {
+            const int j = threadIdx.x * WPT + q;
+            if (j < nwin) off[j] = (int32_t)o;
+            o += gv[q];
+        }
+        if (threadIdx.x == 0) off[nwin] = (int32_t)total;
+        __syncthreads();
+        for (int64_t p = threadIdx.x; p < total; p += NT) {
+            int lo = 0, hi = nwin - 1;   // the group holding output position p
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (off[mid] <= p) lo = mid;
+                else hi = mid - 1;
+            }
+            const int64_t src = staged_at(r, first[lo] + (p - off[lo]));
+            const int64_t dst = staged_at(r, p);
+            c.cs.tmp_adj[dst] = c.cs.hg_adj[src];
+            c.cs.tmp_ew[dst] = c.cs.hg_ew[src];
+        }
+        if (threadIdx.x == 0) c.cs.cdeg[x] = (int32_t)total;
+        __syncthreads();   // off and first are rewritten for the next row
+    }
 }
 
 // --- 4. compaction ----------------------------------------------------------------
@@ -2986,6 +3337,25 @@ void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, h
         KAPPA_PROF("fill_big", s);
         hipLaunchKernelGGL(fill_big_k, dim3(grid_for(n_hint, 4096, 256)), dim3(BIG_THREADS), 0, s,
                            c, l);
+    }
+    if (c.huge) {
+        const unsigned rows = grid_for(n_hint, 4096, 512);
+        {
+            KAPPA_PROF("fill_huge_prep", s);
+            hipLaunchKernelGGL(fill_huge_prep_k, dim3(rows), dim3(HUGE_THREADS), 0, s, c, l);
+        }
+        {
+            KAPPA_PROF("fill_huge_small", s);
+            hipLaunchKernelGGL(fill_huge_small_k, dim3(grid_for(n_hint, 256, 2048)), dim3(BLOCK), 0,
+                               s, c, l);
+        }
+        {
+            KAPPA_PROF("fill_huge_big", s);
+            hipLaunchKernelGGL(fill_huge_big_k, dim3(grid_for(n_hint, 16384, 256)),
+                               dim3(HUGE_THREADS), 0, s, c, l);
+        }
+        KAPPA_PROF("fill_huge_pack", s);
+        hipLaunchKernelGGL(fill_huge_pack_k, dim3(rows), dim3(HUGE_THREADS), 0, s, c, l);
     }
     if (c.cs.hub_acc) {
         KAPPA_PROF("fill_large", s);

@@ -45,6 +45,15 @@ constexpr int ROW_SMALL_G = 16;
 constexpr int ROW_WAVE_MAX = 512;   // one wave per row, bitonic sort of <= 512 in LDS
 constexpr int ROW_MID_MAX = 4094;   // one block per row, bitonic sort of <= 4096 in LDS
 constexpr int ROW_BIG_MAX = 16382;  // one 1024-thread block per row, sort of <= 16384 in LDS
+// Rows above ROW_BIG_MAX (large rows) are merged by key buckets when the
+// next level has at most HUGE_NC_MAX nodes and the row at most HUGE_ROW_MAX
+// entries; the others by dense hub accumulators, which only graphs of more
+// than HUGE_NC_MAX nodes allocate.
+constexpr int HG_BINS = 4096;                       // key buckets of a row
+constexpr int HG_WINS = 2048;                       // groups per row at most
+constexpr int HG_WIN_MIN = 256;                     // positions per group window (at least)
+constexpr int64_t HUGE_NC_MAX = (int64_t)HG_BINS << 11;   // buckets of at most 2^11 keys
+constexpr int64_t HUGE_ROW_MAX = (int64_t)HG_WINS * 8192;
 constexpr int HUB_SLOTS = 32;       // rows above ROW_MID_MAX: dense accumulators (at least)
 constexpr int HUB_SLOTS_MAX = 256;  //   and at most, within HUB_BUDGET bytes of accumulators
 constexpr int64_t HUB_BUDGET = (int64_t)4 << 30;
@@ -659,6 +668,19 @@ struct ContractScratch {
                           // bitmap (hub_w1 words), then its summary (a bit per word)
     int64_t hub_words, hub_w1;
     int32_t hub_slots;    // rows merged at once in the hub accumulators
+    // large rows by key buckets (null unless Ctx::huge): the groups merged
+    // where they lie in hg_adj / hg_ew (the staging positions' twins), group
+    // lists by size, per group slot its first position and merged count, per
+    // large row its first slot and group count; hg_cnt: small groups, large
+    // groups, slots (zero between levels)
+    int32_t *hg_adj;      // nnz
+    uint32_t *hg_ew;      // nnz
+    int4 *hg_small;       // hg_cap: row list index, first position, size, slot
+    int4 *hg_big;         // hg_cap
+    int2 *hg_slot;        // hg_cap
+    int2 *hg_row;         // hg_rows
+    int32_t *hg_cnt;      // 4
+    int64_t hg_cap, hg_rows;
 };
 
 // Batched form: per-graph stop rules on a disjoint union of `count` graphs.
@@ -699,7 +721,8 @@ struct Ctx {
     int32_t block_bits = -1;   // >= 0: two-phase matcher with blocks of 2^block_bits ids
     int32_t big_blocks = 64;   // blocks per round launch for rows above BIN_MID_MAX entries
     int32_t big_rows = 1;      // 1: rows of 4095..16382 entries get the big-row sort launch;
-                               // 0: they join the large rows (hub accumulators)
+                               // 0: they join the large rows
+    int32_t huge = 0;          // 1: large rows get the key-bucket merge launches
 };
 
 // K bump allocations in the arena with one read and one write of the cursor
