@@ -345,6 +345,9 @@ def main():
                          "own (0: one engine per rating)")
     ap.add_argument("--uploaders", type=int, default=2, help="serve: upload threads of the "
                                                              "level-granular server")
+    ap.add_argument("--persistent", action="store_true",
+                    help="run a level's matching rounds after the first in one cooperative launch "
+                         "(kappa_persistent_enable; the library's default is a launch per round)")
     ap.add_argument("--graphs", action="store_true",
                     help="replay repeated launch sequences as HIP graphs (kappa_graphs_enable; "
                          "the library's default is direct launches)")
@@ -384,9 +387,10 @@ def main():
     import paper_0910_2004_amd as K
     from workloads import rgg
 
-    if args.graphs:
+    if args.graphs or args.persistent:
         import paper_0910_2004_amd as K
-        K.graphs_enable(True)
+        K.graphs_enable(args.graphs)
+        K.persistent_enable(args.persistent)
     if args.workload == "batch4096":
         return bench_batch(args)
     if args.workload == "serve":
@@ -609,6 +613,7 @@ def single_graph(args, rmat_mode, primary):
                    "node_order": args.order, "block_bits": args.block_bits,
                    "relabel_ms": relabel_ms,
                    "ratings_concurrent": not args.serial_ratings, "graph_replay": bool(args.graphs),
+                   "persistent_rounds": bool(args.persistent),
                    "n": g.n, "m": g.m, "edges_per_step": edges_step, "k": k, "stop_n": stop_n,
                    "seed": seed, "graph_seed": (3, 33) if rmat_mode else 2, "levels_n": levels},
         "roofline": roof,
@@ -704,7 +709,7 @@ def bench_batch(args):
                                "of edges, half rgg mean degree 8, weights uniform [1, 16], "
                                "expansion*2, stop n<=256 per graph",
                    "graphs": len(graphs), "n": du.n, "m": edges, "seed": 4,
-                   "graph_replay": bool(args.graphs),
+                   "graph_replay": bool(args.graphs), "persistent_rounds": bool(args.persistent),
                    "levels_max": int(max(levels)), "levels_mean": round(float(np.mean(levels)), 2)},
         "plain_loop": None if plain is None else
         {"ms": round(plain, 1), "value": round(edges / (plain / 1e3), 1), "unit": "edges/s",

@@ -502,6 +502,21 @@ void kappa_arena_first(uint64_t bytes);
    kernels.  Results do not depend on it. */
 void kappa_tail_enable(int32_t on);
 
+/* on = 1: the matching rounds after the first of a level run in one
+   cooperative launch (every workgroup resident; the pick and mate phases of
+   a round separated by grid-wide barriers whose waits are bounded, so a
+   broken state fails the call with KAPPA_E_HIP rather than hang), on levels
+   whose long rows are not scanned in chunks; the others, and every level
+   when the device cannot launch it, keep one launch per phase and round.
+   on = 0 (the default, measured faster: 8.7 against 21.2 ms per step on the
+   random geometric graph of 2^20 nodes, 86.9 against 99.3 ms on the batch of
+   4096 graphs) launches every round's kernels.  Results do not depend on it.
+   A cooperative launch needs the device to itself: with kernels of other
+   streams running beside it, some of its workgroups may not be resident,
+   its barrier waits time out and the call fails with KAPPA_E_HIP.  HIP-graph
+   replay is not used while it is on. */
+void kappa_persistent_enable(int32_t on);
+
 /* Tunable thresholds of the level kernels.  None changes a result (every
    hierarchy and partition is the same under any valid table); they move
    work between kernels.  Valid ranges in brackets; the compiled defaults in

@@ -15,6 +15,6 @@ from ._lib import (  # noqa: F401
     kappa_initial_partition, kappa_project, kappa_cut_balance, kappa_cut_balance_noalloc,
     kappa_uncoarsen, kappa_cache_release,
     kappa_refine, kappa_uncoarsen_refined, refine_params, REFINE_PRESETS, REFINE_K_MAX,
-    graphs_enable, tail_enable, arena_first, use_torch_allocator, profile_enable, profile_reset, profile_read,
+    graphs_enable, tail_enable, persistent_enable, arena_first, use_torch_allocator, profile_enable, profile_reset, profile_read,
     tuning_get, tuning_set, tuning_load, TUNING_FIELDS,
 )

@@ -179,6 +179,7 @@ def lib():
         "kappa_server_active": (i32, [P]),
         "kappa_server_step": (st, [P, P, i32, ctypes.POINTER(i32)]),
         "kappa_server_interrupt": (st, [P, i32]),
+        "kappa_persistent_enable": (None, [i32]),
         "kappa_tuning_get": (st, [ctypes.POINTER(c_tuning)]),
         "kappa_tuning_set": (st, [ctypes.POINTER(c_tuning)]),
         "kappa_tuning_load": (st, [ctypes.c_char_p]),
@@ -773,6 +774,12 @@ def use_torch_allocator(on: bool = True):
     else:
         _check("kappa_set_allocator", lib().kappa_set_allocator(_ALLOC_FN(), _FREE_FN(), None))
         _allocator = None
+
+
+def persistent_enable(on: bool = True):
+    """Run a level's matching rounds after the first in one cooperative
+    launch (on) or one launch per phase and round (off, the default)."""
+    lib().kappa_persistent_enable(1 if on else 0)
 
 
 def tail_enable(on: bool = True):

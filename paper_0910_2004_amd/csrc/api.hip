@@ -480,7 +480,7 @@ constexpr size_t KEEP_GRAPHS = 24, KEEP_SEEN = 48;
 
 template <class E>
 hipError_t run_seq(StreamCache *c, hipStream_t s, const std::vector<uint64_t> &key, E &&enqueue) {
-    if (!g_graphs_on || g_prof.on) {
+    if (!g_graphs_on || g_prof.on || g_persistent_on) {   // cooperative launches are not captured
         enqueue(s);
         return hipGetLastError();
     }
@@ -687,6 +687,7 @@ void carve_scratch(Carve &cv, const DevGraph &g, int rating, bool hubs, Ctx &c,
     ms.out = rating == KAPPA_INNER_OUTER ? cv.get<uint32_t>(g.n) : nullptr;
     ms.tile_row = rating == KAPPA_INNER_OUTER ? cv.get<int32_t>(tile_rows_needed(g.nnz)) : nullptr;
     ms.state = cv.get<MatchState>(1);
+    ms.coop_bar = cv.get<unsigned>(2 + ARRIVE_WORDS);
     cs.rep_of = cv.get<int32_t>(g.n);
     cs.partner = cv.get<int32_t>(g.n);
     cs.cdeg = cv.get<int32_t>(g.n);
@@ -738,6 +739,7 @@ void fill_scratch(const DevGraph &g, const Ctx &c, hipStream_t s) {
     z.add(c.cs.arrive, ARRIVE_WORDS);
     z.add(c.cs.row_cnt, 8);
     z.add(c.cs.totals, 4 * 2);
+    z.add(c.ms.coop_bar, 2 + ARRIVE_WORDS);
     z.add(c.cs.hg_cnt, 4);
     // the matching state: list counters, round statistics, merge counts
     static_assert(sizeof(MatchState) % 4 == 0, "zeroed as words");
@@ -2529,6 +2531,7 @@ extern "C" void kappa_graphs_enable(int32_t on) { g_graphs_on = on != 0; }
 extern "C" void kappa_arena_first(uint64_t bytes) { g_arena_first.store(bytes); }
 
 extern "C" void kappa_tail_enable(int32_t on) { g_tail_on = on != 0; }
+extern "C" void kappa_persistent_enable(int32_t on) { g_persistent_on = on != 0; }
 
 extern "C" const char *kappa_status_str(kappa_status st) {
     switch (st) {

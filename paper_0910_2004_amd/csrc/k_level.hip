@@ -3183,6 +3183,120 @@ static void launch_later_round(const Ctx &c, int l, int r, const PickGrid &pg, i
     hipLaunchKernelGGL((mate_k<R, false>), dim3(list_blocks), dim3(BLOCK), 0, s, c, l, r);
 }
 
+// ---------------------------------------------------------------------------
+// Persistent matching rounds (opt-in, kappa_persistent_enable): rounds 2, 3,
+// ... of a level in one cooperative launch (every block resident), the pick
+// and mate phases of a round separated by grid barriers, until the pending
+// set is empty or small enough for the finisher (the same hand-over tests as
+// the round kernels) or r_cap rounds have run.  Levels whose long rows are
+// scanned in chunks (power-law graphs) keep the round kernels.
+// ---------------------------------------------------------------------------
+bool g_persistent_on = false;
+constexpr int COOP_SPIN_LIMIT = 1 << 24;   // polls before a barrier wait gives up
+
+// Grid barrier: bar[0] the generation, bar[1] the groups arrived, bar[2 + g]
+// the blocks of group g arrived (groups of ARRIVE_GROUP blocks).  The last
+// arrival resets the counters and advances the generation.  A wait is
+// bounded: after COOP_SPIN_LIMIT polls the block flags CF_STATE and returns
+// false (the call then fails), so no wave spins forever.
+__device__ __forceinline__ bool grid_barrier(unsigned *bar, uint32_t *flags) {
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned gen0 = __hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();   // this block's writes before its arrival
+        const unsigned nb = gridDim.x, grp = blockIdx.x / ARRIVE_GROUP;
+        const unsigned ngrp = (nb + ARRIVE_GROUP - 1) / ARRIVE_GROUP;
+        const unsigned gsz = min((unsigned)ARRIVE_GROUP, nb - grp * ARRIVE_GROUP);
+        bool last = false;
+        if (atomicAdd(&bar[2 + grp], 1u) == gsz - 1) {
+            atomicExch(&bar[2 + grp], 0u);
+            if (atomicAdd(&bar[1], 1u) == ngrp - 1) {
+                atomicExch(&bar[1], 0u);
+                last = true;
+            }
+        }
+        if (last) {
+            __threadfence();
+            atomicAdd(&bar[0], 1u);
+        } else {
+            int spins = 0;
+            while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen0) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > COOP_SPIN_LIMIT) {
+                    atomicOr(flags, (uint32_t)CF_STATE);
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        __threadfence();   // the other blocks' writes before this block goes on
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+template <int R>
+__global__ void __launch_bounds__(BLOCK) rounds_coop_k(Ctx c, int l, int r_first, int r_cap,
+                                                       PickGrid pg) {
+    __shared__ Cand shc[BLOCK / WAVE];
+    __shared__ int64_t sh[3 * (BLOCK / WAVE) + 1];
+    __shared__ int32_t sbase[3];
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_MATCH, g)) return;   // the same for every block
+    MatchState *st = c.ms.state;
+    const uint64_t seed = level_seed(c, l);
+    for (int r = r_first; r <= r_cap; ++r) {
+        // every block reads the same state after a barrier: uniform exits
+        if (__hip_atomic_load(&st->handoff, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != -1) return;
+        const RoundIn ri = round_inputs<false>(c, g, r, st->cnt[(r - 1) & 3]);
+        const int64_t total = (int64_t)ri.cn[0] + ri.cn[1] + ri.cn[2];
+        if (total == 0 || total <= c.t.tail_max) {
+            if (blockIdx.x == 0 && threadIdx.x == 0)
+                atomicCAS(&st->handoff, -1, total == 0 ? -2 : r - 1);
+            return;
+        }
+        unsigned bid = blockIdx.x;
+        if (bid < pg.b0) {
+            pick_bin0<R, false>(c, g, seed, ri, bid, pg.b0);
+        } else if ((bid -= pg.b0) < pg.b1) {
+            pick_bin1<R, false>(c, g, seed, ri, bid, pg.b1);
+        } else {
+            bid -= pg.b1;
+            pick_bin2<R, false, BLOCK>(c, g, seed, ri, bid, pg.b2, shc);
+        }
+        if (!grid_barrier(c.ms.coop_bar, &c.ctrl->flags)) return;
+        if (blockIdx.x == 0 && threadIdx.x < 4) {   // as mate_k
+            st->cnt[(r + 2) & 3][threadIdx.x] = 0;
+            st->scnt[(r + 2) & 3][threadIdx.x] = 0;
+        }
+        mate_phase<R, false>(c, g, L, r, ri, st->cnt[r & 3], blockIdx.x, gridDim.x, sh, sbase);
+        if (!grid_barrier(c.ms.coop_bar, &c.ctrl->flags)) return;
+    }
+}
+
+// Blocks of a cooperative launch of rounds_coop_k<R> on this device (every
+// block resident), cached per rating.
+template <int R>
+static unsigned coop_blocks() {
+    static unsigned cached[64] = {};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev < 0 || dev >= 64) return 0;
+    if (!cached[dev]) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rounds_coop_k<R>, BLOCK, 0) !=
+                hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cached[dev] = (unsigned)std::min<int64_t>((int64_t)per_cu * cus, ARRIVE_MAX_BLOCKS);
+    }
+    return cached[dev];
+}
+
 template <int R>
 static void match_impl(const Ctx &c, int l, int32_t n_hint, int rounds, hipStream_t s) {
     // per-round kernels; round r's grid follows a geometric estimate of the
@@ -3190,8 +3304,38 @@ static void match_impl(const Ctx &c, int l, int32_t n_hint, int rounds, hipStrea
     // power-law graphs keep most of their pending nodes for many rounds (hubs
     // wait on each other), so their grids do not shrink with the rounds
     const double decay = c.big_blocks > 64 ? 1.0 : 0.7;
+    const unsigned coop = g_persistent_on && !c.ms.hub.rec ? coop_blocks<R>() : 0;
     double est = n_hint;
     for (int r = 1; r <= rounds; ++r, est *= decay) {
+        if (r == 2 && coop >= 16) {
+            // the later rounds in one persistent launch (if it cannot be
+            // launched, the round kernels go on)
+            const unsigned nb = std::min<unsigned>(coop, grid_for((int64_t)est + 1, BLOCK / SMALL_G,
+                                                                  4096));
+            PickGrid cg;
+            cg.b2 = std::max(1u, std::min(64u, nb / 16));
+            cg.b1 = std::max(1u, std::min(256u, nb / 4));
+            cg.b0 = nb > cg.b1 + cg.b2 + 1 ? nb - cg.b1 - cg.b2 : 1;
+            const unsigned grid = cg.b0 + cg.b1 + cg.b2;
+            const int r_cap = std::max(rounds, STAT_ROUNDS - 2);
+            if (grid <= coop) {
+                hipError_t e;
+                {
+                    KAPPA_PROF("rounds_persistent", s);
+                    Ctx cc = c;
+                    int ll = l, r0 = 2, rc = r_cap;
+                    void *args[] = {&cc, &ll, &r0, &rc, &cg};
+                    e = hipLaunchCooperativeKernel((const void *)rounds_coop_k<R>, dim3(grid),
+                                                   dim3(BLOCK), args, 0, s);
+                }
+                if (e == hipSuccess) {
+                    KAPPA_PROF("match_finish", s);
+                    hipLaunchKernelGGL(finish_k<R>, dim3(1), dim3(FINISH_THREADS), 0, s, c, l, r_cap);
+                    return;
+                }
+                (void)hipGetLastError();   // not launched: no state changed
+            }
+        }
         int64_t e = (int64_t)est + 1;
         PickGrid pg;
         pg.b0 = grid_for(e, BLOCK / SMALL_G, 2048);

@@ -648,6 +648,7 @@ struct MatchScratch {
     int32_t *loc;           // two-phase: n, the block phase's partner (-1: none)
     LocKey *lkey;           // two-phase: n, the key of that edge
     HubChunks hub;          // rec == nullptr: long rows are scanned by one block each
+    unsigned *coop_bar;     // 2 + ARRIVE_WORDS: the persistent rounds' grid barrier (zero)
 };
 
 // Contraction scratch (sized for level 0).
@@ -871,6 +872,7 @@ void launch_batch_extract(const DevGraph &u, const int32_t *cmap, const int32_t 
 // for kappa_match.  out_kernels: compute Out(v) (innerOuter) from the graph;
 // otherwise it must already be in the scratch (written by the previous
 // level's compaction).  Needs st->cnt zero on entry.
+extern bool g_persistent_on;   // matching rounds of a level in one cooperative launch
 void launch_level_match(const Ctx &c, int l, int32_t n_hint, int64_t nnz_cap, int rounds,
                         bool stop_rules, bool out_kernels, hipStream_t s);
 // k_sort.hip: stable LSD radix sort of n < 2^31 (key, 32-bit value) pairs by
