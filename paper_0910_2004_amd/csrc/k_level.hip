@@ -2693,16 +2693,50 @@ __device__ __forceinline__ void compact_small_body(const Ctx &c, int l, unsigned
     }
 }
 
+// Rows of 65..512 entries (class 1): one wave each.
 template <int NT>
-__device__ __forceinline__ void compact_big_body(const Ctx &c, int l, unsigned bid, unsigned nb) {
+__device__ __forceinline__ void compact_wave_body(const Ctx &c, int l, unsigned bid, unsigned nb) {
+    DevGraph g;
+    LevelDesc *L = c.lv + l;
+    if (!load_level(L, PH_COMPACT, g)) return;
+    const LevelDesc *N = c.lv + l + 1;
+    uint32_t *out = c.rating == KAPPA_INNER_OUTER ? c.ms.out : nullptr;
+    const int64_t c1 = c.cs.row_cnt[1];
+    const int32_t *list = class_list(c.cs, g.n, 1);
+    const int lane = lane_id();
+    for (int64_t i = (int64_t)bid * (NT / WAVE) + threadIdx.x / WAVE; i < c1;
+         i += (int64_t)nb * (NT / WAVE)) {   // wave-uniform
+        const int32_t x = list[i];
+        const RowSrc r = row_src(g, c, x);
+        const int64_t dst = N->xadj[x];
+        const int32_t len = c.cs.cdeg[x];
+        uint32_t sum = 0;
+        for (int t = lane; t < len; t += WAVE) {
+            const int64_t at = staged_at(r, t);
+            const uint32_t w = c.cs.tmp_ew[at];
+            N->adj[dst + t] = c.cs.tmp_adj[at];
+            N->ew[dst + t] = w;
+            sum += w;
+        }
+        if (out) {
+            sum = wave_sum(sum);
+            if (lane == 0) out[x] = sum;
+        }
+    }
+}
+
+// Rows of the classes above (from `first_cls`): one block each.
+template <int NT>
+__device__ __forceinline__ void compact_big_body(const Ctx &c, int l, unsigned bid, unsigned nb,
+                                                 int first_cls = 1) {
     __shared__ uint32_t sh[NT / WAVE + 1];
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_COMPACT, g)) return;
     const LevelDesc *N = c.lv + l + 1;
     uint32_t *out = c.rating == KAPPA_INNER_OUTER ? c.ms.out : nullptr;
-    const int64_t c1 = c.cs.row_cnt[1], c2 = c.cs.row_cnt[2], c3 = c.cs.row_cnt[3],
-                  c4 = c.cs.row_cnt[4];
+    const int64_t c1 = first_cls <= 1 ? c.cs.row_cnt[1] : 0, c2 = c.cs.row_cnt[2],
+                  c3 = c.cs.row_cnt[3], c4 = c.cs.row_cnt[4];
     for (int64_t i = bid; i < c1 + c2 + c3 + c4; i += nb) {
         const int32_t x = i < c1 ? class_list(c.cs, g.n, 1)[i]
                         : i < c1 + c2 ? class_list(c.cs, g.n, 2)[i - c1]
@@ -2725,13 +2759,18 @@ __device__ __forceinline__ void compact_big_body(const Ctx &c, int l, unsigned b
         }
     }
 }
-// Both row kinds in one launch: blocks [0, small_blocks) copy the small rows,
-// the rest the rows of the mid and large classes.
-__global__ void __launch_bounds__(BLOCK) compact_k(Ctx c, int l, unsigned small_blocks) {
+// Every row kind in one launch: blocks [0, small_blocks) copy the small rows,
+// the next wave_blocks the rows of 65..512 entries a wave each, the rest the
+// longer rows a block each.
+__global__ void __launch_bounds__(BLOCK) compact_k(Ctx c, int l, unsigned small_blocks,
+                                                   unsigned wave_blocks) {
     if (blockIdx.x < small_blocks)
         compact_small_body<BLOCK>(c, l, blockIdx.x, small_blocks);
+    else if (blockIdx.x < small_blocks + wave_blocks)
+        compact_wave_body<BLOCK>(c, l, blockIdx.x - small_blocks, wave_blocks);
     else
-        compact_big_body<BLOCK>(c, l, blockIdx.x - small_blocks, gridDim.x - small_blocks);
+        compact_big_body<BLOCK>(c, l, blockIdx.x - small_blocks - wave_blocks,
+                                gridDim.x - small_blocks - wave_blocks, 2);
 }
 
 // ===========================================================================
@@ -3509,8 +3548,9 @@ void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, h
                 c.cs.totals + 2, s);
     {
         KAPPA_PROF("compact", s);
-        const unsigned sb = grid_for(n_hint, SM_ROWS * 2, 4096), bb = grid_for(n_hint, 64, 2048);
-        hipLaunchKernelGGL(compact_k, dim3(sb + bb), dim3(BLOCK), 0, s, c, l, sb);
+        const unsigned sb = grid_for(n_hint, SM_ROWS * 2, 4096), wb = grid_for(n_hint, 256, 1024),
+                       bb = grid_for(n_hint, 1024, 512);
+        hipLaunchKernelGGL(compact_k, dim3(sb + wb + bb), dim3(BLOCK), 0, s, c, l, sb, wb);
     }
     (void)n_cap;
 }
