@@ -639,16 +639,19 @@ kappa_status validate_impl(const DevGraph &g, hipStream_t s, int32_t *maxdeg_out
     static_assert(sizeof(RB) % 4 == 0, "zeroed as words");
     RB *dv = nullptr;
     int32_t *tr = nullptr;
+    char *sort_ws = nullptr;
+    const size_t sort_bytes = trusted ? 0 : val_sort_ws_bytes(g.n, g.nnz);
     std::unique_ptr<Workspace> w;
     bool ok = carve_workspace(s, w, [&](Carve &cv) {
         dv = cv.get<RB>(1);
         tr = cv.get<int32_t>(tile_rows_needed(g.nnz));
+        sort_ws = sort_bytes ? cv.get<char>((int64_t)sort_bytes) : nullptr;
     });
     if (!ok) return KAPPA_E_NOMEM;
     ZeroRanges z;
     z.add(dv, sizeof(RB) / 4);
     launch_zero(z, s);
-    launch_validate(g, tr, &dv->flags, dv->sums, dv->mdeg, s, trusted);
+    launch_validate(g, tr, &dv->flags, dv->sums, dv->mdeg, s, trusted, sort_ws);
     RB *rb = (RB *)pinned(sizeof(RB));
     if (!rb) return KAPPA_E_NOMEM;
     HIPCHK(hipMemcpyAsync(rb, dv, sizeof(RB), hipMemcpyDeviceToHost, s));

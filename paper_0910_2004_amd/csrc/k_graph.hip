@@ -189,8 +189,10 @@ __global__ void __launch_bounds__(BLOCK) validate_offsets_k(DevGraph g, uint32_t
     if (wbad && lane_id() == 0) atomicOr(flags, 1u);
 }
 
-// The reverse-entry check runs the binary searches of a thread's entries in
-// lockstep, so their loads overlap.
+// SEARCH: the reverse-entry check by binary searches (a thread's searches
+// in lockstep, so their loads overlap); otherwise the sorted check below
+// does it and this pass keeps the local checks and the counts.
+template <bool SEARCH>
 __global__ void __launch_bounds__(BLOCK) validate_entries_k(DevGraph g, const int32_t *tile_row,
                                                             uint32_t *flags, uint64_t *sums) {
     __shared__ int64_t s_off[ETILE_ROWS + 1];
@@ -227,6 +229,7 @@ __global__ void __launch_bounds__(BLOCK) validate_entries_k(DevGraph g, const in
             if (u > v) { wsum += w; uu[i] = u; ++above; }
             else ++below;
         }
+        if (!SEARCH) continue;
         for (int i = 0; i < ETILE_ITEMS; ++i)
             if (uu[i] >= 0) { lo[i] = g.xadj[uu[i]]; len[i] = g.xadj[uu[i] + 1] - lo[i]; }
         // lower_bound of v in row u, all searches advanced together
@@ -260,8 +263,98 @@ __global__ void __launch_bounds__(BLOCK) validate_entries_k(DevGraph g, const in
     if (bad && lane_id() == 0) atomicOr(flags, bad);
 }
 
+// Sorted reverse-entry check (large graphs): the entries below the diagonal,
+// in CSR order, are sorted by (row, neighbour); the entries above it,
+// written as keys (neighbour << shift | row) and sorted, must equal them one
+// for one, weights included.  With no duplicates in a row and as many
+// entries above as below (both checked by the entry pass), that is the
+// symmetry test.  Random searches into other rows (one cache line per step)
+// become sequential passes and a radix sort.
+// low[v]: entries of row v below the diagonal (a binary search for v in row v).
+__global__ void __launch_bounds__(BLOCK) val_low_k(DevGraph g, const uint32_t *flags, int64_t *low) {
+    if (flags[0] & 1u) return;   // offsets broken
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = g.xadj[v], len = g.xadj[v + 1] - lo;
+        const int64_t b = lo;
+        while (len > 0) {
+            const int64_t half = len >> 1;
+            if (g.adj[lo + half] < v) { lo += half + 1; len -= half + 1; }
+            else len = half;
+        }
+        low[v] = lo - b;
+    }
+}
+// The entries above the diagonal as sorted-check keys; row v's occupy
+// positions from xadj[v] - lowstart[v] (the entries above the diagonal of
+// the rows before v) on.
+__global__ void __launch_bounds__(BLOCK) val_upper_k(DevGraph g, const int32_t *tile_row,
+                                                     uint32_t *flags, const int64_t *low,
+                                                     const int64_t *lowstart, int shift,
+                                                     int64_t cap, uint64_t *key, uint32_t *val) {
+    __shared__ int64_t s_off[ETILE_ROWS + 1];
+    if (flags[0] & 1u) return;
+    const int64_t ntiles = etiles(g.nnz);
+    uint32_t bad = 0;
+    for (int64_t tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
+        TileCtx t = tile_begin(g, tile_row, tt, s_off);
+        for (int i = 0; i < ETILE_ITEMS; ++i) {
+            const int64_t j = t.j0 + (int64_t)i * BLOCK + threadIdx.x;
+            if (j >= t.j1) continue;
+            const int32_t v = tile_row_of(g, t, s_off, j);
+            const int32_t u = g.adj[j];
+            if (u <= v || u >= g.n) continue;   // below the diagonal, or flagged by the entry pass
+            const int64_t rs = tile_row_start(g, t, s_off, v);
+            const int64_t k = j - rs - low[v];
+            const int64_t pos = rs - lowstart[v] + k;
+            if (k < 0 || pos < 0 || pos >= cap) { bad |= 2; continue; }   // unsorted or unbalanced
+            key[pos] = ((uint64_t)(uint32_t)u << shift) | (uint32_t)v;
+            val[pos] = g.ew[j];
+        }
+    }
+    for (int off = WAVE / 2; off > 0; off >>= 1) bad |= __shfl_xor(bad, off, WAVE);
+    if (bad && lane_id() == 0) atomicOr(flags, bad);
+}
+// Every entry below the diagonal against the sorted keys: the p-th such entry
+// of row u is number lowstart[u] + p.
+__global__ void __launch_bounds__(BLOCK) val_match_k(DevGraph g, const int32_t *tile_row,
+                                                     uint32_t *flags, const int64_t *low,
+                                                     const int64_t *lowstart, int shift,
+                                                     int64_t cap, const uint64_t *key,
+                                                     const uint32_t *val) {
+    __shared__ int64_t s_off[ETILE_ROWS + 1];
+    if (flags[0] & 1u) return;
+    const int64_t ntiles = etiles(g.nnz);
+    uint32_t bad = 0;
+    for (int64_t tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
+        TileCtx t = tile_begin(g, tile_row, tt, s_off);
+        for (int i = 0; i < ETILE_ITEMS; ++i) {
+            const int64_t j = t.j0 + (int64_t)i * BLOCK + threadIdx.x;
+            if (j >= t.j1) continue;
+            const int32_t u = tile_row_of(g, t, s_off, j);
+            const int32_t v = g.adj[j];
+            const int64_t p = j - tile_row_start(g, t, s_off, u);
+            if (p >= low[u]) continue;   // not below the diagonal
+            const int64_t idx = lowstart[u] + p;
+            if (v < 0 || idx >= cap || key[idx] != (((uint64_t)(uint32_t)u << shift) | (uint32_t)v) ||
+                val[idx] != g.ew[j])
+                bad |= 2;
+        }
+    }
+    for (int off = WAVE / 2; off > 0; off >>= 1) bad |= __shfl_xor(bad, off, WAVE);
+    if (bad && lane_id() == 0) atomicOr(flags, bad);
+}
+
+size_t val_sort_ws_bytes(int64_t n, int64_t nnz) {
+    if (nnz < VAL_SORT_MIN_NNZ || nnz / 2 >= ((int64_t)1 << 31)) return 0;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const int64_t cap = nnz / 2 > 0 ? nnz / 2 : 1;
+    return 2 * al(8 * ((size_t)n + 1)) + al(exclusive_sum_ws_bytes(n)) + 2 * al(8 * (size_t)cap) +
+           2 * al(4 * (size_t)cap) + al(radix_sort_ws_bytes(cap, 8));
+}
+
 void launch_validate(const DevGraph &g, int32_t *tile_row, uint32_t *flags, uint64_t *sums,
-                     int32_t *maxdeg, hipStream_t s, bool offsets_only) {
+                     int32_t *maxdeg, hipStream_t s, bool offsets_only, char *sort_ws) {
     int64_t nt = etiles(g.nnz);
     {
         KAPPA_PROF("validate_offsets", s);
@@ -270,9 +363,50 @@ void launch_validate(const DevGraph &g, int32_t *tile_row, uint32_t *flags, uint
     }
     if (nt == 0 || offsets_only) return;
     launch_tile_rows(g, tile_row, s);
-    KAPPA_PROF("validate_entries", s);
-    hipLaunchKernelGGL(validate_entries_k, dim3(grid_for(nt, 1, 8192)), dim3(BLOCK), 0, s, g,
-                       tile_row, flags, sums);
+    const bool sorted = sort_ws && val_sort_ws_bytes(g.n, g.nnz) > 0;
+    {
+        KAPPA_PROF("validate_entries", s);
+        if (sorted)
+            hipLaunchKernelGGL(validate_entries_k<false>, dim3(grid_for(nt, 1, 8192)), dim3(BLOCK), 0,
+                               s, g, tile_row, flags, sums);
+        else
+            hipLaunchKernelGGL(validate_entries_k<true>, dim3(grid_for(nt, 1, 8192)), dim3(BLOCK), 0,
+                               s, g, tile_row, flags, sums);
+    }
+    if (!sorted) return;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const int64_t cap = g.nnz / 2;
+    char *p = sort_ws;
+    int64_t *low = (int64_t *)p;
+    p += al(8 * ((size_t)g.n + 1));
+    int64_t *lowstart = (int64_t *)p;
+    p += al(8 * ((size_t)g.n + 1));
+    char *sum_ws = p;
+    p += al(exclusive_sum_ws_bytes(g.n));
+    uint64_t *key = (uint64_t *)p;
+    p += al(8 * (size_t)cap);
+    uint64_t *kout = (uint64_t *)p;
+    p += al(8 * (size_t)cap);
+    uint32_t *val = (uint32_t *)p;
+    p += al(4 * (size_t)cap);
+    uint32_t *vout = (uint32_t *)p;
+    p += al(4 * (size_t)cap);
+    char *rs_ws = p;
+    int shift = 1;
+    while (shift < 31 && ((int64_t)1 << shift) < (int64_t)g.n) ++shift;
+    {
+        KAPPA_PROF("validate_sorted", s);
+        hipLaunchKernelGGL(val_low_k, dim3(grid_for(g.n, BLOCK, 4096)), dim3(BLOCK), 0, s, g, flags,
+                           low);
+        exclusive_sum_i64(low, lowstart, g.n, sum_ws, s);
+        hipLaunchKernelGGL(val_upper_k, dim3(grid_for(nt, 1, 8192)), dim3(BLOCK), 0, s, g, tile_row,
+                           flags, low, lowstart, shift, cap, key, val);
+        // the keys are written row by row, so those of one neighbour already
+        // ascend by row: a stable sort by the neighbour bits alone orders them
+        radix_sort_pairs<uint64_t>(key, kout, val, vout, cap, shift, 2 * shift, rs_ws, s);
+        hipLaunchKernelGGL(val_match_k, dim3(grid_for(nt, 1, 8192)), dim3(BLOCK), 0, s, g, tile_row,
+                           flags, low, lowstart, shift, cap, kout, vout);
+    }
 }
 
 // ---------------------------------------------------------------------------

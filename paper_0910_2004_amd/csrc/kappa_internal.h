@@ -786,8 +786,14 @@ void launch_tile_rows(const DevGraph &g, int32_t *tile_row, hipStream_t s);
 // maxdeg[NSHARD] (zeroed): max row length per shard.  Computes its own tile
 // rows into tile_row.
 // offsets_only: the offsets pass alone (row offsets, c(V), maximum degree).
+// Graphs of at least VAL_SORT_MIN_NNZ entries check symmetry by sorting (a
+// workspace of val_sort_ws_bytes bytes, sort_ws); smaller ones, or a null
+// sort_ws, by binary searches.
+constexpr int64_t VAL_SORT_MIN_NNZ = (int64_t)1 << 22;
+size_t val_sort_ws_bytes(int64_t n, int64_t nnz);
 void launch_validate(const DevGraph &g, int32_t *tile_row, uint32_t *flags, uint64_t *sums,
-                     int32_t *maxdeg, hipStream_t s, bool offsets_only = false);
+                     int32_t *maxdeg, hipStream_t s, bool offsets_only = false,
+                     char *sort_ws = nullptr);
 void launch_out(const DevGraph &g, const int32_t *tile_row, uint32_t *out, hipStream_t s);
 void launch_rate(const DevGraph &g, const int32_t *tile_row, int rating, const uint32_t *out,
                  uint64_t *num, uint64_t *den, hipStream_t s);
