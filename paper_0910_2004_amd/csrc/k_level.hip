@@ -1836,6 +1836,14 @@ __global__ void __launch_bounds__(BLOCK) fill_small_k(Ctx c, int l) {
     fill_small_body<BLOCK>(c, l, blockIdx.x, gridDim.x);
 }
 
+// Sorted arrays in LDS are left in a padded layout: position p lives in
+// slot p + p / 32.  A thread that writes (or reads) E consecutive positions
+// with E in {1, 2, 4, 8, 16} then touches distinct banks across its half-wave,
+// where the plain layout would put every lane of a half-wave on a handful of
+// banks (stride E * 8 bytes).
+__host__ __device__ constexpr int lds_padded(int p) { return p + p / 32; }
+__device__ __forceinline__ int lds_pad(int p) { return p + (p >> 5); }
+
 // One compare-exchange stage (block size k, distance j) of a bitonic sort of
 // s[lo, lo + 2 * npairs): pair p pairs element t (bit j clear) with t | j and
 // orders them ascending when bit k of t is clear.  The caller's threads take
@@ -1937,7 +1945,8 @@ __device__ __forceinline__ void reg_bitonic(uint64_t (&v)[E], int tid, uint64_t 
 
 // Sorts s[0, P) (P = E * NT, every thread of the block calling) through
 // registers: slot tid + e * NT is read as position tid * E + e (any initial
-// placement sorts), and the sorted positions are written back in order.
+// placement sorts), and the sorted positions are written back in the padded
+// layout (s holds lds_padded(P) entries).
 template <int E, int NT>
 __device__ __forceinline__ void block_sort_regs(uint64_t *s, int tid) {
     uint64_t v[E];
@@ -1947,7 +1956,7 @@ __device__ __forceinline__ void block_sort_regs(uint64_t *s, int tid) {
     reg_bitonic<E, NT>(v, tid, s);
     if (E * NT > E * WAVE) __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) s[tid * E + e] = v[e];
+    for (int e = 0; e < E; ++e) s[lds_pad(tid * E + e)] = v[e];
 }
 
 // The register sort for P = E * NT with E in {4, 8, 16}; false: not such a P
@@ -1962,10 +1971,12 @@ __device__ __forceinline__ bool block_sort_regs_p(uint64_t *s, int P) {
 }
 
 // Sorts s[0, P) ascending (P a power of two, 2 <= P) with the block's NT
-// threads: in registers where P = 4, 8 or 16 per thread, else in LDS, where
-// the stages whose compare distance stays inside one wave's contiguous slice
-// of the array (P / waves elements) need only that wave's LDS order and only
-// the few wider stages take a block barrier.  Ends with a block barrier.
+// threads into the padded layout (s holds lds_padded(P) entries): in
+// registers where P = 4, 8 or 16 per thread, else in LDS, where the stages
+// whose compare distance stays inside one wave's contiguous slice of the
+// array (P / waves elements) need only that wave's LDS order and only the
+// few wider stages take a block barrier, followed by a move into the padded
+// layout.  Ends with a block barrier.
 template <int NT>
 __device__ __forceinline__ void block_sort(uint64_t *s, int P) {
     constexpr int NW = NT / WAVE;
@@ -1992,6 +2003,16 @@ __device__ __forceinline__ void block_sort(uint64_t *s, int P) {
         }
     }
     if (!synced) __syncthreads();
+    // into the padded layout, NT positions at a time from the top: a chunk's
+    // slots lie at or above its own positions, so no unread position below
+    // it is overwritten
+    for (int hi = P; hi > 0; hi -= NT) {
+        const int p = hi - NT + (int)threadIdx.x;
+        const uint64_t v = p >= 0 ? s[p] : 0;
+        __syncthreads();
+        if (p >= 0) s[lds_pad(p)] = v;
+        __syncthreads();
+    }
 }
 
 // --- 2b. mid and big rows: one block per row, the row staged in LDS and sorted
@@ -2035,24 +2056,26 @@ __device__ __forceinline__ void fill_block_body(const Ctx &c, int l, unsigned bi
         __syncthreads();
         block_sort<NT>(s, P);
         // leaders: first entry of each run of equal keys
+        // (the sorted entries are in the padded layout)
         const int ipt = (P + NT - 1) / NT;
         const int t0 = threadIdx.x * ipt;
         int64_t mine = 0;
         for (int q = 0; q < ipt; ++q) {
             int t = t0 + q;
             if (t >= P) break;
-            uint32_t k = (uint32_t)(s[t] >> 32);
-            if (k != INVALID_KEY && (t == 0 || (uint32_t)(s[t - 1] >> 32) != k)) ++mine;
+            uint32_t k = (uint32_t)(s[lds_pad(t)] >> 32);
+            if (k != INVALID_KEY && (t == 0 || (uint32_t)(s[lds_pad(t - 1)] >> 32) != k)) ++mine;
         }
         int64_t total;
         int64_t rank = block_excl_scan(mine, sh, &total);
         for (int q = 0; q < ipt; ++q) {
             int t = t0 + q;
             if (t >= P) break;
-            uint32_t k = (uint32_t)(s[t] >> 32);
-            if (k == INVALID_KEY || (t > 0 && (uint32_t)(s[t - 1] >> 32) == k)) continue;
+            uint32_t k = (uint32_t)(s[lds_pad(t)] >> 32);
+            if (k == INVALID_KEY || (t > 0 && (uint32_t)(s[lds_pad(t - 1)] >> 32) == k)) continue;
             uint32_t sum = 0;
-            for (int e = t; e < P && (uint32_t)(s[e] >> 32) == k; ++e) sum += (uint32_t)s[e];
+            for (int e = t; e < P && (uint32_t)(s[lds_pad(e)] >> 32) == k; ++e)
+                sum += (uint32_t)s[lds_pad(e)];
             int64_t at = staged_at(r, rank);
             c.cs.tmp_adj[at] = (int32_t)k;
             c.cs.tmp_ew[at] = sum;
@@ -2065,7 +2088,7 @@ __device__ __forceinline__ void fill_block_body(const Ctx &c, int l, unsigned bi
 template <int NT>
 __device__ __forceinline__ void fill_mid_body(const Ctx &c, int l, unsigned bid, unsigned nb,
                                               int cls = 3) {
-    __shared__ uint64_t s[MID_P];
+    __shared__ uint64_t s[lds_padded(MID_P)];
     fill_block_body<NT, MID_P>(c, l, bid, nb, cls, s);
 }
 
@@ -2075,7 +2098,7 @@ constexpr int BIG_P = ROW_BIG_MAX + 2;
 constexpr int BIG_THREADS = 1024;
 static_assert((BIG_P & (BIG_P - 1)) == 0, "big-row sort size");
 __global__ void __launch_bounds__(BIG_THREADS) fill_big_k(Ctx c, int l) {
-    __shared__ uint64_t s[BIG_P];
+    __shared__ uint64_t s[lds_padded(BIG_P)];
     fill_block_body<BIG_THREADS, BIG_P>(c, l, blockIdx.x, gridDim.x, 4, s);
 }
 // --- 2a'. rows of 65..512 entries: one wave per row; the renamed entries are
@@ -2093,7 +2116,7 @@ __device__ __forceinline__ void fill_wave_body(const Ctx &c, int l, unsigned bid
     const int64_t count = c.cs.row_cnt[1];
     const int32_t *list = class_list(c.cs, g.n, 1);
     const int wv = threadIdx.x / WAVE, lane = lane_id();
-    uint64_t *s = lds + (int64_t)wv * WR_P;
+    uint64_t *s = lds + (int64_t)wv * lds_padded(WR_P);
     const int64_t gw = (int64_t)bid * (NT / WAVE) + wv, gs = (int64_t)nb * (NT / WAVE);
     for (int64_t i = gw; i < count; i += gs) {   // wave-uniform
         const int32_t x = list[i];
@@ -2128,16 +2151,19 @@ __device__ __forceinline__ void fill_wave_body(const Ctx &c, int l, unsigned bid
         else if (P == 4 * WAVE) block_sort_regs<4, WAVE>(s, lane);
         else block_sort_regs<8, WAVE>(s, lane);
         wave_sync_lds();
-        // leaders (first entry of each run of equal keys) in order; runs summed
+        // leaders (first entry of each run of equal keys) in order; runs
+        // summed (the sorted entries are in the padded layout)
         int32_t rank = 0;
         for (int t0 = 0; t0 < P; t0 += WAVE) {
             const int t = t0 + lane;
-            const uint32_t k = (uint32_t)(s[t] >> 32);
-            const bool lead = k != INVALID_KEY && (t == 0 || (uint32_t)(s[t - 1] >> 32) != k);
+            const uint32_t k = (uint32_t)(s[lds_pad(t)] >> 32);
+            const bool lead =
+                k != INVALID_KEY && (t == 0 || (uint32_t)(s[lds_pad(t - 1)] >> 32) != k);
             const uint64_t m = __ballot(lead);
             if (lead) {
                 uint32_t sum = 0;
-                for (int e = t; e < P && (uint32_t)(s[e] >> 32) == k; ++e) sum += (uint32_t)s[e];
+                for (int e = t; e < P && (uint32_t)(s[lds_pad(e)] >> 32) == k; ++e)
+                    sum += (uint32_t)s[lds_pad(e)];
                 const int64_t at = staged_at(r, rank + (int32_t)__popcll(m & lanemask_lt()));
                 c.cs.tmp_adj[at] = (int32_t)k;
                 c.cs.tmp_ew[at] = sum;
@@ -2153,8 +2179,9 @@ __device__ __forceinline__ void fill_wave_body(const Ctx &c, int l, unsigned bid
 // merge the rows of 65..512 entries one wave each, the others the rows of
 // 513..4094 entries one block each (one LDS array serves either).
 __global__ void __launch_bounds__(BLOCK) fill_mid_k(Ctx c, int l, unsigned wave_blocks) {
-    static_assert((BLOCK / WAVE) * WR_P <= MID_P, "the wave rows' slices fit the block rows' array");
-    __shared__ uint64_t s[MID_P];
+    static_assert((BLOCK / WAVE) * lds_padded(WR_P) <= lds_padded(MID_P),
+                  "the wave rows' slices fit the block rows' array");
+    __shared__ uint64_t s[lds_padded(MID_P)];
     if (blockIdx.x < wave_blocks)
         fill_wave_body<BLOCK>(c, l, blockIdx.x, wave_blocks, s);
     else
@@ -2470,8 +2497,8 @@ __global__ void __launch_bounds__(HUGE_THREADS) fill_huge_prep_k(Ctx c, int l) {
     }
 }
 
-// The merged entries of a sorted group s[0, P) (NT threads, a block or one
-// wave) into hg_adj / hg_ew at positions a, a + 1, ... of row r; returns how
+// The merged entries of a sorted group s[0, P) (padded layout; NT threads, a
+// block or one wave) into hg_adj / hg_ew at positions a, a + 1, ... of row r; returns how
 // many (every thread).  sh: NT / WAVE + 1 int64 of LDS (a block only).
 template <int NT>
 __device__ __forceinline__ int32_t hg_emit(const Ctx &c, const uint64_t *s, int P, const RowSrc &r,
@@ -2483,8 +2510,8 @@ __device__ __forceinline__ int32_t hg_emit(const Ctx &c, const uint64_t *s, int 
     for (int q = 0; q < ipt; ++q) {
         const int t = t0 + q;
         if (t >= P) break;
-        const uint32_t k = (uint32_t)(s[t] >> 32);
-        if (k != INVALID_KEY && (t == 0 || (uint32_t)(s[t - 1] >> 32) != k)) ++mine;
+        const uint32_t k = (uint32_t)(s[lds_pad(t)] >> 32);
+        if (k != INVALID_KEY && (t == 0 || (uint32_t)(s[lds_pad(t - 1)] >> 32) != k)) ++mine;
     }
     int64_t total, rank;
     if (NT == WAVE) {
@@ -2497,10 +2524,11 @@ __device__ __forceinline__ int32_t hg_emit(const Ctx &c, const uint64_t *s, int 
     for (int q = 0; q < ipt; ++q) {
         const int t = t0 + q;
         if (t >= P) break;
-        const uint32_t k = (uint32_t)(s[t] >> 32);
-        if (k == INVALID_KEY || (t > 0 && (uint32_t)(s[t - 1] >> 32) == k)) continue;
+        const uint32_t k = (uint32_t)(s[lds_pad(t)] >> 32);
+        if (k == INVALID_KEY || (t > 0 && (uint32_t)(s[lds_pad(t - 1)] >> 32) == k)) continue;
         uint32_t sum = 0;
-        for (int e = t; e < P && (uint32_t)(s[e] >> 32) == k; ++e) sum += (uint32_t)s[e];
+        for (int e = t; e < P && (uint32_t)(s[lds_pad(e)] >> 32) == k; ++e)
+            sum += (uint32_t)s[lds_pad(e)];
         const int64_t at = staged_at(r, a + rank);
         c.cs.hg_adj[at] = (int32_t)k;
         c.cs.hg_ew[at] = sum;
@@ -2511,13 +2539,13 @@ __device__ __forceinline__ int32_t hg_emit(const Ctx &c, const uint64_t *s, int 
 
 // Groups of at most WR_P entries: one wave each, sorted in registers.
 __global__ void __launch_bounds__(BLOCK) fill_huge_small_k(Ctx c, int l) {
-    __shared__ uint64_t lds[(BLOCK / WAVE) * WR_P];
+    __shared__ uint64_t lds[(BLOCK / WAVE) * lds_padded(WR_P)];
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_CONTRACT, g)) return;
     if (c.lv[l + 1].n > HUGE_NC_MAX) return;
     const int wv = threadIdx.x / WAVE, lane = lane_id();
-    uint64_t *sl = lds + wv * WR_P;
+    uint64_t *sl = lds + wv * lds_padded(WR_P);
     const int32_t *list = class_list(c.cs, g.n, 2);
     const int64_t count = min<int64_t>(c.cs.hg_cnt[0], c.cs.hg_cap);
     for (int64_t q = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv; q < count;
@@ -2550,7 +2578,7 @@ __global__ void __launch_bounds__(BLOCK) fill_huge_small_k(Ctx c, int l) {
 // The larger groups: one block each.
 __global__ void __launch_bounds__(HUGE_THREADS) fill_huge_big_k(Ctx c, int l) {
     constexpr int NT = HUGE_THREADS;
-    __shared__ uint64_t s[BIG_P];
+    __shared__ uint64_t s[lds_padded(BIG_P)];
     __shared__ int64_t sh[NT / WAVE + 1];
     DevGraph g;
     LevelDesc *L = c.lv + l;
