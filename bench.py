@@ -61,9 +61,10 @@ def bytes_cut_entries(D):
 
 
 def bytes_pick_round(A, Dr):
-    # a matching round after the first, pick side, over the A nodes that
-    # point (degree sum Dr): per entry adj, w, the neighbour's attribute and
-    # mate (16); per node its two int64 offsets, own attribute, best (24)
+    # a matching round after the first, pick side, over the A nodes that scan
+    # their row again (degree sum Dr): per entry adj, w, the neighbour's
+    # attribute and mate (16); per node its two int64 offsets, own attribute,
+    # best (24)
     return 16 * Dr + 24 * A
 
 
@@ -127,10 +128,11 @@ def merge_class_stats(H):
     return tot
 
 
-MODELS = {"pick": "per round r >= 2 run as a grid launch: 16 B per entry of the A_r pointing "
-                  "nodes (adj, w, attribute, mate of the neighbour) + 24 B per pointing node "
-                  "(int64 offsets, own attribute, best); A_r and their degree sum from the "
-                  "level's round statistics",
+MODELS = {"pick": "per round r >= 2 run as a grid launch: 16 B per entry of the rows that "
+                  "scan again in round r (adj, w, attribute, mate of the neighbour) + 24 B per "
+                  "such row (int64 offsets, own attribute, best); rows and degree sum from the "
+                  "level's rescan statistics (every pending node, unless long rows are "
+                  "chunked: then only those whose choice was matched away)",
           "mate": "per round r >= 2 run as a grid launch: 12 B per pointing node",
           "pick_first": "per level: 16 B/node + 12 B/entry (innerOuter 20 + 16)",
           "fill_small": "per level: 28 B/coarse row + 16 B/matched pair + 12 B/fine entry + 8 B/coarse entry",
@@ -161,14 +163,17 @@ def counter_traffic(kernel, tag):
 
 
 def level_stats(H):
-    """Per level: n, entries, |M|, rounds, rounds run as grid launches, and
-    the per-round (pointing nodes, their degree sum)."""
+    """Per level: n, entries, |M|, rounds, rounds run as grid launches, the
+    per-round (pointing nodes, their degree sum) and the per-round (rows
+    scanned again, their degree sum)."""
     out = []
     for l in range(len(H)):
         inf = H.info(l)
         _, p, d = H.round_stats(l)
+        _, rr, rd = H.rescan_stats(l)
         out.append((int(inf.n), int(inf.nnz), int(inf.matched), int(inf.rounds),
-                    int(inf.grid_rounds), [int(x) for x in p], [int(x) for x in d]))
+                    int(inf.grid_rounds), [int(x) for x in p], [int(x) for x in d],
+                    [int(x) for x in rr], [int(x) for x in rd]))
     return out
 
 
@@ -183,13 +188,13 @@ def model_bytes(stats_by_rating, classes=None, n0=0, D0=0):
             tot[name] += bytes_merge(*cs[name])
     for rating, lv in stats_by_rating.items():
         io = rating == 1
-        for l, (n, D, matched, rounds, grid_rounds, pt, dg) in enumerate(lv):
+        for l, (n, D, matched, rounds, grid_rounds, pt, dg, rr, rd) in enumerate(lv):
             tot["cut_entries"] += bytes_cut_entries(D)
             if l + 1 < len(lv):
                 nc, Dc = lv[l + 1][0], lv[l + 1][1]
                 tot["pick_first"] += bytes_pick_first(n, D, io)
                 for r in range(2, min(grid_rounds, len(pt)) + 1):
-                    tot["pick"] += bytes_pick_round(pt[r - 1], dg[r - 1])
+                    tot["pick"] += bytes_pick_round(rr[r - 1], rd[r - 1])
                     tot["mate"] += bytes_mate_round(pt[r - 1])
                 if not classes:
                     tot["fill_small"] += bytes_fill_small(n, D, nc, Dc, matched)

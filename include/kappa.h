@@ -246,6 +246,19 @@ kappa_status kappa_hierarchy_level(const kappa_hierarchy *h, int32_t l, kappa_gr
 int32_t kappa_hierarchy_round_stats(const kappa_hierarchy *h, int32_t l, int64_t *pointing,
                                     int64_t *degsum, int32_t cap);
 
+/* Rescan statistics of level l's matching, for the same rounds: rows[r] =
+   the nodes whose row the pick scanned again in round r (0-based) and
+   degsum[r] = the sum of their degrees.  Without chunked rows every pending
+   node of a later round is scanned again; where long rows are scanned in
+   chunks (a power-law graph), a pending node whose choice is still free
+   keeps it and is not counted, and only the rounds run as grid launches are
+   counted.  Either way the nodes counted pointed in the round before.  Index
+   0 (the first round, which scans every row) holds zeros.  Copies
+   min(rounds, cap) entries and returns the round count, as
+   kappa_hierarchy_round_stats. */
+int32_t kappa_hierarchy_rescan_stats(const kappa_hierarchy *h, int32_t l, int64_t *rows,
+                                     int64_t *degsum, int32_t cap);
+
 /* Frees h (stream-ordered on the stream it was built on). NULL is a no-op. */
 void kappa_hierarchy_free(kappa_hierarchy *h);
 

@@ -156,6 +156,7 @@ def lib():
         "kappa_hierarchy_level": (st, [P, i32, ctypes.POINTER(c_graph), ctypes.POINTER(P),
                                        ctypes.POINTER(c_level_info)]),
         "kappa_hierarchy_round_stats": (i32, [P, i32, P, P, i32]),
+        "kappa_hierarchy_rescan_stats": (i32, [P, i32, P, P, i32]),
         "kappa_hierarchy_free": (None, [P]),
         "kappa_initial_partition": (st, [i32, i32, u64, P, P]),
         "kappa_project": (st, [P, i32, i32, P, P, P]),
@@ -427,6 +428,16 @@ class Hierarchy:
         d = np.zeros(64, dtype=np.int64)
         r = lib().kappa_hierarchy_round_stats(self.handle, l, p.ctypes.data_as(ctypes.c_void_p),
                                               d.ctypes.data_as(ctypes.c_void_p), 64)
+        k = min(r, 64)
+        return int(r), p[:k].copy(), d[:k].copy()
+
+    def rescan_stats(self, l: int):
+        """(rounds, rows that scanned their row again per round, their degree sum)."""
+        import numpy as np
+        p = np.zeros(64, dtype=np.int64)
+        d = np.zeros(64, dtype=np.int64)
+        r = lib().kappa_hierarchy_rescan_stats(self.handle, l, p.ctypes.data_as(ctypes.c_void_p),
+                                               d.ctypes.data_as(ctypes.c_void_p), 64)
         k = min(r, 64)
         return int(r), p[:k].copy(), d[:k].copy()
 

@@ -813,6 +813,7 @@ struct kappa_level {
     int64_t matched = 0;
     int32_t stop = KAPPA_STOP_NONE;
     std::vector<int64_t> pointing, degsum;
+    std::vector<int64_t> rescan, rescan_deg;   // rows rescanned per round, their degree sum
 };
 
 struct kappa_hierarchy {
@@ -1112,6 +1113,8 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
             for (int i = 0; i < keep; ++i) {
                 L.pointing.push_back(hl[l].stat[i][0]);
                 L.degsum.push_back(hl[l].stat[i][1]);
+                L.rescan.push_back(hl[l].stat[i][2]);
+                L.rescan_deg.push_back(hl[l].stat[i][3]);
             }
         } else {
             L.rounds = 0;
@@ -1733,6 +1736,18 @@ extern "C" int32_t kappa_hierarchy_round_stats(const kappa_hierarchy *h, int32_t
     for (int32_t i = 0; i < k; ++i) {
         if (pointing) pointing[i] = L.pointing[i];
         if (degsum) degsum[i] = L.degsum[i];
+    }
+    return L.rounds;
+}
+
+extern "C" int32_t kappa_hierarchy_rescan_stats(const kappa_hierarchy *h, int32_t l,
+                                                int64_t *rows, int64_t *degsum, int32_t cap) {
+    if (!h || l < 0 || l >= (int32_t)h->levels.size() || cap < 0) return KAPPA_E_ARG;
+    const kappa_level &L = h->levels[l];
+    int32_t k = std::min<int32_t>(cap, (int32_t)L.rescan.size());
+    for (int32_t i = 0; i < k; ++i) {
+        if (rows) rows[i] = L.rescan[i];
+        if (degsum) degsum[i] = L.rescan_deg[i];
     }
     return L.rounds;
 }

@@ -706,6 +706,7 @@ __device__ __forceinline__ void mate_phase(const Ctx &c, const DevGraph &g, Leve
     const int opar = r & 1;
     const PList ol[3] = {plist(c.ms, n, opar, 0), plist(c.ms, n, opar, 1), plist(c.ms, n, opar, 2)};
     int64_t point = 0, degs = 0, pairs = 0;
+    int64_t scanned = 0, sdeg = 0;   // later rounds without chunked rows: every entry rescanned
     bool bad = false;
     // pass p, slot k of block b covers entries ((p * MK + k) * nb + b) * blockDim.x + t
     const int64_t row = (int64_t)nb * blockDim.x, per_pass = row * MK;
@@ -758,6 +759,8 @@ __device__ __forceinline__ void mate_phase(const Ctx &c, const DevGraph &g, Leve
             bin[k] = -1;
             const int32_t v = vv[k], b = bb[k];
             if (v < 0) continue;
+            ++scanned;
+            sdeg += dd[k];
             int32_t m = -1;
             if (b >= 0) {
                 ++point;
@@ -781,12 +784,22 @@ __device__ __forceinline__ void mate_phase(const Ctx &c, const DevGraph &g, Leve
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_STATE);
     block_sum3(point, degs, pairs, sh);
+    const int ri_ = r - 1 < STAT_ROUNDS ? r - 1 : STAT_ROUNDS - 1, sd = shard_of_block();
     if (threadIdx.x == 0 && point > 0) {
-        const int ri_ = r - 1 < STAT_ROUNDS ? r - 1 : STAT_ROUNDS - 1, sd = shard_of_block();
         atomicAdd((unsigned long long *)&st->sstat[ri_][0][sd], (unsigned long long)point);
         atomicAdd((unsigned long long *)&st->sstat[ri_][1][sd], (unsigned long long)degs);
         if (pairs) atomicAdd((unsigned long long *)&st->sstat[ri_][2][sd], (unsigned long long)pairs);
         atomicMax(&st->sround[sd], r);
+    }
+    // the rows this round's pick scanned, where it scans every pending row
+    // (with chunked rows the preparation counts the rows that rescan)
+    if (!FIRST && !c.ms.hub.rec) {
+        int64_t none = 0;
+        block_sum3(scanned, sdeg, none, sh);
+        if (threadIdx.x == 0 && scanned > 0) {
+            atomicAdd((unsigned long long *)&st->sstat[ri_][3][sd], (unsigned long long)scanned);
+            atomicAdd((unsigned long long *)&st->sstat[ri_][4][sd], (unsigned long long)sdeg);
+        }
     }
 }
 
@@ -871,7 +884,7 @@ __global__ void __launch_bounds__(BLOCK) pick_k(Ctx c, int l, int r, PickGrid pg
 // pending, or few enough for the finisher).  A thread's MK entries are loaded
 // together.
 __global__ void __launch_bounds__(BLOCK) prep_k(Ctx c, int l, int r) {
-    __shared__ int64_t sh[BLOCK / WAVE + 1];
+    __shared__ int64_t sh[3 * (BLOCK / WAVE) + 1];
     __shared__ int32_t sbase[2];
     DevGraph g;
     LevelDesc *L = c.lv + l;
@@ -893,6 +906,7 @@ __global__ void __launch_bounds__(BLOCK) prep_k(Ctx c, int l, int r) {
                     c.ms.hub.first + (int64_t)par * g.n, sc + 3, c.ms.hub.cap};
     const int2 *nrec = c.ms.nrec;
     const int64_t row = (int64_t)gridDim.x * blockDim.x, per_pass = row * MK;
+    int64_t rrows = 0, rdeg = 0;   // the round's rescanning rows and their degrees
     for (int64_t base = 0; base < total; base += per_pass) {   // block-uniform
         const int64_t first = base + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
         int32_t vv[MK], bb[MK], dd[MK], jj[MK], bin[MK];
@@ -918,6 +932,10 @@ __global__ void __launch_bounds__(BLOCK) prep_k(Ctx c, int l, int r) {
             const bool live = bin[k] >= 0 && (uint32_t)vv[k] < (uint32_t)g.n;
             resc[k] = live && !keeps_choice(bb[k], g.n, nrec);
             if (bin[k] >= 0 && !live) bin[k] = -1;   // valid lists never
+            if (resc[k]) {
+                ++rrows;
+                rdeg += dd[k];
+            }
         }
         // rows of bins 0 and 1 that rescan: block-aggregated append
         int64_t packed = 0;
@@ -944,6 +962,13 @@ __global__ void __launch_bounds__(BLOCK) prep_k(Ctx c, int l, int r) {
             }
         }
         __syncthreads();   // sbase is reused by the next pass
+    }
+    int64_t none = 0;
+    block_sum3(rrows, rdeg, none, sh);
+    if (threadIdx.x == 0 && rrows > 0) {
+        const int ri_ = r - 1 < STAT_ROUNDS ? r - 1 : STAT_ROUNDS - 1, sd = shard_of_block();
+        atomicAdd((unsigned long long *)&st->sstat[ri_][3][sd], (unsigned long long)rrows);
+        atomicAdd((unsigned long long *)&st->sstat[ri_][4][sd], (unsigned long long)rdeg);
     }
 }
 
@@ -1048,14 +1073,18 @@ __device__ void close_matching(const Ctx &c, LevelDesc *L, bool capped, int grid
     {
         const int w = threadIdx.x / WAVE, nw = NT / WAVE;
         const int slots = (int)min<int64_t>(s_acc[1], STAT_ROUNDS);
-        for (int q = w; q < slots * 3; q += nw) {
-            const int i = q / 3, f = q % 3;
+        for (int q = w; q < slots * 5; q += nw) {
+            const int i = q / 5, f = q % 5;
             int64_t *p = &st->sstat[i][f][lane_id()];
             const int64_t v = wave_sum(*p);
             *p = 0;
             if (lane_id() == 0) {
                 if (f < 2) L->stat[i][f] = v;
-                else if (v) atomicAdd((unsigned long long *)&s_acc[0], (unsigned long long)v);
+                else if (f == 2) {
+                    if (v) atomicAdd((unsigned long long *)&s_acc[0], (unsigned long long)v);
+                } else {
+                    L->stat[i][f - 1] = v;
+                }
             }
         }
     }
@@ -1885,13 +1914,17 @@ __device__ __forceinline__ void bitonic_stage(uint64_t *s, int lo, int npairs, i
 // LDS s (P entries, stored slot e * NT + tid so that a wave's accesses hit
 // consecutive slots) between block barriers.  Every loop has a constant trip
 // count and unrolls, so j, k and the register indices are constants.
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+__device__ __forceinline__ uint64_t shfl_xor_v(uint64_t v, int m) {
     const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, WAVE);
     const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, WAVE);
     return ((uint64_t)hi << 32) | lo;
 }
-template <int E, int NT>
-__device__ __forceinline__ void reg_bitonic(uint64_t (&v)[E], int tid, uint64_t *s) {
+__device__ __forceinline__ uint32_t shfl_xor_v(uint32_t v, int m) {
+    return (uint32_t)__shfl_xor((int)v, m, WAVE);
+}
+// T: uint64_t, or uint32_t (one shuffle and a min / max pair per exchange)
+template <int E, int NT, class T>
+__device__ __forceinline__ void reg_bitonic(T (&v)[E], int tid, T *s) {
     constexpr int P = E * NT;
     constexpr int LOGP = __builtin_ctz(P);
     static_assert((E & (E - 1)) == 0 && (NT & (NT - 1)) == 0 && NT >= WAVE, "sort shape");
@@ -1906,9 +1939,8 @@ __device__ __forceinline__ void reg_bitonic(uint64_t (&v)[E], int tid, uint64_t 
                 for (int e = 0; e < E; ++e) {
                     if ((e & j) != 0) continue;
                     const bool up = (((tid * E + e) & k) == 0);
-                    const uint64_t a = v[e], b = v[e | j];
-                    const bool lt = a < b;
-                    const uint64_t lo = lt ? a : b, hi = lt ? b : a;
+                    const T a = v[e], b = v[e | j];
+                    const T lo = a < b ? a : b, hi = a < b ? b : a;
                     v[e] = up ? lo : hi;
                     v[e | j] = up ? hi : lo;
                 }
@@ -1918,10 +1950,10 @@ __device__ __forceinline__ void reg_bitonic(uint64_t (&v)[E], int tid, uint64_t 
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const bool up = (((tid * E + e) & k) == 0);
-                    const uint64_t o = shfl_xor64(v[e], m);
+                    const T o = shfl_xor_v(v[e], m);
                     const bool take_min = lower == up;
-                    const bool lt = v[e] < o;
-                    v[e] = take_min ? (lt ? v[e] : o) : (lt ? o : v[e]);
+                    const T lo = v[e] < o ? v[e] : o, hi = v[e] < o ? o : v[e];
+                    v[e] = take_min ? lo : hi;
                 }
             } else {
                 const int m = j / E;
@@ -1932,10 +1964,10 @@ __device__ __forceinline__ void reg_bitonic(uint64_t (&v)[E], int tid, uint64_t 
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const bool up = (((tid * E + e) & k) == 0);
-                    const uint64_t o = s[e * NT + (tid ^ m)];
+                    const T o = s[e * NT + (tid ^ m)];
                     const bool take_min = lower == up;
-                    const bool lt = v[e] < o;
-                    v[e] = take_min ? (lt ? v[e] : o) : (lt ? o : v[e]);
+                    const T lo = v[e] < o ? v[e] : o, hi = v[e] < o ? o : v[e];
+                    v[e] = take_min ? lo : hi;
                 }
                 __syncthreads();
             }
@@ -1947,13 +1979,13 @@ __device__ __forceinline__ void reg_bitonic(uint64_t (&v)[E], int tid, uint64_t 
 // registers: slot tid + e * NT is read as position tid * E + e (any initial
 // placement sorts), and the sorted positions are written back in the padded
 // layout (s holds lds_padded(P) entries).
-template <int E, int NT>
-__device__ __forceinline__ void block_sort_regs(uint64_t *s, int tid) {
-    uint64_t v[E];
+template <int E, int NT, class T = uint64_t>
+__device__ __forceinline__ void block_sort_regs(T *s, int tid) {
+    T v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = s[tid + e * NT];
     if (E * NT > E * WAVE) __syncthreads();   // the LDS stages overwrite s
-    reg_bitonic<E, NT>(v, tid, s);
+    reg_bitonic<E, NT, T>(v, tid, s);
     if (E * NT > E * WAVE) __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) s[lds_pad(tid * E + e)] = v[e];
@@ -2015,8 +2047,101 @@ __device__ __forceinline__ void block_sort(uint64_t *s, int P) {
     }
 }
 
-// --- 2b. mid and big rows: one block per row, the row staged in LDS and sorted
-//         (block_sort), then a leader scan.  s: PMAX entries of LDS. ----------------
+// --- 2b. sort values of a merged row.  Wide: (key << 32 | weight) in 64 bits.
+//          Narrow, where every coarse id shifted by lp = log2(P) bits fits in
+//          32 (nc << lp < 2^32): (key << lp | position) in 32 bits, the weight
+//          kept by position in a second LDS array, so that an exchange of the
+//          sort is one shuffle and a min / max pair.  Padding and the
+//          contracted edge are all ones in either form (a narrow value never
+//          is: its key is below nc) and read as INVALID_KEY.
+struct WideRep {
+    using T = uint64_t;
+    __device__ T make(uint32_t key, uint32_t w, int) const {
+        return key == INVALID_KEY ? ~0ull : ((uint64_t)key << 32) | w;
+    }
+    __device__ uint32_t key(T v) const { return (uint32_t)(v >> 32); }
+    __device__ uint32_t weight(T v) const { return (uint32_t)v; }
+};
+struct NarrowRep {
+    using T = uint32_t;
+    uint32_t *wt;   // weights by position
+    int lp;
+    __device__ T make(uint32_t key, uint32_t w, int pos) const {
+        wt[pos] = w;
+        return key == INVALID_KEY ? ~0u : (key << lp) | (uint32_t)pos;
+    }
+    __device__ uint32_t key(T v) const { return v == ~0u ? INVALID_KEY : v >> lp; }
+    __device__ uint32_t weight(T v) const { return wt[v & ((1u << lp) - 1)]; }
+};
+// nc << lp < 2^32
+__device__ __forceinline__ bool narrow_fits(int64_t nc, int lp) {
+    return ((uint64_t)nc << lp) < ((uint64_t)1 << 32);
+}
+
+// --- 2b'. mid and big rows: one block per row, the row staged in LDS and
+//          sorted (block_sort), then a leader scan.  s: lds_padded(PMAX)
+//          64-bit entries of LDS. -------------------------------------------
+template <int NT, class Rep>
+__device__ __forceinline__ int64_t block_row_merge(const Ctx &c, const DevGraph &g,
+                                                   const int32_t *cmap, const RowSrc &r, int P,
+                                                   typename Rep::T *s, const Rep &rep, int64_t *sh) {
+    using T = typename Rep::T;
+    const int tot = (int)r.tot;
+    for (int t0 = threadIdx.x; t0 < P; t0 += NT * 4) {
+        T val[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u * NT;
+            val[u] = (T)~(T)0;
+            if (t < tot) {
+                uint32_t k, w;
+                row_entry(g, cmap, r, t, k, w);
+                val[u] = rep.make(k, w, t);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (t0 + u * NT < P) s[t0 + u * NT] = val[u];
+    }
+    __syncthreads();
+    if constexpr (sizeof(T) == 8) {
+        block_sort<NT>(s, P);
+    } else {   // the callers take the narrow form only for P = 4, 8 or 16 per thread
+        if (P == 4 * NT) block_sort_regs<4, NT, T>(s, threadIdx.x);
+        else if (P == 8 * NT) block_sort_regs<8, NT, T>(s, threadIdx.x);
+        else block_sort_regs<16, NT, T>(s, threadIdx.x);
+        __syncthreads();
+    }
+    // leaders: first entry of each run of equal keys (padded layout)
+    const int ipt = (P + NT - 1) / NT;
+    const int t0 = threadIdx.x * ipt;
+    int64_t mine = 0;
+    for (int q = 0; q < ipt; ++q) {
+        const int t = t0 + q;
+        if (t >= P) break;
+        const uint32_t k = rep.key(s[lds_pad(t)]);
+        if (k != INVALID_KEY && (t == 0 || rep.key(s[lds_pad(t - 1)]) != k)) ++mine;
+    }
+    int64_t total;
+    int64_t rank = block_excl_scan(mine, sh, &total);
+    for (int q = 0; q < ipt; ++q) {
+        const int t = t0 + q;
+        if (t >= P) break;
+        const uint32_t k = rep.key(s[lds_pad(t)]);
+        if (k == INVALID_KEY || (t > 0 && rep.key(s[lds_pad(t - 1)]) == k)) continue;
+        uint32_t sum = 0;
+        for (int e = t; e < P; ++e) {
+            const T v = s[lds_pad(e)];
+            if (rep.key(v) != k) break;
+            sum += rep.weight(v);
+        }
+        const int64_t at = staged_at(r, rank);
+        c.cs.tmp_adj[at] = (int32_t)k;
+        c.cs.tmp_ew[at] = sum;
+        ++rank;
+    }
+    return total;
+}
 template <int NT, int PMAX>
 __device__ __forceinline__ void fill_block_body(const Ctx &c, int l, unsigned bid, unsigned nb,
                                                 int cls, uint64_t *s) {
@@ -2025,61 +2150,27 @@ __device__ __forceinline__ void fill_block_body(const Ctx &c, int l, unsigned bi
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_CONTRACT, g)) return;
     const int32_t *cmap = L->cmap;
+    const int64_t nc = c.lv[l + 1].n;
     const int64_t count = c.cs.row_cnt[cls];
     const int32_t *list = class_list(c.cs, g.n, cls);
     for (int64_t i = bid; i < count; i += nb) {
         const int32_t x = list[i];
         const RowSrc r = row_src(g, c, x);
-        const int tot = (int)r.tot;
         int P = 2;
-        while (P < tot) P <<= 1;
+        while (P < r.tot) P <<= 1;
         if (P > PMAX) {   // valid class lists never
             if (threadIdx.x == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_STATE);
             continue;
         }
-        for (int t0 = threadIdx.x; t0 < P; t0 += NT * 4) {
-            uint64_t val[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int t = t0 + u * NT;
-                val[u] = ~0ull;
-                if (t < tot) {
-                    uint32_t k, w;
-                    row_entry(g, cmap, r, t, k, w);
-                    val[u] = ((uint64_t)k << 32) | w;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (t0 + u * NT < P) s[t0 + u * NT] = val[u];
-        }
-        __syncthreads();
-        block_sort<NT>(s, P);
-        // leaders: first entry of each run of equal keys
-        // (the sorted entries are in the padded layout)
-        const int ipt = (P + NT - 1) / NT;
-        const int t0 = threadIdx.x * ipt;
-        int64_t mine = 0;
-        for (int q = 0; q < ipt; ++q) {
-            int t = t0 + q;
-            if (t >= P) break;
-            uint32_t k = (uint32_t)(s[lds_pad(t)] >> 32);
-            if (k != INVALID_KEY && (t == 0 || (uint32_t)(s[lds_pad(t - 1)] >> 32) != k)) ++mine;
-        }
+        const int lp = __builtin_ctz(P);
         int64_t total;
-        int64_t rank = block_excl_scan(mine, sh, &total);
-        for (int q = 0; q < ipt; ++q) {
-            int t = t0 + q;
-            if (t >= P) break;
-            uint32_t k = (uint32_t)(s[lds_pad(t)] >> 32);
-            if (k == INVALID_KEY || (t > 0 && (uint32_t)(s[lds_pad(t - 1)] >> 32) == k)) continue;
-            uint32_t sum = 0;
-            for (int e = t; e < P && (uint32_t)(s[lds_pad(e)] >> 32) == k; ++e)
-                sum += (uint32_t)s[lds_pad(e)];
-            int64_t at = staged_at(r, rank);
-            c.cs.tmp_adj[at] = (int32_t)k;
-            c.cs.tmp_ew[at] = sum;
-            ++rank;
+        if ((P == 4 * NT || P == 8 * NT || P == 16 * NT) && narrow_fits(nc, lp)) {
+            // values in the first lds_padded(P) words, weights after lds_padded(PMAX)
+            uint32_t *s32 = (uint32_t *)s;
+            total = block_row_merge<NT>(c, g, cmap, r, P, s32,
+                                        NarrowRep{s32 + lds_padded(PMAX), lp}, sh);
+        } else {
+            total = block_row_merge<NT>(c, g, cmap, r, P, s, WideRep{}, sh);
         }
         if (threadIdx.x == 0) c.cs.cdeg[x] = (int32_t)total;
         __syncthreads();
@@ -2105,71 +2196,92 @@ __global__ void __launch_bounds__(BIG_THREADS) fill_big_k(Ctx c, int l) {
 //          compacted into the wave's LDS slice, bitonic-sorted in registers and
 //          lane shuffles, written back in order, then a leader scan ------------------
 constexpr int WR_P = ROW_WAVE_MAX;   // sort size of a wave row (power of two)
+constexpr int WR_LP = 9;             // log2(WR_P): the narrow form's position bits
+static_assert((1 << WR_LP) == WR_P, "wave row position bits");
+template <class Rep>
+__device__ __forceinline__ int32_t wave_row_merge(const Ctx &c, const DevGraph &g,
+                                                  const int32_t *cmap, const RowSrc &r,
+                                                  typename Rep::T *s, const Rep &rep) {
+    using T = typename Rep::T;
+    const int lane = lane_id();
+    // the renamed entries without the contracted edge (at most the row's
+    // bound, <= WR_P of them), packed to the front of the slice
+    const int tot = (int)r.tot;
+    constexpr int U = (WR_P + 2 + WAVE - 1) / WAVE;   // entries per lane (bound + 2 at most)
+    uint32_t kk[U], ww[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int t = u * WAVE + lane;
+        kk[u] = INVALID_KEY;
+        ww[u] = 0;
+        if (t < tot) row_entry(g, cmap, r, t, kk[u], ww[u]);
+    }
+    int q = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const bool keep = kk[u] != INVALID_KEY;
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+            const int pos = q + (int)__popcll(m & lanemask_lt());
+            s[pos] = rep.make(kk[u], ww[u], pos);
+        }
+        q += (int)__popcll(m);
+    }
+    int P = WAVE;
+    while (P < q) P <<= 1;
+    for (int t = q + lane; t < P; t += WAVE) s[t] = (T)~(T)0;   // padding sorts last
+    wave_sync_lds();
+    // in registers and lane shuffles (P / WAVE values per lane)
+    if (P == WAVE) block_sort_regs<1, WAVE, T>(s, lane);
+    else if (P == 2 * WAVE) block_sort_regs<2, WAVE, T>(s, lane);
+    else if (P == 4 * WAVE) block_sort_regs<4, WAVE, T>(s, lane);
+    else block_sort_regs<8, WAVE, T>(s, lane);
+    wave_sync_lds();
+    // leaders (first entry of each run of equal keys) in order; runs summed
+    // (the sorted entries are in the padded layout)
+    int32_t rank = 0;
+    for (int t0 = 0; t0 < P; t0 += WAVE) {
+        const int t = t0 + lane;
+        const uint32_t k = rep.key(s[lds_pad(t)]);
+        const bool lead = k != INVALID_KEY && (t == 0 || rep.key(s[lds_pad(t - 1)]) != k);
+        const uint64_t m = __ballot(lead);
+        if (lead) {
+            uint32_t sum = 0;
+            for (int e = t; e < P; ++e) {
+                const T v = s[lds_pad(e)];
+                if (rep.key(v) != k) break;
+                sum += rep.weight(v);
+            }
+            const int64_t at = staged_at(r, rank + (int32_t)__popcll(m & lanemask_lt()));
+            c.cs.tmp_adj[at] = (int32_t)k;
+            c.cs.tmp_ew[at] = sum;
+        }
+        rank += (int32_t)__popcll(m);
+    }
+    return rank;
+}
 template <int NT>
 __device__ __forceinline__ void fill_wave_body(const Ctx &c, int l, unsigned bid, unsigned nb,
                                                uint64_t *lds) {
     static_assert((WR_P & (WR_P - 1)) == 0 && WR_P % WAVE == 0, "wave sort size");
+    static_assert(lds_padded(WR_P) + WR_P <= 2 * lds_padded(WR_P), "narrow weights fit the slice");
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_CONTRACT, g)) return;
     const int32_t *cmap = L->cmap;
+    const bool narrow = narrow_fits(c.lv[l + 1].n, WR_LP);
     const int64_t count = c.cs.row_cnt[1];
     const int32_t *list = class_list(c.cs, g.n, 1);
     const int wv = threadIdx.x / WAVE, lane = lane_id();
     uint64_t *s = lds + (int64_t)wv * lds_padded(WR_P);
+    uint32_t *s32 = (uint32_t *)s;
     const int64_t gw = (int64_t)bid * (NT / WAVE) + wv, gs = (int64_t)nb * (NT / WAVE);
     for (int64_t i = gw; i < count; i += gs) {   // wave-uniform
         const int32_t x = list[i];
         const RowSrc r = row_src(g, c, x);
-        // the renamed entries without the contracted edge (at most the row's
-        // bound, <= WR_P of them), packed to the front of the slice
-        const int tot = (int)r.tot;
-        constexpr int U = (WR_P + 2 + WAVE - 1) / WAVE;   // entries per lane (bound + 2 at most)
-        uint32_t kk[U], ww[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int t = u * WAVE + lane;
-            kk[u] = INVALID_KEY;
-            ww[u] = 0;
-            if (t < tot) row_entry(g, cmap, r, t, kk[u], ww[u]);
-        }
-        int q = 0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool keep = kk[u] != INVALID_KEY;
-            const uint64_t m = __ballot(keep);
-            if (keep) s[q + __popcll(m & lanemask_lt())] = ((uint64_t)kk[u] << 32) | ww[u];
-            q += (int)__popcll(m);
-        }
-        int P = WAVE;
-        while (P < q) P <<= 1;
-        for (int t = q + lane; t < P; t += WAVE) s[t] = ~0ull;   // padding sorts last
-        wave_sync_lds();
-        // in registers and lane shuffles (P / WAVE values per lane)
-        if (P == WAVE) block_sort_regs<1, WAVE>(s, lane);
-        else if (P == 2 * WAVE) block_sort_regs<2, WAVE>(s, lane);
-        else if (P == 4 * WAVE) block_sort_regs<4, WAVE>(s, lane);
-        else block_sort_regs<8, WAVE>(s, lane);
-        wave_sync_lds();
-        // leaders (first entry of each run of equal keys) in order; runs
-        // summed (the sorted entries are in the padded layout)
-        int32_t rank = 0;
-        for (int t0 = 0; t0 < P; t0 += WAVE) {
-            const int t = t0 + lane;
-            const uint32_t k = (uint32_t)(s[lds_pad(t)] >> 32);
-            const bool lead =
-                k != INVALID_KEY && (t == 0 || (uint32_t)(s[lds_pad(t - 1)] >> 32) != k);
-            const uint64_t m = __ballot(lead);
-            if (lead) {
-                uint32_t sum = 0;
-                for (int e = t; e < P && (uint32_t)(s[lds_pad(e)] >> 32) == k; ++e)
-                    sum += (uint32_t)s[lds_pad(e)];
-                const int64_t at = staged_at(r, rank + (int32_t)__popcll(m & lanemask_lt()));
-                c.cs.tmp_adj[at] = (int32_t)k;
-                c.cs.tmp_ew[at] = sum;
-            }
-            rank += (int32_t)__popcll(m);
-        }
+        const int32_t rank =
+            narrow ? wave_row_merge(c, g, cmap, r, s32, NarrowRep{s32 + lds_padded(WR_P), WR_LP})
+                   : wave_row_merge(c, g, cmap, r, s, WideRep{});
         if (lane == 0) c.cs.cdeg[x] = rank;
         wave_sync_lds();   // the slice is rewritten by the next row
     }

@@ -579,7 +579,10 @@ struct LevelDesc {
     int64_t matched;
     int32_t rounds, stop, phase;
     int32_t grid_rounds;   // rounds run by the multi-block kernels (the rest: the finisher)
-    int64_t stat[STAT_ROUNDS][2];   // per round: nodes with a free neighbour, their degree sum
+    // per round: nodes with a free neighbour, their degree sum; the rows
+    // rescanned in the round and their degree sum (the same two where every
+    // such node rescans)
+    int64_t stat[STAT_ROUNDS][4];
 };
 
 enum ControlFlags : uint32_t {
@@ -611,7 +614,9 @@ struct MatchState {
     int32_t handoff;        // -1: rounds continue; r >= 0: the finisher resumes after round r; -2: done
     int32_t pad[3];
     int32_t sround[NSHARD];               // per shard: last round in which some node pointed
-    int64_t sstat[STAT_ROUNDS][3][NSHARD];  // per round and shard: pointing nodes, their degree sum, pairs
+    // per round and shard: pointing nodes, their degree sum, pairs, rows
+    // rescanned, their degree sum
+    int64_t sstat[STAT_ROUNDS][5][NSHARD];
     int64_t spairs[NSHARD];                 // two-phase merge: pairs per shard (zero between uses)
 };
 
