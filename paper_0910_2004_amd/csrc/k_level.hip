@@ -2817,13 +2817,29 @@ __device__ __forceinline__ void compact_small_body(const Ctx &c, int l, unsigned
         }
         uint32_t sum = 0;
         if (mine) {
-            int64_t dst = N->xadj[x];
-            for (int t = sub; t < len; t += ROW_SMALL_G) {
-                int64_t at = staged_at(r, t);
-                uint32_t w = c.cs.tmp_ew[at];
-                N->adj[dst + t] = c.cs.tmp_adj[at];
-                N->ew[dst + t] = w;
-                sum += w;
+            // a lane's entries loaded before any is stored (the stores could
+            // alias the loads as far as the compiler knows)
+            constexpr int U = (SM_CAP + ROW_SMALL_G - 1) / ROW_SMALL_G;
+            const int64_t dst = N->xadj[x];
+            int32_t kk[U];
+            uint32_t ww[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = sub + u * ROW_SMALL_G;
+                if (t < len) {
+                    const int64_t at = staged_at(r, t);
+                    kk[u] = c.cs.tmp_adj[at];
+                    ww[u] = c.cs.tmp_ew[at];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = sub + u * ROW_SMALL_G;
+                if (t < len) {
+                    N->adj[dst + t] = kk[u];
+                    N->ew[dst + t] = ww[u];
+                    sum += ww[u];
+                }
             }
         }
         if (out) {
@@ -2851,12 +2867,27 @@ __device__ __forceinline__ void compact_wave_body(const Ctx &c, int l, unsigned 
         const int64_t dst = N->xadj[x];
         const int32_t len = c.cs.cdeg[x];
         uint32_t sum = 0;
-        for (int t = lane; t < len; t += WAVE) {
-            const int64_t at = staged_at(r, t);
-            const uint32_t w = c.cs.tmp_ew[at];
-            N->adj[dst + t] = c.cs.tmp_adj[at];
-            N->ew[dst + t] = w;
-            sum += w;
+        // a lane's entries loaded before any is stored
+        constexpr int U = ROW_WAVE_MAX / WAVE;
+        int32_t kk[U];
+        uint32_t ww[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = lane + u * WAVE;
+            if (t < len) {
+                const int64_t at = staged_at(r, t);
+                kk[u] = c.cs.tmp_adj[at];
+                ww[u] = c.cs.tmp_ew[at];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = lane + u * WAVE;
+            if (t < len) {
+                N->adj[dst + t] = kk[u];
+                N->ew[dst + t] = ww[u];
+                sum += ww[u];
+            }
         }
         if (out) {
             sum = wave_sum(sum);
@@ -2886,12 +2917,28 @@ __device__ __forceinline__ void compact_big_body(const Ctx &c, int l, unsigned b
         int64_t dst = N->xadj[x];
         int32_t len = c.cs.cdeg[x];
         uint32_t sum = 0;
-        for (int t = threadIdx.x; t < len; t += NT) {
-            int64_t at = staged_at(r, t);
-            uint32_t w = c.cs.tmp_ew[at];
-            N->adj[dst + t] = c.cs.tmp_adj[at];
-            N->ew[dst + t] = w;
-            sum += w;
+        // four entries per thread loaded before they are stored
+        for (int t0 = threadIdx.x; t0 < len; t0 += 4 * NT) {
+            int32_t kk[4];
+            uint32_t ww[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + u * NT;
+                if (t < len) {
+                    const int64_t at = staged_at(r, t);
+                    kk[u] = c.cs.tmp_adj[at];
+                    ww[u] = c.cs.tmp_ew[at];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + u * NT;
+                if (t < len) {
+                    N->adj[dst + t] = kk[u];
+                    N->ew[dst + t] = ww[u];
+                    sum += ww[u];
+                }
+            }
         }
         if (out) {
             sum = block_sum(sum, sh);
