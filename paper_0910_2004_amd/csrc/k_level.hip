@@ -1771,18 +1771,47 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Class-list appends through a per-wave LDS buffer: a wave writes its list
+// entries out WBUF_FLUSH or more at a time with one atomic on the list's
+// counter, instead of one (returning) atomic per loop iteration; those
+// atomics all hit one address and serialise across the chip.  n is
+// wave-uniform.
+constexpr int WBUF_FLUSH = 32;
+constexpr int WBUF_CAP = WBUF_FLUSH + WAVE;
+__device__ __forceinline__ void wbuf_flush(int32_t *buf, int &n, int32_t *list, int32_t *counter) {
+    if (n == 0) return;
+    wave_sync_lds();
+    int base = 0;
+    if (lane_id() == 0) base = atomicAdd(counter, n);
+    base = __shfl(base, 0, WAVE);
+    for (int t = lane_id(); t < n; t += WAVE) list[base + t] = buf[t];
+    n = 0;
+    wave_sync_lds();   // the buffer is refilled next
+}
+__device__ __forceinline__ void wbuf_add(bool pred, int32_t val, int32_t *buf, int &n,
+                                         int32_t *list, int32_t *counter) {
+    const uint64_t mask = __ballot(pred);
+    if (mask == 0) return;
+    if (pred) buf[n + (int)__popcll(mask & lanemask_lt())] = val;
+    n += (int)__popcll(mask);
+    if (n >= WBUF_FLUSH) wbuf_flush(buf, n, list, counter);
+}
+
 // --- 2a. small rows: 16 lanes per row, rank sort; every coarse row passes
 //         here (empty rows get degree 0, bigger rows go to the class lists) --
 // The contraction phases below are written for `nb` blocks of NT threads
 // (block `bid`): the kernels run them over their grid; the tail kernel runs
 // them in one workgroup.
 // BIG: rows of the big class get their own list (false: they join the large rows).
-template <int NT, bool BIG = true>
+// BUF: class-list appends through per-wave LDS buffers (wbuf_add).
+template <int NT, bool BIG = true, bool BUF = false>
 __device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bid, unsigned nb) {
     constexpr int ROWS = NT / ROW_SMALL_G;
     __shared__ uint32_t sk[ROWS][SM_CAP];   // renamed entries
     __shared__ uint32_t sr[ROWS][SM_CAP];   // first occurrences only (others INVALID_KEY)
     __shared__ uint32_t sw[ROWS][SM_CAP];   // weights; a first occurrence collects its duplicates'
+    __shared__ int32_t wb[BUF ? NT / WAVE : 1][4][BUF ? WBUF_CAP : 1];
+    int wn[4] = {0, 0, 0, 0};
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_CONTRACT, g)) return;
@@ -1808,10 +1837,18 @@ __device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bi
             if (cls == 2 && !c.cs.hub_acc && !(BIG && c.huge && huge_row(count, r.tot)))
                 need_hubs = true;
         }
-        wave_append(sub == 0 && cls == 1, x, lists1, &c.cs.row_cnt[1]);
-        wave_append(sub == 0 && cls == 2, x, lists2, &c.cs.row_cnt[2]);
-        wave_append(sub == 0 && cls == 3, x, lists3, &c.cs.row_cnt[3]);
-        wave_append(sub == 0 && cls == 4, x, lists4, &c.cs.row_cnt[4]);
+        if constexpr (BUF) {
+            int32_t(*b)[WBUF_CAP] = wb[threadIdx.x / WAVE];
+            wbuf_add(sub == 0 && cls == 1, x, b[0], wn[0], lists1, &c.cs.row_cnt[1]);
+            wbuf_add(sub == 0 && cls == 2, x, b[1], wn[1], lists2, &c.cs.row_cnt[2]);
+            wbuf_add(sub == 0 && cls == 3, x, b[2], wn[2], lists3, &c.cs.row_cnt[3]);
+            wbuf_add(sub == 0 && cls == 4, x, b[3], wn[3], lists4, &c.cs.row_cnt[4]);
+        } else {
+            wave_append(sub == 0 && cls == 1, x, lists1, &c.cs.row_cnt[1]);
+            wave_append(sub == 0 && cls == 2, x, lists2, &c.cs.row_cnt[2]);
+            wave_append(sub == 0 && cls == 3, x, lists3, &c.cs.row_cnt[3]);
+            wave_append(sub == 0 && cls == 4, x, lists4, &c.cs.row_cnt[4]);
+        }
         const int tot = cls == 0 ? (int)r.tot : 0;
         {
             constexpr int U = (SM_CAP + ROW_SMALL_G - 1) / ROW_SMALL_G;   // entries per lane
@@ -1859,10 +1896,17 @@ __device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bi
         if (live && sub == 0 && cls <= 0) c.cs.cdeg[x] = nl;
         wave_sync_lds();
     }
+    if constexpr (BUF) {
+        int32_t(*b)[WBUF_CAP] = wb[threadIdx.x / WAVE];
+        wbuf_flush(b[0], wn[0], lists1, &c.cs.row_cnt[1]);
+        wbuf_flush(b[1], wn[1], lists2, &c.cs.row_cnt[2]);
+        wbuf_flush(b[2], wn[2], lists3, &c.cs.row_cnt[3]);
+        wbuf_flush(b[3], wn[3], lists4, &c.cs.row_cnt[4]);
+    }
     if (__ballot(need_hubs) && lane_id() == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_HUBS);
 }
 __global__ void __launch_bounds__(BLOCK) fill_small_k(Ctx c, int l) {
-    fill_small_body<BLOCK>(c, l, blockIdx.x, gridDim.x);
+    fill_small_body<BLOCK, true, true>(c, l, blockIdx.x, gridDim.x);
 }
 
 // Sorted arrays in LDS are left in a padded layout: position p lives in
@@ -2775,17 +2819,32 @@ __global__ void __launch_bounds__(HUGE_THREADS) fill_huge_pack_k(Ctx c, int l) {
         }
         if (threadIdx.x == 0) off[nwin] = (int32_t)total;
         __syncthreads();
-        for (int64_t p = threadIdx.x; p < total; p += NT) {
-            int lo = 0, hi = nwin - 1;   // the group holding output position p
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (off[mid] <= p) lo = mid;
-                else hi = mid - 1;
+        // four positions per thread, loaded before they are stored
+        for (int64_t p0 = threadIdx.x; p0 < total; p0 += 4 * NT) {
+            int32_t kk[4];
+            uint32_t ww[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t p = p0 + (int64_t)u * NT;
+                if (p >= total) continue;
+                int lo = 0, hi = nwin - 1;   // the group holding output position p
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (off[mid] <= p) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int64_t src = staged_at(r, first[lo] + (p - off[lo]));
+                kk[u] = c.cs.hg_adj[src];
+                ww[u] = c.cs.hg_ew[src];
             }
-            const int64_t src = staged_at(r, first[lo] + (p - off[lo]));
-            const int64_t dst = staged_at(r, p);
-            c.cs.tmp_adj[dst] = c.cs.hg_adj[src];
-            c.cs.tmp_ew[dst] = c.cs.hg_ew[src];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t p = p0 + (int64_t)u * NT;
+                if (p >= total) continue;
+                const int64_t dst = staged_at(r, p);
+                c.cs.tmp_adj[dst] = kk[u];
+                c.cs.tmp_ew[dst] = ww[u];
+            }
         }
         if (threadIdx.x == 0) c.cs.cdeg[x] = (int32_t)total;
         __syncthreads();   // off and first are rewritten for the next row
