@@ -727,13 +727,14 @@ void carve_scratch(Carve &cv, const DevGraph &g, int rating, bool hubs, Ctx &c,
     // two-phase matcher (c.block_bits set before carving)
     ms.loc = c.block_bits >= 0 ? cv.get<int32_t>(g.n) : nullptr;
     ms.lkey = c.block_bits >= 0 ? cv.get<LocKey>(g.n) : nullptr;
-    ms.hub = HubChunks{nullptr, nullptr, nullptr, 0, nullptr};
+    ms.hub = HubChunks{nullptr, nullptr, nullptr, 0, nullptr, nullptr};
     if (chunks) {
         ms.hub.cap = hub_chunk_cap(g.nnz);
         ms.hub.rec = cv.get<int2>(2 * ms.hub.cap);
         ms.hub.first = cv.get<int32_t>(2 * (int64_t)g.n);
         ms.hub.part = cv.get<Cand>(ms.hub.cap);
         ms.hub.scan = cv.get<int2>(2 * (int64_t)g.n);
+        ms.hub.kfirst = cv.get<int32_t>(g.n);
     }
 }
 

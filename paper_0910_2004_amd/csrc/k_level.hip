@@ -307,34 +307,41 @@ __device__ __forceinline__ uint64_t row_seed(const Ctx &c, const DevGraph &g, in
 constexpr int MK = 8;
 // Where the chunk records of appended bin-2 entries go (rec == nullptr: none;
 // the one-workgroup finisher scans long rows whole).  cnt: the record counter.
+// kfirst (round 1 only): each row's first record is also kept by node.
 struct HubOut {
     int2 *rec;
     int32_t *first;
     int32_t *cnt;
     int64_t cap;
+    int32_t *kfirst;
 };
 __device__ __forceinline__ HubOut hub_out(const Ctx &c, int32_t n, int par, int32_t *cnt3) {
-    HubOut h{nullptr, nullptr, nullptr, 0};
+    HubOut h{nullptr, nullptr, nullptr, 0, nullptr};
     if (!c.ms.hub.rec) return h;
     h.rec = c.ms.hub.rec + (int64_t)par * c.ms.hub.cap;
     h.first = c.ms.hub.first + (int64_t)par * n;
     h.cnt = cnt3 + 3;
     h.cap = c.ms.hub.cap;
+    h.kfirst = c.ms.hub.kfirst;
     return h;
 }
 __device__ __forceinline__ int32_t hub_chunks_of(int64_t deg) {
     return (int32_t)((deg + HUB_CHUNK - 1) / HUB_CHUNK);
 }
-// Records {p, 0 .. k-1} for the bin-2 entry at list position p of degree d.
-__device__ __forceinline__ void hub_emit(const HubOut &h, int32_t p, int32_t d, Control *ctrl) {
+// Records {p, 0 .. k-1} for the bin-2 entry (node v) at list position p of
+// degree d.
+__device__ __forceinline__ void hub_emit(const HubOut &h, int32_t p, int32_t v, int32_t d,
+                                         Control *ctrl) {
     const int32_t k = hub_chunks_of(d);
     const int32_t base = atomicAdd(h.cnt, k);
     if ((int64_t)base + k > h.cap) {   // cannot happen: the capacity bounds every level
         atomicOr(&ctrl->flags, (uint32_t)CF_STATE);
         h.first[p] = -1;
+        if (h.kfirst) h.kfirst[v] = -1;
         return;
     }
     h.first[p] = base;
+    if (h.kfirst) h.kfirst[v] = base;
     for (int32_t q = 0; q < k; ++q) h.rec[base + q] = make_int2(p, q);
 }
 __device__ __forceinline__ void block_append_mk(const int bin[MK], const int32_t v[MK],
@@ -367,7 +374,7 @@ __device__ __forceinline__ void block_append_mk(const int bin[MK], const int32_t
         o.v[p] = v[k];
         o.b[p] = b[k];
         o.d[p] = d[k];
-        if (bin[k] == 2 && ho.rec) hub_emit(ho, p, d[k], ctrl);
+        if (bin[k] == 2 && ho.rec) hub_emit(ho, p, v[k], d[k], ctrl);
     }
     __syncthreads();   // sbase is reused by the next call
 }
@@ -620,27 +627,43 @@ __device__ __forceinline__ void pick_scan1(const Ctx &c, const DevGraph &g, uint
 }
 
 // bin 2 in the grid rounds: one block per chunk of HUB_CHUNK entries.  A row
-// of one chunk gets its choice at once; longer rows leave one maximum per
-// chunk in hub.part for hub_reduce_k.  Records exist only for rows that scan
-// this round (round 1: every row; later rounds: the rows whose choice was
-// matched away, found by prep_k).
+// of one chunk gets its choice at once; longer rows keep one maximum per
+// chunk in hub.part, at the row's round-1 records (hub.kfirst) for the whole
+// level, for hub_reduce_k.  Records exist only for rows that scan this round
+// (round 1: every row; later rounds: the rows whose choice was matched away,
+// found by prep_k).  In a later round a chunk whose kept maximum is still
+// free, or that had no free neighbour, keeps it without a scan: the free
+// set only shrinks, so that maximum is still the chunk's best free
+// neighbour.  r: the round (statistics).
 template <int R, bool FIRST>
 __device__ __forceinline__ void pick_bin2_chunks(const Ctx &c, const DevGraph &g, uint64_t seed,
                                                  const RoundIn &ri, unsigned bid, unsigned nb,
-                                                 Cand *sh) {
+                                                 Cand *sh, int r) {
     constexpr int T = HUB_CHUNK / BLOCK;
     static_assert(T * BLOCK == HUB_CHUNK, "a chunk is T entries per thread");
     int32_t *best = c.ms.best;
     const int2 *nrec = c.ms.nrec;
     const uint32_t *out = c.ms.out;
+    int64_t scanned = 0;   // entries scanned by this block (thread 0)
     for (int64_t q = bid; q < ri.nrec; q += nb) {   // block-uniform
         const int2 rc = ri.rec[q];
         if ((uint32_t)rc.x >= (uint32_t)ri.cn[2]) continue;   // valid records never
         const int32_t v = checked_node(ri.in[2].v[rc.x], g.n, c.ctrl);
         if (v < 0) continue;
         const int64_t rb = g.xadj[v], re = g.xadj[v + 1];
+        const int32_t kc = hub_chunks_of(re - rb);
+        const int32_t kf = kc > 1 ? c.ms.hub.kfirst[v] : 0;
+        if (kc > 1 && (kf < 0 || (int64_t)kf + kc > c.ms.hub.cap)) {   // valid records never
+            if (threadIdx.x == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_STATE);
+            continue;
+        }
+        if (!FIRST && kc > 1) {
+            const int32_t ku = c.ms.hub.part[kf + rc.y].u;
+            if (ku < 0 || nrec[ku].y < 0) continue;
+        }
         const int64_t j0 = rb + (int64_t)rc.y * HUB_CHUNK;
         const int64_t j1 = min(re, j0 + HUB_CHUNK);
+        scanned += j1 - j0;
         const uint32_t av = FIRST ? attr_src<R>(g, out, v) : (uint32_t)nrec[v].x;
         const int32_t base = local_base(g, v);
         const uint64_t sv = row_seed(c, g, v, seed);
@@ -677,14 +700,18 @@ __device__ __forceinline__ void pick_bin2_chunks(const Ctx &c, const DevGraph &g
         }
         cd = block_reduce_cand(cd, v, sh);
         if (threadIdx.x == 0) {
-            if (hub_chunks_of(re - rb) == 1) {
+            if (kc == 1) {
                 best[v] = cd.u;
                 ri.in[2].b[rc.x] = cd.u;
             } else {
-                const int32_t f = ri.first[rc.x];
-                if (f >= 0) c.ms.hub.part[f + rc.y] = cd;
+                c.ms.hub.part[kf + rc.y] = cd;
             }
         }
+    }
+    if (!FIRST && threadIdx.x == 0 && scanned > 0) {
+        const int ri_ = r - 1 < STAT_ROUNDS ? r - 1 : STAT_ROUNDS - 1;
+        atomicAdd((unsigned long long *)&c.ms.state->sstat[ri_][4][shard_of_block()],
+                  (unsigned long long)scanned);
     }
 }
 
@@ -863,7 +890,7 @@ __global__ void __launch_bounds__(BLOCK) pick_k(Ctx c, int l, int r, PickGrid pg
         bid -= pg.b0;
         if (bid < pg.b1) { pick_scan1<R>(c, g, seed, ri, bid, pg.b1); return; }
         bid -= pg.b1;
-        pick_bin2_chunks<R, false>(c, g, seed, ri, bid, pg.b2, sh);
+        pick_bin2_chunks<R, false>(c, g, seed, ri, bid, pg.b2, sh, r);
         return;
     }
     if (bid < pg.b0) { pick_bin0<R, FIRST, F>(c, g, seed, ri, bid, pg.b0); return; }
@@ -871,7 +898,7 @@ __global__ void __launch_bounds__(BLOCK) pick_k(Ctx c, int l, int r, PickGrid pg
     if (bid < pg.b1) { pick_bin1<R, FIRST, F>(c, g, seed, ri, bid, pg.b1); return; }
     bid -= pg.b1;
     if (F == 0 && ri.rec)
-        pick_bin2_chunks<R, FIRST>(c, g, seed, ri, bid, pg.b2, sh);
+        pick_bin2_chunks<R, FIRST>(c, g, seed, ri, bid, pg.b2, sh, r);
     else
         pick_bin2<R, FIRST, BLOCK, F>(c, g, seed, ri, bid, pg.b2, sh);
 }
@@ -903,7 +930,7 @@ __global__ void __launch_bounds__(BLOCK) prep_k(Ctx c, int l, int r) {
     int2 *const scan0 = c.ms.hub.scan, *const scan1 = c.ms.hub.scan + g.n;
     const int par = (r - 1) & 1;
     const HubOut ho{c.ms.hub.rec + (int64_t)par * c.ms.hub.cap,
-                    c.ms.hub.first + (int64_t)par * g.n, sc + 3, c.ms.hub.cap};
+                    c.ms.hub.first + (int64_t)par * g.n, sc + 3, c.ms.hub.cap, nullptr};
     const int2 *nrec = c.ms.nrec;
     const int64_t row = (int64_t)gridDim.x * blockDim.x, per_pass = row * MK;
     int64_t rrows = 0, rdeg = 0;   // the round's rescanning rows and their degrees
@@ -934,7 +961,7 @@ __global__ void __launch_bounds__(BLOCK) prep_k(Ctx c, int l, int r) {
             if (bin[k] >= 0 && !live) bin[k] = -1;   // valid lists never
             if (resc[k]) {
                 ++rrows;
-                rdeg += dd[k];
+                if (bin[k] < 2) rdeg += dd[k];   // chunked rows: the pick counts what it scans
             }
         }
         // rows of bins 0 and 1 that rescan: block-aggregated append
@@ -954,7 +981,7 @@ __global__ void __launch_bounds__(BLOCK) prep_k(Ctx c, int l, int r) {
 #pragma unroll
         for (int k = 0; k < MK; ++k) {
             if (bin[k] == 2) {
-                if (resc[k]) hub_emit(ho, jj[k], dd[k], c.ctrl);
+                if (resc[k]) hub_emit(ho, jj[k], vv[k], dd[k], c.ctrl);
                 else ho.first[jj[k]] = -1;
             } else if (resc[k]) {
                 if (bin[k] == 0) scan0[p0++] = make_int2(vv[k], jj[k]);
@@ -993,9 +1020,11 @@ __global__ void __launch_bounds__(BLOCK) hub_reduce_k(Ctx c, int l, int r) {
         if ((uint32_t)v >= (uint32_t)g.n) continue;   // flagged by the pick
         const int32_t k = hub_chunks_of(g.xadj[v + 1] - g.xadj[v]);
         if (k <= 1) continue;
+        const int32_t kf = c.ms.hub.kfirst[v];   // the row's chunk maxima for the level
+        if (kf < 0 || (int64_t)kf + k > c.ms.hub.cap) continue;   // flagged by the pick
         Cand cd = cand_none();
         for (int32_t q = lane_id(); q < k; q += WAVE) {
-            const Cand o = c.ms.hub.part[f + q];
+            const Cand o = c.ms.hub.part[kf + q];
             if (cand_better(o, cd, v)) cd = o;
         }
         cd = group_reduce<WAVE>(cd, v);

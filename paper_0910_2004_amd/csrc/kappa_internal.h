@@ -642,6 +642,8 @@ struct HubChunks {
     int64_t cap;
     int2 *scan;      // 2 * n: per bin 0 / 1, {node, list position} of the rows a round
                      // rescans (written by the round's preparation)
+    int32_t *kfirst; // n: per node of a chunked row, its first record of round 1, where
+                     // part keeps the row's chunk maxima for the rest of the level
 };
 struct MatchScratch {
     int32_t *best;          // n: current choice of every node (-1: none)
