@@ -207,7 +207,7 @@ def model_bytes(stats_by_rating, classes=None, n0=0, D0=0):
 KERNEL_SYMBOLS = {"pick": r"pick_k<\d, false, 0, (true|false)>", "mate": r"mate_k<\d, false>",
                   "pick_first": r"pick_k<\d, true, 0, false>", "fill_small": r"fill_small_k",
                   "fill_mid": r"fill_mid_k", "fill_big": r"fill_big_k",
-                  "fill_large": r"fill_large_k", "validate_entries": r"validate_entries_k",
+                  "fill_large": r"fill_large_k", "validate_entries": r"validate_entries_k(<(true|false)>)?",
                   "compact": r"compact_k", "cut_entries": r"up_entries_k<(true|false)>",
                   "refine_fm": r"ref_fm_k"}
 # the sources a kernel's stored counters depend on (they go stale when these change)
