@@ -1952,11 +1952,12 @@ __device__ __forceinline__ int lds_pad(int p) { return p + (p >> 5); }
 // pairs first, first + stride, ...; each thread loads up to BS_BATCH pairs
 // before it stores any (the pairs of a stage are disjoint).
 constexpr int BS_BATCH = 8;
-__device__ __forceinline__ void bitonic_stage(uint64_t *s, int lo, int npairs, int k, int j,
-                                              int first, int stride) {
+template <class T>
+__device__ __forceinline__ void bitonic_stage(T *s, int lo, int npairs, int k, int j, int first,
+                                              int stride) {
     const int lj = __ffs(j) - 1;
     for (int p0 = first; p0 < npairs; p0 += stride * BS_BATCH) {
-        uint64_t a[BS_BATCH], b[BS_BATCH];
+        T a[BS_BATCH], b[BS_BATCH];
         int t[BS_BATCH];
 #pragma unroll
         for (int q = 0; q < BS_BATCH; ++q) {
@@ -2066,11 +2067,11 @@ __device__ __forceinline__ void block_sort_regs(T *s, int tid) {
 
 // The register sort for P = E * NT with E in {4, 8, 16}; false: not such a P
 // (the caller sorts in LDS instead).
-template <int NT>
-__device__ __forceinline__ bool block_sort_regs_p(uint64_t *s, int P) {
-    if (P == 4 * NT) block_sort_regs<4, NT>(s, threadIdx.x);
-    else if (P == 8 * NT) block_sort_regs<8, NT>(s, threadIdx.x);
-    else if (P == 16 * NT) block_sort_regs<16, NT>(s, threadIdx.x);
+template <int NT, class T = uint64_t>
+__device__ __forceinline__ bool block_sort_regs_p(T *s, int P) {
+    if (P == 4 * NT) block_sort_regs<4, NT, T>(s, threadIdx.x);
+    else if (P == 8 * NT) block_sort_regs<8, NT, T>(s, threadIdx.x);
+    else if (P == 16 * NT) block_sort_regs<16, NT, T>(s, threadIdx.x);
     else return false;
     return true;
 }
@@ -2082,10 +2083,10 @@ __device__ __forceinline__ bool block_sort_regs_p(uint64_t *s, int P) {
 // array (P / waves elements) need only that wave's LDS order and only the
 // few wider stages take a block barrier, followed by a move into the padded
 // layout.  Ends with a block barrier.
-template <int NT>
-__device__ __forceinline__ void block_sort(uint64_t *s, int P) {
+template <int NT, class T = uint64_t>
+__device__ __forceinline__ void block_sort(T *s, int P) {
     constexpr int NW = NT / WAVE;
-    if (block_sort_regs_p<NT>(s, P)) {
+    if (block_sort_regs_p<NT, T>(s, P)) {
         __syncthreads();
         return;
     }
@@ -2113,7 +2114,7 @@ __device__ __forceinline__ void block_sort(uint64_t *s, int P) {
     // it is overwritten
     for (int hi = P; hi > 0; hi -= NT) {
         const int p = hi - NT + (int)threadIdx.x;
-        const uint64_t v = p >= 0 ? s[p] : 0;
+        const T v = p >= 0 ? s[p] : (T)0;
         __syncthreads();
         if (p >= 0) s[lds_pad(p)] = v;
         __syncthreads();
@@ -2135,20 +2136,23 @@ struct WideRep {
     __device__ uint32_t key(T v) const { return (uint32_t)(v >> 32); }
     __device__ uint32_t weight(T v) const { return (uint32_t)v; }
 };
+// base: keys are stored less base (every key of the sort at least base and
+// below base + span, with span << lp < 2^32).
 struct NarrowRep {
     using T = uint32_t;
     uint32_t *wt;   // weights by position
     int lp;
+    uint32_t base;
     __device__ T make(uint32_t key, uint32_t w, int pos) const {
         wt[pos] = w;
-        return key == INVALID_KEY ? ~0u : (key << lp) | (uint32_t)pos;
+        return key == INVALID_KEY ? ~0u : ((key - base) << lp) | (uint32_t)pos;
     }
-    __device__ uint32_t key(T v) const { return v == ~0u ? INVALID_KEY : v >> lp; }
+    __device__ uint32_t key(T v) const { return v == ~0u ? INVALID_KEY : (v >> lp) + base; }
     __device__ uint32_t weight(T v) const { return wt[v & ((1u << lp) - 1)]; }
 };
-// nc << lp < 2^32
-__device__ __forceinline__ bool narrow_fits(int64_t nc, int lp) {
-    return ((uint64_t)nc << lp) < ((uint64_t)1 << 32);
+// span << lp < 2^32 (span: the number of distinct keys possible)
+__device__ __forceinline__ bool narrow_fits(int64_t span, int lp) {
+    return ((uint64_t)span << lp) < ((uint64_t)1 << 32);
 }
 
 // --- 2b'. mid and big rows: one block per row, the row staged in LDS and
@@ -2241,7 +2245,7 @@ __device__ __forceinline__ void fill_block_body(const Ctx &c, int l, unsigned bi
             // values in the first lds_padded(P) words, weights after lds_padded(PMAX)
             uint32_t *s32 = (uint32_t *)s;
             total = block_row_merge<NT>(c, g, cmap, r, P, s32,
-                                        NarrowRep{s32 + lds_padded(PMAX), lp}, sh);
+                                        NarrowRep{s32 + lds_padded(PMAX), lp, 0}, sh);
         } else {
             total = block_row_merge<NT>(c, g, cmap, r, P, s, WideRep{}, sh);
         }
@@ -2353,7 +2357,7 @@ __device__ __forceinline__ void fill_wave_body(const Ctx &c, int l, unsigned bid
         const int32_t x = list[i];
         const RowSrc r = row_src(g, c, x);
         const int32_t rank =
-            narrow ? wave_row_merge(c, g, cmap, r, s32, NarrowRep{s32 + lds_padded(WR_P), WR_LP})
+            narrow ? wave_row_merge(c, g, cmap, r, s32, NarrowRep{s32 + lds_padded(WR_P), WR_LP, 0})
                    : wave_row_merge(c, g, cmap, r, s, WideRep{});
         if (lane == 0) c.cs.cdeg[x] = rank;
         wave_sync_lds();   // the slice is rewritten by the next row
@@ -2683,11 +2687,14 @@ __global__ void __launch_bounds__(HUGE_THREADS) fill_huge_prep_k(Ctx c, int l) {
 }
 
 // The merged entries of a sorted group s[0, P) (padded layout; NT threads, a
-// block or one wave) into hg_adj / hg_ew at positions a, a + 1, ... of row r; returns how
-// many (every thread).  sh: NT / WAVE + 1 int64 of LDS (a block only).
-template <int NT>
-__device__ __forceinline__ int32_t hg_emit(const Ctx &c, const uint64_t *s, int P, const RowSrc &r,
-                                           int32_t a, int64_t *sh) {
+// block or one wave) into hg_adj / hg_ew at positions a, a + 1, ... of row r;
+// returns how many (every thread).  sh: NT / WAVE + 1 int64 of LDS (a block
+// only).
+template <int NT, class Rep>
+__device__ __forceinline__ int32_t hg_emit(const Ctx &c, const typename Rep::T *s, int P,
+                                           const RowSrc &r, int32_t a, int64_t *sh,
+                                           const Rep &rep) {
+    using T = typename Rep::T;
     const int tid = NT == WAVE ? lane_id() : (int)threadIdx.x;
     const int ipt = (P + NT - 1) / NT;
     const int t0 = tid * ipt;
@@ -2695,8 +2702,8 @@ __device__ __forceinline__ int32_t hg_emit(const Ctx &c, const uint64_t *s, int 
     for (int q = 0; q < ipt; ++q) {
         const int t = t0 + q;
         if (t >= P) break;
-        const uint32_t k = (uint32_t)(s[lds_pad(t)] >> 32);
-        if (k != INVALID_KEY && (t == 0 || (uint32_t)(s[lds_pad(t - 1)] >> 32) != k)) ++mine;
+        const uint32_t k = rep.key(s[lds_pad(t)]);
+        if (k != INVALID_KEY && (t == 0 || rep.key(s[lds_pad(t - 1)]) != k)) ++mine;
     }
     int64_t total, rank;
     if (NT == WAVE) {
@@ -2709,11 +2716,14 @@ __device__ __forceinline__ int32_t hg_emit(const Ctx &c, const uint64_t *s, int 
     for (int q = 0; q < ipt; ++q) {
         const int t = t0 + q;
         if (t >= P) break;
-        const uint32_t k = (uint32_t)(s[lds_pad(t)] >> 32);
-        if (k == INVALID_KEY || (t > 0 && (uint32_t)(s[lds_pad(t - 1)] >> 32) == k)) continue;
+        const uint32_t k = rep.key(s[lds_pad(t)]);
+        if (k == INVALID_KEY || (t > 0 && rep.key(s[lds_pad(t - 1)]) == k)) continue;
         uint32_t sum = 0;
-        for (int e = t; e < P && (uint32_t)(s[lds_pad(e)] >> 32) == k; ++e)
-            sum += (uint32_t)s[lds_pad(e)];
+        for (int e = t; e < P; ++e) {
+            const T v = s[lds_pad(e)];
+            if (rep.key(v) != k) break;
+            sum += rep.weight(v);
+        }
         const int64_t at = staged_at(r, a + rank);
         c.cs.hg_adj[at] = (int32_t)k;
         c.cs.hg_ew[at] = sum;
@@ -2722,15 +2732,70 @@ __device__ __forceinline__ int32_t hg_emit(const Ctx &c, const uint64_t *s, int 
     return (int32_t)total;
 }
 
+// The keys of a group lie in its first and last entries' buckets (the
+// entries are in bucket order): the narrow form's key base and span.
+__device__ __forceinline__ void hg_key_range(const Ctx &c, const RowSrc &r, int32_t a, int32_t m,
+                                             int shb, uint32_t &base, int64_t &span) {
+    const uint32_t k0 = (uint32_t)c.cs.tmp_adj[staged_at(r, a)];
+    const uint32_t k1 = (uint32_t)c.cs.tmp_adj[staged_at(r, a + m - 1)];
+    base = (k0 >> shb) << shb;
+    span = ((int64_t)(k1 >> shb) + 1 - (k0 >> shb)) << shb;
+}
+__device__ __forceinline__ int hg_shift(int64_t nc) {
+    int shb = 0;
+    while ((((nc > 0 ? nc : 1) - 1) >> shb) >= HG_BINS) ++shb;   // keys < nc -> buckets < HG_BINS
+    return shb;
+}
+
+// A group's P values (m entries, the rest padding) into s, sorted (block or
+// wave sort by NT), then merged; returns the merged count.
+template <int NT, class Rep>
+__device__ __forceinline__ int32_t hg_group(const Ctx &c, const RowSrc &r, int32_t a, int32_t m,
+                                            int P, typename Rep::T *s, const Rep &rep,
+                                            int64_t *sh) {
+    using T = typename Rep::T;
+    const int tid = NT == WAVE ? lane_id() : (int)threadIdx.x;
+    for (int t0 = tid; t0 < P; t0 += NT * 4) {
+        T val[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u * NT;
+            val[u] = (T)~(T)0;
+            if (t < m) {
+                const int64_t at = staged_at(r, a + t);
+                val[u] = rep.make((uint32_t)c.cs.tmp_adj[at], c.cs.tmp_ew[at], t);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (t0 + u * NT < P) s[t0 + u * NT] = val[u];
+    }
+    if (NT == WAVE) {
+        wave_sync_lds();
+        if (P == WAVE) block_sort_regs<1, WAVE, T>(s, tid);
+        else if (P == 2 * WAVE) block_sort_regs<2, WAVE, T>(s, tid);
+        else if (P == 4 * WAVE) block_sort_regs<4, WAVE, T>(s, tid);
+        else block_sort_regs<8, WAVE, T>(s, tid);
+        wave_sync_lds();
+    } else {
+        __syncthreads();
+        block_sort<NT, T>(s, P);
+    }
+    return hg_emit<NT>(c, s, P, r, a, sh, rep);
+}
+
 // Groups of at most WR_P entries: one wave each, sorted in registers.
 __global__ void __launch_bounds__(BLOCK) fill_huge_small_k(Ctx c, int l) {
     __shared__ uint64_t lds[(BLOCK / WAVE) * lds_padded(WR_P)];
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_CONTRACT, g)) return;
-    if (c.lv[l + 1].n > HUGE_NC_MAX) return;
+    const int64_t nc = c.lv[l + 1].n;
+    if (nc > HUGE_NC_MAX) return;
+    const int shb = hg_shift(nc);
     const int wv = threadIdx.x / WAVE, lane = lane_id();
     uint64_t *sl = lds + wv * lds_padded(WR_P);
+    uint32_t *sl32 = (uint32_t *)sl;
     const int32_t *list = class_list(c.cs, g.n, 2);
     const int64_t count = min<int64_t>(c.cs.hg_cnt[0], c.cs.hg_cap);
     for (int64_t q = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv; q < count;
@@ -2740,21 +2805,15 @@ __global__ void __launch_bounds__(BLOCK) fill_huge_small_k(Ctx c, int l) {
         const int32_t a = d.y, m = d.z;
         int P = WAVE;
         while (P < m) P <<= 1;
-        for (int t = lane; t < P; t += WAVE) {
-            uint64_t v = ~0ull;
-            if (t < m) {
-                const int64_t at = staged_at(r, a + t);
-                v = ((uint64_t)(uint32_t)c.cs.tmp_adj[at] << 32) | c.cs.tmp_ew[at];
-            }
-            sl[t] = v;
-        }
-        wave_sync_lds();
-        if (P == WAVE) block_sort_regs<1, WAVE>(sl, lane);
-        else if (P == 2 * WAVE) block_sort_regs<2, WAVE>(sl, lane);
-        else if (P == 4 * WAVE) block_sort_regs<4, WAVE>(sl, lane);
-        else block_sort_regs<8, WAVE>(sl, lane);
-        wave_sync_lds();
-        const int32_t merged = hg_emit<WAVE>(c, sl, P, r, a, nullptr);
+        uint32_t base;
+        int64_t span;
+        hg_key_range(c, r, a, m, shb, base, span);
+        const int lp = __builtin_ctz(P);
+        const int32_t merged =
+            narrow_fits(span, lp)
+                ? hg_group<WAVE>(c, r, a, m, P, sl32, NarrowRep{sl32 + lds_padded(WR_P), lp, base},
+                                 nullptr)
+                : hg_group<WAVE>(c, r, a, m, P, sl, WideRep{}, nullptr);
         if (lane == 0) c.cs.hg_slot[d.w].y = merged;
         wave_sync_lds();   // the slice is reloaded for the wave's next group
     }
@@ -2768,7 +2827,10 @@ __global__ void __launch_bounds__(HUGE_THREADS) fill_huge_big_k(Ctx c, int l) {
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_CONTRACT, g)) return;
-    if (c.lv[l + 1].n > HUGE_NC_MAX) return;
+    const int64_t nc = c.lv[l + 1].n;
+    if (nc > HUGE_NC_MAX) return;
+    const int shb = hg_shift(nc);
+    uint32_t *s32 = (uint32_t *)s;
     const int32_t *list = class_list(c.cs, g.n, 2);
     const int64_t count = min<int64_t>(c.cs.hg_cnt[1], c.cs.hg_cap);
     for (int64_t q = blockIdx.x; q < count; q += gridDim.x) {   // block-uniform
@@ -2781,24 +2843,14 @@ __global__ void __launch_bounds__(HUGE_THREADS) fill_huge_big_k(Ctx c, int l) {
             if (threadIdx.x == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_STATE);
             continue;
         }
-        for (int t0 = threadIdx.x; t0 < P; t0 += NT * 4) {
-            uint64_t val[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int t = t0 + u * NT;
-                val[u] = ~0ull;
-                if (t < m) {
-                    const int64_t at = staged_at(r, a + t);
-                    val[u] = ((uint64_t)(uint32_t)c.cs.tmp_adj[at] << 32) | c.cs.tmp_ew[at];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (t0 + u * NT < P) s[t0 + u * NT] = val[u];
-        }
-        __syncthreads();
-        block_sort<NT>(s, P);
-        const int32_t merged = hg_emit<NT>(c, s, P, r, a, sh);
+        uint32_t base;
+        int64_t span;
+        hg_key_range(c, r, a, m, shb, base, span);
+        const int lp = __builtin_ctz(P);
+        const int32_t merged =
+            narrow_fits(span, lp)
+                ? hg_group<NT>(c, r, a, m, P, s32, NarrowRep{s32 + lds_padded(BIG_P), lp, base}, sh)
+                : hg_group<NT>(c, r, a, m, P, s, WideRep{}, sh);
         if (threadIdx.x == 0) c.cs.hg_slot[d.w].y = merged;
         __syncthreads();   // s is reloaded for the block's next group
     }
