@@ -2819,11 +2819,11 @@ __global__ void __launch_bounds__(BLOCK) fill_huge_small_k(Ctx c, int l) {
     }
 }
 
-// The larger groups: one block each.
-__global__ void __launch_bounds__(HUGE_THREADS) fill_huge_big_k(Ctx c, int l) {
-    constexpr int NT = HUGE_THREADS;
-    __shared__ uint64_t s[lds_padded(BIG_P)];
-    __shared__ int64_t sh[NT / WAVE + 1];
+// The larger groups: one block of NT threads each, those of MIN+1..PMAX
+// entries (a block of BLOCK threads sorts up to MID_P in registers with few
+// barriers; the 1024-thread blocks take only the groups beyond that).
+template <int NT, int PMAX, int MIN>
+__device__ __forceinline__ void huge_group_body(const Ctx &c, int l, uint64_t *s, int64_t *sh) {
     DevGraph g;
     LevelDesc *L = c.lv + l;
     if (!load_level(L, PH_CONTRACT, g)) return;
@@ -2835,25 +2835,38 @@ __global__ void __launch_bounds__(HUGE_THREADS) fill_huge_big_k(Ctx c, int l) {
     const int64_t count = min<int64_t>(c.cs.hg_cnt[1], c.cs.hg_cap);
     for (int64_t q = blockIdx.x; q < count; q += gridDim.x) {   // block-uniform
         const int4 d = c.cs.hg_big[q];
-        const RowSrc r = row_src(g, c, list[d.x]);
         const int32_t a = d.y, m = d.z;
+        if (m <= MIN) continue;   // the other group kernel's
         int P = 2;
         while (P < m) P <<= 1;
-        if (P > BIG_P) {   // valid groups never
-            if (threadIdx.x == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_STATE);
+        if (P > PMAX) {
+            // the mid kernel leaves these to the big one; valid groups never
+            // exceed the big kernel's sort
+            if (PMAX == BIG_P && threadIdx.x == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_STATE);
             continue;
         }
+        const RowSrc r = row_src(g, c, list[d.x]);
         uint32_t base;
         int64_t span;
         hg_key_range(c, r, a, m, shb, base, span);
         const int lp = __builtin_ctz(P);
         const int32_t merged =
             narrow_fits(span, lp)
-                ? hg_group<NT>(c, r, a, m, P, s32, NarrowRep{s32 + lds_padded(BIG_P), lp, base}, sh)
+                ? hg_group<NT>(c, r, a, m, P, s32, NarrowRep{s32 + lds_padded(PMAX), lp, base}, sh)
                 : hg_group<NT>(c, r, a, m, P, s, WideRep{}, sh);
         if (threadIdx.x == 0) c.cs.hg_slot[d.w].y = merged;
         __syncthreads();   // s is reloaded for the block's next group
     }
+}
+__global__ void __launch_bounds__(BLOCK) fill_huge_mid_k(Ctx c, int l) {
+    __shared__ uint64_t s[lds_padded(MID_P)];
+    __shared__ int64_t sh[BLOCK / WAVE + 1];
+    huge_group_body<BLOCK, MID_P, WR_P>(c, l, s, sh);
+}
+__global__ void __launch_bounds__(HUGE_THREADS) fill_huge_big_k(Ctx c, int l) {
+    __shared__ uint64_t s[lds_padded(BIG_P)];
+    __shared__ int64_t sh[HUGE_THREADS / WAVE + 1];
+    huge_group_body<HUGE_THREADS, BIG_P, MID_P>(c, l, s, sh);
 }
 
 // Each large row's merged groups packed from position 0 on.
@@ -3857,6 +3870,11 @@ void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, h
         {
             KAPPA_PROF("fill_huge_small", s);
             hipLaunchKernelGGL(fill_huge_small_k, dim3(grid_for(n_hint, 256, 2048)), dim3(BLOCK), 0,
+                               s, c, l);
+        }
+        {
+            KAPPA_PROF("fill_huge_mid", s);
+            hipLaunchKernelGGL(fill_huge_mid_k, dim3(grid_for(n_hint, 2048, 1024)), dim3(BLOCK), 0,
                                s, c, l);
         }
         {
