@@ -1862,7 +1862,10 @@ __device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bi
         if (live) {
             r = row_src(g, c, x);
             cls = row_class(row_bound(r), c.t.row_small_max);
-            if ((!BIG || !c.big_rows) && cls == 4) cls = 2;
+            // rows of 4095..16382 entries take the key buckets where those
+            // apply (groups of a few hundred entries, sorted a wave each),
+            // else a 1024-thread block each (fill_big_k)
+            if (cls == 4 && (!BIG || !c.big_rows || (c.huge && huge_row(count, r.tot)))) cls = 2;
             if (cls == 2 && !c.cs.hub_acc && !(BIG && c.huge && huge_row(count, r.tot)))
                 need_hubs = true;
         }
