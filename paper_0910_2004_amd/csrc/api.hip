@@ -715,7 +715,9 @@ void carve_scratch(Carve &cv, const DevGraph &g, int rating, bool hubs, Ctx &c,
     const bool dense = hubs && (g.n > HUGE_NC_MAX || tail);
     cs.hub_acc = dense ? cv.get<uint32_t>((int64_t)cs.hub_slots * g.n) : nullptr;
     cs.hub_bits = dense ? cv.get<uint32_t>((int64_t)cs.hub_slots * cs.hub_words) : nullptr;
-    cs.hg_rows = g.nnz / (ROW_BIG_MAX + 1) + 64;             // large rows at most
+    // rows whose bound exceeds ROW_MID_MAX at most (the bounds sum to at
+    // most nnz): every row the key buckets may take
+    cs.hg_rows = g.nnz / (ROW_MID_MAX + 1) + 64;
     cs.hg_cap = g.nnz / HG_WIN_MIN + 2 * cs.hg_rows;         // groups at most
     cs.hg_adj = c.huge ? cv.get<int32_t>(g.nnz) : nullptr;
     cs.hg_ew = c.huge ? cv.get<uint32_t>(g.nnz) : nullptr;

@@ -300,3 +300,16 @@ def test_trusted_input_skips_entry_checks_only():
     st = K.lib().kappa_coarsen(ctypes.byref(dg.c()), ctypes.byref(p), ctypes.byref(h),
                                K._lib._stream())
     assert st == K.E_ARG
+
+
+def test_many_rows_of_thousands_of_entries():
+    """Hundreds of coarse rows of 4095..16382 entries (hubs of about 4500
+    leaves each): more than a sixteen-thousandth of the entries, so the key
+    buckets' row capacity must count such rows too."""
+    rng = np.random.default_rng(31)
+    hubs, leaves, deg = 300, 60000, 4500
+    a = np.repeat(np.arange(hubs), deg)
+    b = np.concatenate([rng.choice(leaves, size=deg, replace=False) for _ in range(hubs)]) + hubs
+    g = csr_from_edges(hubs + leaves, a, b, rng.integers(1, 60, size=a.size).astype(np.uint32))
+    assert int(np.diff(g.xadj)[:hubs].min()) > 4094
+    check_hierarchy(g, 0, 7, stop_n=2000, k=16)
