@@ -2553,7 +2553,8 @@ __global__ void __launch_bounds__(LARGE_THREADS) fill_large_k(Ctx c, int l) {
 // Equal keys share a bucket, so runs never cross groups; the merge output is
 // in a separate array, so the copy needs no ordering between its threads.
 constexpr int HUGE_THREADS = 1024;
-constexpr int HG_U = 8;   // entries per thread in flight
+constexpr int HG_U = 8;      // entries per thread in flight
+constexpr int HG_KEEP = 16;  // entries per thread kept between the two passes
 __global__ void __launch_bounds__(HUGE_THREADS) fill_huge_prep_k(Ctx c, int l) {
     constexpr int NT = HUGE_THREADS;
     static_assert(HG_BINS % NT == 0, "buckets per thread");
@@ -2577,18 +2578,34 @@ __global__ void __launch_bounds__(HUGE_THREADS) fill_huge_prep_k(Ctx c, int l) {
         if (!huge_row(nc, r.tot)) continue;   // block-uniform
         for (int b = threadIdx.x; b < HG_BINS; b += NT) hist[b] = 0;
         __syncthreads();
-        // histogram
-        for (int64_t t0 = threadIdx.x; t0 < r.tot; t0 += (int64_t)NT * HG_U) {
-            uint32_t k[HG_U], w[HG_U];
+        // histogram; a row of at most NT * HG_KEEP entries keeps its renamed
+        // entries in registers for the scatter below (one gather, not two)
+        const bool keep = r.tot <= (int64_t)NT * HG_KEEP;   // block-uniform
+        uint32_t kk[HG_KEEP], kw[HG_KEEP];
+        if (keep) {
 #pragma unroll
-            for (int u = 0; u < HG_U; ++u) {
-                const int64_t t = t0 + (int64_t)u * NT;
-                k[u] = INVALID_KEY;
-                if (t < r.tot) row_entry(g, cmap, r, t, k[u], w[u]);
+            for (int u = 0; u < HG_KEEP; ++u) {
+                const int64_t t = threadIdx.x + (int64_t)u * NT;
+                kk[u] = INVALID_KEY;
+                kw[u] = 0;
+                if (t < r.tot) row_entry(g, cmap, r, t, kk[u], kw[u]);
             }
 #pragma unroll
-            for (int u = 0; u < HG_U; ++u)
-                if (k[u] != INVALID_KEY) atomicAdd(&hist[k[u] >> shb], 1);
+            for (int u = 0; u < HG_KEEP; ++u)
+                if (kk[u] != INVALID_KEY) atomicAdd(&hist[kk[u] >> shb], 1);
+        } else {
+            for (int64_t t0 = threadIdx.x; t0 < r.tot; t0 += (int64_t)NT * HG_U) {
+                uint32_t k[HG_U], w[HG_U];
+#pragma unroll
+                for (int u = 0; u < HG_U; ++u) {
+                    const int64_t t = t0 + (int64_t)u * NT;
+                    k[u] = INVALID_KEY;
+                    if (t < r.tot) row_entry(g, cmap, r, t, k[u], w[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < HG_U; ++u)
+                    if (k[u] != INVALID_KEY) atomicAdd(&hist[k[u] >> shb], 1);
+            }
         }
         __syncthreads();
         // exclusive scan (HG_BINS / NT consecutive buckets per thread)
@@ -2634,7 +2651,17 @@ __global__ void __launch_bounds__(HUGE_THREADS) fill_huge_prep_k(Ctx c, int l) {
         __syncthreads();
         if (s_base < 0) continue;   // block-uniform
         // scatter into bucket order (hist as cursors)
-        for (int64_t t0 = threadIdx.x; t0 < r.tot; t0 += (int64_t)NT * HG_U) {
+        if (keep) {
+#pragma unroll
+            for (int u = 0; u < HG_KEEP; ++u) {
+                if (kk[u] == INVALID_KEY) continue;
+                const int32_t pos = atomicAdd(&hist[kk[u] >> shb], 1);
+                const int64_t at = staged_at(r, pos);
+                c.cs.tmp_adj[at] = (int32_t)kk[u];
+                c.cs.tmp_ew[at] = kw[u];
+            }
+        }
+        for (int64_t t0 = keep ? r.tot : threadIdx.x; t0 < r.tot; t0 += (int64_t)NT * HG_U) {
             uint32_t k[HG_U], w[HG_U];
 #pragma unroll
             for (int u = 0; u < HG_U; ++u) {
