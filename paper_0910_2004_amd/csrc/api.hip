@@ -651,9 +651,21 @@ kappa_status validate_impl(const DevGraph &g, hipStream_t s, int32_t *maxdeg_out
     ZeroRanges z;
     z.add(dv, sizeof(RB) / 4);
     launch_zero(z, s);
-    launch_validate(g, tr, &dv->flags, dv->sums, dv->mdeg, s, trusted, sort_ws);
     RB *rb = (RB *)pinned(sizeof(RB));
     if (!rb) return KAPPA_E_NOMEM;
+    if (sort_ws) {
+        // large graphs: the maximum degree decides between the sorted symmetry
+        // test and the binary searches (one read-back more)
+        launch_validate(g, tr, &dv->flags, dv->sums, dv->mdeg, s, true);
+        HIPCHK(hipMemcpyAsync(rb->mdeg, dv->mdeg, sizeof(rb->mdeg), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        int32_t md0 = 0;
+        for (int i = 0; i < NSHARD; ++i) md0 = std::max(md0, rb->mdeg[i]);
+        launch_validate(g, tr, &dv->flags, dv->sums, dv->mdeg, s, false,
+                        md0 > VAL_SORT_MIN_DEG ? sort_ws : nullptr, true);
+    } else {
+        launch_validate(g, tr, &dv->flags, dv->sums, dv->mdeg, s, trusted, nullptr);
+    }
     HIPCHK(hipMemcpyAsync(rb, dv, sizeof(RB), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     uint64_t tot[4] = {0, 0, 0, 0};

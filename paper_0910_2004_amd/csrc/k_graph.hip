@@ -354,9 +354,10 @@ size_t val_sort_ws_bytes(int64_t n, int64_t nnz) {
 }
 
 void launch_validate(const DevGraph &g, int32_t *tile_row, uint32_t *flags, uint64_t *sums,
-                     int32_t *maxdeg, hipStream_t s, bool offsets_only, char *sort_ws) {
+                     int32_t *maxdeg, hipStream_t s, bool offsets_only, char *sort_ws,
+                     bool entries_only) {
     int64_t nt = etiles(g.nnz);
-    {
+    if (!entries_only) {
         KAPPA_PROF("validate_offsets", s);
         hipLaunchKernelGGL(validate_offsets_k, dim3(grid_for((int64_t)g.n + 1, BLOCK * 4, 1024)),
                            dim3(BLOCK), 0, s, g, flags, sums, maxdeg);

@@ -810,23 +810,20 @@ __device__ __forceinline__ void mate_phase(const Ctx &c, const DevGraph &g, Leve
         block_append_mk(bin, vv, bb, dd, ol, ocnt, sh, sbase);
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_STATE);
-    block_sum3(point, degs, pairs, sh);
+    // with the rows this round's pick scanned, where it scans every pending
+    // row (with chunked rows the preparation counts the rows that rescan)
+    int64_t sums[5] = {point, degs, pairs, scanned, sdeg};
+    block_sum_n<5>(sums, sh);
     const int ri_ = r - 1 < STAT_ROUNDS ? r - 1 : STAT_ROUNDS - 1, sd = shard_of_block();
-    if (threadIdx.x == 0 && point > 0) {
-        atomicAdd((unsigned long long *)&st->sstat[ri_][0][sd], (unsigned long long)point);
-        atomicAdd((unsigned long long *)&st->sstat[ri_][1][sd], (unsigned long long)degs);
-        if (pairs) atomicAdd((unsigned long long *)&st->sstat[ri_][2][sd], (unsigned long long)pairs);
+    if (threadIdx.x == 0 && sums[0] > 0) {
+        atomicAdd((unsigned long long *)&st->sstat[ri_][0][sd], (unsigned long long)sums[0]);
+        atomicAdd((unsigned long long *)&st->sstat[ri_][1][sd], (unsigned long long)sums[1]);
+        if (sums[2]) atomicAdd((unsigned long long *)&st->sstat[ri_][2][sd], (unsigned long long)sums[2]);
         atomicMax(&st->sround[sd], r);
     }
-    // the rows this round's pick scanned, where it scans every pending row
-    // (with chunked rows the preparation counts the rows that rescan)
-    if (!FIRST && !c.ms.hub.rec) {
-        int64_t none = 0;
-        block_sum3(scanned, sdeg, none, sh);
-        if (threadIdx.x == 0 && scanned > 0) {
-            atomicAdd((unsigned long long *)&st->sstat[ri_][3][sd], (unsigned long long)scanned);
-            atomicAdd((unsigned long long *)&st->sstat[ri_][4][sd], (unsigned long long)sdeg);
-        }
+    if (!FIRST && !c.ms.hub.rec && threadIdx.x == 0 && sums[3] > 0) {
+        atomicAdd((unsigned long long *)&st->sstat[ri_][3][sd], (unsigned long long)sums[3]);
+        atomicAdd((unsigned long long *)&st->sstat[ri_][4][sd], (unsigned long long)sums[4]);
     }
 }
 
@@ -911,7 +908,7 @@ __global__ void __launch_bounds__(BLOCK) pick_k(Ctx c, int l, int r, PickGrid pg
 // pending, or few enough for the finisher).  A thread's MK entries are loaded
 // together.
 __global__ void __launch_bounds__(BLOCK) prep_k(Ctx c, int l, int r) {
-    __shared__ int64_t sh[3 * (BLOCK / WAVE) + 1];
+    __shared__ int64_t sh[5 * (BLOCK / WAVE) + 1];
     __shared__ int32_t sbase[2];
     DevGraph g;
     LevelDesc *L = c.lv + l;
@@ -1037,7 +1034,7 @@ __global__ void __launch_bounds__(BLOCK) hub_reduce_k(Ctx c, int l, int r) {
 
 template <int R, bool FIRST>
 __global__ void __launch_bounds__(BLOCK) mate_k(Ctx c, int l, int r) {
-    __shared__ int64_t sh[3 * (BLOCK / WAVE) + 1];
+    __shared__ int64_t sh[5 * (BLOCK / WAVE) + 1];
     __shared__ int32_t sbase[3];
     DevGraph g;
     LevelDesc *L = c.lv + l;
@@ -1152,7 +1149,7 @@ __device__ void close_matching(const Ctx &c, LevelDesc *L, bool capped, int grid
 template <int R, int F = 0>
 __global__ void __launch_bounds__(FINISH_THREADS) finish_k(Ctx c, int l, int r_last) {
     __shared__ Cand shc[FINISH_THREADS / WAVE];
-    __shared__ int64_t sh[3 * (FINISH_THREADS / WAVE) + 1];
+    __shared__ int64_t sh[5 * (FINISH_THREADS / WAVE) + 1];
     __shared__ int32_t s_cnt[2][4];
     __shared__ int32_t sbase[3];
     __shared__ int64_t s_acc[2];
@@ -1518,7 +1515,7 @@ block_match_k(Ctx c, int l) {
 // block partner took a gap edge stays unmatched.  Gap partners are read from
 // the node records (their mate field), block partners from loc.
 __global__ void __launch_bounds__(BLOCK) merge_k(Ctx c, int l) {
-    __shared__ int64_t sh[3 * (BLOCK / WAVE) + 1];
+    __shared__ int64_t sh[5 * (BLOCK / WAVE) + 1];
     LevelDesc *L = c.lv + l;
     if (L->phase != PH_MERGE) return;
     const int32_t n = L->n;
@@ -3161,7 +3158,7 @@ struct TailMatchLds {
 template <int R>
 __device__ __noinline__ void tail_round1(const Ctx &c, int l, TailMatchLds &t) {
     __shared__ Cand shc[TAIL_THREADS / WAVE];
-    __shared__ int64_t sh[3 * (TAIL_THREADS / WAVE) + 1];
+    __shared__ int64_t sh[5 * (TAIL_THREADS / WAVE) + 1];
     __shared__ int32_t sbase[3];
     LevelDesc *L = c.lv + l;
     DevGraph g;
@@ -3188,7 +3185,7 @@ __device__ __noinline__ void tail_round1(const Ctx &c, int l, TailMatchLds &t) {
 template <int R>
 __device__ __noinline__ void tail_rounds(const Ctx &c, int l, TailMatchLds &t) {
     __shared__ Cand shc[TAIL_THREADS / WAVE];
-    __shared__ int64_t sh[3 * (TAIL_THREADS / WAVE) + 1];
+    __shared__ int64_t sh[5 * (TAIL_THREADS / WAVE) + 1];
     __shared__ int32_t sbase[3];
     __shared__ int64_t s_acc[2];
     LevelDesc *L = c.lv + l;
@@ -3651,7 +3648,7 @@ template <int R>
 __global__ void __launch_bounds__(BLOCK) rounds_coop_k(Ctx c, int l, int r_first, int r_cap,
                                                        PickGrid pg) {
     __shared__ Cand shc[BLOCK / WAVE];
-    __shared__ int64_t sh[3 * (BLOCK / WAVE) + 1];
+    __shared__ int64_t sh[5 * (BLOCK / WAVE) + 1];
     __shared__ int32_t sbase[3];
     DevGraph g;
     LevelDesc *L = c.lv + l;

@@ -271,6 +271,28 @@ __device__ __forceinline__ bool arrive_last(unsigned *cnt) {
     return true;
 }
 
+// Block sums of K per-thread values, valid in thread 0 (two barriers).
+// sh: K * (blockDim.x / WAVE) entries.
+template <int K>
+__device__ __forceinline__ void block_sum_n(int64_t (&v)[K], int64_t *sh) {
+#pragma unroll
+    for (int q = 0; q < K; ++q) v[q] = wave_sum(v[q]);
+    const int w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    __syncthreads();   // sh may still be read by a previous use
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) sh[q * nw + w] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            v[q] = 0;
+            for (int i = 0; i < nw; ++i) v[q] += sh[q * nw + i];
+        }
+    }
+}
+
 // Block sums of three per-thread values, valid in thread 0 (two barriers).
 // sh: 3 * (blockDim.x / WAVE) entries.
 __device__ __forceinline__ void block_sum3(int64_t &a, int64_t &b, int64_t &c, int64_t *sh) {
@@ -793,14 +815,19 @@ void launch_tile_rows(const DevGraph &g, int32_t *tile_row, hipStream_t s);
 // maxdeg[NSHARD] (zeroed): max row length per shard.  Computes its own tile
 // rows into tile_row.
 // offsets_only: the offsets pass alone (row offsets, c(V), maximum degree).
-// Graphs of at least VAL_SORT_MIN_NNZ entries check symmetry by sorting (a
-// workspace of val_sort_ws_bytes bytes, sort_ws); smaller ones, or a null
-// sort_ws, by binary searches.
+// With a sort_ws of val_sort_ws_bytes bytes (graphs of at least
+// VAL_SORT_MIN_NNZ entries) symmetry is checked by sorting, else by binary
+// searches.  The caller passes sort_ws only for graphs with rows above
+// VAL_SORT_MIN_DEG entries (the offsets pass's maximum degree): there each
+// search probe of a long row fetches a line of its own, while the searches
+// of short, cache-resident rows cost less than the sort.  entries_only: the
+// offsets pass has run already.
 constexpr int64_t VAL_SORT_MIN_NNZ = (int64_t)1 << 22;
+constexpr int32_t VAL_SORT_MIN_DEG = 1024;
 size_t val_sort_ws_bytes(int64_t n, int64_t nnz);
 void launch_validate(const DevGraph &g, int32_t *tile_row, uint32_t *flags, uint64_t *sums,
                      int32_t *maxdeg, hipStream_t s, bool offsets_only = false,
-                     char *sort_ws = nullptr);
+                     char *sort_ws = nullptr, bool entries_only = false);
 void launch_out(const DevGraph &g, const int32_t *tile_row, uint32_t *out, hipStream_t s);
 void launch_rate(const DevGraph &g, const int32_t *tile_row, int rating, const uint32_t *out,
                  uint64_t *num, uint64_t *den, hipStream_t s);

@@ -1,7 +1,8 @@
-"""Validation of large graphs (at least 2^22 entries): the symmetry test by
-sorting the entries above the diagonal and matching them one for one with
-those below it.  Valid graphs pass; every way of breaking symmetry, order or
-weights is rejected, as by the binary-search test of smaller graphs."""
+"""Validation of large graphs (at least 2^22 entries) with rows above 1024
+entries: the symmetry test by sorting the entries above the diagonal and
+matching them one for one with those below it (large graphs with short rows
+keep the binary searches).  Valid graphs pass; every way of breaking
+symmetry, order or weights is rejected, as by the binary searches."""
 import numpy as np
 import pytest
 
@@ -41,8 +42,8 @@ def big():
 
 @pytest.fixture(scope="module")
 def big_weighted():
-    g = rmat(18, 16, seed=3, wseed=4)   # weights in [1, 100]
-    assert g.xadj[-1] >= (1 << 22)
+    g = rmat(18, 16, seed=3, wseed=4)   # weights in [1, 100]; rows above 1024 entries
+    assert g.xadj[-1] >= (1 << 22) and int(np.diff(g.xadj).max()) > 1024
     return g
 
 
@@ -52,18 +53,18 @@ def test_valid_graphs_pass(big, big_weighted):
 
 
 @pytest.mark.parametrize("upper", [True, False])
-def test_one_weight_changed(big, upper):
+def test_one_weight_changed(big_weighted, upper):
     rng = np.random.default_rng(5 + upper)
-    g = _copy(big)
+    g = _copy(big_weighted)
     _, j = _entry(g, rng, upper)
     g.ew[j] = g.ew[j] + 1
     assert _status(g) == K.E_GRAPH
 
 
 @pytest.mark.parametrize("upper", [True, False])
-def test_one_neighbour_changed(big, upper):
+def test_one_neighbour_changed(big_weighted, upper):
     rng = np.random.default_rng(7 + upper)
-    g = _copy(big)
+    g = _copy(big_weighted)
     for _ in range(10000):
         v, j = _entry(g, rng, upper)
         a, b = int(g.xadj[v]), int(g.xadj[v + 1])
@@ -78,15 +79,15 @@ def test_one_neighbour_changed(big, upper):
     assert _status(g) == K.E_GRAPH
 
 
-def test_unsorted_row_and_self_loop(big):
+def test_unsorted_row_and_self_loop(big_weighted):
     rng = np.random.default_rng(9)
-    g = _copy(big)
+    g = _copy(big_weighted)
     v, j = _entry(g, rng, True)
     a = int(g.xadj[v])
     g.adj[a], g.adj[a + 1] = g.adj[a + 1], g.adj[a]
     g.ew[a], g.ew[a + 1] = g.ew[a + 1], g.ew[a]
     assert _status(g) == K.E_GRAPH
-    g = _copy(big)
+    g = _copy(big_weighted)
     v, j = _entry(g, rng, True)
     g.adj[j] = v
     assert _status(g) == K.E_GRAPH
@@ -105,4 +106,14 @@ def test_two_rows_swap_weights(big_weighted):
     else:
         raise AssertionError("no two different weights")
     g.ew[j1], g.ew[j2] = g.ew[j2], g.ew[j1]
+    assert _status(g) == K.E_GRAPH
+
+
+def test_large_graph_with_short_rows_keeps_the_searches(big):
+    """rgg 2^20 (rows of about 8 entries): the binary searches, rejecting a
+    changed weight as well."""
+    rng = np.random.default_rng(13)
+    g = _copy(big)
+    _, j = _entry(g, rng, True)
+    g.ew[j] = g.ew[j] + 1
     assert _status(g) == K.E_GRAPH
