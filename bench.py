@@ -527,13 +527,13 @@ def single_graph(args, rmat_mode, primary):
     K.profile_enable(True)
     torch.cuda.synchronize()
     for _ in range(args.steps):
-        step(serial=True)
+        pstats = step(serial=True)   # level statistics incl. rescans (recorded while profiling)
     torch.cuda.synchronize()
     K.profile_enable(False)
     prof = K.profile_read()
     K.profile_reset()
 
-    lv = {r: stats[r][0] for r in ratings}
+    lv = {r: pstats[r][0] for r in ratings}
     mb = model_bytes(lv, classes, g.n, g.nnz)
     total_ms = sum(ms for _, ms in prof.values()) / args.steps
     kern = sorted(prof.items(), key=lambda kv: -kv[1][1])

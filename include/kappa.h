@@ -253,8 +253,10 @@ int32_t kappa_hierarchy_round_stats(const kappa_hierarchy *h, int32_t l, int64_t
    chunks (a power-law graph), a pending node whose choice is still free
    keeps it and is not counted, and only the rounds run as grid launches are
    counted.  Either way the nodes counted pointed in the round before.  Index
-   0 (the first round, which scans every row) holds zeros.  Copies
-   min(rounds, cap) entries and returns the round count, as
+   0 (the first round, which scans every row) holds zeros.  Recorded only
+   while the per-launch profiler is on (kappa_profile_enable) when the
+   hierarchy is built, since gathering them costs time; zeros otherwise.
+   Copies min(rounds, cap) entries and returns the round count, as
    kappa_hierarchy_round_stats. */
 int32_t kappa_hierarchy_rescan_stats(const kappa_hierarchy *h, int32_t l, int64_t *rows,
                                      int64_t *degsum, int32_t cap);

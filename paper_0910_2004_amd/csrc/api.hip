@@ -884,6 +884,7 @@ kappa_status coarsen_attempt(const DevGraph &d0, int32_t maxdeg0, const kappa_co
     // graphs without long rows at level 0 rarely grow rows of thousands of
     // entries: such rows then take the hub accumulators (no big-row launch)
     c.big_rows = maxdeg0 > BIN_MID_MAX ? 1 : 0;
+    c.rescan_stats = g_prof.on ? 1 : 0;
     const int maxl = p->max_levels;
     const int32_t count = bi ? bi->count : 0;
     uint32_t *bflag = nullptr;

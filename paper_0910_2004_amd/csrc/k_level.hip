@@ -708,7 +708,7 @@ __device__ __forceinline__ void pick_bin2_chunks(const Ctx &c, const DevGraph &g
             }
         }
     }
-    if (!FIRST && threadIdx.x == 0 && scanned > 0) {
+    if (!FIRST && c.rescan_stats && threadIdx.x == 0 && scanned > 0) {
         const int ri_ = r - 1 < STAT_ROUNDS ? r - 1 : STAT_ROUNDS - 1;
         atomicAdd((unsigned long long *)&c.ms.state->sstat[ri_][4][shard_of_block()],
                   (unsigned long long)scanned);
@@ -811,9 +811,15 @@ __device__ __forceinline__ void mate_phase(const Ctx &c, const DevGraph &g, Leve
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_STATE);
     // with the rows this round's pick scanned, where it scans every pending
-    // row (with chunked rows the preparation counts the rows that rescan)
+    // row (with chunked rows the preparation counts the rows that rescan),
+    // while the profiler asks for them
     int64_t sums[5] = {point, degs, pairs, scanned, sdeg};
-    block_sum_n<5>(sums, sh);
+    if (c.rescan_stats) {
+        block_sum_n<5>(sums, sh);
+    } else {
+        block_sum3(sums[0], sums[1], sums[2], sh);
+        sums[3] = 0;
+    }
     const int ri_ = r - 1 < STAT_ROUNDS ? r - 1 : STAT_ROUNDS - 1, sd = shard_of_block();
     if (threadIdx.x == 0 && sums[0] > 0) {
         atomicAdd((unsigned long long *)&st->sstat[ri_][0][sd], (unsigned long long)sums[0]);
@@ -987,6 +993,7 @@ __global__ void __launch_bounds__(BLOCK) prep_k(Ctx c, int l, int r) {
         }
         __syncthreads();   // sbase is reused by the next pass
     }
+    if (!c.rescan_stats) return;
     int64_t none = 0;
     block_sum3(rrows, rdeg, none, sh);
     if (threadIdx.x == 0 && rrows > 0) {
@@ -1934,8 +1941,11 @@ __device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bi
     }
     if (__ballot(need_hubs) && lane_id() == 0) atomicOr(&c.ctrl->flags, (uint32_t)CF_HUBS);
 }
+// BUF: graphs with long rows (many rows for the class lists) append through
+// the per-wave buffers; others (few list rows) directly.
+template <bool BUF>
 __global__ void __launch_bounds__(BLOCK) fill_small_k(Ctx c, int l) {
-    fill_small_body<BLOCK, true, true>(c, l, blockIdx.x, gridDim.x);
+    fill_small_body<BLOCK, true, BUF>(c, l, blockIdx.x, gridDim.x);
 }
 
 // Sorted arrays in LDS are left in a padded layout: position p lives in
@@ -2996,7 +3006,17 @@ __device__ __forceinline__ void compact_small_body(const Ctx &c, int l, unsigned
             mine = row_bound(r) <= c.t.row_small_max;   // else compact_big copies it
         }
         uint32_t sum = 0;
-        if (mine) {
+        if (mine && len <= ROW_SMALL_G) {   // one entry per lane
+            const int64_t dst = N->xadj[x];
+            if (sub < len) {
+                const int64_t at = staged_at(r, sub);
+                const int32_t k = c.cs.tmp_adj[at];
+                const uint32_t w = c.cs.tmp_ew[at];
+                N->adj[dst + sub] = k;
+                N->ew[dst + sub] = w;
+                sum = w;
+            }
+        } else if (mine) {
             // a lane's entries loaded before any is stored (the stores could
             // alias the loads as far as the compiler knows)
             constexpr int U = (SM_CAP + ROW_SMALL_G - 1) / ROW_SMALL_G;
@@ -3875,8 +3895,12 @@ void launch_level_contract(const Ctx &c, int l, int32_t n_hint, int32_t n_cap, h
                 c.cs.totals + 0, s);
     {
         KAPPA_PROF("fill_small", s);
-        hipLaunchKernelGGL(fill_small_k, dim3(grid_for(n_hint, SM_ROWS * 2, 4096)), dim3(BLOCK), 0,
-                           s, c, l);
+        if (c.big_rows)
+            hipLaunchKernelGGL(fill_small_k<true>, dim3(grid_for(n_hint, SM_ROWS * 2, 4096)),
+                               dim3(BLOCK), 0, s, c, l);
+        else
+            hipLaunchKernelGGL(fill_small_k<false>, dim3(grid_for(n_hint, SM_ROWS * 2, 4096)),
+                               dim3(BLOCK), 0, s, c, l);
     }
     {
         KAPPA_PROF("fill_mid", s);

@@ -753,6 +753,7 @@ struct Ctx {
     int32_t big_rows = 1;      // 1: rows of 4095..16382 entries get the big-row sort launch;
                                // 0: they join the large rows
     int32_t huge = 0;          // 1: large rows get the key-bucket merge launches
+    int32_t rescan_stats = 0;  // 1: record the rescan statistics (while the profiler is on)
 };
 
 // K bump allocations in the arena with one read and one write of the cursor

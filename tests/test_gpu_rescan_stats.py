@@ -15,6 +15,15 @@ from workloads import rgg, rmat
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(autouse=True)
+def profiling():
+    """The rescan statistics are recorded while the profiler is on."""
+    K.profile_enable(True)
+    yield
+    K.profile_enable(False)
+    K.profile_reset()
+
+
 def test_every_pending_row_without_chunks():
     g = rgg(1 << 15, seed=5)
     assert int(np.diff(g.xadj).max()) <= 1024   # no chunked rows
@@ -44,3 +53,12 @@ def test_bounded_by_round_stats_with_chunks():
             assert rd[i] >= rr[i]   # a pointing node has a neighbour
         total += int(rr.sum())
     assert total > 0
+
+
+def test_zero_without_the_profiler():
+    K.profile_enable(False)
+    g = rmat(14, 16, seed=9, wseed=10)
+    H = K.kappa_coarsen(dev(g), O.EXPANSION_STAR2, 7, 256)
+    for l in range(len(H) - 1):
+        _, rr, rd = H.rescan_stats(l)
+        assert not rr.any() and not rd.any()
