@@ -48,7 +48,9 @@ constexpr int ROW_BIG_MAX = 16382;  // one 1024-thread block per row, sort of <=
 // Rows above ROW_BIG_MAX (large rows) are merged by key buckets when the
 // next level has at most HUGE_NC_MAX nodes and the row at most HUGE_ROW_MAX
 // entries; the others by dense hub accumulators, which only graphs of more
-// than HUGE_NC_MAX nodes allocate.
+// than HUGE_NC_MAX nodes allocate.  Rows of ROW_MID_MAX+1..ROW_BIG_MAX
+// entries take the key buckets too where those apply; the big-row block
+// sort only otherwise.
 constexpr int HG_BINS = 4096;                       // key buckets of a row
 constexpr int HG_WINS = 2048;                       // groups per row at most
 constexpr int HG_WIN_MIN = 256;                     // positions per group window (at least)
@@ -750,8 +752,9 @@ struct Ctx {
     BatchCtx b;
     int32_t block_bits = -1;   // >= 0: two-phase matcher with blocks of 2^block_bits ids
     int32_t big_blocks = 64;   // blocks per round launch for rows above BIN_MID_MAX entries
-    int32_t big_rows = 1;      // 1: rows of 4095..16382 entries get the big-row sort launch;
-                               // 0: they join the large rows
+    int32_t big_rows = 1;      // 1: rows of 4095..16382 entries get the big-row sort launch
+                               // where the key buckets do not apply (and the small-row
+                               // merge buffers its list appends); 0: they join the large rows
     int32_t huge = 0;          // 1: large rows get the key-bucket merge launches
     int32_t rescan_stats = 0;  // 1: record the rescan statistics (while the profiler is on)
 };
