@@ -315,7 +315,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default: 15 for the single-graph workloads, "
+                         "about a second of work that brings a freshly started GPU to its "
+                         "steady clocks; 3 otherwise)")
     ap.add_argument("--scale", type=int, default=20, help="log2 of the node count")
     ap.add_argument("--k", type=int, default=64)
     ap.add_argument("--block-bits", type=int, default=None,
@@ -375,6 +378,8 @@ def main():
                                                "--output-format csv -- python3 <repo>/bench.py --steps 3 "
                                                "--warmup 1 --no-cpu-baseline --no-secondary")
     args = ap.parse_args()
+    if args.warmup is None:
+        args.warmup = 15 if args.workload in ("rmat22", "rgg20") else 3
     if args.summarize_pmc:
         return summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.summarize_pmc[2],
                              args.pmc_command, args.pmc_tag)
