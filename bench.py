@@ -16,6 +16,7 @@ launch stream, in a second timed pass with per-launch events enabled) and the
 oracle's time on the host for a bounded sample (cpu_baseline).
 """
 import argparse
+import gc
 import json
 import math
 import os
@@ -498,6 +499,11 @@ def single_graph(args, rmat_mode, primary):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # the host's cyclic garbage collector paused a timed step now and then
+    # (about 40 ms once per run, Python-side work, not the library's): collect
+    # first and hold it off while timing, as timeit does
+    gc.collect()
+    gc.disable()
     t1 = time.perf_counter()
     marks = [t1]
     for _ in range(args.steps):
@@ -505,8 +511,10 @@ def single_graph(args, rmat_mode, primary):
         marks.append(time.perf_counter())
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    gc.enable()
     ms_step = (t2 - t1) * 1e3 / args.steps
     med_ms = float(np.median(np.diff(marks))) * 1e3
+    log("step times (ms): " + " ".join(f"{x * 1e3:.1f}" for x in np.diff(marks)))
     edges_step = g.m * len(ratings)
     value = edges_step / (ms_step / 1e3)
     # all levels' edges (sum over the hierarchy of |E_l|) per second
@@ -689,6 +697,8 @@ def bench_batch(args):
         B = K.kappa_coarsen_batch(du, off, 0, 4, 256)
         del B
     torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()   # no host garbage-collector pause inside the timed steps
     t1 = time.perf_counter()
     for _ in range(args.steps):
         B = K.kappa_coarsen_batch(du, off, 0, 4, 256)
@@ -696,6 +706,7 @@ def bench_batch(args):
         del B
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t1) * 1e3 / args.steps
+    gc.enable()
     plain = None
     if not args.no_plain_loop:
         plain = plain_loop(K, graphs, torch)
@@ -760,6 +771,8 @@ def bench_refine(args):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()   # no host garbage-collector pause inside the timed steps
     t1 = time.perf_counter()
     for _ in range(args.steps):
         _, res, st = step()
@@ -770,6 +783,7 @@ def bench_refine(args):
         _, plain = K.kappa_uncoarsen(H, k, part_seed, eps[0], eps[1])
     torch.cuda.synchronize()
     plain_ms = (time.perf_counter() - tp) * 1e3 / args.steps
+    gc.enable()
 
     K.profile_reset()
     K.profile_enable(True)
