@@ -1568,7 +1568,8 @@ __global__ void __launch_bounds__(WAVE) merge_close_k(Ctx c, int l) {
 // ===========================================================================
 constexpr uint32_t INVALID_KEY = 0xffffffffu;
 constexpr int SM_ROWS = BLOCK / ROW_SMALL_G;      // 16 small rows per block
-constexpr int SM_CAP = ROW_SMALL_MAX + 2;        // entries incl. the dropped edge
+// entries incl. the dropped edge, rounded to whole 16-byte reads
+constexpr int SM_CAP = (ROW_SMALL_MAX + 2 + 3) / 4 * 4;
 constexpr int MID_P = 4096;
 
 // --- 1. coarse ids: scan of representative flags; the apply writes the whole
@@ -1840,8 +1841,8 @@ __device__ __forceinline__ void wbuf_add(bool pred, int32_t val, int32_t *buf, i
 template <int NT, bool BIG = true, bool BUF = false>
 __device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bid, unsigned nb) {
     constexpr int ROWS = NT / ROW_SMALL_G;
-    __shared__ uint32_t sk[ROWS][SM_CAP];   // renamed entries
-    __shared__ uint32_t sr[ROWS][SM_CAP];   // first occurrences only (others INVALID_KEY)
+    __shared__ __align__(16) uint32_t sk[ROWS][SM_CAP];   // renamed entries
+    __shared__ __align__(16) uint32_t sr[ROWS][SM_CAP];   // first occurrences only (others INVALID_KEY)
     __shared__ uint32_t sw[ROWS][SM_CAP];   // weights; a first occurrence collects its duplicates'
     __shared__ int32_t wb[BUF ? NT / WAVE : 1][4][BUF ? WBUF_CAP : 1];
     int wn[4] = {0, 0, 0, 0};
@@ -1908,13 +1909,22 @@ __device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bi
         wave_sync_lds();
         // the first occurrence of a key leads; a later one adds its weight
         // to it (only leaders receive, only non-leaders send)
+        // (keys read four at a time; slots past the row are masked)
         for (int t = sub; t < tot; t += ROW_SMALL_G) {
             const uint32_t k = sk[grp][t];
-            bool lead = k != INVALID_KEY;
-            int q = 0;
-            for (; q < t && lead; ++q) lead = sk[grp][q] != k;
+            int first = -1;   // the first earlier occurrence of k
+            if (k != INVALID_KEY) {
+                for (int q0 = 0; q0 < t; q0 += 4) {
+                    const uint4 x = *reinterpret_cast<const uint4 *>(&sk[grp][q0]);
+                    if (x.x == k) { first = q0; break; }
+                    if (q0 + 1 < t && x.y == k) { first = q0 + 1; break; }
+                    if (q0 + 2 < t && x.z == k) { first = q0 + 2; break; }
+                    if (q0 + 3 < t && x.w == k) { first = q0 + 3; break; }
+                }
+            }
+            const bool lead = k != INVALID_KEY && first < 0;
             sr[grp][t] = lead ? k : INVALID_KEY;
-            if (!lead && k != INVALID_KEY) atomicAdd(&sw[grp][q - 1], sw[grp][t]);
+            if (first >= 0) atomicAdd(&sw[grp][first], sw[grp][t]);
         }
         wave_sync_lds();
         int nl = 0;
@@ -1922,7 +1932,11 @@ __device__ __forceinline__ void fill_small_body(const Ctx &c, int l, unsigned bi
             const uint32_t k = sr[grp][t];
             if (k == INVALID_KEY) continue;
             int rank = 0;   // distinct keys below k
-            for (int q = 0; q < tot; ++q) rank += sr[grp][q] < k ? 1 : 0;
+            for (int q0 = 0; q0 < tot; q0 += 4) {
+                const uint4 x = *reinterpret_cast<const uint4 *>(&sr[grp][q0]);
+                rank += (x.x < k ? 1 : 0) + (q0 + 1 < tot && x.y < k ? 1 : 0) +
+                        (q0 + 2 < tot && x.z < k ? 1 : 0) + (q0 + 3 < tot && x.w < k ? 1 : 0);
+            }
             int64_t at = staged_at(r, rank);
             c.cs.tmp_adj[at] = (int32_t)k;
             c.cs.tmp_ew[at] = sw[grp][t];
