@@ -581,10 +581,11 @@ def single_graph(args, rmat_mode, primary):
         import oracle as O
         if rmat_mode:
             # the full scale-22 hierarchy takes the oracle minutes: the same
-            # generator at scale 18 (a sixteenth of the edges), whole hierarchy
+            # generator at scale 19 (an eighth of the edges; about 10-15 s on
+            # one host thread), whole hierarchy
             from workloads import rmat
-            gs = rmat(18, 16, seed=3, wseed=33)
-            sample = f"R-MAT scale 18 (|E|={gs.m}), same generator and parameters, whole " \
+            gs = rmat(19, 16, seed=3, wseed=33)
+            sample = f"R-MAT scale 19 (|E|={gs.m}), same generator and parameters, whole " \
                      "hierarchy and way back up on one host thread"
         else:
             gs = g
