@@ -2038,9 +2038,15 @@ __device__ __forceinline__ void reg_bitonic(T (&v)[E], int tid, T *s) {
                     if ((e & j) != 0) continue;
                     const bool up = (((tid * E + e) & k) == 0);
                     const T a = v[e], b = v[e | j];
-                    const T lo = a < b ? a : b, hi = a < b ? b : a;
-                    v[e] = up ? lo : hi;
-                    v[e | j] = up ? hi : lo;
+                    if (sizeof(T) == 4 && k < E) {   // direction fixed at compile time
+                        const T lo = a < b ? a : b, hi = a < b ? b : a;
+                        v[e] = up ? lo : hi;
+                        v[e | j] = up ? hi : lo;
+                    } else {   // one compare; swapped where out of order for the direction
+                        const bool sw = (b < a) == up;
+                        v[e] = sw ? b : a;
+                        v[e | j] = sw ? a : b;
+                    }
                 }
             } else if (j < E * WAVE) {
                 const int m = j / E;
@@ -2050,8 +2056,7 @@ __device__ __forceinline__ void reg_bitonic(T (&v)[E], int tid, T *s) {
                     const bool up = (((tid * E + e) & k) == 0);
                     const T o = shfl_xor_v(v[e], m);
                     const bool take_min = lower == up;
-                    const T lo = v[e] < o ? v[e] : o, hi = v[e] < o ? o : v[e];
-                    v[e] = take_min ? lo : hi;
+                    v[e] = ((o < v[e]) == take_min) ? o : v[e];
                 }
             } else {
                 const int m = j / E;
@@ -2064,8 +2069,7 @@ __device__ __forceinline__ void reg_bitonic(T (&v)[E], int tid, T *s) {
                     const bool up = (((tid * E + e) & k) == 0);
                     const T o = s[e * NT + (tid ^ m)];
                     const bool take_min = lower == up;
-                    const T lo = v[e] < o ? v[e] : o, hi = v[e] < o ? o : v[e];
-                    v[e] = take_min ? lo : hi;
+                    v[e] = ((o < v[e]) == take_min) ? o : v[e];
                 }
                 __syncthreads();
             }
