@@ -2020,7 +2020,10 @@ __device__ __forceinline__ uint64_t shfl_xor_v(uint64_t v, int m) {
 __device__ __forceinline__ uint32_t shfl_xor_v(uint32_t v, int m) {
     return (uint32_t)__shfl_xor((int)v, m, WAVE);
 }
-// T: uint64_t, or uint32_t (one shuffle and a min / max pair per exchange)
+// T: uint64_t, or uint32_t (one shuffle, one compare and one select per
+// exchange).  An exchange compares once and flips the result by the
+// direction: written as a minimum and a maximum, a 64-bit pair compiles to
+// two compares and six selects.
 template <int E, int NT, class T>
 __device__ __forceinline__ void reg_bitonic(T (&v)[E], int tid, T *s) {
     constexpr int P = E * NT;
@@ -2153,7 +2156,7 @@ __device__ __forceinline__ void block_sort(T *s, int P) {
 //          Narrow, where every coarse id shifted by lp = log2(P) bits fits in
 //          32 (nc << lp < 2^32): (key << lp | position) in 32 bits, the weight
 //          kept by position in a second LDS array, so that an exchange of the
-//          sort is one shuffle and a min / max pair.  Padding and the
+//          sort is one shuffle, one 32-bit compare and one select.  Padding and the
 //          contracted edge are all ones in either form (a narrow value never
 //          is: its key is below nc) and read as INVALID_KEY.
 struct WideRep {
